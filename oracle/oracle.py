@@ -1,0 +1,237 @@
+"""Python driver of the FP64 CPU oracle (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module. It does not import the library under
+test, and the library never imports it. It takes plain arrays and duck-typed
+segment / phase records (attributes ``id, kind, normal, u_max, c_in`` and
+``duration, open, c_in``), so the same seeded inputs can be handed to both.
+
+The time loop, the valve schedule lookup and the boundary-segment geometry
+(halfway-wall positions of each inlet profile) are computed here, on the oracle
+side, independently of the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+SEG_KIND = {"inlet": 1, "outlet": 2}
+
+
+class _OrcLattice(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("periodic_x", ctypes.c_int32), ("periodic_y", ctypes.c_int32),
+        ("mask", ctypes.c_void_p),
+        ("tau_f", ctypes.c_double), ("tau_g", ctypes.c_double),
+        ("w0", ctypes.c_double), ("rho_w", ctypes.c_double),
+        ("k_decay", ctypes.c_double),
+        ("R", ctypes.c_void_p),
+        ("seg_kind", ctypes.c_void_p), ("seg_nrm", ctypes.c_void_p),
+        ("seg_umax", ctypes.c_void_p), ("seg_s0", ctypes.c_void_p),
+        ("seg_s1", ctypes.c_void_p),
+    ]
+
+
+def use_library(path: Optional[str]) -> None:
+    """Point the oracle at another build of lbm_oracle.c (``None``: the
+    default oracle/liboracle.so). Used by the test that plants mistakes in
+    the oracle source to show that the pins catch them."""
+    global _LIB, _LIB_PATH
+    _LIB = None
+    _LIB_PATH = path
+
+
+_LIB_PATH: Optional[str] = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load oracle/liboracle.so, building it with gcc if it is absent."""
+    global _LIB
+    if _LIB is None:
+        path = _LIB_PATH or os.path.join(HERE, "liboracle.so")
+        if _LIB_PATH is None and not os.path.exists(path):
+            from . import build_oracle
+            build_oracle.build()
+        L = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        D = ctypes.c_double
+        L.orc_feq.argtypes = [D, D, D, P]
+        L.orc_geq.argtypes = [D, D, D, D, P]
+        L.orc_step.argtypes = [P, P, P, P, P, P, P, P, P]
+        L.orc_init_eq.argtypes = [P, P, P, P, P, P, P]
+        L.orc_moments.argtypes = [P, P, P, P, P, P, P]
+        L.orc_totals.argtypes = [P, P, P, P, P]
+        for fn in ("orc_feq", "orc_geq", "orc_step", "orc_init_eq",
+                   "orc_moments", "orc_totals"):
+            getattr(L, fn).restype = None
+        _LIB = L
+    return _LIB
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def feq(rho: float, ux: float, uy: float) -> np.ndarray:
+    """D2Q9 equilibrium of Eq. (5) with the weights of Eq. (6)."""
+    out = np.zeros(9)
+    lib().orc_feq(rho, ux, uy, _ptr(out))
+    return out
+
+
+def geq(C: float, ux: float, uy: float, w0: float) -> np.ndarray:
+    """Linear compound equilibrium, Eq. (9) generalised to a rest weight w0."""
+    out = np.zeros(5)
+    lib().orc_geq(C, ux, uy, w0, _ptr(out))
+    return out
+
+
+def tau_g_from_D(D: float, w0: float) -> float:
+    """Compound relaxation time for diffusion coefficient D.
+
+    The paper states D = (2 tau_g - 1)/4 for its D2Q4 lattice (after Eq. 9),
+    i.e. D = cs2 (tau_g - 1/2) with cs2 = 1/2. With a rest weight w0 the
+    lattice sound speed squared is cs2 = (1 - w0)/2.
+    """
+    cs2 = (1.0 - w0) / 2.0
+    return 0.5 + D / cs2
+
+
+def segment_extent(mask: np.ndarray, seg_id: int, normal) -> tuple:
+    """Halfway-wall positions (s0, s1) of a segment's ghost line.
+
+    The tangential coordinate is y for a segment whose normal is along x and
+    x otherwise; the profile vanishes half a cell beyond the outermost ghost
+    cells, where the neighbouring walls sit under halfway bounce-back.
+    """
+    ys, xs = np.nonzero(mask == seg_id)
+    if ys.size == 0:
+        raise ValueError(f"segment {seg_id} has no cells in the mask")
+    s = ys if normal[0] != 0 else xs
+    return float(s.min()) - 0.5, float(s.max()) + 0.5
+
+
+class Oracle:
+    """Two-array FP64 reference run of the coupled D2Q9 + D2Q5 lattice."""
+
+    def __init__(self, mask: np.ndarray, *, tau_f: float, D: float,
+                 w0: float = 1.0 / 3.0, rho0: float = 1.0, k_decay: float = 0.0,
+                 periodic: Sequence[bool] = (False, False),
+                 segments: Iterable = (), schedule: Optional[Sequence] = None,
+                 t_origin: int = 0, R: Optional[np.ndarray] = None,
+                 tau_g: Optional[float] = None):
+        self.mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        self.ny, self.nx = self.mask.shape
+        self.w0 = float(w0)
+        self.tau_f = float(tau_f)
+        self.tau_g = float(tau_g) if tau_g is not None else tau_g_from_D(D, w0)
+        self.rho0 = float(rho0)
+        self.segments = {s.id: s for s in segments}
+        self.schedule = list(schedule) if schedule else None
+        self.t_origin = int(t_origin)
+        self.t = 0
+
+        self._kind = np.zeros(256, np.int32)
+        self._nrm = np.zeros((256, 2), np.int32)
+        self._umax = np.zeros(256)
+        self._s0 = np.zeros(256)
+        self._s1 = np.ones(256)
+        self._cin_default = np.zeros(256)
+        for s in self.segments.values():
+            self._kind[s.id] = SEG_KIND[s.kind]
+            self._nrm[s.id] = s.normal
+            self._umax[s.id] = s.u_max
+            self._cin_default[s.id] = s.c_in
+            self._s0[s.id], self._s1[s.id] = segment_extent(self.mask, s.id, s.normal)
+        self.R = None if R is None else np.ascontiguousarray(R, dtype=np.float64)
+
+        self._c = _OrcLattice(
+            self.nx, self.ny, int(bool(periodic[0])), int(bool(periodic[1])),
+            _ptr(self.mask), self.tau_f, self.tau_g, self.w0, self.rho0,
+            float(k_decay), _ptr(self.R), _ptr(self._kind), _ptr(self._nrm),
+            _ptr(self._umax), _ptr(self._s0), _ptr(self._s1))
+        n = self.nx * self.ny
+        self.f = np.zeros((self.ny, self.nx, 9))
+        self.g = np.zeros((self.ny, self.nx, 5))
+        self._fn = np.zeros_like(self.f)
+        self._gn = np.zeros_like(self.g)
+        self.flux_mass = np.zeros(256)
+        self.flux_solute = np.zeros(256)
+        self.init()
+
+    # -- schedule -------------------------------------------------------
+    def phase(self, t: int):
+        """(open[256], c_in[256]) in force during step t -> t+1.
+
+        The schedule is a periodic list of phases; phase k covers the steps
+        [t_origin + start_k, t_origin + start_k + duration_k) modulo the
+        period. With no schedule every segment is open.
+        """
+        open_ = np.zeros(256, np.uint8)
+        c_in = self._cin_default.copy()
+        if self.schedule is None:
+            for sid in self.segments:
+                open_[sid] = 1
+            return open_, c_in
+        period = sum(int(p.duration) for p in self.schedule)
+        tau = (t - self.t_origin) % period
+        for p in self.schedule:
+            if tau < p.duration:
+                for sid in p.open:
+                    open_[sid] = 1
+                for sid, v in dict(p.c_in).items():
+                    c_in[sid] = v
+                return open_, c_in
+            tau -= p.duration
+        raise AssertionError("unreachable")
+
+    # -- state ------------------------------------------------------------
+    def init(self, rho=None, ux=None, uy=None, C=None):
+        shape = (self.ny, self.nx)
+        def full(a, v):
+            return np.full(shape, v) if a is None else np.ascontiguousarray(a, np.float64).reshape(shape)
+        rho, ux, uy, C = full(rho, self.rho0), full(ux, 0.0), full(uy, 0.0), full(C, 0.0)
+        lib().orc_init_eq(ctypes.byref(self._c), _ptr(rho), _ptr(ux), _ptr(uy),
+                          _ptr(C), _ptr(self.f), _ptr(self.g))
+        self.t = 0
+        self.flux_mass[:] = 0.0
+        self.flux_solute[:] = 0.0
+
+    def set_populations(self, f: np.ndarray, g: np.ndarray, t: int = 0):
+        self.f[...] = np.asarray(f, np.float64).reshape(self.f.shape)
+        self.g[...] = np.asarray(g, np.float64).reshape(self.g.shape)
+        self.t = int(t)
+
+    def step(self, n: int = 1):
+        L = lib()
+        for _ in range(int(n)):
+            open_, c_in = self.phase(self.t)
+            L.orc_step(ctypes.byref(self._c), _ptr(self.f), _ptr(self.g),
+                       _ptr(self._fn), _ptr(self._gn), _ptr(open_), _ptr(c_in),
+                       _ptr(self.flux_mass), _ptr(self.flux_solute))
+            self.f, self._fn = self._fn, self.f
+            self.g, self._gn = self._gn, self.g
+            self.t += 1
+
+    def fields(self):
+        """rho, ux, uy, C arrays of shape (ny, nx); NaN off the fluid."""
+        shape = (self.ny, self.nx)
+        rho, ux, uy, C = (np.empty(shape) for _ in range(4))
+        lib().orc_moments(ctypes.byref(self._c), _ptr(self.f), _ptr(self.g),
+                          _ptr(rho), _ptr(ux), _ptr(uy), _ptr(C))
+        return rho, ux, uy, C
+
+    def totals(self):
+        """(fluid mass, compound amount) summed over fluid nodes."""
+        m = ctypes.c_double()
+        s = ctypes.c_double()
+        lib().orc_totals(ctypes.byref(self._c), _ptr(self.f), _ptr(self.g),
+                         ctypes.byref(m), ctypes.byref(s))
+        return m.value, s.value

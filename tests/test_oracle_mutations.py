@@ -1,0 +1,81 @@
+"""The pins are sharp: plant one plausible mistake at a time in the oracle's
+C source (on the CPU), rebuild it, and check that at least one pin fails.
+
+Each mutation is a dropped term, a flipped sign, a wrong weight, index or
+direction table entry in one part of the coupled step.
+"""
+import os
+
+import pytest
+
+from oracle import build_oracle
+from oracle import oracle as orc
+from tests import test_oracle_pins as P
+
+PINS = [
+    (P.test_feq_full_moment_basis, dict(rho=1.03, ux=0.05, uy=-0.02)),
+    (P.test_feq_weights_isotropy, {}),
+    (P.test_geq_full_moment_basis, dict(w0=1 / 3, C=0.7, ux=0.05, uy=-0.03)),
+    (P.test_periodic_conservation_mass_momentum_solute, {}),
+    (P.test_source_and_decay_enter_solute_budget, {}),
+    (P.test_uniform_equilibrium_is_fixed_point, {}),
+    (P.test_tau_f_one_streams_the_equilibrium, {}),
+    (P.test_tau_g_one_is_ftcs_scheme, dict(w0=1 / 3)),
+    (P.test_compound_lattice_exact_fourier_evolution, {}),
+    (P.test_closed_box_conserves_with_bounce_back_and_closed_valves, {}),
+    (P.test_inlet_mass_inflow_closed_form, {}),
+    (P.test_inlet_concentration_fills_channel, {}),
+    (P.test_poiseuille_profile_and_linear_pressure_drop, {}),
+    (P.test_advected_gaussian_closed_form_and_second_order, {}),
+]
+
+MUTATIONS = {
+    "diagonal weight": ("1.0 / 36.0, 1.0 / 36.0};", "1.0 / 36.0, 1.0 / 35.0};"),
+    "feq (e.u)^2 coefficient": ("4.5 * eu * eu - 1.5 * usq", "4.0 * eu * eu - 1.5 * usq"),
+    "feq u^2 coefficient": ("4.5 * eu * eu - 1.5 * usq", "4.5 * eu * eu - 1.0 * usq"),
+    "feq linear coefficient": ("1.0 + 3.0 * eu", "1.0 + 2.0 * eu"),
+    "geq divides by cs2": ("(1.0 + eu / cs2)", "(1.0 + eu * cs2)"),
+    "compound axis weight": ("wg5[i] = (1.0 - w0) / 4.0;", "wg5[i] = (1.0 - w0) / 5.0;"),
+    "opposite of diagonals": ("{0, 3, 4, 1, 2, 7, 8, 5, 6}", "{0, 3, 4, 1, 2, 8, 7, 6, 5}"),
+    "direction table": ("EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1}", "EY[9] = {0, 0, 1, 0, -1, 1, -1, -1, 1}"),
+    "f relaxation sign": ("fx[i] - omega_f * (fx[i] - feq[i])", "fx[i] + omega_f * (fx[i] - feq[i])"),
+    "g relaxation term": ("gx[i] - omega_g * (gx[i] - geq[i])", "gx[i] - omega_g * (gx[i] + geq[i])"),
+    "u_y from j_x": ("double ux = jx / rho, uy = jy / rho;\n  u[0]", "double ux = jx / rho, uy = jx / rho;\n  u[0]"),
+    "source weight dropped": ("+ wg[i] * src;", "+ src;"),
+    "decay sign": ("- L->k_decay * C;", "+ L->k_decay * C;"),
+    "inlet momentum sign": ("in_f = out_f - 6.0 * WF[i]", "in_f = out_f + 6.0 * WF[i]"),
+    "inlet momentum factor": ("in_f = out_f - 6.0 * WF[i]", "in_f = out_f - 3.0 * WF[i]"),
+    "anti-bounce-back factor": ("2.0 * wg[i] * c_in[code]", "1.0 * wg[i] * c_in[code]"),
+    "anti-bounce-back sign": ("in_g = -out_g + 2.0", "in_g = out_g + 2.0"),
+    "outlet f sign": ("in_f = -out_f + 2.0 * WF[i]", "in_f = out_f + 2.0 * WF[i]"),
+    "outlet g direction": ("if (has_g) in_g = gp[5 * node + i];", "if (has_g) in_g = gp[5 * node + opp];"),
+    "periodic wrap": ("x = (x + L->nx) % L->nx;", "x = (x + L->nx + 1) % L->nx;"),
+    "inlet profile": ("4.0 * L->seg_umax[seg]", "6.0 * L->seg_umax[seg]"),
+    "wall bounce-back loses mass": ("in_f = out_f;\n          in_g = out_g;\n        } else if",
+                                    "in_f = 0.999 * out_f;\n          in_g = out_g;\n        } else if"),
+    "tau_f": ("double omega_f = 1.0 / L->tau_f;", "double omega_f = 1.0 / (L->tau_f + 0.05);"),
+    "tau_g": ("double omega_g = 1.0 / L->tau_g;", "double omega_g = 1.0 / (L->tau_g + 0.05);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_some_pin_catches(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = open(build_oracle.SRC).read()
+    assert src.count(old) >= 1, f"mutation site not found: {name}"
+    mut = os.path.join(tmp_path, "mut.c")
+    with open(mut, "w") as fh:
+        fh.write(src.replace(old, new, 1))
+    lib_path = build_oracle.build(src=mut, out=os.path.join(tmp_path, "libmut.so"))
+    orc.use_library(lib_path)
+    caught = []
+    try:
+        for fn, kw in PINS:
+            try:
+                fn(**kw)
+            except AssertionError:
+                caught.append(fn.__name__)
+                break
+    finally:
+        orc.use_library(None)
+    assert caught, f"no pin fails when the oracle has: {name}"
