@@ -1,0 +1,225 @@
+/*
+ * gg.h - C ABI of the MI355X (gfx950) coupled lattice Boltzmann library.
+ *
+ * The library advances, on one GPU, the coupled scheme of Tanaka & Iber,
+ * "Simulation of a Microfluidic Gradient Generator using Lattice Boltzmann
+ * Methods" (arXiv:1307.4703):
+ *   - fluid: D2Q9 lattice BGK (paper Eqs. 3-7), relaxation time tau_f,
+ *     kinematic viscosity nu = (tau_f - 1/2)/3;
+ *   - compound: multi-distribution advection-diffusion lattice (paper
+ *     Eqs. 8-9) on D2Q5 with rest weight w0 (w0 = 0 is the paper's D2Q4),
+ *     linear equilibrium g_i^eq = w_i C (1 + e_i.u/cs2), cs2 = (1 - w0)/2,
+ *     D = cs2 (tau_g - 1/2), driven by the velocity of the same node at the
+ *     same step (the one-way coupling of the Results section), with the
+ *     source term R - kC of paper Eq. 2;
+ *   - one fused collide-and-stream per time step on a masked lattice, with
+ *     halfway bounce-back walls and boundary segments (inlets / outlets)
+ *     that a periodic valve schedule opens and closes (the alternate
+ *     flushing of the Experimental Layout section).
+ *
+ * Conventions for every function below:
+ *   - Arrays are row-major with x fastest: element (x, y) is at y*nx + x.
+ *   - Pointers are borrowed for the duration of the call; the library copies
+ *     what it keeps. GG_DEVICE pointers are HIP device pointers that the
+ *     library reads or writes on the lattice's stream.
+ *   - Every call returns a gg_status; on failure nothing is thrown, the
+ *     library state is left as before the call where that is possible, and
+ *     gg_last_error() returns a message (thread-local).
+ *   - Work is issued on the HIP stream given to gg_create. gg_step returns
+ *     before the GPU is done; gg_read, gg_read_populations, gg_diagnostics
+ *     and gg_save wait for the stream.
+ */
+#ifndef GG_H
+#define GG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Mask values: 0 fluid, 1 wall, GG_FIRST_SEGMENT .. GG_FIRST_SEGMENT +
+ * GG_MAX_SEGMENTS - 1 ghost cells of a boundary segment. */
+#define GG_MASK_FLUID 0
+#define GG_MASK_WALL 1
+#define GG_FIRST_SEGMENT 2
+#define GG_MAX_SEGMENTS 16
+#define GG_MAX_PHASES 64
+
+typedef enum gg_status {
+  GG_OK = 0,
+  GG_ERR_ARG = 1,        /* invalid argument */
+  GG_ERR_MASK = 2,       /* invalid geometry */
+  GG_ERR_OOM = 3,        /* device or host allocation failed */
+  GG_ERR_HIP = 4,        /* a HIP runtime call failed */
+  GG_ERR_NONFINITE = 5,  /* diagnostics found a NaN or Inf population */
+  GG_ERR_STATE = 6       /* call not valid in the current state */
+} gg_status;
+
+/* Population storage. Collision arithmetic is FP64 for GG_F64 and FP32
+ * otherwise. GG_F16_SHIFTED stores h_i = f_i - w_i rho0 and
+ * h^g_i = g_i - w^g_i c_shift in IEEE binary16, rounded to nearest even. */
+typedef enum gg_storage { GG_F64 = 0, GG_F32 = 1, GG_F16_SHIFTED = 2 } gg_storage;
+
+typedef enum gg_where { GG_HOST = 0, GG_DEVICE = 1 } gg_where;
+
+/* Boundary segment kinds.
+ * GG_SEG_INLET : while open, a velocity inlet. Each link from a ghost cell
+ *   into fluid node z carries the moving-wall bounce-back of the halfway
+ *   wall, F(z,i) = f*(z,opp i) - 6 w_i rho0 (e_opp.u_w), with wall velocity
+ *   u_w = -n u(s): a parabola of centre speed u_max across the segment,
+ *   zero half a cell beyond its outermost ghost cells, evaluated at the
+ *   tangential coordinate s of z; the compound gets anti-bounce-back for
+ *   the Dirichlet value C_in: G(z,i) = -g*(z,opp i) + 2 w^g_i C_in.
+ * GG_SEG_OUTLET : while open, an outflow at the reference density rho0 with
+ *   zero normal gradient of the velocity (anti-bounce-back using the
+ *   node's own velocity), and zero-gradient for the compound.
+ * A closed segment is a wall (halfway bounce-back for f and g). */
+typedef enum gg_seg_kind { GG_SEG_INLET = 1, GG_SEG_OUTLET = 2 } gg_seg_kind;
+
+typedef struct gg_params {
+  double tau_f;       /* fluid relaxation time, > 1/2 (paper Eq. 4) */
+  double D;           /* compound diffusion coefficient, > 0 (after Eq. 9) */
+  double w0;          /* compound rest weight, 0 <= w0 < 1 */
+  double rho0;        /* reference density: default initial density,
+                         density of inlet/outlet links, FP16 shift of f */
+  double k_decay;     /* first-order decay rate k >= 0 in R - kC (Eq. 2) */
+  double c_shift;     /* FP16 shift of the compound populations */
+  int32_t periodic_x; /* nonzero: x wraps; else the x edges are walls */
+  int32_t periodic_y;
+} gg_params;
+
+/* One phase of a periodic valve schedule. Bit (id - GG_FIRST_SEGMENT) of
+ * open_mask opens segment id for `duration` steps; bit k of c_in_set makes
+ * c_in[k] the inlet concentration of segment GG_FIRST_SEGMENT + k in this
+ * phase (otherwise the value given to gg_set_segment applies). */
+typedef struct gg_phase {
+  int64_t duration;
+  uint32_t open_mask;
+  uint32_t c_in_set;
+  double c_in[GG_MAX_SEGMENTS];
+} gg_phase;
+
+/* FP64 diagnostics at the current time t (populations before collision). */
+typedef struct gg_diag {
+  int64_t t;             /* completed time steps since gg_init */
+  int64_t n_fluid;       /* fluid nodes */
+  int64_t n_nonfinite;   /* fluid nodes with a NaN/Inf population */
+  double mass;           /* sum over fluid nodes of sum_i f_i */
+  double solute;         /* sum over fluid nodes of sum_i g_i */
+  double mass_in;        /* accumulated net mass entering through inlets */
+  double mass_out;       /* ... through outlets (negative = leaving) */
+  double solute_in;      /* accumulated net compound through inlets */
+  double solute_out;     /* ... through outlets */
+  double max_u;          /* max |u| over fluid nodes */
+  double max_u_region;   /* max |u| over fluid nodes flagged by gg_set_region */
+  double max_pe_region;  /* max_u_region / D: the largest cell Peclet number */
+  double seg_mass[GG_MAX_SEGMENTS];    /* accumulated net mass per segment */
+  double seg_solute[GG_MAX_SEGMENTS];  /* accumulated net compound per segment */
+} gg_diag;
+
+typedef struct gg_lattice gg_lattice;
+typedef struct gg_batch gg_batch;
+
+/* Create a lattice from a mask (host, nx*ny bytes). Fluid nodes with no
+ * fluid neighbour among their 8 neighbours, unknown mask values and more
+ * than two distinct segments next to one fluid node are GG_ERR_MASK.
+ * `hip_stream` (a hipStream_t, may be NULL for the null stream) carries all
+ * later work. Populations start at equilibrium with rho0, u = 0, C = 0. */
+gg_status gg_create(const uint8_t *mask, int32_t nx, int32_t ny,
+                    const gg_params *params, gg_storage storage,
+                    void *hip_stream, gg_lattice **out);
+
+/* Configure segment `id` (a mask value >= GG_FIRST_SEGMENT). (nrm_x, nrm_y)
+ * is the outward unit normal, along an axis, pointing from the fluid into
+ * the ghost line; every ghost cell of the segment must have a fluid cell
+ * one step against the normal (GG_ERR_MASK otherwise). u_max is the centre
+ * speed of an inlet profile, c_in its default concentration. */
+gg_status gg_set_segment(gg_lattice *lat, int32_t id, gg_seg_kind kind,
+                         int32_t nrm_x, int32_t nrm_y, double u_max,
+                         double c_in);
+
+/* Periodic valve schedule: phases repeat with period sum(duration); the
+ * phase in force during step t -> t+1 is the one containing
+ * (t - t_origin) mod period. n_phases = 0 removes the schedule (every
+ * configured segment open). */
+gg_status gg_set_schedule(gg_lattice *lat, const gg_phase *phases,
+                          int32_t n_phases, int64_t t_origin);
+
+/* Per-node source R (nx*ny doubles, host or device) of paper Eq. 2; NULL
+ * removes it. Only the bounding box of its nonzero entries is stored. */
+gg_status gg_set_source(gg_lattice *lat, const double *R, gg_where where);
+
+/* Region flag per node (host, nx*ny bytes, nonzero = inside) for the
+ * region velocity and Peclet diagnostics; NULL clears it. */
+gg_status gg_set_region(gg_lattice *lat, const uint8_t *region);
+
+/* Equilibrium initial state f = f^eq(rho, u), g = g^eq(C, u) at every
+ * fluid node from nx*ny arrays (NULL: rho0, 0, 0, 0 respectively); resets
+ * t to 0 and the accumulated boundary fluxes to zero. */
+gg_status gg_init(gg_lattice *lat, const double *rho, const double *ux,
+                  const double *uy, const double *C, gg_where where);
+
+/* Advance n >= 0 time steps. Asynchronous. */
+gg_status gg_step(gg_lattice *lat, int64_t n);
+
+/* Macroscopic fields at the current time (nx*ny doubles each; NaN off the
+ * fluid; NULL skips a field): rho = sum f_i, u = sum f_i e_i / rho,
+ * C = sum g_i (paper Eq. 7 and the definition after Eq. 9). */
+gg_status gg_read(gg_lattice *lat, double *rho, double *ux, double *uy,
+                  double *C, gg_where where);
+
+/* Populations at the current time in natural order: f[i*nx*ny + y*nx + x]
+ * for i = 0..8 and g[i*nx*ny + ...] for i = 0..4 (FP64; zero off the
+ * fluid; NULL skips). Directions follow paper Eq. 3: 1..4 = +x, +y, -x, -y;
+ * 5..8 = (+1,+1), (-1,+1), (-1,-1), (+1,-1). */
+gg_status gg_read_populations(gg_lattice *lat, double *f, double *g,
+                              gg_where where);
+
+/* FP64 diagnostics; GG_ERR_NONFINITE (with *out filled) if any fluid node
+ * holds a non-finite population. */
+gg_status gg_diagnostics(gg_lattice *lat, gg_diag *out);
+
+/* Snapshot of the full state (populations, time, fluxes). With buf NULL,
+ * *nbytes receives the size needed. gg_load accepts only a snapshot of a
+ * lattice with the same mask dimensions and storage. */
+gg_status gg_save(gg_lattice *lat, void *buf, size_t *nbytes);
+gg_status gg_load(gg_lattice *lat, const void *buf, size_t nbytes);
+
+/* Kernel launch shape: tiles of tile_x * tile_y nodes (one work-group each,
+ * tile_x * tile_y in {64, 128, 256, 512}, tile_x a multiple of 8); only
+ * tiles holding a fluid node are launched. graph_chunk > 0 replays
+ * gg_step in HIP graphs of that many steps; 0 launches every step. */
+gg_status gg_set_launch(gg_lattice *lat, int32_t tile_x, int32_t tile_y,
+                        int32_t graph_chunk);
+
+/* Number of fluid nodes and launched tiles. */
+gg_status gg_info(const gg_lattice *lat, int64_t *n_fluid, int64_t *n_tiles,
+                  int64_t *t);
+
+/* Instrumentation: advance n >= 1 steps launching every step kernel
+ * between two HIP events on the lattice's stream (no graphs) and return
+ * in *kernel_ms the mean event-measured duration of one step kernel. Waits
+ * for the stream. */
+gg_status gg_step_timed(gg_lattice *lat, int64_t n, double *kernel_ms);
+
+/* Instrumentation: copy `bytes` (a multiple of 16) from src to dst, both
+ * device buffers, `reps` times with a plain streaming kernel on hip_stream,
+ * and return in *ms the mean event-measured duration of one copy. Used to
+ * measure achievable HBM bandwidth and to calibrate traffic counters. */
+gg_status gg_stream_copy(void *dst, const void *src, size_t bytes, int32_t reps,
+                         void *hip_stream, double *ms);
+
+/* Wait for all work issued on the lattice's stream. */
+gg_status gg_sync(gg_lattice *lat);
+
+void gg_destroy(gg_lattice *lat);
+
+/* Message of the last failed call on this thread. */
+const char *gg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GG_H */

@@ -36,6 +36,9 @@
  * written.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -343,4 +346,13 @@ void orc_totals(const orc_lattice *L, const double *f, const double *g,
   }
   *mass = sm + cm;
   *solute = ss + cs;
+}
+
+/* Number of OpenMP threads a step uses (1 without OpenMP). */
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

@@ -71,6 +71,8 @@ def lib() -> ctypes.CDLL:
         for fn in ("orc_feq", "orc_geq", "orc_step", "orc_init_eq",
                    "orc_moments", "orc_totals"):
             getattr(L, fn).restype = None
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = ctypes.c_int
         _LIB = L
     return _LIB
 
@@ -91,6 +93,11 @@ def geq(C: float, ux: float, uy: float, w0: float) -> np.ndarray:
     out = np.zeros(5)
     lib().orc_geq(C, ux, uy, w0, _ptr(out))
     return out
+
+
+def threads() -> int:
+    """OpenMP threads used by one oracle step."""
+    return int(lib().orc_threads())
 
 
 def tau_g_from_D(D: float, w0: float) -> float:

@@ -1,0 +1,117 @@
+"""ctypes binding of the C ABI in include/gg.h (argument marshalling only).
+
+The names mirror the C functions. Loading fails loudly when libgg.so has not
+been built: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libgg.so")
+
+GG_OK = 0
+GG_ERR_ARG = 1
+GG_ERR_MASK = 2
+GG_ERR_OOM = 3
+GG_ERR_HIP = 4
+GG_ERR_NONFINITE = 5
+GG_ERR_STATE = 6
+
+GG_F64, GG_F32, GG_F16_SHIFTED = 0, 1, 2
+GG_HOST, GG_DEVICE = 0, 1
+GG_SEG_INLET, GG_SEG_OUTLET = 1, 2
+GG_FIRST_SEGMENT = 2
+GG_MAX_SEGMENTS = 16
+GG_MAX_PHASES = 64
+
+STORAGE = {"f64": GG_F64, "f32": GG_F32, "f16": GG_F16_SHIFTED}
+
+
+class gg_params(ctypes.Structure):
+    _fields_ = [("tau_f", ctypes.c_double), ("D", ctypes.c_double),
+                ("w0", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("k_decay", ctypes.c_double), ("c_shift", ctypes.c_double),
+                ("periodic_x", ctypes.c_int32), ("periodic_y", ctypes.c_int32)]
+
+
+class gg_phase(ctypes.Structure):
+    _fields_ = [("duration", ctypes.c_int64), ("open_mask", ctypes.c_uint32),
+                ("c_in_set", ctypes.c_uint32),
+                ("c_in", ctypes.c_double * GG_MAX_SEGMENTS)]
+
+
+class gg_diag(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int64), ("n_fluid", ctypes.c_int64),
+                ("n_nonfinite", ctypes.c_int64),
+                ("mass", ctypes.c_double), ("solute", ctypes.c_double),
+                ("mass_in", ctypes.c_double), ("mass_out", ctypes.c_double),
+                ("solute_in", ctypes.c_double), ("solute_out", ctypes.c_double),
+                ("max_u", ctypes.c_double), ("max_u_region", ctypes.c_double),
+                ("max_pe_region", ctypes.c_double),
+                ("seg_mass", ctypes.c_double * GG_MAX_SEGMENTS),
+                ("seg_solute", ctypes.c_double * GG_MAX_SEGMENTS)]
+
+
+class GGError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where} failed with status {status}: {message}")
+        self.status = status
+
+
+_LIB = None
+
+P = ctypes.c_void_p
+I32 = ctypes.c_int32
+I64 = ctypes.c_int64
+D = ctypes.c_double
+SIGS = {
+    "gg_create": [P, I32, I32, ctypes.POINTER(gg_params), ctypes.c_int, P, ctypes.POINTER(P)],
+    "gg_set_segment": [P, I32, ctypes.c_int, I32, I32, D, D],
+    "gg_set_schedule": [P, ctypes.POINTER(gg_phase), I32, I64],
+    "gg_set_source": [P, P, ctypes.c_int],
+    "gg_set_region": [P, P],
+    "gg_init": [P, P, P, P, P, ctypes.c_int],
+    "gg_step": [P, I64],
+    "gg_read": [P, P, P, P, P, ctypes.c_int],
+    "gg_read_populations": [P, P, P, ctypes.c_int],
+    "gg_diagnostics": [P, ctypes.POINTER(gg_diag)],
+    "gg_save": [P, P, ctypes.POINTER(ctypes.c_size_t)],
+    "gg_load": [P, P, ctypes.c_size_t],
+    "gg_set_launch": [P, I32, I32, I32],
+    "gg_info": [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)],
+    "gg_sync": [P],
+    "gg_step_timed": [P, I64, ctypes.POINTER(D)],
+    "gg_stream_copy": [P, P, ctypes.c_size_t, I32, P, ctypes.POINTER(D)],
+}
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build the HIP library first "
+                "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.gg_destroy.argtypes = [P]
+        L.gg_destroy.restype = None
+        L.gg_last_error.argtypes = []
+        L.gg_last_error.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def check(status: int, where: str) -> None:
+    if status != GG_OK:
+        msg = lib().gg_last_error().decode(errors="replace")
+        raise GGError(status, where, msg)
+
+
+def call(name: str, *args) -> None:
+    check(getattr(lib(), name)(*args), name)

@@ -1,0 +1,92 @@
+// Device-side data of the coupled lattice: descriptor layout shared by the
+// host runtime and the gfx950 kernels, lattice constants and storage traits.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gg.h"
+
+namespace gg {
+
+// D2Q9 velocity set of paper Eq. 3 (0 rest; 1..4 axes; 5..8 diagonals) and
+// the weights of Eq. 6. Directions 0..4 double as the D2Q5 compound lattice.
+constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+constexpr double WF[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
+                          1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+// Link code byte per node: bit k-1 set <=> cell x + e_k is not fluid
+// (k = 1..8). NOT_FLUID marks a node that is not updated.
+constexpr uint8_t NOT_FLUID = 0xFF;
+
+// Tile flag: some node of the tile has a link into a boundary segment.
+constexpr int TILE_TOUCHES_SEGMENT = 1;
+
+constexpr int NPOP = 14;  // 9 f planes then 5 g planes
+
+// Everything a kernel needs about one lattice. Lives in device memory and
+// is read with uniform (scalar) loads; the host re-uploads it when the
+// parameters change. The time counter lives apart (*t) so that uploads
+// never race with the device-side advance.
+struct LatDesc {
+  int32_t nx, ny, pitch, periodic_x;
+  int32_t periodic_y, n_phases, has_source, has_region;
+  int64_t plane;            // elements between population planes
+  void *pop;                // 14 planes of the storage type
+  const uint8_t *link;      // ny*pitch link codes
+  const uint8_t *mask;      // ny*pitch mask values
+  const uint8_t *region;    // ny*pitch region flags (or null)
+  const double *R;          // source patch, row-major r_w x r_h
+  int32_t r_x0, r_y0, r_w, r_h;
+  int64_t *t;               // completed steps (device counter)
+  double *flux;             // [GG_MAX_SEGMENTS][2] accumulated mass, solute
+  double omega_f, omega_g;  // 1/tau_f, 1/tau_g
+  double w0, wg_axis;       // compound weights: rest, each axis direction
+  double inv_cs2g;          // 1/cs2 of the compound lattice
+  double rho0;              // reference density (inlet/outlet links)
+  double k_decay;
+  double c_shift;           // FP16 shift of g
+  // segments, index id - GG_FIRST_SEGMENT
+  int32_t seg_kind[GG_MAX_SEGMENTS];
+  int32_t seg_nx[GG_MAX_SEGMENTS];
+  int32_t seg_ny[GG_MAX_SEGMENTS];
+  int32_t seg_pad;
+  double seg_umax[GG_MAX_SEGMENTS];
+  double seg_s0[GG_MAX_SEGMENTS];
+  double seg_s1[GG_MAX_SEGMENTS];
+  double seg_inv_w2[GG_MAX_SEGMENTS];
+  // schedule: phase k starts at phase_start[k] within a period; the c_in
+  // table already merges per-phase overrides with the segment defaults.
+  int64_t period, t_origin;
+  int64_t phase_start[GG_MAX_PHASES];
+  uint32_t phase_open[GG_MAX_PHASES];
+  double phase_cin[GG_MAX_PHASES][GG_MAX_SEGMENTS];
+  double seg_cin[GG_MAX_SEGMENTS];  // used when there is no schedule
+};
+
+// Storage traits: load into the compute type, store with rounding.
+template <class S> struct Pop;
+template <> struct Pop<double> {
+  using T = double;
+  static __device__ __forceinline__ T ld(const double *p, T) { return *p; }
+  static __device__ __forceinline__ void st(double *p, T v, T) { *p = v; }
+};
+template <> struct Pop<float> {
+  using T = float;
+  static __device__ __forceinline__ T ld(const float *p, T) { return *p; }
+  static __device__ __forceinline__ void st(float *p, T v, T) { *p = v; }
+};
+template <> struct Pop<__half> {
+  using T = float;
+  static __device__ __forceinline__ T ld(const __half *p, T shift) {
+    return __half2float(*p) + shift;
+  }
+  static __device__ __forceinline__ void st(__half *p, T v, T shift) {
+    *p = __float2half_rn(v - shift);
+  }
+};
+
+}  // namespace gg

@@ -1,0 +1,561 @@
+// gfx950 kernels of the coupled D2Q9 + D2Q5 lattice Boltzmann step.
+//
+// In-place AA streaming over structure-of-arrays planes. With A[x][i] the
+// slot of population i at node x, a time step t does, for every fluid node:
+//   even t: read A[x][i] = f_i(x,t); collide; write the value that must
+//           arrive at x along direction j into A[x][j] (the post-collision
+//           population of the opposite direction, or a boundary value).
+//   odd t : read f_i(x,t) from A[x - e_i][opp i] (or from A[x][i] where
+//           x - e_i is not fluid); collide; write f*_i into A[x + e_i][i]
+//           (or a boundary value into A[x][opp i] where x + e_i is not fluid).
+// Each slot is read and written by one node only within a step, so no
+// synchronisation between work-groups is needed, and every boundary rule
+// (paper Boundary Conditions section, read as bounce-back variants) uses
+// only the node's own post-collision populations and velocity.
+#include <algorithm>
+
+#include "gg_device.h"
+#include "gg_kernels.h"
+
+namespace gg {
+
+struct PhaseNow {
+  uint32_t open;
+  const double *cin;
+};
+
+// Valve phase in force during step t (fixed at the start of the step).
+__device__ __forceinline__ PhaseNow phase_at(const LatDesc &L, int64_t t) {
+  if (L.n_phases == 0) return {0xFFFFFFFFu, L.seg_cin};
+  int64_t tau = (t - L.t_origin) % L.period;
+  if (tau < 0) tau += L.period;
+  int k = 0;
+  while (k + 1 < L.n_phases && L.phase_start[k + 1] <= tau) ++k;
+  return {L.phase_open[k], L.phase_cin[k]};
+}
+
+// Sum over the 64 lanes of a wavefront; every lane must be active.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
+// Add per-lane boundary fluxes (up to two segments per lane, seg < 0 for
+// none) into the FP64 accumulators: one atomic per segment and wavefront.
+__device__ void flush_flux(double *flux, int sa, double ma, double ca, int sb,
+                           double mb, double cb) {
+#pragma unroll
+  for (int slot = 0; slot < 2; ++slot) {
+    const int seg = slot ? sb : sa;
+    const double dm = slot ? mb : ma;
+    const double dc = slot ? cb : ca;
+    unsigned long long pend = __ballot(seg >= 0);
+    while (pend) {
+      const int lead = __ffsll(pend) - 1;
+      const int s = __shfl(seg, lead);
+      const bool mine = seg == s;
+      const double a = wave_sum(mine ? dm : 0.0);
+      const double b = wave_sum(mine ? dc : 0.0);
+      if ((int)__lane_id() == lead) {
+        atomicAdd(flux + 2 * s, a);
+        atomicAdd(flux + 2 * s + 1, b);
+      }
+      pend &= ~__ballot(mine);
+    }
+  }
+}
+
+// Node index of x + e_k for k = 0..8, periodic wrap included; only used for
+// links whose neighbour is fluid (so never outside the lattice).
+struct Neigh {
+  int idx[9];
+  __device__ __forceinline__ Neigh(int x, int y, int nx, int ny, int pitch) {
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const int xx = EX[k] > 0 ? xp : (EX[k] < 0 ? xm : x);
+      const int yy = EY[k] > 0 ? yp : (EY[k] < 0 ? ym : y);
+      idx[k] = yy * pitch + xx;
+    }
+  }
+};
+
+// Populations f_i(x,t), g_i(x,t) in natural order for either parity.
+template <class S>
+__device__ __forceinline__ void load_state(const S *pop, int64_t ps, int node,
+                                           uint8_t lc, bool odd, const Neigh &nb,
+                                           const typename Pop<S>::T *shf,
+                                           const typename Pop<S>::T *shg,
+                                           typename Pop<S>::T *f,
+                                           typename Pop<S>::T *g) {
+  using P = Pop<S>;
+  if (!odd) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = P::ld(pop + i * ps + node, shf[i]);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) g[i] = P::ld(pop + (9 + i) * ps + node, shg[i]);
+  } else {
+    f[0] = P::ld(pop + node, shf[0]);
+    g[0] = P::ld(pop + 9 * ps + node, shg[0]);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const bool nf = (lc >> (OPP[i] - 1)) & 1;  // x - e_i not fluid
+      const S *a = nf ? pop + i * ps + node : pop + OPP[i] * ps + nb.idx[OPP[i]];
+      f[i] = P::ld(a, shf[i]);
+    }
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+      const bool nf = (lc >> (OPP[i] - 1)) & 1;
+      const S *a = nf ? pop + (9 + i) * ps + node
+                      : pop + (9 + OPP[i]) * ps + nb.idx[OPP[i]];
+      g[i] = P::ld(a, shg[i]);
+    }
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void shifts(const LatDesc &L, T *shf, T *shg) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) shf[i] = (T)(WF[i] * L.rho0);
+  shg[0] = (T)(L.w0 * L.c_shift);
+#pragma unroll
+  for (int i = 1; i < 5; ++i) shg[i] = (T)(L.wg_axis * L.c_shift);
+}
+
+// ---------------------------------------------------------------------------
+// The fused coupled step.
+// ---------------------------------------------------------------------------
+template <class S, int BS>
+__global__ void __launch_bounds__(BS)
+    k_step(const LatDesc *__restrict__ descs, const int4 *__restrict__ tiles,
+           int n_tiles, int per_xcd, int tx_shift, int dt) {
+  using P = Pop<S>;
+  using T = typename P::T;
+  // Work-groups are dealt to the 8 XCDs round-robin; give each XCD a
+  // contiguous run of tiles so neighbouring tiles share an L2.
+  const int tile = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (tile >= n_tiles) return;
+  const int4 tl = tiles[tile];
+  const LatDesc &L = descs[tl.x];
+  const int tmask = (1 << tx_shift) - 1;
+  const int x = tl.y + (int)(threadIdx.x & tmask);
+  const int y = tl.z + (int)(threadIdx.x >> tx_shift);
+  const int nx = L.nx, ny = L.ny, pitch = L.pitch;
+  const int64_t ps = L.plane;
+  const int64_t t = *L.t + dt;
+  const bool odd = (t & 1) != 0;
+  S *const pop = static_cast<S *>(L.pop);
+  const bool seg_tile = (tl.w & TILE_TOUCHES_SEGMENT) != 0;
+  PhaseNow ph{0u, nullptr};
+  if (seg_tile) ph = phase_at(L, t);
+
+  const int node = y * pitch + x;
+  const uint8_t lc = (x < nx && y < ny) ? L.link[node] : NOT_FLUID;
+
+  int sa = -1, sb = -1;
+  double ma = 0.0, ca = 0.0, mb = 0.0, cb = 0.0;
+
+  if (lc != NOT_FLUID) {
+    T shf[9], shg[5];
+    shifts<T>(L, shf, shg);
+    const Neigh nb(x, y, nx, ny, pitch);
+    T f[9], g[5];
+    load_state<S>(pop, ps, node, lc, odd, nb, shf, shg, f, g);
+
+    // Moments of f, paper Eq. 7 (sum over i = 0..8).
+    const T rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const T jy = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
+    const T inv_rho = T(1) / rho;
+    const T ux = jx * inv_rho, uy = jy * inv_rho;
+    const T usq = ux * ux + uy * uy;
+
+    // BGK relaxation of f toward the quadratic equilibrium, Eqs. 4-6.
+    const T om_f = (T)L.omega_f;
+    T pf[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const T eu = (T)EX[i] * ux + (T)EY[i] * uy;
+      const T feq = (T)WF[i] * rho * (T(1) + T(3) * eu + T(4.5) * eu * eu - T(1.5) * usq);
+      pf[i] = f[i] + om_f * (feq - f[i]);
+    }
+
+    // Compound: linear equilibrium with this node's u (Eq. 9), BGK (Eq. 8),
+    // source R - kC of Eq. 2 distributed with the lattice weights.
+    const T C = g[0] + g[1] + g[2] + g[3] + g[4];
+    const T wg[5] = {(T)L.w0, (T)L.wg_axis, (T)L.wg_axis, (T)L.wg_axis, (T)L.wg_axis};
+    const T ics = (T)L.inv_cs2g;
+    T src = -(T)L.k_decay * C;
+    if (L.has_source) {
+      const int rx = x - L.r_x0, ry = y - L.r_y0;
+      if (rx >= 0 && rx < L.r_w && ry >= 0 && ry < L.r_h)
+        src += (T)L.R[ry * L.r_w + rx];
+    }
+    const T om_g = (T)L.omega_g;
+    T pg[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      const T eu = (T)EX[i] * ux + (T)EY[i] * uy;
+      const T geq = wg[i] * C * (T(1) + eu * ics);
+      pg[i] = g[i] + om_g * (geq - g[i]) + wg[i] * src;
+    }
+
+    // Value arriving at x along direction j: from a fluid neighbour it is
+    // that neighbour's own business; for a wall or closed valve it is the
+    // bounced population f*(x, opp j); open segments overwrite below.
+    T in_f[9], in_g[5];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) in_f[j] = pf[OPP[j]];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) in_g[j] = pg[OPP[j]];
+
+    if (seg_tile && lc != 0) {
+      const T rho0 = (T)L.rho0;
+#pragma unroll
+      for (int j = 1; j < 9; ++j) {
+        if (!((lc >> (OPP[j] - 1)) & 1)) continue;  // x - e_j is fluid
+        int sx = x - EX[j], sy = y - EY[j];
+        bool inside = true;
+        if (sx < 0 || sx >= nx) {
+          if (L.periodic_x) sx = (sx + nx) % nx; else inside = false;
+        }
+        if (sy < 0 || sy >= ny) {
+          if (L.periodic_y) sy = (sy + ny) % ny; else inside = false;
+        }
+        const int code = inside ? (int)L.mask[sy * pitch + sx] : GG_MASK_WALL;
+        if (code < GG_FIRST_SEGMENT) continue;
+        const int s = code - GG_FIRST_SEGMENT;
+        if (!((ph.open >> s) & 1u)) continue;  // closed valve: a wall
+        T vf, vg = T(0);
+        if (L.seg_kind[s] == GG_SEG_INLET) {
+          // moving-wall bounce-back, wall velocity -n u(s) with a parabolic
+          // profile across the segment; anti-bounce-back for C_in
+          const T coord = L.seg_nx[s] != 0 ? (T)y : (T)x;
+          const T us = (T)(4.0 * L.seg_umax[s]) * (coord - (T)L.seg_s0[s]) *
+                       ((T)L.seg_s1[s] - coord) * (T)L.seg_inv_w2[s];
+          const T en = (T)(EX[j] * L.seg_nx[s] + EY[j] * L.seg_ny[s]);
+          vf = pf[OPP[j]] - T(6) * (T)WF[j] * rho0 * en * us;
+          if (j < 5) vg = -pg[OPP[j]] + T(2) * wg[j] * (T)ph.cin[s];
+        } else {
+          // outflow at the reference density with the node's own u;
+          // the compound leaves with zero gradient
+          const T eu = (T)EX[j] * ux + (T)EY[j] * uy;
+          vf = -pf[OPP[j]] + T(2) * (T)WF[j] * rho0 * (T(1) + T(4.5) * eu * eu - T(1.5) * usq);
+          if (j < 5) vg = pg[j];
+        }
+        double dm = (double)(vf - pf[OPP[j]]);
+        double dc = (j < 5) ? (double)(vg - pg[OPP[j]]) : 0.0;
+        in_f[j] = vf;
+        if (j < 5) in_g[j] = vg;
+        if (sa < 0 || sa == s) {
+          sa = s; ma += dm; ca += dc;
+        } else {
+          sb = s; mb += dm; cb += dc;
+        }
+      }
+    }
+
+    if (!odd) {
+      P::st(pop + node, pf[0], shf[0]);
+#pragma unroll
+      for (int j = 1; j < 9; ++j) P::st(pop + j * ps + node, in_f[j], shf[j]);
+      P::st(pop + 9 * ps + node, pg[0], shg[0]);
+#pragma unroll
+      for (int j = 1; j < 5; ++j) P::st(pop + (9 + j) * ps + node, in_g[j], shg[j]);
+    } else {
+      P::st(pop + node, pf[0], shf[0]);
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        const bool nft = (lc >> (i - 1)) & 1;  // x + e_i not fluid
+        S *a = nft ? pop + OPP[i] * ps + node : pop + i * ps + nb.idx[i];
+        P::st(a, nft ? in_f[OPP[i]] : pf[i], shf[i]);
+      }
+      P::st(pop + 9 * ps + node, pg[0], shg[0]);
+#pragma unroll
+      for (int i = 1; i < 5; ++i) {
+        const bool nft = (lc >> (i - 1)) & 1;
+        S *a = nft ? pop + (9 + OPP[i]) * ps + node : pop + (9 + i) * ps + nb.idx[i];
+        P::st(a, nft ? in_g[OPP[i]] : pg[i], shg[i]);
+      }
+    }
+  }
+
+  if (seg_tile) flush_flux(L.flux, sa, ma, ca, sb, mb, cb);
+}
+
+// ---------------------------------------------------------------------------
+// Equilibrium initialisation (natural order, t = 0).
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ void __launch_bounds__(256)
+    k_init(const LatDesc *__restrict__ desc, const int4 *__restrict__ tiles,
+           int n_tiles, int tx_shift, const double *__restrict__ rho_in,
+           const double *__restrict__ ux_in, const double *__restrict__ uy_in,
+           const double *__restrict__ c_in) {
+  using P = Pop<S>;
+  using T = typename P::T;
+  const int tile = blockIdx.x;
+  if (tile >= n_tiles) return;
+  const int4 tl = tiles[tile];
+  const LatDesc &L = *desc;
+  const int tmask = (1 << tx_shift) - 1;
+  const int x = tl.y + (int)(threadIdx.x & tmask);
+  const int y = tl.z + (int)(threadIdx.x >> tx_shift);
+  if (x >= L.nx || y >= L.ny) return;
+  const int node = y * L.pitch + x;
+  const int64_t ps = L.plane;
+  S *const pop = static_cast<S *>(L.pop);
+  T shf[9], shg[5];
+  shifts<T>(L, shf, shg);
+  if (L.link[node] == NOT_FLUID) {
+    for (int i = 0; i < 9; ++i) P::st(pop + i * ps + node, shf[i], shf[i]);
+    for (int i = 0; i < 5; ++i) P::st(pop + (9 + i) * ps + node, shg[i], shg[i]);
+    return;
+  }
+  const int k = y * L.nx + x;
+  const T rho = rho_in ? (T)rho_in[k] : (T)L.rho0;
+  const T ux = ux_in ? (T)ux_in[k] : T(0);
+  const T uy = uy_in ? (T)uy_in[k] : T(0);
+  const T C = c_in ? (T)c_in[k] : T(0);
+  const T usq = ux * ux + uy * uy;
+  for (int i = 0; i < 9; ++i) {
+    const T eu = (T)EX[i] * ux + (T)EY[i] * uy;
+    const T feq = (T)WF[i] * rho * (T(1) + T(3) * eu + T(4.5) * eu * eu - T(1.5) * usq);
+    P::st(pop + i * ps + node, feq, shf[i]);
+  }
+  const T ics = (T)L.inv_cs2g;
+  for (int i = 0; i < 5; ++i) {
+    const T w = i == 0 ? (T)L.w0 : (T)L.wg_axis;
+    const T eu = (T)EX[i] * ux + (T)EY[i] * uy;
+    P::st(pop + (9 + i) * ps + node, w * C * (T(1) + eu * ics), shg[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Read-back: macroscopic fields and natural-order populations (FP64 out).
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ void __launch_bounds__(256)
+    k_read(const LatDesc *__restrict__ desc, const int4 *__restrict__ tiles,
+           int n_tiles, int tx_shift, double *__restrict__ rho_out,
+           double *__restrict__ ux_out, double *__restrict__ uy_out,
+           double *__restrict__ c_out, double *__restrict__ f_out,
+           double *__restrict__ g_out) {
+  using P = Pop<S>;
+  using T = typename P::T;
+  const int tile = blockIdx.x;
+  if (tile >= n_tiles) return;
+  const int4 tl = tiles[tile];
+  const LatDesc &L = *desc;
+  const int tmask = (1 << tx_shift) - 1;
+  const int x = tl.y + (int)(threadIdx.x & tmask);
+  const int y = tl.z + (int)(threadIdx.x >> tx_shift);
+  if (x >= L.nx || y >= L.ny) return;
+  const int node = y * L.pitch + x;
+  const uint8_t lc = L.link[node];
+  if (lc == NOT_FLUID) return;
+  const bool odd = (*L.t & 1) != 0;
+  T shf[9], shg[5];
+  shifts<T>(L, shf, shg);
+  const Neigh nb(x, y, L.nx, L.ny, L.pitch);
+  T fT[9], gT[5];
+  load_state<S>(static_cast<const S *>(L.pop), L.plane, node, lc, odd, nb, shf, shg, fT, gT);
+  const int64_t n = (int64_t)L.nx * L.ny;
+  const int k = y * L.nx + x;
+  double f[9], g[5];
+  for (int i = 0; i < 9; ++i) f[i] = (double)fT[i];
+  for (int i = 0; i < 5; ++i) g[i] = (double)gT[i];
+  if (f_out)
+    for (int i = 0; i < 9; ++i) f_out[i * n + k] = f[i];
+  if (g_out)
+    for (int i = 0; i < 5; ++i) g_out[i * n + k] = g[i];
+  const double rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+  const double jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+  const double jy = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
+  if (rho_out) rho_out[k] = rho;
+  if (ux_out) ux_out[k] = jx / rho;
+  if (uy_out) uy_out[k] = jy / rho;
+  if (c_out) c_out[k] = g[0] + g[1] + g[2] + g[3] + g[4];
+}
+
+// Fills nx*ny doubles with a value (marks non-fluid nodes before k_read).
+__global__ void k_fill(double *__restrict__ p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 diagnostics: wavefront reductions, one atomic per wavefront.
+// acc: [0] mass, [1] solute, [2] max|u| bits, [3] max|u| region bits,
+//      [4] non-finite count, [5] fluid count
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ void __launch_bounds__(256)
+    k_reduce(const LatDesc *__restrict__ desc, const int4 *__restrict__ tiles,
+             int n_tiles, int tx_shift, double *__restrict__ acc) {
+  using P = Pop<S>;
+  using T = typename P::T;
+  const int tile = blockIdx.x;
+  if (tile >= n_tiles) return;
+  const int4 tl = tiles[tile];
+  const LatDesc &L = *desc;
+  const int tmask = (1 << tx_shift) - 1;
+  const int x = tl.y + (int)(threadIdx.x & tmask);
+  const int y = tl.z + (int)(threadIdx.x >> tx_shift);
+  const int node = y * L.pitch + x;
+  const uint8_t lc = (x < L.nx && y < L.ny) ? L.link[node] : NOT_FLUID;
+  double m = 0.0, c = 0.0, um = 0.0, ur = 0.0, bad = 0.0, cnt = 0.0;
+  if (lc != NOT_FLUID) {
+    const bool odd = (*L.t & 1) != 0;
+    T shf[9], shg[5];
+    shifts<T>(L, shf, shg);
+    const Neigh nb(x, y, L.nx, L.ny, L.pitch);
+    T fT[9], gT[5];
+    load_state<S>(static_cast<const S *>(L.pop), L.plane, node, lc, odd, nb, shf, shg, fT, gT);
+    double rho = 0.0, jx = 0.0, jy = 0.0, C = 0.0;
+    bool finite = true;
+    for (int i = 0; i < 9; ++i) {
+      const double v = (double)fT[i];
+      finite = finite && isfinite(v);
+      rho += v;
+      jx += EX[i] * v;
+      jy += EY[i] * v;
+    }
+    for (int i = 0; i < 5; ++i) {
+      const double v = (double)gT[i];
+      finite = finite && isfinite(v);
+      C += v;
+    }
+    cnt = 1.0;
+    if (finite) {
+      m = rho;
+      c = C;
+      um = sqrt(jx * jx + jy * jy) / rho;
+      if (L.has_region && L.region[node]) ur = um;
+    } else {
+      bad = 1.0;
+    }
+  }
+  m = wave_sum(m);
+  c = wave_sum(c);
+  bad = wave_sum(bad);
+  cnt = wave_sum(cnt);
+  um = wave_max(um);
+  ur = wave_max(ur);
+  if (__lane_id() == 0 && cnt > 0.0) {
+    atomicAdd(acc + 0, m);
+    atomicAdd(acc + 1, c);
+    // non-negative doubles order like their bit patterns
+    atomicMax(reinterpret_cast<unsigned long long *>(acc + 2), (unsigned long long)__double_as_longlong(um));
+    atomicMax(reinterpret_cast<unsigned long long *>(acc + 3), (unsigned long long)__double_as_longlong(ur));
+    atomicAdd(acc + 4, bad);
+    atomicAdd(acc + 5, cnt);
+  }
+}
+
+// Plain streaming copy, 16 bytes per lane per iteration.
+__global__ void __launch_bounds__(256) k_copy(int4 *__restrict__ dst, const int4 *__restrict__ src, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// Advance the step counters of n lattices by k (after k step launches).
+__global__ void k_advance(const LatDesc *__restrict__ descs, int n, int64_t k) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) *descs[i].t += k;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch wrappers.
+// ---------------------------------------------------------------------------
+template <class S>
+static hipError_t launch_step_s(int bs, const LatDesc *d, const int4 *tiles, int n_tiles,
+                                int tx_shift, int dt, hipStream_t st) {
+  const int per_xcd = (n_tiles + 7) / 8;
+  const dim3 grid(8 * per_xcd);
+  switch (bs) {
+    case 64: k_step<S, 64><<<grid, 64, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
+    case 128: k_step<S, 128><<<grid, 128, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
+    case 256: k_step<S, 256><<<grid, 256, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
+    case 512: k_step<S, 512><<<grid, 512, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_step(gg_storage s, int block, const LatDesc *d, const int4 *tiles,
+                       int n_tiles, int tx_shift, int dt, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (s) {
+    case GG_F64: return launch_step_s<double>(block, d, tiles, n_tiles, tx_shift, dt, st);
+    case GG_F32: return launch_step_s<float>(block, d, tiles, n_tiles, tx_shift, dt, st);
+    case GG_F16_SHIFTED: return launch_step_s<__half>(block, d, tiles, n_tiles, tx_shift, dt, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// The auxiliary kernels run 256-thread work-groups over 256-node tiles.
+hipError_t launch_init(gg_storage s, const LatDesc *d, const int4 *tiles, int n_tiles,
+                       int tx_shift, const double *rho, const double *ux,
+                       const double *uy, const double *c, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (s) {
+    case GG_F64: k_init<double><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, rho, ux, uy, c); break;
+    case GG_F32: k_init<float><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, rho, ux, uy, c); break;
+    case GG_F16_SHIFTED: k_init<__half><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, rho, ux, uy, c); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_read(gg_storage s, const LatDesc *d, const int4 *tiles, int n_tiles,
+                       int tx_shift, double *rho, double *ux, double *uy, double *c,
+                       double *f, double *g, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (s) {
+    case GG_F64: k_read<double><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, rho, ux, uy, c, f, g); break;
+    case GG_F32: k_read<float><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, rho, ux, uy, c, f, g); break;
+    case GG_F16_SHIFTED: k_read<__half><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, rho, ux, uy, c, f, g); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_fill<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(gg_storage s, const LatDesc *d, const int4 *tiles, int n_tiles,
+                         int tx_shift, double *acc, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (s) {
+    case GG_F64: k_reduce<double><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, acc); break;
+    case GG_F32: k_reduce<float><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, acc); break;
+    case GG_F16_SHIFTED: k_reduce<__half><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, acc); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st) {
+  const int64_t n = (int64_t)(bytes / 16);
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 256 * 64);
+  if (n > 0)
+    k_copy<<<(unsigned)blocks, 256, 0, st>>>(static_cast<int4 *>(dst), static_cast<const int4 *>(src), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(const LatDesc *descs, int n, int64_t k, hipStream_t st) {
+  k_advance<<<(n + 63) / 64, 64, 0, st>>>(descs, n, k);
+  return hipGetLastError();
+}
+
+}  // namespace gg

@@ -1,0 +1,55 @@
+// Host-side lattice object shared by the runtime translation units.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "gg_device.h"
+
+struct SegHost {
+  bool set = false;
+  int kind = 0;
+  int nrm_x = 0, nrm_y = 0;
+  double u_max = 0.0, c_in = 0.0;
+  double s0 = 0.0, s1 = 1.0;  // halfway-wall tangential coordinates
+};
+
+struct gg_lattice {
+  int32_t nx = 0, ny = 0, pitch = 0;
+  int64_t plane = 0;
+  gg_storage storage = GG_F32;
+  size_t esize = 4;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  gg_params p{};
+  double tau_g = 0.0, cs2g = 0.0;
+  std::vector<uint8_t> mask;         // nx*ny
+  std::vector<uint8_t> link;         // pitch*ny link codes
+  std::vector<uint8_t> touches_seg;  // nx*ny: fluid node next to a segment
+  int64_t n_fluid = 0;
+  SegHost seg[GG_MAX_SEGMENTS];
+  bool seg_present[GG_MAX_SEGMENTS] = {};
+  std::vector<gg_phase> phases;
+  int64_t t_origin = 0;
+  int64_t t = 0;  // host mirror of the device counter
+  int r_box[4] = {0, 0, 0, 0};
+
+  void *d_pop = nullptr;
+  uint8_t *d_link = nullptr, *d_mask = nullptr, *d_region = nullptr;
+  double *d_R = nullptr;
+  int64_t *d_t = nullptr;
+  double *d_flux = nullptr, *d_acc = nullptr;
+  gg::LatDesc *d_desc = nullptr;
+  gg::LatDesc h{};
+  int4 *d_tiles = nullptr;
+  int n_tiles = 0, tile_x = 64, tile_y = 4;
+  int4 *d_aux_tiles = nullptr;
+  int n_aux_tiles = 0;
+  int graph_chunk = 64;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+};
+
+gg_status gg_upload_desc(gg_lattice *L);
+gg_status gg_rebuild_tiles(gg_lattice *L);
+void gg_free_device(gg_lattice *L);

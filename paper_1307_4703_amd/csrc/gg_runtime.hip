@@ -1,0 +1,744 @@
+// Host runtime behind the C ABI of include/gg.h: geometry classification,
+// boundary segments, valve schedule, device memory, launches and graphs.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gg_device.h"
+#include "gg_kernels.h"
+#include "gg_runtime.h"
+
+using namespace gg;
+
+namespace {
+
+thread_local std::string g_err;
+
+gg_status fail(gg_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+#define GG_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return fail(GG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t storage_bytes(gg_storage s) {
+  switch (s) {
+    case GG_F64: return 8;
+    case GG_F32: return 4;
+    case GG_F16_SHIFTED: return 2;
+  }
+  return 0;
+}
+
+int ilog2(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Lattice object
+// ---------------------------------------------------------------------------
+
+void gg_free_device(gg_lattice *L) {
+  if (L->graph_exec) (void)hipGraphExecDestroy(L->graph_exec);
+  if (L->graph) (void)hipGraphDestroy(L->graph);
+  L->graph_exec = nullptr;
+  L->graph = nullptr;
+  void *ptrs[] = {L->d_pop, L->d_link, L->d_mask, L->d_region, L->d_R, L->d_t,
+                  L->d_flux, L->d_acc, L->d_desc, L->d_tiles, L->d_aux_tiles};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (L->cap_stream) (void)hipStreamDestroy(L->cap_stream);
+}
+
+gg_status gg_upload_desc(gg_lattice *L) {
+  LatDesc &h = L->h;
+  std::memset(&h, 0, sizeof(h));
+  h.nx = L->nx;
+  h.ny = L->ny;
+  h.pitch = L->pitch;
+  h.periodic_x = L->p.periodic_x != 0;
+  h.periodic_y = L->p.periodic_y != 0;
+  h.plane = L->plane;
+  h.pop = L->d_pop;
+  h.link = L->d_link;
+  h.mask = L->d_mask;
+  h.region = L->d_region;
+  h.has_region = L->d_region != nullptr;
+  h.R = L->d_R;
+  h.has_source = L->d_R != nullptr;
+  h.r_x0 = L->r_box[0];
+  h.r_y0 = L->r_box[1];
+  h.r_w = L->r_box[2];
+  h.r_h = L->r_box[3];
+  h.t = L->d_t;
+  h.flux = L->d_flux;
+  h.omega_f = 1.0 / L->p.tau_f;
+  h.omega_g = 1.0 / L->tau_g;
+  h.w0 = L->p.w0;
+  h.wg_axis = (1.0 - L->p.w0) / 4.0;
+  h.inv_cs2g = 1.0 / L->cs2g;
+  h.rho0 = L->p.rho0;
+  h.k_decay = L->p.k_decay;
+  h.c_shift = L->p.c_shift;
+  for (int s = 0; s < GG_MAX_SEGMENTS; ++s) {
+    const SegHost &g = L->seg[s];
+    h.seg_kind[s] = g.set ? g.kind : 0;
+    h.seg_nx[s] = g.nrm_x;
+    h.seg_ny[s] = g.nrm_y;
+    h.seg_umax[s] = g.u_max;
+    h.seg_s0[s] = g.s0;
+    h.seg_s1[s] = g.s1;
+    h.seg_inv_w2[s] = g.set ? 1.0 / ((g.s1 - g.s0) * (g.s1 - g.s0)) : 0.0;
+    h.seg_cin[s] = g.c_in;
+  }
+  h.n_phases = (int32_t)L->phases.size();
+  h.t_origin = L->t_origin;
+  int64_t start = 0;
+  for (size_t k = 0; k < L->phases.size(); ++k) {
+    const gg_phase &ph = L->phases[k];
+    h.phase_start[k] = start;
+    start += ph.duration;
+    h.phase_open[k] = ph.open_mask;
+    for (int s = 0; s < GG_MAX_SEGMENTS; ++s)
+      h.phase_cin[k][s] = ((ph.c_in_set >> s) & 1u) ? ph.c_in[s] : L->seg[s].c_in;
+  }
+  h.period = start > 0 ? start : 1;
+  GG_HIP(hipMemcpyAsync(L->d_desc, &h, sizeof(h), hipMemcpyHostToDevice, L->stream));
+  GG_HIP(hipStreamSynchronize(L->stream));
+  return GG_OK;
+}
+
+// Tiles of tx*ty nodes holding at least one fluid node, row-major.
+static void build_tiles(const gg_lattice *L, int tx, int ty, int inst,
+                        std::vector<int4> &out) {
+  for (int y0 = 0; y0 < L->ny; y0 += ty)
+    for (int x0 = 0; x0 < L->nx; x0 += tx) {
+      bool any = false, seg = false;
+      for (int y = y0; y < std::min(y0 + ty, L->ny); ++y)
+        for (int x = x0; x < std::min(x0 + tx, L->nx); ++x) {
+          if (L->link[(size_t)y * L->pitch + x] == NOT_FLUID) continue;
+          any = true;
+          if (L->touches_seg[(size_t)y * L->nx + x]) seg = true;
+        }
+      if (any) out.push_back(make_int4(inst, x0, y0, seg ? TILE_TOUCHES_SEGMENT : 0));
+    }
+}
+
+gg_status gg_rebuild_tiles(gg_lattice *L) {
+  std::vector<int4> t;
+  build_tiles(L, L->tile_x, L->tile_y, 0, t);
+  if (L->d_tiles) (void)hipFree(L->d_tiles);
+  L->d_tiles = nullptr;
+  L->n_tiles = (int)t.size();
+  if (!t.empty()) {
+    GG_HIP(hipMalloc(&L->d_tiles, t.size() * sizeof(int4)));
+    GG_HIP(hipMemcpy(L->d_tiles, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
+  }
+  if (L->graph_exec) (void)hipGraphExecDestroy(L->graph_exec);
+  if (L->graph) (void)hipGraphDestroy(L->graph);
+  L->graph_exec = nullptr;
+  L->graph = nullptr;
+  return GG_OK;
+}
+
+static gg_status check_params(const gg_params *p) {
+  if (!p) return fail(GG_ERR_ARG, "params is NULL");
+  if (!(p->tau_f > 0.5)) return fail(GG_ERR_ARG, "tau_f must exceed 1/2");
+  if (!(p->D > 0.0)) return fail(GG_ERR_ARG, "D must be positive");
+  if (!(p->w0 >= 0.0 && p->w0 < 1.0)) return fail(GG_ERR_ARG, "w0 must lie in [0, 1)");
+  if (!(p->rho0 > 0.0)) return fail(GG_ERR_ARG, "rho0 must be positive");
+  if (!(p->k_decay >= 0.0)) return fail(GG_ERR_ARG, "k_decay must be non-negative");
+  if (!std::isfinite(p->c_shift)) return fail(GG_ERR_ARG, "c_shift must be finite");
+  return GG_OK;
+}
+
+extern "C" {
+
+const char *gg_last_error(void) { return g_err.c_str(); }
+
+gg_status gg_create(const uint8_t *mask, int32_t nx, int32_t ny, const gg_params *params,
+                    gg_storage storage, void *hip_stream, gg_lattice **out) {
+  if (!out) return fail(GG_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!mask) return fail(GG_ERR_ARG, "mask is NULL");
+  if (nx < 1 || ny < 1) return fail(GG_ERR_ARG, "lattice dimensions must be positive");
+  const size_t esize = storage_bytes(storage);
+  if (esize == 0) return fail(GG_ERR_ARG, "unknown storage");
+  gg_status st = check_params(params);
+  if (st != GG_OK) return st;
+  const int pitch = (nx + 63) / 64 * 64;
+  if ((int64_t)pitch * ny > (int64_t)0x7FFFFFFF - 64)
+    return fail(GG_ERR_ARG, "lattice too large for 32-bit node indices");
+
+  gg_lattice *L = new gg_lattice();
+  L->nx = nx;
+  L->ny = ny;
+  L->pitch = pitch;
+  // Plane stride: whole rows plus a 1.25 KiB-ish stagger so that the 14
+  // population planes do not start on the same DRAM channel.
+  L->plane = (int64_t)pitch * ny + 320;
+  L->storage = storage;
+  L->esize = esize;
+  L->stream = (hipStream_t)hip_stream;
+  L->p = *params;
+  L->cs2g = (1.0 - params->w0) / 2.0;
+  L->tau_g = 0.5 + params->D / L->cs2g;
+  L->mask.assign(mask, mask + (size_t)nx * ny);
+  L->t_origin = 0;
+  L->t = 0;
+
+  // classify links
+  L->link.assign((size_t)pitch * ny, NOT_FLUID);
+  L->touches_seg.assign((size_t)nx * ny, 0);
+  int64_t nf = 0;
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      const uint8_t m = L->mask[(size_t)y * nx + x];
+      if (m > GG_FIRST_SEGMENT + GG_MAX_SEGMENTS - 1) {
+        gg_status s = fail(GG_ERR_MASK, "mask value " + std::to_string(m) + " at (" +
+                                            std::to_string(x) + "," + std::to_string(y) +
+                                            ") is not 0, 1 or a segment id 2..17");
+        delete L;
+        return s;
+      }
+      if (m >= GG_FIRST_SEGMENT) L->seg_present[m - GG_FIRST_SEGMENT] = true;
+      if (m != GG_MASK_FLUID) continue;
+      uint8_t code = 0;
+      int segs[8], nseg = 0;
+      for (int k = 1; k < 9; ++k) {
+        int xx = x + EX[k], yy = y + EY[k];
+        bool inside = true;
+        if (xx < 0 || xx >= nx) {
+          if (params->periodic_x) xx = (xx + nx) % nx; else inside = false;
+        }
+        if (yy < 0 || yy >= ny) {
+          if (params->periodic_y) yy = (yy + ny) % ny; else inside = false;
+        }
+        const uint8_t mm = inside ? L->mask[(size_t)yy * nx + xx] : (uint8_t)GG_MASK_WALL;
+        if (mm != GG_MASK_FLUID) code |= (uint8_t)(1u << (k - 1));
+        if (mm >= GG_FIRST_SEGMENT) {
+          bool seen = false;
+          for (int q = 0; q < nseg; ++q) seen = seen || segs[q] == mm;
+          if (!seen) segs[nseg++] = mm;
+        }
+      }
+      if (code == NOT_FLUID) {
+        gg_status s = fail(GG_ERR_MASK, "fluid node (" + std::to_string(x) + "," +
+                                            std::to_string(y) + ") has no fluid neighbour");
+        delete L;
+        return s;
+      }
+      if (nseg > 2) {
+        gg_status s = fail(GG_ERR_MASK, "fluid node (" + std::to_string(x) + "," +
+                                            std::to_string(y) + ") touches more than two segments");
+        delete L;
+        return s;
+      }
+      L->touches_seg[(size_t)y * nx + x] = nseg > 0;
+      L->link[(size_t)y * pitch + x] = code;
+      ++nf;
+    }
+  L->n_fluid = nf;
+
+  auto alloc = [&](void **p, size_t bytes) -> gg_status {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return fail(GG_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    return GG_OK;
+  };
+  const size_t pop_bytes = (size_t)NPOP * L->plane * esize;
+  if ((st = alloc(&L->d_pop, pop_bytes)) != GG_OK ||
+      (st = alloc((void **)&L->d_link, (size_t)pitch * ny)) != GG_OK ||
+      (st = alloc((void **)&L->d_mask, (size_t)pitch * ny)) != GG_OK ||
+      (st = alloc((void **)&L->d_t, sizeof(int64_t))) != GG_OK ||
+      (st = alloc((void **)&L->d_flux, 2 * GG_MAX_SEGMENTS * sizeof(double))) != GG_OK ||
+      (st = alloc((void **)&L->d_acc, 8 * sizeof(double))) != GG_OK ||
+      (st = alloc((void **)&L->d_desc, sizeof(LatDesc))) != GG_OK) {
+    gg_free_device(L);
+    delete L;
+    return st;
+  }
+  std::vector<uint8_t> mpitch((size_t)pitch * ny, GG_MASK_WALL);
+  for (int y = 0; y < ny; ++y)
+    std::memcpy(&mpitch[(size_t)y * pitch], &L->mask[(size_t)y * nx], nx);
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMemcpy(L->d_link, L->link.data(), L->link.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(L->d_mask, mpitch.data(), mpitch.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(L->d_pop, 0, pop_bytes);
+  if (e == hipSuccess) e = hipMemset(L->d_t, 0, sizeof(int64_t));
+  if (e == hipSuccess) e = hipMemset(L->d_flux, 0, 2 * GG_MAX_SEGMENTS * sizeof(double));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&L->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    gg_status s = fail(GG_ERR_HIP, std::string("lattice set-up: ") + hipGetErrorString(e));
+    gg_free_device(L);
+    delete L;
+    return s;
+  }
+  // auxiliary kernels always run 64 x 4 tiles
+  std::vector<int4> aux;
+  build_tiles(L, 64, 4, 0, aux);
+  L->n_aux_tiles = (int)aux.size();
+  if (!aux.empty()) {
+    if ((st = alloc((void **)&L->d_aux_tiles, aux.size() * sizeof(int4))) != GG_OK) {
+      gg_free_device(L);
+      delete L;
+      return st;
+    }
+    if (hipMemcpy(L->d_aux_tiles, aux.data(), aux.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess) {
+      gg_free_device(L);
+      delete L;
+      return fail(GG_ERR_HIP, "upload of the tile list failed");
+    }
+  }
+  L->tile_x = 64;
+  L->tile_y = 4;
+  L->graph_chunk = 64;
+  if ((st = gg_rebuild_tiles(L)) != GG_OK || (st = gg_upload_desc(L)) != GG_OK ||
+      (st = gg_init(L, nullptr, nullptr, nullptr, nullptr, GG_HOST)) != GG_OK) {
+    gg_free_device(L);
+    delete L;
+    return st;
+  }
+  *out = L;
+  return GG_OK;
+}
+
+void gg_destroy(gg_lattice *L) {
+  if (!L) return;
+  (void)hipStreamSynchronize(L->stream);
+  gg_free_device(L);
+  delete L;
+}
+
+gg_status gg_set_segment(gg_lattice *L, int32_t id, gg_seg_kind kind, int32_t nrm_x,
+                         int32_t nrm_y, double u_max, double c_in) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (id < GG_FIRST_SEGMENT || id >= GG_FIRST_SEGMENT + GG_MAX_SEGMENTS)
+    return fail(GG_ERR_ARG, "segment id must lie in 2..17");
+  if (kind != GG_SEG_INLET && kind != GG_SEG_OUTLET) return fail(GG_ERR_ARG, "unknown segment kind");
+  if (std::abs(nrm_x) + std::abs(nrm_y) != 1) return fail(GG_ERR_ARG, "normal must be an axis unit vector");
+  if (!std::isfinite(u_max) || !std::isfinite(c_in)) return fail(GG_ERR_ARG, "u_max and c_in must be finite");
+  int smin = 1 << 30, smax = -(1 << 30);
+  int64_t cells = 0;
+  for (int y = 0; y < L->ny; ++y)
+    for (int x = 0; x < L->nx; ++x) {
+      if (L->mask[(size_t)y * L->nx + x] != id) continue;
+      ++cells;
+      int xi = x - nrm_x, yi = y - nrm_y;
+      bool inside = true;
+      if (xi < 0 || xi >= L->nx) {
+        if (L->p.periodic_x) xi = (xi + L->nx) % L->nx; else inside = false;
+      }
+      if (yi < 0 || yi >= L->ny) {
+        if (L->p.periodic_y) yi = (yi + L->ny) % L->ny; else inside = false;
+      }
+      if (!inside || L->mask[(size_t)yi * L->nx + xi] != GG_MASK_FLUID)
+        return fail(GG_ERR_MASK, "segment " + std::to_string(id) + " ghost cell (" +
+                                     std::to_string(x) + "," + std::to_string(y) +
+                                     ") has no fluid cell against its normal");
+      const int s = nrm_x != 0 ? y : x;
+      smin = std::min(smin, s);
+      smax = std::max(smax, s);
+    }
+  if (cells == 0) return fail(GG_ERR_MASK, "segment " + std::to_string(id) + " has no cells in the mask");
+  SegHost &g = L->seg[id - GG_FIRST_SEGMENT];
+  g.set = true;
+  g.kind = kind;
+  g.nrm_x = nrm_x;
+  g.nrm_y = nrm_y;
+  g.u_max = u_max;
+  g.c_in = c_in;
+  g.s0 = smin - 0.5;
+  g.s1 = smax + 0.5;
+  return gg_upload_desc(L);
+}
+
+gg_status gg_set_schedule(gg_lattice *L, const gg_phase *phases, int32_t n, int64_t t_origin) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (n < 0 || n > GG_MAX_PHASES) return fail(GG_ERR_ARG, "n_phases must lie in 0..64");
+  if (n > 0 && !phases) return fail(GG_ERR_ARG, "phases is NULL");
+  int64_t period = 0;
+  for (int k = 0; k < n; ++k) {
+    if (phases[k].duration <= 0) return fail(GG_ERR_ARG, "phase durations must be positive");
+    if (phases[k].open_mask >> GG_MAX_SEGMENTS) return fail(GG_ERR_ARG, "open_mask has bits beyond segment 17");
+    period += phases[k].duration;
+    if (period > ((int64_t)1 << 60)) return fail(GG_ERR_ARG, "schedule period too long");
+  }
+  L->phases.assign(phases, phases + n);
+  L->t_origin = t_origin;
+  return gg_upload_desc(L);
+}
+
+gg_status gg_set_source(gg_lattice *L, const double *R, gg_where where) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (L->d_R) (void)hipFree(L->d_R);
+  L->d_R = nullptr;
+  L->r_box[0] = L->r_box[1] = L->r_box[2] = L->r_box[3] = 0;
+  if (R) {
+    const size_t n = (size_t)L->nx * L->ny;
+    std::vector<double> h(n);
+    if (where == GG_DEVICE) {
+      GG_HIP(hipStreamSynchronize(L->stream));
+      GG_HIP(hipMemcpy(h.data(), R, n * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+      std::memcpy(h.data(), R, n * sizeof(double));
+    }
+    int x0 = L->nx, y0 = L->ny, x1 = -1, y1 = -1;
+    for (int y = 0; y < L->ny; ++y)
+      for (int x = 0; x < L->nx; ++x) {
+        const double v = h[(size_t)y * L->nx + x];
+        if (!std::isfinite(v)) return fail(GG_ERR_ARG, "source has non-finite entries");
+        if (v != 0.0 && L->mask[(size_t)y * L->nx + x] == GG_MASK_FLUID) {
+          x0 = std::min(x0, x); x1 = std::max(x1, x);
+          y0 = std::min(y0, y); y1 = std::max(y1, y);
+        }
+      }
+    if (x1 >= 0) {
+      const int w = x1 - x0 + 1, hh = y1 - y0 + 1;
+      std::vector<double> patch((size_t)w * hh);
+      for (int y = 0; y < hh; ++y)
+        for (int x = 0; x < w; ++x) patch[(size_t)y * w + x] = h[(size_t)(y0 + y) * L->nx + x0 + x];
+      GG_HIP(hipMalloc(&L->d_R, patch.size() * sizeof(double)));
+      GG_HIP(hipMemcpy(L->d_R, patch.data(), patch.size() * sizeof(double), hipMemcpyHostToDevice));
+      L->r_box[0] = x0; L->r_box[1] = y0; L->r_box[2] = w; L->r_box[3] = hh;
+    }
+  }
+  return gg_upload_desc(L);
+}
+
+gg_status gg_set_region(gg_lattice *L, const uint8_t *region) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (L->d_region) (void)hipFree(L->d_region);
+  L->d_region = nullptr;
+  if (region) {
+    std::vector<uint8_t> r((size_t)L->pitch * L->ny, 0);
+    for (int y = 0; y < L->ny; ++y)
+      for (int x = 0; x < L->nx; ++x) r[(size_t)y * L->pitch + x] = region[(size_t)y * L->nx + x] ? 1 : 0;
+    GG_HIP(hipMalloc(&L->d_region, r.size()));
+    GG_HIP(hipMemcpy(L->d_region, r.data(), r.size(), hipMemcpyHostToDevice));
+  }
+  return gg_upload_desc(L);
+}
+
+gg_status gg_init(gg_lattice *L, const double *rho, const double *ux, const double *uy,
+                  const double *C, gg_where where) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  const size_t n = (size_t)L->nx * L->ny;
+  const double *src[4] = {rho, ux, uy, C};
+  double *dev[4] = {nullptr, nullptr, nullptr, nullptr};
+  gg_status st = GG_OK;
+  if (where == GG_HOST) {
+    for (int q = 0; q < 4 && st == GG_OK; ++q) {
+      if (!src[q]) continue;
+      if (hipMalloc(&dev[q], n * sizeof(double)) != hipSuccess) {
+        st = fail(GG_ERR_OOM, "hipMalloc of an initial field failed");
+        break;
+      }
+      if (hipMemcpy(dev[q], src[q], n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        st = fail(GG_ERR_HIP, "copy of an initial field failed");
+    }
+  } else {
+    for (int q = 0; q < 4; ++q) dev[q] = const_cast<double *>(src[q]);
+  }
+  if (st == GG_OK) {
+    hipError_t e = launch_init(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6,
+                               dev[0], dev[1], dev[2], dev[3], L->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(L->d_t, 0, sizeof(int64_t), L->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(L->d_flux, 0, 2 * GG_MAX_SEGMENTS * sizeof(double), L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) st = fail(GG_ERR_HIP, std::string("init: ") + hipGetErrorString(e));
+  }
+  if (where == GG_HOST)
+    for (int q = 0; q < 4; ++q)
+      if (dev[q]) (void)hipFree(dev[q]);
+  if (st == GG_OK) L->t = 0;
+  return st;
+}
+
+static gg_status check_segments(gg_lattice *L) {
+  for (int s = 0; s < GG_MAX_SEGMENTS; ++s)
+    if (L->seg_present[s] && !L->seg[s].set)
+      return fail(GG_ERR_STATE, "segment " + std::to_string(s + GG_FIRST_SEGMENT) +
+                                    " is in the mask but was not configured");
+  return GG_OK;
+}
+
+gg_status gg_step(gg_lattice *L, int64_t n) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (n < 0) return fail(GG_ERR_ARG, "n must be non-negative");
+  gg_status st = check_segments(L);
+  if (st != GG_OK) return st;
+  const int block = L->tile_x * L->tile_y;
+  const int txs = ilog2(L->tile_x);
+  int64_t left = n;
+  const int K = L->graph_chunk;
+  if (K > 0 && left >= K) {
+    if (!L->graph_exec) {
+      GG_HIP(hipStreamBeginCapture(L->cap_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e = hipSuccess;
+      for (int dt = 0; dt < K && e == hipSuccess; ++dt)
+        e = launch_step(L->storage, block, L->d_desc, L->d_tiles, L->n_tiles, txs, dt, L->cap_stream);
+      if (e == hipSuccess) e = launch_advance(L->d_desc, 1, K, L->cap_stream);
+      hipGraph_t g = nullptr;
+      hipError_t e2 = hipStreamEndCapture(L->cap_stream, &g);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(GG_ERR_HIP, std::string("graph capture: ") +
+                                    hipGetErrorString(e != hipSuccess ? e : e2));
+      }
+      L->graph = g;
+      GG_HIP(hipGraphInstantiate(&L->graph_exec, L->graph, nullptr, nullptr, 0));
+    }
+    while (left >= K) {
+      GG_HIP(hipGraphLaunch(L->graph_exec, L->stream));
+      left -= K;
+      L->t += K;
+    }
+  }
+  if (left > 0) {
+    for (int64_t dt = 0; dt < left; ++dt)
+      GG_HIP(launch_step(L->storage, block, L->d_desc, L->d_tiles, L->n_tiles, txs, (int)dt, L->stream));
+    GG_HIP(launch_advance(L->d_desc, 1, left, L->stream));
+    L->t += left;
+  }
+  return GG_OK;
+}
+
+static gg_status gg_read_impl(gg_lattice *L, double *rho, double *ux, double *uy, double *C,
+                       double *f, double *g, gg_where where) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  const int64_t n = (int64_t)L->nx * L->ny;
+  double *user[6] = {rho, ux, uy, C, f, g};
+  const int64_t len[6] = {n, n, n, n, 9 * n, 5 * n};
+  const double fillv[6] = {NAN, NAN, NAN, NAN, 0.0, 0.0};
+  double *dev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  gg_status st = GG_OK;
+  for (int q = 0; q < 6; ++q) {
+    if (!user[q]) continue;
+    if (where == GG_HOST) {
+      if (hipMalloc(&dev[q], len[q] * sizeof(double)) != hipSuccess) {
+        st = fail(GG_ERR_OOM, "hipMalloc of a read-back buffer failed");
+        break;
+      }
+    } else {
+      dev[q] = user[q];
+    }
+    if (launch_fill(dev[q], len[q], fillv[q], L->stream) != hipSuccess) {
+      st = fail(GG_ERR_HIP, "fill of a read-back buffer failed");
+      break;
+    }
+  }
+  if (st == GG_OK) {
+    hipError_t e = launch_read(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6,
+                               dev[0], dev[1], dev[2], dev[3], dev[4], dev[5], L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e == hipSuccess && where == GG_HOST)
+      for (int q = 0; q < 6 && e == hipSuccess; ++q)
+        if (user[q]) e = hipMemcpy(user[q], dev[q], len[q] * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) st = fail(GG_ERR_HIP, std::string("read: ") + hipGetErrorString(e));
+  }
+  if (where == GG_HOST)
+    for (int q = 0; q < 6; ++q)
+      if (dev[q]) (void)hipFree(dev[q]);
+  return st;
+}
+
+gg_status gg_read(gg_lattice *L, double *rho, double *ux, double *uy, double *C, gg_where where) {
+  return gg_read_impl(L, rho, ux, uy, C, nullptr, nullptr, where);
+}
+
+gg_status gg_read_populations(gg_lattice *L, double *f, double *g, gg_where where) {
+  return gg_read_impl(L, nullptr, nullptr, nullptr, nullptr, f, g, where);
+}
+
+gg_status gg_diagnostics(gg_lattice *L, gg_diag *out) {
+  if (!L || !out) return fail(GG_ERR_ARG, "NULL argument");
+  GG_HIP(hipMemsetAsync(L->d_acc, 0, 8 * sizeof(double), L->stream));
+  GG_HIP(launch_reduce(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6, L->d_acc, L->stream));
+  double acc[8], flux[2 * GG_MAX_SEGMENTS];
+  int64_t t = 0;
+  GG_HIP(hipStreamSynchronize(L->stream));
+  GG_HIP(hipMemcpy(acc, L->d_acc, sizeof(acc), hipMemcpyDeviceToHost));
+  GG_HIP(hipMemcpy(flux, L->d_flux, sizeof(flux), hipMemcpyDeviceToHost));
+  GG_HIP(hipMemcpy(&t, L->d_t, sizeof(t), hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof(*out));
+  out->t = t;
+  out->n_fluid = L->n_fluid;
+  out->n_nonfinite = (int64_t)acc[4];
+  out->mass = acc[0];
+  out->solute = acc[1];
+  out->max_u = acc[2];
+  out->max_u_region = acc[3];
+  out->max_pe_region = acc[3] / L->p.D;
+  for (int s = 0; s < GG_MAX_SEGMENTS; ++s) {
+    out->seg_mass[s] = flux[2 * s];
+    out->seg_solute[s] = flux[2 * s + 1];
+    if (!L->seg[s].set) continue;
+    if (L->seg[s].kind == GG_SEG_INLET) {
+      out->mass_in += flux[2 * s];
+      out->solute_in += flux[2 * s + 1];
+    } else {
+      out->mass_out += flux[2 * s];
+      out->solute_out += flux[2 * s + 1];
+    }
+  }
+  if (out->n_nonfinite > 0)
+    return fail(GG_ERR_NONFINITE, std::to_string(out->n_nonfinite) + " fluid nodes hold non-finite populations");
+  return GG_OK;
+}
+
+// Snapshot layout: header, 14 population planes, fluxes.
+struct SnapHeader {
+  char magic[8];
+  int32_t version, nx, ny, storage;
+  int64_t pitch, plane, t;
+};
+
+gg_status gg_save(gg_lattice *L, void *buf, size_t *nbytes) {
+  if (!L || !nbytes) return fail(GG_ERR_ARG, "NULL argument");
+  const size_t pop_bytes = (size_t)NPOP * L->plane * L->esize;
+  const size_t need = sizeof(SnapHeader) + pop_bytes + 2 * GG_MAX_SEGMENTS * sizeof(double);
+  if (!buf) {
+    *nbytes = need;
+    return GG_OK;
+  }
+  if (*nbytes < need) return fail(GG_ERR_ARG, "snapshot buffer too small");
+  GG_HIP(hipStreamSynchronize(L->stream));
+  SnapHeader h;
+  std::memcpy(h.magic, "GGLBMSNP", 8);
+  h.version = 1;
+  h.nx = L->nx;
+  h.ny = L->ny;
+  h.storage = (int32_t)L->storage;
+  h.pitch = L->pitch;
+  h.plane = L->plane;
+  GG_HIP(hipMemcpy(&h.t, L->d_t, sizeof(int64_t), hipMemcpyDeviceToHost));
+  char *p = static_cast<char *>(buf);
+  std::memcpy(p, &h, sizeof(h));
+  GG_HIP(hipMemcpy(p + sizeof(h), L->d_pop, pop_bytes, hipMemcpyDeviceToHost));
+  GG_HIP(hipMemcpy(p + sizeof(h) + pop_bytes, L->d_flux, 2 * GG_MAX_SEGMENTS * sizeof(double),
+                   hipMemcpyDeviceToHost));
+  *nbytes = need;
+  return GG_OK;
+}
+
+gg_status gg_load(gg_lattice *L, const void *buf, size_t nbytes) {
+  if (!L || !buf) return fail(GG_ERR_ARG, "NULL argument");
+  const size_t pop_bytes = (size_t)NPOP * L->plane * L->esize;
+  const size_t need = sizeof(SnapHeader) + pop_bytes + 2 * GG_MAX_SEGMENTS * sizeof(double);
+  if (nbytes < need) return fail(GG_ERR_ARG, "snapshot too small");
+  SnapHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (std::memcmp(h.magic, "GGLBMSNP", 8) != 0 || h.version != 1)
+    return fail(GG_ERR_ARG, "not a lattice snapshot");
+  if (h.nx != L->nx || h.ny != L->ny || h.storage != (int32_t)L->storage ||
+      h.pitch != L->pitch || h.plane != L->plane)
+    return fail(GG_ERR_ARG, "snapshot belongs to a lattice of another shape or storage");
+  const char *p = static_cast<const char *>(buf);
+  GG_HIP(hipStreamSynchronize(L->stream));
+  GG_HIP(hipMemcpy(L->d_pop, p + sizeof(h), pop_bytes, hipMemcpyHostToDevice));
+  GG_HIP(hipMemcpy(L->d_flux, p + sizeof(h) + pop_bytes, 2 * GG_MAX_SEGMENTS * sizeof(double),
+                   hipMemcpyHostToDevice));
+  GG_HIP(hipMemcpy(L->d_t, &h.t, sizeof(int64_t), hipMemcpyHostToDevice));
+  L->t = h.t;
+  return GG_OK;
+}
+
+gg_status gg_set_launch(gg_lattice *L, int32_t tile_x, int32_t tile_y, int32_t graph_chunk) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  const int bs = tile_x * tile_y;
+  if (tile_x < 8 || (tile_x & (tile_x - 1)) || tile_y < 1 ||
+      (bs != 64 && bs != 128 && bs != 256 && bs != 512))
+    return fail(GG_ERR_ARG, "tile_x must be a power of two >= 8 and tile_x*tile_y one of 64, 128, 256, 512");
+  if (graph_chunk < 0 || graph_chunk > 100000) return fail(GG_ERR_ARG, "graph_chunk must lie in 0..100000");
+  GG_HIP(hipStreamSynchronize(L->stream));
+  L->tile_x = tile_x;
+  L->tile_y = tile_y;
+  L->graph_chunk = graph_chunk;
+  return gg_rebuild_tiles(L);
+}
+
+gg_status gg_info(const gg_lattice *L, int64_t *n_fluid, int64_t *n_tiles, int64_t *t) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (n_fluid) *n_fluid = L->n_fluid;
+  if (n_tiles) *n_tiles = L->n_tiles;
+  if (t) *t = L->t;
+  return GG_OK;
+}
+
+gg_status gg_step_timed(gg_lattice *L, int64_t n, double *kernel_ms) {
+  if (!L || !kernel_ms) return fail(GG_ERR_ARG, "NULL argument");
+  if (n < 1) return fail(GG_ERR_ARG, "n must be positive");
+  gg_status st = check_segments(L);
+  if (st != GG_OK) return st;
+  const int block = L->tile_x * L->tile_y;
+  const int txs = ilog2(L->tile_x);
+  std::vector<hipEvent_t> ev(2 * (size_t)n, nullptr);
+  hipError_t e = hipSuccess;
+  for (size_t k = 0; k < ev.size() && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
+  for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt) {
+    e = hipEventRecord(ev[2 * dt], L->stream);
+    if (e == hipSuccess)
+      e = launch_step(L->storage, block, L->d_desc, L->d_tiles, L->n_tiles, txs, (int)dt, L->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * dt + 1], L->stream);
+  }
+  if (e == hipSuccess) e = launch_advance(L->d_desc, 1, n, L->stream);
+  if (e == hipSuccess) L->t += n;
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  double total = 0.0;
+  for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt) {
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, ev[2 * dt], ev[2 * dt + 1]);
+    total += ms;
+  }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (e != hipSuccess) return fail(GG_ERR_HIP, std::string("timed steps: ") + hipGetErrorString(e));
+  *kernel_ms = total / (double)n;
+  return GG_OK;
+}
+
+gg_status gg_stream_copy(void *dst, const void *src, size_t bytes, int32_t reps,
+                         void *hip_stream, double *ms) {
+  if (!dst || !src || !ms || reps < 1 || bytes % 16 != 0)
+    return fail(GG_ERR_ARG, "copy needs device buffers, reps >= 1 and a multiple of 16 bytes");
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipEvent_t a = nullptr, b = nullptr;
+  GG_HIP(hipEventCreate(&a));
+  GG_HIP(hipEventCreate(&b));
+  double total = 0.0;
+  hipError_t e = hipSuccess;
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    e = hipEventRecord(a, st);
+    if (e == hipSuccess) e = launch_copy(dst, src, bytes, st);
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float x = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&x, a, b);
+    total += x;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return fail(GG_ERR_HIP, std::string("copy: ") + hipGetErrorString(e));
+  *ms = total / reps;
+  return GG_OK;
+}
+
+gg_status gg_sync(gg_lattice *L) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  GG_HIP(hipStreamSynchronize(L->stream));
+  return GG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,196 @@
+"""Python face of the lattice library: a thin object over the C ABI.
+
+Every time step runs in the HIP kernels of libgg.so; this module only
+marshals arguments. PyTorch, when present, supplies the HIP stream and device
+buffers for device-side read-back.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, Iterable, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _abi as A
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _current_stream() -> Optional[int]:
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+def make_phases(schedule: Sequence) -> "ctypes.Array":
+    """Phase records (attributes duration, open, c_in) -> gg_phase array."""
+    arr = (A.gg_phase * max(1, len(schedule)))()
+    for k, p in enumerate(schedule):
+        arr[k].duration = int(p.duration)
+        m = 0
+        for sid in p.open:
+            m |= 1 << (int(sid) - A.GG_FIRST_SEGMENT)
+        arr[k].open_mask = m
+        cs = 0
+        for sid, v in dict(p.c_in).items():
+            j = int(sid) - A.GG_FIRST_SEGMENT
+            cs |= 1 << j
+            arr[k].c_in[j] = float(v)
+        arr[k].c_in_set = cs
+    return arr
+
+
+class Lattice:
+    """A coupled D2Q9 + D2Q5 lattice on the GPU (see include/gg.h)."""
+
+    def __init__(self, mask: np.ndarray, *, tau_f: float, D: float,
+                 w0: float = 1.0 / 3.0, rho0: float = 1.0, k_decay: float = 0.0,
+                 c_shift: float = 0.0, periodic: Tuple[bool, bool] = (False, False),
+                 storage: str = "f32", stream: Optional[int] = None):
+        self.mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        self.ny, self.nx = self.mask.shape
+        self.storage = storage
+        self.D = float(D)
+        p = A.gg_params(float(tau_f), float(D), float(w0), float(rho0),
+                        float(k_decay), float(c_shift), int(bool(periodic[0])),
+                        int(bool(periodic[1])))
+        self.stream = _current_stream() if stream is None else stream
+        h = ctypes.c_void_p()
+        A.call("gg_create", _dptr(self.mask), self.nx, self.ny, ctypes.byref(p),
+               A.STORAGE[storage], ctypes.c_void_p(self.stream or 0), ctypes.byref(h))
+        self._h = h
+        self.segments: Dict[int, object] = {}
+
+    # ------------------------------------------------------------------
+    @classmethod
+    def from_workload(cls, wl, *, storage: Optional[str] = None,
+                      stream: Optional[int] = None, init: bool = True) -> "Lattice":
+        lat = cls(wl.mask, tau_f=wl.tau_f, D=wl.D, w0=wl.w0, rho0=wl.rho0,
+                  k_decay=wl.k_decay, c_shift=wl.c_shift, periodic=wl.periodic,
+                  storage=storage or wl.storage, stream=stream)
+        for s in wl.segments:
+            lat.set_segment(s.id, s.kind, s.normal, s.u_max, s.c_in)
+        if wl.schedule:
+            lat.set_schedule(wl.schedule, wl.t_origin)
+        if wl.region is not None:
+            lat.set_region(wl.region)
+        if init:
+            lat.init(**(wl.init or {}))
+        return lat
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_segment(self, sid: int, kind: str, normal, u_max: float = 0.0,
+                    c_in: float = 0.0) -> None:
+        k = {"inlet": A.GG_SEG_INLET, "outlet": A.GG_SEG_OUTLET}[kind]
+        A.call("gg_set_segment", self._h, int(sid), k, int(normal[0]),
+               int(normal[1]), float(u_max), float(c_in))
+
+    def set_schedule(self, schedule: Optional[Sequence], t_origin: int = 0) -> None:
+        if not schedule:
+            A.call("gg_set_schedule", self._h, None, 0, int(t_origin))
+            return
+        arr = make_phases(schedule)
+        A.call("gg_set_schedule", self._h, arr, len(schedule), int(t_origin))
+
+    def set_source(self, R: Optional[np.ndarray]) -> None:
+        if R is None:
+            A.call("gg_set_source", self._h, None, A.GG_HOST)
+            return
+        R = np.ascontiguousarray(R, dtype=np.float64).reshape(self.ny, self.nx)
+        A.call("gg_set_source", self._h, _dptr(R), A.GG_HOST)
+
+    def set_region(self, region: Optional[np.ndarray]) -> None:
+        if region is None:
+            A.call("gg_set_region", self._h, None)
+            return
+        r = np.ascontiguousarray(region, dtype=np.uint8).reshape(self.ny, self.nx)
+        A.call("gg_set_region", self._h, _dptr(r))
+
+    def init(self, rho=None, ux=None, uy=None, C=None) -> None:
+        arrs = []
+        for a in (rho, ux, uy, C):
+            arrs.append(None if a is None else
+                        np.ascontiguousarray(a, dtype=np.float64).reshape(self.ny, self.nx))
+        ptrs = [None if a is None else _dptr(a) for a in arrs]
+        A.call("gg_init", self._h, *ptrs, A.GG_HOST)
+
+    def step(self, n: int = 1) -> None:
+        A.call("gg_step", self._h, int(n))
+
+    def set_launch(self, tile_x: int = 64, tile_y: int = 4, graph_chunk: int = 64) -> None:
+        A.call("gg_set_launch", self._h, int(tile_x), int(tile_y), int(graph_chunk))
+
+    def step_timed(self, n: int) -> float:
+        """Advance n steps with every step kernel between HIP events; mean
+        kernel duration in milliseconds."""
+        ms = ctypes.c_double()
+        A.call("gg_step_timed", self._h, int(n), ctypes.byref(ms))
+        return ms.value
+
+    def sync(self) -> None:
+        A.call("gg_sync", self._h)
+
+    # ------------------------------------------------------------------
+    def read(self) -> Tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
+        """(rho, ux, uy, C) on the host, shape (ny, nx), NaN off the fluid."""
+        out = [np.empty((self.ny, self.nx)) for _ in range(4)]
+        A.call("gg_read", self._h, *[_dptr(a) for a in out], A.GG_HOST)
+        return tuple(out)
+
+    def read_device(self, rho, ux, uy, C) -> None:
+        """Write the fields into device buffers (torch tensors or None)."""
+        ptrs = [None if a is None else ctypes.c_void_p(a.data_ptr()) for a in (rho, ux, uy, C)]
+        A.call("gg_read", self._h, *ptrs, A.GG_DEVICE)
+
+    def populations(self) -> Tuple[np.ndarray, np.ndarray]:
+        """f (9, ny, nx) and g (5, ny, nx) in natural order, FP64."""
+        f = np.empty((9, self.ny, self.nx))
+        g = np.empty((5, self.ny, self.nx))
+        A.call("gg_read_populations", self._h, _dptr(f), _dptr(g), A.GG_HOST)
+        return f, g
+
+    def diagnostics(self, check_finite: bool = True) -> dict:
+        d = A.gg_diag()
+        st = A.lib().gg_diagnostics(self._h, ctypes.byref(d))
+        if st != A.GG_OK and (check_finite or st != A.GG_ERR_NONFINITE):
+            A.check(st, "gg_diagnostics")
+        out = {k: getattr(d, k) for k, _ in A.gg_diag._fields_
+               if k not in ("seg_mass", "seg_solute")}
+        out["seg_mass"] = np.array(d.seg_mass[:])
+        out["seg_solute"] = np.array(d.seg_solute[:])
+        return out
+
+    def info(self) -> dict:
+        nf, nt, t = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        A.call("gg_info", self._h, ctypes.byref(nf), ctypes.byref(nt), ctypes.byref(t))
+        return {"n_fluid": nf.value, "n_tiles": nt.value, "t": t.value}
+
+    def save(self) -> bytes:
+        n = ctypes.c_size_t(0)
+        A.call("gg_save", self._h, None, ctypes.byref(n))
+        buf = ctypes.create_string_buffer(n.value)
+        A.call("gg_save", self._h, buf, ctypes.byref(n))
+        return buf.raw[: n.value]
+
+    def load(self, snap: bytes) -> None:
+        A.call("gg_load", self._h, snap, len(snap))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            A.lib().gg_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
