@@ -190,7 +190,8 @@ gg_status gg_load(gg_lattice *lat, const void *buf, size_t nbytes);
 /* Kernel launch shape: tiles of tile_x * tile_y nodes (one work-group each,
  * tile_x * tile_y in {64, 128, 256, 512}, tile_x a multiple of 8); only
  * tiles holding a fluid node are launched. graph_chunk > 0 replays
- * gg_step in HIP graphs of that many steps; 0 launches every step. */
+ * gg_step in HIP graphs of that many steps (rounded up to even); 0
+ * launches every step. */
 gg_status gg_set_launch(gg_lattice *lat, int32_t tile_x, int32_t tile_y,
                         int32_t graph_chunk);
 
@@ -199,10 +200,10 @@ gg_status gg_info(const gg_lattice *lat, int64_t *n_fluid, int64_t *n_tiles,
                   int64_t *t);
 
 /* Instrumentation: advance n >= 1 steps launching every step kernel
- * between two HIP events on the lattice's stream (no graphs) and return
- * in *kernel_ms the mean event-measured duration of one step kernel. Waits
- * for the stream. */
-gg_status gg_step_timed(gg_lattice *lat, int64_t n, double *kernel_ms);
+ * between two HIP events on the lattice's stream (no graphs) and return the
+ * mean event-measured duration, in ms, of the even-step and of the
+ * odd-step kernels (either pointer may be NULL). Waits for the stream. */
+gg_status gg_step_timed(gg_lattice *lat, int64_t n, double *ms_even, double *ms_odd);
 
 /* Instrumentation: copy `bytes` (a multiple of 16) from src to dst, both
  * device buffers, `reps` times with a plain streaming kernel on hip_stream,

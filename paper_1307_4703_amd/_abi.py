@@ -82,7 +82,7 @@ SIGS = {
     "gg_set_launch": [P, I32, I32, I32],
     "gg_info": [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)],
     "gg_sync": [P],
-    "gg_step_timed": [P, I64, ctypes.POINTER(D)],
+    "gg_step_timed": [P, I64, ctypes.POINTER(D), ctypes.POINTER(D)],
     "gg_stream_copy": [P, P, ctypes.c_size_t, I32, P, ctypes.POINTER(D)],
 }
 

@@ -25,20 +25,32 @@ constexpr uint8_t NOT_FLUID = 0xFF;
 // Tile flag: some node of the tile has a link into a boundary segment.
 constexpr int TILE_TOUCHES_SEGMENT = 1;
 
+// One launched tile: lattice (instance) index, origin, flags.
+struct Tile {
+  int32_t inst, x0, y0, flags;
+};
+
 constexpr int NPOP = 14;  // 9 f planes then 5 g planes
 
 // Everything a kernel needs about one lattice. Lives in device memory and
 // is read with uniform (scalar) loads; the host re-uploads it when the
 // parameters change. The time counter lives apart (*t) so that uploads
 // never race with the device-side advance.
+//
+// Plane layout: node (x, y) sits at element node0 + y*pitch + x. Rows are
+// padded (pitch > nx, a multiple of 64 elements) and one padding row lies
+// before and after the lattice, so the cells x = -1, x = nx, y = -1 and
+// y = ny are addressable: stores toward a non-fluid neighbour outside the
+// lattice land there and are never read.
 struct LatDesc {
   int32_t nx, ny, pitch, periodic_x;
   int32_t periodic_y, n_phases, has_source, has_region;
+  int32_t node0, pad0;
   int64_t plane;            // elements between population planes
   void *pop;                // 14 planes of the storage type
-  const uint8_t *link;      // ny*pitch link codes
-  const uint8_t *mask;      // ny*pitch mask values
-  const uint8_t *region;    // ny*pitch region flags (or null)
+  const uint8_t *link;      // link codes, plane layout
+  const uint8_t *mask;      // mask values, plane layout
+  const uint8_t *region;    // region flags, plane layout (or null)
   const double *R;          // source patch, row-major r_w x r_h
   int32_t r_x0, r_y0, r_w, r_h;
   int64_t *t;               // completed steps (device counter)
@@ -67,25 +79,54 @@ struct LatDesc {
   double seg_cin[GG_MAX_SEGMENTS];  // used when there is no schedule
 };
 
-// Storage traits: load into the compute type, store with rounding.
+// Address spaces: the descriptor and tile lists are read-only while a
+// kernel runs and are read through the constant space (scalar loads); the
+// population planes live in the global space (global_load / global_store
+// rather than flat accesses).
+#define GG_GLOBAL __attribute__((address_space(1)))
+#define GG_CONST __attribute__((address_space(4)))
+
+// Cache policy of the population streams: nontemporal loads / stores mark
+// the lines for early eviction (every population is touched once a step).
+#ifndef GG_NT_LOAD
+#define GG_NT_LOAD 0
+#endif
+#ifndef GG_NT_STORE
+#define GG_NT_STORE 0
+#endif
+
+template <class V> __device__ __forceinline__ V gload(const GG_GLOBAL V *p) {
+  if constexpr (GG_NT_LOAD) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <class V> __device__ __forceinline__ void gstore(GG_GLOBAL V *p, V v) {
+  if constexpr (GG_NT_STORE) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// Storage traits: load into the compute type, store with rounding. W is the
+// raw storage word that sits in the planes.
 template <class S> struct Pop;
 template <> struct Pop<double> {
   using T = double;
-  static __device__ __forceinline__ T ld(const double *p, T) { return *p; }
-  static __device__ __forceinline__ void st(double *p, T v, T) { *p = v; }
+  using W = double;
+  static __device__ __forceinline__ T ld(const GG_GLOBAL W *p, T) { return gload(p); }
+  static __device__ __forceinline__ void st(GG_GLOBAL W *p, T v, T) { gstore(p, v); }
 };
 template <> struct Pop<float> {
   using T = float;
-  static __device__ __forceinline__ T ld(const float *p, T) { return *p; }
-  static __device__ __forceinline__ void st(float *p, T v, T) { *p = v; }
+  using W = float;
+  static __device__ __forceinline__ T ld(const GG_GLOBAL W *p, T) { return gload(p); }
+  static __device__ __forceinline__ void st(GG_GLOBAL W *p, T v, T) { gstore(p, v); }
 };
 template <> struct Pop<__half> {
   using T = float;
-  static __device__ __forceinline__ T ld(const __half *p, T shift) {
-    return __half2float(*p) + shift;
+  using W = unsigned short;
+  static __device__ __forceinline__ T ld(const GG_GLOBAL W *p, T shift) {
+    return __half2float(__ushort_as_half(gload(p))) + shift;
   }
-  static __device__ __forceinline__ void st(__half *p, T v, T shift) {
-    *p = __float2half_rn(v - shift);
+  static __device__ __forceinline__ void st(GG_GLOBAL W *p, T v, T shift) {
+    gstore(p, __half_as_ushort(__float2half_rn(v - shift)));
   }
 };
 

@@ -6,19 +6,19 @@
 namespace gg {
 
 // Fused coupled step over a tile list; block = threads per work-group
-// (64, 128, 256 or 512), tile width 1 << tx_shift, dt added to the device
-// step counter of each lattice.
-hipError_t launch_step(gg_storage s, int block, const LatDesc *d, const int4 *tiles,
+// (64, 128, 256 or 512), tile width 1 << tx_shift, odd = parity of the
+// step, dt added to the device step counter of each lattice.
+hipError_t launch_step(gg_storage s, int block, bool odd, const LatDesc *d, const Tile *tiles,
                        int n_tiles, int tx_shift, int dt, hipStream_t st);
 
 // Auxiliary kernels: 256-thread work-groups over one lattice's tiles.
-hipError_t launch_init(gg_storage s, const LatDesc *d, const int4 *tiles, int n_tiles,
+hipError_t launch_init(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                        int tx_shift, const double *rho, const double *ux,
                        const double *uy, const double *c, hipStream_t st);
-hipError_t launch_read(gg_storage s, const LatDesc *d, const int4 *tiles, int n_tiles,
+hipError_t launch_read(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                        int tx_shift, double *rho, double *ux, double *uy, double *c,
                        double *f, double *g, hipStream_t st);
-hipError_t launch_reduce(gg_storage s, const LatDesc *d, const int4 *tiles, int n_tiles,
+hipError_t launch_reduce(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                          int tx_shift, double *acc, hipStream_t st);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
 hipError_t launch_advance(const LatDesc *descs, int n, int64_t k, hipStream_t st);

@@ -12,6 +12,11 @@
 // synchronisation between work-groups is needed, and every boundary rule
 // (paper Boundary Conditions section, read as bounce-back variants) uses
 // only the node's own post-collision populations and velocity.
+//
+// Memory access shape: every plane is addressed as a uniform base pointer
+// (scalar registers) plus a 32-bit per-lane element offset; consecutive
+// lanes hold consecutive x, so each wavefront touches whole cache lines
+// (shifted by one element for the x-neighbours of the odd step).
 #include <algorithm>
 
 #include "gg_device.h"
@@ -19,13 +24,15 @@
 
 namespace gg {
 
+using CDesc = const GG_CONST LatDesc;
+
 struct PhaseNow {
   uint32_t open;
-  const double *cin;
+  const GG_CONST double *cin;
 };
 
 // Valve phase in force during step t (fixed at the start of the step).
-__device__ __forceinline__ PhaseNow phase_at(const LatDesc &L, int64_t t) {
+__device__ __forceinline__ PhaseNow phase_at(CDesc &L, int64_t t) {
   if (L.n_phases == 0) return {0xFFFFFFFFu, L.seg_cin};
   int64_t tau = (t - L.t_origin) % L.period;
   if (tau < 0) tau += L.period;
@@ -72,57 +79,74 @@ __device__ void flush_flux(double *flux, int sa, double ma, double ca, int sb,
   }
 }
 
-// Node index of x + e_k for k = 0..8, periodic wrap included; only used for
-// links whose neighbour is fluid (so never outside the lattice).
+// Element offset of x + e_k for k = 0..8: wrapped along periodic axes,
+// otherwise possibly in the padding around the lattice (always addressable).
 struct Neigh {
-  int idx[9];
-  __device__ __forceinline__ Neigh(int x, int y, int nx, int ny, int pitch) {
-    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  uint32_t idx[9];
+  __device__ __forceinline__ Neigh(CDesc &L, int x, int y) {
+    const int xm = (x == 0 && L.periodic_x) ? L.nx - 1 : x - 1;
+    const int xp = (x == L.nx - 1 && L.periodic_x) ? 0 : x + 1;
+    const int ym = (y == 0 && L.periodic_y) ? L.ny - 1 : y - 1;
+    const int yp = (y == L.ny - 1 && L.periodic_y) ? 0 : y + 1;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       const int xx = EX[k] > 0 ? xp : (EX[k] < 0 ? xm : x);
       const int yy = EY[k] > 0 ? yp : (EY[k] < 0 ? ym : y);
-      idx[k] = yy * pitch + xx;
+      idx[k] = (uint32_t)(L.node0 + yy * L.pitch + xx);
     }
   }
 };
 
-// Populations f_i(x,t), g_i(x,t) in natural order for either parity.
-template <class S>
-__device__ __forceinline__ void load_state(const S *pop, int64_t ps, int node,
-                                           uint8_t lc, bool odd, const Neigh &nb,
+// Uniform base pointers of the 14 population planes. Elements are reached
+// through a 32-bit byte offset (every plane is smaller than 4 GiB), which
+// maps onto the scalar-base + vector-offset form of global memory access.
+template <class W> struct Planes {
+  GG_GLOBAL W *p[NPOP];
+  __device__ __forceinline__ Planes(CDesc &L) {
+    GG_GLOBAL W *base = (GG_GLOBAL W *)L.pop;
+#pragma unroll
+    for (int i = 0; i < NPOP; ++i) p[i] = base + (int64_t)i * L.plane;
+  }
+  __device__ __forceinline__ GG_GLOBAL W *at(int i, uint32_t idx) const {
+    return (GG_GLOBAL W *)((GG_GLOBAL char *)p[i] + idx * (uint32_t)sizeof(W));
+  }
+};
+
+// Populations f_i(x,t), g_i(x,t) in natural order for step parity ODD.
+template <class S, bool ODD>
+__device__ __forceinline__ void load_state(const Planes<typename Pop<S>::W> &pl, uint32_t node,
+                                           uint8_t lc, const Neigh &nb,
                                            const typename Pop<S>::T *shf,
                                            const typename Pop<S>::T *shg,
-                                           typename Pop<S>::T *f,
-                                           typename Pop<S>::T *g) {
+                                           typename Pop<S>::T *f, typename Pop<S>::T *g) {
   using P = Pop<S>;
-  if (!odd) {
+  if (!ODD) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = P::ld(pop + i * ps + node, shf[i]);
+    for (int i = 0; i < 9; ++i) f[i] = P::ld(pl.at(i, node), shf[i]);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) g[i] = P::ld(pop + (9 + i) * ps + node, shg[i]);
+    for (int i = 0; i < 5; ++i) g[i] = P::ld(pl.at(9 + i, node), shg[i]);
   } else {
-    f[0] = P::ld(pop + node, shf[0]);
-    g[0] = P::ld(pop + 9 * ps + node, shg[0]);
+    // streamed in from x - e_i, stored by that node in slot opp(i)
+    f[0] = P::ld(pl.at(0, node), shf[0]);
 #pragma unroll
-    for (int i = 1; i < 9; ++i) {
-      const bool nf = (lc >> (OPP[i] - 1)) & 1;  // x - e_i not fluid
-      const S *a = nf ? pop + i * ps + node : pop + OPP[i] * ps + nb.idx[OPP[i]];
-      f[i] = P::ld(a, shf[i]);
-    }
+    for (int i = 1; i < 9; ++i) f[i] = P::ld(pl.at(OPP[i], nb.idx[OPP[i]]), shf[i]);
+    g[0] = P::ld(pl.at(9, node), shg[0]);
 #pragma unroll
-    for (int i = 1; i < 5; ++i) {
-      const bool nf = (lc >> (OPP[i] - 1)) & 1;
-      const S *a = nf ? pop + (9 + i) * ps + node
-                      : pop + (9 + OPP[i]) * ps + nb.idx[OPP[i]];
-      g[i] = P::ld(a, shg[i]);
+    for (int i = 1; i < 5; ++i) g[i] = P::ld(pl.at(9 + OPP[i], nb.idx[OPP[i]]), shg[i]);
+    if (lc != 0) {
+      // x - e_i not fluid: this node stored the boundary value in its own slot i
+#pragma unroll
+      for (int i = 1; i < 9; ++i)
+        if ((lc >> (OPP[i] - 1)) & 1) f[i] = P::ld(pl.at(i, node), shf[i]);
+#pragma unroll
+      for (int i = 1; i < 5; ++i)
+        if ((lc >> (OPP[i] - 1)) & 1) g[i] = P::ld(pl.at(9 + i, node), shg[i]);
     }
   }
 }
 
 template <class T>
-__device__ __forceinline__ void shifts(const LatDesc &L, T *shf, T *shg) {
+__device__ __forceinline__ void shifts(CDesc &L, T *shf, T *shg) {
 #pragma unroll
   for (int i = 0; i < 9; ++i) shf[i] = (T)(WF[i] * L.rho0);
   shg[0] = (T)(L.w0 * L.c_shift);
@@ -133,42 +157,48 @@ __device__ __forceinline__ void shifts(const LatDesc &L, T *shf, T *shg) {
 // ---------------------------------------------------------------------------
 // The fused coupled step.
 // ---------------------------------------------------------------------------
-template <class S, int BS>
-__global__ void __launch_bounds__(BS)
-    k_step(const LatDesc *__restrict__ descs, const int4 *__restrict__ tiles,
+// ODD is the parity of the step, known to the host (the layout of the state
+// alternates between the two forms above).
+#ifdef GG_WAVES_PER_EU
+#define GG_STEP_ATTR __attribute__((amdgpu_waves_per_eu(GG_WAVES_PER_EU)))
+#else
+#define GG_STEP_ATTR
+#endif
+template <class S, int BS, bool ODD>
+__global__ void __launch_bounds__(BS) GG_STEP_ATTR
+    k_step(const LatDesc *__restrict__ descs, const Tile *__restrict__ tiles,
            int n_tiles, int per_xcd, int tx_shift, int dt) {
   using P = Pop<S>;
   using T = typename P::T;
   // Work-groups are dealt to the 8 XCDs round-robin; give each XCD a
   // contiguous run of tiles so neighbouring tiles share an L2.
+  using W = typename P::W;
   const int tile = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
   if (tile >= n_tiles) return;
-  const int4 tl = tiles[tile];
-  const LatDesc &L = descs[tl.x];
+  const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
+  CDesc &L = ((CDesc *)descs)[tl.inst];
   const int tmask = (1 << tx_shift) - 1;
-  const int x = tl.y + (int)(threadIdx.x & tmask);
-  const int y = tl.z + (int)(threadIdx.x >> tx_shift);
+  const int x = tl.x0 + (int)(threadIdx.x & tmask);
+  const int y = tl.y0 + (int)(threadIdx.x >> tx_shift);
   const int nx = L.nx, ny = L.ny, pitch = L.pitch;
-  const int64_t ps = L.plane;
-  const int64_t t = *L.t + dt;
-  const bool odd = (t & 1) != 0;
-  S *const pop = static_cast<S *>(L.pop);
-  const bool seg_tile = (tl.w & TILE_TOUCHES_SEGMENT) != 0;
+  const int64_t t = *(const GG_CONST int64_t *)L.t + dt;
+  const bool seg_tile = (tl.flags & TILE_TOUCHES_SEGMENT) != 0;
   PhaseNow ph{0u, nullptr};
   if (seg_tile) ph = phase_at(L, t);
 
-  const int node = y * pitch + x;
-  const uint8_t lc = (x < nx && y < ny) ? L.link[node] : NOT_FLUID;
+  const uint32_t node = (uint32_t)(L.node0 + y * pitch + x);
+  const uint8_t lc = (x < nx && y < ny) ? ((const GG_GLOBAL uint8_t *)L.link)[node] : NOT_FLUID;
 
   int sa = -1, sb = -1;
   double ma = 0.0, ca = 0.0, mb = 0.0, cb = 0.0;
 
   if (lc != NOT_FLUID) {
+    const Planes<W> pl(L);
     T shf[9], shg[5];
     shifts<T>(L, shf, shg);
-    const Neigh nb(x, y, nx, ny, pitch);
+    const Neigh nb(L, x, y);
     T f[9], g[5];
-    load_state<S>(pop, ps, node, lc, odd, nb, shf, shg, f, g);
+    load_state<S, ODD>(pl, node, lc, nb, shf, shg, f, g);
 
     // Moments of f, paper Eq. 7 (sum over i = 0..8).
     const T rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
@@ -197,7 +227,7 @@ __global__ void __launch_bounds__(BS)
     if (L.has_source) {
       const int rx = x - L.r_x0, ry = y - L.r_y0;
       if (rx >= 0 && rx < L.r_w && ry >= 0 && ry < L.r_h)
-        src += (T)L.R[ry * L.r_w + rx];
+        src += (T)((const GG_GLOBAL double *)L.R)[ry * L.r_w + rx];
     }
     const T om_g = (T)L.omega_g;
     T pg[5];
@@ -208,9 +238,10 @@ __global__ void __launch_bounds__(BS)
       pg[i] = g[i] + om_g * (geq - g[i]) + wg[i] * src;
     }
 
-    // Value arriving at x along direction j: from a fluid neighbour it is
-    // that neighbour's own business; for a wall or closed valve it is the
-    // bounced population f*(x, opp j); open segments overwrite below.
+    // Value arriving at x along direction j when x - e_j is not fluid: the
+    // bounced population f*(x, opp j) for a wall or closed valve; open
+    // segments overwrite below. (For fluid x - e_j the same slot carries
+    // f*(x, opp j) to that neighbour.)
     T in_f[9], in_g[5];
 #pragma unroll
     for (int j = 0; j < 9; ++j) in_f[j] = pf[OPP[j]];
@@ -230,7 +261,8 @@ __global__ void __launch_bounds__(BS)
         if (sy < 0 || sy >= ny) {
           if (L.periodic_y) sy = (sy + ny) % ny; else inside = false;
         }
-        const int code = inside ? (int)L.mask[sy * pitch + sx] : GG_MASK_WALL;
+        const int code = inside ? (int)((const GG_GLOBAL uint8_t *)L.mask)[L.node0 + sy * pitch + sx]
+                                : GG_MASK_WALL;
         if (code < GG_FIRST_SEGMENT) continue;
         const int s = code - GG_FIRST_SEGMENT;
         if (!((ph.open >> s) & 1u)) continue;  // closed valve: a wall
@@ -251,8 +283,8 @@ __global__ void __launch_bounds__(BS)
           vf = -pf[OPP[j]] + T(2) * (T)WF[j] * rho0 * (T(1) + T(4.5) * eu * eu - T(1.5) * usq);
           if (j < 5) vg = pg[j];
         }
-        double dm = (double)(vf - pf[OPP[j]]);
-        double dc = (j < 5) ? (double)(vg - pg[OPP[j]]) : 0.0;
+        const double dm = (double)(vf - pf[OPP[j]]);
+        const double dc = (j < 5) ? (double)(vg - pg[OPP[j]]) : 0.0;
         in_f[j] = vf;
         if (j < 5) in_g[j] = vg;
         if (sa < 0 || sa == s) {
@@ -263,32 +295,34 @@ __global__ void __launch_bounds__(BS)
       }
     }
 
-    if (!odd) {
-      P::st(pop + node, pf[0], shf[0]);
+    if (!ODD) {
 #pragma unroll
-      for (int j = 1; j < 9; ++j) P::st(pop + j * ps + node, in_f[j], shf[j]);
-      P::st(pop + 9 * ps + node, pg[0], shg[0]);
+      for (int j = 0; j < 9; ++j) P::st(pl.at(j, node), in_f[j], shf[j]);
 #pragma unroll
-      for (int j = 1; j < 5; ++j) P::st(pop + (9 + j) * ps + node, in_g[j], shg[j]);
+      for (int j = 0; j < 5; ++j) P::st(pl.at(9 + j, node), in_g[j], shg[j]);
     } else {
-      P::st(pop + node, pf[0], shf[0]);
+      P::st(pl.at(0, node), pf[0], shf[0]);
+      P::st(pl.at(9, node), pg[0], shg[0]);
+      // free flight to x + e_i; where that cell is not fluid the value lands
+      // in a slot nobody reads
 #pragma unroll
-      for (int i = 1; i < 9; ++i) {
-        const bool nft = (lc >> (i - 1)) & 1;  // x + e_i not fluid
-        S *a = nft ? pop + OPP[i] * ps + node : pop + i * ps + nb.idx[i];
-        P::st(a, nft ? in_f[OPP[i]] : pf[i], shf[i]);
-      }
-      P::st(pop + 9 * ps + node, pg[0], shg[0]);
+      for (int i = 1; i < 9; ++i) P::st(pl.at(i, nb.idx[i]), pf[i], shf[i]);
 #pragma unroll
-      for (int i = 1; i < 5; ++i) {
-        const bool nft = (lc >> (i - 1)) & 1;
-        S *a = nft ? pop + (9 + OPP[i]) * ps + node : pop + (9 + i) * ps + nb.idx[i];
-        P::st(a, nft ? in_g[OPP[i]] : pg[i], shg[i]);
+      for (int i = 1; i < 5; ++i) P::st(pl.at(9 + i, nb.idx[i]), pg[i], shg[i]);
+      if (lc != 0) {
+        // x + e_i not fluid: the value arriving here along opp(i) goes to
+        // this node's own slot opp(i)
+#pragma unroll
+        for (int i = 1; i < 9; ++i)
+          if ((lc >> (i - 1)) & 1) P::st(pl.at(OPP[i], node), in_f[OPP[i]], shf[i]);
+#pragma unroll
+        for (int i = 1; i < 5; ++i)
+          if ((lc >> (i - 1)) & 1) P::st(pl.at(9 + OPP[i], node), in_g[OPP[i]], shg[i]);
       }
     }
   }
 
-  if (seg_tile) flush_flux(L.flux, sa, ma, ca, sb, mb, cb);
+  if (seg_tile) flush_flux((double *)L.flux, sa, ma, ca, sb, mb, cb);
 }
 
 // ---------------------------------------------------------------------------
@@ -296,28 +330,29 @@ __global__ void __launch_bounds__(BS)
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ void __launch_bounds__(256)
-    k_init(const LatDesc *__restrict__ desc, const int4 *__restrict__ tiles,
+    k_init(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles,
            int n_tiles, int tx_shift, const double *__restrict__ rho_in,
            const double *__restrict__ ux_in, const double *__restrict__ uy_in,
            const double *__restrict__ c_in) {
   using P = Pop<S>;
   using T = typename P::T;
+  using W = typename P::W;
   const int tile = blockIdx.x;
   if (tile >= n_tiles) return;
-  const int4 tl = tiles[tile];
-  const LatDesc &L = *desc;
+  const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
+  CDesc &L = *(CDesc *)desc;
   const int tmask = (1 << tx_shift) - 1;
-  const int x = tl.y + (int)(threadIdx.x & tmask);
-  const int y = tl.z + (int)(threadIdx.x >> tx_shift);
+  const int x = tl.x0 + (int)(threadIdx.x & tmask);
+  const int y = tl.y0 + (int)(threadIdx.x >> tx_shift);
   if (x >= L.nx || y >= L.ny) return;
-  const int node = y * L.pitch + x;
-  const int64_t ps = L.plane;
-  S *const pop = static_cast<S *>(L.pop);
+  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+  const Planes<W> pl(L);
   T shf[9], shg[5];
   shifts<T>(L, shf, shg);
-  if (L.link[node] == NOT_FLUID) {
-    for (int i = 0; i < 9; ++i) P::st(pop + i * ps + node, shf[i], shf[i]);
-    for (int i = 0; i < 5; ++i) P::st(pop + (9 + i) * ps + node, shg[i], shg[i]);
+  if (((const GG_GLOBAL uint8_t *)L.link)[node] == NOT_FLUID) {
+    // never read; stored as zero populations
+    for (int i = 0; i < 9; ++i) P::st(pl.at(i, node), shf[i], shf[i]);
+    for (int i = 0; i < 5; ++i) P::st(pl.at(9 + i, node), shg[i], shg[i]);
     return;
   }
   const int k = y * L.nx + x;
@@ -329,14 +364,29 @@ __global__ void __launch_bounds__(256)
   for (int i = 0; i < 9; ++i) {
     const T eu = (T)EX[i] * ux + (T)EY[i] * uy;
     const T feq = (T)WF[i] * rho * (T(1) + T(3) * eu + T(4.5) * eu * eu - T(1.5) * usq);
-    P::st(pop + i * ps + node, feq, shf[i]);
+    P::st(pl.at(i, node), feq, shf[i]);
   }
   const T ics = (T)L.inv_cs2g;
   for (int i = 0; i < 5; ++i) {
     const T w = i == 0 ? (T)L.w0 : (T)L.wg_axis;
     const T eu = (T)EX[i] * ux + (T)EY[i] * uy;
-    P::st(pop + (9 + i) * ps + node, w * C * (T(1) + eu * ics), shg[i]);
+    P::st(pl.at(9 + i, node), w * C * (T(1) + eu * ics), shg[i]);
   }
+}
+
+// Gathers f(x,t), g(x,t) of the current parity for the auxiliary kernels.
+template <class S>
+__device__ __forceinline__ void gather(CDesc &L, uint32_t node, uint8_t lc, int x, int y,
+                                       typename Pop<S>::T *f, typename Pop<S>::T *g) {
+  using T = typename Pop<S>::T;
+  const Planes<typename Pop<S>::W> pl(L);
+  T shf[9], shg[5];
+  shifts<T>(L, shf, shg);
+  const Neigh nb(L, x, y);
+  if (*(const GG_CONST int64_t *)L.t & 1)
+    load_state<S, true>(pl, node, lc, nb, shf, shg, f, g);
+  else
+    load_state<S, false>(pl, node, lc, nb, shf, shg, f, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -344,30 +394,25 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ void __launch_bounds__(256)
-    k_read(const LatDesc *__restrict__ desc, const int4 *__restrict__ tiles,
+    k_read(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles,
            int n_tiles, int tx_shift, double *__restrict__ rho_out,
            double *__restrict__ ux_out, double *__restrict__ uy_out,
            double *__restrict__ c_out, double *__restrict__ f_out,
            double *__restrict__ g_out) {
-  using P = Pop<S>;
-  using T = typename P::T;
+  using T = typename Pop<S>::T;
   const int tile = blockIdx.x;
   if (tile >= n_tiles) return;
-  const int4 tl = tiles[tile];
-  const LatDesc &L = *desc;
+  const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
+  CDesc &L = *(CDesc *)desc;
   const int tmask = (1 << tx_shift) - 1;
-  const int x = tl.y + (int)(threadIdx.x & tmask);
-  const int y = tl.z + (int)(threadIdx.x >> tx_shift);
+  const int x = tl.x0 + (int)(threadIdx.x & tmask);
+  const int y = tl.y0 + (int)(threadIdx.x >> tx_shift);
   if (x >= L.nx || y >= L.ny) return;
-  const int node = y * L.pitch + x;
-  const uint8_t lc = L.link[node];
+  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+  const uint8_t lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
   if (lc == NOT_FLUID) return;
-  const bool odd = (*L.t & 1) != 0;
-  T shf[9], shg[5];
-  shifts<T>(L, shf, shg);
-  const Neigh nb(x, y, L.nx, L.ny, L.pitch);
   T fT[9], gT[5];
-  load_state<S>(static_cast<const S *>(L.pop), L.plane, node, lc, odd, nb, shf, shg, fT, gT);
+  gather<S>(L, node, lc, x, y, fT, gT);
   const int64_t n = (int64_t)L.nx * L.ny;
   const int k = y * L.nx + x;
   double f[9], g[5];
@@ -399,27 +444,22 @@ __global__ void k_fill(double *__restrict__ p, int64_t n, double v) {
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ void __launch_bounds__(256)
-    k_reduce(const LatDesc *__restrict__ desc, const int4 *__restrict__ tiles,
+    k_reduce(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles,
              int n_tiles, int tx_shift, double *__restrict__ acc) {
-  using P = Pop<S>;
-  using T = typename P::T;
+  using T = typename Pop<S>::T;
   const int tile = blockIdx.x;
   if (tile >= n_tiles) return;
-  const int4 tl = tiles[tile];
-  const LatDesc &L = *desc;
+  const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
+  CDesc &L = *(CDesc *)desc;
   const int tmask = (1 << tx_shift) - 1;
-  const int x = tl.y + (int)(threadIdx.x & tmask);
-  const int y = tl.z + (int)(threadIdx.x >> tx_shift);
-  const int node = y * L.pitch + x;
-  const uint8_t lc = (x < L.nx && y < L.ny) ? L.link[node] : NOT_FLUID;
+  const int x = tl.x0 + (int)(threadIdx.x & tmask);
+  const int y = tl.y0 + (int)(threadIdx.x >> tx_shift);
+  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+  const uint8_t lc = (x < L.nx && y < L.ny) ? ((const GG_GLOBAL uint8_t *)L.link)[node] : NOT_FLUID;
   double m = 0.0, c = 0.0, um = 0.0, ur = 0.0, bad = 0.0, cnt = 0.0;
   if (lc != NOT_FLUID) {
-    const bool odd = (*L.t & 1) != 0;
-    T shf[9], shg[5];
-    shifts<T>(L, shf, shg);
-    const Neigh nb(x, y, L.nx, L.ny, L.pitch);
     T fT[9], gT[5];
-    load_state<S>(static_cast<const S *>(L.pop), L.plane, node, lc, odd, nb, shf, shg, fT, gT);
+    gather<S>(L, node, lc, x, y, fT, gT);
     double rho = 0.0, jx = 0.0, jy = 0.0, C = 0.0;
     bool finite = true;
     for (int i = 0; i < 9; ++i) {
@@ -439,7 +479,7 @@ __global__ void __launch_bounds__(256)
       m = rho;
       c = C;
       um = sqrt(jx * jx + jy * jy) / rho;
-      if (L.has_region && L.region[node]) ur = um;
+      if (L.has_region && ((const GG_GLOBAL uint8_t *)L.region)[node]) ur = um;
     } else {
       bad = 1.0;
     }
@@ -461,50 +501,65 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Plain streaming copy, 16 bytes per lane per iteration.
+// Plain streaming copy: each lane moves four 16-byte words per iteration,
+// all four loads issued before the stores.
 __global__ void __launch_bounds__(256) k_copy(int4 *__restrict__ dst, const int4 *__restrict__ src, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = src[i];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const int4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
 }
 
 // Advance the step counters of n lattices by k (after k step launches).
 __global__ void k_advance(const LatDesc *__restrict__ descs, int n, int64_t k) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) *descs[i].t += k;
+  if (i < n) *(GG_GLOBAL int64_t *)descs[i].t += k;
 }
 
 // ---------------------------------------------------------------------------
 // Host-side launch wrappers.
 // ---------------------------------------------------------------------------
-template <class S>
-static hipError_t launch_step_s(int bs, const LatDesc *d, const int4 *tiles, int n_tiles,
+template <class S, bool ODD>
+static hipError_t launch_step_p(int bs, const LatDesc *d, const Tile *tiles, int n_tiles,
                                 int tx_shift, int dt, hipStream_t st) {
   const int per_xcd = (n_tiles + 7) / 8;
   const dim3 grid(8 * per_xcd);
   switch (bs) {
-    case 64: k_step<S, 64><<<grid, 64, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
-    case 128: k_step<S, 128><<<grid, 128, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
-    case 256: k_step<S, 256><<<grid, 256, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
-    case 512: k_step<S, 512><<<grid, 512, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
+    case 64: k_step<S, 64, ODD><<<grid, 64, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
+    case 128: k_step<S, 128, ODD><<<grid, 128, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
+    case 256: k_step<S, 256, ODD><<<grid, 256, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
+    case 512: k_step<S, 512, ODD><<<grid, 512, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_step(gg_storage s, int block, const LatDesc *d, const int4 *tiles,
+template <class S>
+static hipError_t launch_step_s(int bs, bool odd, const LatDesc *d, const Tile *tiles,
+                                int n_tiles, int tx_shift, int dt, hipStream_t st) {
+  return odd ? launch_step_p<S, true>(bs, d, tiles, n_tiles, tx_shift, dt, st)
+             : launch_step_p<S, false>(bs, d, tiles, n_tiles, tx_shift, dt, st);
+}
+
+hipError_t launch_step(gg_storage s, int block, bool odd, const LatDesc *d, const Tile *tiles,
                        int n_tiles, int tx_shift, int dt, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   switch (s) {
-    case GG_F64: return launch_step_s<double>(block, d, tiles, n_tiles, tx_shift, dt, st);
-    case GG_F32: return launch_step_s<float>(block, d, tiles, n_tiles, tx_shift, dt, st);
-    case GG_F16_SHIFTED: return launch_step_s<__half>(block, d, tiles, n_tiles, tx_shift, dt, st);
+    case GG_F64: return launch_step_s<double>(block, odd, d, tiles, n_tiles, tx_shift, dt, st);
+    case GG_F32: return launch_step_s<float>(block, odd, d, tiles, n_tiles, tx_shift, dt, st);
+    case GG_F16_SHIFTED: return launch_step_s<__half>(block, odd, d, tiles, n_tiles, tx_shift, dt, st);
   }
   return hipErrorInvalidValue;
 }
 
 // The auxiliary kernels run 256-thread work-groups over 256-node tiles.
-hipError_t launch_init(gg_storage s, const LatDesc *d, const int4 *tiles, int n_tiles,
+hipError_t launch_init(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                        int tx_shift, const double *rho, const double *ux,
                        const double *uy, const double *c, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
@@ -516,7 +571,7 @@ hipError_t launch_init(gg_storage s, const LatDesc *d, const int4 *tiles, int n_
   return hipGetLastError();
 }
 
-hipError_t launch_read(gg_storage s, const LatDesc *d, const int4 *tiles, int n_tiles,
+hipError_t launch_read(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                        int tx_shift, double *rho, double *ux, double *uy, double *c,
                        double *f, double *g, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
@@ -534,7 +589,7 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(gg_storage s, const LatDesc *d, const int4 *tiles, int n_tiles,
+hipError_t launch_reduce(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                          int tx_shift, double *acc, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   switch (s) {
@@ -547,7 +602,7 @@ hipError_t launch_reduce(gg_storage s, const LatDesc *d, const int4 *tiles, int 
 
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st) {
   const int64_t n = (int64_t)(bytes / 16);
-  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 256 * 64);
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 256 * 16);
   if (n > 0)
     k_copy<<<(unsigned)blocks, 256, 0, st>>>(static_cast<int4 *>(dst), static_cast<const int4 *>(src), n);
   return hipGetLastError();

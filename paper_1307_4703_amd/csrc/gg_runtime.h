@@ -15,8 +15,10 @@ struct SegHost {
 };
 
 struct gg_lattice {
-  int32_t nx = 0, ny = 0, pitch = 0;
-  int64_t plane = 0;
+  int32_t nx = 0, ny = 0, pitch = 0, node0 = 0;
+  int64_t plane_elems = 0;  // addressable elements of one plane (with padding)
+  int64_t plane = 0;        // stride between planes
+  size_t nid(int x, int y) const { return (size_t)node0 + (size_t)y * pitch + x; }
   gg_storage storage = GG_F32;
   size_t esize = 4;
   hipStream_t stream = nullptr;
@@ -24,7 +26,7 @@ struct gg_lattice {
   gg_params p{};
   double tau_g = 0.0, cs2g = 0.0;
   std::vector<uint8_t> mask;         // nx*ny
-  std::vector<uint8_t> link;         // pitch*ny link codes
+  std::vector<uint8_t> link;         // link codes, plane layout
   std::vector<uint8_t> touches_seg;  // nx*ny: fluid node next to a segment
   int64_t n_fluid = 0;
   SegHost seg[GG_MAX_SEGMENTS];
@@ -41,9 +43,9 @@ struct gg_lattice {
   double *d_flux = nullptr, *d_acc = nullptr;
   gg::LatDesc *d_desc = nullptr;
   gg::LatDesc h{};
-  int4 *d_tiles = nullptr;
+  gg::Tile *d_tiles = nullptr;
   int n_tiles = 0, tile_x = 64, tile_y = 4;
-  int4 *d_aux_tiles = nullptr;
+  gg::Tile *d_aux_tiles = nullptr;
   int n_aux_tiles = 0;
   int graph_chunk = 64;
   hipGraph_t graph = nullptr;

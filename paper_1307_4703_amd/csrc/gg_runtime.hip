@@ -68,6 +68,7 @@ gg_status gg_upload_desc(gg_lattice *L) {
   h.nx = L->nx;
   h.ny = L->ny;
   h.pitch = L->pitch;
+  h.node0 = L->node0;
   h.periodic_x = L->p.periodic_x != 0;
   h.periodic_y = L->p.periodic_y != 0;
   h.plane = L->plane;
@@ -122,29 +123,29 @@ gg_status gg_upload_desc(gg_lattice *L) {
 
 // Tiles of tx*ty nodes holding at least one fluid node, row-major.
 static void build_tiles(const gg_lattice *L, int tx, int ty, int inst,
-                        std::vector<int4> &out) {
+                        std::vector<Tile> &out) {
   for (int y0 = 0; y0 < L->ny; y0 += ty)
     for (int x0 = 0; x0 < L->nx; x0 += tx) {
       bool any = false, seg = false;
       for (int y = y0; y < std::min(y0 + ty, L->ny); ++y)
         for (int x = x0; x < std::min(x0 + tx, L->nx); ++x) {
-          if (L->link[(size_t)y * L->pitch + x] == NOT_FLUID) continue;
+          if (L->link[L->nid(x, y)] == NOT_FLUID) continue;
           any = true;
           if (L->touches_seg[(size_t)y * L->nx + x]) seg = true;
         }
-      if (any) out.push_back(make_int4(inst, x0, y0, seg ? TILE_TOUCHES_SEGMENT : 0));
+      if (any) out.push_back(Tile{inst, x0, y0, seg ? TILE_TOUCHES_SEGMENT : 0});
     }
 }
 
 gg_status gg_rebuild_tiles(gg_lattice *L) {
-  std::vector<int4> t;
+  std::vector<Tile> t;
   build_tiles(L, L->tile_x, L->tile_y, 0, t);
   if (L->d_tiles) (void)hipFree(L->d_tiles);
   L->d_tiles = nullptr;
   L->n_tiles = (int)t.size();
   if (!t.empty()) {
-    GG_HIP(hipMalloc(&L->d_tiles, t.size() * sizeof(int4)));
-    GG_HIP(hipMemcpy(L->d_tiles, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
+    GG_HIP(hipMalloc(&L->d_tiles, t.size() * sizeof(Tile)));
+    GG_HIP(hipMemcpy(L->d_tiles, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice));
   }
   if (L->graph_exec) (void)hipGraphExecDestroy(L->graph_exec);
   if (L->graph) (void)hipGraphDestroy(L->graph);
@@ -178,17 +179,23 @@ gg_status gg_create(const uint8_t *mask, int32_t nx, int32_t ny, const gg_params
   if (esize == 0) return fail(GG_ERR_ARG, "unknown storage");
   gg_status st = check_params(params);
   if (st != GG_OK) return st;
-  const int pitch = (nx + 63) / 64 * 64;
-  if ((int64_t)pitch * ny > (int64_t)0x7FFFFFFF - 64)
-    return fail(GG_ERR_ARG, "lattice too large for 32-bit node indices");
+  // one padding column (x = nx, doubling as x = -1 of the next row) and one
+  // padding row on each side; rows start on 64-element boundaries
+  const int pitch = (nx + 1 + 63) / 64 * 64;
+  const int64_t plane_elems = (int64_t)(ny + 2) * pitch + 128;
+  // kernels address a plane with a 32-bit byte offset
+  if (plane_elems * (int64_t)esize > ((int64_t)1 << 32) - 4096)
+    return fail(GG_ERR_ARG, "lattice too large: one population plane must stay below 4 GiB");
 
   gg_lattice *L = new gg_lattice();
   L->nx = nx;
   L->ny = ny;
   L->pitch = pitch;
-  // Plane stride: whole rows plus a 1.25 KiB-ish stagger so that the 14
-  // population planes do not start on the same DRAM channel.
-  L->plane = (int64_t)pitch * ny + 320;
+  L->node0 = pitch + 64;
+  L->plane_elems = plane_elems;
+  // Plane stride: the padded plane plus a stagger so that the 14 planes do
+  // not start on the same DRAM channel.
+  L->plane = plane_elems + 320;
   L->storage = storage;
   L->esize = esize;
   L->stream = (hipStream_t)hip_stream;
@@ -200,7 +207,7 @@ gg_status gg_create(const uint8_t *mask, int32_t nx, int32_t ny, const gg_params
   L->t = 0;
 
   // classify links
-  L->link.assign((size_t)pitch * ny, NOT_FLUID);
+  L->link.assign((size_t)plane_elems, NOT_FLUID);
   L->touches_seg.assign((size_t)nx * ny, 0);
   int64_t nf = 0;
   for (int y = 0; y < ny; ++y)
@@ -247,7 +254,7 @@ gg_status gg_create(const uint8_t *mask, int32_t nx, int32_t ny, const gg_params
         return s;
       }
       L->touches_seg[(size_t)y * nx + x] = nseg > 0;
-      L->link[(size_t)y * pitch + x] = code;
+      L->link[L->nid(x, y)] = code;
       ++nf;
     }
   L->n_fluid = nf;
@@ -259,8 +266,8 @@ gg_status gg_create(const uint8_t *mask, int32_t nx, int32_t ny, const gg_params
   };
   const size_t pop_bytes = (size_t)NPOP * L->plane * esize;
   if ((st = alloc(&L->d_pop, pop_bytes)) != GG_OK ||
-      (st = alloc((void **)&L->d_link, (size_t)pitch * ny)) != GG_OK ||
-      (st = alloc((void **)&L->d_mask, (size_t)pitch * ny)) != GG_OK ||
+      (st = alloc((void **)&L->d_link, (size_t)plane_elems)) != GG_OK ||
+      (st = alloc((void **)&L->d_mask, (size_t)plane_elems)) != GG_OK ||
       (st = alloc((void **)&L->d_t, sizeof(int64_t))) != GG_OK ||
       (st = alloc((void **)&L->d_flux, 2 * GG_MAX_SEGMENTS * sizeof(double))) != GG_OK ||
       (st = alloc((void **)&L->d_acc, 8 * sizeof(double))) != GG_OK ||
@@ -269,9 +276,9 @@ gg_status gg_create(const uint8_t *mask, int32_t nx, int32_t ny, const gg_params
     delete L;
     return st;
   }
-  std::vector<uint8_t> mpitch((size_t)pitch * ny, GG_MASK_WALL);
+  std::vector<uint8_t> mpitch((size_t)plane_elems, GG_MASK_WALL);
   for (int y = 0; y < ny; ++y)
-    std::memcpy(&mpitch[(size_t)y * pitch], &L->mask[(size_t)y * nx], nx);
+    std::memcpy(&mpitch[L->nid(0, y)], &L->mask[(size_t)y * nx], nx);
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMemcpy(L->d_link, L->link.data(), L->link.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(L->d_mask, mpitch.data(), mpitch.size(), hipMemcpyHostToDevice);
@@ -286,16 +293,16 @@ gg_status gg_create(const uint8_t *mask, int32_t nx, int32_t ny, const gg_params
     return s;
   }
   // auxiliary kernels always run 64 x 4 tiles
-  std::vector<int4> aux;
+  std::vector<Tile> aux;
   build_tiles(L, 64, 4, 0, aux);
   L->n_aux_tiles = (int)aux.size();
   if (!aux.empty()) {
-    if ((st = alloc((void **)&L->d_aux_tiles, aux.size() * sizeof(int4))) != GG_OK) {
+    if ((st = alloc((void **)&L->d_aux_tiles, aux.size() * sizeof(Tile))) != GG_OK) {
       gg_free_device(L);
       delete L;
       return st;
     }
-    if (hipMemcpy(L->d_aux_tiles, aux.data(), aux.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(L->d_aux_tiles, aux.data(), aux.size() * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess) {
       gg_free_device(L);
       delete L;
       return fail(GG_ERR_HIP, "upload of the tile list failed");
@@ -422,9 +429,9 @@ gg_status gg_set_region(gg_lattice *L, const uint8_t *region) {
   if (L->d_region) (void)hipFree(L->d_region);
   L->d_region = nullptr;
   if (region) {
-    std::vector<uint8_t> r((size_t)L->pitch * L->ny, 0);
+    std::vector<uint8_t> r((size_t)L->plane_elems, 0);
     for (int y = 0; y < L->ny; ++y)
-      for (int x = 0; x < L->nx; ++x) r[(size_t)y * L->pitch + x] = region[(size_t)y * L->nx + x] ? 1 : 0;
+      for (int x = 0; x < L->nx; ++x) r[L->nid(x, y)] = region[(size_t)y * L->nx + x] ? 1 : 0;
     GG_HIP(hipMalloc(&L->d_region, r.size()));
     GG_HIP(hipMemcpy(L->d_region, r.data(), r.size(), hipMemcpyHostToDevice));
   }
@@ -474,22 +481,36 @@ static gg_status check_segments(gg_lattice *L) {
   return GG_OK;
 }
 
+// Launch `n` step kernels on `st` for a lattice whose device counter reads
+// t0 (host mirror), then advance the counter.
+static hipError_t launch_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t st) {
+  const int block = L->tile_x * L->tile_y;
+  const int txs = ilog2(L->tile_x);
+  hipError_t e = hipSuccess;
+  for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt)
+    e = launch_step(L->storage, block, ((t0 + dt) & 1) != 0, L->d_desc, L->d_tiles,
+                    L->n_tiles, txs, (int)dt, st);
+  if (e == hipSuccess) e = launch_advance(L->d_desc, 1, n, st);
+  return e;
+}
+
 gg_status gg_step(gg_lattice *L, int64_t n) {
   if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
   if (n < 0) return fail(GG_ERR_ARG, "n must be non-negative");
   gg_status st = check_segments(L);
   if (st != GG_OK) return st;
-  const int block = L->tile_x * L->tile_y;
-  const int txs = ilog2(L->tile_x);
   int64_t left = n;
-  const int K = L->graph_chunk;
-  if (K > 0 && left >= K) {
+  const int K = L->graph_chunk;  // even, so every replay starts on an even step
+  if (K > 0 && (L->t & 1) && left >= K + 1) {
+    // graphs are captured for an even starting step
+    GG_HIP(launch_steps(L, L->t, 1, L->stream));
+    L->t += 1;
+    left -= 1;
+  }
+  if (K > 0 && !(L->t & 1) && left >= K) {
     if (!L->graph_exec) {
       GG_HIP(hipStreamBeginCapture(L->cap_stream, hipStreamCaptureModeThreadLocal));
-      hipError_t e = hipSuccess;
-      for (int dt = 0; dt < K && e == hipSuccess; ++dt)
-        e = launch_step(L->storage, block, L->d_desc, L->d_tiles, L->n_tiles, txs, dt, L->cap_stream);
-      if (e == hipSuccess) e = launch_advance(L->d_desc, 1, K, L->cap_stream);
+      hipError_t e = launch_steps(L, 0, K, L->cap_stream);
       hipGraph_t g = nullptr;
       hipError_t e2 = hipStreamEndCapture(L->cap_stream, &g);
       if (e != hipSuccess || e2 != hipSuccess) {
@@ -507,9 +528,7 @@ gg_status gg_step(gg_lattice *L, int64_t n) {
     }
   }
   if (left > 0) {
-    for (int64_t dt = 0; dt < left; ++dt)
-      GG_HIP(launch_step(L->storage, block, L->d_desc, L->d_tiles, L->n_tiles, txs, (int)dt, L->stream));
-    GG_HIP(launch_advance(L->d_desc, 1, left, L->stream));
+    GG_HIP(launch_steps(L, L->t, left, L->stream));
     L->t += left;
   }
   return GG_OK;
@@ -665,7 +684,7 @@ gg_status gg_set_launch(gg_lattice *L, int32_t tile_x, int32_t tile_y, int32_t g
   GG_HIP(hipStreamSynchronize(L->stream));
   L->tile_x = tile_x;
   L->tile_y = tile_y;
-  L->graph_chunk = graph_chunk;
+  L->graph_chunk = (graph_chunk + 1) / 2 * 2;  // even: replays keep the parity
   return gg_rebuild_tiles(L);
 }
 
@@ -677,8 +696,8 @@ gg_status gg_info(const gg_lattice *L, int64_t *n_fluid, int64_t *n_tiles, int64
   return GG_OK;
 }
 
-gg_status gg_step_timed(gg_lattice *L, int64_t n, double *kernel_ms) {
-  if (!L || !kernel_ms) return fail(GG_ERR_ARG, "NULL argument");
+gg_status gg_step_timed(gg_lattice *L, int64_t n, double *ms_even, double *ms_odd) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
   if (n < 1) return fail(GG_ERR_ARG, "n must be positive");
   gg_status st = check_segments(L);
   if (st != GG_OK) return st;
@@ -687,25 +706,31 @@ gg_status gg_step_timed(gg_lattice *L, int64_t n, double *kernel_ms) {
   std::vector<hipEvent_t> ev(2 * (size_t)n, nullptr);
   hipError_t e = hipSuccess;
   for (size_t k = 0; k < ev.size() && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
+  const int64_t t0 = L->t;
   for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt) {
     e = hipEventRecord(ev[2 * dt], L->stream);
     if (e == hipSuccess)
-      e = launch_step(L->storage, block, L->d_desc, L->d_tiles, L->n_tiles, txs, (int)dt, L->stream);
+      e = launch_step(L->storage, block, ((t0 + dt) & 1) != 0, L->d_desc, L->d_tiles,
+                      L->n_tiles, txs, (int)dt, L->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * dt + 1], L->stream);
   }
   if (e == hipSuccess) e = launch_advance(L->d_desc, 1, n, L->stream);
   if (e == hipSuccess) L->t += n;
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
-  double total = 0.0;
+  double tot[2] = {0.0, 0.0};
+  int64_t cnt[2] = {0, 0};
   for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt) {
     float ms = 0.0f;
     e = hipEventElapsedTime(&ms, ev[2 * dt], ev[2 * dt + 1]);
-    total += ms;
+    const int par = (int)((t0 + dt) & 1);
+    tot[par] += ms;
+    cnt[par] += 1;
   }
   for (hipEvent_t x : ev)
     if (x) (void)hipEventDestroy(x);
   if (e != hipSuccess) return fail(GG_ERR_HIP, std::string("timed steps: ") + hipGetErrorString(e));
-  *kernel_ms = total / (double)n;
+  if (ms_even) *ms_even = cnt[0] ? tot[0] / (double)cnt[0] : 0.0;
+  if (ms_odd) *ms_odd = cnt[1] ? tot[1] / (double)cnt[1] : 0.0;
   return GG_OK;
 }
 

@@ -129,12 +129,12 @@ class Lattice:
     def set_launch(self, tile_x: int = 64, tile_y: int = 4, graph_chunk: int = 64) -> None:
         A.call("gg_set_launch", self._h, int(tile_x), int(tile_y), int(graph_chunk))
 
-    def step_timed(self, n: int) -> float:
+    def step_timed(self, n: int) -> Tuple[float, float]:
         """Advance n steps with every step kernel between HIP events; mean
-        kernel duration in milliseconds."""
-        ms = ctypes.c_double()
-        A.call("gg_step_timed", self._h, int(n), ctypes.byref(ms))
-        return ms.value
+        (even-step, odd-step) kernel durations in milliseconds."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        A.call("gg_step_timed", self._h, int(n), ctypes.byref(a), ctypes.byref(b))
+        return a.value, b.value
 
     def sync(self) -> None:
         A.call("gg_sync", self._h)
