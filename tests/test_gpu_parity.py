@@ -158,5 +158,7 @@ def test_gradient_generator_full_size_f32():
         assert err[k] < v, (k, err)
     d = lat.diagnostics()
     m, s = o.totals()
-    assert d["mass"] == pytest.approx(m, rel=1e-6)
+    # plain FP32 populations near w_i round with a correlated bias: about
+    # 1e-8 of the mass per step (see the precision notes)
+    assert d["mass"] == pytest.approx(m, rel=2e-5)
     assert d["max_u_region"] < 0.1 * 0.04  # the chamber stays nearly still
