@@ -37,21 +37,19 @@ def bytes_per_update(storage):
 
 def workload(name):
     from paper_1307_4703_amd import workloads as W
-    if name == "gg2048_f32":
-        return W.gradient_generator(storage="f32")
-    if name == "gg2048_f16":
-        return W.gradient_generator(storage="f16")
-    if name == "gg8192_f16":
-        return W.gradient_generator(scale=4.0, storage="f16")
-    if name == "gg8192_f32":
-        return W.gradient_generator(scale=4.0, storage="f32")
-    if name == "allfluid8192_f32":
-        return W.all_fluid_channel(storage="f32")
-    if name == "allfluid8192_f16":
-        return W.all_fluid_channel(storage="f16")
-    if name == "straight_f64":
-        return W.straight_channel()
-    raise SystemExit(f"unknown workload {name}")
+    table = {
+        "gg2048_f32": lambda: W.gradient_generator(storage="f32"),
+        "gg2048_f16": lambda: W.gradient_generator(storage="f16"),
+        "gg8192_f16": lambda: W.gradient_generator(scale=4.0, storage="f16"),
+        "gg8192_f16_pe2000": lambda: W.gradient_generator(scale=4.0, storage="f16", peclet=2000.0),
+        "gg8192_f32": lambda: W.gradient_generator(scale=4.0, storage="f32"),
+        "allfluid8192_f32": lambda: W.all_fluid_channel(storage="f32"),
+        "allfluid8192_f16": lambda: W.all_fluid_channel(storage="f16"),
+        "straight_f64": lambda: W.straight_channel(),
+    }
+    if name not in table:
+        raise SystemExit(f"unknown workload {name}; choose from {sorted(table)}")
+    return table[name]()
 
 
 def kernel_hash():
@@ -68,54 +66,67 @@ def load_traffic(wl_name):
             data = json.load(fh)
     except (OSError, ValueError):
         return None
-    ent = data.get(wl_name)
-    if not ent or ent.get("kernel_sha") != kernel_hash():
+    ent = data.get("workloads", {}).get(wl_name)
+    if not ent or data.get("kernel_sha") != kernel_hash():
         return None
     return ent.get("bytes_per_launch")
 
 
-def make_lattice(name, tile, chunk):
+def time_lattice(name, steps, warmup, tile, chunk):
+    """Graph-replayed steps timed with HIP events on the lattice's stream
+    (torch's current stream), plus an even/odd kernel breakdown."""
+    import torch
     from paper_1307_4703_amd import Lattice
     wl = workload(name)
     lat = Lattice.from_workload(wl)
     lat.set_launch(tile[0], tile[1], chunk)
-    return wl, lat
-
-
-def time_lattice(name, steps, warmup, tile, chunk):
-    import torch
-    wl, lat = make_lattice(name, tile, chunk)
     nf = lat.info()["n_fluid"]
     log(f"{wl.name}: {wl.nx}x{wl.ny}, {nf} fluid nodes, storage {wl.storage}, "
         f"tile {tile}, graph chunk {chunk}; warmup {warmup}")
     lat.step(warmup)
     lat.sync()
     torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     log(f"timed region: {steps} steps")
     t0 = time.perf_counter()
+    ev0.record(stream)
     lat.step(steps)
+    ev1.record(stream)
     lat.sync()
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    n_k = min(steps, 2000)
-    log(f"per-kernel event timing over {n_k} step launches")
-    kms = lat.step_timed(n_k)
-    diag = lat.diagnostics()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    n_k = min(steps, 400 if nf > 1e7 else 2000)
+    ms_even, ms_odd = lat.step_timed(n_k)
+    diag = lat.diagnostics(check_finite=False)
     lat.close()
-    return wl, nf, dt, kms, diag
+    return {"wl": wl, "nf": nf, "wall_s": wall, "event_ms": ev_ms,
+            "kernel_ms": ev_ms / steps, "ms_even": ms_even, "ms_odd": ms_odd, "diag": diag}
+
+
+def roofline(r, storage, traffic):
+    bpl = r["nf"] * bytes_per_update(storage)
+    ach = bpl / (r["kernel_ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes_per_launch": bpl, "kernel_ms": round(r["kernel_ms"], 5),
+            "kernel_ms_even_odd": [round(r["ms_even"], 5), round(r["ms_odd"], 5)]}
 
 
 def copy_bandwidth(nbytes=2 << 30, reps=20):
     import ctypes
     import torch
     from paper_1307_4703_amd import _abi as A
-    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    a = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     ms = ctypes.c_double()
     stream = torch.cuda.current_stream().cuda_stream
     A.call("gg_stream_copy", ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(a.data_ptr()),
            nbytes, reps, ctypes.c_void_p(stream), ctypes.byref(ms))
-    return 2.0 * nbytes / (ms.value * 1e-3) / 1e9, ms.value
+    del a, b
+    return 2.0 * nbytes / (ms.value * 1e-3) / 1e9
 
 
 def cpu_baseline(name, budget_s=15.0):
@@ -138,32 +149,22 @@ def cpu_baseline(name, budget_s=15.0):
     t0 = time.perf_counter()
     o.step(n)
     dt = time.perf_counter() - t0
-    return {"value": nf * n / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
+    return {"value": round(nf * n / dt / 1e6, 2), "unit": "MLUPS", "cores": oracle.threads(),
             "kind": "oracle",
-            "sample": f"{n} FP64 oracle steps of {wl.name} ({nf} fluid nodes) from its initial state"}
-
-
-def roofline(nf, storage, kms, traffic):
-    bpl = nf * bytes_per_update(storage)
-    ach = bpl / (kms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(ach / PEAK_HBM_GBS, 4),
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": bpl,
-            "kernel_ms": round(kms, 5)}
+            "sample": f"{n} FP64 oracle steps of {wl.name} ({nf} fluid nodes) from rest"}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--workload", default="gg2048_f32")
     ap.add_argument("--tile", default="64x4")
     ap.add_argument("--chunk", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the out-of-cache roofline lattice and the copy bandwidth")
+                    help="skip the out-of-cache and FP16 lattices and the copy bandwidth")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -176,16 +177,16 @@ def main():
     torch.cuda.set_device(0)
     tile = tuple(int(v) for v in args.tile.split("x"))
 
-    wl, nf, dt, kms, diag = time_lattice(args.workload, args.steps, args.warmup, tile, args.chunk)
-    mlups = nf * args.steps / dt / 1e6
+    r = time_lattice(args.workload, args.steps, args.warmup, tile, args.chunk)
+    wl, nf = r["wl"], r["nf"]
     out = {
         "metric": METRIC,
-        "value": round(mlups, 1),
+        "value": round(nf * args.steps / (r["event_ms"] * 1e-3) / 1e6, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 6),
+        "ms_per_step": round(r["event_ms"] / args.steps, 6),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -193,31 +194,33 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "n_fluid": nf,
                    "storage": wl.storage, "D": wl.D, "tau_f": wl.tau_f,
-                   "schedule_half_period": wl.schedule[0].duration if wl.schedule else None,
+                   "valve_half_period": wl.schedule[0].duration if wl.schedule else None,
                    "tile": args.tile, "graph_chunk": args.chunk,
                    "bytes_per_update": bytes_per_update(wl.storage),
-                   "lattice_updates_per_s": round(wl.nx * wl.ny * args.steps / dt / 1e6, 1),
+                   "wall_clock_mlups": round(nf * args.steps / r["wall_s"] / 1e6, 1),
+                   "lattice_mlups": round(wl.nx * wl.ny * args.steps / (r["event_ms"] * 1e-3) / 1e6, 1),
                    "parallelism": "single GPU"},
-        "roofline": roofline(nf, wl.storage, kms, load_traffic(args.workload)),
-        "mass_drift_check": {"t": diag["t"], "mass": diag["mass"],
-                             "max_u_chamber": diag["max_u_region"],
-                             "max_cell_peclet_chamber": diag["max_pe_region"]},
+        "roofline": roofline(r, wl.storage, load_traffic(args.workload)),
+        "diagnostics": {"t": r["diag"]["t"], "mass": r["diag"]["mass"],
+                        "n_nonfinite": r["diag"]["n_nonfinite"],
+                        "max_u_chamber": r["diag"]["max_u_region"],
+                        "max_cell_peclet_chamber": r["diag"]["max_pe_region"]},
     }
     if not args.no_extra:
-        try:
-            bw, cms = copy_bandwidth()
-            out["copy_bandwidth_gbs"] = round(bw, 1)
-            log(f"plain copy: {bw:.0f} GB/s")
-        except Exception as e:  # report, do not hide
-            out["copy_bandwidth_gbs"] = f"failed: {e}"
-        if args.workload.startswith("gg2048"):
-            st = args.workload.split("_")[1]
-            name = f"allfluid8192_{st}"
-            wl2, nf2, dt2, kms2, _ = time_lattice(name, 1000, 100, tile, args.chunk)
-            r2 = roofline(nf2, wl2.storage, kms2, load_traffic(name))
-            r2["workload"] = wl2.name
-            r2["mlups"] = round(nf2 * 1000 / dt2 / 1e6, 1)
-            out["roofline_out_of_cache"] = r2
+        out["copy_bandwidth_gbs"] = round(copy_bandwidth(), 1)
+        log(f"plain copy: {out['copy_bandwidth_gbs']} GB/s")
+        extra = {}
+        for name, steps in (("allfluid8192_f32", 1000), ("allfluid8192_f16", 1000),
+                            ("gg8192_f16", 2000)):
+            if name == args.workload:
+                continue
+            r2 = time_lattice(name, steps, 100, tile, args.chunk)
+            e = roofline(r2, r2["wl"].storage, load_traffic(name))
+            e["mlups"] = round(r2["nf"] * steps / (r2["event_ms"] * 1e-3) / 1e6, 1)
+            e["workload"] = r2["wl"].name
+            e["storage"] = r2["wl"].storage
+            extra[name] = e
+        out["roofline_other_lattices"] = extra
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
