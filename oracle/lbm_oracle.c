@@ -356,3 +356,91 @@ int orc_threads(void) {
   return 1;
 #endif
 }
+
+/* ---------------------------------------------------------------- */
+/* Discrete adjoint of one compound step (test infrastructure)         */
+/* ---------------------------------------------------------------- */
+
+/* The compound update t -> t+1 is affine in g for a given fluid state:
+ *   collision  g*_i = (1 - w) g_i + (w W_i(u) - k wg_i) C + wg_i R,
+ *              W_i(u) = wg_i (1 + e_i.u / cs2), C = sum_j g_j   (Eqs. 2, 8, 9)
+ *   streaming  G(z, i) = g*_i(z - e_i)            (fluid source)
+ *              G(z, i) = g*_opp(z)                (wall, closed valve)
+ *              G(z, i) = -g*_opp(z) + 2 wg_i C_in (open inlet)
+ *              G(z, i) = g*_i(z)                  (open outlet)
+ * Given lam = dL/dG at t+1, this computes dL/dg at t (lam_out) and adds the
+ * step's contribution to dL/dR (per node), dL/dC_in (per mask value) and
+ * dL/domega_g. f and g are the populations at time t (u is taken from f).
+ * Each node gathers lam* = dL/dg* over every use of its post-collision
+ * populations, then applies the transposed collision matrix. */
+void orc_adjoint_step(const orc_lattice *L, const double *f, const double *g,
+                      const double *lam, double *lam_out, const uint8_t *open,
+                      double *dR, double *dcin, double *domega) {
+  const int nx = L->nx, ny = L->ny;
+  const size_t n = (size_t)nx * ny;
+  const double omega = 1.0 / L->tau_g;
+  const double cs2 = (1.0 - L->w0) / 2.0;
+  double wg[5];
+  orc_gweights(L->w0, wg);
+  memset(lam_out, 0, sizeof(double) * 5 * n);
+  double *rowacc = (double *)calloc((size_t)ny * 257, sizeof(double));
+
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y) {
+    double *ra = rowacc + (size_t)y * 257;
+    for (int x = 0; x < nx; ++x) {
+      size_t node = (size_t)y * nx + x;
+      if (L->mask[node] != 0) continue;
+      const double *fx = f + 9 * node, *gx = g + 5 * node, *lx = lam + 5 * node;
+      double rho = 0.0, jx = 0.0, jy = 0.0, C = 0.0;
+      for (int i = 0; i < 9; ++i) {
+        rho += fx[i];
+        jx += fx[i] * EX[i];
+        jy += fx[i] * EY[i];
+      }
+      for (int i = 0; i < 5; ++i) C += gx[i];
+      double ux = jx / rho, uy = jy / rho;
+
+      double ls[5];
+      ls[0] = lx[0];
+      for (int j = 1; j < 5; ++j) {
+        ls[j] = 0.0;
+        int opp = OPP[j];
+        int xt = 0, yt = 0;
+        int code = cell_code(L, x + EX[j], y + EY[j], &xt, &yt);
+        if (code == 0) {
+          ls[j] += lam[5 * ((size_t)yt * nx + xt) + j];
+        } else {
+          int kind = (code >= 2) ? L->seg_kind[code] : ORC_SEG_NONE;
+          if (kind != ORC_SEG_NONE && !open[code]) kind = ORC_SEG_NONE;
+          if (kind == ORC_SEG_NONE) {
+            ls[j] += lx[opp];
+          } else if (kind == ORC_SEG_INLET) {
+            ls[j] -= lx[opp];
+            ra[code] += 2.0 * wg[opp] * lx[opp];
+          } /* open outlet ahead: g*_j leaves the domain */
+        }
+        int xs = 0, ys = 0;
+        int scode = cell_code(L, x - EX[j], y - EY[j], &xs, &ys);
+        if (scode >= 2 && L->seg_kind[scode] == ORC_SEG_OUTLET && open[scode])
+          ls[j] += lx[j]; /* the outlet ghost behind re-emits g*_j */
+      }
+
+      double W[5], s = 0.0, dr = 0.0, dw = 0.0;
+      for (int j = 0; j < 5; ++j) {
+        W[j] = wg[j] * (1.0 + (EX[j] * ux + EY[j] * uy) / cs2);
+        s += (omega * W[j] - L->k_decay * wg[j]) * ls[j];
+        dr += wg[j] * ls[j];
+        dw -= ls[j] * (gx[j] - W[j] * C);
+      }
+      for (int i = 0; i < 5; ++i) lam_out[5 * node + i] = (1.0 - omega) * ls[i] + s;
+      if (dR) dR[node] += dr;
+      ra[256] += dw;
+    }
+  }
+  for (int y = 0; y < ny; ++y) {
+    for (int m = 0; m < 256; ++m) dcin[m] += rowacc[(size_t)y * 257 + m];
+    *domega += rowacc[(size_t)y * 257 + 256];
+  }
+  free(rowacc);
+}

@@ -71,6 +71,8 @@ def lib() -> ctypes.CDLL:
         for fn in ("orc_feq", "orc_geq", "orc_step", "orc_init_eq",
                    "orc_moments", "orc_totals"):
             getattr(L, fn).restype = None
+        L.orc_adjoint_step.argtypes = [P] * 9
+        L.orc_adjoint_step.restype = None
         L.orc_threads.argtypes = []
         L.orc_threads.restype = ctypes.c_int
         _LIB = L
@@ -242,3 +244,37 @@ class Oracle:
         lib().orc_totals(ctypes.byref(self._c), _ptr(self.f), _ptr(self.g),
                          ctypes.byref(m), ctypes.byref(s))
         return m.value, s.value
+
+    # -- discrete adjoint -------------------------------------------------
+    def adjoint(self, n_steps: int, weight: np.ndarray, target: np.ndarray):
+        """Run n_steps forward from the current state, then the discrete
+        adjoint back to the start, for L = 1/2 sum_x weight (C_T - target)^2.
+
+        Returns (loss, dL/dC_in per mask value [256], dL/dD, dL/dR [ny, nx]).
+        Every intermediate state is kept in memory (small lattices only).
+        """
+        weight = np.asarray(weight, np.float64).reshape(self.ny, self.nx)
+        target = np.asarray(target, np.float64).reshape(self.ny, self.nx)
+        fl = self.mask == 0
+        states = []
+        for _ in range(int(n_steps)):
+            states.append((self.f.copy(), self.g.copy(), self.phase(self.t)[0], self.t))
+            self.step(1)
+        C = self.g.sum(axis=2)
+        resid = np.where(fl, weight * (C - target), 0.0)
+        loss = 0.5 * float(np.sum(np.where(fl, weight * (C - target) ** 2, 0.0)))
+        lam = np.ascontiguousarray(np.repeat(resid[:, :, None], 5, axis=2))
+        lam_out = np.zeros_like(lam)
+        dR = np.zeros((self.ny, self.nx))
+        dcin = np.zeros(256)
+        domega = ctypes.c_double(0.0)
+        L = lib()
+        for f, g, open_, _t in reversed(states):
+            L.orc_adjoint_step(ctypes.byref(self._c), _ptr(f), _ptr(g), _ptr(lam),
+                               _ptr(lam_out), _ptr(open_), _ptr(dR), _ptr(dcin),
+                               ctypes.byref(domega))
+            lam, lam_out = lam_out, lam
+        self.lam0 = lam
+        cs2 = (1.0 - self.w0) / 2.0
+        domega_dD = -1.0 / (self.tau_g ** 2 * cs2)
+        return loss, dcin, domega.value * domega_dD, dR

@@ -10,6 +10,7 @@ import pytest
 
 from oracle import build_oracle
 from oracle import oracle as orc
+from tests import test_oracle_adjoint as AD
 from tests import test_oracle_pins as P
 
 PINS = [
@@ -27,6 +28,9 @@ PINS = [
     (P.test_inlet_concentration_fills_channel, {}),
     (P.test_poiseuille_profile_and_linear_pressure_drop, {}),
     (P.test_advected_gaussian_closed_form_and_second_order, {}),
+    (AD.test_adjoint_step_is_transpose_of_forward_step, dict(t_phase=0)),
+    (AD.test_adjoint_step_is_transpose_of_forward_step, dict(t_phase=15)),
+    (AD.test_adjoint_gradients_match_central_differences, {}),
 ]
 
 MUTATIONS = {
@@ -55,6 +59,15 @@ MUTATIONS = {
                                     "in_f = 0.999 * out_f;\n          in_g = out_g;\n        } else if"),
     "tau_f": ("double omega_f = 1.0 / L->tau_f;", "double omega_f = 1.0 / (L->tau_f + 0.05);"),
     "tau_g": ("double omega_g = 1.0 / L->tau_g;", "double omega_g = 1.0 / (L->tau_g + 0.05);"),
+    "adjoint inlet sign": ("ls[j] -= lx[opp];", "ls[j] += lx[opp];"),
+    "adjoint outlet re-emission": ("ls[j] += lx[j]; /* the outlet", "ls[j] += 0.0 * lx[j]; /* the outlet"),
+    "adjoint collision": ("lam_out[5 * node + i] = (1.0 - omega) * ls[i] + s;",
+                          "lam_out[5 * node + i] = (1.0 - omega) * ls[i] + 0.5 * s;"),
+    "adjoint C_in factor": ("ra[code] += 2.0 * wg[opp]", "ra[code] += 1.0 * wg[opp]"),
+    "adjoint omega sign": ("dw -= ls[j] * (gx[j] - W[j] * C);", "dw += ls[j] * (gx[j] - W[j] * C);"),
+    "adjoint source weight": ("dr += wg[j] * ls[j];", "dr += ls[j];"),
+    "adjoint wall transpose": ("            ls[j] += lx[opp];\n          } else if (kind == ORC_SEG_INLET) {",
+                               "            ls[j] += lx[j];\n          } else if (kind == ORC_SEG_INLET) {"),
 }
 
 
