@@ -199,6 +199,35 @@ gg_status gg_set_launch(gg_lattice *lat, int32_t tile_x, int32_t tile_y,
 gg_status gg_info(const gg_lattice *lat, int64_t *n_fluid, int64_t *n_tiles,
                   int64_t *t);
 
+/* Gradients returned by gg_adjoint. */
+typedef struct gg_grads {
+  double loss;                      /* 1/2 sum_x weight(x) (C(x) - target(x))^2 */
+  double d_c_in[GG_MAX_SEGMENTS];   /* dL/dC_in of segment GG_FIRST_SEGMENT + k,
+                                       for a change of its inlet concentration
+                                       in every phase in which it is open */
+  double d_D;                       /* dL/dD */
+  double d_omega_g;                 /* dL/d(1/tau_g) */
+  int64_t ckpt_every;               /* steps between checkpoints used */
+  int64_t n_checkpoints;
+} gg_grads;
+
+/* Discrete adjoint of the coupled step with respect to the compound's
+ * parameters. From the current state at time t0, advances n_steps >= 1
+ * (the lattice ends at t0 + n_steps, as after gg_step), evaluates
+ * L = 1/2 sum_x weight(x) (C(x) - target(x))^2 on the final compound field,
+ * then runs the hand-written adjoint of each step backwards. The fluid does
+ * not depend on the compound (one-way coupling), so only the compound
+ * populations carry an adjoint; the fluid velocity of each step is
+ * recomputed from checkpoints taken every ckpt_every steps (0: ceil(sqrt(n)))
+ * and taped for one segment at a time. weight and target are host arrays of
+ * nx*ny doubles. r_box = {x0, y0, w, h} (or NULL) selects the nodes whose
+ * source gradient dL/dR is written to d_R (host, w*h doubles, row-major).
+ * Device memory: about n/ckpt_every copies of the state plus ckpt_every
+ * tape slots of 7 fields; GG_ERR_OOM if it does not fit. */
+gg_status gg_adjoint(gg_lattice *lat, int64_t n_steps, int64_t ckpt_every,
+                     const double *weight, const double *target,
+                     const int32_t *r_box, double *d_R, gg_grads *out);
+
 /* Instrumentation: advance n >= 1 steps launching every step kernel
  * between two HIP events on the lattice's stream (no graphs) and return the
  * mean event-measured duration, in ms, of the even-step and of the

@@ -54,6 +54,13 @@ class gg_diag(ctypes.Structure):
                 ("seg_solute", ctypes.c_double * GG_MAX_SEGMENTS)]
 
 
+class gg_grads(ctypes.Structure):
+    _fields_ = [("loss", ctypes.c_double),
+                ("d_c_in", ctypes.c_double * GG_MAX_SEGMENTS),
+                ("d_D", ctypes.c_double), ("d_omega_g", ctypes.c_double),
+                ("ckpt_every", ctypes.c_int64), ("n_checkpoints", ctypes.c_int64)]
+
+
 class GGError(RuntimeError):
     def __init__(self, status: int, where: str, message: str):
         super().__init__(f"{where} failed with status {status}: {message}")
@@ -83,6 +90,7 @@ SIGS = {
     "gg_info": [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)],
     "gg_sync": [P],
     "gg_step_timed": [P, I64, ctypes.POINTER(D), ctypes.POINTER(D)],
+    "gg_adjoint": [P, I64, I64, P, P, P, P, ctypes.POINTER(gg_grads)],
     "gg_stream_copy": [P, P, ctypes.c_size_t, I32, P, ctypes.POINTER(D)],
 }
 

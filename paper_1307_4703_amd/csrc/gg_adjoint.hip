@@ -1,0 +1,334 @@
+// gfx950 kernels of the discrete adjoint of the compound lattice.
+//
+// The compound update t -> t+1 is affine in g for a given fluid velocity
+// field (the fluid does not feel the compound: the one-way coupling of the
+// Results section). With C = sum_j g_j and W_j(u) = w_j (1 + e_j.u/cs2):
+//   collision  g*_i = (1 - w) g_i + (w W_i - k w_i) C + w_i R      (Eqs. 2, 8, 9)
+//   links      G(z,i) = g*_i(z - e_i)      fluid source
+//              G(z,i) = g*_opp(z)          wall or closed valve
+//              G(z,i) = -g*_opp(z) + 2 w_i C_in   open inlet
+//              G(z,i) = g*_i(z)            open outlet
+// The adjoint step takes lam = dL/dG(t+1) and gives dL/dg(t): each node
+// gathers lam* = dL/dg* over every use of its post-collision populations
+// (a pull over the links), then applies the transposed collision matrix.
+// Parameter gradients accumulate on the way: dL/dR per node, dL/dC_in per
+// segment, dL/domega_g per work-group.
+#include "gg_adjoint.h"
+#include "gg_device.h"
+
+namespace gg {
+
+using CDesc = const GG_CONST LatDesc;
+
+namespace {
+
+struct Ph {
+  uint32_t open;
+  const GG_CONST double *cin;
+};
+
+__device__ __forceinline__ Ph phase_of(CDesc &L, int64_t t) {
+  if (L.n_phases == 0) return {0xFFFFFFFFu, L.seg_cin};
+  int64_t tau = (t - L.t_origin) % L.period;
+  if (tau < 0) tau += L.period;
+  int k = 0;
+  while (k + 1 < L.n_phases && L.phase_start[k + 1] <= tau) ++k;
+  return {L.phase_open[k], L.phase_cin[k]};
+}
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Work-group sum into one value (every thread of the group must call).
+template <int BS>
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+  v = wsum(v);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < BS / 64; ++k) s += lds[k];
+  return s;
+}
+
+template <class W>
+__device__ __forceinline__ const GG_GLOBAL W *at(const void *base, int64_t plane, int i, uint32_t node) {
+  return (const GG_GLOBAL W *)((const GG_GLOBAL char *)((const GG_GLOBAL W *)base + (int64_t)i * plane) +
+                               node * (uint32_t)sizeof(W));
+}
+template <class W>
+__device__ __forceinline__ GG_GLOBAL W *atw(void *base, int64_t plane, int i, uint32_t node) {
+  return (GG_GLOBAL W *)((GG_GLOBAL char *)((GG_GLOBAL W *)base + (int64_t)i * plane) +
+                         node * (uint32_t)sizeof(W));
+}
+
+// Populations of the current state in natural order (parity from *L.t).
+template <class S>
+__device__ __forceinline__ void gather_state(CDesc &L, uint32_t node, uint8_t lc, int x, int y,
+                                             typename Pop<S>::T *f, typename Pop<S>::T *g) {
+  using P = Pop<S>;
+  using T = typename P::T;
+  using W = typename P::W;
+  const bool odd = (*(const GG_CONST int64_t *)L.t & 1) != 0;
+  const int xm = (x == 0 && L.periodic_x) ? L.nx - 1 : x - 1;
+  const int xp = (x == L.nx - 1 && L.periodic_x) ? 0 : x + 1;
+  const int ym = (y == 0 && L.periodic_y) ? L.ny - 1 : y - 1;
+  const int yp = (y == L.ny - 1 && L.periodic_y) ? 0 : y + 1;
+  for (int i = 0; i < 9; ++i) {
+    const T sh = (T)(WF[i] * L.rho0);
+    uint32_t src = node;
+    int pl = i;
+    if (odd && i > 0 && !((lc >> (OPP[i] - 1)) & 1)) {
+      const int xx = EX[OPP[i]] > 0 ? xp : (EX[OPP[i]] < 0 ? xm : x);
+      const int yy = EY[OPP[i]] > 0 ? yp : (EY[OPP[i]] < 0 ? ym : y);
+      src = (uint32_t)(L.node0 + yy * L.pitch + xx);
+      pl = OPP[i];
+    }
+    f[i] = P::ld(at<W>(L.pop, L.plane, pl, src), sh);
+  }
+  for (int i = 0; i < 5; ++i) {
+    const T sh = (T)((i == 0 ? L.w0 : L.wg_axis) * L.c_shift);
+    uint32_t src = node;
+    int pl = i;
+    if (odd && i > 0 && !((lc >> (OPP[i] - 1)) & 1)) {
+      const int xx = EX[OPP[i]] > 0 ? xp : (EX[OPP[i]] < 0 ? xm : x);
+      const int yy = EY[OPP[i]] > 0 ? yp : (EY[OPP[i]] < 0 ? ym : y);
+      src = (uint32_t)(L.node0 + yy * L.pitch + xx);
+      pl = OPP[i];
+    }
+    g[i] = P::ld(at<W>(L.pop, L.plane, 9 + pl, src), sh);
+  }
+}
+
+// Tape: g_i(x,t) and u(x,t) of the current state, in the compute type.
+template <class S>
+__global__ void __launch_bounds__(256)
+    k_tape(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles, int n_tiles,
+           int tx_shift, void *__restrict__ tape) {
+  using T = typename Pop<S>::T;
+  const int tile = blockIdx.x;
+  if (tile >= n_tiles) return;
+  const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
+  CDesc &L = *(CDesc *)desc;
+  const int x = tl.x0 + (int)(threadIdx.x & ((1 << tx_shift) - 1));
+  const int y = tl.y0 + (int)(threadIdx.x >> tx_shift);
+  if (x >= L.nx || y >= L.ny) return;
+  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+  const uint8_t lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
+  if (lc == NOT_FLUID) return;
+  T f[9], g[5];
+  gather_state<S>(L, node, lc, x, y, f, g);
+  const T rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+  const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+  const T jy = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
+  const T inv = T(1) / rho;
+  for (int i = 0; i < 5; ++i) *atw<T>(tape, L.plane, i, node) = g[i];
+  *atw<T>(tape, L.plane, 5, node) = jx * inv;
+  *atw<T>(tape, L.plane, 6, node) = jy * inv;
+}
+
+// Seed: lam(x,i) = weight(x) (C(x) - target(x)) at the final state; the loss
+// 1/2 sum weight (C - target)^2 goes into per-work-group partial sums.
+template <class S>
+__global__ void __launch_bounds__(256)
+    k_seed(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles, int n_tiles,
+           int tx_shift, const double *__restrict__ weight, const double *__restrict__ target,
+           void *__restrict__ lam, double *__restrict__ partial) {
+  using T = typename Pop<S>::T;
+  __shared__ double lds[4];
+  const int tile = blockIdx.x;
+  if (tile >= n_tiles) return;
+  const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
+  CDesc &L = *(CDesc *)desc;
+  const int x = tl.x0 + (int)(threadIdx.x & ((1 << tx_shift) - 1));
+  const int y = tl.y0 + (int)(threadIdx.x >> tx_shift);
+  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+  const uint8_t lc = (x < L.nx && y < L.ny) ? ((const GG_GLOBAL uint8_t *)L.link)[node] : NOT_FLUID;
+  double loss = 0.0;
+  if (lc != NOT_FLUID) {
+    T f[9], g[5];
+    gather_state<S>(L, node, lc, x, y, f, g);
+    const double C = (double)g[0] + (double)g[1] + (double)g[2] + (double)g[3] + (double)g[4];
+    const int k = y * L.nx + x;
+    const double r = weight[k] * (C - target[k]);
+    loss = 0.5 * weight[k] * (C - target[k]) * (C - target[k]);
+    for (int i = 0; i < 5; ++i) *atw<T>(lam, L.plane, i, node) = (T)r;
+  }
+  const double s = block_sum<256>(loss, lds);
+  if (threadIdx.x == 0) partial[tile] += s;
+}
+
+// One adjoint step (pull over the links, then the transposed collision).
+template <class T>
+__global__ void __launch_bounds__(256)
+    k_adjoint(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles, int n_tiles,
+              int tx_shift, int64_t t, const void *__restrict__ lam_in, void *__restrict__ lam_out,
+              const void *__restrict__ tape, double *__restrict__ dR, int32_t rx0, int32_t ry0,
+              int32_t rw, int32_t rh, double *__restrict__ dcin, double *__restrict__ partial) {
+  __shared__ double lds[4];
+  const int tile = blockIdx.x;
+  if (tile >= n_tiles) return;
+  const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
+  CDesc &L = *(CDesc *)desc;
+  const int x = tl.x0 + (int)(threadIdx.x & ((1 << tx_shift) - 1));
+  const int y = tl.y0 + (int)(threadIdx.x >> tx_shift);
+  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+  const uint8_t lc = (x < L.nx && y < L.ny) ? ((const GG_GLOBAL uint8_t *)L.link)[node] : NOT_FLUID;
+  const bool seg_tile = (tl.flags & TILE_TOUCHES_SEGMENT) != 0;
+  Ph ph{0u, nullptr};
+  if (seg_tile) ph = phase_of(L, t);
+  int sa = -1, sb = -1;
+  double ma = 0.0, mb = 0.0, dw = 0.0;
+
+  if (lc != NOT_FLUID) {
+    const T wg[5] = {(T)L.w0, (T)L.wg_axis, (T)L.wg_axis, (T)L.wg_axis, (T)L.wg_axis};
+    T lx[5];
+    for (int i = 0; i < 5; ++i) lx[i] = *at<T>(lam_in, L.plane, i, node);
+    const int xm = (x == 0 && L.periodic_x) ? L.nx - 1 : x - 1;
+    const int xp = (x == L.nx - 1 && L.periodic_x) ? 0 : x + 1;
+    const int ym = (y == 0 && L.periodic_y) ? L.ny - 1 : y - 1;
+    const int yp = (y == L.ny - 1 && L.periodic_y) ? 0 : y + 1;
+    T ls[5];
+    ls[0] = lx[0];
+#pragma unroll
+    for (int j = 1; j < 5; ++j) {
+      ls[j] = T(0);
+      if (!((lc >> (j - 1)) & 1)) {  // x + e_j fluid: g*_j(x) streams there
+        const int xx = EX[j] > 0 ? xp : (EX[j] < 0 ? xm : x);
+        const int yy = EY[j] > 0 ? yp : (EY[j] < 0 ? ym : y);
+        ls[j] = *at<T>(lam_in, L.plane, j, (uint32_t)(L.node0 + yy * L.pitch + xx));
+      }
+    }
+    if (lc != 0) {
+#pragma unroll
+      for (int j = 1; j < 5; ++j) {
+        // link toward x + e_j when that cell is not fluid
+        if ((lc >> (j - 1)) & 1) {
+          int code = GG_MASK_WALL;
+          if (seg_tile) {
+            int sx = x + EX[j], sy = y + EY[j];
+            bool inside = true;
+            if (sx < 0 || sx >= L.nx) {
+              if (L.periodic_x) sx = (sx + L.nx) % L.nx; else inside = false;
+            }
+            if (sy < 0 || sy >= L.ny) {
+              if (L.periodic_y) sy = (sy + L.ny) % L.ny; else inside = false;
+            }
+            if (inside) code = ((const GG_GLOBAL uint8_t *)L.mask)[L.node0 + sy * L.pitch + sx];
+          }
+          const int s = code - GG_FIRST_SEGMENT;
+          const bool open = code >= GG_FIRST_SEGMENT && ((ph.open >> s) & 1u);
+          if (!open) {
+            ls[j] += lx[OPP[j]];  // bounce-back returns g*_j as G(x, opp j)
+          } else if (L.seg_kind[s] == GG_SEG_INLET) {
+            ls[j] -= lx[OPP[j]];  // anti-bounce-back
+            const double d = 2.0 * (double)wg[OPP[j]] * (double)lx[OPP[j]];
+            if (sa < 0 || sa == s) { sa = s; ma += d; } else { sb = s; mb += d; }
+          }  // open outlet ahead: g*_j leaves the lattice
+        }
+        // an open outlet behind x re-emits g*_j(x) into x
+        if (seg_tile && ((lc >> (OPP[j] - 1)) & 1)) {
+          int sx = x - EX[j], sy = y - EY[j];
+          bool inside = true;
+          if (sx < 0 || sx >= L.nx) {
+            if (L.periodic_x) sx = (sx + L.nx) % L.nx; else inside = false;
+          }
+          if (sy < 0 || sy >= L.ny) {
+            if (L.periodic_y) sy = (sy + L.ny) % L.ny; else inside = false;
+          }
+          const int code = inside ? (int)((const GG_GLOBAL uint8_t *)L.mask)[L.node0 + sy * L.pitch + sx]
+                                  : GG_MASK_WALL;
+          const int s = code - GG_FIRST_SEGMENT;
+          if (code >= GG_FIRST_SEGMENT && ((ph.open >> s) & 1u) && L.seg_kind[s] == GG_SEG_OUTLET)
+            ls[j] += lx[j];
+        }
+      }
+    }
+    // transposed collision with the taped state of step t
+    T g[5];
+    for (int i = 0; i < 5; ++i) g[i] = *at<T>(tape, L.plane, i, node);
+    const T ux = *at<T>(tape, L.plane, 5, node), uy = *at<T>(tape, L.plane, 6, node);
+    const T C = g[0] + g[1] + g[2] + g[3] + g[4];
+    const T om = (T)L.omega_g, kd = (T)L.k_decay, ics = (T)L.inv_cs2g;
+    T s = T(0), dr = T(0), dwl = T(0);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const T Wj = wg[j] * (T(1) + ((T)EX[j] * ux + (T)EY[j] * uy) * ics);
+      s += (om * Wj - kd * wg[j]) * ls[j];
+      dr += wg[j] * ls[j];
+      dwl -= ls[j] * (g[j] - Wj * C);
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) *atw<T>(lam_out, L.plane, i, node) = (T(1) - om) * ls[i] + s;
+    dw = (double)dwl;
+    if (dR) {
+      const int px = x - rx0, py = y - ry0;
+      if (px >= 0 && px < rw && py >= 0 && py < rh) dR[py * rw + px] += (double)dr;
+    }
+  }
+
+  if (seg_tile) {
+    // inlet-concentration gradients: one atomic per segment and wavefront
+#pragma unroll
+    for (int slot = 0; slot < 2; ++slot) {
+      const int seg = slot ? sb : sa;
+      const double v = slot ? mb : ma;
+      unsigned long long pend = __ballot(seg >= 0);
+      while (pend) {
+        const int lead = __ffsll(pend) - 1;
+        const int sg = __shfl(seg, lead);
+        const bool mine = seg == sg;
+        const double a = wsum(mine ? v : 0.0);
+        if ((int)__lane_id() == lead) atomicAdd(dcin + sg, a);
+        pend &= ~__ballot(mine);
+      }
+    }
+  }
+  const double bs = block_sum<256>(dw, lds);
+  if (threadIdx.x == 0) partial[tile] += bs;
+}
+
+}  // namespace
+
+hipError_t launch_tape(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
+                       int tx_shift, void *tape, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (s) {
+    case GG_F64: k_tape<double><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, tape); break;
+    case GG_F32: k_tape<float><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, tape); break;
+    case GG_F16_SHIFTED: k_tape<__half><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, tape); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_seed(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
+                       int tx_shift, const double *weight, const double *target, void *lam,
+                       double *partial, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (s) {
+    case GG_F64: k_seed<double><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, weight, target, lam, partial); break;
+    case GG_F32: k_seed<float><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, weight, target, lam, partial); break;
+    case GG_F16_SHIFTED: k_seed<__half><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, weight, target, lam, partial); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
+                          int tx_shift, int64_t t, const void *lam_in, void *lam_out,
+                          const void *tape, double *dR, const int32_t box[4], double *dcin,
+                          double *partial, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (s == GG_F64)
+    k_adjoint<double><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, t, lam_in, lam_out, tape,
+                                              dR, box[0], box[1], box[2], box[3], dcin, partial);
+  else
+    k_adjoint<float><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, t, lam_in, lam_out, tape,
+                                             dR, box[0], box[1], box[2], box[3], dcin, partial);
+  return hipGetLastError();
+}
+
+}  // namespace gg

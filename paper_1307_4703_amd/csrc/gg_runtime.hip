@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "gg_adjoint.h"
 #include "gg_device.h"
 #include "gg_kernels.h"
 #include "gg_runtime.h"
@@ -693,6 +694,136 @@ gg_status gg_info(const gg_lattice *L, int64_t *n_fluid, int64_t *n_tiles, int64
   if (n_fluid) *n_fluid = L->n_fluid;
   if (n_tiles) *n_tiles = L->n_tiles;
   if (t) *t = L->t;
+  return GG_OK;
+}
+
+// Device buffers of one adjoint run, freed on every exit path.
+struct AdjointBuffers {
+  std::vector<void *> ptrs;
+  ~AdjointBuffers() {
+    for (void *p : ptrs)
+      if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(void **p, size_t bytes) {
+    *p = nullptr;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) ptrs.push_back(*p);
+    return e;
+  }
+};
+
+gg_status gg_adjoint(gg_lattice *L, int64_t n, int64_t s, const double *weight,
+                     const double *target, const int32_t *r_box, double *d_R, gg_grads *out) {
+  if (!L || !weight || !target || !out) return fail(GG_ERR_ARG, "NULL argument");
+  if (n < 1) return fail(GG_ERR_ARG, "n_steps must be positive");
+  if (s < 0) return fail(GG_ERR_ARG, "ckpt_every must be non-negative");
+  int32_t box[4] = {0, 0, 0, 0};
+  if (r_box) {
+    for (int k = 0; k < 4; ++k) box[k] = r_box[k];
+    if (box[0] < 0 || box[1] < 0 || box[2] < 1 || box[3] < 1 || box[0] + box[2] > L->nx ||
+        box[1] + box[3] > L->ny)
+      return fail(GG_ERR_ARG, "r_box must lie inside the lattice");
+    if (!d_R) return fail(GG_ERR_ARG, "d_R is NULL while r_box is given");
+  }
+  gg_status st = check_segments(L);
+  if (st != GG_OK) return st;
+  if (s == 0) s = (int64_t)std::ceil(std::sqrt((double)n));
+  s = std::min<int64_t>(s, n);
+  const int64_t K = (n + s - 1) / s;
+  const size_t pop_bytes = (size_t)NPOP * L->plane * L->esize;
+  const size_t tsz = L->storage == GG_F64 ? 8 : 4;
+  const size_t slot = (size_t)7 * L->plane * tsz;
+  const size_t lam_bytes = (size_t)5 * L->plane * tsz;
+  const size_t nxy = (size_t)L->nx * L->ny;
+  const int na = std::max(L->n_aux_tiles, 1);
+
+  AdjointBuffers B;
+  void *ckpt, *scr_pop, *scr_desc, *scr_t, *scr_flux, *tape, *lam0, *lam1, *wdev, *tdev, *dRdev,
+      *dcin, *pw, *pl;
+  const size_t need = (size_t)K * pop_bytes + pop_bytes + (size_t)s * slot + 2 * lam_bytes;
+  if (B.alloc(&ckpt, (size_t)K * pop_bytes) != hipSuccess || B.alloc(&scr_pop, pop_bytes) != hipSuccess ||
+      B.alloc(&scr_desc, sizeof(LatDesc)) != hipSuccess || B.alloc(&scr_t, sizeof(int64_t)) != hipSuccess ||
+      B.alloc(&scr_flux, 2 * GG_MAX_SEGMENTS * sizeof(double)) != hipSuccess ||
+      B.alloc(&tape, (size_t)s * slot) != hipSuccess || B.alloc(&lam0, lam_bytes) != hipSuccess ||
+      B.alloc(&lam1, lam_bytes) != hipSuccess || B.alloc(&wdev, nxy * sizeof(double)) != hipSuccess ||
+      B.alloc(&tdev, nxy * sizeof(double)) != hipSuccess ||
+      B.alloc(&dRdev, std::max<size_t>(1, (size_t)box[2] * box[3]) * sizeof(double)) != hipSuccess ||
+      B.alloc(&dcin, GG_MAX_SEGMENTS * sizeof(double)) != hipSuccess ||
+      B.alloc(&pw, na * sizeof(double)) != hipSuccess || B.alloc(&pl, na * sizeof(double)) != hipSuccess)
+    return fail(GG_ERR_OOM, "adjoint needs about " + std::to_string(need >> 20) +
+                                " MiB of device memory (checkpoints, tape, adjoint fields)");
+  GG_HIP(hipMemset(lam0, 0, lam_bytes));
+  GG_HIP(hipMemset(lam1, 0, lam_bytes));
+  GG_HIP(hipMemset(dRdev, 0, std::max<size_t>(1, (size_t)box[2] * box[3]) * sizeof(double)));
+  GG_HIP(hipMemset(dcin, 0, GG_MAX_SEGMENTS * sizeof(double)));
+  GG_HIP(hipMemset(pw, 0, na * sizeof(double)));
+  GG_HIP(hipMemset(pl, 0, na * sizeof(double)));
+  GG_HIP(hipMemset(scr_flux, 0, 2 * GG_MAX_SEGMENTS * sizeof(double)));
+  GG_HIP(hipMemcpy(wdev, weight, nxy * sizeof(double), hipMemcpyHostToDevice));
+  GG_HIP(hipMemcpy(tdev, target, nxy * sizeof(double), hipMemcpyHostToDevice));
+
+  // forward pass with checkpoints
+  const int64_t t0 = L->t;
+  for (int64_t k = 0; k < K; ++k) {
+    GG_HIP(hipMemcpyAsync((char *)ckpt + (size_t)k * pop_bytes, L->d_pop, pop_bytes,
+                          hipMemcpyDeviceToDevice, L->stream));
+    st = gg_step(L, std::min<int64_t>(s, n - k * s));
+    if (st != GG_OK) return st;
+  }
+  GG_HIP(launch_seed(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6, (const double *)wdev,
+                     (const double *)tdev, lam0, (double *)pl, L->stream));
+
+  // recomputation copy of the lattice: its own state, counter and fluxes
+  LatDesc hs = L->h;
+  hs.pop = scr_pop;
+  hs.t = (int64_t *)scr_t;
+  hs.flux = (double *)scr_flux;
+  GG_HIP(hipMemcpy(scr_desc, &hs, sizeof(hs), hipMemcpyHostToDevice));
+  const LatDesc *sd = (const LatDesc *)scr_desc;
+  const int block = L->tile_x * L->tile_y;
+  const int txs = ilog2(L->tile_x);
+  void *lam[2] = {lam0, lam1};
+  int cur = 0;
+  for (int64_t k = K - 1; k >= 0; --k) {
+    const int64_t tk = t0 + k * s;
+    const int64_t nk = std::min<int64_t>(s, n - k * s);
+    GG_HIP(hipMemcpyAsync(scr_pop, (char *)ckpt + (size_t)k * pop_bytes, pop_bytes,
+                          hipMemcpyDeviceToDevice, L->stream));
+    GG_HIP(hipMemcpyAsync(scr_t, &tk, sizeof(tk), hipMemcpyHostToDevice, L->stream));
+    GG_HIP(hipStreamSynchronize(L->stream));  // tk lives on the host stack
+    for (int64_t j = 0; j < nk; ++j) {
+      GG_HIP(launch_tape(L->storage, sd, L->d_aux_tiles, L->n_aux_tiles, 6, (char *)tape + (size_t)j * slot,
+                         L->stream));
+      GG_HIP(launch_step(L->storage, block, ((tk + j) & 1) != 0, sd, L->d_tiles, L->n_tiles, txs, 0,
+                         L->stream));
+      GG_HIP(launch_advance(sd, 1, 1, L->stream));
+    }
+    for (int64_t j = nk - 1; j >= 0; --j) {
+      GG_HIP(launch_adjoint(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6, tk + j, lam[cur],
+                            lam[1 - cur], (const char *)tape + (size_t)j * slot,
+                            r_box ? (double *)dRdev : nullptr, box, (double *)dcin, (double *)pw,
+                            L->stream));
+      cur = 1 - cur;
+    }
+  }
+  GG_HIP(hipStreamSynchronize(L->stream));
+  std::vector<double> hpw(na), hpl(na);
+  GG_HIP(hipMemcpy(hpw.data(), pw, na * sizeof(double), hipMemcpyDeviceToHost));
+  GG_HIP(hipMemcpy(hpl.data(), pl, na * sizeof(double), hipMemcpyDeviceToHost));
+  double dom = 0.0, loss = 0.0;
+  for (int k = 0; k < na; ++k) {
+    dom += hpw[k];
+    loss += hpl[k];
+  }
+  std::memset(out, 0, sizeof(*out));
+  out->loss = loss;
+  GG_HIP(hipMemcpy(out->d_c_in, dcin, GG_MAX_SEGMENTS * sizeof(double), hipMemcpyDeviceToHost));
+  out->d_omega_g = dom;
+  out->d_D = dom * (-1.0 / (L->tau_g * L->tau_g * L->cs2g));
+  out->ckpt_every = s;
+  out->n_checkpoints = K;
+  if (r_box)
+    GG_HIP(hipMemcpy(d_R, dRdev, (size_t)box[2] * box[3] * sizeof(double), hipMemcpyDeviceToHost));
   return GG_OK;
 }
 

@@ -139,6 +139,24 @@ class Lattice:
     def sync(self) -> None:
         A.call("gg_sync", self._h)
 
+    def adjoint(self, n_steps: int, weight: np.ndarray, target: np.ndarray,
+                r_box: Optional[Sequence[int]] = None, ckpt_every: int = 0) -> dict:
+        """Advance n_steps and return L = 1/2 sum weight (C - target)^2 with
+        its gradients (include/gg.h, gg_adjoint)."""
+        w = np.ascontiguousarray(weight, np.float64).reshape(self.ny, self.nx)
+        t = np.ascontiguousarray(target, np.float64).reshape(self.ny, self.nx)
+        out = A.gg_grads()
+        box = None
+        dR = None
+        if r_box is not None:
+            box = (ctypes.c_int32 * 4)(*[int(v) for v in r_box])
+            dR = np.zeros((int(r_box[3]), int(r_box[2])))
+        A.call("gg_adjoint", self._h, int(n_steps), int(ckpt_every), _dptr(w), _dptr(t),
+               box, None if dR is None else _dptr(dR), ctypes.byref(out))
+        return {"loss": out.loss, "d_c_in": np.array(out.d_c_in[:]), "d_D": out.d_D,
+                "d_omega_g": out.d_omega_g, "d_R": dR, "ckpt_every": out.ckpt_every,
+                "n_checkpoints": out.n_checkpoints}
+
     # ------------------------------------------------------------------
     def read(self) -> Tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
         """(rho, ux, uy, C) on the host, shape (ny, nx), NaN off the fluid."""

@@ -329,3 +329,31 @@ def random_mask(nx: int, ny: int, seed: int, *, wall_frac: float = 0.15,
             nb += pad[1 + dy: 1 + dy + ny, 1 + dx: 1 + dx + nx]
     mask[fl & (nb == 0)] = WALL
     return mask
+
+
+# ---------------------------------------------------------------------------
+# Chamber misfit (inverse problem on the gradient generator)
+# ---------------------------------------------------------------------------
+
+def chamber_misfit_setup(wl: Workload):
+    """Loss window, linear target ramp and source patch for a gradient
+    generator: the window is the two pre-chambers and the chamber; the target
+    falls linearly from 1 at the source-channel wall to 0 at the sink-channel
+    wall; the source patch is a 64 x 64 box (scaled with the lattice) at the
+    mouth of the left pre-chamber. Returns (weight, target, r_box)."""
+    lay = wl.layout  # type: ignore[attr-defined]
+    weight = np.zeros(wl.mask.shape)
+    for (a, b, c, d) in (lay.left_prechamber, lay.chamber, lay.right_prechamber):
+        weight[c:d, a:b] = 1.0
+    weight[wl.mask != FLUID] = 0.0
+    x = np.arange(wl.nx, dtype=np.float64)
+    x_src = lay.left_channel[1]
+    x_snk = lay.right_channel[0]
+    ramp = np.clip(1.0 - (x - x_src) / float(x_snk - x_src), 0.0, 1.0)
+    target = np.broadcast_to(ramp[None, :], wl.mask.shape).copy()
+    s = wl.nx / 2048.0
+    side = max(2, int(round(64 * s)))
+    a, b, c, d = lay.left_prechamber
+    yc = (c + d) // 2
+    r_box = (a, max(c, yc - side // 2), min(side, b - a), min(side, d - c))
+    return weight, target, r_box

@@ -1,0 +1,162 @@
+"""GPU adjoint (gg_adjoint) against the FP64 oracle's discrete adjoint and
+against central finite differences of the FP64 forward path."""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_1307_4703_amd import Lattice, workloads as W
+from tests.parity_util import log, seeded_init
+
+pytestmark = pytest.mark.gpu
+
+
+def _small(storage="f64", half_period=15):
+    wl = W.gradient_generator(nx=160, ny=80, half_period=half_period, storage=storage)
+    return wl
+
+
+def _problem(wl, seed=4):
+    rng = np.random.default_rng(seed)
+    weight = np.where(wl.mask == 0, rng.random(wl.mask.shape), 0.0)
+    target = rng.random(wl.mask.shape)
+    return weight, target
+
+
+def _gpu_adjoint(wl, storage, init, steps, weight, target, r_box, ckpt=0, R=None):
+    lat = Lattice.from_workload(wl, storage=storage, init=False)
+    lat.init(**init)
+    if R is not None:
+        lat.set_source(R)
+    res = lat.adjoint(steps, weight, target, r_box=r_box, ckpt_every=ckpt)
+    return lat, res
+
+
+def _oracle_adjoint(wl, init, steps, weight, target, R=None):
+    o = Oracle(wl.mask, tau_f=wl.tau_f, D=wl.D, w0=wl.w0, k_decay=wl.k_decay,
+               segments=wl.segments, schedule=wl.schedule, R=R)
+    o.init(**init)
+    return o.adjoint(steps, weight, target)
+
+
+@pytest.mark.parametrize("ckpt", [0, 1, 7, 60])
+def test_f64_adjoint_matches_oracle(ckpt):
+    wl = _small()
+    wl.k_decay = 2e-3
+    init = seeded_init(wl, 3)
+    weight, target = _problem(wl)
+    steps = 60
+    R = np.zeros(wl.mask.shape)
+    fl = np.argwhere(wl.mask == 0)
+    y0, x0 = fl[len(fl) // 2]
+    R[y0:y0 + 3, x0:x0 + 4] = 1e-3
+    r_box = (int(x0) - 5, int(y0) - 4, 16, 12)
+    log(f"f64 adjoint ckpt={ckpt}")
+    lat, g = _gpu_adjoint(wl, "f64", init, steps, weight, target, r_box, ckpt, R=R)
+    loss, dcin, dD, dR = _oracle_adjoint(wl, init, steps, weight, target, R=R)
+    log(f"loss gpu {g['loss']!r} oracle {loss!r}; dD {g['d_D']!r} {dD!r}")
+    assert g["loss"] == pytest.approx(loss, rel=1e-12)
+    for sid in (2, 4):
+        assert g["d_c_in"][sid - 2] == pytest.approx(dcin[sid], rel=1e-10, abs=1e-14)
+    assert g["d_D"] == pytest.approx(dD, rel=1e-10)
+    ref = dR[r_box[1]:r_box[1] + r_box[3], r_box[0]:r_box[0] + r_box[2]]
+    assert np.max(np.abs(g["d_R"] - ref)) <= 1e-10 * np.max(np.abs(ref))
+    assert lat.info()["t"] == steps
+    if ckpt == 7:
+        assert g["n_checkpoints"] == 9 and g["ckpt_every"] == 7
+
+
+def test_adjoint_leaves_the_same_final_state_as_stepping():
+    wl = _small(storage="f32")
+    init = seeded_init(wl, 5)
+    weight, target = _problem(wl)
+    a, _ = _gpu_adjoint(wl, "f32", init, 37, weight, target, None, 5)
+    b = Lattice.from_workload(wl, storage="f32", init=False)
+    b.init(**init)
+    b.step(37)
+    fa, ga = a.populations()
+    fb, gb = b.populations()
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+
+
+def test_f32_adjoint_against_f64_oracle():
+    wl = _small(storage="f32")
+    init = seeded_init(wl, 6)
+    weight, target = _problem(wl)
+    steps = 80
+    log("f32 adjoint vs oracle")
+    lat, g = _gpu_adjoint(wl, "f32", init, steps, weight, target, None)
+    loss, dcin, dD, dR = _oracle_adjoint(wl, init, steps, weight, target)
+    log(f"f32: dcin {g['d_c_in'][0]!r} vs {dcin[2]!r}, dD {g['d_D']!r} vs {dD!r}")
+    assert g["loss"] == pytest.approx(loss, rel=1e-4)
+    assert g["d_c_in"][0] == pytest.approx(dcin[2], rel=1e-3)
+    assert g["d_c_in"][2] == pytest.approx(dcin[4], rel=1e-3, abs=1e-6 * abs(dcin[2]))
+    assert g["d_D"] == pytest.approx(dD, rel=1e-3)
+
+
+def _loss_f64(wl, steps, weight, target, c_src=1.0, c_snk=0.0, D=None, R=None):
+    from paper_1307_4703_amd.autograd import _with_parameters
+    wl2 = _with_parameters(wl, np.array([c_src, c_snk]), wl.D if D is None else D)
+    lat = Lattice.from_workload(wl2, storage="f64")
+    if R is not None:
+        lat.set_source(R)
+    lat.step(steps)
+    rho, ux, uy, C = lat.read()
+    fl = wl.mask == 0
+    lat.close()
+    return 0.5 * float(np.sum(np.where(fl, weight * (C - target) ** 2, 0.0)))
+
+
+def test_full_size_adjoint_against_central_differences():
+    """Gradient generator 2048x1024, FP32 forward and adjoint over 20000
+    steps with sqrt(N) checkpoints; gradients with respect to the source and
+    sink inlet concentrations, D and source values on the 64x64 patch agree
+    with central differences (h = 1e-4) of the FP64 forward path to 1e-3."""
+    wl = W.gradient_generator(storage="f32")
+    weight, target, r_box = W.chamber_misfit_setup(wl)
+    steps = 20000
+    log("full-size FP32 adjoint, 20000 steps")
+    lat = Lattice.from_workload(wl, storage="f32")
+    g = lat.adjoint(steps, weight, target, r_box=r_box)
+    lat.close()
+    log(f"loss {g['loss']!r} d_c_in {g['d_c_in'][:4]!r} d_D {g['d_D']!r} ckpt {g['ckpt_every']}")
+    h = 1e-4
+    fd_src = (_loss_f64(wl, steps, weight, target, c_src=1 + h) -
+              _loss_f64(wl, steps, weight, target, c_src=1 - h)) / (2 * h)
+    fd_snk = (_loss_f64(wl, steps, weight, target, c_snk=h) -
+              _loss_f64(wl, steps, weight, target, c_snk=-h)) / (2 * h)
+    fd_D = (_loss_f64(wl, steps, weight, target, D=wl.D + h) -
+            _loss_f64(wl, steps, weight, target, D=wl.D - h)) / (2 * h)
+    log(f"FD: src {fd_src!r} snk {fd_snk!r} D {fd_D!r}")
+    assert g["d_c_in"][0] == pytest.approx(fd_src, rel=1e-3)
+    assert g["d_c_in"][2] == pytest.approx(fd_snk, rel=1e-3)
+    assert g["d_D"] == pytest.approx(fd_D, rel=1e-3)
+    x0, y0, w, hh = r_box
+    for (py, px) in ((0, 0), (hh // 2, w // 2), (hh - 1, w - 1), (3, w // 3)):
+        R = np.zeros(wl.mask.shape)
+        R[y0 + py, x0 + px] = h
+        lp = _loss_f64(wl, steps, weight, target, R=R)
+        R[y0 + py, x0 + px] = -h
+        lm = _loss_f64(wl, steps, weight, target, R=R)
+        fd = (lp - lm) / (2 * h)
+        log(f"R[{py},{px}] adjoint {g['d_R'][py, px]!r} FD {fd!r}")
+        assert g["d_R"][py, px] == pytest.approx(fd, rel=1e-3)
+
+
+def test_torch_autograd_function():
+    import torch
+    from paper_1307_4703_amd.autograd import chamber_misfit
+    wl = _small(storage="f64")
+    weight, target = _problem(wl)
+    r_box = (30, 30, 8, 8)
+    c = torch.tensor([1.0, 0.0], dtype=torch.float64, requires_grad=True)
+    D = torch.tensor(wl.D, dtype=torch.float64, requires_grad=True)
+    R = torch.zeros((8, 8), dtype=torch.float64, requires_grad=True)
+    loss = chamber_misfit(c, D, R, wl, 50, weight, target, r_box, storage="f64")
+    (3.0 * loss).backward()
+    o = Oracle(wl.mask, tau_f=wl.tau_f, D=wl.D, w0=wl.w0, segments=wl.segments,
+               schedule=wl.schedule)
+    l2, dcin, dD, dR = o.adjoint(50, weight, target)
+    assert float(loss) == pytest.approx(l2, rel=1e-12)
+    assert float(c.grad[0]) == pytest.approx(3.0 * dcin[2], rel=1e-9)
+    assert float(D.grad) == pytest.approx(3.0 * dD, rel=1e-9)
+    np.testing.assert_allclose(R.grad.numpy(), 3.0 * dR[30:38, 30:38], rtol=1e-9, atol=1e-15)
