@@ -129,6 +129,51 @@ def copy_bandwidth(nbytes=2 << 30, reps=20):
     return 2.0 * nbytes / (ms.value * 1e-3) / 1e9
 
 
+def batch_bench(steps=2000, seq_steps=400, n=64, seed=4703, tune_steps=16):
+    """64 seeded gradient generators of uneven size (FP32): aggregate
+    fluid-node updates per second of one batched, graph-captured launch per
+    step (launch shape from the autotuner) against stepping the instances
+    one after the other with the same kernels."""
+    import torch
+    from paper_1307_4703_amd import Batch, Lattice, tune, workloads as W
+    wls = W.batch_instances(n, seed)
+    log(f"batch: creating {n} lattices")
+    lats = [Lattice.from_workload(wl, storage="f32") for wl in wls]
+    nf = sum(l.info()["n_fluid"] for l in lats)
+    best = tune.tune_batch(lats, steps=tune_steps, use_cache=False)
+    log(f"batch: tuned tile {best['tile']} persist {best['persist']}")
+    b = Batch(lats, tile=tuple(best["tile"]), persist=best["persist"], graph_chunk=64)
+    b.step(64)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    b.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_b = e0.elapsed_time(e1) * 1e-3
+    b.close()
+    for lat in lats:
+        lat.set_launch(best["tile"][0], best["tile"][1], 64)
+        lat.step(64)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for lat in lats:
+        lat.step(seq_steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_s = e0.elapsed_time(e1) * 1e-3
+    for lat in lats:
+        lat.close()
+    mb = nf * steps / t_b / 1e6
+    ms = nf * seq_steps / t_s / 1e6
+    return {"n_instances": n, "seed": seed, "n_fluid_total": nf, "tile": best["tile"],
+            "persist": best["persist"], "steps": steps, "ms_per_step": round(t_b / steps * 1e3, 5),
+            "batched_mlups": round(mb, 1), "sequential_mlups": round(ms, 1),
+            "speedup": round(mb / ms, 3),
+            "achieved_gbs": round(nf * bytes_per_update("f32") * steps / t_b / 1e9, 1)}
+
+
 def cpu_baseline(name, budget_s=15.0):
     """The FP64 oracle, as it stands, on the host cores: a bounded number of
     steps of the same workload from its initial state."""
@@ -221,6 +266,7 @@ def main():
             e["storage"] = r2["wl"].storage
             extra[name] = e
         out["roofline_other_lattices"] = extra
+        out["batched_64_instances"] = batch_bench()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

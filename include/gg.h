@@ -199,6 +199,24 @@ gg_status gg_set_launch(gg_lattice *lat, int32_t tile_x, int32_t tile_y,
 gg_status gg_info(const gg_lattice *lat, int64_t *n_fluid, int64_t *n_tiles,
                   int64_t *t);
 
+/* Batched launch: many lattices advanced together, one flat launch over
+ * the concatenated tile lists of all of them per step (two when the
+ * lattices sit at steps of different parity), graph-captured in chunks of
+ * graph_chunk steps (0: plain launches). All lattices must share the
+ * storage type and the HIP stream; the batch copies their configuration
+ * (parameters, segments, schedules) at creation, so later changes to a
+ * member need a new batch. The members' states advance in place: after
+ * gg_batch_step(b, n) every member is n steps further, exactly as after
+ * gg_step(member, n). tile_x, tile_y as in gg_set_launch (0, 0: 64 x 4);
+ * persist > 0 caps the grid at that many work-groups, which then loop over
+ * the tiles (a persistent launch); 0 launches one work-group per tile. */
+gg_status gg_batch_create(gg_lattice *const *lats, int32_t n, int32_t tile_x,
+                          int32_t tile_y, int32_t persist, int32_t graph_chunk,
+                          gg_batch **out);
+gg_status gg_batch_step(gg_batch *batch, int64_t n);
+gg_status gg_batch_info(const gg_batch *batch, int64_t *n_tiles, int64_t *n_fluid);
+void gg_batch_destroy(gg_batch *batch);
+
 /* Gradients returned by gg_adjoint. */
 typedef struct gg_grads {
   double loss;                      /* 1/2 sum_x weight(x) (C(x) - target(x))^2 */

@@ -4,7 +4,7 @@ after Tanaka & Iber, arXiv:1307.4703.
 The compute path is the HIP library libgg.so (C ABI in include/gg.h); this
 package binds it (``Lattice``) and provides the seeded synthetic workloads.
 """
-from .lattice import Lattice, make_phases  # noqa: F401
+from .lattice import Batch, Lattice, make_phases  # noqa: F401
 from . import workloads  # noqa: F401
 
-__all__ = ["Lattice", "make_phases", "workloads"]
+__all__ = ["Batch", "Lattice", "make_phases", "workloads"]

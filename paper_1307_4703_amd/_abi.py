@@ -91,6 +91,9 @@ SIGS = {
     "gg_sync": [P],
     "gg_step_timed": [P, I64, ctypes.POINTER(D), ctypes.POINTER(D)],
     "gg_adjoint": [P, I64, I64, P, P, P, P, ctypes.POINTER(gg_grads)],
+    "gg_batch_create": [ctypes.POINTER(P), I32, I32, I32, I32, I32, ctypes.POINTER(P)],
+    "gg_batch_step": [P, I64],
+    "gg_batch_info": [P, ctypes.POINTER(I64), ctypes.POINTER(I64)],
     "gg_stream_copy": [P, P, ctypes.c_size_t, I32, P, ctypes.POINTER(D)],
 }
 
@@ -109,6 +112,8 @@ def lib() -> ctypes.CDLL:
             fn.restype = ctypes.c_int
         L.gg_destroy.argtypes = [P]
         L.gg_destroy.restype = None
+        L.gg_batch_destroy.argtypes = [P]
+        L.gg_batch_destroy.restype = None
         L.gg_last_error.argtypes = []
         L.gg_last_error.restype = ctypes.c_char_p
         _LIB = L

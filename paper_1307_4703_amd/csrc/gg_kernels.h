@@ -7,9 +7,11 @@ namespace gg {
 
 // Fused coupled step over a tile list; block = threads per work-group
 // (64, 128, 256 or 512), tile width 1 << tx_shift, odd = parity of the
-// step, dt added to the device step counter of each lattice.
+// step, dt added to the device step counter of each lattice. persist > 0
+// caps the grid at that many work-groups (rounded up to a multiple of 8),
+// which then stride through the tiles.
 hipError_t launch_step(gg_storage s, int block, bool odd, const LatDesc *d, const Tile *tiles,
-                       int n_tiles, int tx_shift, int dt, hipStream_t st);
+                       int n_tiles, int tx_shift, int dt, hipStream_t st, int persist = 0);
 
 // Auxiliary kernels: 256-thread work-groups over one lattice's tiles.
 hipError_t launch_init(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,

@@ -164,17 +164,14 @@ __device__ __forceinline__ void shifts(CDesc &L, T *shf, T *shg) {
 #else
 #define GG_STEP_ATTR
 #endif
-template <class S, int BS, bool ODD>
-__global__ void __launch_bounds__(BS) GG_STEP_ATTR
-    k_step(const LatDesc *__restrict__ descs, const Tile *__restrict__ tiles,
-           int n_tiles, int per_xcd, int tx_shift, int dt) {
+// One tile of the fused step (every lane of the work-group calls it).
+template <class S, bool ODD>
+__device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
+                                          const Tile *__restrict__ tiles, int tile,
+                                          int tx_shift, int dt) {
   using P = Pop<S>;
   using T = typename P::T;
-  // Work-groups are dealt to the 8 XCDs round-robin; give each XCD a
-  // contiguous run of tiles so neighbouring tiles share an L2.
   using W = typename P::W;
-  const int tile = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
-  if (tile >= n_tiles) return;
   const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
   CDesc &L = ((CDesc *)descs)[tl.inst];
   const int tmask = (1 << tx_shift) - 1;
@@ -323,6 +320,22 @@ __global__ void __launch_bounds__(BS) GG_STEP_ATTR
   }
 
   if (seg_tile) flush_flux((double *)L.flux, sa, ma, ca, sb, mb, cb);
+}
+
+// The fused step over a tile list. Work-groups are dealt to the 8 XCDs
+// round-robin; block b handles tile (b mod 8) * per_xcd + b / 8, so each XCD
+// processes a contiguous run of tiles (neighbouring tiles share an L2). With
+// a grid smaller than 8 * per_xcd (a multiple of 8), blocks stride through
+// the list and stay on their XCD's run (persistent launch).
+template <class S, int BS, bool ODD>
+__global__ void __launch_bounds__(BS) GG_STEP_ATTR
+    k_step(const LatDesc *__restrict__ descs, const Tile *__restrict__ tiles,
+           int n_tiles, int per_xcd, int tx_shift, int dt) {
+  const int nb = 8 * per_xcd;
+  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int tile = (b & 7) * per_xcd + (b >> 3);
+    if (tile < n_tiles) step_tile<S, ODD>(descs, tiles, tile, tx_shift, dt);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -519,9 +532,10 @@ __global__ void k_advance(const LatDesc *__restrict__ descs, int n, int64_t k) {
 // ---------------------------------------------------------------------------
 template <class S, bool ODD>
 static hipError_t launch_step_p(int bs, const LatDesc *d, const Tile *tiles, int n_tiles,
-                                int tx_shift, int dt, hipStream_t st) {
+                                int tx_shift, int dt, int persist, hipStream_t st) {
   const int per_xcd = (n_tiles + 7) / 8;
-  const dim3 grid(8 * per_xcd);
+  const int full = 8 * per_xcd;
+  const dim3 grid(persist > 0 ? std::min(full, (persist + 7) / 8 * 8) : full);
   switch (bs) {
     case 64: k_step<S, 64, ODD><<<grid, 64, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
     case 128: k_step<S, 128, ODD><<<grid, 128, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
@@ -534,18 +548,18 @@ static hipError_t launch_step_p(int bs, const LatDesc *d, const Tile *tiles, int
 
 template <class S>
 static hipError_t launch_step_s(int bs, bool odd, const LatDesc *d, const Tile *tiles,
-                                int n_tiles, int tx_shift, int dt, hipStream_t st) {
-  return odd ? launch_step_p<S, true>(bs, d, tiles, n_tiles, tx_shift, dt, st)
-             : launch_step_p<S, false>(bs, d, tiles, n_tiles, tx_shift, dt, st);
+                                int n_tiles, int tx_shift, int dt, int persist, hipStream_t st) {
+  return odd ? launch_step_p<S, true>(bs, d, tiles, n_tiles, tx_shift, dt, persist, st)
+             : launch_step_p<S, false>(bs, d, tiles, n_tiles, tx_shift, dt, persist, st);
 }
 
 hipError_t launch_step(gg_storage s, int block, bool odd, const LatDesc *d, const Tile *tiles,
-                       int n_tiles, int tx_shift, int dt, hipStream_t st) {
+                       int n_tiles, int tx_shift, int dt, hipStream_t st, int persist) {
   if (n_tiles <= 0) return hipSuccess;
   switch (s) {
-    case GG_F64: return launch_step_s<double>(block, odd, d, tiles, n_tiles, tx_shift, dt, st);
-    case GG_F32: return launch_step_s<float>(block, odd, d, tiles, n_tiles, tx_shift, dt, st);
-    case GG_F16_SHIFTED: return launch_step_s<__half>(block, odd, d, tiles, n_tiles, tx_shift, dt, st);
+    case GG_F64: return launch_step_s<double>(block, odd, d, tiles, n_tiles, tx_shift, dt, persist, st);
+    case GG_F32: return launch_step_s<float>(block, odd, d, tiles, n_tiles, tx_shift, dt, persist, st);
+    case GG_F16_SHIFTED: return launch_step_s<__half>(block, odd, d, tiles, n_tiles, tx_shift, dt, persist, st);
   }
   return hipErrorInvalidValue;
 }

@@ -827,6 +827,165 @@ gg_status gg_adjoint(gg_lattice *L, int64_t n, int64_t s, const double *weight,
   return GG_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batched launch
+// ---------------------------------------------------------------------------
+
+struct gg_batch {
+  std::vector<gg_lattice *> lats;
+  gg_storage storage = GG_F32;
+  hipStream_t stream = nullptr, cap_stream = nullptr;
+  LatDesc *d_descs = nullptr;
+  Tile *d_tiles[2] = {nullptr, nullptr};  // lattices at even / odd t at creation
+  int n_tiles[2] = {0, 0};
+  int tile_x = 64, tile_y = 4, persist = 0, chunk = 0;
+  int64_t steps = 0;  // steps taken by the batch
+  int64_t n_fluid = 0;
+  std::vector<int64_t> t_created;  // member times when the batch was made
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+};
+
+static void batch_free(gg_batch *B) {
+  if (B->graph_exec) (void)hipGraphExecDestroy(B->graph_exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  if (B->d_descs) (void)hipFree(B->d_descs);
+  for (int g = 0; g < 2; ++g)
+    if (B->d_tiles[g]) (void)hipFree(B->d_tiles[g]);
+  if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+  delete B;
+}
+
+// n steps of the batch on `st` (group parity from the batch's step count)
+static hipError_t batch_launch(gg_batch *B, int64_t s0, int64_t n, hipStream_t st) {
+  const int block = B->tile_x * B->tile_y;
+  const int txs = ilog2(B->tile_x);
+  hipError_t e = hipSuccess;
+  for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt)
+    for (int g = 0; g < 2 && e == hipSuccess; ++g)
+      if (B->n_tiles[g] > 0)
+        e = launch_step(B->storage, block, ((s0 + dt + g) & 1) != 0, B->d_descs, B->d_tiles[g],
+                        B->n_tiles[g], txs, (int)dt, st, B->persist);
+  if (e == hipSuccess) e = launch_advance(B->d_descs, (int)B->lats.size(), n, st);
+  return e;
+}
+
+gg_status gg_batch_create(gg_lattice *const *lats, int32_t n, int32_t tile_x, int32_t tile_y,
+                          int32_t persist, int32_t graph_chunk, gg_batch **out) {
+  if (!out || !lats || n < 1) return fail(GG_ERR_ARG, "need at least one lattice");
+  *out = nullptr;
+  if (tile_x == 0 && tile_y == 0) {
+    tile_x = 64;
+    tile_y = 4;
+  }
+  const int bs = tile_x * tile_y;
+  if (tile_x < 8 || (tile_x & (tile_x - 1)) || tile_y < 1 ||
+      (bs != 64 && bs != 128 && bs != 256 && bs != 512))
+    return fail(GG_ERR_ARG, "tile_x must be a power of two >= 8 and tile_x*tile_y one of 64, 128, 256, 512");
+  if (persist < 0 || graph_chunk < 0 || graph_chunk > 100000) return fail(GG_ERR_ARG, "bad persist or graph_chunk");
+  for (int k = 0; k < n; ++k) {
+    if (!lats[k]) return fail(GG_ERR_ARG, "NULL lattice in the batch");
+    if (lats[k]->storage != lats[0]->storage) return fail(GG_ERR_ARG, "batch members must share the storage type");
+    if (lats[k]->stream != lats[0]->stream) return fail(GG_ERR_ARG, "batch members must share the HIP stream");
+    for (int j = 0; j < k; ++j)
+      if (lats[j] == lats[k]) return fail(GG_ERR_ARG, "a lattice appears twice in the batch");
+    gg_status st = check_segments(lats[k]);
+    if (st != GG_OK) return st;
+  }
+  gg_batch *B = new gg_batch();
+  B->lats.assign(lats, lats + n);
+  B->storage = lats[0]->storage;
+  B->stream = lats[0]->stream;
+  B->tile_x = tile_x;
+  B->tile_y = tile_y;
+  B->persist = persist;
+  B->chunk = (graph_chunk + 1) / 2 * 2;
+  std::vector<LatDesc> descs(n);
+  std::vector<Tile> tiles[2];
+  for (int k = 0; k < n; ++k) {
+    descs[k] = lats[k]->h;
+    build_tiles(lats[k], tile_x, tile_y, k, tiles[lats[k]->t & 1]);
+    B->n_fluid += lats[k]->n_fluid;
+    B->t_created.push_back(lats[k]->t);
+  }
+  hipError_t e = hipStreamSynchronize(B->stream);
+  if (e == hipSuccess) e = hipMalloc(&B->d_descs, n * sizeof(LatDesc));
+  if (e == hipSuccess) e = hipMemcpy(B->d_descs, descs.data(), n * sizeof(LatDesc), hipMemcpyHostToDevice);
+  for (int g = 0; g < 2 && e == hipSuccess; ++g) {
+    B->n_tiles[g] = (int)tiles[g].size();
+    if (tiles[g].empty()) continue;
+    e = hipMalloc(&B->d_tiles[g], tiles[g].size() * sizeof(Tile));
+    if (e == hipSuccess)
+      e = hipMemcpy(B->d_tiles[g], tiles[g].data(), tiles[g].size() * sizeof(Tile), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    batch_free(B);
+    return fail(GG_ERR_HIP, std::string("batch set-up: ") + hipGetErrorString(e));
+  }
+  *out = B;
+  return GG_OK;
+}
+
+gg_status gg_batch_step(gg_batch *B, int64_t n) {
+  if (!B) return fail(GG_ERR_ARG, "batch is NULL");
+  if (n < 0) return fail(GG_ERR_ARG, "n must be non-negative");
+  // members stepped on their own since the batch was created would no
+  // longer sit in their parity group
+  for (size_t k = 0; k < B->lats.size(); ++k) {
+    const gg_lattice *L = B->lats[k];
+    if (L->t - B->t_created[k] != B->steps)
+      return fail(GG_ERR_STATE, "batch member " + std::to_string(k) +
+                                    " was stepped, loaded or re-initialised outside the batch");
+  }
+  int64_t left = n;
+  const int K = B->chunk;
+  if (K > 0 && (B->steps & 1) && left >= K + 1) {  // replays start on an even batch step
+    GG_HIP(batch_launch(B, B->steps, 1, B->stream));
+    B->steps += 1;
+    left -= 1;
+  }
+  if (K > 0 && !(B->steps & 1) && left >= K) {
+    if (!B->graph_exec) {
+      GG_HIP(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e = batch_launch(B, 0, K, B->cap_stream);
+      hipGraph_t g = nullptr;
+      hipError_t e2 = hipStreamEndCapture(B->cap_stream, &g);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(GG_ERR_HIP, std::string("batch graph capture: ") +
+                                    hipGetErrorString(e != hipSuccess ? e : e2));
+      }
+      B->graph = g;
+      GG_HIP(hipGraphInstantiate(&B->graph_exec, B->graph, nullptr, nullptr, 0));
+    }
+    while (left >= K) {
+      GG_HIP(hipGraphLaunch(B->graph_exec, B->stream));
+      left -= K;
+      B->steps += K;
+    }
+  }
+  if (left > 0) {
+    GG_HIP(batch_launch(B, B->steps, left, B->stream));
+    B->steps += left;
+  }
+  for (gg_lattice *L : B->lats) L->t += n;
+  return GG_OK;
+}
+
+gg_status gg_batch_info(const gg_batch *B, int64_t *n_tiles, int64_t *n_fluid) {
+  if (!B) return fail(GG_ERR_ARG, "batch is NULL");
+  if (n_tiles) *n_tiles = (int64_t)B->n_tiles[0] + B->n_tiles[1];
+  if (n_fluid) *n_fluid = B->n_fluid;
+  return GG_OK;
+}
+
+void gg_batch_destroy(gg_batch *B) {
+  if (!B) return;
+  (void)hipStreamSynchronize(B->stream);
+  batch_free(B);
+}
+
 gg_status gg_step_timed(gg_lattice *L, int64_t n, double *ms_even, double *ms_odd) {
   if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
   if (n < 1) return fail(GG_ERR_ARG, "n must be positive");

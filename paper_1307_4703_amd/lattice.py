@@ -212,3 +212,41 @@ class Lattice:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Several lattices advanced by one flat launch per step (gg_batch_*).
+
+    The lattices keep their own state; after ``step(n)`` each of them is n
+    steps further, exactly as after ``Lattice.step(n)``.
+    """
+
+    def __init__(self, lattices: Sequence[Lattice], tile: Tuple[int, int] = (64, 4),
+                 persist: int = 0, graph_chunk: int = 64):
+        self.lattices = list(lattices)
+        arr = (ctypes.c_void_p * len(self.lattices))(*[l.handle.value for l in self.lattices])
+        h = ctypes.c_void_p()
+        A.call("gg_batch_create", arr, len(self.lattices), int(tile[0]), int(tile[1]),
+               int(persist), int(graph_chunk), ctypes.byref(h))
+        self._h = h
+        self.tile = tuple(tile)
+        self.persist = int(persist)
+
+    def step(self, n: int = 1) -> None:
+        A.call("gg_batch_step", self._h, int(n))
+
+    def info(self) -> dict:
+        nt, nf = ctypes.c_int64(), ctypes.c_int64()
+        A.call("gg_batch_info", self._h, ctypes.byref(nt), ctypes.byref(nf))
+        return {"n_tiles": nt.value, "n_fluid": nf.value}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            A.lib().gg_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

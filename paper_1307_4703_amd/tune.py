@@ -1,0 +1,110 @@
+"""Launch-shape autotuner for single lattices and batches.
+
+Candidates are tile shapes (tile_x x tile_y nodes per work-group) and, for
+batches, persistent grid sizes. Each candidate is timed on the GPU with HIP
+events over a few graph-replayed steps (the lattices advance while being
+tuned, so tune before the run or on a copy). Results are cached in a JSON
+file keyed by the device name, storage type and the lattices' shapes and
+fluid counts.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+from typing import Dict, Iterable, List, Optional, Sequence, Tuple
+
+TILES: Tuple[Tuple[int, int], ...] = ((64, 4), (32, 8), (64, 2), (128, 2), (128, 1),
+                                      (64, 8), (128, 4), (256, 1), (32, 4), (16, 8))
+PERSIST: Tuple[int, ...] = (0, 2048, 4096)
+
+
+def cache_path() -> str:
+    base = os.environ.get("XDG_CACHE_HOME") or os.path.join(os.path.expanduser("~"), ".cache")
+    return os.path.join(base, "paper_1307_4703_amd", "tune.json")
+
+
+def _key(lattices: Sequence, kind: str) -> str:
+    import torch
+    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
+    desc = [(l.nx, l.ny, l.storage, l.info()["n_fluid"]) for l in lattices]
+    h = hashlib.sha256(json.dumps([dev, kind, desc]).encode()).hexdigest()[:20]
+    return f"{kind}:{h}"
+
+
+def _load(path: str) -> Dict:
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path: str, key: str, value) -> None:
+    data = _load(path)
+    data[key] = value
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(data, fh, indent=1)
+    os.replace(tmp, path)
+
+
+def _time(fn, steps: int) -> float:
+    import torch
+    stream = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    fn(2)  # capture graphs, warm caches
+    torch.cuda.synchronize()
+    a.record(stream)
+    fn(steps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def tune_lattice(lat, steps: int = 64, tiles: Iterable[Tuple[int, int]] = TILES,
+                 graph_chunk: int = 64, use_cache: bool = True,
+                 path: Optional[str] = None) -> Dict:
+    """Pick the tile shape with the shortest step time; applies it."""
+    path = path or cache_path()
+    key = _key([lat], "lattice")
+    if use_cache:
+        hit = _load(path).get(key)
+        if hit:
+            lat.set_launch(hit["tile"][0], hit["tile"][1], graph_chunk)
+            return hit
+    results: List[Dict] = []
+    for t in tiles:
+        lat.set_launch(t[0], t[1], graph_chunk)
+        results.append({"tile": list(t), "ms_per_step": _time(lat.step, steps)})
+    best = min(results, key=lambda r: r["ms_per_step"])
+    lat.set_launch(best["tile"][0], best["tile"][1], graph_chunk)
+    out = {"tile": best["tile"], "ms_per_step": best["ms_per_step"], "all": results}
+    _store(path, key, out)
+    return out
+
+
+def tune_batch(lattices: Sequence, steps: int = 32, tiles: Iterable[Tuple[int, int]] = TILES,
+               persist: Iterable[int] = PERSIST, graph_chunk: int = 64,
+               use_cache: bool = True, path: Optional[str] = None) -> Dict:
+    """Pick tile shape and persistent grid size for a batch of lattices."""
+    from .lattice import Batch
+    path = path or cache_path()
+    key = _key(lattices, "batch")
+    if use_cache:
+        hit = _load(path).get(key)
+        if hit:
+            return hit
+    results: List[Dict] = []
+    for t in tiles:
+        for p in persist:
+            b = Batch(lattices, tile=t, persist=p, graph_chunk=graph_chunk)
+            results.append({"tile": list(t), "persist": p, "ms_per_step": _time(b.step, steps)})
+            b.close()
+    best = min(results, key=lambda r: r["ms_per_step"])
+    out = {"tile": best["tile"], "persist": best["persist"], "ms_per_step": best["ms_per_step"],
+           "all": results}
+    _store(path, key, out)
+    return out

@@ -1,0 +1,95 @@
+"""Batched launch: many uneven lattices in one flat launch per step must give
+bitwise the same states as stepping each lattice on its own (same kernels,
+same arithmetic, only the work-group to tile assignment differs)."""
+import numpy as np
+import pytest
+
+from paper_1307_4703_amd import Batch, Lattice, _abi as A, workloads as W
+from tests.parity_util import log, seeded_init
+
+pytestmark = pytest.mark.gpu
+
+
+def _members():
+    wls = [W.gradient_generator(nx=256, ny=128, half_period=9, storage="f32"),
+           W.gradient_generator(nx=384, ny=192, half_period=14, peclet=1500.0, storage="f32",
+                                chamber_width=300),
+           W.gradient_generator(nx=300, ny=150, half_period=5, storage="f32"),
+           W.straight_channel(96, 40, storage="f32")]
+    m = W.random_mask(131, 67, seed=3, periodic=(True, False))
+    wls.append(W.Workload("random", m, tau_f=0.7, D=0.02, periodic=(True, False), storage="f32"))
+    return wls
+
+
+def _make(wls, seed0=0):
+    lats = []
+    for k, wl in enumerate(wls):
+        lat = Lattice.from_workload(wl, init=False)
+        lat.init(**seeded_init(wl, seed0 + k))
+        lats.append(lat)
+    return lats
+
+
+def _states(lats):
+    return [lat.populations() for lat in lats]
+
+
+@pytest.mark.parametrize("tile,persist,chunk", [((64, 4), 0, 8), ((32, 8), 64, 0),
+                                                ((128, 2), 512, 16)])
+def test_batch_equals_individual(tile, persist, chunk):
+    wls = _members()
+    log(f"batch tile {tile} persist {persist} chunk {chunk}")
+    ref = _make(wls)
+    for lat in ref:
+        lat.step(53)
+    lats = _make(wls)
+    b = Batch(lats, tile=tile, persist=persist, graph_chunk=chunk)
+    b.step(20)
+    b.step(33)
+    b.close()
+    for (fa, ga), (fb, gb) in zip(_states(ref), _states(lats)):
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+    for lat in lats:
+        assert lat.info()["t"] == 53
+
+
+def test_batch_members_at_different_parities():
+    wls = _members()
+    ref = _make(wls)
+    lats = _make(wls)
+    for k in (1, 3):
+        ref[k].step(1)
+        lats[k].step(1)
+    for lat in ref:
+        lat.step(17)
+    b = Batch(lats, graph_chunk=4)
+    b.step(17)
+    for (fa, ga), (fb, gb) in zip(_states(ref), _states(lats)):
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+
+
+def test_batch_refuses_members_stepped_outside():
+    wls = _members()[:2]
+    lats = _make(wls)
+    b = Batch(lats)
+    b.step(3)
+    lats[0].step(1)
+    with pytest.raises(A.GGError) as e:
+        b.step(1)
+    assert e.value.status == A.GG_ERR_STATE
+
+
+def test_autotuner_picks_and_caches(tmp_path):
+    from paper_1307_4703_amd import tune
+    wl = W.gradient_generator(nx=512, ny=256, storage="f32")
+    lat = Lattice.from_workload(wl)
+    path = str(tmp_path / "tune.json")
+    res = tune.tune_lattice(lat, steps=16, tiles=((64, 4), (32, 8), (128, 2)), path=path)
+    assert tuple(res["tile"]) in ((64, 4), (32, 8), (128, 2))
+    assert len(res["all"]) == 3
+    again = tune.tune_lattice(lat, steps=16, path=path)
+    assert again["tile"] == res["tile"]
+    wls = _members()[:3]
+    lats = _make(wls)
+    rb = tune.tune_batch(lats, steps=8, tiles=((64, 4), (32, 8)), persist=(0, 256), path=path)
+    assert len(rb["all"]) == 4 and rb["persist"] in (0, 256)
