@@ -199,6 +199,61 @@ def cpu_baseline(name, budget_s=15.0):
             "sample": f"{n} FP64 oracle steps of {wl.name} ({nf} fluid nodes) from rest"}
 
 
+def digest_counters(prof_dir, grids, out_path):
+    """Turn two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch) into HBM bytes per step launch for the workloads named in
+    ``grids`` ({"grid size[/element type]": workload}), scaled by what the same counters read
+    for the plain copy kernel of known size; writes ``out_path`` (JSON)."""
+    import csv
+    from collections import defaultdict
+
+    def per_dispatch(path, counter):
+        acc = defaultdict(list)
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] == counter:
+                    acc[(row["Kernel_Name"], int(row["Grid_Size"]))].append(float(row["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    fetch = per_dispatch(os.path.join(prof_dir, "pmc_fetch", "fetch_counter_collection.csv"),
+                         "FETCH_SIZE")
+    write = per_dispatch(os.path.join(prof_dir, "pmc_write", "write_counter_collection.csv"),
+                         "WRITE_SIZE")
+    copy = [k for k in fetch if "k_copy" in k[0]]
+    if len(copy) != 1:
+        raise SystemExit("expected exactly one copy-kernel grid in the counter runs")
+    ck = copy[0]
+    n_copy = ck[1] * 16  # one 16-byte vector per lane, read and written
+    fs, ws = n_copy / 1024.0 / fetch[ck], n_copy / 1024.0 / write[ck]
+    data = {"kernel_sha": kernel_hash(), "source": os.path.relpath(KERNEL_SRC, ROOT),
+            "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
+            "calibration": {"kernel": "gg::k_copy", "bytes_read": n_copy, "bytes_written": n_copy,
+                            "FETCH_SIZE_KiB": fetch[ck], "WRITE_SIZE_KiB": write[ck]},
+            "workloads": {}}
+    for key, name in grids.items():
+        grid, _, elem = key.partition("/")
+        grid = int(grid)
+        steps = {k: v for k, v in fetch.items() if k[1] == grid and f"k_step<{elem}" in k[0]}
+        if not steps:
+            raise SystemExit(f"no step kernel with grid size {grid} ({name})")
+        par = {}
+        for k in steps:
+            odd = k[0].split(",")[2].strip().startswith("true")
+            par["odd" if odd else "even"] = {"fetch_bytes": round(fetch[k] * 1024 * fs),
+                                             "write_bytes": round(write.get(k, 0.0) * 1024 * ws)}
+        tot = [v["fetch_bytes"] + v["write_bytes"] for v in par.values()]
+        bpl = round(sum(tot) / len(tot))
+        wl = workload(name)
+        import numpy as np
+        alg = int(np.count_nonzero(wl.mask == 0)) * bytes_per_update(wl.storage)
+        data["workloads"][name] = {"bytes_per_launch": bpl, "algorithmic_bytes_per_launch": alg,
+                                   "ratio_to_algorithmic": round(bpl / alg, 4),
+                                   "per_parity": par, "grid_size": grid}
+    with open(out_path, "w") as fh:
+        json.dump(data, fh, indent=1)
+    return data
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,7 +265,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the out-of-cache and FP16 lattices and the copy bandwidth")
+    ap.add_argument("--digest", metavar="DIR",
+                    help="no run: digest rocprofv3 counter CSVs under DIR into profiles/traffic.json")
+    ap.add_argument("--grids", default="",
+                    help="with --digest: grid[/element type]=workload pairs, comma separated")
     args = ap.parse_args()
+    if args.digest:
+        grids = dict(kv.split("=") for kv in args.grids.split(",") if kv)
+        d = digest_counters(args.digest, grids, os.path.join(ROOT, "profiles", "traffic.json"))
+        print(json.dumps(d["workloads"]))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the lattice is not sharded across GPUs in this build)", file=sys.stderr)
