@@ -58,8 +58,10 @@ typedef enum gg_status {
 } gg_status;
 
 /* Population storage. Collision arithmetic is FP64 for GG_F64 and FP32
- * otherwise. GG_F16_SHIFTED stores h_i = f_i - w_i rho0 and
- * h^g_i = g_i - w^g_i c_shift in IEEE binary16, rounded to nearest even. */
+ * otherwise. Every storage type holds the deviations from rest,
+ * h_i = f_i - w_i rho0 and h^g_i = g_i - w^g_i c_shift, and the step
+ * computes on them; GG_F16_SHIFTED stores them in IEEE binary16, rounded to
+ * nearest even. */
 typedef enum gg_storage { GG_F64 = 0, GG_F32 = 1, GG_F16_SHIFTED = 2 } gg_storage;
 
 typedef enum gg_where { GG_HOST = 0, GG_DEVICE = 1 } gg_where;
@@ -83,9 +85,11 @@ typedef struct gg_params {
   double D;           /* compound diffusion coefficient, > 0 (after Eq. 9) */
   double w0;          /* compound rest weight, 0 <= w0 < 1 */
   double rho0;        /* reference density: default initial density,
-                         density of inlet/outlet links, FP16 shift of f */
+                         density of inlet/outlet links, shift of f */
   double k_decay;     /* first-order decay rate k >= 0 in R - kC (Eq. 2) */
-  double c_shift;     /* FP16 shift of the compound populations */
+  double c_shift;     /* shift C_s of the compound populations (finite);
+                         0 keeps a compound at 0 exact, a mid-range value
+                         uses the range of binary16 best */
   int32_t periodic_x; /* nonzero: x wraps; else the x edges are walls */
   int32_t periodic_y;
 } gg_params;

@@ -66,7 +66,7 @@ __device__ __forceinline__ GG_GLOBAL W *atw(void *base, int64_t plane, int i, ui
                          node * (uint32_t)sizeof(W));
 }
 
-// Populations of the current state in natural order (parity from *L.t).
+// Deviations df, dg of the current state in natural order (parity from *L.t).
 template <class S>
 __device__ __forceinline__ void gather_state(CDesc &L, uint32_t node, uint8_t lc, int x, int y,
                                              typename Pop<S>::T *f, typename Pop<S>::T *g) {
@@ -79,7 +79,6 @@ __device__ __forceinline__ void gather_state(CDesc &L, uint32_t node, uint8_t lc
   const int ym = (y == 0 && L.periodic_y) ? L.ny - 1 : y - 1;
   const int yp = (y == L.ny - 1 && L.periodic_y) ? 0 : y + 1;
   for (int i = 0; i < 9; ++i) {
-    const T sh = (T)(WF[i] * L.rho0);
     uint32_t src = node;
     int pl = i;
     if (odd && i > 0 && !((lc >> (OPP[i] - 1)) & 1)) {
@@ -88,10 +87,9 @@ __device__ __forceinline__ void gather_state(CDesc &L, uint32_t node, uint8_t lc
       src = (uint32_t)(L.node0 + yy * L.pitch + xx);
       pl = OPP[i];
     }
-    f[i] = P::ld(at<W>(L.pop, L.plane, pl, src), sh);
+    f[i] = P::ld(at<W>(L.pop, L.plane, pl, src));
   }
   for (int i = 0; i < 5; ++i) {
-    const T sh = (T)((i == 0 ? L.w0 : L.wg_axis) * L.c_shift);
     uint32_t src = node;
     int pl = i;
     if (odd && i > 0 && !((lc >> (OPP[i] - 1)) & 1)) {
@@ -100,11 +98,12 @@ __device__ __forceinline__ void gather_state(CDesc &L, uint32_t node, uint8_t lc
       src = (uint32_t)(L.node0 + yy * L.pitch + xx);
       pl = OPP[i];
     }
-    g[i] = P::ld(at<W>(L.pop, L.plane, 9 + pl, src), sh);
+    g[i] = P::ld(at<W>(L.pop, L.plane, 9 + pl, src));
   }
 }
 
-// Tape: g_i(x,t) and u(x,t) of the current state, in the compute type.
+// Tape: dg_i(x,t) = g_i - w_i C_s and u(x,t) of the current state, in the
+// compute type.
 template <class S>
 __global__ void __launch_bounds__(256)
     k_tape(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles, int n_tiles,
@@ -122,7 +121,7 @@ __global__ void __launch_bounds__(256)
   if (lc == NOT_FLUID) return;
   T f[9], g[5];
   gather_state<S>(L, node, lc, x, y, f, g);
-  const T rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+  const T rho = (T)L.rho0 + (f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8]);
   const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const T jy = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
   const T inv = T(1) / rho;
@@ -152,18 +151,22 @@ __global__ void __launch_bounds__(256)
   if (lc != NOT_FLUID) {
     T f[9], g[5];
     gather_state<S>(L, node, lc, x, y, f, g);
-    const double C = (double)g[0] + (double)g[1] + (double)g[2] + (double)g[3] + (double)g[4];
+    const double C = L.c_shift + ((double)g[0] + (double)g[1] + (double)g[2] + (double)g[3] +
+                                  (double)g[4]);
     const int k = y * L.nx + x;
     const double r = weight[k] * (C - target[k]);
     loss = 0.5 * weight[k] * (C - target[k]) * (C - target[k]);
-    for (int i = 0; i < 5; ++i) *atw<T>(lam, L.plane, i, node) = (T)r;
+    for (int i = 0; i < 5; ++i) *atw<double>(lam, L.plane, i, node) = r;
   }
   const double s = block_sum<256>(loss, lds);
   if (threadIdx.x == 0) partial[tile] += s;
 }
 
 // One adjoint step (pull over the links, then the transposed collision).
-template <class T>
+// The adjoint field is FP64 for every storage type: the tape (type TT) holds
+// the forward state in its compute type; lam has no rest part to subtract,
+// and an FP32 lam drifts by about 1e-7 relative per step.
+template <class TT>
 __global__ void __launch_bounds__(256)
     k_adjoint(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles, int n_tiles,
               int tx_shift, int64_t t, const void *__restrict__ lam_in, void *__restrict__ lam_out,
@@ -185,7 +188,9 @@ __global__ void __launch_bounds__(256)
   double ma = 0.0, mb = 0.0, dw = 0.0;
 
   if (lc != NOT_FLUID) {
-    const T wg[5] = {(T)L.w0, (T)L.wg_axis, (T)L.wg_axis, (T)L.wg_axis, (T)L.wg_axis};
+    using T = double;
+    const T wga = (T)(TT)L.wg_axis;  // the forward step's weights
+    const T wg[5] = {(T)(TT(1) - TT(4) * (TT)L.wg_axis), wga, wga, wga, wga};
     T lx[5];
     for (int i = 0; i < 5; ++i) lx[i] = *at<T>(lam_in, L.plane, i, node);
     const int xm = (x == 0 && L.periodic_x) ? L.nx - 1 : x - 1;
@@ -250,17 +255,20 @@ __global__ void __launch_bounds__(256)
     }
     // transposed collision with the taped state of step t
     T g[5];
-    for (int i = 0; i < 5; ++i) g[i] = *at<T>(tape, L.plane, i, node);
-    const T ux = *at<T>(tape, L.plane, 5, node), uy = *at<T>(tape, L.plane, 6, node);
-    const T C = g[0] + g[1] + g[2] + g[3] + g[4];
+    for (int i = 0; i < 5; ++i) g[i] = (T)*at<TT>(tape, L.plane, i, node);
+    const T ux = (T)*at<TT>(tape, L.plane, 5, node), uy = (T)*at<TT>(tape, L.plane, 6, node);
+    const T dC = g[0] + g[1] + g[2] + g[3] + g[4];  // taped deviations
+    const T C = (T)L.c_shift + dC;
     const T om = (T)L.omega_g, kd = (T)L.k_decay, ics = (T)L.inv_cs2g;
     T s = T(0), dr = T(0), dwl = T(0);
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
-      const T Wj = wg[j] * (T(1) + ((T)EX[j] * ux + (T)EY[j] * uy) * ics);
+      const T eu = ((T)EX[j] * ux + (T)EY[j] * uy) * ics;
+      const T Wj = wg[j] * (T(1) + eu);
       s += (om * Wj - kd * wg[j]) * ls[j];
       dr += wg[j] * ls[j];
-      dwl -= ls[j] * (g[j] - Wj * C);
+      // g_j - g^eq_j from the deviations: dg_j - w_j (dC + C e.u / cs2)
+      dwl -= ls[j] * (g[j] - wg[j] * (dC + C * eu));
     }
 #pragma unroll
     for (int i = 0; i < 5; ++i) *atw<T>(lam_out, L.plane, i, node) = (T(1) - om) * ls[i] + s;

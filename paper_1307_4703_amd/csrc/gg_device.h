@@ -60,7 +60,7 @@ struct LatDesc {
   double inv_cs2g;          // 1/cs2 of the compound lattice
   double rho0;              // reference density (inlet/outlet links)
   double k_decay;
-  double c_shift;           // FP16 shift of g
+  double c_shift;           // C_s: the planes hold g_i - w_i C_s
   // segments, index id - GG_FIRST_SEGMENT
   int32_t seg_kind[GG_MAX_SEGMENTS];
   int32_t seg_nx[GG_MAX_SEGMENTS];
@@ -105,28 +105,32 @@ template <class V> __device__ __forceinline__ void gstore(GG_GLOBAL V *p, V v) {
 }
 
 // Storage traits: load into the compute type, store with rounding. W is the
-// raw storage word that sits in the planes.
+// raw storage word that sits in the planes. Every storage type holds the
+// deviations df_i = f_i - w_i rho0 and dg_i = g_i - w_i C_s (the rest state
+// subtracted), and the step computes on the deviations directly, so the
+// rounding of the stored and of the computed values is relative to the
+// departure from rest rather than to w_i rho0.
 template <class S> struct Pop;
 template <> struct Pop<double> {
   using T = double;
   using W = double;
-  static __device__ __forceinline__ T ld(const GG_GLOBAL W *p, T) { return gload(p); }
-  static __device__ __forceinline__ void st(GG_GLOBAL W *p, T v, T) { gstore(p, v); }
+  static __device__ __forceinline__ T ld(const GG_GLOBAL W *p) { return gload(p); }
+  static __device__ __forceinline__ void st(GG_GLOBAL W *p, T v) { gstore(p, v); }
 };
 template <> struct Pop<float> {
   using T = float;
   using W = float;
-  static __device__ __forceinline__ T ld(const GG_GLOBAL W *p, T) { return gload(p); }
-  static __device__ __forceinline__ void st(GG_GLOBAL W *p, T v, T) { gstore(p, v); }
+  static __device__ __forceinline__ T ld(const GG_GLOBAL W *p) { return gload(p); }
+  static __device__ __forceinline__ void st(GG_GLOBAL W *p, T v) { gstore(p, v); }
 };
 template <> struct Pop<__half> {
   using T = float;
   using W = unsigned short;
-  static __device__ __forceinline__ T ld(const GG_GLOBAL W *p, T shift) {
-    return __half2float(__ushort_as_half(gload(p))) + shift;
+  static __device__ __forceinline__ T ld(const GG_GLOBAL W *p) {
+    return __half2float(__ushort_as_half(gload(p)));
   }
-  static __device__ __forceinline__ void st(GG_GLOBAL W *p, T v, T shift) {
-    gstore(p, __half_as_ushort(__float2half_rn(v - shift)));
+  static __device__ __forceinline__ void st(GG_GLOBAL W *p, T v) {
+    gstore(p, __half_as_ushort(__float2half_rn(v)));
   }
 };
 

@@ -112,46 +112,35 @@ template <class W> struct Planes {
   }
 };
 
-// Populations f_i(x,t), g_i(x,t) in natural order for step parity ODD.
+// Deviations df_i(x,t), dg_i(x,t) in natural order for step parity ODD.
 template <class S, bool ODD>
 __device__ __forceinline__ void load_state(const Planes<typename Pop<S>::W> &pl, uint32_t node,
                                            uint8_t lc, const Neigh &nb,
-                                           const typename Pop<S>::T *shf,
-                                           const typename Pop<S>::T *shg,
                                            typename Pop<S>::T *f, typename Pop<S>::T *g) {
   using P = Pop<S>;
   if (!ODD) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = P::ld(pl.at(i, node), shf[i]);
+    for (int i = 0; i < 9; ++i) f[i] = P::ld(pl.at(i, node));
 #pragma unroll
-    for (int i = 0; i < 5; ++i) g[i] = P::ld(pl.at(9 + i, node), shg[i]);
+    for (int i = 0; i < 5; ++i) g[i] = P::ld(pl.at(9 + i, node));
   } else {
     // streamed in from x - e_i, stored by that node in slot opp(i)
-    f[0] = P::ld(pl.at(0, node), shf[0]);
+    f[0] = P::ld(pl.at(0, node));
 #pragma unroll
-    for (int i = 1; i < 9; ++i) f[i] = P::ld(pl.at(OPP[i], nb.idx[OPP[i]]), shf[i]);
-    g[0] = P::ld(pl.at(9, node), shg[0]);
+    for (int i = 1; i < 9; ++i) f[i] = P::ld(pl.at(OPP[i], nb.idx[OPP[i]]));
+    g[0] = P::ld(pl.at(9, node));
 #pragma unroll
-    for (int i = 1; i < 5; ++i) g[i] = P::ld(pl.at(9 + OPP[i], nb.idx[OPP[i]]), shg[i]);
+    for (int i = 1; i < 5; ++i) g[i] = P::ld(pl.at(9 + OPP[i], nb.idx[OPP[i]]));
     if (lc != 0) {
       // x - e_i not fluid: this node stored the boundary value in its own slot i
 #pragma unroll
       for (int i = 1; i < 9; ++i)
-        if ((lc >> (OPP[i] - 1)) & 1) f[i] = P::ld(pl.at(i, node), shf[i]);
+        if ((lc >> (OPP[i] - 1)) & 1) f[i] = P::ld(pl.at(i, node));
 #pragma unroll
       for (int i = 1; i < 5; ++i)
-        if ((lc >> (OPP[i] - 1)) & 1) g[i] = P::ld(pl.at(9 + i, node), shg[i]);
+        if ((lc >> (OPP[i] - 1)) & 1) g[i] = P::ld(pl.at(9 + i, node));
     }
   }
-}
-
-template <class T>
-__device__ __forceinline__ void shifts(CDesc &L, T *shf, T *shg) {
-#pragma unroll
-  for (int i = 0; i < 9; ++i) shf[i] = (T)(WF[i] * L.rho0);
-  shg[0] = (T)(L.w0 * L.c_shift);
-#pragma unroll
-  for (int i = 1; i < 5; ++i) shg[i] = (T)(L.wg_axis * L.c_shift);
 }
 
 // ---------------------------------------------------------------------------
@@ -191,34 +180,44 @@ __device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
 
   if (lc != NOT_FLUID) {
     const Planes<W> pl(L);
-    T shf[9], shg[5];
-    shifts<T>(L, shf, shg);
     const Neigh nb(L, x, y);
-    T f[9], g[5];
-    load_state<S, ODD>(pl, node, lc, nb, shf, shg, f, g);
+    T f[9], g[5];  // deviations from rest, df_i and dg_i
+    load_state<S, ODD>(pl, node, lc, nb, f, g);
 
-    // Moments of f, paper Eq. 7 (sum over i = 0..8).
-    const T rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    // Moments of f, paper Eq. 7 (sum over i = 0..8): rho = rho0 + sum df_i;
+    // the rest part w_i rho0 carries no momentum.
+    const T rho0 = (T)L.rho0;
+    const T drho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    const T rho = rho0 + drho;
     const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     const T jy = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
     const T inv_rho = T(1) / rho;
     const T ux = jx * inv_rho, uy = jy * inv_rho;
     const T usq = ux * ux + uy * uy;
 
-    // BGK relaxation of f toward the quadratic equilibrium, Eqs. 4-6.
+    // BGK relaxation of f toward the quadratic equilibrium, Eqs. 4-6, for
+    // the deviations: f^eq_i - w_i rho0 = w_i (drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)).
     const T om_f = (T)L.omega_f;
     T pf[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const T eu = (T)EX[i] * ux + (T)EY[i] * uy;
-      const T feq = (T)WF[i] * rho * (T(1) + T(3) * eu + T(4.5) * eu * eu - T(1.5) * usq);
-      pf[i] = f[i] + om_f * (feq - f[i]);
+      const T dfeq = (T)WF[i] * (drho + rho * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * usq));
+      pf[i] = f[i] + om_f * (dfeq - f[i]);
     }
 
     // Compound: linear equilibrium with this node's u (Eq. 9), BGK (Eq. 8),
-    // source R - kC of Eq. 2 distributed with the lattice weights.
-    const T C = g[0] + g[1] + g[2] + g[3] + g[4];
-    const T wg[5] = {(T)L.w0, (T)L.wg_axis, (T)L.wg_axis, (T)L.wg_axis, (T)L.wg_axis};
+    // source R - kC of Eq. 2 distributed with the lattice weights. With
+    // C = C_s + dC: g^eq_i - w_i C_s = w_i (dC + C e.u / cs2).
+    const T cs = (T)L.c_shift;
+    const T dC = g[0] + g[1] + g[2] + g[3] + g[4];
+    const T C = cs + dC;
+    // The rest weight is 1 - 4 w_axis in the compute type, so the five
+    // weights sum to one exactly: with both weights rounded on their own
+    // (1/3 and 1/6 in FP32 sum to 1 + 3e-8) every collision would create
+    // solute in proportion to C.
+    const T wga = (T)L.wg_axis;
+    const T wg[5] = {T(1) - T(4) * wga, wga, wga, wga, wga};
     const T ics = (T)L.inv_cs2g;
     T src = -(T)L.k_decay * C;
     if (L.has_source) {
@@ -231,8 +230,8 @@ __device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
       const T eu = (T)EX[i] * ux + (T)EY[i] * uy;
-      const T geq = wg[i] * C * (T(1) + eu * ics);
-      pg[i] = g[i] + om_g * (geq - g[i]) + wg[i] * src;
+      const T dgeq = wg[i] * (dC + C * eu * ics);
+      pg[i] = g[i] + om_g * (dgeq - g[i]) + wg[i] * src;
     }
 
     // Value arriving at x along direction j when x - e_j is not fluid: the
@@ -246,7 +245,8 @@ __device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
     for (int j = 0; j < 5; ++j) in_g[j] = pg[OPP[j]];
 
     if (seg_tile && lc != 0) {
-      const T rho0 = (T)L.rho0;
+      // (every rule below is written for the deviations; w_j = w_opp(j), so
+      // the rest parts cancel except where noted)
 #pragma unroll
       for (int j = 1; j < 9; ++j) {
         if (!((lc >> (OPP[j] - 1)) & 1)) continue;  // x - e_j is fluid
@@ -272,12 +272,12 @@ __device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
                        ((T)L.seg_s1[s] - coord) * (T)L.seg_inv_w2[s];
           const T en = (T)(EX[j] * L.seg_nx[s] + EY[j] * L.seg_ny[s]);
           vf = pf[OPP[j]] - T(6) * (T)WF[j] * rho0 * en * us;
-          if (j < 5) vg = -pg[OPP[j]] + T(2) * wg[j] * (T)ph.cin[s];
+          if (j < 5) vg = -pg[OPP[j]] + T(2) * wg[j] * ((T)ph.cin[s] - cs);
         } else {
           // outflow at the reference density with the node's own u;
           // the compound leaves with zero gradient
           const T eu = (T)EX[j] * ux + (T)EY[j] * uy;
-          vf = -pf[OPP[j]] + T(2) * (T)WF[j] * rho0 * (T(1) + T(4.5) * eu * eu - T(1.5) * usq);
+          vf = -pf[OPP[j]] + T(2) * (T)WF[j] * rho0 * (T(4.5) * eu * eu - T(1.5) * usq);
           if (j < 5) vg = pg[j];
         }
         const double dm = (double)(vf - pf[OPP[j]]);
@@ -294,27 +294,27 @@ __device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
 
     if (!ODD) {
 #pragma unroll
-      for (int j = 0; j < 9; ++j) P::st(pl.at(j, node), in_f[j], shf[j]);
+      for (int j = 0; j < 9; ++j) P::st(pl.at(j, node), in_f[j]);
 #pragma unroll
-      for (int j = 0; j < 5; ++j) P::st(pl.at(9 + j, node), in_g[j], shg[j]);
+      for (int j = 0; j < 5; ++j) P::st(pl.at(9 + j, node), in_g[j]);
     } else {
-      P::st(pl.at(0, node), pf[0], shf[0]);
-      P::st(pl.at(9, node), pg[0], shg[0]);
+      P::st(pl.at(0, node), pf[0]);
+      P::st(pl.at(9, node), pg[0]);
       // free flight to x + e_i; where that cell is not fluid the value lands
       // in a slot nobody reads
 #pragma unroll
-      for (int i = 1; i < 9; ++i) P::st(pl.at(i, nb.idx[i]), pf[i], shf[i]);
+      for (int i = 1; i < 9; ++i) P::st(pl.at(i, nb.idx[i]), pf[i]);
 #pragma unroll
-      for (int i = 1; i < 5; ++i) P::st(pl.at(9 + i, nb.idx[i]), pg[i], shg[i]);
+      for (int i = 1; i < 5; ++i) P::st(pl.at(9 + i, nb.idx[i]), pg[i]);
       if (lc != 0) {
         // x + e_i not fluid: the value arriving here along opp(i) goes to
         // this node's own slot opp(i)
 #pragma unroll
         for (int i = 1; i < 9; ++i)
-          if ((lc >> (i - 1)) & 1) P::st(pl.at(OPP[i], node), in_f[OPP[i]], shf[i]);
+          if ((lc >> (i - 1)) & 1) P::st(pl.at(OPP[i], node), in_f[OPP[i]]);
 #pragma unroll
         for (int i = 1; i < 5; ++i)
-          if ((lc >> (i - 1)) & 1) P::st(pl.at(9 + OPP[i], node), in_g[OPP[i]], shg[i]);
+          if ((lc >> (i - 1)) & 1) P::st(pl.at(9 + OPP[i], node), in_g[OPP[i]]);
       }
     }
   }
@@ -360,46 +360,44 @@ __global__ void __launch_bounds__(256)
   if (x >= L.nx || y >= L.ny) return;
   const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
   const Planes<W> pl(L);
-  T shf[9], shg[5];
-  shifts<T>(L, shf, shg);
   if (((const GG_GLOBAL uint8_t *)L.link)[node] == NOT_FLUID) {
-    // never read; stored as zero populations
-    for (int i = 0; i < 9; ++i) P::st(pl.at(i, node), shf[i], shf[i]);
-    for (int i = 0; i < 5; ++i) P::st(pl.at(9 + i, node), shg[i], shg[i]);
+    // never read; stored as the rest state
+    for (int i = 0; i < 14; ++i) P::st(pl.at(i, node), T(0));
     return;
   }
+  // deviations from rest, differences taken in FP64
   const int k = y * L.nx + x;
+  const T drho = rho_in ? (T)(rho_in[k] - L.rho0) : T(0);
   const T rho = rho_in ? (T)rho_in[k] : (T)L.rho0;
   const T ux = ux_in ? (T)ux_in[k] : T(0);
   const T uy = uy_in ? (T)uy_in[k] : T(0);
   const T C = c_in ? (T)c_in[k] : T(0);
+  const T dC = (T)((c_in ? c_in[k] : 0.0) - L.c_shift);
   const T usq = ux * ux + uy * uy;
   for (int i = 0; i < 9; ++i) {
     const T eu = (T)EX[i] * ux + (T)EY[i] * uy;
-    const T feq = (T)WF[i] * rho * (T(1) + T(3) * eu + T(4.5) * eu * eu - T(1.5) * usq);
-    P::st(pl.at(i, node), feq, shf[i]);
+    P::st(pl.at(i, node), (T)WF[i] * (drho + rho * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * usq)));
   }
   const T ics = (T)L.inv_cs2g;
+  const T wga = (T)L.wg_axis;
   for (int i = 0; i < 5; ++i) {
-    const T w = i == 0 ? (T)L.w0 : (T)L.wg_axis;
+    const T w = i == 0 ? T(1) - T(4) * wga : wga;  // weights summing to one exactly
     const T eu = (T)EX[i] * ux + (T)EY[i] * uy;
-    P::st(pl.at(9 + i, node), w * C * (T(1) + eu * ics), shg[i]);
+    P::st(pl.at(9 + i, node), w * (dC + C * eu * ics));
   }
 }
 
-// Gathers f(x,t), g(x,t) of the current parity for the auxiliary kernels.
+// Gathers the deviations df(x,t), dg(x,t) of the current parity for the
+// auxiliary kernels.
 template <class S>
 __device__ __forceinline__ void gather(CDesc &L, uint32_t node, uint8_t lc, int x, int y,
                                        typename Pop<S>::T *f, typename Pop<S>::T *g) {
-  using T = typename Pop<S>::T;
   const Planes<typename Pop<S>::W> pl(L);
-  T shf[9], shg[5];
-  shifts<T>(L, shf, shg);
   const Neigh nb(L, x, y);
   if (*(const GG_CONST int64_t *)L.t & 1)
-    load_state<S, true>(pl, node, lc, nb, shf, shg, f, g);
+    load_state<S, true>(pl, node, lc, nb, f, g);
   else
-    load_state<S, false>(pl, node, lc, nb, shf, shg, f, g);
+    load_state<S, false>(pl, node, lc, nb, f, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -428,20 +426,25 @@ __global__ void __launch_bounds__(256)
   gather<S>(L, node, lc, x, y, fT, gT);
   const int64_t n = (int64_t)L.nx * L.ny;
   const int k = y * L.nx + x;
-  double f[9], g[5];
+  double f[9], g[5];  // deviations, FP64
   for (int i = 0; i < 9; ++i) f[i] = (double)fT[i];
   for (int i = 0; i < 5; ++i) g[i] = (double)gT[i];
   if (f_out)
-    for (int i = 0; i < 9; ++i) f_out[i * n + k] = f[i];
+    for (int i = 0; i < 9; ++i) f_out[i * n + k] = f[i] + WF[i] * L.rho0;
   if (g_out)
-    for (int i = 0; i < 5; ++i) g_out[i * n + k] = g[i];
-  const double rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    for (int i = 0; i < 5; ++i) {
+      // the weights of the step, in its compute type
+      const T wga = (T)L.wg_axis;
+      const double w = (double)(i == 0 ? T(1) - T(4) * wga : wga);
+      g_out[i * n + k] = g[i] + w * L.c_shift;
+    }
+  const double rho = L.rho0 + (f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8]);
   const double jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const double jy = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
   if (rho_out) rho_out[k] = rho;
   if (ux_out) ux_out[k] = jx / rho;
   if (uy_out) uy_out[k] = jy / rho;
-  if (c_out) c_out[k] = g[0] + g[1] + g[2] + g[3] + g[4];
+  if (c_out) c_out[k] = L.c_shift + (g[0] + g[1] + g[2] + g[3] + g[4]);
 }
 
 // Fills nx*ny doubles with a value (marks non-fluid nodes before k_read).
@@ -473,7 +476,7 @@ __global__ void __launch_bounds__(256)
   if (lc != NOT_FLUID) {
     T fT[9], gT[5];
     gather<S>(L, node, lc, x, y, fT, gT);
-    double rho = 0.0, jx = 0.0, jy = 0.0, C = 0.0;
+    double rho = 0.0, jx = 0.0, jy = 0.0, C = 0.0;  // deviations first
     bool finite = true;
     for (int i = 0; i < 9; ++i) {
       const double v = (double)fT[i];
@@ -487,6 +490,8 @@ __global__ void __launch_bounds__(256)
       finite = finite && isfinite(v);
       C += v;
     }
+    rho += L.rho0;
+    C += L.c_shift;
     cnt = 1.0;
     if (finite) {
       m = rho;

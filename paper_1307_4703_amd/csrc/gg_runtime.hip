@@ -733,7 +733,7 @@ gg_status gg_adjoint(gg_lattice *L, int64_t n, int64_t s, const double *weight,
   const size_t pop_bytes = (size_t)NPOP * L->plane * L->esize;
   const size_t tsz = L->storage == GG_F64 ? 8 : 4;
   const size_t slot = (size_t)7 * L->plane * tsz;
-  const size_t lam_bytes = (size_t)5 * L->plane * tsz;
+  const size_t lam_bytes = (size_t)5 * L->plane * sizeof(double);
   const size_t nxy = (size_t)L->nx * L->ny;
   const int na = std::max(L->n_aux_tiles, 1);
 
