@@ -22,7 +22,9 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "coupled NSE+CDE MLUPS and % HBM roofline on 1 MI355X; FP32/FP16 vs FP64 error"
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
-KERNEL_SRC = os.path.join(ROOT, "paper_1307_4703_amd", "csrc", "gg_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1307_4703_amd", "csrc")
+KERNEL_SRC = [os.path.join(CSRC, f) for f in ("gg_device.h", "gg_node.h", "gg_kernels.hip",
+                                                "gg_fused.hip")]
 
 
 def log(msg):
@@ -53,8 +55,11 @@ def workload(name):
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(wl_name):
@@ -72,17 +77,26 @@ def load_traffic(wl_name):
     return ent.get("bytes_per_launch")
 
 
-def time_lattice(name, steps, warmup, tile, chunk):
+def time_lattice(name, steps, warmup, tile, chunk, form=None):
     """Graph-replayed steps timed with HIP events on the lattice's stream
-    (torch's current stream), plus an even/odd kernel breakdown."""
+    (torch's current stream), after the autotuner picked the launch form
+    (single steps or a two-step pass); plus per-kernel timings."""
     import torch
     from paper_1307_4703_amd import Lattice
+    from paper_1307_4703_amd import tune as T
     wl = workload(name)
     lat = Lattice.from_workload(wl)
     lat.set_launch(tile[0], tile[1], chunk)
     nf = lat.info()["n_fluid"]
+    if form is None:
+        res = T.tune_lattice(lat, steps=64 if nf > 1e7 else 256, graph_chunk=chunk,
+                             use_cache=False)
+        form = {"tile": res["tile"], "fuse": res["fuse"], "rows": res["rows"]}
+    else:
+        form = {"tile": list(tile), **form}
+        lat.set_two_step(form["fuse"], form["rows"])
     log(f"{wl.name}: {wl.nx}x{wl.ny}, {nf} fluid nodes, storage {wl.storage}, "
-        f"tile {tile}, graph chunk {chunk}; warmup {warmup}")
+        f"form {form}, graph chunk {chunk}; warmup {warmup}")
     lat.step(warmup)
     lat.sync()
     torch.cuda.synchronize()
@@ -98,21 +112,39 @@ def time_lattice(name, steps, warmup, tile, chunk):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = ev0.elapsed_time(ev1)
-    n_k = min(steps, 400 if nf > 1e7 else 2000)
+    n_k = min(steps, 200 if nf > 1e7 else 1000)
+    extra = {}
+    if form["fuse"] >= 2:
+        extra["ms_pass_plain_launches"] = lat.step2_timed(max(1, n_k // 4))
+    fuse = form["fuse"]
+    lat.set_two_step(1)  # single-step kernels, for the breakdown
     ms_even, ms_odd = lat.step_timed(n_k)
     diag = lat.diagnostics(check_finite=False)
     lat.close()
-    return {"wl": wl, "nf": nf, "wall_s": wall, "event_ms": ev_ms,
-            "kernel_ms": ev_ms / steps, "ms_even": ms_even, "ms_odd": ms_odd, "diag": diag}
+    spl = 2 if fuse >= 2 else 1  # steps per launch of the dominant kernel
+    return {"wl": wl, "nf": nf, "wall_s": wall, "event_ms": ev_ms, "form": form,
+            "steps_per_launch": spl, "launch_ms": ev_ms / steps * spl,
+            "ms_even": ms_even, "ms_odd": ms_odd, "diag": diag, **extra}
 
 
 def roofline(r, storage, traffic):
+    """Dominant kernel: the two-step pass (each population read and written
+    once per launch, two steps) or the single step; algorithmic bytes per
+    launch = fluid nodes x (14 x 2 x storage bytes + 1 link byte)."""
     bpl = r["nf"] * bytes_per_update(storage)
-    ach = bpl / (r["kernel_ms"] * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
-            "algorithmic_bytes_per_launch": bpl, "kernel_ms": round(r["kernel_ms"], 5),
-            "kernel_ms_even_odd": [round(r["ms_even"], 5), round(r["ms_odd"], 5)]}
+    ach = bpl / (r["launch_ms"] * 1e-3) / 1e9
+    out = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
+           "algorithmic_bytes_per_launch": bpl, "steps_per_launch": r["steps_per_launch"],
+           "kernel_ms": round(r["launch_ms"], 5),
+           "single_step_kernel_ms_even_odd": [round(r["ms_even"], 5), round(r["ms_odd"], 5)],
+           # the rate in updates, priced at the single-step bytes per update
+           "update_rate_frac_of_single_step_roofline":
+               round(r["nf"] * bytes_per_update(storage) * r["steps_per_launch"] /
+                     (r["launch_ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    if "ms_pass_plain_launches" in r:
+        out["kernel_ms_pass_plain_launches"] = round(r["ms_pass_plain_launches"], 5)
+    return out
 
 
 def copy_bandwidth(nbytes=2 << 30, reps=20):
@@ -202,7 +234,8 @@ def cpu_baseline(name, budget_s=15.0):
 def digest_counters(prof_dir, grids, out_path):
     """Turn two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per
     dispatch) into HBM bytes per step launch for the workloads named in
-    ``grids`` ({"grid size[/element type]": workload}), scaled by what the same counters read
+    ``grids`` ({"grid size/kernel name part": workload}; the bytes of all
+    matching kernels are averaged), scaled by what the same counters read
     for the plain copy kernel of known size; writes ``out_path`` (JSON)."""
     import csv
     from collections import defaultdict
@@ -225,22 +258,22 @@ def digest_counters(prof_dir, grids, out_path):
     ck = copy[0]
     n_copy = ck[1] * 16  # one 16-byte vector per lane, read and written
     fs, ws = n_copy / 1024.0 / fetch[ck], n_copy / 1024.0 / write[ck]
-    data = {"kernel_sha": kernel_hash(), "source": os.path.relpath(KERNEL_SRC, ROOT),
+    data = {"kernel_sha": kernel_hash(), "source": [os.path.relpath(p, ROOT) for p in KERNEL_SRC],
             "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
             "calibration": {"kernel": "gg::k_copy", "bytes_read": n_copy, "bytes_written": n_copy,
                             "FETCH_SIZE_KiB": fetch[ck], "WRITE_SIZE_KiB": write[ck]},
             "workloads": {}}
     for key, name in grids.items():
-        grid, _, elem = key.partition("/")
+        grid, _, kname = key.partition("/")
         grid = int(grid)
-        steps = {k: v for k, v in fetch.items() if k[1] == grid and f"k_step<{elem}" in k[0]}
+        steps = {k: v for k, v in fetch.items() if k[1] == grid and kname in k[0]}
         if not steps:
-            raise SystemExit(f"no step kernel with grid size {grid} ({name})")
+            raise SystemExit(f"no kernel {kname!r} with grid size {grid} ({name})")
         par = {}
         for k in steps:
-            odd = k[0].split(",")[2].strip().startswith("true")
-            par["odd" if odd else "even"] = {"fetch_bytes": round(fetch[k] * 1024 * fs),
-                                             "write_bytes": round(write.get(k, 0.0) * 1024 * ws)}
+            tag = k[0].split("(")[0].split("::")[-1]
+            par[tag] = {"fetch_bytes": round(fetch[k] * 1024 * fs),
+                        "write_bytes": round(write.get(k, 0.0) * 1024 * ws)}
         tot = [v["fetch_bytes"] + v["write_bytes"] for v in par.values()]
         bpl = round(sum(tot) / len(tot))
         wl = workload(name)
@@ -248,7 +281,7 @@ def digest_counters(prof_dir, grids, out_path):
         alg = int(np.count_nonzero(wl.mask == 0)) * bytes_per_update(wl.storage)
         data["workloads"][name] = {"bytes_per_launch": bpl, "algorithmic_bytes_per_launch": alg,
                                    "ratio_to_algorithmic": round(bpl / alg, 4),
-                                   "per_parity": par, "grid_size": grid}
+                                   "per_kernel": par, "grid_size": grid, "kernel": kname}
     with open(out_path, "w") as fh:
         json.dump(data, fh, indent=1)
     return data
@@ -262,13 +295,17 @@ def main():
     ap.add_argument("--workload", default="gg2048_f32")
     ap.add_argument("--tile", default="64x4")
     ap.add_argument("--chunk", type=int, default=64)
+    ap.add_argument("--fuse", type=int, default=0,
+                    help="launch form (1 single steps, 2-4 two-step passes); 0: autotune")
+    ap.add_argument("--rows", type=int, default=6, help="rows of the two-step strips or tiles")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the out-of-cache and FP16 lattices and the copy bandwidth")
     ap.add_argument("--digest", metavar="DIR",
                     help="no run: digest rocprofv3 counter CSVs under DIR into profiles/traffic.json")
     ap.add_argument("--grids", default="",
-                    help="with --digest: grid[/element type]=workload pairs, comma separated")
+                    help="with --digest: grid/kernel=workload pairs, comma separated "
+                         "(kernel: a part of the kernel name, e.g. k_tile2<float)")
     args = ap.parse_args()
     if args.digest:
         grids = dict(kv.split("=") for kv in args.grids.split(",") if kv)
@@ -286,7 +323,8 @@ def main():
     torch.cuda.set_device(0)
     tile = tuple(int(v) for v in args.tile.split("x"))
 
-    r = time_lattice(args.workload, args.steps, args.warmup, tile, args.chunk)
+    form = {"fuse": args.fuse, "rows": args.rows} if args.fuse else None
+    r = time_lattice(args.workload, args.steps, args.warmup, tile, args.chunk, form)
     wl, nf = r["wl"], r["nf"]
     out = {
         "metric": METRIC,
@@ -304,8 +342,8 @@ def main():
         "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "n_fluid": nf,
                    "storage": wl.storage, "D": wl.D, "tau_f": wl.tau_f,
                    "valve_half_period": wl.schedule[0].duration if wl.schedule else None,
-                   "tile": args.tile, "graph_chunk": args.chunk,
-                   "bytes_per_update": bytes_per_update(wl.storage),
+                   "launch_form": r["form"], "graph_chunk": args.chunk,
+                   "bytes_per_update_single_step": bytes_per_update(wl.storage),
                    "wall_clock_mlups": round(nf * args.steps / r["wall_s"] / 1e6, 1),
                    "lattice_mlups": round(wl.nx * wl.ny * args.steps / (r["event_ms"] * 1e-3) / 1e6, 1),
                    "parallelism": "single GPU"},
@@ -323,7 +361,7 @@ def main():
                             ("gg8192_f16", 2000)):
             if name == args.workload:
                 continue
-            r2 = time_lattice(name, steps, 100, tile, args.chunk)
+            r2 = time_lattice(name, steps, 100, tile, args.chunk, form)
             e = roofline(r2, r2["wl"].storage, load_traffic(name))
             e["mlups"] = round(r2["nf"] * steps / (r2["event_ms"] * 1e-3) / 1e6, 1)
             e["workload"] = r2["wl"].name

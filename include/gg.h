@@ -165,7 +165,10 @@ gg_status gg_set_region(gg_lattice *lat, const uint8_t *region);
 gg_status gg_init(gg_lattice *lat, const double *rho, const double *ux,
                   const double *uy, const double *C, gg_where where);
 
-/* Advance n >= 0 time steps. Asynchronous. */
+/* Advance n >= 0 time steps. Asynchronous. With the two-step pass on (the
+ * default, see gg_set_two_step) the steps from an even t go in passes of
+ * two steps each, in groups of four steps; a leftover or odd-t step runs
+ * as a single step. Both ways give the same state, bit for bit. */
 gg_status gg_step(gg_lattice *lat, int64_t n);
 
 /* Macroscopic fields at the current time (nx*ny doubles each; NaN off the
@@ -191,13 +194,35 @@ gg_status gg_diagnostics(gg_lattice *lat, gg_diag *out);
 gg_status gg_save(gg_lattice *lat, void *buf, size_t *nbytes);
 gg_status gg_load(gg_lattice *lat, const void *buf, size_t nbytes);
 
-/* Kernel launch shape: tiles of tile_x * tile_y nodes (one work-group each,
- * tile_x * tile_y in {64, 128, 256, 512}, tile_x a multiple of 8); only
- * tiles holding a fluid node are launched. graph_chunk > 0 replays
- * gg_step in HIP graphs of that many steps (rounded up to even); 0
- * launches every step. */
+/* Kernel launch shape of the single steps: tiles of tile_x * tile_y nodes
+ * (one work-group each, tile_x * tile_y in {64, 128, 256, 512}, tile_x a
+ * multiple of 8); only tiles holding a fluid node are launched.
+ * graph_chunk > 0 replays gg_step in HIP graphs of that many steps (rounded
+ * up to even, to a multiple of 4 with the two-step pass); 0 launches every
+ * step. */
 gg_status gg_set_launch(gg_lattice *lat, int32_t tile_x, int32_t tile_y,
                         int32_t graph_chunk);
+
+/* Two-step pass (fuse = 2, 3 or 4; a new lattice starts with fuse = 3,
+ * strip_h = 6) or single steps only (fuse = 1). The pass reads the state
+ * of an even step once and writes the state two steps later into a second
+ * set of population planes (same size as the first; allocated while
+ * fuse >= 2, freed by fuse = 1), so every population crosses HBM once per
+ * two steps instead of once per step.
+ *   fuse = 2: one wavefront walks a strip of 62 columns x strip_h rows
+ *     (1..4096), keeping the first step's result of each row in registers;
+ *   fuse = 3: one work-group of strip_h + 2 wavefronts (strip_h 6 or 14)
+ *     does a tile of 62 columns x strip_h rows, all rows at once, with the
+ *     first step's row-crossing populations exchanged through LDS;
+ *   fuse = 4: the tiles of fuse = 3, with the boundary-segment rules
+ *     compiled into the one kernel that does every tile (with 2 and 3 the
+ *     strips and tiles that touch a segment run in a kernel of their own,
+ *     beside the others on a second stream, which keeps the boundary code
+ *     out of the others' register budget).
+ * Each collides a one-node halo around its strip or tile once more for the
+ * first step. Errors: GG_ERR_ARG for other values, GG_ERR_OOM if the
+ * planes do not fit. */
+gg_status gg_set_two_step(gg_lattice *lat, int32_t fuse, int32_t strip_h);
 
 /* Number of fluid nodes and launched tiles. */
 gg_status gg_info(const gg_lattice *lat, int64_t *n_fluid, int64_t *n_tiles,
@@ -255,6 +280,12 @@ gg_status gg_adjoint(gg_lattice *lat, int64_t n_steps, int64_t ckpt_every,
  * mean event-measured duration, in ms, of the even-step and of the
  * odd-step kernels (either pointer may be NULL). Waits for the stream. */
 gg_status gg_step_timed(gg_lattice *lat, int64_t n, double *ms_even, double *ms_odd);
+
+/* Instrumentation: with the two-step pass on and t even, run 2 * n_pairs
+ * passes (4 * n_pairs steps) between HIP events on the lattice's stream and
+ * return the mean event-measured duration of one pass, in ms. Waits for
+ * the stream. GG_ERR_STATE if the pass is off or t is odd. */
+gg_status gg_step2_timed(gg_lattice *lat, int64_t n_pairs, double *ms_pass);
 
 /* Instrumentation: copy `bytes` (a multiple of 16) from src to dst, both
  * device buffers, `reps` times with a plain streaming kernel on hip_stream,

@@ -90,6 +90,8 @@ SIGS = {
     "gg_info": [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)],
     "gg_sync": [P],
     "gg_step_timed": [P, I64, ctypes.POINTER(D), ctypes.POINTER(D)],
+    "gg_set_two_step": [P, I32, I32],
+    "gg_step2_timed": [P, I64, ctypes.POINTER(D)],
     "gg_adjoint": [P, I64, I64, P, P, P, P, ctypes.POINTER(gg_grads)],
     "gg_batch_create": [ctypes.POINTER(P), I32, I32, I32, I32, I32, ctypes.POINTER(P)],
     "gg_batch_step": [P, I64],

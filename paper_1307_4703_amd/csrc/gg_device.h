@@ -48,6 +48,7 @@ struct LatDesc {
   int32_t node0, pad0;
   int64_t plane;            // elements between population planes
   void *pop;                // 14 planes of the storage type
+  void *pop_b;              // second plane set of the two-step pass (or null)
   const uint8_t *link;      // link codes, plane layout
   const uint8_t *mask;      // mask values, plane layout
   const uint8_t *region;    // region flags, plane layout (or null)
@@ -116,22 +117,35 @@ template <> struct Pop<double> {
   using W = double;
   static __device__ __forceinline__ T ld(const GG_GLOBAL W *p) { return gload(p); }
   static __device__ __forceinline__ void st(GG_GLOBAL W *p, T v) { gstore(p, v); }
+  // the value a store followed by a load gives back
+  static __device__ __forceinline__ T rt(T v) { return v; }
 };
 template <> struct Pop<float> {
   using T = float;
   using W = float;
   static __device__ __forceinline__ T ld(const GG_GLOBAL W *p) { return gload(p); }
   static __device__ __forceinline__ void st(GG_GLOBAL W *p, T v) { gstore(p, v); }
+  static __device__ __forceinline__ T rt(T v) { return v; }
 };
 template <> struct Pop<__half> {
   using T = float;
   using W = unsigned short;
+  // FP32 result first, then round to nearest-even binary16. The empty asm
+  // keeps the compiler from folding the conversion into the arithmetic that
+  // produced v (a mixed-precision FMA with one rounding), which it would do
+  // in some kernels and not in others.
+  static __device__ __forceinline__ __half to_half(T v) {
+    asm("" : "+v"(v));
+    return __float2half_rn(v);
+  }
   static __device__ __forceinline__ T ld(const GG_GLOBAL W *p) {
     return __half2float(__ushort_as_half(gload(p)));
   }
   static __device__ __forceinline__ void st(GG_GLOBAL W *p, T v) {
-    gstore(p, __half_as_ushort(__float2half_rn(v)));
+    gstore(p, __half_as_ushort(to_half(v)));
   }
+  // the value a store followed by a load gives back
+  static __device__ __forceinline__ T rt(T v) { return __half2float(to_half(v)); }
 };
 
 }  // namespace gg

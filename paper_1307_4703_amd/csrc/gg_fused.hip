@@ -1,0 +1,399 @@
+// Two coupled time steps in one pass over memory.
+//
+// The lattice state at an even step t is in natural order in one plane set
+// (slot i of node x holds df_i(x,t)); the pass reads it once and writes the
+// state at t + 2, in natural order, into the other plane set. One wavefront
+// owns a strip of 62 columns and H rows. Its 64 lanes hold the columns
+// x0 - 1 .. x0 + 62 and it walks the rows y0 - 1 .. y0 + H, so the strip
+// plus a one-node halo is collided once for step t:
+//
+//   row y:   load df, dg (natural order) -> collide (step t) -> post1(y)
+//            the populations post1 sends to its own row and to the rows
+//            y - 1 and y + 1 reach the right columns through lane shifts;
+//   row y-1: its state at t + 1 is now complete (the populations it pulls
+//            from rows y - 2, y - 1 and y, or its own boundary values where
+//            the source is not fluid) -> collide (step t + 1) -> store the
+//            post-collision populations into the neighbours' slots of the
+//            other plane set (or boundary values into its own slots).
+//
+// This is the same data flow as an even AA step followed by an odd one,
+// with the intermediate state kept in registers instead of memory: each node
+// goes through collide_node with the same inputs (the intermediate values
+// are rounded to the storage type, as a store and load would round them),
+// so the result is the one the single-step kernels give. The halo lanes and
+// rows are collided for step t only, for the populations they send into
+// the strip; they are owned by the neighbouring strips, which collide and
+// store them themselves.
+#include "gg_device.h"
+#include "gg_kernels.h"
+#include "gg_node.h"
+
+namespace gg {
+
+namespace {
+
+constexpr int STRIP_W = 62;  // owned columns per wavefront
+
+// x - e_j is not fluid for a node with link code lc (j = 1..8)
+__device__ __forceinline__ bool src_solid(uint8_t lc, int j) { return (lc >> (OPP[j] - 1)) & 1; }
+
+template <class T> __device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1); }
+template <class T> __device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1); }
+
+// Step t + 1 at node (x, y) from its state sf, sg at t + 1 (natural order),
+// with the post-collision populations pushed into the neighbours' slots of
+// the destination planes (or, toward a non-fluid neighbour, the value that
+// arrives here along the opposite direction into this node's own slot).
+template <class S, bool SEG>
+__device__ __forceinline__ void second_step(CDesc &L, const Planes<typename Pop<S>::W> &dst,
+                                            int x, int y, uint8_t lc, const PhaseNow &ph,
+                                            const typename Pop<S>::T *sf,
+                                            const typename Pop<S>::T *sg, Flux &fx) {
+  using P = Pop<S>;
+  using T = typename P::T;
+  T qf[9], qg[5], jf[9], jg[5];
+  collide_node<T>(L, x, y, lc, SEG, ph, sf, sg, qf, qg, jf, jg, fx, true);
+  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+  const Neigh nb(L, x, y);
+  P::st(dst.at(0, node), qf[0]);
+  P::st(dst.at(9, node), qg[0]);
+#pragma unroll
+  for (int i = 1; i < 9; ++i) P::st(dst.at(i, nb.idx[i]), qf[i]);
+#pragma unroll
+  for (int i = 1; i < 5; ++i) P::st(dst.at(9 + i, nb.idx[i]), qg[i]);
+  if (lc != 0) {
+    // x + e_i not fluid: the value arriving along opp(i) stays here
+#pragma unroll
+    for (int i = 1; i < 9; ++i)
+      if ((lc >> (i - 1)) & 1) P::st(dst.at(OPP[i], node), jf[OPP[i]]);
+#pragma unroll
+    for (int i = 1; i < 5; ++i)
+      if ((lc >> (i - 1)) & 1) P::st(dst.at(9 + OPP[i], node), jg[OPP[i]]);
+  }
+}
+
+// Height of a strip (rows) is kept in the tile flags above bit 8.
+__device__ __forceinline__ int strip_rows(int flags) { return flags >> 8; }
+
+template <class S, bool SEG>
+__device__ __forceinline__ void strip_two_steps(const LatDesc *__restrict__ descs,
+                                                const Tile *__restrict__ strips, int s, int dir,
+                                                int dt) {
+  using P = Pop<S>;
+  using T = typename P::T;
+  using W = typename P::W;
+  const int lane = (int)(threadIdx.x & 63);
+  const GG_CONST Tile &tl = ((const GG_CONST Tile *)strips)[s];
+  CDesc &L = ((CDesc *)descs)[tl.inst];
+  const int nx = L.nx, ny = L.ny, pitch = L.pitch;
+  const int H = strip_rows(tl.flags);
+  const int64_t t = *(const GG_CONST int64_t *)L.t + dt;
+  PhaseNow ph1{0u, nullptr}, ph2{0u, nullptr};
+  if (SEG) {
+    ph1 = phase_at(L, t);
+    ph2 = phase_at(L, t + 1);
+  }
+  const Planes<W> src(dir ? L.pop_b : L.pop, L.plane);
+  const Planes<W> dst(dir ? L.pop : L.pop_b, L.plane);
+  const GG_GLOBAL uint8_t *link = (const GG_GLOBAL uint8_t *)L.link;
+
+  // this lane's column: addressable for -1 <= x <= nx (wrapped if periodic)
+  const int xr = tl.x0 - 1 + lane;
+  const bool col = xr >= -1 && xr <= nx;
+  int x = xr;
+  if (L.periodic_x) x = xr < 0 ? xr + nx : (xr >= nx ? xr - nx : xr);
+  const bool own_col = lane >= 1 && lane <= STRIP_W && xr >= 0 && xr < nx;
+
+  // row r of the strip is lattice row y0 + r, addressable for -1 <= y <= ny
+  // (wrapped if periodic)
+  auto row_y = [&](int r) -> int {
+    const int yr = tl.y0 + r;
+    return L.periodic_y ? (yr < 0 ? yr + ny : (yr >= ny ? yr - ny : yr)) : yr;
+  };
+  auto node_of = [&](int r, bool &ok) -> uint32_t {
+    const int yr = tl.y0 + r;
+    ok = col && yr >= -1 && yr <= ny;
+    return (uint32_t)(L.node0 + row_y(r) * pitch + x);
+  };
+
+  T sf[9], sg[5];  // state at t + 1 of the previous row (this column)
+  T uf2 = T(0), uf5 = T(0), uf6 = T(0), ug2 = T(0);  // pulls it passes up
+  uint8_t lcp = NOT_FLUID;
+  int yprev = 0;
+  bool own_prev = false;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) sf[i] = T(0);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) sg[i] = T(0);
+  Flux fx;
+
+  // Software pipeline: the link codes run two rows ahead and the
+  // populations one row ahead of the row being computed, so both are in
+  // flight while the current row is collided, and only fluid cells load.
+  T nf[9], ng[5];
+  uint8_t nlc, nnlc = NOT_FLUID;
+  {
+    bool ok;
+    const uint32_t node = node_of(-1, ok);
+    nlc = ok ? link[node] : NOT_FLUID;
+    if (nlc != NOT_FLUID) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) nf[i] = P::ld(src.at(i, node));
+#pragma unroll
+      for (int i = 0; i < 5; ++i) ng[i] = P::ld(src.at(9 + i, node));
+    }
+    const uint32_t node2 = node_of(0, ok);
+    if (ok) nnlc = link[node2];
+  }
+
+  for (int r = -1; r <= H; ++r) {
+    bool ok;
+    const int y = row_y(r);
+    const bool own = own_col && r >= 0 && r < H && tl.y0 + r < ny;
+    const uint8_t lc = nlc;
+    T f[9], g[5];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = nf[i];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) g[i] = ng[i];
+    // loads of row r + 1 (populations) and r + 2 (link codes)
+    nlc = nnlc;
+    nnlc = NOT_FLUID;
+    if (r < H) {
+      const uint32_t node1 = node_of(r + 1, ok);
+      if (nlc != NOT_FLUID) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) nf[i] = P::ld(src.at(i, node1));
+#pragma unroll
+        for (int i = 0; i < 5; ++i) ng[i] = P::ld(src.at(9 + i, node1));
+      }
+      if (r + 1 < H) {
+        const uint32_t node2 = node_of(r + 2, ok);
+        if (ok) nnlc = link[node2];
+      }
+    }
+
+    // step t at (x, y)
+    T pf[9], pg[5], inf[9], ing[5];
+    if (lc != NOT_FLUID) {
+      collide_node<T>(L, x, y, lc, SEG, ph1, f, g, pf, pg, inf, ing, fx, own);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) pf[i] = inf[i] = T(0);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) pg[i] = ing[i] = T(0);
+    }
+    // populations that change column on their way (every lane takes part)
+    const T zf1 = from_left(pf[1]), zf3 = from_right(pf[3]);
+    const T zg1 = from_left(pg[1]), zg3 = from_right(pg[3]);
+    const T vf5 = from_left(pf[5]), vf6 = from_right(pf[6]);
+    const T df7 = from_right(pf[7]), df8 = from_left(pf[8]);
+
+    // the previous row pulls f4, f7, f8, g4 from this row: step t + 1 there
+    if (own_prev && lcp != NOT_FLUID) {
+      if (!src_solid(lcp, 4)) sf[4] = P::rt(pf[4]);
+      if (!src_solid(lcp, 7)) sf[7] = P::rt(df7);
+      if (!src_solid(lcp, 8)) sf[8] = P::rt(df8);
+      if (!src_solid(lcp, 4)) sg[4] = P::rt(pg[4]);
+      second_step<S, SEG>(L, dst, x, yprev, lcp, ph2, sf, sg, fx);
+    }
+
+    // state at t + 1 of this row, without the pulls from the row below
+    if (lc != NOT_FLUID) {
+      sf[0] = P::rt(pf[0]);
+      sg[0] = P::rt(pg[0]);
+      sf[1] = P::rt(src_solid(lc, 1) ? inf[1] : zf1);
+      sf[3] = P::rt(src_solid(lc, 3) ? inf[3] : zf3);
+      sg[1] = P::rt(src_solid(lc, 1) ? ing[1] : zg1);
+      sg[3] = P::rt(src_solid(lc, 3) ? ing[3] : zg3);
+      sf[2] = P::rt(src_solid(lc, 2) ? inf[2] : uf2);
+      sf[5] = P::rt(src_solid(lc, 5) ? inf[5] : uf5);
+      sf[6] = P::rt(src_solid(lc, 6) ? inf[6] : uf6);
+      sg[2] = P::rt(src_solid(lc, 2) ? ing[2] : ug2);
+      sf[4] = P::rt(inf[4]);
+      sf[7] = P::rt(inf[7]);
+      sf[8] = P::rt(inf[8]);
+      sg[4] = P::rt(ing[4]);
+    }
+    uf2 = pf[2];
+    uf5 = vf5;
+    uf6 = vf6;
+    ug2 = pg[2];
+    lcp = lc;
+    yprev = y;
+    own_prev = own;
+    if (SEG) fx.flush((double *)L.flux);
+  }
+}
+
+
+// Two steps over a strip list: 256-thread work-groups, one strip per
+// wavefront. Work-groups are dealt to the 8 XCDs so that each XCD walks a
+// contiguous run of strips (the list runs along each band of rows, so
+// neighbouring strips, which share cache lines at their edges, share an L2).
+// SEG: strips with links to boundary segments (their own kernel, so that
+// the boundary rules do not set the register budget of the others).
+template <class S, bool SEG>
+__global__ void __launch_bounds__(256)
+    k_step2(const LatDesc *__restrict__ descs, const Tile *__restrict__ strips, int n_strips,
+            int per_xcd, int dir, int dt) {
+  const int nb = 8 * per_xcd;
+  // the wavefront index, marked uniform so that the strip, the descriptor
+  // and the plane bases are read with scalar loads
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int s = ((b & 7) * per_xcd + (b >> 3)) * 4 + w;
+    if (s < n_strips) strip_two_steps<S, SEG>(descs, strips, s, dir, dt);
+  }
+}
+
+// Row-parallel form of the same two steps, for lattices too small to keep
+// the GPU busy with walking strips: one work-group per tile of 62 columns x
+// R rows (at most; the row count is in the tile flags), R + 2 wavefronts,
+// wavefront w on lattice row y0 - 1 + w. Every wavefront does step t on its
+// row; the populations that cross rows (f2, f5, f6, g2 up; f4, f7, f8, g4
+// down) go through LDS; after one barrier the owned rows do step t + 1.
+template <class S, bool SEG, int R>
+__global__ void __launch_bounds__((R + 2) * 64)
+    k_tile2(const LatDesc *__restrict__ descs, const Tile *__restrict__ tiles, int n_tiles,
+            int per_xcd, int dir, int dt) {
+  using P = Pop<S>;
+  using T = typename P::T;
+  using W = typename P::W;
+  __shared__ T lds_up[R + 2][4][64];
+  __shared__ T lds_dn[R + 2][4][64];
+  const int lane = (int)(threadIdx.x & 63);
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int nb = 8 * per_xcd;
+  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int tile = (b & 7) * per_xcd + (b >> 3);
+    if (tile >= n_tiles) continue;  // the same for the whole work-group
+    const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
+    CDesc &L = ((CDesc *)descs)[tl.inst];
+    const int nx = L.nx, ny = L.ny, pitch = L.pitch;
+    const int rows = strip_rows(tl.flags);
+    const int64_t t = *(const GG_CONST int64_t *)L.t + dt;
+    // with SEG, the tiles without segment links skip the boundary rules
+    const bool seg = SEG && (tl.flags & TILE_TOUCHES_SEGMENT) != 0;
+    PhaseNow ph1{0u, nullptr}, ph2{0u, nullptr};
+    if (seg) {
+      ph1 = phase_at(L, t);
+      ph2 = phase_at(L, t + 1);
+    }
+    const Planes<W> src(dir ? L.pop_b : L.pop, L.plane);
+    const Planes<W> dst(dir ? L.pop : L.pop_b, L.plane);
+
+    const int xr = tl.x0 - 1 + lane;
+    const bool col = xr >= -1 && xr <= nx;
+    int x = xr;
+    if (L.periodic_x) x = xr < 0 ? xr + nx : (xr >= nx ? xr - nx : xr);
+    const bool own_col = lane >= 1 && lane <= STRIP_W && xr >= 0 && xr < nx;
+    const int yr = tl.y0 - 1 + w;
+    int y = yr;
+    if (L.periodic_y) y = yr < 0 ? yr + ny : (yr >= ny ? yr - ny : yr);
+    const bool row = yr >= -1 && yr <= ny && w <= rows + 1;
+    const bool own = own_col && w >= 1 && w <= rows && yr < ny;
+    const uint32_t node = (uint32_t)(L.node0 + y * pitch + x);
+    const uint8_t lc = (row && col) ? ((const GG_GLOBAL uint8_t *)L.link)[node] : NOT_FLUID;
+
+    // step t on this row
+    Flux fx;
+    T pf[9], pg[5], inf[9], ing[5];
+    if (lc != NOT_FLUID) {
+      T f[9], g[5];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = P::ld(src.at(i, node));
+#pragma unroll
+      for (int i = 0; i < 5; ++i) g[i] = P::ld(src.at(9 + i, node));
+      collide_node<T>(L, x, y, lc, seg, ph1, f, g, pf, pg, inf, ing, fx, own);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) pf[i] = inf[i] = T(0);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) pg[i] = ing[i] = T(0);
+    }
+    const T zf1 = from_left(pf[1]), zf3 = from_right(pf[3]);
+    const T zg1 = from_left(pg[1]), zg3 = from_right(pg[3]);
+    lds_up[w][0][lane] = pf[2];
+    lds_up[w][1][lane] = from_left(pf[5]);
+    lds_up[w][2][lane] = from_right(pf[6]);
+    lds_up[w][3][lane] = pg[2];
+    lds_dn[w][0][lane] = pf[4];
+    lds_dn[w][1][lane] = from_right(pf[7]);
+    lds_dn[w][2][lane] = from_left(pf[8]);
+    lds_dn[w][3][lane] = pg[4];
+    __syncthreads();
+
+    // step t + 1 on the owned rows
+    if (own && lc != NOT_FLUID) {
+      T sf[9], sg[5];
+      sf[0] = P::rt(pf[0]);
+      sg[0] = P::rt(pg[0]);
+      sf[1] = P::rt(src_solid(lc, 1) ? inf[1] : zf1);
+      sf[3] = P::rt(src_solid(lc, 3) ? inf[3] : zf3);
+      sg[1] = P::rt(src_solid(lc, 1) ? ing[1] : zg1);
+      sg[3] = P::rt(src_solid(lc, 3) ? ing[3] : zg3);
+      sf[2] = P::rt(src_solid(lc, 2) ? inf[2] : lds_up[w - 1][0][lane]);
+      sf[5] = P::rt(src_solid(lc, 5) ? inf[5] : lds_up[w - 1][1][lane]);
+      sf[6] = P::rt(src_solid(lc, 6) ? inf[6] : lds_up[w - 1][2][lane]);
+      sg[2] = P::rt(src_solid(lc, 2) ? ing[2] : lds_up[w - 1][3][lane]);
+      sf[4] = P::rt(src_solid(lc, 4) ? inf[4] : lds_dn[w + 1][0][lane]);
+      sf[7] = P::rt(src_solid(lc, 7) ? inf[7] : lds_dn[w + 1][1][lane]);
+      sf[8] = P::rt(src_solid(lc, 8) ? inf[8] : lds_dn[w + 1][2][lane]);
+      sg[4] = P::rt(src_solid(lc, 4) ? ing[4] : lds_dn[w + 1][3][lane]);
+      if (seg)
+        second_step<S, true>(L, dst, x, y, lc, ph2, sf, sg, fx);
+      else
+        second_step<S, false>(L, dst, x, y, lc, ph2, sf, sg, fx);
+    }
+    if (seg) fx.flush((double *)L.flux);
+    __syncthreads();  // the LDS rows are reused by the next tile
+  }
+}
+
+}  // namespace
+
+hipError_t launch_step2(gg_storage s, bool seg, const LatDesc *d, const Tile *strips, int n_strips,
+                        int dir, int dt, hipStream_t st, int persist) {
+  if (n_strips <= 0) return hipSuccess;
+  const int nblk = (n_strips + 3) / 4;
+  const int per_xcd = (nblk + 7) / 8;
+  int grid = 8 * per_xcd;
+  if (persist > 0) grid = std::min(grid, (persist + 7) / 8 * 8);
+#define GG_LAUNCH2(TYPE, SEGV) \
+  k_step2<TYPE, SEGV><<<grid, 256, 0, st>>>(d, strips, n_strips, per_xcd, dir, dt)
+  switch (s) {
+    case GG_F64: if (seg) GG_LAUNCH2(double, true); else GG_LAUNCH2(double, false); break;
+    case GG_F32: if (seg) GG_LAUNCH2(float, true); else GG_LAUNCH2(float, false); break;
+    case GG_F16_SHIFTED: if (seg) GG_LAUNCH2(__half, true); else GG_LAUNCH2(__half, false); break;
+  }
+#undef GG_LAUNCH2
+  return hipGetLastError();
+}
+
+hipError_t launch_tile2(gg_storage s, bool seg, int rows, const LatDesc *d, const Tile *tiles,
+                        int n_tiles, int dir, int dt, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  const int per_xcd = (n_tiles + 7) / 8;
+  const int grid = 8 * per_xcd;
+#define GG_LAUNCHT(TYPE, SEGV, RV) \
+  k_tile2<TYPE, SEGV, RV><<<grid, ((RV) + 2) * 64, 0, st>>>(d, tiles, n_tiles, per_xcd, dir, dt)
+#define GG_LAUNCHT_S(TYPE)                           \
+  do {                                               \
+    if (seg && rows <= 2) GG_LAUNCHT(TYPE, true, 2); \
+    else if (seg && rows <= 6) GG_LAUNCHT(TYPE, true, 6); \
+    else if (seg) GG_LAUNCHT(TYPE, true, 14);        \
+    else if (rows <= 6) GG_LAUNCHT(TYPE, false, 6);  \
+    else GG_LAUNCHT(TYPE, false, 14);                \
+  } while (0)
+  switch (s) {
+    case GG_F64: GG_LAUNCHT_S(double); break;
+    case GG_F32: GG_LAUNCHT_S(float); break;
+    case GG_F16_SHIFTED: GG_LAUNCHT_S(__half); break;
+  }
+#undef GG_LAUNCHT_S
+#undef GG_LAUNCHT
+  return hipGetLastError();
+}
+
+}  // namespace gg

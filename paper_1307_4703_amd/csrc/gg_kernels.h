@@ -13,6 +13,20 @@ namespace gg {
 hipError_t launch_step(gg_storage s, int block, bool odd, const LatDesc *d, const Tile *tiles,
                        int n_tiles, int tx_shift, int dt, hipStream_t st, int persist = 0);
 
+// Two steps in one pass (t even, natural order in): strips of 62 columns x
+// (flags >> 8) rows, four per 256-thread work-group; seg selects the kernel
+// for strips with segment links; dir 0 reads the plane set pop and writes
+// pop_b, dir 1 the reverse; dt as for launch_step.
+hipError_t launch_step2(gg_storage s, bool seg, const LatDesc *d, const Tile *strips, int n_strips,
+                        int dir, int dt, hipStream_t st, int persist = 0);
+
+// The same two steps row-parallel: one work-group of rows + 2 wavefronts
+// per tile of 62 columns x (flags >> 8) rows, rows 2, 6 or 14; seg selects
+// the kernel that also carries the boundary rules (applied to the tiles
+// whose segment bit is set).
+hipError_t launch_tile2(gg_storage s, bool seg, int rows, const LatDesc *d, const Tile *tiles,
+                        int n_tiles, int dir, int dt, hipStream_t st);
+
 // Auxiliary kernels: 256-thread work-groups over one lattice's tiles.
 hipError_t launch_init(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                        int tx_shift, const double *rho, const double *ux,

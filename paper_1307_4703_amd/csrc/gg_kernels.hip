@@ -21,127 +21,9 @@
 
 #include "gg_device.h"
 #include "gg_kernels.h"
+#include "gg_node.h"
 
 namespace gg {
-
-using CDesc = const GG_CONST LatDesc;
-
-struct PhaseNow {
-  uint32_t open;
-  const GG_CONST double *cin;
-};
-
-// Valve phase in force during step t (fixed at the start of the step).
-__device__ __forceinline__ PhaseNow phase_at(CDesc &L, int64_t t) {
-  if (L.n_phases == 0) return {0xFFFFFFFFu, L.seg_cin};
-  int64_t tau = (t - L.t_origin) % L.period;
-  if (tau < 0) tau += L.period;
-  int k = 0;
-  while (k + 1 < L.n_phases && L.phase_start[k + 1] <= tau) ++k;
-  return {L.phase_open[k], L.phase_cin[k]};
-}
-
-// Sum over the 64 lanes of a wavefront; every lane must be active.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  return v;
-}
-
-// Add per-lane boundary fluxes (up to two segments per lane, seg < 0 for
-// none) into the FP64 accumulators: one atomic per segment and wavefront.
-__device__ void flush_flux(double *flux, int sa, double ma, double ca, int sb,
-                           double mb, double cb) {
-#pragma unroll
-  for (int slot = 0; slot < 2; ++slot) {
-    const int seg = slot ? sb : sa;
-    const double dm = slot ? mb : ma;
-    const double dc = slot ? cb : ca;
-    unsigned long long pend = __ballot(seg >= 0);
-    while (pend) {
-      const int lead = __ffsll(pend) - 1;
-      const int s = __shfl(seg, lead);
-      const bool mine = seg == s;
-      const double a = wave_sum(mine ? dm : 0.0);
-      const double b = wave_sum(mine ? dc : 0.0);
-      if ((int)__lane_id() == lead) {
-        atomicAdd(flux + 2 * s, a);
-        atomicAdd(flux + 2 * s + 1, b);
-      }
-      pend &= ~__ballot(mine);
-    }
-  }
-}
-
-// Element offset of x + e_k for k = 0..8: wrapped along periodic axes,
-// otherwise possibly in the padding around the lattice (always addressable).
-struct Neigh {
-  uint32_t idx[9];
-  __device__ __forceinline__ Neigh(CDesc &L, int x, int y) {
-    const int xm = (x == 0 && L.periodic_x) ? L.nx - 1 : x - 1;
-    const int xp = (x == L.nx - 1 && L.periodic_x) ? 0 : x + 1;
-    const int ym = (y == 0 && L.periodic_y) ? L.ny - 1 : y - 1;
-    const int yp = (y == L.ny - 1 && L.periodic_y) ? 0 : y + 1;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const int xx = EX[k] > 0 ? xp : (EX[k] < 0 ? xm : x);
-      const int yy = EY[k] > 0 ? yp : (EY[k] < 0 ? ym : y);
-      idx[k] = (uint32_t)(L.node0 + yy * L.pitch + xx);
-    }
-  }
-};
-
-// Uniform base pointers of the 14 population planes. Elements are reached
-// through a 32-bit byte offset (every plane is smaller than 4 GiB), which
-// maps onto the scalar-base + vector-offset form of global memory access.
-template <class W> struct Planes {
-  GG_GLOBAL W *p[NPOP];
-  __device__ __forceinline__ Planes(CDesc &L) {
-    GG_GLOBAL W *base = (GG_GLOBAL W *)L.pop;
-#pragma unroll
-    for (int i = 0; i < NPOP; ++i) p[i] = base + (int64_t)i * L.plane;
-  }
-  __device__ __forceinline__ GG_GLOBAL W *at(int i, uint32_t idx) const {
-    return (GG_GLOBAL W *)((GG_GLOBAL char *)p[i] + idx * (uint32_t)sizeof(W));
-  }
-};
-
-// Deviations df_i(x,t), dg_i(x,t) in natural order for step parity ODD.
-template <class S, bool ODD>
-__device__ __forceinline__ void load_state(const Planes<typename Pop<S>::W> &pl, uint32_t node,
-                                           uint8_t lc, const Neigh &nb,
-                                           typename Pop<S>::T *f, typename Pop<S>::T *g) {
-  using P = Pop<S>;
-  if (!ODD) {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = P::ld(pl.at(i, node));
-#pragma unroll
-    for (int i = 0; i < 5; ++i) g[i] = P::ld(pl.at(9 + i, node));
-  } else {
-    // streamed in from x - e_i, stored by that node in slot opp(i)
-    f[0] = P::ld(pl.at(0, node));
-#pragma unroll
-    for (int i = 1; i < 9; ++i) f[i] = P::ld(pl.at(OPP[i], nb.idx[OPP[i]]));
-    g[0] = P::ld(pl.at(9, node));
-#pragma unroll
-    for (int i = 1; i < 5; ++i) g[i] = P::ld(pl.at(9 + OPP[i], nb.idx[OPP[i]]));
-    if (lc != 0) {
-      // x - e_i not fluid: this node stored the boundary value in its own slot i
-#pragma unroll
-      for (int i = 1; i < 9; ++i)
-        if ((lc >> (OPP[i] - 1)) & 1) f[i] = P::ld(pl.at(i, node));
-#pragma unroll
-      for (int i = 1; i < 5; ++i)
-        if ((lc >> (OPP[i] - 1)) & 1) g[i] = P::ld(pl.at(9 + i, node));
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // The fused coupled step.
@@ -175,8 +57,7 @@ __device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
   const uint32_t node = (uint32_t)(L.node0 + y * pitch + x);
   const uint8_t lc = (x < nx && y < ny) ? ((const GG_GLOBAL uint8_t *)L.link)[node] : NOT_FLUID;
 
-  int sa = -1, sb = -1;
-  double ma = 0.0, ca = 0.0, mb = 0.0, cb = 0.0;
+  Flux fx;
 
   if (lc != NOT_FLUID) {
     const Planes<W> pl(L);
@@ -184,113 +65,8 @@ __device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
     T f[9], g[5];  // deviations from rest, df_i and dg_i
     load_state<S, ODD>(pl, node, lc, nb, f, g);
 
-    // Moments of f, paper Eq. 7 (sum over i = 0..8): rho = rho0 + sum df_i;
-    // the rest part w_i rho0 carries no momentum.
-    const T rho0 = (T)L.rho0;
-    const T drho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-    const T rho = rho0 + drho;
-    const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-    const T jy = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
-    const T inv_rho = T(1) / rho;
-    const T ux = jx * inv_rho, uy = jy * inv_rho;
-    const T usq = ux * ux + uy * uy;
-
-    // BGK relaxation of f toward the quadratic equilibrium, Eqs. 4-6, for
-    // the deviations: f^eq_i - w_i rho0 = w_i (drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)).
-    const T om_f = (T)L.omega_f;
-    T pf[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const T eu = (T)EX[i] * ux + (T)EY[i] * uy;
-      const T dfeq = (T)WF[i] * (drho + rho * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * usq));
-      pf[i] = f[i] + om_f * (dfeq - f[i]);
-    }
-
-    // Compound: linear equilibrium with this node's u (Eq. 9), BGK (Eq. 8),
-    // source R - kC of Eq. 2 distributed with the lattice weights. With
-    // C = C_s + dC: g^eq_i - w_i C_s = w_i (dC + C e.u / cs2).
-    const T cs = (T)L.c_shift;
-    const T dC = g[0] + g[1] + g[2] + g[3] + g[4];
-    const T C = cs + dC;
-    // The rest weight is 1 - 4 w_axis in the compute type, so the five
-    // weights sum to one exactly: with both weights rounded on their own
-    // (1/3 and 1/6 in FP32 sum to 1 + 3e-8) every collision would create
-    // solute in proportion to C.
-    const T wga = (T)L.wg_axis;
-    const T wg[5] = {T(1) - T(4) * wga, wga, wga, wga, wga};
-    const T ics = (T)L.inv_cs2g;
-    T src = -(T)L.k_decay * C;
-    if (L.has_source) {
-      const int rx = x - L.r_x0, ry = y - L.r_y0;
-      if (rx >= 0 && rx < L.r_w && ry >= 0 && ry < L.r_h)
-        src += (T)((const GG_GLOBAL double *)L.R)[ry * L.r_w + rx];
-    }
-    const T om_g = (T)L.omega_g;
-    T pg[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      const T eu = (T)EX[i] * ux + (T)EY[i] * uy;
-      const T dgeq = wg[i] * (dC + C * eu * ics);
-      pg[i] = g[i] + om_g * (dgeq - g[i]) + wg[i] * src;
-    }
-
-    // Value arriving at x along direction j when x - e_j is not fluid: the
-    // bounced population f*(x, opp j) for a wall or closed valve; open
-    // segments overwrite below. (For fluid x - e_j the same slot carries
-    // f*(x, opp j) to that neighbour.)
-    T in_f[9], in_g[5];
-#pragma unroll
-    for (int j = 0; j < 9; ++j) in_f[j] = pf[OPP[j]];
-#pragma unroll
-    for (int j = 0; j < 5; ++j) in_g[j] = pg[OPP[j]];
-
-    if (seg_tile && lc != 0) {
-      // (every rule below is written for the deviations; w_j = w_opp(j), so
-      // the rest parts cancel except where noted)
-#pragma unroll
-      for (int j = 1; j < 9; ++j) {
-        if (!((lc >> (OPP[j] - 1)) & 1)) continue;  // x - e_j is fluid
-        int sx = x - EX[j], sy = y - EY[j];
-        bool inside = true;
-        if (sx < 0 || sx >= nx) {
-          if (L.periodic_x) sx = (sx + nx) % nx; else inside = false;
-        }
-        if (sy < 0 || sy >= ny) {
-          if (L.periodic_y) sy = (sy + ny) % ny; else inside = false;
-        }
-        const int code = inside ? (int)((const GG_GLOBAL uint8_t *)L.mask)[L.node0 + sy * pitch + sx]
-                                : GG_MASK_WALL;
-        if (code < GG_FIRST_SEGMENT) continue;
-        const int s = code - GG_FIRST_SEGMENT;
-        if (!((ph.open >> s) & 1u)) continue;  // closed valve: a wall
-        T vf, vg = T(0);
-        if (L.seg_kind[s] == GG_SEG_INLET) {
-          // moving-wall bounce-back, wall velocity -n u(s) with a parabolic
-          // profile across the segment; anti-bounce-back for C_in
-          const T coord = L.seg_nx[s] != 0 ? (T)y : (T)x;
-          const T us = (T)(4.0 * L.seg_umax[s]) * (coord - (T)L.seg_s0[s]) *
-                       ((T)L.seg_s1[s] - coord) * (T)L.seg_inv_w2[s];
-          const T en = (T)(EX[j] * L.seg_nx[s] + EY[j] * L.seg_ny[s]);
-          vf = pf[OPP[j]] - T(6) * (T)WF[j] * rho0 * en * us;
-          if (j < 5) vg = -pg[OPP[j]] + T(2) * wg[j] * ((T)ph.cin[s] - cs);
-        } else {
-          // outflow at the reference density with the node's own u;
-          // the compound leaves with zero gradient
-          const T eu = (T)EX[j] * ux + (T)EY[j] * uy;
-          vf = -pf[OPP[j]] + T(2) * (T)WF[j] * rho0 * (T(4.5) * eu * eu - T(1.5) * usq);
-          if (j < 5) vg = pg[j];
-        }
-        const double dm = (double)(vf - pf[OPP[j]]);
-        const double dc = (j < 5) ? (double)(vg - pg[OPP[j]]) : 0.0;
-        in_f[j] = vf;
-        if (j < 5) in_g[j] = vg;
-        if (sa < 0 || sa == s) {
-          sa = s; ma += dm; ca += dc;
-        } else {
-          sb = s; mb += dm; cb += dc;
-        }
-      }
-    }
+    T pf[9], pg[5], in_f[9], in_g[5];
+    collide_node<T>(L, x, y, lc, seg_tile, ph, f, g, pf, pg, in_f, in_g, fx, true);
 
     if (!ODD) {
 #pragma unroll
@@ -319,7 +95,7 @@ __device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
     }
   }
 
-  if (seg_tile) flush_flux((double *)L.flux, sa, ma, ca, sb, mb, cb);
+  if (seg_tile) fx.flush((double *)L.flux);
 }
 
 // The fused step over a tile list. Work-groups are dealt to the 8 XCDs

@@ -37,6 +37,7 @@ struct gg_lattice {
   int r_box[4] = {0, 0, 0, 0};
 
   void *d_pop = nullptr;
+  void *d_pop_b = nullptr;  // second plane set of the two-step pass
   uint8_t *d_link = nullptr, *d_mask = nullptr, *d_region = nullptr;
   double *d_R = nullptr;
   int64_t *d_t = nullptr;
@@ -48,6 +49,19 @@ struct gg_lattice {
   gg::Tile *d_aux_tiles = nullptr;
   int n_aux_tiles = 0;
   int graph_chunk = 64;
+  // two-step pass: fuse = 2, 3, 4 advance pairs of steps in one pass over
+  // memory (walking strips of 62 columns x strip_h rows, or row-parallel
+  // tiles of strip_h rows with the boundary kernel apart or in one kernel);
+  // fuse = 1 keeps to single steps
+  int fuse = 3, strip_h = 6;
+  gg::Tile *d_strips = nullptr;      // strips without segment links
+  int n_strips = 0;
+  gg::Tile *d_seg_strips = nullptr;  // strips with segment links (2 rows each)
+  int n_seg_strips = 0;
+  // the segment strips run beside the others: forked onto a side stream and
+  // joined back every pass (also inside captured graphs)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
 };

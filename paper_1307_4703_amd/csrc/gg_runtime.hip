@@ -56,11 +56,15 @@ void gg_free_device(gg_lattice *L) {
   if (L->graph) (void)hipGraphDestroy(L->graph);
   L->graph_exec = nullptr;
   L->graph = nullptr;
-  void *ptrs[] = {L->d_pop, L->d_link, L->d_mask, L->d_region, L->d_R, L->d_t,
-                  L->d_flux, L->d_acc, L->d_desc, L->d_tiles, L->d_aux_tiles};
+  void *ptrs[] = {L->d_pop, L->d_pop_b, L->d_link, L->d_mask, L->d_region, L->d_R, L->d_t,
+                  L->d_flux, L->d_acc, L->d_desc, L->d_tiles, L->d_aux_tiles, L->d_strips,
+                  L->d_seg_strips};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (L->cap_stream) (void)hipStreamDestroy(L->cap_stream);
+  if (L->side) (void)hipStreamDestroy(L->side);
+  if (L->ev_fork) (void)hipEventDestroy(L->ev_fork);
+  if (L->ev_join) (void)hipEventDestroy(L->ev_join);
 }
 
 gg_status gg_upload_desc(gg_lattice *L) {
@@ -74,6 +78,7 @@ gg_status gg_upload_desc(gg_lattice *L) {
   h.periodic_y = L->p.periodic_y != 0;
   h.plane = L->plane;
   h.pop = L->d_pop;
+  h.pop_b = L->d_pop_b;
   h.link = L->d_link;
   h.mask = L->d_mask;
   h.region = L->d_region;
@@ -138,6 +143,46 @@ static void build_tiles(const gg_lattice *L, int tx, int ty, int inst,
     }
 }
 
+// Strips of the two-step pass: 62 owned columns x h rows holding at least
+// one fluid node, listed band by band (rows y0 .. y0 + h - 1) from left to
+// right: horizontally adjacent strips store into the same cache lines at
+// their common edge every row, so they go to the same XCD (a contiguous run
+// of the list) and run side by side in one work-group. With split, a band
+// piece with a link to a boundary segment is cut into 2-row strips and
+// those with segment links go to the second list; otherwise it stays whole
+// in the first. Flags: strip height << 8 | segment bit.
+static void build_strips(const gg_lattice *L, int h, int inst, bool split, std::vector<Tile> &main,
+                         std::vector<Tile> &seg) {
+  auto scan = [&](int x0, int y0, int rows, bool &any, bool &sg) {
+    any = sg = false;
+    for (int y = y0; y < std::min(y0 + rows, L->ny); ++y)
+      for (int x = x0; x < std::min(x0 + 62, L->nx); ++x) {
+        if (L->link[L->nid(x, y)] == NOT_FLUID) continue;
+        any = true;
+        if (L->touches_seg[(size_t)y * L->nx + x]) sg = true;
+      }
+  };
+  for (int y0 = 0; y0 < L->ny; y0 += h)
+    for (int x0 = 0; x0 < L->nx; x0 += 62) {
+      bool any, sg;
+      scan(x0, y0, h, any, sg);
+      if (!any) continue;
+      if (!sg || !split) {
+        main.push_back(Tile{inst, x0, y0, (h << 8) | (sg ? TILE_TOUCHES_SEGMENT : 0)});
+        continue;
+      }
+      for (int yy = y0; yy < std::min(y0 + h, L->ny); yy += 2) {
+        const int rows = std::min(2, y0 + h - yy);
+        scan(x0, yy, rows, any, sg);
+        if (!any) continue;
+        if (sg)
+          seg.push_back(Tile{inst, x0, yy, (rows << 8) | TILE_TOUCHES_SEGMENT});
+        else
+          main.push_back(Tile{inst, x0, yy, rows << 8});
+      }
+    }
+}
+
 gg_status gg_rebuild_tiles(gg_lattice *L) {
   std::vector<Tile> t;
   build_tiles(L, L->tile_x, L->tile_y, 0, t);
@@ -147,6 +192,21 @@ gg_status gg_rebuild_tiles(gg_lattice *L) {
   if (!t.empty()) {
     GG_HIP(hipMalloc(&L->d_tiles, t.size() * sizeof(Tile)));
     GG_HIP(hipMemcpy(L->d_tiles, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  }
+  std::vector<Tile> sv, ss;
+  build_strips(L, L->strip_h, 0, L->fuse != 4, sv, ss);
+  if (L->d_strips) (void)hipFree(L->d_strips);
+  if (L->d_seg_strips) (void)hipFree(L->d_seg_strips);
+  L->d_strips = L->d_seg_strips = nullptr;
+  L->n_strips = (int)sv.size();
+  L->n_seg_strips = (int)ss.size();
+  if (!sv.empty()) {
+    GG_HIP(hipMalloc(&L->d_strips, sv.size() * sizeof(Tile)));
+    GG_HIP(hipMemcpy(L->d_strips, sv.data(), sv.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  }
+  if (!ss.empty()) {
+    GG_HIP(hipMalloc(&L->d_seg_strips, ss.size() * sizeof(Tile)));
+    GG_HIP(hipMemcpy(L->d_seg_strips, ss.data(), ss.size() * sizeof(Tile), hipMemcpyHostToDevice));
   }
   if (L->graph_exec) (void)hipGraphExecDestroy(L->graph_exec);
   if (L->graph) (void)hipGraphDestroy(L->graph);
@@ -266,7 +326,7 @@ gg_status gg_create(const uint8_t *mask, int32_t nx, int32_t ny, const gg_params
     return GG_OK;
   };
   const size_t pop_bytes = (size_t)NPOP * L->plane * esize;
-  if ((st = alloc(&L->d_pop, pop_bytes)) != GG_OK ||
+  if ((st = alloc(&L->d_pop, pop_bytes)) != GG_OK || (st = alloc(&L->d_pop_b, pop_bytes)) != GG_OK ||
       (st = alloc((void **)&L->d_link, (size_t)plane_elems)) != GG_OK ||
       (st = alloc((void **)&L->d_mask, (size_t)plane_elems)) != GG_OK ||
       (st = alloc((void **)&L->d_t, sizeof(int64_t))) != GG_OK ||
@@ -284,9 +344,13 @@ gg_status gg_create(const uint8_t *mask, int32_t nx, int32_t ny, const gg_params
   if (e == hipSuccess) e = hipMemcpy(L->d_link, L->link.data(), L->link.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(L->d_mask, mpitch.data(), mpitch.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(L->d_pop, 0, pop_bytes);
+  if (e == hipSuccess) e = hipMemset(L->d_pop_b, 0, pop_bytes);
   if (e == hipSuccess) e = hipMemset(L->d_t, 0, sizeof(int64_t));
   if (e == hipSuccess) e = hipMemset(L->d_flux, 0, 2 * GG_MAX_SEGMENTS * sizeof(double));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&L->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&L->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&L->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&L->ev_join, hipEventDisableTiming);
   if (e != hipSuccess) {
     gg_status s = fail(GG_ERR_HIP, std::string("lattice set-up: ") + hipGetErrorString(e));
     gg_free_device(L);
@@ -483,14 +547,46 @@ static gg_status check_segments(gg_lattice *L) {
 }
 
 // Launch `n` step kernels on `st` for a lattice whose device counter reads
-// t0 (host mirror), then advance the counter.
-static hipError_t launch_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t st) {
-  const int block = L->tile_x * L->tile_y;
-  const int txs = ilog2(L->tile_x);
+// t0 (host mirror), then advance the counter. With the two-step pass on,
+// t0 even and n a multiple of 4, the steps go in n/2 passes that alternate
+// between the two plane sets and end in the first one.
+// One two-step pass: the segment strips on the side stream, forked from and
+// joined back to st (inside a capture this becomes two graph branches).
+static hipError_t launch_pass(gg_lattice *L, int dir, int dt, hipStream_t st) {
   hipError_t e = hipSuccess;
-  for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt)
-    e = launch_step(L->storage, block, ((t0 + dt) & 1) != 0, L->d_desc, L->d_tiles,
-                    L->n_tiles, txs, (int)dt, st);
+  const bool fork = L->n_seg_strips > 0 && L->n_strips > 0;
+  if (L->fuse == 4)  // one kernel with the boundary rules for every tile
+    return launch_tile2(L->storage, true, L->strip_h, L->d_desc, L->d_strips, L->n_strips, dir, dt,
+                        st);
+  auto run = [&](bool seg, const Tile *list, int n, hipStream_t s) {
+    return L->fuse == 3 ? launch_tile2(L->storage, seg, L->strip_h, L->d_desc, list, n, dir, dt, s)
+                        : launch_step2(L->storage, seg, L->d_desc, list, n, dir, dt, s);
+  };
+  if (fork) {
+    e = hipEventRecord(L->ev_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(L->side, L->ev_fork, 0);
+    if (e == hipSuccess) e = run(true, L->d_seg_strips, L->n_seg_strips, L->side);
+    if (e == hipSuccess) e = hipEventRecord(L->ev_join, L->side);
+  } else if (L->n_seg_strips > 0) {
+    e = run(true, L->d_seg_strips, L->n_seg_strips, st);
+  }
+  if (e == hipSuccess) e = run(false, L->d_strips, L->n_strips, st);
+  if (fork && e == hipSuccess) e = hipStreamWaitEvent(st, L->ev_join, 0);
+  return e;
+}
+
+static hipError_t launch_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (L->fuse >= 2 && !(t0 & 1) && n % 4 == 0) {
+    for (int64_t k = 0; k < n / 2 && e == hipSuccess; ++k)
+      e = launch_pass(L, (int)(k & 1), (int)(2 * k), st);
+  } else {
+    const int block = L->tile_x * L->tile_y;
+    const int txs = ilog2(L->tile_x);
+    for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt)
+      e = launch_step(L->storage, block, ((t0 + dt) & 1) != 0, L->d_desc, L->d_tiles,
+                      L->n_tiles, txs, (int)dt, st);
+  }
   if (e == hipSuccess) e = launch_advance(L->d_desc, 1, n, st);
   return e;
 }
@@ -501,14 +597,15 @@ gg_status gg_step(gg_lattice *L, int64_t n) {
   gg_status st = check_segments(L);
   if (st != GG_OK) return st;
   int64_t left = n;
-  const int K = L->graph_chunk;  // even, so every replay starts on an even step
-  if (K > 0 && (L->t & 1) && left >= K + 1) {
-    // graphs are captured for an even starting step
+  // graph chunk: even (a multiple of 4 with the two-step pass), so every
+  // replay starts on an even step and leaves the state in the first plane set
+  const int K = L->graph_chunk;
+  if ((L->t & 1) && left > 0) {
     GG_HIP(launch_steps(L, L->t, 1, L->stream));
     L->t += 1;
     left -= 1;
   }
-  if (K > 0 && !(L->t & 1) && left >= K) {
+  if (K > 0 && left >= K) {
     if (!L->graph_exec) {
       GG_HIP(hipStreamBeginCapture(L->cap_stream, hipStreamCaptureModeThreadLocal));
       hipError_t e = launch_steps(L, 0, K, L->cap_stream);
@@ -527,6 +624,12 @@ gg_status gg_step(gg_lattice *L, int64_t n) {
       left -= K;
       L->t += K;
     }
+  }
+  const int64_t quads = L->fuse >= 2 ? left / 4 * 4 : 0;
+  if (quads > 0) {
+    GG_HIP(launch_steps(L, L->t, quads, L->stream));
+    L->t += quads;
+    left -= quads;
   }
   if (left > 0) {
     GG_HIP(launch_steps(L, L->t, left, L->stream));
@@ -685,7 +788,39 @@ gg_status gg_set_launch(gg_lattice *L, int32_t tile_x, int32_t tile_y, int32_t g
   GG_HIP(hipStreamSynchronize(L->stream));
   L->tile_x = tile_x;
   L->tile_y = tile_y;
-  L->graph_chunk = (graph_chunk + 1) / 2 * 2;  // even: replays keep the parity
+  // even (a multiple of 4 with the two-step pass): replays keep the parity
+  const int q = L->fuse >= 2 ? 4 : 2;
+  L->graph_chunk = (graph_chunk + q - 1) / q * q;
+  return gg_rebuild_tiles(L);
+}
+
+gg_status gg_set_two_step(gg_lattice *L, int32_t fuse, int32_t strip_h) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (fuse < 1 || fuse > 4) return fail(GG_ERR_ARG, "fuse must be 1, 2, 3 or 4");
+  if (fuse == 2 && (strip_h < 1 || strip_h > 4096))
+    return fail(GG_ERR_ARG, "strips walk 1..4096 rows");
+  if (fuse >= 3 && strip_h != 6 && strip_h != 14)
+    return fail(GG_ERR_ARG, "row-parallel tiles have 6 or 14 rows");
+  GG_HIP(hipStreamSynchronize(L->stream));
+  if (fuse >= 2 && !L->d_pop_b) {
+    const size_t pop_bytes = (size_t)NPOP * L->plane * L->esize;
+    hipError_t e = hipMalloc(&L->d_pop_b, pop_bytes);
+    if (e != hipSuccess) {
+      L->d_pop_b = nullptr;
+      return fail(GG_ERR_OOM, std::string("second plane set: ") + hipGetErrorString(e));
+    }
+    GG_HIP(hipMemset(L->d_pop_b, 0, pop_bytes));
+  }
+  if (fuse == 1 && L->d_pop_b) {
+    GG_HIP(hipFree(L->d_pop_b));
+    L->d_pop_b = nullptr;
+  }
+  L->fuse = fuse;
+  if (fuse >= 2) L->strip_h = strip_h;
+  const int q = fuse >= 2 ? 4 : 2;
+  L->graph_chunk = (L->graph_chunk + q - 1) / q * q;
+  gg_status st = gg_upload_desc(L);
+  if (st != GG_OK) return st;
   return gg_rebuild_tiles(L);
 }
 
@@ -1021,6 +1156,38 @@ gg_status gg_step_timed(gg_lattice *L, int64_t n, double *ms_even, double *ms_od
   if (e != hipSuccess) return fail(GG_ERR_HIP, std::string("timed steps: ") + hipGetErrorString(e));
   if (ms_even) *ms_even = cnt[0] ? tot[0] / (double)cnt[0] : 0.0;
   if (ms_odd) *ms_odd = cnt[1] ? tot[1] / (double)cnt[1] : 0.0;
+  return GG_OK;
+}
+
+gg_status gg_step2_timed(gg_lattice *L, int64_t n_pairs, double *ms_pass) {
+  if (!L || !ms_pass) return fail(GG_ERR_ARG, "NULL argument");
+  if (n_pairs < 1) return fail(GG_ERR_ARG, "n_pairs must be positive");
+  if (L->fuse < 2) return fail(GG_ERR_STATE, "the two-step pass is off");
+  if (L->t & 1) return fail(GG_ERR_STATE, "the two-step pass starts on an even step");
+  gg_status st = check_segments(L);
+  if (st != GG_OK) return st;
+  const int64_t n = 2 * n_pairs;  // passes, even: the state ends in the first plane set
+  std::vector<hipEvent_t> ev(2 * (size_t)n, nullptr);
+  hipError_t e = hipSuccess;
+  for (size_t k = 0; k < ev.size() && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
+  for (int64_t k = 0; k < n && e == hipSuccess; ++k) {
+    e = hipEventRecord(ev[2 * k], L->stream);
+    if (e == hipSuccess) e = launch_pass(L, (int)(k & 1), (int)(2 * k), L->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * k + 1], L->stream);
+  }
+  if (e == hipSuccess) e = launch_advance(L->d_desc, 1, 2 * n, L->stream);
+  if (e == hipSuccess) L->t += 2 * n;
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  double tot = 0.0;
+  for (int64_t k = 0; k < n && e == hipSuccess; ++k) {
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]);
+    tot += ms;
+  }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (e != hipSuccess) return fail(GG_ERR_HIP, std::string("timed passes: ") + hipGetErrorString(e));
+  *ms_pass = tot / (double)n;
   return GG_OK;
 }
 

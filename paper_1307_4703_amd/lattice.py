@@ -133,6 +133,20 @@ class Lattice:
     def set_launch(self, tile_x: int = 64, tile_y: int = 4, graph_chunk: int = 64) -> None:
         A.call("gg_set_launch", self._h, int(tile_x), int(tile_y), int(graph_chunk))
 
+    def set_two_step(self, fuse: int = 3, strip_h: int = 6) -> None:
+        """Two steps per pass over memory (fuse = 2: walking strips of
+        strip_h rows; 3, the default: row-parallel tiles of 6 or 14 rows with
+        the boundary kernel apart; 4: the same in one kernel) or single steps
+        (fuse = 1); include/gg.h, gg_set_two_step."""
+        A.call("gg_set_two_step", self._h, int(fuse), int(strip_h))
+
+    def step2_timed(self, n_pairs: int) -> float:
+        """Run 2 * n_pairs two-step passes between HIP events; mean duration
+        of one pass in milliseconds."""
+        a = ctypes.c_double()
+        A.call("gg_step2_timed", self._h, int(n_pairs), ctypes.byref(a))
+        return a.value
+
     def step_timed(self, n: int) -> Tuple[float, float]:
         """Advance n steps with every step kernel between HIP events; mean
         (even-step, odd-step) kernel durations in milliseconds."""

@@ -1,9 +1,11 @@
 """Launch-shape autotuner for single lattices and batches.
 
-Candidates are tile shapes (tile_x x tile_y nodes per work-group) and, for
-batches, persistent grid sizes. Each candidate is timed on the GPU with HIP
-events over a few graph-replayed steps (the lattices advance while being
-tuned, so tune before the run or on a copy). Results are cached in a JSON
+Candidates are tile shapes (tile_x x tile_y nodes per work-group) of the
+single steps, the forms of the two-step pass (walking strips, row-parallel
+tiles with the boundary rules in a kernel of their own or in the one
+kernel) and, for batches, persistent grid sizes. Each candidate is timed
+on the GPU with HIP events over a few graph-replayed steps (the lattices
+advance while being tuned, so tune before the run or on a copy). Results are cached in a JSON
 file keyed by the device name, storage type and the lattices' shapes and
 fluid counts.
 """
@@ -17,6 +19,8 @@ from typing import Dict, Iterable, List, Optional, Sequence, Tuple
 TILES: Tuple[Tuple[int, int], ...] = ((64, 4), (32, 8), (64, 2), (128, 2), (128, 1),
                                       (64, 8), (128, 4), (256, 1), (32, 4), (16, 8))
 PERSIST: Tuple[int, ...] = (0, 2048, 4096)
+# (fuse, rows) of gg_set_two_step; fuse 1 is the single-step path
+TWO_STEP: Tuple[Tuple[int, int], ...] = ((3, 6), (3, 14), (4, 6), (4, 14), (2, 8), (2, 16))
 
 
 def cache_path() -> str:
@@ -55,7 +59,7 @@ def _time(fn, steps: int) -> float:
     stream = torch.cuda.current_stream()
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
-    fn(2)  # capture graphs, warm caches
+    fn(4)  # capture graphs, warm caches
     torch.cuda.synchronize()
     a.record(stream)
     fn(steps)
@@ -65,23 +69,36 @@ def _time(fn, steps: int) -> float:
 
 
 def tune_lattice(lat, steps: int = 64, tiles: Iterable[Tuple[int, int]] = TILES,
-                 graph_chunk: int = 64, use_cache: bool = True,
-                 path: Optional[str] = None) -> Dict:
-    """Pick the tile shape with the shortest step time; applies it."""
+                 two_step: Iterable[Tuple[int, int]] = TWO_STEP, graph_chunk: int = 64,
+                 use_cache: bool = True, path: Optional[str] = None) -> Dict:
+    """Pick the single-step tile shape with the shortest step time, then the
+    fastest of single steps and the two-step forms; applies both. steps
+    should be a multiple of 4 (two-step passes come in pairs)."""
     path = path or cache_path()
-    key = _key([lat], "lattice")
+    key = _key([lat], "lattice2")
     if use_cache:
         hit = _load(path).get(key)
         if hit:
             lat.set_launch(hit["tile"][0], hit["tile"][1], graph_chunk)
+            lat.set_two_step(hit["fuse"], hit["rows"])
             return hit
     results: List[Dict] = []
+    lat.set_two_step(1)
     for t in tiles:
         lat.set_launch(t[0], t[1], graph_chunk)
-        results.append({"tile": list(t), "ms_per_step": _time(lat.step, steps)})
+        results.append({"tile": list(t), "fuse": 1, "rows": 0,
+                        "ms_per_step": _time(lat.step, steps)})
     best = min(results, key=lambda r: r["ms_per_step"])
     lat.set_launch(best["tile"][0], best["tile"][1], graph_chunk)
-    out = {"tile": best["tile"], "ms_per_step": best["ms_per_step"], "all": results}
+    for fuse, rows in two_step:
+        lat.set_two_step(fuse, rows)
+        results.append({"tile": best["tile"], "fuse": fuse, "rows": rows,
+                        "ms_per_step": _time(lat.step, steps)})
+    best = min(results, key=lambda r: r["ms_per_step"])
+    lat.set_launch(best["tile"][0], best["tile"][1], graph_chunk)
+    lat.set_two_step(best["fuse"], best["rows"] or 6)
+    out = {"tile": best["tile"], "fuse": best["fuse"], "rows": best["rows"] or 6,
+           "ms_per_step": best["ms_per_step"], "all": results}
     _store(path, key, out)
     return out
 

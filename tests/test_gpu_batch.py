@@ -84,11 +84,13 @@ def test_autotuner_picks_and_caches(tmp_path):
     wl = W.gradient_generator(nx=512, ny=256, storage="f32")
     lat = Lattice.from_workload(wl)
     path = str(tmp_path / "tune.json")
-    res = tune.tune_lattice(lat, steps=16, tiles=((64, 4), (32, 8), (128, 2)), path=path)
+    res = tune.tune_lattice(lat, steps=16, tiles=((64, 4), (32, 8), (128, 2)),
+                            two_step=((3, 6), (4, 14)), path=path)
     assert tuple(res["tile"]) in ((64, 4), (32, 8), (128, 2))
-    assert len(res["all"]) == 3
+    assert (res["fuse"], res["rows"]) in ((1, 6), (3, 6), (4, 14))
+    assert len(res["all"]) == 5
     again = tune.tune_lattice(lat, steps=16, path=path)
-    assert again["tile"] == res["tile"]
+    assert again["tile"] == res["tile"] and again["fuse"] == res["fuse"]
     wls = _members()[:3]
     lats = _make(wls)
     rb = tune.tune_batch(lats, steps=8, tiles=((64, 4), (32, 8)), persist=(0, 256), path=path)

@@ -1,0 +1,118 @@
+"""Two-step pass: the state after stepping with passes of two steps (strips
+of 62 columns walked row by row, or row-parallel tiles exchanging through
+LDS; a one-node halo collided once more) must be bitwise the state the
+single-step kernels give, for every storage type, boundary kind,
+periodicity, strip height and schedule phase; boundary fluxes agree to
+FP64 rounding (their atomics add in another order)."""
+import numpy as np
+import pytest
+
+from paper_1307_4703_amd import workloads as W
+from tests.parity_util import log, make_lattice, seeded_init
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(wl, storage, seed, strip_h, chunk=0, R=None, mode=2):
+    init = seeded_init(wl, seed)
+    one = make_lattice(wl, storage, init, chunk=chunk)
+    one.set_two_step(1)
+    two = make_lattice(wl, storage, init, chunk=chunk)
+    two.set_two_step(mode, strip_h)
+    if R is not None:
+        one.set_source(R)
+        two.set_source(R)
+    return one, two
+
+
+def _same_state(one, two, steps):
+    fa, ga = one.populations()
+    fb, gb = two.populations()
+    assert one.info()["t"] == two.info()["t"] == steps
+    if not (np.array_equal(fa, fb) and np.array_equal(ga, gb)):
+        bad = np.argwhere(np.any(fa != fb, axis=0) | np.any(ga != gb, axis=0))
+        raise AssertionError(f"{len(bad)} nodes differ, first {bad[:5].tolist()}")
+    da, db = one.diagnostics(), two.diagnostics()
+    for k in ("mass_in", "mass_out", "solute_in", "solute_out"):
+        assert db[k] == pytest.approx(da[k], rel=1e-12, abs=1e-12), k
+
+
+MODES = [(2, 1), (2, 5), (2, 16), (3, 6), (3, 14), (4, 6), (4, 14)]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("mode,strip_h", MODES)
+def test_gradient_generator_valves(storage, mode, strip_h):
+    """Ragged 300x150 gradient generator, valves switching every 7 steps
+    (on odd and even steps, so inside and between the two steps of a pass)."""
+    wl = W.gradient_generator(nx=300, ny=150, half_period=7, storage=storage)
+    log(f"two-step vs single, {storage}, mode {mode}, rows {strip_h}")
+    one, two = _pair(wl, storage, 11, strip_h, mode=mode)
+    for n in (8, 3, 29):  # 40 steps: passes, an odd leftover, odd starts
+        one.step(n)
+        two.step(n)
+    _same_state(one, two, 40)
+
+
+@pytest.mark.parametrize("mode,strip_h", [(2, 7), (3, 6), (4, 14)])
+@pytest.mark.parametrize("periodic", [(True, False), (False, True), (True, True), (False, False)])
+def test_random_masks_periodic(periodic, mode, strip_h):
+    """Obstacles everywhere, 133x71 (not a multiple of the 62-column strip),
+    every combination of periodic axes."""
+    mask = W.random_mask(133, 71, seed=7, periodic=periodic)
+    wl = W.Workload("random", mask, tau_f=0.7, D=0.03, periodic=periodic)
+    log(f"two-step vs single, random mask, periodic {periodic}, mode {mode}")
+    one, two = _pair(wl, "f64", 3, strip_h, mode=mode)
+    one.step(36)
+    two.step(36)
+    _same_state(one, two, 36)
+
+
+@pytest.mark.parametrize("mode,strip_h", [(2, 4), (3, 14)])
+def test_narrow_periodic_lattice(mode, strip_h):
+    """A periodic lattice narrower than one strip: the halo lanes wrap onto
+    the strip's own columns."""
+    mask = np.zeros((24, 20), np.uint8)
+    mask[0, :] = 1
+    mask[-1, :] = 1
+    wl = W.Workload("narrow", mask, tau_f=0.9, D=0.02, periodic=(True, False))
+    one, two = _pair(wl, "f32", 4, strip_h, mode=mode)
+    one.step(24)
+    two.step(24)
+    _same_state(one, two, 24)
+
+
+@pytest.mark.parametrize("mode,strip_h", [(2, 16), (3, 6), (4, 6)])
+def test_source_decay_d2q4_and_graphs(mode, strip_h):
+    """w0 = 0 (D2Q4), decay, a source patch, graph-replayed passes."""
+    wl = W.gradient_generator(nx=300, ny=150, half_period=11, storage="f32", w0=0.0)
+    wl.k_decay = 1e-3
+    rng = np.random.default_rng(2)
+    R = np.zeros(wl.mask.shape)
+    R[60:90, 100:140] = 1e-3 * rng.random((30, 40))
+    one, two = _pair(wl, "f32", 5, strip_h, chunk=8, R=R, mode=mode)
+    one.step(50)
+    two.step(50)
+    _same_state(one, two, 50)
+
+
+@pytest.mark.parametrize("mode,strip_h", [(2, 16), (3, 14), (4, 6)])
+def test_straight_channel_inlet_outlet(mode, strip_h):
+    """Velocity inlet and pressure outlet on vertical segments (the strip's
+    halo lanes sit on the ghost columns)."""
+    wl = W.straight_channel(storage="f64")
+    one, two = _pair(wl, "f64", 0, strip_h, mode=mode)
+    one.step(120)
+    two.step(120)
+    _same_state(one, two, 120)
+
+
+@pytest.mark.parametrize("mode,strip_h", [(2, 16), (3, 6)])
+def test_timed_passes_keep_the_state(mode, strip_h):
+    """gg_step2_timed advances like gg_step."""
+    wl = W.gradient_generator(nx=300, ny=150, half_period=9, storage="f32")
+    one, two = _pair(wl, "f32", 8, strip_h, mode=mode)
+    one.step(12)
+    ms = two.step2_timed(3)
+    assert ms > 0.0
+    _same_state(one, two, 12)
