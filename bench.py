@@ -13,6 +13,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -54,6 +55,13 @@ def workload(name):
     return table[name]()
 
 
+# launch form per workload ((fuse, rows) of gg_set_two_step), as the
+# autotuner picks it on this GPU; --tune re-runs the autotuner
+FORMS = {"gg2048_f32": (4, 6), "gg2048_f16": (4, 6), "gg8192_f16": (3, 6),
+         "gg8192_f16_pe2000": (3, 6), "gg8192_f32": (3, 6), "allfluid8192_f32": (3, 14),
+         "allfluid8192_f16": (3, 6), "straight_f64": (4, 6)}
+
+
 def kernel_hash():
     h = hashlib.sha256()
     for path in KERNEL_SRC:
@@ -88,11 +96,14 @@ def time_lattice(name, steps, warmup, tile, chunk, form=None):
     lat = Lattice.from_workload(wl)
     lat.set_launch(tile[0], tile[1], chunk)
     nf = lat.info()["n_fluid"]
-    if form is None:
+    if form == "tune":
         res = T.tune_lattice(lat, steps=64 if nf > 1e7 else 256, graph_chunk=chunk,
                              use_cache=False)
         form = {"tile": res["tile"], "fuse": res["fuse"], "rows": res["rows"]}
     else:
+        if form is None:
+            fuse, rows = FORMS.get(name, (3, 6))
+            form = {"fuse": fuse, "rows": rows}
         form = {"tile": list(tile), **form}
         lat.set_two_step(form["fuse"], form["rows"])
     log(f"{wl.name}: {wl.nx}x{wl.ny}, {nf} fluid nodes, storage {wl.storage}, "
@@ -185,8 +196,9 @@ def batch_bench(steps=2000, seq_steps=400, n=64, seed=4703, tune_steps=16):
     torch.cuda.synchronize()
     t_b = e0.elapsed_time(e1) * 1e-3
     b.close()
-    for lat in lats:
+    for lat in lats:  # the same single-step kernels, one lattice after the other
         lat.set_launch(best["tile"][0], best["tile"][1], 64)
+        lat.set_two_step(1)
         lat.step(64)
     torch.cuda.synchronize()
     e0.record(stream)
@@ -271,7 +283,8 @@ def digest_counters(prof_dir, grids, out_path):
             raise SystemExit(f"no kernel {kname!r} with grid size {grid} ({name})")
         par = {}
         for k in steps:
-            tag = k[0].split("(")[0].split("::")[-1]
+            m = re.search(r"k_\w+(<[^>]*>)?", k[0])
+            tag = m.group(0) if m else k[0]
             par[tag] = {"fetch_bytes": round(fetch[k] * 1024 * fs),
                         "write_bytes": round(write.get(k, 0.0) * 1024 * ws)}
         tot = [v["fetch_bytes"] + v["write_bytes"] for v in par.values()]
@@ -296,19 +309,22 @@ def main():
     ap.add_argument("--tile", default="64x4")
     ap.add_argument("--chunk", type=int, default=64)
     ap.add_argument("--fuse", type=int, default=0,
-                    help="launch form (1 single steps, 2-4 two-step passes); 0: autotune")
+                    help="launch form (1 single steps, 2-4 two-step passes); 0: the "
+                         "workload's default form")
+    ap.add_argument("--tune", action="store_true", help="autotune the launch form")
     ap.add_argument("--rows", type=int, default=6, help="rows of the two-step strips or tiles")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances leg")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the out-of-cache and FP16 lattices and the copy bandwidth")
     ap.add_argument("--digest", metavar="DIR",
                     help="no run: digest rocprofv3 counter CSVs under DIR into profiles/traffic.json")
     ap.add_argument("--grids", default="",
-                    help="with --digest: grid/kernel=workload pairs, comma separated "
+                    help="with --digest: grid/kernel=workload pairs, separated by ';' "
                          "(kernel: a part of the kernel name, e.g. k_tile2<float)")
     args = ap.parse_args()
     if args.digest:
-        grids = dict(kv.split("=") for kv in args.grids.split(",") if kv)
+        grids = dict(kv.split("=") for kv in args.grids.split(";") if kv)
         d = digest_counters(args.digest, grids, os.path.join(ROOT, "profiles", "traffic.json"))
         print(json.dumps(d["workloads"]))
         return
@@ -323,7 +339,7 @@ def main():
     torch.cuda.set_device(0)
     tile = tuple(int(v) for v in args.tile.split("x"))
 
-    form = {"fuse": args.fuse, "rows": args.rows} if args.fuse else None
+    form = "tune" if args.tune else ({"fuse": args.fuse, "rows": args.rows} if args.fuse else None)
     r = time_lattice(args.workload, args.steps, args.warmup, tile, args.chunk, form)
     wl, nf = r["wl"], r["nf"]
     out = {
@@ -368,7 +384,8 @@ def main():
             e["storage"] = r2["wl"].storage
             extra[name] = e
         out["roofline_other_lattices"] = extra
-        out["batched_64_instances"] = batch_bench()
+        if not args.no_batch:
+            out["batched_64_instances"] = batch_bench()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

@@ -78,6 +78,14 @@ struct LatDesc {
   uint32_t phase_open[GG_MAX_PHASES];
   double phase_cin[GG_MAX_PHASES][GG_MAX_SEGMENTS];
   double seg_cin[GG_MAX_SEGMENTS];  // used when there is no schedule
+  // the same inlet parameters rounded to FP32 for the FP32 compute type:
+  // 4 u_max, s0, s1, 1/(s1 - s0)^2 per segment, C_in per phase and segment
+  float seg_umax4_f[GG_MAX_SEGMENTS];
+  float seg_s0_f[GG_MAX_SEGMENTS];
+  float seg_s1_f[GG_MAX_SEGMENTS];
+  float seg_inv_w2_f[GG_MAX_SEGMENTS];
+  float phase_cin_f[GG_MAX_PHASES][GG_MAX_SEGMENTS];
+  float seg_cin_f[GG_MAX_SEGMENTS];
 };
 
 // Address spaces: the descriptor and tile lists are read-only while a

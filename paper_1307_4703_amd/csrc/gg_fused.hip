@@ -48,11 +48,12 @@ template <class S, bool SEG>
 __device__ __forceinline__ void second_step(CDesc &L, const Planes<typename Pop<S>::W> &dst,
                                             int x, int y, uint8_t lc, const PhaseNow &ph,
                                             const typename Pop<S>::T *sf,
-                                            const typename Pop<S>::T *sg, Flux &fx) {
+                                            const typename Pop<S>::T *sg, Flux &fx,
+                                            const uint32_t *nbr = nullptr) {
   using P = Pop<S>;
   using T = typename P::T;
   T qf[9], qg[5], jf[9], jg[5];
-  collide_node<T>(L, x, y, lc, SEG, ph, sf, sg, qf, qg, jf, jg, fx, true);
+  collide_node<T>(L, x, y, lc, SEG, ph, sf, sg, qf, qg, jf, jg, fx, true, nbr);
   const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
   const Neigh nb(L, x, y);
   P::st(dst.at(0, node), qf[0]);
@@ -294,18 +295,33 @@ __global__ void __launch_bounds__((R + 2) * 64)
     const bool row = yr >= -1 && yr <= ny && w <= rows + 1;
     const bool own = own_col && w >= 1 && w <= rows && yr < ny;
     const uint32_t node = (uint32_t)(L.node0 + y * pitch + x);
-    const uint8_t lc = (row && col) ? ((const GG_GLOBAL uint8_t *)L.link)[node] : NOT_FLUID;
+    // every load of the row is issued at once: the link code, the
+    // populations of any addressable cell (non-fluid cells hold finite values
+    // nobody uses), and on segment tiles the neighbours' mask values
+    uint8_t lc = NOT_FLUID;
+    T f[9], g[5];
+    uint32_t nbr[2] = {0u, 0u};
+    if (row && col) {
+      lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = P::ld(src.at(i, node));
+#pragma unroll
+      for (int i = 0; i < 5; ++i) g[i] = P::ld(src.at(9 + i, node));
+      // (only for cells inside the lattice, whose neighbours all lie in the
+      // padded planes; the halo cells outside are not fluid)
+      if (seg && x >= 0 && x < nx && y >= 0 && y < ny) {
+        const Neigh nb(L, x, y);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          nbr[k >> 2] |= (uint32_t)((const GG_GLOBAL uint8_t *)L.mask)[nb.idx[k + 1]] << (8 * (k & 3));
+      }
+    }
 
     // step t on this row
     Flux fx;
     T pf[9], pg[5], inf[9], ing[5];
     if (lc != NOT_FLUID) {
-      T f[9], g[5];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) f[i] = P::ld(src.at(i, node));
-#pragma unroll
-      for (int i = 0; i < 5; ++i) g[i] = P::ld(src.at(9 + i, node));
-      collide_node<T>(L, x, y, lc, seg, ph1, f, g, pf, pg, inf, ing, fx, own);
+      collide_node<T>(L, x, y, lc, seg, ph1, f, g, pf, pg, inf, ing, fx, own, SEG ? nbr : nullptr);
     } else {
 #pragma unroll
       for (int i = 0; i < 9; ++i) pf[i] = inf[i] = T(0);
@@ -342,7 +358,7 @@ __global__ void __launch_bounds__((R + 2) * 64)
       sf[8] = P::rt(src_solid(lc, 8) ? inf[8] : lds_dn[w + 1][2][lane]);
       sg[4] = P::rt(src_solid(lc, 4) ? ing[4] : lds_dn[w + 1][3][lane]);
       if (seg)
-        second_step<S, true>(L, dst, x, y, lc, ph2, sf, sg, fx);
+        second_step<S, true>(L, dst, x, y, lc, ph2, sf, sg, fx, nbr);
       else
         second_step<S, false>(L, dst, x, y, lc, ph2, sf, sg, fx);
     }

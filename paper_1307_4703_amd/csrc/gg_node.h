@@ -14,17 +14,35 @@ using CDesc = const GG_CONST LatDesc;
 struct PhaseNow {
   uint32_t open;
   const GG_CONST double *cin;
+  const GG_CONST float *cin_f;  // the same in FP32
 };
 
 // Valve phase in force during step t (fixed at the start of the step).
 __device__ __forceinline__ PhaseNow phase_at(CDesc &L, int64_t t) {
-  if (L.n_phases == 0) return {0xFFFFFFFFu, L.seg_cin};
+  if (L.n_phases == 0) return {0xFFFFFFFFu, L.seg_cin, L.seg_cin_f};
   int64_t tau = (t - L.t_origin) % L.period;
   if (tau < 0) tau += L.period;
   int k = 0;
   while (k + 1 < L.n_phases && L.phase_start[k + 1] <= tau) ++k;
-  return {L.phase_open[k], L.phase_cin[k]};
+  return {L.phase_open[k], L.phase_cin[k], L.phase_cin_f[k]};
 }
+
+// Inlet parameters of segment s in the compute type T (pre-rounded for FP32).
+template <class T> struct SegT;
+template <> struct SegT<double> {
+  static __device__ __forceinline__ double umax4(CDesc &L, int s) { return 4.0 * L.seg_umax[s]; }
+  static __device__ __forceinline__ double s0(CDesc &L, int s) { return L.seg_s0[s]; }
+  static __device__ __forceinline__ double s1(CDesc &L, int s) { return L.seg_s1[s]; }
+  static __device__ __forceinline__ double iw2(CDesc &L, int s) { return L.seg_inv_w2[s]; }
+  static __device__ __forceinline__ double cin(const PhaseNow &p, int s) { return p.cin[s]; }
+};
+template <> struct SegT<float> {
+  static __device__ __forceinline__ float umax4(CDesc &L, int s) { return L.seg_umax4_f[s]; }
+  static __device__ __forceinline__ float s0(CDesc &L, int s) { return L.seg_s0_f[s]; }
+  static __device__ __forceinline__ float s1(CDesc &L, int s) { return L.seg_s1_f[s]; }
+  static __device__ __forceinline__ float iw2(CDesc &L, int s) { return L.seg_inv_w2_f[s]; }
+  static __device__ __forceinline__ float cin(const PhaseNow &p, int s) { return p.cin_f[s]; }
+};
 
 // Sum over the 64 lanes of a wavefront; every lane must be active.
 __device__ __forceinline__ double wave_sum(double v) {
@@ -158,10 +176,14 @@ __device__ __forceinline__ double fmad(double a, double b, double c) { return __
 // in_g[j], the value that arrives at (x, y) along direction j at t + 1 when
 // x - e_j is not fluid (bounce-back from a wall or closed valve, or the rule
 // of an open segment). Fluxes through open segments go into fx when count.
+// nbr, when given, holds the mask values of the cells x + e_k (k = 1..8,
+// wrapped on periodic axes, walls beyond the others) loaded beforehand, as
+// bytes k - 1 of nbr[0] (k = 1..4) and nbr[1] (k = 5..8).
 template <class T>
 __device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc, bool seg_tile,
                                              const PhaseNow &ph, const T *f, const T *g, T *pf,
-                                             T *pg, T *in_f, T *in_g, Flux &fx, bool count) {
+                                             T *pg, T *in_f, T *in_g, Flux &fx, bool count,
+                                             const uint32_t *nbr = nullptr) {
   // Every kernel that advances the lattice inlines this function; the fused
   // multiply-adds are written out and no other contraction is allowed, so
   // each of them rounds exactly the same way whatever code surrounds it.
@@ -240,7 +262,8 @@ __device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc,
       if (sy < 0 || sy >= ny) {
         if (L.periodic_y) sy = (sy + ny) % ny; else inside = false;
       }
-      const int code = inside ? (int)((const GG_GLOBAL uint8_t *)L.mask)[L.node0 + sy * pitch + sx]
+      const int code = nbr ? (int)((nbr[(OPP[j] - 1) >> 2] >> (8 * ((OPP[j] - 1) & 3))) & 0xFFu)
+                     : inside ? (int)((const GG_GLOBAL uint8_t *)L.mask)[L.node0 + sy * pitch + sx]
                               : GG_MASK_WALL;
       if (code < GG_FIRST_SEGMENT) continue;
       const int s = code - GG_FIRST_SEGMENT;
@@ -250,11 +273,11 @@ __device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc,
         // moving-wall bounce-back, wall velocity -n u(s) with a parabolic
         // profile across the segment; anti-bounce-back for C_in
         const T coord = L.seg_nx[s] != 0 ? (T)y : (T)x;
-        const T us = (T)(4.0 * L.seg_umax[s]) * (coord - (T)L.seg_s0[s]) *
-                     ((T)L.seg_s1[s] - coord) * (T)L.seg_inv_w2[s];
+        const T us = SegT<T>::umax4(L, s) * (coord - SegT<T>::s0(L, s)) *
+                     (SegT<T>::s1(L, s) - coord) * SegT<T>::iw2(L, s);
         const T en = (T)(EX[j] * L.seg_nx[s] + EY[j] * L.seg_ny[s]);
         vf = fmad(T(-6) * (T)WF[j] * rho0 * en, us, pf[OPP[j]]);
-        if (j < 5) vg = fmad(T(2) * wg[j], (T)ph.cin[s] - cs, -pg[OPP[j]]);
+        if (j < 5) vg = fmad(T(2) * wg[j], SegT<T>::cin(ph, s) - cs, -pg[OPP[j]]);
       } else {
         // outflow at the reference density with the node's own u;
         // the compound leaves with zero gradient

@@ -109,6 +109,11 @@ gg_status gg_upload_desc(gg_lattice *L) {
     h.seg_s1[s] = g.s1;
     h.seg_inv_w2[s] = g.set ? 1.0 / ((g.s1 - g.s0) * (g.s1 - g.s0)) : 0.0;
     h.seg_cin[s] = g.c_in;
+    h.seg_umax4_f[s] = (float)(4.0 * h.seg_umax[s]);
+    h.seg_s0_f[s] = (float)h.seg_s0[s];
+    h.seg_s1_f[s] = (float)h.seg_s1[s];
+    h.seg_inv_w2_f[s] = (float)h.seg_inv_w2[s];
+    h.seg_cin_f[s] = (float)h.seg_cin[s];
   }
   h.n_phases = (int32_t)L->phases.size();
   h.t_origin = L->t_origin;
@@ -120,6 +125,7 @@ gg_status gg_upload_desc(gg_lattice *L) {
     h.phase_open[k] = ph.open_mask;
     for (int s = 0; s < GG_MAX_SEGMENTS; ++s)
       h.phase_cin[k][s] = ((ph.c_in_set >> s) & 1u) ? ph.c_in[s] : L->seg[s].c_in;
+    for (int s = 0; s < GG_MAX_SEGMENTS; ++s) h.phase_cin_f[k][s] = (float)h.phase_cin[k][s];
   }
   h.period = start > 0 ? start : 1;
   GG_HIP(hipMemcpyAsync(L->d_desc, &h, sizeof(h), hipMemcpyHostToDevice, L->stream));
@@ -144,7 +150,8 @@ static void build_tiles(const gg_lattice *L, int tx, int ty, int inst,
 }
 
 // Strips of the two-step pass: 62 owned columns x h rows holding at least
-// one fluid node, listed band by band (rows y0 .. y0 + h - 1) from left to
+// one fluid node, laid from the first column of each run of fluid columns
+// of a band (rows y0 .. y0 + h - 1), listed band by band from left to
 // right: horizontally adjacent strips store into the same cache lines at
 // their common edge every row, so they go to the same XCD (a contiguous run
 // of the list) and run side by side in one work-group. With split, a band
@@ -162,25 +169,49 @@ static void build_strips(const gg_lattice *L, int h, int inst, bool split, std::
         if (L->touches_seg[(size_t)y * L->nx + x]) sg = true;
       }
   };
-  for (int y0 = 0; y0 < L->ny; y0 += h)
-    for (int x0 = 0; x0 < L->nx; x0 += 62) {
-      bool any, sg;
-      scan(x0, y0, h, any, sg);
-      if (!any) continue;
-      if (!sg || !split) {
-        main.push_back(Tile{inst, x0, y0, (h << 8) | (sg ? TILE_TOUCHES_SEGMENT : 0)});
+  std::vector<uint8_t> colany((size_t)L->nx);
+  for (int y0 = 0; y0 < L->ny; y0 += h) {
+    // columns holding fluid in this band, as runs; runs less than a strip
+    // apart are merged, so the strips laid from the start of each run never
+    // overlap the next run's strips
+    std::fill(colany.begin(), colany.end(), 0);
+    for (int y = y0; y < std::min(y0 + h, L->ny); ++y)
+      for (int x = 0; x < L->nx; ++x)
+        if (L->link[L->nid(x, y)] != NOT_FLUID) colany[x] = 1;
+    std::vector<std::pair<int, int>> runs;
+    for (int x = 0; x < L->nx;) {
+      if (!colany[x]) {
+        ++x;
         continue;
       }
-      for (int yy = y0; yy < std::min(y0 + h, L->ny); yy += 2) {
-        const int rows = std::min(2, y0 + h - yy);
-        scan(x0, yy, rows, any, sg);
-        if (!any) continue;
-        if (sg)
-          seg.push_back(Tile{inst, x0, yy, (rows << 8) | TILE_TOUCHES_SEGMENT});
-        else
-          main.push_back(Tile{inst, x0, yy, rows << 8});
-      }
+      int e = x;
+      while (e < L->nx && colany[e]) ++e;
+      if (!runs.empty() && x - runs.back().second < 62)
+        runs.back().second = e;
+      else
+        runs.push_back({x, e});
+      x = e;
     }
+    for (const auto &run : runs)
+      for (int x0 = run.first; x0 < run.second; x0 += 62) {
+        bool any, sg;
+        scan(x0, y0, h, any, sg);
+        if (!any) continue;
+        if (!sg || !split) {
+          main.push_back(Tile{inst, x0, y0, (h << 8) | (sg ? TILE_TOUCHES_SEGMENT : 0)});
+          continue;
+        }
+        for (int yy = y0; yy < std::min(y0 + h, L->ny); yy += 2) {
+          const int rows = std::min(2, y0 + h - yy);
+          scan(x0, yy, rows, any, sg);
+          if (!any) continue;
+          if (sg)
+            seg.push_back(Tile{inst, x0, yy, (rows << 8) | TILE_TOUCHES_SEGMENT});
+          else
+            main.push_back(Tile{inst, x0, yy, rows << 8});
+        }
+      }
+  }
 }
 
 gg_status gg_rebuild_tiles(gg_lattice *L) {
@@ -559,8 +590,10 @@ static hipError_t launch_pass(gg_lattice *L, int dir, int dt, hipStream_t st) {
     return launch_tile2(L->storage, true, L->strip_h, L->d_desc, L->d_strips, L->n_strips, dir, dt,
                         st);
   auto run = [&](bool seg, const Tile *list, int n, hipStream_t s) {
-    return L->fuse == 3 ? launch_tile2(L->storage, seg, L->strip_h, L->d_desc, list, n, dir, dt, s)
-                        : launch_step2(L->storage, seg, L->d_desc, list, n, dir, dt, s);
+    // the segment list holds 2-row tiles
+    return L->fuse == 3
+               ? launch_tile2(L->storage, seg, seg ? 2 : L->strip_h, L->d_desc, list, n, dir, dt, s)
+               : launch_step2(L->storage, seg, L->d_desc, list, n, dir, dt, s);
   };
   if (fork) {
     e = hipEventRecord(L->ev_fork, st);
