@@ -243,6 +243,15 @@ gg_status gg_batch_create(gg_lattice *const *lats, int32_t n, int32_t tile_x,
                           int32_t tile_y, int32_t persist, int32_t graph_chunk,
                           gg_batch **out);
 gg_status gg_batch_step(gg_batch *batch, int64_t n);
+
+/* Two-step pass for the batch (see gg_set_two_step): fuse 3 or 4 with
+ * tiles of rows = 6 or 14 rows, over the members' tiles in one flat list
+ * (fuse 3: the boundary tiles of all members in a second list on a second
+ * stream); fuse = 1 goes back to single steps. Every member must have its
+ * second plane set (fuse >= 2 on the member, the default) and all members
+ * must sit at steps of one parity (else GG_ERR_STATE). The states advance
+ * exactly as with single steps. */
+gg_status gg_batch_set_two_step(gg_batch *batch, int32_t fuse, int32_t rows);
 gg_status gg_batch_info(const gg_batch *batch, int64_t *n_tiles, int64_t *n_fluid);
 void gg_batch_destroy(gg_batch *batch);
 

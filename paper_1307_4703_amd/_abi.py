@@ -95,6 +95,7 @@ SIGS = {
     "gg_adjoint": [P, I64, I64, P, P, P, P, ctypes.POINTER(gg_grads)],
     "gg_batch_create": [ctypes.POINTER(P), I32, I32, I32, I32, I32, ctypes.POINTER(P)],
     "gg_batch_step": [P, I64],
+    "gg_batch_set_two_step": [P, I32, I32],
     "gg_batch_info": [P, ctypes.POINTER(I64), ctypes.POINTER(I64)],
     "gg_stream_copy": [P, P, ctypes.c_size_t, I32, P, ctypes.POINTER(D)],
 }

@@ -34,8 +34,10 @@ hipError_t launch_init(gg_storage s, const LatDesc *d, const Tile *tiles, int n_
 hipError_t launch_read(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                        int tx_shift, double *rho, double *ux, double *uy, double *c,
                        double *f, double *g, hipStream_t st);
+// FP64 diagnostics into acc[0..5] (mass, solute, max|u|, region max|u|,
+// non-finite count, fluid count) through partial[6 * n_tiles].
 hipError_t launch_reduce(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
-                         int tx_shift, double *acc, hipStream_t st);
+                         int tx_shift, double *partial, double *acc, hipStream_t st);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
 hipError_t launch_advance(const LatDesc *descs, int n, int64_t k, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);

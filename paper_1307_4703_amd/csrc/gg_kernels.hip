@@ -230,15 +230,18 @@ __global__ void k_fill(double *__restrict__ p, int64_t n, double v) {
 }
 
 // ---------------------------------------------------------------------------
-// FP64 diagnostics: wavefront reductions, one atomic per wavefront.
-// acc: [0] mass, [1] solute, [2] max|u| bits, [3] max|u| region bits,
-//      [4] non-finite count, [5] fluid count
+// FP64 diagnostics: wavefront reductions, then one partial per work-group
+// (no atomics, so the totals do not depend on the order of the work-groups),
+// then one work-group folds the partials.
+// partial[6 * tile + k] / acc[k]: [0] mass, [1] solute, [2] max|u|,
+// [3] max|u| in the region, [4] non-finite count, [5] fluid count
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ void __launch_bounds__(256)
     k_reduce(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles,
-             int n_tiles, int tx_shift, double *__restrict__ acc) {
+             int n_tiles, int tx_shift, double *__restrict__ partial) {
   using T = typename Pop<S>::T;
+  __shared__ double lds[4][6];
   const int tile = blockIdx.x;
   if (tile >= n_tiles) return;
   const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
@@ -248,50 +251,73 @@ __global__ void __launch_bounds__(256)
   const int y = tl.y0 + (int)(threadIdx.x >> tx_shift);
   const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
   const uint8_t lc = (x < L.nx && y < L.ny) ? ((const GG_GLOBAL uint8_t *)L.link)[node] : NOT_FLUID;
-  double m = 0.0, c = 0.0, um = 0.0, ur = 0.0, bad = 0.0, cnt = 0.0;
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (lc != NOT_FLUID) {
     T fT[9], gT[5];
     gather<S>(L, node, lc, x, y, fT, gT);
     double rho = 0.0, jx = 0.0, jy = 0.0, C = 0.0;  // deviations first
     bool finite = true;
     for (int i = 0; i < 9; ++i) {
-      const double v = (double)fT[i];
-      finite = finite && isfinite(v);
-      rho += v;
-      jx += EX[i] * v;
-      jy += EY[i] * v;
+      const double q = (double)fT[i];
+      finite = finite && isfinite(q);
+      rho += q;
+      jx += EX[i] * q;
+      jy += EY[i] * q;
     }
     for (int i = 0; i < 5; ++i) {
-      const double v = (double)gT[i];
-      finite = finite && isfinite(v);
-      C += v;
+      const double q = (double)gT[i];
+      finite = finite && isfinite(q);
+      C += q;
     }
     rho += L.rho0;
     C += L.c_shift;
-    cnt = 1.0;
+    v[5] = 1.0;
     if (finite) {
-      m = rho;
-      c = C;
-      um = sqrt(jx * jx + jy * jy) / rho;
-      if (L.has_region && ((const GG_GLOBAL uint8_t *)L.region)[node]) ur = um;
+      v[0] = rho;
+      v[1] = C;
+      v[2] = sqrt(jx * jx + jy * jy) / rho;
+      if (L.has_region && ((const GG_GLOBAL uint8_t *)L.region)[node]) v[3] = v[2];
     } else {
-      bad = 1.0;
+      v[4] = 1.0;
     }
   }
-  m = wave_sum(m);
-  c = wave_sum(c);
-  bad = wave_sum(bad);
-  cnt = wave_sum(cnt);
-  um = wave_max(um);
-  ur = wave_max(ur);
-  if (__lane_id() == 0 && cnt > 0.0) {
-    atomicAdd(acc + 0, m);
-    atomicAdd(acc + 1, c);
-    // non-negative doubles order like their bit patterns
-    atomicMax(reinterpret_cast<unsigned long long *>(acc + 2), (unsigned long long)__double_as_longlong(um));
-    atomicMax(reinterpret_cast<unsigned long long *>(acc + 3), (unsigned long long)__double_as_longlong(ur));
-    atomicAdd(acc + 4, bad);
-    atomicAdd(acc + 5, cnt);
+  const int w = (int)(threadIdx.x >> 6);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double r = (k == 2 || k == 3) ? wave_max(v[k]) : wave_sum(v[k]);
+    if (__lane_id() == 0) lds[w][k] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int k = (int)threadIdx.x;
+    double r = lds[0][k];
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q)
+      r = (k == 2 || k == 3) ? fmax(r, lds[q][k]) : r + lds[q][k];
+    partial[6 * tile + k] = r;
+  }
+}
+
+// Folds the per-work-group partials into acc[0..5] (one work-group).
+__global__ void __launch_bounds__(256)
+    k_reduce_final(const double *__restrict__ partial, int n_tiles, double *__restrict__ acc) {
+  __shared__ double lds[4][6];
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int t = (int)threadIdx.x; t < n_tiles; t += (int)blockDim.x)
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      v[k] = (k == 2 || k == 3) ? fmax(v[k], partial[6 * t + k]) : v[k] + partial[6 * t + k];
+  const int w = (int)(threadIdx.x >> 6);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double r = (k == 2 || k == 3) ? wave_max(v[k]) : wave_sum(v[k]);
+    if (__lane_id() == 0) lds[w][k] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int k = (int)threadIdx.x;
+    double r = lds[0][k];
+    for (int q = 1; q < 4; ++q) r = (k == 2 || k == 3) ? fmax(r, lds[q][k]) : r + lds[q][k];
+    acc[k] = r;
   }
 }
 
@@ -377,13 +403,14 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st) {
 }
 
 hipError_t launch_reduce(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
-                         int tx_shift, double *acc, hipStream_t st) {
+                         int tx_shift, double *partial, double *acc, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   switch (s) {
-    case GG_F64: k_reduce<double><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, acc); break;
-    case GG_F32: k_reduce<float><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, acc); break;
-    case GG_F16_SHIFTED: k_reduce<__half><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, acc); break;
+    case GG_F64: k_reduce<double><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, partial); break;
+    case GG_F32: k_reduce<float><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, partial); break;
+    case GG_F16_SHIFTED: k_reduce<__half><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, partial); break;
   }
+  k_reduce_final<<<1, 256, 0, st>>>(partial, n_tiles, acc);
   return hipGetLastError();
 }
 

@@ -42,6 +42,7 @@ struct gg_lattice {
   double *d_R = nullptr;
   int64_t *d_t = nullptr;
   double *d_flux = nullptr, *d_acc = nullptr;
+  double *d_partial = nullptr;  // per-tile partials of the diagnostics
   gg::LatDesc *d_desc = nullptr;
   gg::LatDesc h{};
   gg::Tile *d_tiles = nullptr;

@@ -58,7 +58,7 @@ void gg_free_device(gg_lattice *L) {
   L->graph = nullptr;
   void *ptrs[] = {L->d_pop, L->d_pop_b, L->d_link, L->d_mask, L->d_region, L->d_R, L->d_t,
                   L->d_flux, L->d_acc, L->d_desc, L->d_tiles, L->d_aux_tiles, L->d_strips,
-                  L->d_seg_strips};
+                  L->d_seg_strips, L->d_partial};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (L->cap_stream) (void)hipStreamDestroy(L->cap_stream);
@@ -720,8 +720,15 @@ gg_status gg_read_populations(gg_lattice *L, double *f, double *g, gg_where wher
 
 gg_status gg_diagnostics(gg_lattice *L, gg_diag *out) {
   if (!L || !out) return fail(GG_ERR_ARG, "NULL argument");
+  if (!L->d_partial && L->n_aux_tiles > 0) {
+    if (hipMalloc(&L->d_partial, (size_t)6 * L->n_aux_tiles * sizeof(double)) != hipSuccess) {
+      L->d_partial = nullptr;
+      return fail(GG_ERR_OOM, "diagnostics partials");
+    }
+  }
   GG_HIP(hipMemsetAsync(L->d_acc, 0, 8 * sizeof(double), L->stream));
-  GG_HIP(launch_reduce(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6, L->d_acc, L->stream));
+  GG_HIP(launch_reduce(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6, L->d_partial,
+                       L->d_acc, L->stream));
   double acc[8], flux[2 * GG_MAX_SEGMENTS];
   int64_t t = 0;
   GG_HIP(hipStreamSynchronize(L->stream));
@@ -1012,6 +1019,12 @@ struct gg_batch {
   std::vector<int64_t> t_created;  // member times when the batch was made
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  // two-step pass over all members (fuse 3 or 4, tiles of `rows` rows)
+  int fuse = 1, rows = 6;
+  Tile *d_strips = nullptr, *d_seg_strips = nullptr;
+  int n_strips = 0, n_seg_strips = 0;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 static void batch_free(gg_batch *B) {
@@ -1020,20 +1033,60 @@ static void batch_free(gg_batch *B) {
   if (B->d_descs) (void)hipFree(B->d_descs);
   for (int g = 0; g < 2; ++g)
     if (B->d_tiles[g]) (void)hipFree(B->d_tiles[g]);
+  if (B->d_strips) (void)hipFree(B->d_strips);
+  if (B->d_seg_strips) (void)hipFree(B->d_seg_strips);
   if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+  if (B->side) (void)hipStreamDestroy(B->side);
+  if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
+  if (B->ev_join) (void)hipEventDestroy(B->ev_join);
   delete B;
+}
+
+// The batch runs two-step passes when they are on, the members sit at even
+// steps (the batch's step count plus the parity of the group they were all
+// in at creation) and n is a multiple of 4 (pairs of passes end in the
+// members' first plane sets).
+static bool batch_passes(const gg_batch *B, int64_t s0, int64_t n) {
+  return B->fuse >= 3 && n % 4 == 0 && ((s0 + (B->n_tiles[0] > 0 ? 0 : 1)) & 1) == 0;
 }
 
 // n steps of the batch on `st` (group parity from the batch's step count)
 static hipError_t batch_launch(gg_batch *B, int64_t s0, int64_t n, hipStream_t st) {
-  const int block = B->tile_x * B->tile_y;
-  const int txs = ilog2(B->tile_x);
   hipError_t e = hipSuccess;
-  for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt)
-    for (int g = 0; g < 2 && e == hipSuccess; ++g)
-      if (B->n_tiles[g] > 0)
-        e = launch_step(B->storage, block, ((s0 + dt + g) & 1) != 0, B->d_descs, B->d_tiles[g],
-                        B->n_tiles[g], txs, (int)dt, st, B->persist);
+  if (batch_passes(B, s0, n)) {
+    const bool fork = B->fuse == 3 && B->n_seg_strips > 0 && B->n_strips > 0;
+    for (int64_t k = 0; k < n / 2 && e == hipSuccess; ++k) {
+      const int dir = (int)(k & 1), dt = (int)(2 * k);
+      if (B->fuse == 4) {
+        e = launch_tile2(B->storage, true, B->rows, B->d_descs, B->d_strips, B->n_strips, dir, dt,
+                         st);
+        continue;
+      }
+      if (fork) {
+        e = hipEventRecord(B->ev_fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(B->side, B->ev_fork, 0);
+        if (e == hipSuccess)
+          e = launch_tile2(B->storage, true, 2, B->d_descs, B->d_seg_strips, B->n_seg_strips, dir,
+                           dt, B->side);
+        if (e == hipSuccess) e = hipEventRecord(B->ev_join, B->side);
+      } else if (B->n_seg_strips > 0) {
+        e = launch_tile2(B->storage, true, 2, B->d_descs, B->d_seg_strips, B->n_seg_strips, dir,
+                         dt, st);
+      }
+      if (e == hipSuccess)
+        e = launch_tile2(B->storage, false, B->rows, B->d_descs, B->d_strips, B->n_strips, dir,
+                         dt, st);
+      if (fork && e == hipSuccess) e = hipStreamWaitEvent(st, B->ev_join, 0);
+    }
+  } else {
+    const int block = B->tile_x * B->tile_y;
+    const int txs = ilog2(B->tile_x);
+    for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt)
+      for (int g = 0; g < 2 && e == hipSuccess; ++g)
+        if (B->n_tiles[g] > 0)
+          e = launch_step(B->storage, block, ((s0 + dt + g) & 1) != 0, B->d_descs, B->d_tiles[g],
+                          B->n_tiles[g], txs, (int)dt, st, B->persist);
+  }
   if (e == hipSuccess) e = launch_advance(B->d_descs, (int)B->lats.size(), n, st);
   return e;
 }
@@ -1108,6 +1161,48 @@ gg_status gg_batch_step(gg_batch *B, int64_t n) {
   }
   int64_t left = n;
   const int K = B->chunk;
+  if (B->fuse >= 3) {
+    // all members in one parity group; s_even: a batch step count at which
+    // they sit at even steps
+    const int64_t s_even = B->n_tiles[0] > 0 ? 0 : 1;
+    if (((B->steps + s_even) & 1) && left > 0) {  // to even member steps
+      GG_HIP(batch_launch(B, B->steps, 1, B->stream));
+      B->steps += 1;
+      left -= 1;
+    }
+    if (K > 0 && left >= K) {
+      if (!B->graph_exec) {  // K is a multiple of 4: passes only
+        GG_HIP(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = batch_launch(B, s_even, K, B->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(B->cap_stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);
+          return fail(GG_ERR_HIP, std::string("batch graph capture: ") +
+                                      hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        B->graph = g;
+        GG_HIP(hipGraphInstantiate(&B->graph_exec, B->graph, nullptr, nullptr, 0));
+      }
+      while (left >= K) {
+        GG_HIP(hipGraphLaunch(B->graph_exec, B->stream));
+        left -= K;
+        B->steps += K;
+      }
+    }
+    const int64_t quads = left / 4 * 4;
+    if (quads > 0) {
+      GG_HIP(batch_launch(B, B->steps, quads, B->stream));
+      B->steps += quads;
+      left -= quads;
+    }
+    if (left > 0) {
+      GG_HIP(batch_launch(B, B->steps, left, B->stream));
+      B->steps += left;
+    }
+    for (gg_lattice *L : B->lats) L->t += n;
+    return GG_OK;
+  }
   if (K > 0 && (B->steps & 1) && left >= K + 1) {  // replays start on an even batch step
     GG_HIP(batch_launch(B, B->steps, 1, B->stream));
     B->steps += 1;
@@ -1138,6 +1233,50 @@ gg_status gg_batch_step(gg_batch *B, int64_t n) {
     B->steps += left;
   }
   for (gg_lattice *L : B->lats) L->t += n;
+  return GG_OK;
+}
+
+gg_status gg_batch_set_two_step(gg_batch *B, int32_t fuse, int32_t rows) {
+  if (!B) return fail(GG_ERR_ARG, "batch is NULL");
+  if (fuse != 1 && fuse != 3 && fuse != 4) return fail(GG_ERR_ARG, "fuse must be 1, 3 or 4");
+  if (fuse >= 3 && rows != 6 && rows != 14) return fail(GG_ERR_ARG, "tiles have 6 or 14 rows");
+  if (fuse >= 3 && B->n_tiles[0] > 0 && B->n_tiles[1] > 0)
+    return fail(GG_ERR_STATE, "the two-step pass needs all members at steps of one parity");
+  for (size_t k = 0; k < B->lats.size() && fuse >= 3; ++k)
+    if (!B->lats[k]->d_pop_b)
+      return fail(GG_ERR_STATE, "member " + std::to_string(k) +
+                                    " has no second plane set (gg_set_two_step with fuse >= 2)");
+  GG_HIP(hipStreamSynchronize(B->stream));
+  if (B->graph_exec) (void)hipGraphExecDestroy(B->graph_exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  B->graph_exec = nullptr;
+  B->graph = nullptr;
+  if (B->d_strips) (void)hipFree(B->d_strips);
+  if (B->d_seg_strips) (void)hipFree(B->d_seg_strips);
+  B->d_strips = B->d_seg_strips = nullptr;
+  B->n_strips = B->n_seg_strips = 0;
+  B->fuse = fuse;
+  B->rows = rows;
+  if (fuse == 1) return GG_OK;
+  std::vector<Tile> sv, ss;
+  for (size_t k = 0; k < B->lats.size(); ++k)
+    build_strips(B->lats[k], rows, (int)k, fuse == 3, sv, ss);
+  B->n_strips = (int)sv.size();
+  B->n_seg_strips = (int)ss.size();
+  if (!sv.empty()) {
+    GG_HIP(hipMalloc(&B->d_strips, sv.size() * sizeof(Tile)));
+    GG_HIP(hipMemcpy(B->d_strips, sv.data(), sv.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  }
+  if (!ss.empty()) {
+    GG_HIP(hipMalloc(&B->d_seg_strips, ss.size() * sizeof(Tile)));
+    GG_HIP(hipMemcpy(B->d_seg_strips, ss.data(), ss.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  }
+  if (!B->side) {
+    GG_HIP(hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking));
+    GG_HIP(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
+    GG_HIP(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming));
+  }
+  B->chunk = (B->chunk + 3) / 4 * 4;
   return GG_OK;
 }
 

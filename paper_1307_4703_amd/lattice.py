@@ -240,7 +240,7 @@ class Batch:
     """
 
     def __init__(self, lattices: Sequence[Lattice], tile: Tuple[int, int] = (64, 4),
-                 persist: int = 0, graph_chunk: int = 64):
+                 persist: int = 0, graph_chunk: int = 64, fuse: int = 1, rows: int = 6):
         self.lattices = list(lattices)
         arr = (ctypes.c_void_p * len(self.lattices))(*[l.handle.value for l in self.lattices])
         h = ctypes.c_void_p()
@@ -249,6 +249,13 @@ class Batch:
         self._h = h
         self.tile = tuple(tile)
         self.persist = int(persist)
+        if fuse != 1:
+            self.set_two_step(fuse, rows)
+
+    def set_two_step(self, fuse: int = 4, rows: int = 6) -> None:
+        """Two-step passes over all members (fuse 3 or 4) or single steps
+        (fuse 1); include/gg.h, gg_batch_set_two_step."""
+        A.call("gg_batch_set_two_step", self._h, int(fuse), int(rows))
 
     def step(self, n: int = 1) -> None:
         A.call("gg_batch_step", self._h, int(n))

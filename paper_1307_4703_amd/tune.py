@@ -104,12 +104,16 @@ def tune_lattice(lat, steps: int = 64, tiles: Iterable[Tuple[int, int]] = TILES,
 
 
 def tune_batch(lattices: Sequence, steps: int = 32, tiles: Iterable[Tuple[int, int]] = TILES,
-               persist: Iterable[int] = PERSIST, graph_chunk: int = 64,
-               use_cache: bool = True, path: Optional[str] = None) -> Dict:
-    """Pick tile shape and persistent grid size for a batch of lattices."""
+               persist: Iterable[int] = PERSIST,
+               two_step: Iterable[Tuple[int, int]] = ((4, 6), (4, 14), (3, 6), (3, 14)),
+               graph_chunk: int = 64, use_cache: bool = True,
+               path: Optional[str] = None) -> Dict:
+    """Pick the launch form of a batch: single steps with a tile shape and a
+    persistent grid size, or a two-step form (with the best tile shape for
+    the single steps that align the parity). steps: a multiple of 4."""
     from .lattice import Batch
     path = path or cache_path()
-    key = _key(lattices, "batch")
+    key = _key(lattices, "batch2")
     if use_cache:
         hit = _load(path).get(key)
         if hit:
@@ -118,10 +122,18 @@ def tune_batch(lattices: Sequence, steps: int = 32, tiles: Iterable[Tuple[int, i
     for t in tiles:
         for p in persist:
             b = Batch(lattices, tile=t, persist=p, graph_chunk=graph_chunk)
-            results.append({"tile": list(t), "persist": p, "ms_per_step": _time(b.step, steps)})
+            results.append({"tile": list(t), "persist": p, "fuse": 1, "rows": 6,
+                            "ms_per_step": _time(b.step, steps)})
             b.close()
+    single = min(results, key=lambda r: r["ms_per_step"])
+    for fuse, rows in two_step:
+        b = Batch(lattices, tile=tuple(single["tile"]), persist=single["persist"],
+                  graph_chunk=graph_chunk, fuse=fuse, rows=rows)
+        results.append({"tile": single["tile"], "persist": single["persist"], "fuse": fuse,
+                        "rows": rows, "ms_per_step": _time(b.step, steps)})
+        b.close()
     best = min(results, key=lambda r: r["ms_per_step"])
-    out = {"tile": best["tile"], "persist": best["persist"], "ms_per_step": best["ms_per_step"],
-           "all": results}
+    out = {k: best[k] for k in ("tile", "persist", "fuse", "rows", "ms_per_step")}
+    out["all"] = results
     _store(path, key, out)
     return out

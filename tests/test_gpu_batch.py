@@ -53,6 +53,40 @@ def test_batch_equals_individual(tile, persist, chunk):
         assert lat.info()["t"] == 53
 
 
+@pytest.mark.parametrize("fuse,rows,chunk", [(4, 6, 8), (3, 6, 0), (3, 14, 16)])
+def test_batch_two_step_equals_individual(fuse, rows, chunk):
+    """Two-step passes over all members in one launch (boundary tiles in the
+    same kernel, or in their own beside it) == each member on its own, also
+    when the batch starts at odd member steps."""
+    wls = _members()
+    log(f"batch two-step fuse {fuse} rows {rows} chunk {chunk}")
+    ref = _make(wls)
+    lats = _make(wls)
+    for lat in ref + lats:
+        lat.step(1)
+    for lat in ref:
+        lat.set_two_step(1)
+        lat.step(45)
+    b = Batch(lats, graph_chunk=chunk, fuse=fuse, rows=rows)
+    b.step(20)
+    b.step(25)
+    b.close()
+    for (fa, ga), (fb, gb) in zip(_states(ref), _states(lats)):
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+    for lat in lats:
+        assert lat.info()["t"] == 46
+
+
+def test_batch_two_step_needs_one_parity():
+    wls = _members()[:2]
+    lats = _make(wls)
+    lats[0].step(1)
+    b = Batch(lats)
+    with pytest.raises(A.GGError) as e:
+        b.set_two_step(4, 6)
+    assert e.value.status == A.GG_ERR_STATE
+
+
 def test_batch_members_at_different_parities():
     wls = _members()
     ref = _make(wls)
@@ -93,5 +127,6 @@ def test_autotuner_picks_and_caches(tmp_path):
     assert again["tile"] == res["tile"] and again["fuse"] == res["fuse"]
     wls = _members()[:3]
     lats = _make(wls)
-    rb = tune.tune_batch(lats, steps=8, tiles=((64, 4), (32, 8)), persist=(0, 256), path=path)
-    assert len(rb["all"]) == 4 and rb["persist"] in (0, 256)
+    rb = tune.tune_batch(lats, steps=8, tiles=((64, 4), (32, 8)), persist=(0, 256),
+                         two_step=((4, 6),), path=path)
+    assert len(rb["all"]) == 5 and rb["persist"] in (0, 256) and rb["fuse"] in (1, 4)
