@@ -287,6 +287,84 @@ void orc_step(const orc_lattice *L, const double *f, const double *g,
 }
 
 /* ---------------------------------------------------------------- */
+/* Compound lattice alone on a frozen velocity field, t -> t+1         */
+/* ---------------------------------------------------------------- */
+
+/* The paper's production path (Results section): the flow reaches its
+ * steady state long before the compound does, so the velocity field of
+ * each valve configuration is computed once and the advection-diffusion
+ * lattice is then advanced on its own, driven by that fixed field. One step
+ * of that lattice: at every fluid node, C = sum g_i, the linear equilibrium
+ * of Eq. (9) with the given u(x), BGK relaxation (Eq. 8) and the reaction
+ * term R - kC of Eq. (2); then free flight with the compound's link rules
+ * (walls and closed valves bounce back, open inlets hold C_in by
+ * anti-bounce-back, open outlets let the compound leave with zero
+ * gradient). ux, uy: ny*nx velocity components (ignored off the fluid).
+ * flux_solute[m] accumulates the compound entering through segment m. */
+void orc_cde_step(const orc_lattice *L, const double *g, double *gn,
+                  const double *ux, const double *uy, const uint8_t *open,
+                  const double *c_in, double *flux_solute) {
+  const int nx = L->nx, ny = L->ny;
+  const size_t n = (size_t)nx * ny;
+  double wg[5];
+  orc_gweights(L->w0, wg);
+  const double omega = 1.0 / L->tau_g;
+
+  double *gp = (double *)calloc(5 * n, sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      size_t node = (size_t)y * nx + x;
+      if (L->mask[node] != 0) continue;
+      const double *gx = g + 5 * node;
+      double C = 0.0;
+      for (int i = 0; i < 5; ++i) C += gx[i];
+      double geq[5];
+      orc_geq(C, ux[node], uy[node], L->w0, geq);
+      double src = (L->R ? L->R[node] : 0.0) - L->k_decay * C;
+      for (int i = 0; i < 5; ++i)
+        gp[5 * node + i] = gx[i] - omega * (gx[i] - geq[i]) + wg[i] * src;
+    }
+
+  memset(gn, 0, sizeof(double) * 5 * n);
+  double *rowflux = (double *)calloc((size_t)ny * 256, sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y) {
+    double *rf = rowflux + (size_t)y * 256;
+    for (int x = 0; x < nx; ++x) {
+      size_t node = (size_t)y * nx + x;
+      if (L->mask[node] != 0) continue;
+      gn[5 * node] = gp[5 * node];
+      for (int i = 1; i < 5; ++i) {
+        int xs = 0, ys = 0;
+        int code = cell_code(L, x - EX[i], y - EY[i], &xs, &ys);
+        double out = gp[5 * node + OPP[i]];
+        if (code == 0) {
+          gn[5 * node + i] = gp[5 * ((size_t)ys * nx + xs) + i];
+          continue;
+        }
+        int kind = (code >= 2) ? L->seg_kind[code] : ORC_SEG_NONE;
+        if (kind != ORC_SEG_NONE && !open[code]) kind = ORC_SEG_NONE;
+        double in;
+        if (kind == ORC_SEG_NONE)
+          in = out;
+        else if (kind == ORC_SEG_INLET)
+          in = -out + 2.0 * wg[i] * c_in[code];
+        else
+          in = gp[5 * node + i];
+        gn[5 * node + i] = in;
+        rf[code] += in - out;
+      }
+    }
+  }
+  for (int y = 0; y < ny; ++y)
+    for (int m = 0; m < 256; ++m)
+      if (flux_solute) flux_solute[m] += rowflux[(size_t)y * 256 + m];
+  free(rowflux);
+  free(gp);
+}
+
+/* ---------------------------------------------------------------- */
 /* Initialisation and read-back                                        */
 /* ---------------------------------------------------------------- */
 

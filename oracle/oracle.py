@@ -71,6 +71,8 @@ def lib() -> ctypes.CDLL:
         for fn in ("orc_feq", "orc_geq", "orc_step", "orc_init_eq",
                    "orc_moments", "orc_totals"):
             getattr(L, fn).restype = None
+        L.orc_cde_step.argtypes = [P] * 8
+        L.orc_cde_step.restype = None
         L.orc_adjoint_step.argtypes = [P] * 9
         L.orc_adjoint_step.restype = None
         L.orc_threads.argtypes = []
@@ -228,6 +230,40 @@ class Oracle:
             self.f, self._fn = self._fn, self.f
             self.g, self._gn = self._gn, self.g
             self.t += 1
+
+    def cde_step(self, n: int, fields: Sequence, phase_field: Optional[Sequence[int]] = None):
+        """Advance only the compound n steps on frozen velocity fields (the
+        paper's decoupled production path); f is left as it is.
+
+        fields: list of (ux, uy) arrays of shape (ny, nx); phase_field[k]:
+        the field used while schedule phase k is in force (default: field 0
+        throughout). Boundary fluxes of the compound go to flux_solute.
+        """
+        fl = [(np.ascontiguousarray(ux, np.float64).reshape(self.ny, self.nx),
+               np.ascontiguousarray(uy, np.float64).reshape(self.ny, self.nx))
+              for ux, uy in fields]
+        L = lib()
+        for _ in range(int(n)):
+            open_, c_in = self.phase(self.t)
+            k = self.phase_index(self.t)
+            ux, uy = fl[phase_field[k] if phase_field is not None else 0]
+            L.orc_cde_step(ctypes.byref(self._c), _ptr(self.g), _ptr(self._gn), _ptr(ux),
+                           _ptr(uy), _ptr(open_), _ptr(c_in), _ptr(self.flux_solute))
+            self.g, self._gn = self._gn, self.g
+            self.t += 1
+
+    def phase_index(self, t: int) -> int:
+        """Index of the schedule phase in force during step t (0 without a
+        schedule)."""
+        if self.schedule is None:
+            return 0
+        period = sum(int(p.duration) for p in self.schedule)
+        tau = (t - self.t_origin) % period
+        for k, p in enumerate(self.schedule):
+            if tau < p.duration:
+                return k
+            tau -= p.duration
+        raise AssertionError("unreachable")
 
     def fields(self):
         """rho, ux, uy, C arrays of shape (ny, nx); NaN off the fluid."""

@@ -11,6 +11,7 @@ import pytest
 from oracle import build_oracle
 from oracle import oracle as orc
 from tests import test_oracle_adjoint as AD
+from tests import test_oracle_cde as CD
 from tests import test_oracle_pins as P
 
 PINS = [
@@ -31,6 +32,9 @@ PINS = [
     (AD.test_adjoint_step_is_transpose_of_forward_step, dict(t_phase=0)),
     (AD.test_adjoint_step_is_transpose_of_forward_step, dict(t_phase=15)),
     (AD.test_adjoint_gradients_match_central_differences, {}),
+    (CD.test_cde_step_equals_the_coupled_compound_update, {}),
+    (CD.test_cde_uniform_velocity_exact_fourier_evolution, {}),
+    (CD.test_cde_closed_box_conserves_solute, {}),
 ]
 
 MUTATIONS = {
@@ -66,6 +70,13 @@ MUTATIONS = {
     "adjoint C_in factor": ("ra[code] += 2.0 * wg[opp]", "ra[code] += 1.0 * wg[opp]"),
     "adjoint omega sign": ("dw -= ls[j] * (gx[j] - W[j] * C);", "dw += ls[j] * (gx[j] - W[j] * C);"),
     "adjoint source weight": ("dr += wg[j] * ls[j];", "dr += ls[j];"),
+    "compound-only relaxation": ("gx[i] - omega * (gx[i] - geq[i])", "gx[i] - omega * (gx[i] + geq[i])"),
+    "compound-only inlet sign": ("in = -out + 2.0 * wg[i] * c_in[code];", "in = out + 2.0 * wg[i] * c_in[code];"),
+    "compound-only outlet direction": ("in = gp[5 * node + i];", "in = gp[5 * node + OPP[i]];"),
+    "compound-only streaming": ("gn[5 * node + i] = gp[5 * ((size_t)ys * nx + xs) + i];",
+                                "gn[5 * node + i] = gp[5 * ((size_t)ys * nx + xs) + OPP[i]];"),
+    "compound-only source": ("+ wg[i] * src;\n    }\n\n  memset(gn", "+ src;\n    }\n\n  memset(gn"),
+    "compound-only wall": ("        if (kind == ORC_SEG_NONE)\n          in = out;", "        if (kind == ORC_SEG_NONE)\n          in = 0.999 * out;"),
     "adjoint wall transpose": ("            ls[j] += lx[opp];\n          } else if (kind == ORC_SEG_INLET) {",
                                "            ls[j] += lx[j];\n          } else if (kind == ORC_SEG_INLET) {"),
 }
