@@ -46,6 +46,7 @@ extern "C" {
 #define GG_FIRST_SEGMENT 2
 #define GG_MAX_SEGMENTS 16
 #define GG_MAX_PHASES 64
+#define GG_MAX_FIELDS 16
 
 typedef enum gg_status {
   GG_OK = 0,
@@ -223,6 +224,44 @@ gg_status gg_set_launch(gg_lattice *lat, int32_t tile_x, int32_t tile_y,
  * first step. Errors: GG_ERR_ARG for other values, GG_ERR_OOM if the
  * planes do not fit. */
 gg_status gg_set_two_step(gg_lattice *lat, int32_t fuse, int32_t strip_h);
+
+/* Compound alone on frozen velocity fields. The paper lets the flow of a
+ * valve configuration settle (it does so far faster than the compound) and
+ * then advances the advection-diffusion lattice alone under that fixed
+ * velocity (Results section): per node a step then moves the 5 compound
+ * populations, 2 velocity components and the link code (FP32 storage: 49
+ * bytes) instead of the 14 populations of the coupled step.
+ *
+ * gg_set_velocity_field stores a velocity field in slot 0..GG_MAX_FIELDS-1
+ * (device memory: two planes of the compute type per slot, FP64 for GG_F64,
+ * FP32 otherwise, allocated on first use and kept until gg_destroy). ux, uy:
+ * nx*ny doubles (y*nx + x; host or device per `where`; only fluid entries
+ * are read, and on the host they must be finite), rounded to the compute
+ * type. With ux = uy = NULL the slot receives the velocity of the current
+ * fluid state, computed as the coupled step computes it (paper Eq. 7 in the
+ * compute type). Synchronises the lattice's stream. Errors: GG_ERR_ARG (slot
+ * out of range, one of ux/uy NULL, non-finite host entries), GG_ERR_OOM. */
+gg_status gg_set_velocity_field(gg_lattice *lat, int32_t slot, const double *ux,
+                                const double *uy, gg_where where);
+
+/* slots[k] (0..GG_MAX_FIELDS-1): the field used while schedule phase k is
+ * in force, k < n <= GG_MAX_PHASES; phases from n on, and every phase after
+ * gg_set_phase_fields(lat, NULL, 0) (the default), use slot 0. Without a
+ * schedule, slots[0] is used throughout. */
+gg_status gg_set_phase_fields(gg_lattice *lat, const int32_t *slots, int32_t n);
+
+/* Advance the compound alone n steps (n even, >= 0; else GG_ERR_ARG): at
+ * every fluid node the compound collides (Eqs. 8-9 with the source of
+ * Eq. 2) with the velocity of the field of the phase in force and streams,
+ * with the link rules of the coupled step for walls, closed valves, inlets
+ * (C_in of the phase) and outlets; solute fluxes through open segments
+ * accumulate as in gg_step. The fluid populations are left untouched and t
+ * advances by n (an even n keeps the fluid planes in the layout that t's
+ * parity expects, so gg_step may follow). With the field of each step equal
+ * to the velocity the coupled step's fluid has at that step, the compound
+ * equals the coupled step's. Asynchronous; replays graphs of graph_chunk
+ * steps (gg_set_launch). GG_ERR_STATE if a phase's slot was never set. */
+gg_status gg_cde_step(gg_lattice *lat, int64_t n);
 
 /* Number of fluid nodes and launched tiles. */
 gg_status gg_info(const gg_lattice *lat, int64_t *n_fluid, int64_t *n_tiles,

@@ -1,0 +1,187 @@
+// gfx950 kernels of the compound lattice alone on frozen velocity fields.
+//
+// The paper computes the flow of each valve configuration once (it reaches
+// its steady state long before the compound does) and then advances the
+// advection-diffusion lattice on its own, driven by that fixed velocity
+// field (Results section). Here a field is a pair of planes in the compute
+// type, one slot per valve configuration, and each schedule phase names the
+// slot it uses. A step reads the 5 compound populations (AA pattern, as in
+// the coupled step), the 2 velocity components and the link code, and
+// writes the 5 populations: per node FP32 5 x 4 x 2 + 2 x 4 + 1 = 49 bytes
+// against 113 for the coupled step. The fluid populations are left alone.
+// The compound arithmetic is the coupled step's (compound_collide and the
+// same link rules), so with the velocity the coupled step's fluid has the
+// result is the coupled step's compound.
+#include "gg_device.h"
+#include "gg_kernels.h"
+#include "gg_node.h"
+
+namespace gg {
+
+namespace {
+
+template <class T>
+__device__ __forceinline__ const GG_GLOBAL T *field_plane(CDesc &L, int slot, int c) {
+  return (const GG_GLOBAL T *)L.ufield + (int64_t)(2 * slot + c) * L.plane;
+}
+
+// One compound-only step over a tile list (one node per lane); ODD is the
+// parity of the step. Block b takes tile (b mod 8) * per_xcd + b / 8, so
+// each XCD does a contiguous run of tiles (work-groups are dealt to the 8
+// XCDs round-robin), and neighbouring tiles, which store into each other's
+// edge lines on odd steps, share an L2.
+template <class S, bool ODD>
+__global__ void __launch_bounds__(256)
+    k_cde(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles, int n_tiles,
+          int per_xcd, int tx_shift, int dt) {
+  using P = Pop<S>;
+  using T = typename P::T;
+  using W = typename P::W;
+  const int tile = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (tile >= n_tiles) return;
+  const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
+  CDesc &L = *(CDesc *)desc;
+  const int tmask = (1 << tx_shift) - 1;
+  const int x = tl.x0 + (int)(threadIdx.x & tmask);
+  const int y = tl.y0 + (int)(threadIdx.x >> tx_shift);
+  const int64_t t = *(const GG_CONST int64_t *)L.t + dt;
+  const bool seg_tile = (tl.flags & TILE_TOUCHES_SEGMENT) != 0;
+  const PhaseNow ph = phase_at(L, t);
+  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+  const uint8_t lc = (x < L.nx && y < L.ny) ? ((const GG_GLOBAL uint8_t *)L.link)[node] : NOT_FLUID;
+  Flux fx;
+  if (lc != NOT_FLUID) {
+    const Planes<W> pl(L);
+    const Neigh nb(L, x, y);
+    T g[5];
+    if (!ODD) {
+#pragma unroll
+      for (int i = 0; i < 5; ++i) g[i] = P::ld(pl.at(9 + i, node));
+    } else {
+      g[0] = P::ld(pl.at(9, node));
+#pragma unroll
+      for (int i = 1; i < 5; ++i)
+        g[i] = ((lc >> (OPP[i] - 1)) & 1) ? P::ld(pl.at(9 + i, node))
+                                         : P::ld(pl.at(9 + OPP[i], nb.idx[OPP[i]]));
+    }
+    const int slot = L.phase_field[ph.index];
+    const T ux = field_plane<T>(L, slot, 0)[node];
+    const T uy = field_plane<T>(L, slot, 1)[node];
+    T pg[5], in_g[5];
+    compound_collide<T>(L, x, y, g, ux, uy, pg);
+    compound_links<T>(L, x, y, lc, seg_tile, ph, pg, in_g, fx, true);
+    if (!ODD) {
+#pragma unroll
+      for (int j = 0; j < 5; ++j) P::st(pl.at(9 + j, node), in_g[j]);
+    } else {
+      P::st(pl.at(9, node), pg[0]);
+#pragma unroll
+      for (int i = 1; i < 5; ++i) P::st(pl.at(9 + i, nb.idx[i]), pg[i]);
+      if (lc != 0) {
+#pragma unroll
+        for (int i = 1; i < 5; ++i)
+          if ((lc >> (i - 1)) & 1) P::st(pl.at(9 + OPP[i], node), in_g[OPP[i]]);
+      }
+    }
+  }
+  if (seg_tile) fx.flush((double *)L.flux);
+}
+
+// Velocity of the current fluid state into field slot `slot` (compute type).
+template <class S>
+__global__ void __launch_bounds__(256)
+    k_capture(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles, int n_tiles,
+              int tx_shift, int slot) {
+  using T = typename Pop<S>::T;
+  const int tile = blockIdx.x;
+  if (tile >= n_tiles) return;
+  const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
+  CDesc &L = *(CDesc *)desc;
+  const int tmask = (1 << tx_shift) - 1;
+  const int x = tl.x0 + (int)(threadIdx.x & tmask);
+  const int y = tl.y0 + (int)(threadIdx.x >> tx_shift);
+  if (x >= L.nx || y >= L.ny) return;
+  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+  const uint8_t lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
+  GG_GLOBAL T *ux = (GG_GLOBAL T *)field_plane<T>(L, slot, 0);
+  GG_GLOBAL T *uy = (GG_GLOBAL T *)field_plane<T>(L, slot, 1);
+  if (lc == NOT_FLUID) {
+    ux[node] = T(0);
+    uy[node] = T(0);
+    return;
+  }
+  const Planes<typename Pop<S>::W> pl(L);
+  const Neigh nb(L, x, y);
+  T f[9], g[5];
+  if (*(const GG_CONST int64_t *)L.t & 1)
+    load_state<S, true>(pl, node, lc, nb, f, g);
+  else
+    load_state<S, false>(pl, node, lc, nb, f, g);
+  T rho, drho, vx, vy;
+  node_velocity<T>(L, f, rho, drho, vx, vy);
+  ux[node] = vx;
+  uy[node] = vy;
+}
+
+// A given field (host order y * nx + x, FP64) into slot `slot`.
+template <class T>
+__global__ void __launch_bounds__(256)
+    k_put_field(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles, int n_tiles,
+                int tx_shift, int slot, const double *__restrict__ ux_in,
+                const double *__restrict__ uy_in) {
+  const int tile = blockIdx.x;
+  if (tile >= n_tiles) return;
+  const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
+  CDesc &L = *(CDesc *)desc;
+  const int tmask = (1 << tx_shift) - 1;
+  const int x = tl.x0 + (int)(threadIdx.x & tmask);
+  const int y = tl.y0 + (int)(threadIdx.x >> tx_shift);
+  if (x >= L.nx || y >= L.ny) return;
+  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+  const int k = y * L.nx + x;
+  ((GG_GLOBAL T *)field_plane<T>(L, slot, 0))[node] = (T)ux_in[k];
+  ((GG_GLOBAL T *)field_plane<T>(L, slot, 1))[node] = (T)uy_in[k];
+}
+
+}  // namespace
+
+hipError_t launch_cde(gg_storage s, bool odd, const LatDesc *d, const Tile *tiles, int n_tiles,
+                      int tx_shift, int dt, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  const int per_xcd = (n_tiles + 7) / 8;
+  const int grid = 8 * per_xcd;
+#define GG_CDE(TYPE)                                                                       \
+  (odd ? k_cde<TYPE, true><<<grid, 256, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt) \
+       : k_cde<TYPE, false><<<grid, 256, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt))
+  switch (s) {
+    case GG_F64: GG_CDE(double); break;
+    case GG_F32: GG_CDE(float); break;
+    case GG_F16_SHIFTED: GG_CDE(__half); break;
+  }
+#undef GG_CDE
+  return hipGetLastError();
+}
+
+hipError_t launch_capture(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
+                          int tx_shift, int slot, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (s) {
+    case GG_F64: k_capture<double><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, slot); break;
+    case GG_F32: k_capture<float><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, slot); break;
+    case GG_F16_SHIFTED: k_capture<__half><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, slot); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_put_field(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
+                            int tx_shift, int slot, const double *ux, const double *uy,
+                            hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (s == GG_F64)
+    k_put_field<double><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, slot, ux, uy);
+  else
+    k_put_field<float><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, slot, ux, uy);
+  return hipGetLastError();
+}
+
+}  // namespace gg

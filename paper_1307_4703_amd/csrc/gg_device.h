@@ -86,6 +86,12 @@ struct LatDesc {
   float seg_inv_w2_f[GG_MAX_SEGMENTS];
   float phase_cin_f[GG_MAX_PHASES][GG_MAX_SEGMENTS];
   float seg_cin_f[GG_MAX_SEGMENTS];
+  // frozen velocity fields of the compound-only step, in the compute type:
+  // component c (0: u_x, 1: u_y) of slot k is the plane starting at element
+  // (2 k + c) * plane of ufield; phase_field[k]: slot used in phase k
+  void *ufield;
+  int32_t n_ufield, ufield_pad;
+  int8_t phase_field[GG_MAX_PHASES];
 };
 
 // Address spaces: the descriptor and tile lists are read-only while a

@@ -27,6 +27,19 @@ hipError_t launch_step2(gg_storage s, bool seg, const LatDesc *d, const Tile *st
 hipError_t launch_tile2(gg_storage s, bool seg, int rows, const LatDesc *d, const Tile *tiles,
                         int n_tiles, int dir, int dt, hipStream_t st);
 
+// Compound-only step on frozen velocity fields (64 x 4 tiles, 256-thread
+// work-groups, XCD-aware tile order as launch_step); odd = parity of the
+// step, dt as for launch_step.
+hipError_t launch_cde(gg_storage s, bool odd, const LatDesc *d, const Tile *tiles, int n_tiles,
+                      int tx_shift, int dt, hipStream_t st);
+// Velocity of the current fluid state into field slot `slot`.
+hipError_t launch_capture(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
+                          int tx_shift, int slot, hipStream_t st);
+// FP64 fields ux, uy (device, y * nx + x) into field slot `slot`.
+hipError_t launch_put_field(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
+                            int tx_shift, int slot, const double *ux, const double *uy,
+                            hipStream_t st);
+
 // Auxiliary kernels: 256-thread work-groups over one lattice's tiles.
 hipError_t launch_init(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                        int tx_shift, const double *rho, const double *ux,

@@ -15,16 +15,17 @@ struct PhaseNow {
   uint32_t open;
   const GG_CONST double *cin;
   const GG_CONST float *cin_f;  // the same in FP32
+  int index;                    // phase number (0 without a schedule)
 };
 
 // Valve phase in force during step t (fixed at the start of the step).
 __device__ __forceinline__ PhaseNow phase_at(CDesc &L, int64_t t) {
-  if (L.n_phases == 0) return {0xFFFFFFFFu, L.seg_cin, L.seg_cin_f};
+  if (L.n_phases == 0) return {0xFFFFFFFFu, L.seg_cin, L.seg_cin_f, 0};
   int64_t tau = (t - L.t_origin) % L.period;
   if (tau < 0) tau += L.period;
   int k = 0;
   while (k + 1 < L.n_phases && L.phase_start[k + 1] <= tau) ++k;
-  return {L.phase_open[k], L.phase_cin[k], L.phase_cin_f[k]};
+  return {L.phase_open[k], L.phase_cin[k], L.phase_cin_f[k], k};
 }
 
 // Inlet parameters of segment s in the compute type T (pre-rounded for FP32).
@@ -171,50 +172,29 @@ struct Flux {
 __device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// Collision of fluid node (x, y) with link code lc, from the deviations f, g
-// of step t (phase ph): post-collision deviations pf, pg, and in_f[j],
-// in_g[j], the value that arrives at (x, y) along direction j at t + 1 when
-// x - e_j is not fluid (bounce-back from a wall or closed valve, or the rule
-// of an open segment). Fluxes through open segments go into fx when count.
-// nbr, when given, holds the mask values of the cells x + e_k (k = 1..8,
-// wrapped on periodic axes, walls beyond the others) loaded beforehand, as
-// bytes k - 1 of nbr[0] (k = 1..4) and nbr[1] (k = 5..8).
+// Density and velocity of the fluid at a node from its deviations df
+// (paper Eq. 7, sum over i = 0..8): rho = rho0 + sum df_i; the rest part
+// w_i rho0 carries no momentum.
 template <class T>
-__device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc, bool seg_tile,
-                                             const PhaseNow &ph, const T *f, const T *g, T *pf,
-                                             T *pg, T *in_f, T *in_g, Flux &fx, bool count,
-                                             const uint32_t *nbr = nullptr) {
-  // Every kernel that advances the lattice inlines this function; the fused
-  // multiply-adds are written out and no other contraction is allowed, so
-  // each of them rounds exactly the same way whatever code surrounds it.
+__device__ __forceinline__ void node_velocity(CDesc &L, const T *f, T &rho, T &drho, T &ux,
+                                              T &uy) {
 #pragma clang fp contract(off)
-  const int nx = L.nx, ny = L.ny, pitch = L.pitch;
-  // Moments of f, paper Eq. 7 (sum over i = 0..8): rho = rho0 + sum df_i;
-  // the rest part w_i rho0 carries no momentum.
-  const T rho0 = (T)L.rho0;
-  const T drho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-  const T rho = rho0 + drho;
+  drho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+  rho = (T)L.rho0 + drho;
   const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const T jy = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
   const T inv_rho = T(1) / rho;
-  const T ux = jx * inv_rho, uy = jy * inv_rho;
-  const T usq = fmad(ux, ux, uy * uy);
+  ux = jx * inv_rho;
+  uy = jy * inv_rho;
+}
 
-  // BGK relaxation of f toward the quadratic equilibrium, Eqs. 4-6, for
-  // the deviations: f^eq_i - w_i rho0 = w_i (drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)).
-  const T om_f = (T)L.omega_f;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const T eu = (T)EX[i] * ux + (T)EY[i] * uy;
-    // 3 e.u + 4.5 (e.u)^2 - 1.5 u.u = e.u (4.5 e.u + 3) - 1.5 u.u
-    const T poly = fmad(eu, fmad(T(4.5), eu, T(3)), T(-1.5) * usq);
-    const T dfeq = (T)WF[i] * fmad(rho, poly, drho);
-    pf[i] = fmad(om_f, dfeq - f[i], f[i]);
-  }
-
-  // Compound: linear equilibrium with this node's u (Eq. 9), BGK (Eq. 8),
-  // source R - kC of Eq. 2 distributed with the lattice weights. With
-  // C = C_s + dC: g^eq_i - w_i C_s = w_i (dC + C e.u / cs2).
+// Compound collision at (x, y) with fluid velocity u: linear equilibrium
+// (Eq. 9), BGK (Eq. 8), source R - kC of Eq. 2 distributed with the
+// lattice weights. With C = C_s + dC: g^eq_i - w_i C_s = w_i (dC + C e.u / cs2).
+template <class T>
+__device__ __forceinline__ void compound_collide(CDesc &L, int x, int y, const T *g, T ux, T uy,
+                                                 T *pg) {
+#pragma clang fp contract(off)
   const T cs = (T)L.c_shift;
   const T dC = g[0] + g[1] + g[2] + g[3] + g[4];
   const T C = cs + dC;
@@ -238,6 +218,47 @@ __device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc,
     const T dgeq = wg[i] * fmad(C * eu, ics, dC);
     pg[i] = fmad(wg[i], src, fmad(om_g, dgeq - g[i], g[i]));
   }
+}
+
+// Collision of fluid node (x, y) with link code lc, from the deviations f, g
+// of step t (phase ph): post-collision deviations pf, pg, and in_f[j],
+// in_g[j], the value that arrives at (x, y) along direction j at t + 1 when
+// x - e_j is not fluid (bounce-back from a wall or closed valve, or the rule
+// of an open segment). Fluxes through open segments go into fx when count.
+// nbr, when given, holds the mask values of the cells x + e_k (k = 1..8,
+// wrapped on periodic axes, walls beyond the others) loaded beforehand, as
+// bytes k - 1 of nbr[0] (k = 1..4) and nbr[1] (k = 5..8).
+template <class T>
+__device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc, bool seg_tile,
+                                             const PhaseNow &ph, const T *f, const T *g, T *pf,
+                                             T *pg, T *in_f, T *in_g, Flux &fx, bool count,
+                                             const uint32_t *nbr = nullptr) {
+  // Every kernel that advances the lattice inlines this function; the fused
+  // multiply-adds are written out and no other contraction is allowed, so
+  // each of them rounds exactly the same way whatever code surrounds it.
+#pragma clang fp contract(off)
+  const int nx = L.nx, ny = L.ny, pitch = L.pitch;
+  const T rho0 = (T)L.rho0;
+  T rho, drho, ux, uy;
+  node_velocity<T>(L, f, rho, drho, ux, uy);
+  const T usq = fmad(ux, ux, uy * uy);
+
+  // BGK relaxation of f toward the quadratic equilibrium, Eqs. 4-6, for
+  // the deviations: f^eq_i - w_i rho0 = w_i (drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)).
+  const T om_f = (T)L.omega_f;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const T eu = (T)EX[i] * ux + (T)EY[i] * uy;
+    // 3 e.u + 4.5 (e.u)^2 - 1.5 u.u = e.u (4.5 e.u + 3) - 1.5 u.u
+    const T poly = fmad(eu, fmad(T(4.5), eu, T(3)), T(-1.5) * usq);
+    const T dfeq = (T)WF[i] * fmad(rho, poly, drho);
+    pf[i] = fmad(om_f, dfeq - f[i], f[i]);
+  }
+
+  compound_collide<T>(L, x, y, g, ux, uy, pg);
+  const T cs = (T)L.c_shift;
+  const T wga = (T)L.wg_axis;
+  const T wg[5] = {T(1) - T(4) * wga, wga, wga, wga, wga};
 
   // Value arriving at x along direction j when x - e_j is not fluid: the
   // bounced population f*(x, opp j) for a wall or closed valve; open
@@ -291,6 +312,45 @@ __device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc,
       if (j < 5) in_g[j] = vg;
       if (count) fx.add(s, dm, dc);
     }
+  }
+}
+
+// Link rules of the compound alone (the compound lines of collide_node):
+// in_g[j], the value arriving at (x, y) along j when x - e_j is not fluid,
+// from the post-collision pg; solute fluxes through open segments into fx.
+template <class T>
+__device__ __forceinline__ void compound_links(CDesc &L, int x, int y, uint8_t lc, bool seg_tile,
+                                               const PhaseNow &ph, const T *pg, T *in_g, Flux &fx,
+                                               bool count) {
+#pragma clang fp contract(off)
+  const int nx = L.nx, ny = L.ny, pitch = L.pitch;
+  const T cs = (T)L.c_shift;
+  const T wga = (T)L.wg_axis;
+  const T wg[5] = {T(1) - T(4) * wga, wga, wga, wga, wga};
+#pragma unroll
+  for (int j = 0; j < 5; ++j) in_g[j] = pg[OPP[j]];
+  if (!seg_tile || lc == 0) return;
+#pragma unroll
+  for (int j = 1; j < 5; ++j) {
+    if (!((lc >> (OPP[j] - 1)) & 1)) continue;  // x - e_j is fluid
+    int sx = x - EX[j], sy = y - EY[j];
+    bool inside = true;
+    if (sx < 0 || sx >= nx) {
+      if (L.periodic_x) sx = (sx + nx) % nx; else inside = false;
+    }
+    if (sy < 0 || sy >= ny) {
+      if (L.periodic_y) sy = (sy + ny) % ny; else inside = false;
+    }
+    const int code = inside ? (int)((const GG_GLOBAL uint8_t *)L.mask)[L.node0 + sy * pitch + sx]
+                            : GG_MASK_WALL;
+    if (code < GG_FIRST_SEGMENT) continue;
+    const int s = code - GG_FIRST_SEGMENT;
+    if (!((ph.open >> s) & 1u)) continue;  // closed valve: a wall
+    const T vg = L.seg_kind[s] == GG_SEG_INLET
+                     ? fmad(T(2) * wg[j], SegT<T>::cin(ph, s) - cs, -pg[OPP[j]])
+                     : pg[j];
+    in_g[j] = vg;
+    if (count) fx.add(s, 0.0, (double)(vg - pg[OPP[j]]));
   }
 }
 

@@ -65,8 +65,19 @@ struct gg_lattice {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  // compound alone on frozen velocity fields: n_ufield slots of two planes
+  // (u_x, u_y) in the compute type; bit k of ufield_set: slot k written;
+  // phase_field[k]: slot used in schedule phase k; graphs of graph_chunk
+  // compound-only steps from an even / odd t
+  void *d_ufield = nullptr;
+  int n_ufield = 0;
+  uint32_t ufield_set = 0;
+  int8_t phase_field[GG_MAX_PHASES] = {};
+  hipGraph_t cde_graph[2] = {nullptr, nullptr};
+  hipGraphExec_t cde_exec[2] = {nullptr, nullptr};
 };
 
 gg_status gg_upload_desc(gg_lattice *L);
 gg_status gg_rebuild_tiles(gg_lattice *L);
 void gg_free_device(gg_lattice *L);
+void gg_drop_cde_graphs(gg_lattice *L);

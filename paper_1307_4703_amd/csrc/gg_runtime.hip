@@ -51,14 +51,24 @@ int ilog2(int v) {
 // Lattice object
 // ---------------------------------------------------------------------------
 
+void gg_drop_cde_graphs(gg_lattice *L) {
+  for (int p = 0; p < 2; ++p) {
+    if (L->cde_exec[p]) (void)hipGraphExecDestroy(L->cde_exec[p]);
+    if (L->cde_graph[p]) (void)hipGraphDestroy(L->cde_graph[p]);
+    L->cde_exec[p] = nullptr;
+    L->cde_graph[p] = nullptr;
+  }
+}
+
 void gg_free_device(gg_lattice *L) {
+  gg_drop_cde_graphs(L);
   if (L->graph_exec) (void)hipGraphExecDestroy(L->graph_exec);
   if (L->graph) (void)hipGraphDestroy(L->graph);
   L->graph_exec = nullptr;
   L->graph = nullptr;
   void *ptrs[] = {L->d_pop, L->d_pop_b, L->d_link, L->d_mask, L->d_region, L->d_R, L->d_t,
                   L->d_flux, L->d_acc, L->d_desc, L->d_tiles, L->d_aux_tiles, L->d_strips,
-                  L->d_seg_strips, L->d_partial};
+                  L->d_seg_strips, L->d_partial, L->d_ufield};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (L->cap_stream) (void)hipStreamDestroy(L->cap_stream);
@@ -128,6 +138,9 @@ gg_status gg_upload_desc(gg_lattice *L) {
     for (int s = 0; s < GG_MAX_SEGMENTS; ++s) h.phase_cin_f[k][s] = (float)h.phase_cin[k][s];
   }
   h.period = start > 0 ? start : 1;
+  h.ufield = L->d_ufield;
+  h.n_ufield = L->n_ufield;
+  for (int k = 0; k < GG_MAX_PHASES; ++k) h.phase_field[k] = L->phase_field[k];
   GG_HIP(hipMemcpyAsync(L->d_desc, &h, sizeof(h), hipMemcpyHostToDevice, L->stream));
   GG_HIP(hipStreamSynchronize(L->stream));
   return GG_OK;
@@ -831,6 +844,7 @@ gg_status gg_set_launch(gg_lattice *L, int32_t tile_x, int32_t tile_y, int32_t g
   // even (a multiple of 4 with the two-step pass): replays keep the parity
   const int q = L->fuse >= 2 ? 4 : 2;
   L->graph_chunk = (graph_chunk + q - 1) / q * q;
+  gg_drop_cde_graphs(L);
   return gg_rebuild_tiles(L);
 }
 
@@ -859,6 +873,7 @@ gg_status gg_set_two_step(gg_lattice *L, int32_t fuse, int32_t strip_h) {
   if (fuse >= 2) L->strip_h = strip_h;
   const int q = fuse >= 2 ? 4 : 2;
   L->graph_chunk = (L->graph_chunk + q - 1) / q * q;
+  gg_drop_cde_graphs(L);
   gg_status st = gg_upload_desc(L);
   if (st != GG_OK) return st;
   return gg_rebuild_tiles(L);
@@ -1386,6 +1401,144 @@ gg_status gg_stream_copy(void *dst, const void *src, size_t bytes, int32_t reps,
   (void)hipEventDestroy(b);
   if (e != hipSuccess) return fail(GG_ERR_HIP, std::string("copy: ") + hipGetErrorString(e));
   *ms = total / reps;
+  return GG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Compound alone on frozen velocity fields
+// ---------------------------------------------------------------------------
+
+static size_t field_esize(const gg_lattice *L) { return L->storage == GG_F64 ? 8 : 4; }
+
+// Grow the field buffer to at least n slots (new slots zero), keeping the
+// contents of the old ones.
+static gg_status grow_fields(gg_lattice *L, int n) {
+  if (n <= L->n_ufield) return GG_OK;
+  const size_t slot_bytes = 2 * (size_t)L->plane * field_esize(L);
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, (size_t)n * slot_bytes);
+  if (e != hipSuccess) return fail(GG_ERR_OOM, std::string("velocity fields: ") + hipGetErrorString(e));
+  e = hipMemset(p, 0, (size_t)n * slot_bytes);
+  if (e == hipSuccess && L->d_ufield)
+    e = hipMemcpy(p, L->d_ufield, (size_t)L->n_ufield * slot_bytes, hipMemcpyDeviceToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(p);
+    return fail(GG_ERR_HIP, std::string("velocity fields: ") + hipGetErrorString(e));
+  }
+  if (L->d_ufield) GG_HIP(hipFree(L->d_ufield));
+  L->d_ufield = p;
+  L->n_ufield = n;
+  return gg_upload_desc(L);
+}
+
+gg_status gg_set_velocity_field(gg_lattice *L, int32_t slot, const double *ux, const double *uy,
+                                gg_where where) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (slot < 0 || slot >= GG_MAX_FIELDS) return fail(GG_ERR_ARG, "slot must lie in 0..GG_MAX_FIELDS-1");
+  if ((ux == nullptr) != (uy == nullptr)) return fail(GG_ERR_ARG, "give both components or neither");
+  GG_HIP(hipStreamSynchronize(L->stream));
+  gg_status st = grow_fields(L, slot + 1);
+  if (st != GG_OK) return st;
+  if (!ux) {
+    GG_HIP(launch_capture(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6, slot, L->stream));
+    GG_HIP(hipStreamSynchronize(L->stream));
+    L->ufield_set |= 1u << slot;
+    return GG_OK;
+  }
+  const size_t n = (size_t)L->nx * L->ny;
+  double *dev[2] = {const_cast<double *>(ux), const_cast<double *>(uy)};
+  if (where == GG_HOST) {
+    for (int q = 0; q < 2; ++q) {
+      const double *src = q ? uy : ux;
+      for (int y = 0; y < L->ny; ++y)
+        for (int x = 0; x < L->nx; ++x)
+          if (L->mask[(size_t)y * L->nx + x] == GG_MASK_FLUID && !std::isfinite(src[(size_t)y * L->nx + x]))
+            return fail(GG_ERR_ARG, "velocity field has non-finite entries on the fluid");
+    }
+    dev[0] = dev[1] = nullptr;
+    for (int q = 0; q < 2 && st == GG_OK; ++q) {
+      if (hipMalloc(&dev[q], n * sizeof(double)) != hipSuccess)
+        st = fail(GG_ERR_OOM, "hipMalloc of a velocity field failed");
+      else if (hipMemcpy(dev[q], q ? uy : ux, n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        st = fail(GG_ERR_HIP, "copy of a velocity field failed");
+    }
+  }
+  if (st == GG_OK) {
+    hipError_t e = launch_put_field(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6, slot,
+                                    dev[0], dev[1], L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) st = fail(GG_ERR_HIP, std::string("velocity field: ") + hipGetErrorString(e));
+  }
+  if (where == GG_HOST)
+    for (int q = 0; q < 2; ++q)
+      if (dev[q]) (void)hipFree(dev[q]);
+  if (st == GG_OK) L->ufield_set |= 1u << slot;
+  return st;
+}
+
+gg_status gg_set_phase_fields(gg_lattice *L, const int32_t *slots, int32_t n) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (n < 0 || n > GG_MAX_PHASES || (n > 0 && !slots))
+    return fail(GG_ERR_ARG, "n must lie in 0..GG_MAX_PHASES with a slot per phase");
+  for (int k = 0; k < n; ++k)
+    if (slots[k] < 0 || slots[k] >= GG_MAX_FIELDS)
+      return fail(GG_ERR_ARG, "slot must lie in 0..GG_MAX_FIELDS-1");
+  GG_HIP(hipStreamSynchronize(L->stream));
+  for (int k = 0; k < GG_MAX_PHASES; ++k) L->phase_field[k] = (int8_t)(k < n ? slots[k] : 0);
+  return gg_upload_desc(L);
+}
+
+// n compound-only steps from a lattice whose counter reads t0 (host mirror),
+// then the counter advances by n.
+static hipError_t launch_cde_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt)
+    e = launch_cde(L->storage, ((t0 + dt) & 1) != 0, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6,
+                   (int)dt, st);
+  if (e == hipSuccess) e = launch_advance(L->d_desc, 1, n, st);
+  return e;
+}
+
+gg_status gg_cde_step(gg_lattice *L, int64_t n) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (n < 0 || (n & 1))
+    return fail(GG_ERR_ARG, "n must be even and non-negative (the fluid planes keep their layout)");
+  gg_status st = check_segments(L);
+  if (st != GG_OK) return st;
+  const int np = std::max<int>(1, (int)L->phases.size());
+  for (int k = 0; k < np; ++k) {
+    const int s = L->phase_field[k];
+    if (s >= L->n_ufield || !((L->ufield_set >> s) & 1u))
+      return fail(GG_ERR_STATE, "velocity field slot " + std::to_string(s) + " of phase " +
+                                    std::to_string(k) + " was never set");
+  }
+  int64_t left = n;
+  const int K = L->graph_chunk;  // even
+  const int par = (int)(L->t & 1);
+  if (K > 0 && left >= K) {
+    if (!L->cde_exec[par]) {
+      GG_HIP(hipStreamBeginCapture(L->cap_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e = launch_cde_steps(L, par, K, L->cap_stream);
+      hipGraph_t g = nullptr;
+      hipError_t e2 = hipStreamEndCapture(L->cap_stream, &g);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(GG_ERR_HIP, std::string("graph capture: ") +
+                                    hipGetErrorString(e != hipSuccess ? e : e2));
+      }
+      L->cde_graph[par] = g;
+      GG_HIP(hipGraphInstantiate(&L->cde_exec[par], g, nullptr, nullptr, 0));
+    }
+    while (left >= K) {
+      GG_HIP(hipGraphLaunch(L->cde_exec[par], L->stream));
+      left -= K;
+      L->t += K;
+    }
+  }
+  if (left > 0) {
+    GG_HIP(launch_cde_steps(L, L->t, left, L->stream));
+    L->t += left;
+  }
   return GG_OK;
 }
 

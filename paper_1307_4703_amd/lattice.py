@@ -157,6 +157,30 @@ class Lattice:
     def sync(self) -> None:
         A.call("gg_sync", self._h)
 
+    # compound alone on frozen velocity fields (include/gg.h, gg_cde_step)
+    def set_velocity_field(self, slot: int, ux: Optional[np.ndarray] = None,
+                           uy: Optional[np.ndarray] = None) -> None:
+        """Store (ux, uy) (host arrays, shape (ny, nx)) in field slot
+        `slot`; with neither given, the velocity of the current fluid state."""
+        if ux is None and uy is None:
+            A.call("gg_set_velocity_field", self._h, int(slot), None, None, A.GG_HOST)
+            return
+        a = np.ascontiguousarray(ux, np.float64).reshape(self.ny, self.nx)
+        b = np.ascontiguousarray(uy, np.float64).reshape(self.ny, self.nx)
+        A.call("gg_set_velocity_field", self._h, int(slot), _dptr(a), _dptr(b), A.GG_HOST)
+
+    def set_phase_fields(self, slots: Optional[Sequence[int]]) -> None:
+        """slots[k]: field slot used in schedule phase k (None: slot 0)."""
+        if not slots:
+            A.call("gg_set_phase_fields", self._h, None, 0)
+            return
+        arr = (ctypes.c_int32 * len(slots))(*[int(v) for v in slots])
+        A.call("gg_set_phase_fields", self._h, arr, len(slots))
+
+    def cde_step(self, n: int = 2) -> None:
+        """Advance the compound alone n (even) steps on the frozen fields."""
+        A.call("gg_cde_step", self._h, int(n))
+
     def adjoint(self, n_steps: int, weight: np.ndarray, target: np.ndarray,
                 r_box: Optional[Sequence[int]] = None, ckpt_every: int = 0) -> dict:
         """Advance n_steps and return L = 1/2 sum weight (C - target)^2 with

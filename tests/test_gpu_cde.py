@@ -1,0 +1,175 @@
+"""GPU parity of the compound-only step on frozen velocity fields (the
+paper's decoupled production path, Results section) against the FP64
+oracle's compound-only step, through the C ABI: given fields per schedule
+phase, fields captured from the fluid state, odd start times, graph replays
+and the full-size gradient generator."""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_1307_4703_amd import workloads as W
+from paper_1307_4703_amd._abi import GGError, GG_ERR_ARG, GG_ERR_STATE
+from tests.parity_util import log, make_lattice, make_oracle, seeded_init
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+# C relative to max(1, max C): FP32 / FP16 storage rounding per step (see
+# the coupled-step parity tests), the field rounded once to FP32
+C_TOL = {"f64": F64_TOL, "f32": 2e-5, "f16": 1e-2}
+
+
+def _fields(shape, seed, amp=0.04):
+    """Two smooth synthetic velocity fields (sums of a few sine modes)."""
+    rng = np.random.default_rng(seed)
+    ny, nx = shape
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    out = []
+    for _ in range(2):
+        comp = []
+        for _c in range(2):
+            v = np.zeros(shape)
+            for _m in range(3):
+                kx, ky = rng.integers(1, 5, 2)
+                ph = rng.random(2) * 2 * np.pi
+                v += np.sin(2 * np.pi * kx * xx / nx + ph[0]) * np.cos(2 * np.pi * ky * yy / ny + ph[1])
+            comp.append(amp / 3 * v)
+        out.append(tuple(comp))
+    return out
+
+
+def _compare(lat, o, fluid, storage, label):
+    _, _, _, C = lat.read()
+    _, _, _, Co = o.fields()
+    f, g = lat.populations()
+    go = np.moveaxis(o.g, 2, 0)
+    errC = float(np.abs(C[fluid] - Co[fluid]).max() / max(1.0, np.abs(Co[fluid]).max()))
+    errg = float(np.abs(g[:, fluid] - go[:, fluid]).max() / max(1e-300, np.abs(go[:, fluid]).max()))
+    log(f"{label}: C err {errC:.3e}, g err {errg:.3e}")
+    assert errC < C_TOL[storage], (label, errC)
+    if storage == "f64":
+        assert errg < F64_TOL, (label, errg)
+    return f
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_given_fields_per_phase(storage):
+    """Ragged 300x150 gradient generator, valves switching every 7 steps,
+    one field per valve phase, source and decay; 40 steps in graph replays
+    of 8 plus plain launches; the fluid populations stay as they were."""
+    wl = W.gradient_generator(nx=300, ny=150, half_period=7, storage=storage)
+    wl.k_decay = 1e-3
+    rng = np.random.default_rng(9)
+    R = np.zeros(wl.mask.shape)
+    R[50:70, 90:130] = 1e-3 * rng.random((20, 40))
+    init = seeded_init(wl, 21)
+    lat = make_lattice(wl, storage, init, chunk=8)
+    lat.set_source(R)
+    fields = _fields(wl.mask.shape, 5)
+    for k, (ux, uy) in enumerate(fields):
+        lat.set_velocity_field(k, ux, uy)
+    lat.set_phase_fields([0, 1])
+    f0, _ = lat.populations()
+    log(f"cde given fields, {storage}")
+    lat.cde_step(18)
+    lat.cde_step(22)
+    o = Oracle(wl.mask, tau_f=wl.tau_f, D=wl.D, w0=wl.w0, rho0=wl.rho0, k_decay=wl.k_decay,
+               segments=wl.segments, schedule=wl.schedule, R=R)
+    o.init(**init)
+    o.cde_step(40, fields, phase_field=[0, 1])
+    fluid = wl.mask == 0
+    f = _compare(lat, o, fluid, storage, f"given fields {storage}")
+    assert np.array_equal(f, f0)
+    d = lat.diagnostics()
+    assert d["t"] == 40
+    tol = {"f64": 1e-11, "f32": 1e-4, "f16": 2e-2}[storage]
+    for sid in (2, 3, 4, 5):
+        assert d["seg_mass"][sid - 2] == 0.0
+        assert d["seg_solute"][sid - 2] == pytest.approx(o.flux_solute[sid], rel=tol, abs=1e-9)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_captured_field_odd_start_then_coupled(storage):
+    """Coupled steps to an odd t, the velocity of that state captured, the
+    compound alone for 24 steps, then coupled steps again: the oracle does
+    the same with the velocity of its own fluid state."""
+    wl = W.gradient_generator(nx=300, ny=150, half_period=9, storage=storage)
+    init = seeded_init(wl, 8)
+    lat = make_lattice(wl, storage, init, chunk=8)
+    o = make_oracle(wl)
+    o.init(**init)
+    lat.step(13)
+    o.step(13)
+    lat.set_velocity_field(0)
+    _, ux, uy, _ = o.fields()
+    log(f"cde captured field, odd start, {storage}")
+    lat.cde_step(24)
+    o.cde_step(24, [(np.nan_to_num(ux), np.nan_to_num(uy))])
+    fluid = wl.mask == 0
+    _compare(lat, o, fluid, storage, f"captured field {storage}")
+    lat.step(7)
+    o.step(7)
+    _compare(lat, o, fluid, storage, f"coupled after cde {storage}")
+    assert lat.info()["t"] == 44
+
+
+def test_periodic_uniform_field_graphs():
+    """Random obstacles on a periodic 133x71 lattice, a uniform field, 64
+    steps as 4 graph replays of 16, FP64."""
+    mask = W.random_mask(133, 71, seed=5, periodic=(True, True))
+    wl = W.Workload("random", mask, tau_f=0.7, D=0.03, periodic=(True, True))
+    init = seeded_init(wl, 2)
+    lat = make_lattice(wl, "f64", init, chunk=16)
+    u = (np.full(mask.shape, 0.05), np.full(mask.shape, -0.03))
+    lat.set_velocity_field(3, *u)
+    lat.set_phase_fields([3])
+    lat.cde_step(64)
+    o = make_oracle(wl)
+    o.init(**init)
+    o.cde_step(64, [u])
+    _compare(lat, o, mask == 0, "f64", "periodic uniform")
+
+
+def test_argument_and_state_errors():
+    wl = W.gradient_generator(nx=300, ny=150, half_period=7, storage="f32")
+    lat = make_lattice(wl, "f32", seeded_init(wl, 1))
+    with pytest.raises(GGError) as e:
+        lat.cde_step(2)  # no field set
+    assert e.value.status == GG_ERR_STATE
+    lat.set_velocity_field(0)
+    with pytest.raises(GGError) as e:
+        lat.cde_step(3)  # odd n would leave the fluid planes in the wrong layout
+    assert e.value.status == GG_ERR_ARG
+    lat.set_phase_fields([0, 2])
+    with pytest.raises(GGError) as e:
+        lat.cde_step(2)  # phase 1 names slot 2, never set
+    assert e.value.status == GG_ERR_STATE
+    with pytest.raises(GGError) as e:
+        lat.set_velocity_field(16)
+    assert e.value.status == GG_ERR_ARG
+    lat.set_phase_fields(None)
+    lat.cde_step(2)
+    assert lat.info()["t"] == 2
+
+
+def test_full_size_gradient_generator_f32():
+    """The 2048x1024 FP32 gradient generator in the launch form the bench
+    times (graph replays of 64 steps): 200 compound-only steps on the
+    velocity captured from the initial state against the oracle on the
+    whole field, and the solute balance (change = net inflow, no source)."""
+    wl = W.gradient_generator()
+    init = seeded_init(wl, 4703)
+    lat = make_lattice(wl, "f32", init)
+    lat.set_velocity_field(0)
+    d0 = lat.diagnostics()
+    log("cde full size 2048x1024 f32, 200 steps")
+    lat.cde_step(200)
+    d1 = lat.diagnostics()
+    o = make_oracle(wl)
+    o.init(**init)
+    _, ux, uy, _ = o.fields()
+    o.cde_step(200, [(np.nan_to_num(ux), np.nan_to_num(uy))])
+    _compare(lat, o, wl.mask == 0, "f32", "full size f32")
+    net_in = sum(d1["seg_solute"]) - sum(d0["seg_solute"])
+    assert d1["solute"] - d0["solute"] == pytest.approx(net_in, rel=1e-5, abs=1e-6 * d0["solute"])
+    assert d1["mass"] == d0["mass"]
