@@ -26,7 +26,8 @@ STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
 CSRC = os.path.join(ROOT, "paper_1307_4703_amd", "csrc")
 # sources of the dominant kernel (the two-step pass); the counters in
 # profiles/traffic.json hold for the hash of these files
-KERNEL_SRC = [os.path.join(CSRC, f) for f in ("gg_device.h", "gg_node.h", "gg_fused.hip")]
+KERNEL_SRC = [os.path.join(CSRC, f)
+              for f in ("gg_device.h", "gg_node.h", "gg_fused.hip", "gg_cde.hip")]
 
 
 def log(msg):
@@ -73,7 +74,8 @@ def kernel_hash():
 
 def load_traffic(wl_name):
     """HBM bytes per step launch from committed rocprofv3 counter runs, or
-    None when they are missing or were taken on another kernel source."""
+    None when they are missing or were taken on another kernel source
+    (wl_name "cde:<workload>" for the compound-only step)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -222,6 +224,65 @@ def batch_bench(steps=2000, seq_steps=400, n=64, seed=4703, tune_steps=32):
             "achieved_gbs": round(nf * bytes_per_update("f32") * steps / t_b / 1e9, 1)}
 
 
+def cde_bytes_per_update(storage):
+    # compound-only step: the 5 compound populations read once and written
+    # once, the two components of the frozen velocity field read (FP64 for
+    # FP64 storage, FP32 otherwise), the 1-byte link code
+    return 5 * 2 * STORAGE_BYTES[storage] + 2 * (8 if storage == "f64" else 4) + 1
+
+
+def cde_bench(name, steps, flow_steps, rows, chunk=64):
+    """The compound alone on a frozen velocity field (the paper's decoupled
+    path): the flow developed for flow_steps coupled steps, its velocity
+    captured into a field slot, then graph-replayed compound-only steps
+    (two-step passes over tiles of `rows` rows, or single steps with rows 0)
+    timed with HIP events on the lattice's stream."""
+    import torch
+    from paper_1307_4703_amd import Lattice
+    wl = workload(name)
+    lat = Lattice.from_workload(wl)
+    lat.set_launch(64, 4, chunk)
+    nf = lat.info()["n_fluid"]
+    lat.step(flow_steps)
+    lat.set_velocity_field(0)
+    lat.set_cde_launch(rows)
+    lat.cde_step(4 * max(chunk, 4))
+    lat.sync()
+    log(f"compound only, {wl.name}: {steps} steps (rows {rows}) on the field after "
+        f"{flow_steps} coupled steps")
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    lat.cde_step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    d = lat.diagnostics(check_finite=False)
+    lat.close()
+    bpu = cde_bytes_per_update(wl.storage)
+    spl = 2 if rows else 1  # steps per launch
+    launch_ms = ms * spl
+    ach = nf * bpu / (launch_ms * 1e-3) / 1e9
+    return {"workload": wl.name, "storage": wl.storage, "n_fluid": nf, "steps": steps,
+            "launch_form": {"rows": rows, "steps_per_launch": spl},
+            "mlups": round(nf / (ms * 1e-3) / 1e6, 1),
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
+                         "traffic": load_traffic("cde:" + name),
+                         "algorithmic_bytes_per_launch": nf * bpu,
+                         "kernel_ms": round(launch_ms, 5),
+                         "update_rate_frac_of_single_step_roofline":
+                             round(nf * bpu * spl / (launch_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
+            "n_nonfinite": d["n_nonfinite"]}
+
+
+# (workload, timed steps, coupled steps that develop the flow first, rows of
+# the two-step tiles or 0 for single steps, as measured fastest on this GPU)
+CDE_LEG = (("gg2048_f32", 4096, 2000, 14), ("allfluid8192_f32", 512, 64, 14),
+           ("gg8192_f16", 1024, 512, 0))
+
+
 def cpu_baseline(name, budget_s=15.0):
     """The FP64 oracle, as it stands, on the host cores: a bounded number of
     steps of the same workload from its initial state."""
@@ -293,9 +354,11 @@ def digest_counters(prof_dir, grids, out_path):
                         "write_bytes": round(write.get(k, 0.0) * 1024 * ws)}
         tot = [v["fetch_bytes"] + v["write_bytes"] for v in par.values()]
         bpl = round(sum(tot) / len(tot))
-        wl = workload(name)
+        cde = name.startswith("cde:")
+        wl = workload(name[4:] if cde else name)
         import numpy as np
-        alg = int(np.count_nonzero(wl.mask == 0)) * bytes_per_update(wl.storage)
+        bpu = cde_bytes_per_update(wl.storage) if cde else bytes_per_update(wl.storage)
+        alg = int(np.count_nonzero(wl.mask == 0)) * bpu
         data["workloads"][name] = {"bytes_per_launch": bpl, "algorithmic_bytes_per_launch": alg,
                                    "ratio_to_algorithmic": round(bpl / alg, 4),
                                    "per_kernel": par, "grid_size": grid, "kernel": kname}
@@ -321,6 +384,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances leg")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the out-of-cache and FP16 lattices and the copy bandwidth")
+    ap.add_argument("--cde-only", action="store_true",
+                    help="time only the compound-only step on frozen velocity fields")
+    ap.add_argument("--cde-steps", type=int, default=0,
+                    help="timed compound-only steps per lattice (0: the defaults)")
     ap.add_argument("--digest", metavar="DIR",
                     help="no run: digest rocprofv3 counter CSVs under DIR into profiles/traffic.json")
     ap.add_argument("--grids", default="",
@@ -342,6 +409,11 @@ def main():
         sys.exit(2)
     torch.cuda.set_device(0)
     tile = tuple(int(v) for v in args.tile.split("x"))
+    cde_leg = [(n, args.cde_steps or k, f, r) for n, k, f, r in CDE_LEG]
+    if args.cde_only:
+        print(json.dumps({name: cde_bench(name, steps, flow, rows, args.chunk)
+                          for name, steps, flow, rows in cde_leg}), flush=True)
+        return
 
     form = "tune" if args.tune else ({"fuse": args.fuse, "rows": args.rows} if args.fuse else None)
     r = time_lattice(args.workload, args.steps, args.warmup, tile, args.chunk, form)
@@ -388,6 +460,9 @@ def main():
             e["storage"] = r2["wl"].storage
             extra[name] = e
         out["roofline_other_lattices"] = extra
+        out["compound_only_frozen_velocity"] = {
+            name: cde_bench(name, steps, flow, rows, args.chunk)
+            for name, steps, flow, rows in cde_leg}
         if not args.no_batch:
             out["batched_64_instances"] = batch_bench()
     if not args.no_cpu_baseline:

@@ -232,17 +232,21 @@ gg_status gg_set_two_step(gg_lattice *lat, int32_t fuse, int32_t strip_h);
  * populations, 2 velocity components and the link code (FP32 storage: 49
  * bytes) instead of the 14 populations of the coupled step.
  *
- * gg_set_velocity_field stores a velocity field in slot 0..GG_MAX_FIELDS-1
- * (device memory: two planes of the compute type per slot, FP64 for GG_F64,
- * FP32 otherwise, allocated on first use and kept until gg_destroy). ux, uy:
- * nx*ny doubles (y*nx + x; host or device per `where`; only fluid entries
- * are read, and on the host they must be finite), rounded to the compute
- * type. With ux = uy = NULL the slot receives the velocity of the current
- * fluid state, computed as the coupled step computes it (paper Eq. 7 in the
- * compute type). Synchronises the lattice's stream. Errors: GG_ERR_ARG (slot
- * out of range, one of ux/uy NULL, non-finite host entries), GG_ERR_OOM. */
+ * gg_set_velocity_field stores scale times a velocity field in slot
+ * 0..GG_MAX_FIELDS-1 (device memory: two planes of the compute type per
+ * slot, FP64 for GG_F64, FP32 otherwise, allocated on first use and kept
+ * until gg_destroy). ux, uy: nx*ny doubles (y*nx + x; host or device per
+ * `where`; only fluid entries are read, and on the host they must be
+ * finite); scale * u is formed in FP64 and rounded to the compute type.
+ * With ux = uy = NULL the slot receives scale times the velocity of the
+ * current fluid state, computed as the coupled step computes it (paper
+ * Eq. 7 in the compute type), times scale in the compute type. scale rescales a
+ * flow computed at one time step to the compound lattice's larger one (the
+ * paper raises the peak velocity to its chosen U^LB this way). Synchronises
+ * the lattice's stream. Errors: GG_ERR_ARG (slot out of range, one of ux/uy
+ * NULL, non-finite scale or host entries), GG_ERR_OOM. */
 gg_status gg_set_velocity_field(gg_lattice *lat, int32_t slot, const double *ux,
-                                const double *uy, gg_where where);
+                                const double *uy, double scale, gg_where where);
 
 /* slots[k] (0..GG_MAX_FIELDS-1): the field used while schedule phase k is
  * in force, k < n <= GG_MAX_PHASES; phases from n on, and every phase after
@@ -260,8 +264,19 @@ gg_status gg_set_phase_fields(gg_lattice *lat, const int32_t *slots, int32_t n);
  * parity expects, so gg_step may follow). With the field of each step equal
  * to the velocity the coupled step's fluid has at that step, the compound
  * equals the coupled step's. Asynchronous; replays graphs of graph_chunk
- * steps (gg_set_launch). GG_ERR_STATE if a phase's slot was never set. */
+ * steps (gg_set_launch). GG_ERR_STATE if a phase's slot was never set.
+ * Steps from an even t go in two-step passes (see gg_set_cde_launch) while
+ * the second plane set exists (gg_set_two_step with fuse >= 2, the
+ * default); the result is the same bit for bit either way. */
 gg_status gg_cde_step(gg_lattice *lat, int64_t n);
+
+/* Launch form of gg_cde_step: rows = 6 or 14 (the default) runs pairs of
+ * steps as one pass over memory, one work-group of rows + 2 wavefronts per
+ * tile of 62 columns x rows, which reads the compound state and the field
+ * once and writes the state two steps later into the second plane set
+ * (the compound planes only); rows = 0 keeps to single steps. GG_ERR_ARG
+ * for other values. */
+gg_status gg_set_cde_launch(gg_lattice *lat, int32_t rows);
 
 /* Number of fluid nodes and launched tiles. */
 gg_status gg_info(const gg_lattice *lat, int64_t *n_fluid, int64_t *n_tiles,

@@ -92,9 +92,10 @@ SIGS = {
     "gg_step_timed": [P, I64, ctypes.POINTER(D), ctypes.POINTER(D)],
     "gg_set_two_step": [P, I32, I32],
     "gg_step2_timed": [P, I64, ctypes.POINTER(D)],
-    "gg_set_velocity_field": [P, I32, P, P, ctypes.c_int],
+    "gg_set_velocity_field": [P, I32, P, P, D, ctypes.c_int],
     "gg_set_phase_fields": [P, P, I32],
     "gg_cde_step": [P, I64],
+    "gg_set_cde_launch": [P, I32],
     "gg_adjoint": [P, I64, I64, P, P, P, P, ctypes.POINTER(gg_grads)],
     "gg_batch_create": [ctypes.POINTER(P), I32, I32, I32, I32, I32, ctypes.POINTER(P)],
     "gg_batch_step": [P, I64],

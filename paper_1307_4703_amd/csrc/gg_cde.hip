@@ -87,11 +87,116 @@ __global__ void __launch_bounds__(256)
   if (seg_tile) fx.flush((double *)L.flux);
 }
 
-// Velocity of the current fluid state into field slot `slot` (compute type).
+// Two compound-only steps in one pass (t even, natural order in): one
+// work-group of R + 2 wavefronts per tile of 62 columns x (flags >> 8) rows,
+// wavefront w on lattice row y0 - 1 + w, lanes on the columns x0 - 1 ..
+// x0 + 62. Every wavefront does step t on its row (the halo once more for
+// the populations it sends into the tile); g1 and g3 cross columns through
+// lane shifts, g2 and g4 cross rows through LDS; after one barrier the
+// owned rows do step t + 1 and store the state at t + 2 in natural order
+// into the other plane set. The velocity is read once for both steps
+// (again only when the phase of step t + 1 uses another field). The values
+// between the steps are rounded to the storage type, as a store and load
+// would round them, so the result is the single steps' bit for bit. Per
+// node and pass (FP32): 5 populations read and written, 2 field values and
+// the link code read, 49 bytes for two steps.
+template <class S, int R>
+__global__ void __launch_bounds__((R + 2) * 64)
+    k_cde_tile2(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles, int n_tiles,
+                int per_xcd, int dir, int dt) {
+  using P = Pop<S>;
+  using T = typename P::T;
+  using W = typename P::W;
+  __shared__ T lds_up[R + 2][64];
+  __shared__ T lds_dn[R + 2][64];
+  const int lane = (int)(threadIdx.x & 63);
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int tile = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (tile >= n_tiles) return;  // the whole work-group
+  const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
+  CDesc &L = *(CDesc *)desc;
+  const int nx = L.nx, ny = L.ny;
+  const int rows = strip_rows(tl.flags);
+  const int64_t t = *(const GG_CONST int64_t *)L.t + dt;
+  const bool seg = (tl.flags & TILE_TOUCHES_SEGMENT) != 0;
+  const PhaseNow ph1 = phase_at(L, t);
+  const PhaseNow ph2 = phase_at(L, t + 1);
+  const int s1 = L.phase_field[ph1.index];
+  const int s2 = L.phase_field[ph2.index];
+  const Planes<W> src(dir ? L.pop_b : L.pop, L.plane);
+  const Planes<W> dst(dir ? L.pop : L.pop_b, L.plane);
+
+  const int xr = tl.x0 - 1 + lane;
+  int x = xr;
+  if (L.periodic_x) x = xr < 0 ? xr + nx : (xr >= nx ? xr - nx : xr);
+  const bool col = xr >= -1 && xr <= nx;
+  const bool own_col = lane >= 1 && lane <= STRIP_W && xr >= 0 && xr < nx;
+  const int yr = tl.y0 - 1 + w;
+  int y = yr;
+  if (L.periodic_y) y = yr < 0 ? yr + ny : (yr >= ny ? yr - ny : yr);
+  const bool row = yr >= -1 && yr <= ny && w <= rows + 1;
+  const bool own = own_col && w >= 1 && w <= rows && yr < ny;
+  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+  uint8_t lc = NOT_FLUID;
+  T g[5], ux = T(0), uy = T(0);
+  if (row && col) {
+    lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) g[i] = P::ld(src.at(9 + i, node));
+    ux = field_plane<T>(L, s1, 0)[node];
+    uy = field_plane<T>(L, s1, 1)[node];
+  }
+
+  // step t on this row
+  Flux fx;
+  T pg[5], ing[5];
+  if (lc != NOT_FLUID) {
+    compound_collide<T>(L, x, y, g, ux, uy, pg);
+    compound_links<T>(L, x, y, lc, seg, ph1, pg, ing, fx, own);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) pg[i] = ing[i] = T(0);
+  }
+  const T z1 = from_left(pg[1]), z3 = from_right(pg[3]);
+  lds_up[w][lane] = pg[2];
+  lds_dn[w][lane] = pg[4];
+  __syncthreads();
+
+  // step t + 1 on the owned rows
+  if (own && lc != NOT_FLUID) {
+    T sg[5];
+    sg[0] = P::rt(pg[0]);
+    sg[1] = P::rt(src_solid(lc, 1) ? ing[1] : z1);
+    sg[3] = P::rt(src_solid(lc, 3) ? ing[3] : z3);
+    sg[2] = P::rt(src_solid(lc, 2) ? ing[2] : lds_up[w - 1][lane]);
+    sg[4] = P::rt(src_solid(lc, 4) ? ing[4] : lds_dn[w + 1][lane]);
+    if (s2 != s1) {
+      ux = field_plane<T>(L, s2, 0)[node];
+      uy = field_plane<T>(L, s2, 1)[node];
+    }
+    T qg[5], jg[5];
+    compound_collide<T>(L, x, y, sg, ux, uy, qg);
+    compound_links<T>(L, x, y, lc, seg, ph2, qg, jg, fx, true);
+    const Neigh nb(L, x, y);
+    P::st(dst.at(9, node), qg[0]);
+#pragma unroll
+    for (int i = 1; i < 5; ++i) P::st(dst.at(9 + i, nb.idx[i]), qg[i]);
+    if (lc != 0) {
+      // x + e_i not fluid: the value arriving along opp(i) stays here
+#pragma unroll
+      for (int i = 1; i < 5; ++i)
+        if ((lc >> (i - 1)) & 1) P::st(dst.at(9 + OPP[i], node), jg[OPP[i]]);
+    }
+  }
+  if (seg) fx.flush((double *)L.flux);
+}
+
+// Velocity of the current fluid state times scale into field slot `slot`
+// (compute type; the product rounded once).
 template <class S>
 __global__ void __launch_bounds__(256)
     k_capture(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles, int n_tiles,
-              int tx_shift, int slot) {
+              int tx_shift, int slot, double scale) {
   using T = typename Pop<S>::T;
   const int tile = blockIdx.x;
   if (tile >= n_tiles) return;
@@ -119,16 +224,17 @@ __global__ void __launch_bounds__(256)
     load_state<S, false>(pl, node, lc, nb, f, g);
   T rho, drho, vx, vy;
   node_velocity<T>(L, f, rho, drho, vx, vy);
-  ux[node] = vx;
-  uy[node] = vy;
+  ux[node] = vx * (T)scale;
+  uy[node] = vy * (T)scale;
 }
 
-// A given field (host order y * nx + x, FP64) into slot `slot`.
+// A given field (host order y * nx + x, FP64) times scale into slot `slot`
+// (the product in FP64, then rounded to the compute type).
 template <class T>
 __global__ void __launch_bounds__(256)
     k_put_field(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles, int n_tiles,
                 int tx_shift, int slot, const double *__restrict__ ux_in,
-                const double *__restrict__ uy_in) {
+                const double *__restrict__ uy_in, double scale) {
   const int tile = blockIdx.x;
   if (tile >= n_tiles) return;
   const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
@@ -139,8 +245,8 @@ __global__ void __launch_bounds__(256)
   if (x >= L.nx || y >= L.ny) return;
   const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
   const int k = y * L.nx + x;
-  ((GG_GLOBAL T *)field_plane<T>(L, slot, 0))[node] = (T)ux_in[k];
-  ((GG_GLOBAL T *)field_plane<T>(L, slot, 1))[node] = (T)uy_in[k];
+  ((GG_GLOBAL T *)field_plane<T>(L, slot, 0))[node] = (T)(scale * ux_in[k]);
+  ((GG_GLOBAL T *)field_plane<T>(L, slot, 1))[node] = (T)(scale * uy_in[k]);
 }
 
 }  // namespace
@@ -162,25 +268,53 @@ hipError_t launch_cde(gg_storage s, bool odd, const LatDesc *d, const Tile *tile
   return hipGetLastError();
 }
 
+hipError_t launch_cde_tile2(gg_storage s, int rows, const LatDesc *d, const Tile *tiles,
+                            int n_tiles, int dir, int dt, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  const int per_xcd = (n_tiles + 7) / 8;
+  const int grid = 8 * per_xcd;
+#define GG_CDE2(TYPE, RV) \
+  k_cde_tile2<TYPE, RV><<<grid, ((RV) + 2) * 64, 0, st>>>(d, tiles, n_tiles, per_xcd, dir, dt)
+#define GG_CDE2_R(TYPE)                    \
+  do {                                     \
+    if (rows <= 6) GG_CDE2(TYPE, 6);       \
+    else GG_CDE2(TYPE, 14);                \
+  } while (0)
+  switch (s) {
+    case GG_F64: GG_CDE2_R(double); break;
+    case GG_F32: GG_CDE2_R(float); break;
+    case GG_F16_SHIFTED: GG_CDE2_R(__half); break;
+  }
+#undef GG_CDE2_R
+#undef GG_CDE2
+  return hipGetLastError();
+}
+
 hipError_t launch_capture(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
-                          int tx_shift, int slot, hipStream_t st) {
+                          int tx_shift, int slot, double scale, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   switch (s) {
-    case GG_F64: k_capture<double><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, slot); break;
-    case GG_F32: k_capture<float><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, slot); break;
-    case GG_F16_SHIFTED: k_capture<__half><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, slot); break;
+    case GG_F64:
+      k_capture<double><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, slot, scale);
+      break;
+    case GG_F32:
+      k_capture<float><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, slot, scale);
+      break;
+    case GG_F16_SHIFTED:
+      k_capture<__half><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, slot, scale);
+      break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_put_field(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                             int tx_shift, int slot, const double *ux, const double *uy,
-                            hipStream_t st) {
+                            double scale, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   if (s == GG_F64)
-    k_put_field<double><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, slot, ux, uy);
+    k_put_field<double><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, slot, ux, uy, scale);
   else
-    k_put_field<float><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, slot, ux, uy);
+    k_put_field<float><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, slot, ux, uy, scale);
   return hipGetLastError();
 }
 

@@ -32,14 +32,6 @@ namespace gg {
 
 namespace {
 
-constexpr int STRIP_W = 62;  // owned columns per wavefront
-
-// x - e_j is not fluid for a node with link code lc (j = 1..8)
-__device__ __forceinline__ bool src_solid(uint8_t lc, int j) { return (lc >> (OPP[j] - 1)) & 1; }
-
-template <class T> __device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1); }
-template <class T> __device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1); }
-
 // Step t + 1 at node (x, y) from its state sf, sg at t + 1 (natural order),
 // with the post-collision populations pushed into the neighbours' slots of
 // the destination planes (or, toward a non-fluid neighbour, the value that
@@ -72,9 +64,6 @@ __device__ __forceinline__ void second_step(CDesc &L, const Planes<typename Pop<
       if ((lc >> (i - 1)) & 1) P::st(dst.at(9 + OPP[i], node), jg[OPP[i]]);
   }
 }
-
-// Height of a strip (rows) is kept in the tile flags above bit 8.
-__device__ __forceinline__ int strip_rows(int flags) { return flags >> 8; }
 
 template <class S, bool SEG>
 __device__ __forceinline__ void strip_two_steps(const LatDesc *__restrict__ descs,

@@ -32,13 +32,19 @@ hipError_t launch_tile2(gg_storage s, bool seg, int rows, const LatDesc *d, cons
 // step, dt as for launch_step.
 hipError_t launch_cde(gg_storage s, bool odd, const LatDesc *d, const Tile *tiles, int n_tiles,
                       int tx_shift, int dt, hipStream_t st);
-// Velocity of the current fluid state into field slot `slot`.
+// Two compound-only steps in one pass (t even, natural order in): one
+// work-group of rows + 2 wavefronts per tile of 62 columns x (flags >> 8)
+// rows, rows 6 or 14; dir 0 reads the compound planes of pop and writes
+// those of pop_b, dir 1 the reverse; dt as for launch_step.
+hipError_t launch_cde_tile2(gg_storage s, int rows, const LatDesc *d, const Tile *tiles,
+                            int n_tiles, int dir, int dt, hipStream_t st);
+// Velocity of the current fluid state times `scale` into field slot `slot`.
 hipError_t launch_capture(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
-                          int tx_shift, int slot, hipStream_t st);
-// FP64 fields ux, uy (device, y * nx + x) into field slot `slot`.
+                          int tx_shift, int slot, double scale, hipStream_t st);
+// FP64 fields scale * ux, scale * uy (device, y * nx + x) into slot `slot`.
 hipError_t launch_put_field(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                             int tx_shift, int slot, const double *ux, const double *uy,
-                            hipStream_t st);
+                            double scale, hipStream_t st);
 
 // Auxiliary kernels: 256-thread work-groups over one lattice's tiles.
 hipError_t launch_init(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,

@@ -168,6 +168,17 @@ struct Flux {
   }
 };
 
+// Pieces of the two-step passes: 62 owned columns per wavefront (lanes 1..62
+// of the columns x0 - 1 .. x0 + 62), the row count of a tile or strip kept
+// in its flags above bit 8, lane shifts that carry a population one column
+// right (from_left) or left (from_right), and the test whether x - e_j is
+// not fluid for a node with link code lc (j = 1..8).
+constexpr int STRIP_W = 62;
+__device__ __forceinline__ int strip_rows(int flags) { return flags >> 8; }
+template <class T> __device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1); }
+template <class T> __device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1); }
+__device__ __forceinline__ bool src_solid(uint8_t lc, int j) { return (lc >> (OPP[j] - 1)) & 1; }
+
 // Fused multiply-add with one rounding, for both compute types.
 __device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }

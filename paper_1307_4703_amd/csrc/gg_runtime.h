@@ -73,6 +73,11 @@ struct gg_lattice {
   int n_ufield = 0;
   uint32_t ufield_set = 0;
   int8_t phase_field[GG_MAX_PHASES] = {};
+  // compound-only steps in two-step passes over tiles of cde_rows rows (6 or
+  // 14; 0: single steps only); the tile list is built on first use
+  int cde_rows = 14;
+  gg::Tile *d_cde_tiles = nullptr;
+  int n_cde_tiles = 0, cde_tiles_rows = 0;
   hipGraph_t cde_graph[2] = {nullptr, nullptr};
   hipGraphExec_t cde_exec[2] = {nullptr, nullptr};
 };

@@ -68,7 +68,7 @@ void gg_free_device(gg_lattice *L) {
   L->graph = nullptr;
   void *ptrs[] = {L->d_pop, L->d_pop_b, L->d_link, L->d_mask, L->d_region, L->d_R, L->d_t,
                   L->d_flux, L->d_acc, L->d_desc, L->d_tiles, L->d_aux_tiles, L->d_strips,
-                  L->d_seg_strips, L->d_partial, L->d_ufield};
+                  L->d_seg_strips, L->d_partial, L->d_ufield, L->d_cde_tiles};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (L->cap_stream) (void)hipStreamDestroy(L->cap_stream);
@@ -1432,15 +1432,17 @@ static gg_status grow_fields(gg_lattice *L, int n) {
 }
 
 gg_status gg_set_velocity_field(gg_lattice *L, int32_t slot, const double *ux, const double *uy,
-                                gg_where where) {
+                                double scale, gg_where where) {
   if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (!std::isfinite(scale)) return fail(GG_ERR_ARG, "scale must be finite");
   if (slot < 0 || slot >= GG_MAX_FIELDS) return fail(GG_ERR_ARG, "slot must lie in 0..GG_MAX_FIELDS-1");
   if ((ux == nullptr) != (uy == nullptr)) return fail(GG_ERR_ARG, "give both components or neither");
   GG_HIP(hipStreamSynchronize(L->stream));
   gg_status st = grow_fields(L, slot + 1);
   if (st != GG_OK) return st;
   if (!ux) {
-    GG_HIP(launch_capture(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6, slot, L->stream));
+    GG_HIP(launch_capture(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6, slot, scale,
+                          L->stream));
     GG_HIP(hipStreamSynchronize(L->stream));
     L->ufield_set |= 1u << slot;
     return GG_OK;
@@ -1465,7 +1467,7 @@ gg_status gg_set_velocity_field(gg_lattice *L, int32_t slot, const double *ux, c
   }
   if (st == GG_OK) {
     hipError_t e = launch_put_field(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6, slot,
-                                    dev[0], dev[1], L->stream);
+                                    dev[0], dev[1], scale, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     if (e != hipSuccess) st = fail(GG_ERR_HIP, std::string("velocity field: ") + hipGetErrorString(e));
   }
@@ -1488,13 +1490,53 @@ gg_status gg_set_phase_fields(gg_lattice *L, const int32_t *slots, int32_t n) {
   return gg_upload_desc(L);
 }
 
+gg_status gg_set_cde_launch(gg_lattice *L, int32_t rows) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (rows != 0 && rows != 6 && rows != 14) return fail(GG_ERR_ARG, "rows must be 0, 6 or 14");
+  GG_HIP(hipStreamSynchronize(L->stream));
+  L->cde_rows = rows;
+  gg_drop_cde_graphs(L);
+  return GG_OK;
+}
+
+// Tile list of the compound-only passes for the current row count.
+static gg_status cde_tiles(gg_lattice *L) {
+  if (L->cde_rows == 0 || L->cde_tiles_rows == L->cde_rows) return GG_OK;
+  std::vector<Tile> list, unused;
+  build_strips(L, L->cde_rows, 0, false, list, unused);
+  if (L->d_cde_tiles) GG_HIP(hipFree(L->d_cde_tiles));
+  L->d_cde_tiles = nullptr;
+  L->n_cde_tiles = (int)list.size();
+  L->cde_tiles_rows = 0;
+  if (!list.empty()) {
+    GG_HIP(hipMalloc(&L->d_cde_tiles, list.size() * sizeof(Tile)));
+    GG_HIP(hipMemcpy(L->d_cde_tiles, list.data(), list.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  }
+  L->cde_tiles_rows = L->cde_rows;
+  return GG_OK;
+}
+
 // n compound-only steps from a lattice whose counter reads t0 (host mirror),
-// then the counter advances by n.
+// then the counter advances by n. With passes on (cde_rows > 0 and the
+// second plane set present), the steps from an even t go in pairs of
+// passes (4 steps) that end in the first plane set; an odd-t first step and
+// the leftover run as single steps.
 static hipError_t launch_cde_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t st) {
   hipError_t e = hipSuccess;
-  for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt)
-    e = launch_cde(L->storage, ((t0 + dt) & 1) != 0, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6,
-                   (int)dt, st);
+  int64_t dt = 0;
+  auto single = [&](int64_t k) {
+    return launch_cde(L->storage, ((t0 + k) & 1) != 0, L->d_desc, L->d_aux_tiles, L->n_aux_tiles,
+                      6, (int)k, st);
+  };
+  if (L->cde_rows > 0 && L->d_pop_b && L->cde_tiles_rows == L->cde_rows) {
+    if ((t0 & 1) && n > 0) e = single(dt++);
+    const int64_t passes = (n - dt) / 4 * 2;
+    for (int64_t k = 0; k < passes && e == hipSuccess; ++k)
+      e = launch_cde_tile2(L->storage, L->cde_rows, L->d_desc, L->d_cde_tiles, L->n_cde_tiles,
+                           (int)(k & 1), (int)(dt + 2 * k), st);
+    dt += 2 * passes;
+  }
+  for (; dt < n && e == hipSuccess; ++dt) e = single(dt);
   if (e == hipSuccess) e = launch_advance(L->d_desc, 1, n, st);
   return e;
 }
@@ -1512,6 +1554,7 @@ gg_status gg_cde_step(gg_lattice *L, int64_t n) {
       return fail(GG_ERR_STATE, "velocity field slot " + std::to_string(s) + " of phase " +
                                     std::to_string(k) + " was never set");
   }
+  if ((st = cde_tiles(L)) != GG_OK) return st;
   int64_t left = n;
   const int K = L->graph_chunk;  // even
   const int par = (int)(L->t & 1);

@@ -159,15 +159,18 @@ class Lattice:
 
     # compound alone on frozen velocity fields (include/gg.h, gg_cde_step)
     def set_velocity_field(self, slot: int, ux: Optional[np.ndarray] = None,
-                           uy: Optional[np.ndarray] = None) -> None:
-        """Store (ux, uy) (host arrays, shape (ny, nx)) in field slot
-        `slot`; with neither given, the velocity of the current fluid state."""
+                           uy: Optional[np.ndarray] = None, scale: float = 1.0) -> None:
+        """Store scale * (ux, uy) (host arrays, shape (ny, nx)) in field slot
+        `slot`; with neither given, scale times the velocity of the current
+        fluid state."""
         if ux is None and uy is None:
-            A.call("gg_set_velocity_field", self._h, int(slot), None, None, A.GG_HOST)
+            A.call("gg_set_velocity_field", self._h, int(slot), None, None, float(scale),
+                   A.GG_HOST)
             return
         a = np.ascontiguousarray(ux, np.float64).reshape(self.ny, self.nx)
         b = np.ascontiguousarray(uy, np.float64).reshape(self.ny, self.nx)
-        A.call("gg_set_velocity_field", self._h, int(slot), _dptr(a), _dptr(b), A.GG_HOST)
+        A.call("gg_set_velocity_field", self._h, int(slot), _dptr(a), _dptr(b), float(scale),
+               A.GG_HOST)
 
     def set_phase_fields(self, slots: Optional[Sequence[int]]) -> None:
         """slots[k]: field slot used in schedule phase k (None: slot 0)."""
@@ -176,6 +179,11 @@ class Lattice:
             return
         arr = (ctypes.c_int32 * len(slots))(*[int(v) for v in slots])
         A.call("gg_set_phase_fields", self._h, arr, len(slots))
+
+    def set_cde_launch(self, rows: int = 14) -> None:
+        """Two-step passes over tiles of 6 or 14 rows for cde_step, or
+        single steps (rows = 0)."""
+        A.call("gg_set_cde_launch", self._h, int(rows))
 
     def cde_step(self, n: int = 2) -> None:
         """Advance the compound alone n (even) steps on the frozen fields."""

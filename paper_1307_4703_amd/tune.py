@@ -3,7 +3,8 @@
 Candidates are tile shapes (tile_x x tile_y nodes per work-group) of the
 single steps, the forms of the two-step pass (walking strips, row-parallel
 tiles with the boundary rules in a kernel of their own or in the one
-kernel) and, for batches, persistent grid sizes. Each candidate is timed
+kernel), for batches persistent grid sizes, and for the compound-only step
+the row count of its two-step tiles. Each candidate is timed
 on the GPU with HIP events over a few graph-replayed steps (the lattices
 advance while being tuned, so tune before the run or on a copy). Results are cached in a JSON
 file keyed by the device name, storage type and the lattices' shapes and
@@ -135,5 +136,29 @@ def tune_batch(lattices: Sequence, steps: int = 32, tiles: Iterable[Tuple[int, i
     best = min(results, key=lambda r: r["ms_per_step"])
     out = {k: best[k] for k in ("tile", "persist", "fuse", "rows", "ms_per_step")}
     out["all"] = results
+    _store(path, key, out)
+    return out
+
+
+def tune_cde(lat, steps: int = 256, rows: Iterable[int] = (0, 6, 14), use_cache: bool = True,
+             path: Optional[str] = None) -> Dict:
+    """Pick the launch form of the compound-only step (two-step passes over
+    tiles of 6 or 14 rows, or single steps) with the shortest step time and
+    apply it. Needs a velocity field for every phase; advances the compound
+    (steps should be a multiple of 4)."""
+    path = path or cache_path()
+    key = _key([lat], "cde")
+    if use_cache:
+        hit = _load(path).get(key)
+        if hit:
+            lat.set_cde_launch(hit["rows"])
+            return hit
+    results: List[Dict] = []
+    for r in rows:
+        lat.set_cde_launch(r)
+        results.append({"rows": r, "ms_per_step": _time(lat.cde_step, steps)})
+    best = min(results, key=lambda x: x["ms_per_step"])
+    lat.set_cde_launch(best["rows"])
+    out = {"rows": best["rows"], "ms_per_step": best["ms_per_step"], "all": results}
     _store(path, key, out)
     return out

@@ -100,11 +100,11 @@ def test_captured_field_odd_start_then_coupled(storage):
     o.init(**init)
     lat.step(13)
     o.step(13)
-    lat.set_velocity_field(0)
+    lat.set_velocity_field(0, scale=2.0)  # a power of two: the same product on both sides
     _, ux, uy, _ = o.fields()
     log(f"cde captured field, odd start, {storage}")
     lat.cde_step(24)
-    o.cde_step(24, [(np.nan_to_num(ux), np.nan_to_num(uy))])
+    o.cde_step(24, [(2.0 * np.nan_to_num(ux), 2.0 * np.nan_to_num(uy))])
     fluid = wl.mask == 0
     _compare(lat, o, fluid, storage, f"captured field {storage}")
     lat.step(7)
@@ -114,19 +114,19 @@ def test_captured_field_odd_start_then_coupled(storage):
 
 
 def test_periodic_uniform_field_graphs():
-    """Random obstacles on a periodic 133x71 lattice, a uniform field, 64
-    steps as 4 graph replays of 16, FP64."""
+    """Random obstacles on a periodic 133x71 lattice, a uniform field given
+    with a scale factor, 64 steps as 4 graph replays of 16, FP64."""
     mask = W.random_mask(133, 71, seed=5, periodic=(True, True))
     wl = W.Workload("random", mask, tau_f=0.7, D=0.03, periodic=(True, True))
     init = seeded_init(wl, 2)
     lat = make_lattice(wl, "f64", init, chunk=16)
-    u = (np.full(mask.shape, 0.05), np.full(mask.shape, -0.03))
-    lat.set_velocity_field(3, *u)
+    u = (np.full(mask.shape, 0.004), np.full(mask.shape, -0.0024))
+    lat.set_velocity_field(3, *u, scale=12.5)  # scaled in FP64, as below
     lat.set_phase_fields([3])
     lat.cde_step(64)
     o = make_oracle(wl)
     o.init(**init)
-    o.cde_step(64, [u])
+    o.cde_step(64, [(12.5 * u[0], 12.5 * u[1])])
     _compare(lat, o, mask == 0, "f64", "periodic uniform")
 
 
@@ -173,3 +173,86 @@ def test_full_size_gradient_generator_f32():
     net_in = sum(d1["seg_solute"]) - sum(d0["seg_solute"])
     assert d1["solute"] - d0["solute"] == pytest.approx(net_in, rel=1e-5, abs=1e-6 * d0["solute"])
     assert d1["mass"] == d0["mass"]
+
+
+def _cde_pair(wl, storage, seed, rows, chunk=0, R=None):
+    init = seeded_init(wl, seed)
+    out = []
+    for r in (0, rows):
+        lat = make_lattice(wl, storage, init, chunk=chunk)
+        if R is not None:
+            lat.set_source(R)
+        lat.set_cde_launch(r)
+        out.append(lat)
+    return out
+
+
+def _same_compound(one, two, t):
+    fa, ga = one.populations()
+    fb, gb = two.populations()
+    assert one.info()["t"] == two.info()["t"] == t
+    assert np.array_equal(fa, fb)
+    if not np.array_equal(ga, gb):
+        bad = np.argwhere(np.any(ga != gb, axis=0))
+        raise AssertionError(f"{len(bad)} nodes differ, first {bad[:5].tolist()}")
+    da, db = one.diagnostics(), two.diagnostics()
+    for a, b in zip(da["seg_solute"], db["seg_solute"]):
+        assert b == pytest.approx(a, rel=1e-12, abs=1e-12)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("rows", [6, 14])
+def test_passes_equal_single_steps(storage, rows):
+    """Two compound-only steps per pass against single steps, bit for bit:
+    ragged gradient generator, valves switching every 7 steps (inside and
+    between the steps of a pass) with a field per phase, a source and decay,
+    odd starts and leftovers, graph replays."""
+    wl = W.gradient_generator(nx=300, ny=150, half_period=7, storage=storage)
+    wl.k_decay = 1e-3
+    rng = np.random.default_rng(3)
+    R = np.zeros(wl.mask.shape)
+    R[40:60, 100:150] = 1e-3 * rng.random((20, 50))
+    one, two = _cde_pair(wl, storage, 12, rows, chunk=8, R=R)
+    fields = _fields(wl.mask.shape, 7)
+    for lat in (one, two):
+        for k, (ux, uy) in enumerate(fields):
+            lat.set_velocity_field(k, ux, uy)
+        lat.set_phase_fields([1, 0])
+    log(f"cde passes vs single steps, {storage}, rows {rows}")
+    for lat in (one, two):
+        lat.step(3)        # odd t
+        lat.cde_step(10)   # a single step, two passes, leftovers
+        lat.cde_step(30)   # graph replays from an odd t
+        lat.step(1)        # even t
+        lat.cde_step(22)
+    _same_compound(one, two, 66)
+
+
+@pytest.mark.parametrize("periodic", [(True, False), (False, True), (True, True), (False, False)])
+def test_passes_random_masks_periodic(periodic):
+    mask = W.random_mask(133, 71, seed=7, periodic=periodic)
+    wl = W.Workload("random", mask, tau_f=0.7, D=0.03, periodic=periodic)
+    one, two = _cde_pair(wl, "f64", 3, 14)
+    u = _fields(mask.shape, 2)[0]
+    for lat in (one, two):
+        lat.set_velocity_field(0, *u)
+        lat.cde_step(36)
+    _same_compound(one, two, 36)
+    o = make_oracle(wl)
+    o.init(**seeded_init(wl, 3))
+    o.cde_step(36, [u])
+    _compare(two, o, mask == 0, "f64", f"passes periodic {periodic}")
+
+
+def test_autotuner_keeps_the_result(tmp_path):
+    """tune_cde times single steps and both tile heights, applies the
+    fastest, and the state it leaves equals single steps over as many steps."""
+    from paper_1307_4703_amd import tune
+    wl = W.gradient_generator(nx=300, ny=150, half_period=9, storage="f32")
+    one, two = _cde_pair(wl, "f32", 6, 14, chunk=8)
+    for lat in (one, two):
+        lat.set_velocity_field(0)
+    res = tune.tune_cde(two, steps=16, path=str(tmp_path / "tune.json"), use_cache=False)
+    assert res["rows"] in (0, 6, 14) and len(res["all"]) == 3
+    one.cde_step(3 * (4 + 16))  # per candidate: 4 warm-up and 16 timed steps
+    _same_compound(one, two, 60)
