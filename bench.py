@@ -463,6 +463,9 @@ def main():
         out["compound_only_frozen_velocity"] = {
             name: cde_bench(name, steps, flow, rows, args.chunk)
             for name, steps, flow, rows in cde_leg}
+        from paper_1307_4703_amd import experiments
+        log("step-profile test (Table 3), four cases, FP32")
+        out["step_profile_table3"] = experiments.step_profile_summary(storage="f32")
         if not args.no_batch:
             out["batched_64_instances"] = batch_bench()
     if not args.no_cpu_baseline:

@@ -141,6 +141,48 @@ def straight_channel(nx: int = 128, ny: int = 64, *, u_max: float = 0.05,
                     storage=storage, init=init)
 
 
+# Step-profile advection test (paper Table 3): the first opening of the
+# source channel. A straight channel 20 nodes wide, at rest with C = 0; its
+# inlet holds C = 1 from t = 0 and the stationary channel flow (a Poiseuille
+# profile peaking at U) carries the step into the channel. Cases (a)-(d):
+# U and D in lattice units and the step count T / dt of Table 3; each front
+# travels 200 nodes.
+STEP_PROFILE_CASES: Dict[str, Tuple[float, float, int]] = {
+    "a": (0.5, 0.00244, 400),
+    "b": (0.05, 0.000244, 4000),
+    "c": (0.1, 0.00244, 2000),
+    "d": (0.01, 0.000244, 20000),
+}
+
+
+def step_profile(case: str, nx: int = 402, width: int = 20,
+                 storage: str = "f64") -> Tuple[Workload, Tuple[np.ndarray, np.ndarray]]:
+    """The channel of the step-profile test and its frozen velocity field.
+
+    Walls at rows 0 and width + 1, inlet ghost column 0 (id 2, C_in = 1),
+    outlet ghost column nx - 1 (id 3). D2Q4 compound lattice (w0 = 0): with
+    U = 0.5 (case a) the equilibrium stays non-negative only there. The
+    field is u_x = 4 U s (H - s) / H^2, s the distance from the halfway wall,
+    H = width; u_y = 0. The fluid parameters (tau_f, the inlet's u_max) do
+    not enter a compound-only run.
+    """
+    U, D, steps = STEP_PROFILE_CASES[case]
+    ny = width + 2
+    mask = np.full((ny, nx), FLUID, np.uint8)
+    mask[0, :] = WALL
+    mask[-1, :] = WALL
+    mask[1:-1, 0] = 2
+    mask[1:-1, -1] = 3
+    segs = [Segment(2, "inlet", (-1, 0), u_max=0.0, c_in=1.0), Segment(3, "outlet", (1, 0))]
+    s = np.arange(ny) - 0.5
+    prof = np.where((s > 0) & (s < width), 4.0 * U * s * (width - s) / width ** 2, 0.0)
+    ux = np.broadcast_to(prof[:, None], (ny, nx)).copy()
+    uy = np.zeros((ny, nx))
+    wl = Workload(name=f"step_profile_{case}", mask=mask, tau_f=0.8, D=D, w0=0.0,
+                  segments=segs, schedule=None, steps=steps, storage=storage)
+    return wl, (ux, uy)
+
+
 # ---------------------------------------------------------------------------
 # Gradient generator
 # ---------------------------------------------------------------------------
