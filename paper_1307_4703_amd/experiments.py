@@ -68,3 +68,209 @@ def step_profile_summary(runs: Optional[Dict[str, Dict]] = None, storage: str = 
                   "seconds": round(r["seconds"], 4),
                   "mlups": None if r["mlups"] is None else round(r["mlups"], 1)}
     return out
+
+
+# ---------------------------------------------------------------------------
+# Long-time gradient formation and inversion (Results; Tables 1-2)
+# ---------------------------------------------------------------------------
+
+# Table 2: compound time step 5e-4 s, so 4 h = 28 800 000 steps; D and the
+# decay rate in lattice units; peak velocity U = 0.5 after rescaling.
+GF_STEPS_PER_HOUR = 7_200_000
+GF_D = 0.00244
+GF_K = 3.34255e-7
+GF_U = 0.5
+
+
+def gradient_generator_paper_scale(storage: str = "f32", k_decay: float = 0.0) -> W.Workload:
+    """The synthetic gradient generator at the paper's resolution (channels
+    20 nodes = 100 um wide, dx = 5 um: 0.2 x the 2048 x 1024 layout), with
+    the compound lattice of Table 2 (D2Q4, D = 0.00244, decay k) and the
+    paper's valve pattern."""
+    wl = W.gradient_generator(scale=0.2, w0=0.0, storage=storage)
+    wl.D = GF_D
+    wl.k_decay = k_decay
+    wl.schedule = W.paper_schedule()
+    return wl
+
+
+def flow_fields(wl, storage: str = "f64", flow_steps: int = 40000) -> Dict[str, tuple]:
+    """Velocity of each valve state after flow_steps coupled steps from rest
+    with only that channel's valves open (the paper precomputes these three
+    fields; with every valve closed the fluid is at rest)."""
+    out = {}
+    for name, open_ids in (("left", frozenset({2, 3})), ("right", frozenset({4, 5}))):
+        lat = Lattice.from_workload(wl, storage=storage)
+        try:
+            lat.set_schedule([W.Phase(flow_steps + 1, open_ids)])
+            lat.step(flow_steps)
+            _, ux, uy, _ = lat.read()
+        finally:
+            lat.close()
+        out[name] = (np.nan_to_num(ux), np.nan_to_num(uy))
+    z = np.zeros(wl.mask.shape)
+    out["closed"] = (z, z.copy())
+    return out
+
+
+def monitor_points(wl) -> Dict[str, tuple]:
+    """(y, x) of three points at the chamber's mid-height: near its left
+    edge, at its centre and near its right edge (stand-ins for the paper's
+    monitoring points, whose positions its figure gives)."""
+    a, b, c, d = wl.layout.chamber
+    yc = (c + d) // 2
+    return {"left": (yc, a + 2), "centre": (yc, (a + b) // 2), "right": (yc, b - 3)}
+
+
+def gradient_formation(hours: float = 4.0, storage: str = "f32", samples_per_hour: int = 30,
+                       flow_steps: int = 40000, swap_hours: Optional[float] = None,
+                       progress=None) -> Dict:
+    """The paper's last experiment on the compound-only step: 4 h of valve
+    flushing (left channel source, right sink), the media swapped at 2 h,
+    once with and once without decay; the two runs advance side by side on
+    two HIP streams. Returns the time series of C at the monitoring points,
+    the mid-height profile across pre-chambers and chamber at the swap and
+    at the end, and the run's update rate. progress(msg), if given, hears
+    of every simulated quarter hour."""
+    import torch
+    swap_hours = hours / 2 if swap_hours is None else swap_hours
+    steps_total = int(round(hours * GF_STEPS_PER_HOUR))
+    chunk = GF_STEPS_PER_HOUR // samples_per_hour
+    swap = int(round(swap_hours * GF_STEPS_PER_HOUR))
+    period = sum(p.duration for p in W.paper_schedule())
+    if chunk % 4 or swap % chunk or swap % period:
+        raise ValueError("samples and the swap must fall on whole passes and periods")
+    base = gradient_generator_paper_scale(storage)
+    fields = flow_fields(base, "f64", flow_steps)
+    umax = max(float(np.hypot(*fields[k]).max()) for k in ("left", "right"))
+    scale = GF_U / umax
+    pts = monitor_points(base)
+    a, b, c, d = base.layout.chamber
+    yc = (c + d) // 2
+    xs = slice(base.layout.left_prechamber[0], base.layout.right_prechamber[1])
+    runs = {}
+    streams = {}
+    for label, k in (("decay", GF_K), ("no_decay", 0.0)):
+        wl = gradient_generator_paper_scale(storage, k)
+        streams[label] = torch.cuda.Stream()
+        lat = Lattice.from_workload(wl, storage=storage, stream=int(streams[label].cuda_stream))
+        for slot, name in enumerate(("left", "right", "closed")):
+            lat.set_velocity_field(slot, *fields[name], scale=scale)
+        lat.set_phase_fields([0, 2, 1, 2])  # left open, closed, right open, closed
+        runs[label] = {"lat": lat, "t": [], **{p: [] for p in pts}}
+    t0 = time.perf_counter()
+    t_steps = 0.0
+    profiles = {}
+    try:
+        for t in range(0, steps_total, chunk):
+            if t == swap:
+                for label, r in runs.items():
+                    r["lat"].set_schedule(W.paper_schedule(c_source=0.0, c_sink=1.0))
+            s0 = time.perf_counter()
+            for r in runs.values():
+                r["lat"].cde_step(chunk)
+            for r in runs.values():
+                r["lat"].sync()
+            t_steps += time.perf_counter() - s0
+            for label, r in runs.items():
+                C = r["lat"].read()[3]
+                r["t"].append((t + chunk) / GF_STEPS_PER_HOUR)
+                for p, (y, x) in pts.items():
+                    r[p].append(float(C[y, x]))
+                if progress and (t + chunk) % (GF_STEPS_PER_HOUR // 4) == 0 and label == "decay":
+                    progress(f"{(t + chunk) / GF_STEPS_PER_HOUR:.2f} h: centre C "
+                             f"{r['centre'][-1]:.4f} (decay), {time.perf_counter() - t0:.0f} s")
+                if t + chunk in (swap, steps_total):
+                    profiles.setdefault(label, {})[f"{(t + chunk) / GF_STEPS_PER_HOUR:g}h"] = \
+                        np.nan_to_num(C[yc, xs]).tolist()
+        diag = {label: r["lat"].diagnostics(check_finite=False) for label, r in runs.items()}
+    finally:
+        for r in runs.values():
+            r["lat"].close()
+    nf = int(np.count_nonzero(base.mask == 0))
+    a_, b_, c_, d_ = base.layout.chamber
+    u_ch = max(float(np.hypot(*fields[k])[c_:d_, a_:b_].max()) for k in ("left", "right"))
+    out = {"hours": hours, "swap_hours": swap_hours, "steps": steps_total, "storage": storage,
+           "scale": scale, "u_max_flow": umax, "chamber_max_u_scaled": u_ch * scale,
+           "n_fluid": nf, "seconds": time.perf_counter() - t0,
+           "seconds_stepping": t_steps,
+           "mlups_two_lattices": 2 * nf * steps_total / t_steps / 1e6,
+           "monitor_points": {p: list(v) for p, v in pts.items()},
+           "profile_x0": xs.start, "profiles": profiles}
+    for label, r in runs.items():
+        out[label] = {"t_hours": r["t"], **{p: r[p] for p in pts},
+                      "n_nonfinite": diag[label]["n_nonfinite"],
+                      "solute": diag[label]["solute"]}
+    return out
+
+
+def time_to_settle(t: List[float], c: List[float], t_from: float, t_to: float,
+                   frac: float = 0.9) -> Optional[float]:
+    """Hours after t_from until c first covers frac of its change between
+    t_from and t_to (the value at the last sample before t_to)."""
+    ts = np.asarray(t)
+    cs = np.asarray(c)
+    i0 = int(np.searchsorted(ts, t_from, side="right")) - 1
+    i1 = int(np.searchsorted(ts, t_to, side="right")) - 1
+    c0 = cs[i0] if i0 >= 0 else 0.0
+    c1 = cs[i1]
+    if c1 == c0:
+        return None
+    goal = c0 + frac * (c1 - c0)
+    for i in range(max(i0, 0), i1 + 1):
+        if (c1 - c0) * (cs[i] - goal) >= 0:
+            return float(ts[i] - t_from)
+    return None
+
+
+def curvature(profile: List[float]) -> float:
+    """Deviation of a profile's middle from the straight line through its
+    ends, relative to the end-to-end difference: 0 for a linear profile,
+    negative where the middle sags below the line."""
+    p = np.asarray(profile)
+    mid = p[len(p) // 2]
+    return float((mid - 0.5 * (p[0] + p[-1])) / abs(p[0] - p[-1]))
+
+
+def gradient_formation_summary(r: Dict) -> Dict:
+    out = {}
+    for label in ("decay", "no_decay"):
+        s = r[label]
+        t = s["t_hours"]
+        prof = r["profiles"][label]
+        out[label] = {
+            "centre_C_at_swap": s["centre"][int(np.argmin(np.abs(np.asarray(t) - r["swap_hours"])))],
+            "centre_C_end": s["centre"][-1],
+            "max_C_chamber_points": max(max(s[p]) for p in r["monitor_points"]),
+            "hours_to_90pct_formation_left_point":
+                time_to_settle(t, s["left"], 0.0, r["swap_hours"]),
+            "hours_to_90pct_after_swap_left_point":
+                time_to_settle(t, s["left"], r["swap_hours"], r["hours"]),
+            "profile_curvature": {k: round(curvature(v), 4) for k, v in prof.items()},
+            "n_nonfinite": s["n_nonfinite"]}
+    out["chamber_max_u_scaled"] = r["chamber_max_u_scaled"]
+    out["mlups_two_lattices"] = round(r["mlups_two_lattices"], 1)
+    out["seconds_stepping"] = round(r["seconds_stepping"], 2)
+    return out
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="run the paper's experiments on the GPU")
+    ap.add_argument("experiment", choices=["step-profile", "gradient-formation"])
+    ap.add_argument("--hours", type=float, default=4.0)
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--out", default=None, help="write the full result as JSON")
+    args = ap.parse_args()
+    if args.experiment == "step-profile":
+        res = step_profile_summary(storage=args.storage)
+        summ = res
+    else:
+        res = gradient_formation(hours=args.hours, storage=args.storage,
+                                 progress=lambda m: print(m, flush=True))
+        summ = gradient_formation_summary(res)
+    if args.out:
+        with open(args.out, "w") as fh:
+            json.dump(res, fh)
+    print(json.dumps(summ), flush=True)
