@@ -27,10 +27,21 @@
  *                                 anti-bounce-back (Dirichlet C_in) for g,
  *        open outlet           -> f: anti-bounce-back at the reference
  *                                 density with the node's own velocity;
- *                                 g: zero-gradient (ghost emits what z emits).
+ *                                 g: zero-gradient (ghost emits what z emits),
+ *        open pressure segment -> the paper's pressure boundary: "do
+ *                                 nothing" (each missing population keeps
+ *                                 the node's value of step t, a zeroth-order
+ *                                 extrapolation in time), then every
+ *                                 population of the node is rescaled so that
+ *                                 its density is the segment's (Eq. 10: u is
+ *                                 unchanged); the compound likewise, rescaled
+ *                                 to C_in, where the segment prescribes it,
+ *                                 and otherwise zero-gradient as at an
+ *                                 outlet.
  *      Outside the domain counts as wall unless that axis is periodic.
- * The paper's own boundary schemes (Boundary Conditions section) are not
- * these; the choice of bounce-back family is a documented reading.
+ * The wall and no-flux schemes of the paper (Boundary Conditions section)
+ * are not these; the choice of the bounce-back family is a documented
+ * reading.
  *
  * Compile with -ffp-contract=off so every product and sum is rounded as
  * written.
@@ -58,6 +69,7 @@ static const double WF[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
 #define ORC_SEG_NONE 0
 #define ORC_SEG_INLET 1
 #define ORC_SEG_OUTLET 2
+#define ORC_SEG_PRESSURE 3
 
 typedef struct orc_lattice {
   int32_t nx, ny;
@@ -75,6 +87,8 @@ typedef struct orc_lattice {
   const double *seg_umax;    /* centre-line inflow speed */
   const double *seg_s0;      /* lower halfway-wall tangential coordinate */
   const double *seg_s1;      /* upper halfway-wall tangential coordinate */
+  const double *seg_rho;     /* density held by a pressure segment */
+  const int32_t *seg_fixc;   /* pressure segment also holds C = C_in */
 } orc_lattice;
 
 /* ---------------------------------------------------------------- */
@@ -129,6 +143,48 @@ static int cell_code(const orc_lattice *L, int x, int y, int *xw, int *yw) {
   *xw = x;
   *yw = y;
   return L->mask[(size_t)y * L->nx + x];
+}
+
+/* Mask value of the open pressure segment that fluid node (x, y) takes its
+ * boundary condition from at this step: the source cell x - e_i of the
+ * lowest-numbered direction i that is a ghost cell of an open pressure
+ * segment; 0 if there is none. */
+static int pressure_segment(const orc_lattice *L, int x, int y, const uint8_t *open) {
+  for (int i = 1; i < 9; ++i) {
+    int xs = 0, ys = 0;
+    int code = cell_code(L, x - EX[i], y - EY[i], &xs, &ys);
+    if (code >= 2 && L->seg_kind[code] == ORC_SEG_PRESSURE && open[code]) return code;
+  }
+  return 0;
+}
+
+/* Rescaling of a pressure-boundary node after streaming (Eq. 10): every f_i
+ * times rho_m / rho, so that the density is the segment's and the velocity
+ * is unchanged. Returns the mass added. */
+static double rescale_f(const orc_lattice *L, int m, double *fz) {
+  double rho = 0.0;
+  for (int i = 0; i < 9; ++i) rho += fz[i];
+  double gam = L->seg_rho[m] / rho;
+  for (int i = 0; i < 9; ++i) fz[i] *= gam;
+  return L->seg_rho[m] - rho;
+}
+
+/* The compound at a pressure-boundary node whose segment prescribes it:
+ * every g_i times C_in / C, or, when C is not positive (nothing to
+ * rescale), the equilibrium at rest w_i C_in. Returns the compound added. */
+static double rescale_g(const orc_lattice *L, int m, double *gz, const double *c_in) {
+  if (!L->seg_fixc[m]) return 0.0;
+  double wg[5];
+  orc_gweights(L->w0, wg);
+  double C = 0.0;
+  for (int i = 0; i < 5; ++i) C += gz[i];
+  if (C > 0.0) {
+    double gam = c_in[m] / C;
+    for (int i = 0; i < 5; ++i) gz[i] *= gam;
+  } else {
+    for (int i = 0; i < 5; ++i) gz[i] = wg[i] * c_in[m];
+  }
+  return c_in[m] - C;
 }
 
 /* Parabolic inflow profile across a velocity-inlet segment, evaluated at the
@@ -254,6 +310,14 @@ void orc_step(const orc_lattice *L, const double *f, const double *g,
           in_f = out_f - 6.0 * WF[i] * L->rho_w * eu;
           /* anti-bounce-back: Dirichlet value C_in at the halfway wall */
           if (has_g) in_g = -out_g + 2.0 * wg[i] * c_in[code];
+        } else if (kind == ORC_SEG_PRESSURE) {
+          /* do nothing: the missing population keeps its value of step t
+           * (the rescaling below then sets the density); the compound the
+           * same where the segment holds C_in, otherwise it leaves with
+           * zero gradient (the ghost emits what z emits), the natural
+           * outflow condition the paper cites for its outlet */
+          in_f = f[9 * node + i];
+          if (has_g) in_g = L->seg_fixc[code] ? g[5 * node + i] : gp[5 * node + i];
         } else {
           /* open outlet. Fluid: anti-bounce-back at the reference density
            * rho_w with the node's own velocity (zero normal gradient of u):
@@ -271,6 +335,12 @@ void orc_step(const orc_lattice *L, const double *f, const double *g,
           gn[5 * node + i] = in_g;
           rf[2 * code + 1] += in_g - out_g;
         }
+      }
+      /* pressure boundary: rescale the streamed state of the node */
+      int m = pressure_segment(L, x, y, open);
+      if (m) {
+        rf[2 * m + 0] += rescale_f(L, m, fn + 9 * node);
+        rf[2 * m + 1] += rescale_g(L, m, gn + 5 * node, c_in);
       }
     }
   }
@@ -350,11 +420,15 @@ void orc_cde_step(const orc_lattice *L, const double *g, double *gn,
           in = out;
         else if (kind == ORC_SEG_INLET)
           in = -out + 2.0 * wg[i] * c_in[code];
+        else if (kind == ORC_SEG_PRESSURE)
+          in = L->seg_fixc[code] ? g[5 * node + i] : gp[5 * node + i];
         else
           in = gp[5 * node + i];
         gn[5 * node + i] = in;
         rf[code] += in - out;
       }
+      int m = pressure_segment(L, x, y, open);
+      if (m) rf[m] += rescale_g(L, m, gn + 5 * node, c_in);
     }
   }
   for (int y = 0; y < ny; ++y)

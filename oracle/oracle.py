@@ -3,8 +3,9 @@
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this module. It does not import the library under
 test, and the library never imports it. It takes plain arrays and duck-typed
-segment / phase records (attributes ``id, kind, normal, u_max, c_in`` and
-``duration, open, c_in``), so the same seeded inputs can be handed to both.
+segment / phase records (attributes ``id, kind, normal, u_max, c_in``, for
+pressure segments also ``rho, fix_c``, and ``duration, open, c_in``), so the
+same seeded inputs can be handed to both.
 
 The time loop, the valve schedule lookup and the boundary-segment geometry
 (halfway-wall positions of each inlet profile) are computed here, on the oracle
@@ -21,7 +22,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
-SEG_KIND = {"inlet": 1, "outlet": 2}
+SEG_KIND = {"inlet": 1, "outlet": 2, "pressure": 3}
 
 
 class _OrcLattice(ctypes.Structure):
@@ -36,6 +37,7 @@ class _OrcLattice(ctypes.Structure):
         ("seg_kind", ctypes.c_void_p), ("seg_nrm", ctypes.c_void_p),
         ("seg_umax", ctypes.c_void_p), ("seg_s0", ctypes.c_void_p),
         ("seg_s1", ctypes.c_void_p),
+        ("seg_rho", ctypes.c_void_p), ("seg_fixc", ctypes.c_void_p),
     ]
 
 
@@ -155,19 +157,25 @@ class Oracle:
         self._s0 = np.zeros(256)
         self._s1 = np.ones(256)
         self._cin_default = np.zeros(256)
+        self._rho = np.ones(256)
+        self._fixc = np.zeros(256, np.int32)
         for s in self.segments.values():
             self._kind[s.id] = SEG_KIND[s.kind]
             self._nrm[s.id] = s.normal
             self._umax[s.id] = s.u_max
             self._cin_default[s.id] = s.c_in
             self._s0[s.id], self._s1[s.id] = segment_extent(self.mask, s.id, s.normal)
+            if s.kind == "pressure":
+                self._rho[s.id] = float(s.rho)
+                self._fixc[s.id] = int(bool(s.fix_c))
         self.R = None if R is None else np.ascontiguousarray(R, dtype=np.float64)
 
         self._c = _OrcLattice(
             self.nx, self.ny, int(bool(periodic[0])), int(bool(periodic[1])),
             _ptr(self.mask), self.tau_f, self.tau_g, self.w0, self.rho0,
             float(k_decay), _ptr(self.R), _ptr(self._kind), _ptr(self._nrm),
-            _ptr(self._umax), _ptr(self._s0), _ptr(self._s1))
+            _ptr(self._umax), _ptr(self._s0), _ptr(self._s1), _ptr(self._rho),
+            _ptr(self._fixc))
         n = self.nx * self.ny
         self.f = np.zeros((self.ny, self.nx, 9))
         self.g = np.zeros((self.ny, self.nx, 5))
@@ -289,6 +297,8 @@ class Oracle:
         Returns (loss, dL/dC_in per mask value [256], dL/dD, dL/dR [ny, nx]).
         Every intermediate state is kept in memory (small lattices only).
         """
+        if any(s.kind == "pressure" for s in self.segments.values()):
+            raise NotImplementedError("the pressure boundary's rescaling is not linear in g")
         weight = np.asarray(weight, np.float64).reshape(self.ny, self.nx)
         target = np.asarray(target, np.float64).reshape(self.ny, self.nx)
         fl = self.mask == 0

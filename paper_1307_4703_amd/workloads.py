@@ -36,8 +36,10 @@ class Segment:
     """A boundary segment: a line of ghost cells with a mask value ``id``.
 
     kind   : "inlet" (velocity inlet carrying a parabolic profile of centre
-             speed ``u_max`` and compound concentration ``c_in``) or
-             "outlet" (zero-gradient outflow).
+             speed ``u_max`` and compound concentration ``c_in``),
+             "outlet" (zero-gradient outflow) or "pressure" (the paper's
+             pressure boundary holding density ``rho``, and, with
+             ``fix_c``, the compound at ``c_in``).
     normal : outward unit normal (from the fluid into the ghost line).
     """
     id: int
@@ -45,6 +47,8 @@ class Segment:
     normal: Tuple[int, int]
     u_max: float = 0.0
     c_in: float = 0.0
+    rho: float = 1.0
+    fix_c: bool = False
 
 
 @dataclass(frozen=True)

@@ -13,6 +13,7 @@ from oracle import oracle as orc
 from tests import test_oracle_adjoint as AD
 from tests import test_oracle_cde as CD
 from tests import test_oracle_pins as P
+from tests import test_oracle_pressure as PR
 
 PINS = [
     (P.test_feq_full_moment_basis, dict(rho=1.03, ux=0.05, uy=-0.02)),
@@ -35,6 +36,15 @@ PINS = [
     (CD.test_cde_step_equals_the_coupled_compound_update, {}),
     (CD.test_cde_uniform_velocity_exact_fourier_evolution, {}),
     (CD.test_cde_closed_box_conserves_solute, {}),
+]
+# the pressure boundary's pins, tried first for mistakes in its code
+PRESSURE_PINS = [
+    (PR.test_density_and_concentration_held_exactly, {}),
+    (PR.test_mass_and_compound_accounting, {}),
+    (PR.test_uniform_rest_state_is_fixed_point, {}),
+    (PR.test_closed_pressure_valves_are_walls, {}),
+    (PR.test_cde_step_equals_coupled_compound_with_pressure_boundaries, {}),
+    (PR.test_pressure_driven_poiseuille, {}),
 ]
 
 MUTATIONS = {
@@ -77,6 +87,17 @@ MUTATIONS = {
                                 "gn[5 * node + i] = gp[5 * ((size_t)ys * nx + xs) + OPP[i]];"),
     "compound-only source": ("+ wg[i] * src;\n    }\n\n  memset(gn", "+ src;\n    }\n\n  memset(gn"),
     "compound-only wall": ("        if (kind == ORC_SEG_NONE)\n          in = out;", "        if (kind == ORC_SEG_NONE)\n          in = 0.999 * out;"),
+    "pressure do-nothing after collision": ("in_f = f[9 * node + i];", "in_f = fp[9 * node + i];"),
+    "pressure rescale inverted": ("double gam = L->seg_rho[m] / rho;", "double gam = rho / L->seg_rho[m];"),
+    "pressure compound guard dropped": ("if (C > 0.0) {\n    double gam = c_in[m] / C;",
+                                        "if (1) {\n    double gam = c_in[m] / C;"),
+    "pressure compound held everywhere": ("if (!L->seg_fixc[m]) return 0.0;", "if (0) return 0.0;"),
+    "pressure ignores the valves": ("L->seg_kind[code] == ORC_SEG_PRESSURE && open[code]) return code;",
+                                    "L->seg_kind[code] == ORC_SEG_PRESSURE) return code;"),
+    "pressure rescale not counted": ("return L->seg_rho[m] - rho;", "return 0.0;"),
+    "pressure compound not counted": ("return c_in[m] - C;", "return 0.0;"),
+    "compound-only pressure rule": ("in = L->seg_fixc[code] ? g[5 * node + i] : gp[5 * node + i];",
+                                    "in = L->seg_fixc[code] ? gp[5 * node + i] : gp[5 * node + i];"),
     "adjoint wall transpose": ("            ls[j] += lx[opp];\n          } else if (kind == ORC_SEG_INLET) {",
                                "            ls[j] += lx[j];\n          } else if (kind == ORC_SEG_INLET) {"),
 }
@@ -93,8 +114,9 @@ def test_some_pin_catches(name, tmp_path):
     lib_path = build_oracle.build(src=mut, out=os.path.join(tmp_path, "libmut.so"))
     orc.use_library(lib_path)
     caught = []
+    pins = PRESSURE_PINS + PINS if "pressure" in name else PINS + PRESSURE_PINS
     try:
-        for fn, kw in PINS:
+        for fn, kw in pins:
             try:
                 fn(**kw)
             except AssertionError:
