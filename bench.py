@@ -466,6 +466,8 @@ def main():
         from paper_1307_4703_amd import experiments
         log("step-profile test (Table 3), four cases, FP32")
         out["step_profile_table3"] = experiments.step_profile_summary(storage="f32")
+        log("boundary kinds: velocity inlet / outflow links against the pressure boundary")
+        out["boundary_kinds"] = experiments.boundary_comparison()
         if not args.no_batch:
             out["batched_64_instances"] = batch_bench()
     if not args.no_cpu_baseline:

@@ -78,8 +78,19 @@ typedef enum gg_where { GG_HOST = 0, GG_DEVICE = 1 } gg_where;
  * GG_SEG_OUTLET : while open, an outflow at the reference density rho0 with
  *   zero normal gradient of the velocity (anti-bounce-back using the
  *   node's own velocity), and zero-gradient for the compound.
+ * GG_SEG_PRESSURE : while open, the paper's pressure boundary (Boundary
+ *   Conditions section, Eq. 10; configured with gg_set_pressure_segment):
+ *   each population arriving from a ghost cell keeps the node's value of
+ *   the step before ("do nothing", zeroth-order extrapolation in time),
+ *   then, after the step, every population of the node is multiplied by
+ *   rho_s / rho so that its density is the segment's rho_s and its velocity
+ *   is unchanged. With hold_c the compound is treated alike and rescaled to
+ *   C_in (where C <= 0 the node takes the equilibrium at rest of C_in);
+ *   otherwise it leaves with zero gradient as at an outlet. A node with
+ *   links to two pressure segments follows the first one met in direction
+ *   order 1..8 (of the source cells x - e_i).
  * A closed segment is a wall (halfway bounce-back for f and g). */
-typedef enum gg_seg_kind { GG_SEG_INLET = 1, GG_SEG_OUTLET = 2 } gg_seg_kind;
+typedef enum gg_seg_kind { GG_SEG_INLET = 1, GG_SEG_OUTLET = 2, GG_SEG_PRESSURE = 3 } gg_seg_kind;
 
 typedef struct gg_params {
   double tau_f;       /* fluid relaxation time, > 1/2 (paper Eq. 4) */
@@ -144,6 +155,17 @@ gg_status gg_create(const uint8_t *mask, int32_t nx, int32_t ny,
 gg_status gg_set_segment(gg_lattice *lat, int32_t id, gg_seg_kind kind,
                          int32_t nrm_x, int32_t nrm_y, double u_max,
                          double c_in);
+
+/* Configure segment `id` as a pressure boundary (GG_SEG_PRESSURE) holding
+ * density rho (> 0; pressure rho / 3) and, if hold_c is nonzero, the
+ * compound at c_in (per-phase overrides as for inlets). Geometry rules as
+ * for gg_set_segment. While a lattice has such a segment its steps run one
+ * at a time (the rescaling follows each step in a kernel of its own), and
+ * gg_adjoint, gg_batch_create, gg_step_timed and gg_step2_timed refuse it
+ * (GG_ERR_STATE): the rescaling is not linear in the compound. */
+gg_status gg_set_pressure_segment(gg_lattice *lat, int32_t id, int32_t nrm_x,
+                                  int32_t nrm_y, double rho, double c_in,
+                                  int32_t hold_c);
 
 /* Periodic valve schedule: phases repeat with period sum(duration); the
  * phase in force during step t -> t+1 is the one containing

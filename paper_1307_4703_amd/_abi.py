@@ -21,7 +21,7 @@ GG_ERR_STATE = 6
 
 GG_F64, GG_F32, GG_F16_SHIFTED = 0, 1, 2
 GG_HOST, GG_DEVICE = 0, 1
-GG_SEG_INLET, GG_SEG_OUTLET = 1, 2
+GG_SEG_INLET, GG_SEG_OUTLET, GG_SEG_PRESSURE = 1, 2, 3
 GG_FIRST_SEGMENT = 2
 GG_MAX_SEGMENTS = 16
 GG_MAX_PHASES = 64
@@ -76,6 +76,7 @@ D = ctypes.c_double
 SIGS = {
     "gg_create": [P, I32, I32, ctypes.POINTER(gg_params), ctypes.c_int, P, ctypes.POINTER(P)],
     "gg_set_segment": [P, I32, ctypes.c_int, I32, I32, D, D],
+    "gg_set_pressure_segment": [P, I32, I32, I32, D, D, I32],
     "gg_set_schedule": [P, ctypes.POINTER(gg_phase), I32, I64],
     "gg_set_source": [P, P, ctypes.c_int],
     "gg_set_region": [P, P],

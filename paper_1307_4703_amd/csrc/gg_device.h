@@ -86,6 +86,10 @@ struct LatDesc {
   float seg_inv_w2_f[GG_MAX_SEGMENTS];
   float phase_cin_f[GG_MAX_PHASES][GG_MAX_SEGMENTS];
   float seg_cin_f[GG_MAX_SEGMENTS];
+  // pressure segments: density held (and in FP32), compound held at C_in
+  double seg_rho[GG_MAX_SEGMENTS];
+  float seg_rho_f[GG_MAX_SEGMENTS];
+  int32_t seg_holdc[GG_MAX_SEGMENTS];
   // frozen velocity fields of the compound-only step, in the compute type:
   // component c (0: u_x, 1: u_y) of slot k is the plane starting at element
   // (2 k + c) * plane of ufield; phase_field[k]: slot used in phase k

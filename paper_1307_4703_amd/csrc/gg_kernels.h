@@ -58,6 +58,11 @@ hipError_t launch_read(gg_storage s, const LatDesc *d, const Tile *tiles, int n_
 hipError_t launch_reduce(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                          int tx_shift, double *partial, double *acc, hipStream_t st);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
+// Pressure boundary: after step (device counter + dt), rescale the state at
+// t + 1 of the n nodes listed as (x, y) pairs that take a boundary value
+// from an open pressure segment; fluid = false rescales the compound only.
+hipError_t launch_rescale(gg_storage s, const LatDesc *d, const int32_t *xy, int n, int dt,
+                          bool fluid, hipStream_t st);
 hipError_t launch_advance(const LatDesc *descs, int n, int64_t k, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
 

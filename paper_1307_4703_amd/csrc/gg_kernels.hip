@@ -423,6 +423,127 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st)
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Pressure boundary: rescaling after a step (paper Eq. 10).
+// ---------------------------------------------------------------------------
+// Writes the deviations df, dg of node x at a step of parity ODD back into
+// the slots load_state reads them from.
+template <class S, bool ODD>
+__device__ __forceinline__ void store_state(const Planes<typename Pop<S>::W> &pl, uint32_t node,
+                                            uint8_t lc, const Neigh &nb,
+                                            const typename Pop<S>::T *f,
+                                            const typename Pop<S>::T *g) {
+  using P = Pop<S>;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const bool own = !ODD || i == 0 || ((lc >> (OPP[i] - 1)) & 1);
+    P::st(own ? pl.at(i, node) : pl.at(OPP[i], nb.idx[OPP[i]]), f[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const bool own = !ODD || i == 0 || ((lc >> (OPP[i] - 1)) & 1);
+    P::st(own ? pl.at(9 + i, node) : pl.at(9 + OPP[i], nb.idx[OPP[i]]), g[i]);
+  }
+}
+
+// After step t (device counter + dt): every listed node with a link from a
+// ghost cell of a pressure segment open at step t has its state at t + 1
+// multiplied through so that rho = rho_s (velocity unchanged), and, where
+// the segment holds the compound, C = C_in (the equilibrium at rest of
+// C_in where C <= 0); the mass and compound added count as the segment's
+// boundary flux. fluid = 0 leaves f alone (compound-only steps). In the
+// deviation form: gamma (w rho0 + df) - w rho0 = gamma df + (gamma - 1) w rho0.
+template <class S>
+__global__ void __launch_bounds__(256)
+    k_rescale(const LatDesc *__restrict__ desc, const int32_t *__restrict__ xy, int n, int dt,
+              int fluid) {
+  using P = Pop<S>;
+  using T = typename P::T;
+  const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (k >= n) return;
+  CDesc &L = *(CDesc *)desc;
+  const int x = xy[2 * k], y = xy[2 * k + 1];
+  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+  const uint8_t lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
+  const int64_t t = *(const GG_CONST int64_t *)L.t + dt;
+  const PhaseNow ph = phase_at(L, t);
+  int s = -1;
+  for (int j = 1; j < 9 && s < 0; ++j) {
+    if (!((lc >> (OPP[j] - 1)) & 1)) continue;  // x - e_j is fluid
+    int sx = x - EX[j], sy = y - EY[j];
+    bool inside = true;
+    if (sx < 0 || sx >= L.nx) {
+      if (L.periodic_x) sx = (sx + L.nx) % L.nx; else inside = false;
+    }
+    if (sy < 0 || sy >= L.ny) {
+      if (L.periodic_y) sy = (sy + L.ny) % L.ny; else inside = false;
+    }
+    if (!inside) continue;
+    const int code = ((const GG_GLOBAL uint8_t *)L.mask)[L.node0 + sy * L.pitch + sx];
+    if (code < GG_FIRST_SEGMENT) continue;
+    const int q = code - GG_FIRST_SEGMENT;
+    if (L.seg_kind[q] == GG_SEG_PRESSURE && ((ph.open >> q) & 1u)) s = q;
+  }
+  if (s < 0) return;
+  const Planes<typename P::W> pl(L);
+  const Neigh nb(L, x, y);
+  T f[9], g[5];
+  const bool odd = ((t + 1) & 1) != 0;  // parity of the state at t + 1
+  if (odd)
+    load_state<S, true>(pl, node, lc, nb, f, g);
+  else
+    load_state<S, false>(pl, node, lc, nb, f, g);
+  double dm = 0.0, dc = 0.0;
+  {
+#pragma clang fp contract(off)
+    if (fluid) {
+      T drho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+      const T rho = (T)L.rho0 + drho;
+      const T rs = SegT<T>::rho(L, s);
+      const T gam = rs / rho;
+      const T rest = (gam - T(1)) * (T)L.rho0;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = fmad(gam, f[i], rest * (T)WF[i]);
+      dm = (double)rs - (double)rho;
+    }
+    if (L.seg_holdc[s]) {
+      const T cs = (T)L.c_shift;
+      const T wga = (T)L.wg_axis;
+      const T wg[5] = {T(1) - T(4) * wga, wga, wga, wga, wga};
+      const T C = cs + (g[0] + g[1] + g[2] + g[3] + g[4]);
+      const T cin = SegT<T>::cin(ph, s);
+      if (C > T(0)) {
+        const T gam = cin / C;
+        const T rest = (gam - T(1)) * cs;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) g[i] = fmad(gam, g[i], rest * wg[i]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) g[i] = wg[i] * (cin - cs);
+      }
+      dc = (double)cin - (double)C;
+    }
+  }
+  if (odd)
+    store_state<S, true>(pl, node, lc, nb, f, g);
+  else
+    store_state<S, false>(pl, node, lc, nb, f, g);
+  if (dm != 0.0) atomicAdd((double *)L.flux + 2 * s, dm);
+  if (dc != 0.0) atomicAdd((double *)L.flux + 2 * s + 1, dc);
+}
+
+hipError_t launch_rescale(gg_storage s, const LatDesc *d, const int32_t *xy, int n, int dt,
+                          bool fluid, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int grid = (n + 255) / 256;
+  switch (s) {
+    case GG_F64: k_rescale<double><<<grid, 256, 0, st>>>(d, xy, n, dt, fluid); break;
+    case GG_F32: k_rescale<float><<<grid, 256, 0, st>>>(d, xy, n, dt, fluid); break;
+    case GG_F16_SHIFTED: k_rescale<__half><<<grid, 256, 0, st>>>(d, xy, n, dt, fluid); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_advance(const LatDesc *descs, int n, int64_t k, hipStream_t st) {
   k_advance<<<(n + 63) / 64, 64, 0, st>>>(descs, n, k);
   return hipGetLastError();

@@ -36,6 +36,7 @@ template <> struct SegT<double> {
   static __device__ __forceinline__ double s1(CDesc &L, int s) { return L.seg_s1[s]; }
   static __device__ __forceinline__ double iw2(CDesc &L, int s) { return L.seg_inv_w2[s]; }
   static __device__ __forceinline__ double cin(const PhaseNow &p, int s) { return p.cin[s]; }
+  static __device__ __forceinline__ double rho(CDesc &L, int s) { return L.seg_rho[s]; }
 };
 template <> struct SegT<float> {
   static __device__ __forceinline__ float umax4(CDesc &L, int s) { return L.seg_umax4_f[s]; }
@@ -43,6 +44,7 @@ template <> struct SegT<float> {
   static __device__ __forceinline__ float s1(CDesc &L, int s) { return L.seg_s1_f[s]; }
   static __device__ __forceinline__ float iw2(CDesc &L, int s) { return L.seg_inv_w2_f[s]; }
   static __device__ __forceinline__ float cin(const PhaseNow &p, int s) { return p.cin_f[s]; }
+  static __device__ __forceinline__ float rho(CDesc &L, int s) { return L.seg_rho_f[s]; }
 };
 
 // Sum over the 64 lanes of a wavefront; every lane must be active.
@@ -310,6 +312,12 @@ __device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc,
         const T en = (T)(EX[j] * L.seg_nx[s] + EY[j] * L.seg_ny[s]);
         vf = fmad(T(-6) * (T)WF[j] * rho0 * en, us, pf[OPP[j]]);
         if (j < 5) vg = fmad(T(2) * wg[j], SegT<T>::cin(ph, s) - cs, -pg[OPP[j]]);
+      } else if (L.seg_kind[s] == GG_SEG_PRESSURE) {
+        // do nothing: the node's own value of step t (the density is set by
+        // the rescaling after the step); the compound alike where it is
+        // held, else zero-gradient as at an outlet
+        vf = f[j];
+        if (j < 5) vg = L.seg_holdc[s] ? g[j] : pg[j];
       } else {
         // outflow at the reference density with the node's own u;
         // the compound leaves with zero gradient
@@ -328,11 +336,12 @@ __device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc,
 
 // Link rules of the compound alone (the compound lines of collide_node):
 // in_g[j], the value arriving at (x, y) along j when x - e_j is not fluid,
-// from the post-collision pg; solute fluxes through open segments into fx.
+// from the pre- and post-collision g, pg; solute fluxes through open
+// segments into fx.
 template <class T>
 __device__ __forceinline__ void compound_links(CDesc &L, int x, int y, uint8_t lc, bool seg_tile,
-                                               const PhaseNow &ph, const T *pg, T *in_g, Flux &fx,
-                                               bool count) {
+                                               const PhaseNow &ph, const T *g, const T *pg,
+                                               T *in_g, Flux &fx, bool count) {
 #pragma clang fp contract(off)
   const int nx = L.nx, ny = L.ny, pitch = L.pitch;
   const T cs = (T)L.c_shift;
@@ -359,7 +368,8 @@ __device__ __forceinline__ void compound_links(CDesc &L, int x, int y, uint8_t l
     if (!((ph.open >> s) & 1u)) continue;  // closed valve: a wall
     const T vg = L.seg_kind[s] == GG_SEG_INLET
                      ? fmad(T(2) * wg[j], SegT<T>::cin(ph, s) - cs, -pg[OPP[j]])
-                     : pg[j];
+                 : (L.seg_kind[s] == GG_SEG_PRESSURE && L.seg_holdc[s]) ? g[j]
+                                                                      : pg[j];
     in_g[j] = vg;
     if (count) fx.add(s, 0.0, (double)(vg - pg[OPP[j]]));
   }

@@ -11,6 +11,8 @@ struct SegHost {
   int kind = 0;
   int nrm_x = 0, nrm_y = 0;
   double u_max = 0.0, c_in = 0.0;
+  double rho = 1.0;    // pressure segments: density held
+  bool hold_c = false; // pressure segments: compound held at c_in
   double s0 = 0.0, s1 = 1.0;  // halfway-wall tangential coordinates
 };
 
@@ -65,6 +67,11 @@ struct gg_lattice {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  // fluid nodes with a link from a pressure segment's ghost cell, as (x, y)
+  // pairs, rescaled after every step; rebuilt when the segments change
+  int32_t *d_press = nullptr;
+  int n_press = 0;
+  bool press_dirty = true;
   // compound alone on frozen velocity fields: n_ufield slots of two planes
   // (u_x, u_y) in the compute type; bit k of ufield_set: slot k written;
   // phase_field[k]: slot used in schedule phase k; graphs of graph_chunk

@@ -68,7 +68,7 @@ void gg_free_device(gg_lattice *L) {
   L->graph = nullptr;
   void *ptrs[] = {L->d_pop, L->d_pop_b, L->d_link, L->d_mask, L->d_region, L->d_R, L->d_t,
                   L->d_flux, L->d_acc, L->d_desc, L->d_tiles, L->d_aux_tiles, L->d_strips,
-                  L->d_seg_strips, L->d_partial, L->d_ufield, L->d_cde_tiles};
+                  L->d_seg_strips, L->d_partial, L->d_ufield, L->d_cde_tiles, L->d_press};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (L->cap_stream) (void)hipStreamDestroy(L->cap_stream);
@@ -124,6 +124,9 @@ gg_status gg_upload_desc(gg_lattice *L) {
     h.seg_s1_f[s] = (float)h.seg_s1[s];
     h.seg_inv_w2_f[s] = (float)h.seg_inv_w2[s];
     h.seg_cin_f[s] = (float)h.seg_cin[s];
+    h.seg_rho[s] = g.rho;
+    h.seg_rho_f[s] = (float)g.rho;
+    h.seg_holdc[s] = g.hold_c ? 1 : 0;
   }
   h.n_phases = (int32_t)L->phases.size();
   h.t_origin = L->t_origin;
@@ -437,14 +440,13 @@ void gg_destroy(gg_lattice *L) {
   delete L;
 }
 
-gg_status gg_set_segment(gg_lattice *L, int32_t id, gg_seg_kind kind, int32_t nrm_x,
-                         int32_t nrm_y, double u_max, double c_in) {
-  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+// Checks the geometry of segment id with outward normal (nrm_x, nrm_y) and
+// returns the halfway-wall tangential coordinates of its ghost line.
+static gg_status segment_geometry(gg_lattice *L, int32_t id, int32_t nrm_x, int32_t nrm_y,
+                                  double *s0, double *s1) {
   if (id < GG_FIRST_SEGMENT || id >= GG_FIRST_SEGMENT + GG_MAX_SEGMENTS)
     return fail(GG_ERR_ARG, "segment id must lie in 2..17");
-  if (kind != GG_SEG_INLET && kind != GG_SEG_OUTLET) return fail(GG_ERR_ARG, "unknown segment kind");
   if (std::abs(nrm_x) + std::abs(nrm_y) != 1) return fail(GG_ERR_ARG, "normal must be an axis unit vector");
-  if (!std::isfinite(u_max) || !std::isfinite(c_in)) return fail(GG_ERR_ARG, "u_max and c_in must be finite");
   int smin = 1 << 30, smax = -(1 << 30);
   int64_t cells = 0;
   for (int y = 0; y < L->ny; ++y)
@@ -468,6 +470,21 @@ gg_status gg_set_segment(gg_lattice *L, int32_t id, gg_seg_kind kind, int32_t nr
       smax = std::max(smax, s);
     }
   if (cells == 0) return fail(GG_ERR_MASK, "segment " + std::to_string(id) + " has no cells in the mask");
+  *s0 = smin - 0.5;
+  *s1 = smax + 0.5;
+  return GG_OK;
+}
+
+gg_status gg_set_segment(gg_lattice *L, int32_t id, gg_seg_kind kind, int32_t nrm_x,
+                         int32_t nrm_y, double u_max, double c_in) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (kind != GG_SEG_INLET && kind != GG_SEG_OUTLET)
+    return fail(GG_ERR_ARG, "unknown segment kind (pressure segments: gg_set_pressure_segment)");
+  if (!std::isfinite(u_max) || !std::isfinite(c_in)) return fail(GG_ERR_ARG, "u_max and c_in must be finite");
+  double s0 = 0.0, s1 = 1.0;
+  gg_status st = segment_geometry(L, id, nrm_x, nrm_y, &s0, &s1);
+  if (st != GG_OK) return st;
+  GG_HIP(hipStreamSynchronize(L->stream));
   SegHost &g = L->seg[id - GG_FIRST_SEGMENT];
   g.set = true;
   g.kind = kind;
@@ -475,9 +492,91 @@ gg_status gg_set_segment(gg_lattice *L, int32_t id, gg_seg_kind kind, int32_t nr
   g.nrm_y = nrm_y;
   g.u_max = u_max;
   g.c_in = c_in;
-  g.s0 = smin - 0.5;
-  g.s1 = smax + 0.5;
+  g.rho = L->p.rho0;
+  g.hold_c = false;
+  g.s0 = s0;
+  g.s1 = s1;
+  L->press_dirty = true;
   return gg_upload_desc(L);
+}
+
+gg_status gg_set_pressure_segment(gg_lattice *L, int32_t id, int32_t nrm_x, int32_t nrm_y,
+                                  double rho, double c_in, int32_t hold_c) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (!(rho > 0.0) || !std::isfinite(rho) || !std::isfinite(c_in))
+    return fail(GG_ERR_ARG, "rho must be positive and finite, c_in finite");
+  double s0 = 0.0, s1 = 1.0;
+  gg_status st = segment_geometry(L, id, nrm_x, nrm_y, &s0, &s1);
+  if (st != GG_OK) return st;
+  GG_HIP(hipStreamSynchronize(L->stream));
+  SegHost &g = L->seg[id - GG_FIRST_SEGMENT];
+  g.set = true;
+  g.kind = GG_SEG_PRESSURE;
+  g.nrm_x = nrm_x;
+  g.nrm_y = nrm_y;
+  g.u_max = 0.0;
+  g.c_in = c_in;
+  g.rho = rho;
+  g.hold_c = hold_c != 0;
+  g.s0 = s0;
+  g.s1 = s1;
+  L->press_dirty = true;
+  return gg_upload_desc(L);
+}
+
+// True if a configured segment is a pressure boundary.
+static bool has_pressure(const gg_lattice *L) {
+  for (int s = 0; s < GG_MAX_SEGMENTS; ++s)
+    if (L->seg[s].set && L->seg[s].kind == GG_SEG_PRESSURE) return true;
+  return false;
+}
+
+// The fluid nodes that take a boundary value from a pressure segment's
+// ghost cell (in any phase), uploaded as (x, y) pairs.
+static gg_status pressure_nodes(gg_lattice *L) {
+  if (!L->press_dirty) return GG_OK;
+  std::vector<int32_t> xy;
+  if (has_pressure(L))
+    for (int y = 0; y < L->ny; ++y)
+      for (int x = 0; x < L->nx; ++x) {
+        const uint8_t lc = L->link[L->nid(x, y)];
+        if (lc == NOT_FLUID || lc == 0) continue;
+        bool any = false;
+        for (int k = 1; k < 9 && !any; ++k) {
+          if (!((lc >> (k - 1)) & 1)) continue;
+          int xx = x + EX[k], yy = y + EY[k];
+          bool inside = true;
+          if (xx < 0 || xx >= L->nx) {
+            if (L->p.periodic_x) xx = (xx + L->nx) % L->nx; else inside = false;
+          }
+          if (yy < 0 || yy >= L->ny) {
+            if (L->p.periodic_y) yy = (yy + L->ny) % L->ny; else inside = false;
+          }
+          if (!inside) continue;
+          const int m = L->mask[(size_t)yy * L->nx + xx];
+          any = m >= GG_FIRST_SEGMENT && L->seg[m - GG_FIRST_SEGMENT].set &&
+                L->seg[m - GG_FIRST_SEGMENT].kind == GG_SEG_PRESSURE;
+        }
+        if (any) {
+          xy.push_back(x);
+          xy.push_back(y);
+        }
+      }
+  if (L->d_press) GG_HIP(hipFree(L->d_press));
+  L->d_press = nullptr;
+  L->n_press = (int)(xy.size() / 2);
+  if (!xy.empty()) {
+    GG_HIP(hipMalloc(&L->d_press, xy.size() * sizeof(int32_t)));
+    GG_HIP(hipMemcpy(L->d_press, xy.data(), xy.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
+  L->press_dirty = false;
+  // captured graphs hold the old list and the old launch form
+  if (L->graph_exec) (void)hipGraphExecDestroy(L->graph_exec);
+  if (L->graph) (void)hipGraphDestroy(L->graph);
+  L->graph_exec = nullptr;
+  L->graph = nullptr;
+  gg_drop_cde_graphs(L);
+  return GG_OK;
 }
 
 gg_status gg_set_schedule(gg_lattice *L, const gg_phase *phases, int32_t n, int64_t t_origin) {
@@ -623,15 +722,20 @@ static hipError_t launch_pass(gg_lattice *L, int dir, int dt, hipStream_t st) {
 
 static hipError_t launch_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t st) {
   hipError_t e = hipSuccess;
-  if (L->fuse >= 2 && !(t0 & 1) && n % 4 == 0) {
+  if (L->fuse >= 2 && !(t0 & 1) && n % 4 == 0 && L->n_press == 0) {
     for (int64_t k = 0; k < n / 2 && e == hipSuccess; ++k)
       e = launch_pass(L, (int)(k & 1), (int)(2 * k), st);
   } else {
+    // (pressure boundaries: one step at a time, each followed by the
+    // rescaling of the boundary nodes)
     const int block = L->tile_x * L->tile_y;
     const int txs = ilog2(L->tile_x);
-    for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt)
+    for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt) {
       e = launch_step(L->storage, block, ((t0 + dt) & 1) != 0, L->d_desc, L->d_tiles,
                       L->n_tiles, txs, (int)dt, st);
+      if (e == hipSuccess && L->n_press > 0)
+        e = launch_rescale(L->storage, L->d_desc, L->d_press, L->n_press, (int)dt, true, st);
+    }
   }
   if (e == hipSuccess) e = launch_advance(L->d_desc, 1, n, st);
   return e;
@@ -642,6 +746,7 @@ gg_status gg_step(gg_lattice *L, int64_t n) {
   if (n < 0) return fail(GG_ERR_ARG, "n must be non-negative");
   gg_status st = check_segments(L);
   if (st != GG_OK) return st;
+  if ((st = pressure_nodes(L)) != GG_OK) return st;
   int64_t left = n;
   // graph chunk: even (a multiple of 4 with the two-step pass), so every
   // replay starts on an even step and leaves the state in the first plane set
@@ -671,7 +776,7 @@ gg_status gg_step(gg_lattice *L, int64_t n) {
       L->t += K;
     }
   }
-  const int64_t quads = L->fuse >= 2 ? left / 4 * 4 : 0;
+  const int64_t quads = L->fuse >= 2 && L->n_press == 0 ? left / 4 * 4 : 0;
   if (quads > 0) {
     GG_HIP(launch_steps(L, L->t, quads, L->stream));
     L->t += quads;
@@ -904,6 +1009,8 @@ struct AdjointBuffers {
 
 gg_status gg_adjoint(gg_lattice *L, int64_t n, int64_t s, const double *weight,
                      const double *target, const int32_t *r_box, double *d_R, gg_grads *out) {
+  if (L && has_pressure(L))
+    return fail(GG_ERR_STATE, "the adjoint does not cover pressure boundaries");
   if (!L || !weight || !target || !out) return fail(GG_ERR_ARG, "NULL argument");
   if (n < 1) return fail(GG_ERR_ARG, "n_steps must be positive");
   if (s < 0) return fail(GG_ERR_ARG, "ckpt_every must be non-negative");
@@ -1127,6 +1234,8 @@ gg_status gg_batch_create(gg_lattice *const *lats, int32_t n, int32_t tile_x, in
       if (lats[j] == lats[k]) return fail(GG_ERR_ARG, "a lattice appears twice in the batch");
     gg_status st = check_segments(lats[k]);
     if (st != GG_OK) return st;
+    if (has_pressure(lats[k]))
+      return fail(GG_ERR_STATE, "batch members may not have pressure boundaries");
   }
   gg_batch *B = new gg_batch();
   B->lats.assign(lats, lats + n);
@@ -1309,6 +1418,7 @@ void gg_batch_destroy(gg_batch *B) {
 }
 
 gg_status gg_step_timed(gg_lattice *L, int64_t n, double *ms_even, double *ms_odd) {
+  if (L && has_pressure(L)) return fail(GG_ERR_STATE, "timed steps do not cover pressure boundaries");
   if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
   if (n < 1) return fail(GG_ERR_ARG, "n must be positive");
   gg_status st = check_segments(L);
@@ -1347,6 +1457,7 @@ gg_status gg_step_timed(gg_lattice *L, int64_t n, double *ms_even, double *ms_od
 }
 
 gg_status gg_step2_timed(gg_lattice *L, int64_t n_pairs, double *ms_pass) {
+  if (L && has_pressure(L)) return fail(GG_ERR_STATE, "timed passes do not cover pressure boundaries");
   if (!L || !ms_pass) return fail(GG_ERR_ARG, "NULL argument");
   if (n_pairs < 1) return fail(GG_ERR_ARG, "n_pairs must be positive");
   if (L->fuse < 2) return fail(GG_ERR_STATE, "the two-step pass is off");
@@ -1528,7 +1639,7 @@ static hipError_t launch_cde_steps(gg_lattice *L, int64_t t0, int64_t n, hipStre
     return launch_cde(L->storage, ((t0 + k) & 1) != 0, L->d_desc, L->d_aux_tiles, L->n_aux_tiles,
                       6, (int)k, st);
   };
-  if (L->cde_rows > 0 && L->d_pop_b && L->cde_tiles_rows == L->cde_rows) {
+  if (L->cde_rows > 0 && L->d_pop_b && L->cde_tiles_rows == L->cde_rows && L->n_press == 0) {
     if ((t0 & 1) && n > 0) e = single(dt++);
     const int64_t passes = (n - dt) / 4 * 2;
     for (int64_t k = 0; k < passes && e == hipSuccess; ++k)
@@ -1536,7 +1647,11 @@ static hipError_t launch_cde_steps(gg_lattice *L, int64_t t0, int64_t n, hipStre
                            (int)(k & 1), (int)(dt + 2 * k), st);
     dt += 2 * passes;
   }
-  for (; dt < n && e == hipSuccess; ++dt) e = single(dt);
+  for (; dt < n && e == hipSuccess; ++dt) {
+    e = single(dt);
+    if (e == hipSuccess && L->n_press > 0)
+      e = launch_rescale(L->storage, L->d_desc, L->d_press, L->n_press, (int)dt, false, st);
+  }
   if (e == hipSuccess) e = launch_advance(L->d_desc, 1, n, st);
   return e;
 }
@@ -1554,7 +1669,7 @@ gg_status gg_cde_step(gg_lattice *L, int64_t n) {
       return fail(GG_ERR_STATE, "velocity field slot " + std::to_string(s) + " of phase " +
                                     std::to_string(k) + " was never set");
   }
-  if ((st = cde_tiles(L)) != GG_OK) return st;
+  if ((st = cde_tiles(L)) != GG_OK || (st = pressure_nodes(L)) != GG_OK) return st;
   int64_t left = n;
   const int K = L->graph_chunk;  // even
   const int par = (int)(L->t & 1);

@@ -254,17 +254,95 @@ def gradient_formation_summary(r: Dict) -> Dict:
     return out
 
 
+# ---------------------------------------------------------------------------
+# The paper's pressure boundary against the bounce-back family
+# ---------------------------------------------------------------------------
+
+def _poiseuille_error(rho, ux, H, nu, xm):
+    """Deviation of the profile at column xm from the parabola of the local
+    pressure gradient (p = rho / 3), relative to its peak."""
+    G = -(rho[1:-1, xm + 20] - rho[1:-1, xm - 20]).mean() / 40 / 3
+    umax = G * H * H / (8 * nu * rho[1:-1, xm].mean())
+    s = np.arange(1, H + 1) - 0.5
+    prof = 4 * umax * s * (H - s) / H ** 2
+    return float(np.abs(ux[1:-1, xm] - prof).max() / umax), float(umax)
+
+
+def boundary_comparison(storage: str = "f64", steps: int = 30000,
+                        rate_steps: int = 2000) -> Dict:
+    """The straight channel (128 x 64, H = 62) driven two ways to steady
+    state: by the velocity inlet and outflow links of the bounce-back family
+    (u_max = 0.05) and by the paper's pressure boundaries holding the
+    densities that drive the same flow; for each, the profile's deviation
+    from the parabola of its own pressure gradient and the spread of the
+    mass flux along the channel. Then the rate of the 2048 x 1024 gradient
+    generator (FP32) with each kind on its four segments."""
+    import torch
+    out: Dict = {}
+    nu = (0.8 - 0.5) / 3
+    base = W.straight_channel(storage=storage, steps=steps)
+    H = base.ny - 2
+    # the density drop that drives u_max = 0.05 over the channel's length
+    drho = 3 * 0.05 * 8 * nu / (H * H) * (base.nx - 3)
+    pres = W.Workload(base.name + "_pressure", base.mask, tau_f=0.8, D=base.D, w0=base.w0,
+                      segments=[W.Segment(2, "pressure", (-1, 0), rho=1 + drho / 2, c_in=1.0,
+                                          fix_c=True),
+                                W.Segment(3, "pressure", (1, 0), rho=1 - drho / 2)],
+                      storage=storage)
+    for label, wl in (("velocity_inlet", base), ("pressure", pres)):
+        lat = Lattice.from_workload(wl, storage=storage)
+        try:
+            lat.step(steps)
+            rho, ux, _, C = lat.read()
+        finally:
+            lat.close()
+        err, umax = _poiseuille_error(rho, ux, H, nu, base.nx // 2)
+        flux = [(rho[1:-1, x] * ux[1:-1, x]).sum() for x in range(1, base.nx - 1)]
+        out[label] = {"profile_error_vs_local_gradient": round(err, 6),
+                      "u_max_local_gradient": round(umax, 6),
+                      "u_centre": round(float(ux[1 + H // 2, base.nx // 2]), 6),
+                      "mass_flux_spread": float(np.ptp(flux) / np.mean(flux)),
+                      "C_outlet_column_mean": round(float(np.nanmean(C[1:-1, -2])), 4)}
+    gg = W.gradient_generator(storage="f32")
+    stream = torch.cuda.current_stream()
+    for label in ("velocity_inlet", "pressure"):
+        if label == "pressure":
+            gg.segments = [W.Segment(2, "pressure", (0, -1), rho=1.002, c_in=1.0, fix_c=True),
+                           W.Segment(3, "pressure", (0, 1), rho=0.998),
+                           W.Segment(4, "pressure", (0, -1), rho=1.002, c_in=0.0, fix_c=True),
+                           W.Segment(5, "pressure", (0, 1), rho=0.998)]
+        lat = Lattice.from_workload(gg)
+        try:
+            lat.step(256)
+            lat.sync()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            lat.step(rate_steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / rate_steps
+            nf = lat.info()["n_fluid"]
+        finally:
+            lat.close()
+        out[label]["gg2048_f32_mlups"] = round(nf / (ms * 1e-3) / 1e6, 1)
+        out[label]["gg2048_f32_us_per_step"] = round(ms * 1e3, 3)
+    return out
+
+
 if __name__ == "__main__":
     import argparse
     import json
     ap = argparse.ArgumentParser(description="run the paper's experiments on the GPU")
-    ap.add_argument("experiment", choices=["step-profile", "gradient-formation"])
+    ap.add_argument("experiment", choices=["step-profile", "gradient-formation", "boundaries"])
     ap.add_argument("--hours", type=float, default=4.0)
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--out", default=None, help="write the full result as JSON")
     args = ap.parse_args()
     if args.experiment == "step-profile":
         res = step_profile_summary(storage=args.storage)
+        summ = res
+    elif args.experiment == "boundaries":
+        res = boundary_comparison()
         summ = res
     else:
         res = gradient_formation(hours=args.hours, storage=args.storage,

@@ -79,7 +79,8 @@ class Lattice:
                   k_decay=wl.k_decay, c_shift=wl.c_shift if storage == "f16" else 0.0,
                   periodic=wl.periodic, storage=storage, stream=stream)
         for s in wl.segments:
-            lat.set_segment(s.id, s.kind, s.normal, s.u_max, s.c_in)
+            lat.set_segment(s.id, s.kind, s.normal, s.u_max, s.c_in,
+                            getattr(s, "rho", 1.0), getattr(s, "fix_c", False))
         if wl.schedule:
             lat.set_schedule(wl.schedule, wl.t_origin)
         if wl.region is not None:
@@ -93,7 +94,15 @@ class Lattice:
         return self._h
 
     def set_segment(self, sid: int, kind: str, normal, u_max: float = 0.0,
-                    c_in: float = 0.0) -> None:
+                    c_in: float = 0.0, rho: float = 1.0, fix_c: bool = False) -> None:
+        """Configure a segment: "inlet" and "outlet" (gg_set_segment, with
+        u_max and c_in) or "pressure" (gg_set_pressure_segment: density rho,
+        and the compound held at c_in when fix_c)."""
+        if kind == "pressure":
+            A.call("gg_set_pressure_segment", self._h, int(sid), int(normal[0]), int(normal[1]),
+                   float(rho), float(c_in), int(bool(fix_c)))
+            self.segments[int(sid)] = (kind, tuple(normal), rho, c_in, fix_c)
+            return
         k = {"inlet": A.GG_SEG_INLET, "outlet": A.GG_SEG_OUTLET}[kind]
         A.call("gg_set_segment", self._h, int(sid), k, int(normal[0]),
                int(normal[1]), float(u_max), float(c_in))
