@@ -152,7 +152,7 @@ __global__ void __launch_bounds__((R + 2) * 64)
   T pg[5], ing[5];
   if (lc != NOT_FLUID) {
     compound_collide<T>(L, x, y, g, ux, uy, pg);
-    compound_links<T>(L, x, y, lc, seg, ph1, g, pg, ing, fx, own);
+    compound_links<T, false>(L, x, y, lc, seg, ph1, g, pg, ing, fx, own);
   } else {
 #pragma unroll
     for (int i = 0; i < 5; ++i) pg[i] = ing[i] = T(0);
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__((R + 2) * 64)
     }
     T qg[5], jg[5];
     compound_collide<T>(L, x, y, sg, ux, uy, qg);
-    compound_links<T>(L, x, y, lc, seg, ph2, sg, qg, jg, fx, true);
+    compound_links<T, false>(L, x, y, lc, seg, ph2, sg, qg, jg, fx, true);
     const Neigh nb(L, x, y);
     P::st(dst.at(9, node), qg[0]);
 #pragma unroll

@@ -45,7 +45,7 @@ __device__ __forceinline__ void second_step(CDesc &L, const Planes<typename Pop<
   using P = Pop<S>;
   using T = typename P::T;
   T qf[9], qg[5], jf[9], jg[5];
-  collide_node<T>(L, x, y, lc, SEG, ph, sf, sg, qf, qg, jf, jg, fx, true, nbr);
+  collide_node<T, false>(L, x, y, lc, SEG, ph, sf, sg, qf, qg, jf, jg, fx, true, nbr);
   const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
   const Neigh nb(L, x, y);
   P::st(dst.at(0, node), qf[0]);
@@ -166,7 +166,7 @@ __device__ __forceinline__ void strip_two_steps(const LatDesc *__restrict__ desc
     // step t at (x, y)
     T pf[9], pg[5], inf[9], ing[5];
     if (lc != NOT_FLUID) {
-      collide_node<T>(L, x, y, lc, SEG, ph1, f, g, pf, pg, inf, ing, fx, own);
+      collide_node<T, false>(L, x, y, lc, SEG, ph1, f, g, pf, pg, inf, ing, fx, own);
     } else {
 #pragma unroll
       for (int i = 0; i < 9; ++i) pf[i] = inf[i] = T(0);
@@ -310,7 +310,8 @@ __global__ void __launch_bounds__((R + 2) * 64)
     Flux fx;
     T pf[9], pg[5], inf[9], ing[5];
     if (lc != NOT_FLUID) {
-      collide_node<T>(L, x, y, lc, seg, ph1, f, g, pf, pg, inf, ing, fx, own, SEG ? nbr : nullptr);
+      collide_node<T, false>(L, x, y, lc, seg, ph1, f, g, pf, pg, inf, ing, fx, own,
+                             SEG ? nbr : nullptr);
     } else {
 #pragma unroll
       for (int i = 0; i < 9; ++i) pf[i] = inf[i] = T(0);

@@ -241,7 +241,13 @@ __device__ __forceinline__ void compound_collide(CDesc &L, int x, int y, const T
 // nbr, when given, holds the mask values of the cells x + e_k (k = 1..8,
 // wrapped on periodic axes, walls beyond the others) loaded beforehand, as
 // bytes k - 1 of nbr[0] (k = 1..4) and nbr[1] (k = 5..8).
-template <class T>
+//
+// PRESS compiles the pressure-boundary rule in. The two-step passes leave it
+// out (a lattice with pressure segments never runs them: its rescaling must
+// follow every step), which keeps the node's pre-collision populations out
+// of their register budget and their control flow as it was; without it an
+// open pressure link would take the outlet rule.
+template <class T, bool PRESS = true>
 __device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc, bool seg_tile,
                                              const PhaseNow &ph, const T *f, const T *g, T *pf,
                                              T *pg, T *in_f, T *in_g, Flux &fx, bool count,
@@ -312,7 +318,7 @@ __device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc,
         const T en = (T)(EX[j] * L.seg_nx[s] + EY[j] * L.seg_ny[s]);
         vf = fmad(T(-6) * (T)WF[j] * rho0 * en, us, pf[OPP[j]]);
         if (j < 5) vg = fmad(T(2) * wg[j], SegT<T>::cin(ph, s) - cs, -pg[OPP[j]]);
-      } else if (L.seg_kind[s] == GG_SEG_PRESSURE) {
+      } else if (PRESS && L.seg_kind[s] == GG_SEG_PRESSURE) {
         // do nothing: the node's own value of step t (the density is set by
         // the rescaling after the step); the compound alike where it is
         // held, else zero-gradient as at an outlet
@@ -338,7 +344,7 @@ __device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc,
 // in_g[j], the value arriving at (x, y) along j when x - e_j is not fluid,
 // from the pre- and post-collision g, pg; solute fluxes through open
 // segments into fx.
-template <class T>
+template <class T, bool PRESS = true>
 __device__ __forceinline__ void compound_links(CDesc &L, int x, int y, uint8_t lc, bool seg_tile,
                                                const PhaseNow &ph, const T *g, const T *pg,
                                                T *in_g, Flux &fx, bool count) {
@@ -368,8 +374,8 @@ __device__ __forceinline__ void compound_links(CDesc &L, int x, int y, uint8_t l
     if (!((ph.open >> s) & 1u)) continue;  // closed valve: a wall
     const T vg = L.seg_kind[s] == GG_SEG_INLET
                      ? fmad(T(2) * wg[j], SegT<T>::cin(ph, s) - cs, -pg[OPP[j]])
-                 : (L.seg_kind[s] == GG_SEG_PRESSURE && L.seg_holdc[s]) ? g[j]
-                                                                      : pg[j];
+                 : (PRESS && L.seg_kind[s] == GG_SEG_PRESSURE && L.seg_holdc[s]) ? g[j]
+                                                                               : pg[j];
     in_g[j] = vg;
     if (count) fx.add(s, 0.0, (double)(vg - pg[OPP[j]]));
   }
