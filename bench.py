@@ -283,9 +283,10 @@ CDE_LEG = (("gg2048_f32", 4096, 2000, 14), ("allfluid8192_f32", 512, 64, 14),
            ("gg8192_f16", 1024, 512, 0))
 
 
-def cpu_baseline(name, budget_s=15.0):
+def cpu_baseline(name, budget_s=15.0, single_budget_s=4.0):
     """The FP64 oracle, as it stands, on the host cores: a bounded number of
-    steps of the same workload from its initial state."""
+    steps of the same workload from its initial state, on all cores and on
+    one."""
     import numpy as np
     import oracle
     wl = workload(name)
@@ -295,17 +296,38 @@ def cpu_baseline(name, budget_s=15.0):
     if wl.init:
         o.init(**wl.init)
     nf = int(np.count_nonzero(wl.mask == 0))
+    cores = oracle.threads()
     t0 = time.perf_counter()
     o.step(1)
     t1 = time.perf_counter() - t0
     n = int(max(1, min(500, budget_s / max(t1, 1e-6))))
-    log(f"cpu baseline: oracle {n} steps (one step took {t1:.3f} s)")
+    log(f"cpu baseline: oracle {n} steps on {cores} threads (one step took {t1:.3f} s)")
     t0 = time.perf_counter()
     o.step(n)
     dt = time.perf_counter() - t0
-    return {"value": round(nf * n / dt / 1e6, 2), "unit": "MLUPS", "cores": oracle.threads(),
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        o.step(1)
+        t1s = time.perf_counter() - t0
+        n1 = int(max(1, min(100, single_budget_s / max(t1s, 1e-6))))
+        t0 = time.perf_counter()
+        o.step(n1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": round(nf * n / dt / 1e6, 2), "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
-            "sample": f"{n} FP64 oracle steps of {wl.name} ({nf} fluid nodes) from rest"}
+            "sample": f"{n} FP64 oracle steps of {wl.name} ({nf} fluid nodes) from rest",
+            "single_thread_value": round(nf * n1 / dt1 / 1e6, 2),
+            "single_thread_sample": f"{n1} further steps on one thread",
+            "cpu_model": model, "nproc": os.cpu_count()}
 
 
 def digest_counters(prof_dir, grids, out_path):
@@ -468,6 +490,14 @@ def main():
         out["step_profile_table3"] = experiments.step_profile_summary(storage="f32")
         log("boundary kinds: velocity inlet / outflow links against the pressure boundary")
         out["boundary_kinds"] = experiments.boundary_comparison()
+        log("reduced-precision storage against FP64: 8192x4096 (Pe 500, 2000) and 2048x1024")
+        from paper_1307_4703_amd import workloads as W
+        out["precision_vs_fp64"] = {
+            "gg8192_pe500": experiments.precision_report(
+                W.gradient_generator(scale=4.0, storage="f16", peclet=500.0), ("f16", "f32")),
+            "gg8192_pe2000": experiments.precision_report(
+                W.gradient_generator(scale=4.0, storage="f16", peclet=2000.0), ("f16",)),
+            "gg2048_pe500": experiments.precision_report(W.gradient_generator(), ("f32", "f16"))}
         if not args.no_batch:
             out["batched_64_instances"] = batch_bench()
     if not args.no_cpu_baseline:

@@ -3,4 +3,5 @@
 Importable only from the test-suite, the smoke entry point and the CPU-baseline
 leg of the benchmark. The HIP library never imports it.
 """
-from .oracle import Oracle, feq, geq, lib, segment_extent, tau_g_from_D, threads  # noqa: F401
+from .oracle import (Oracle, feq, geq, lib, segment_extent, set_threads, tau_g_from_D,  # noqa: F401
+                     threads)

@@ -509,6 +509,15 @@ int orc_threads(void) {
 #endif
 }
 
+/* Threads for the following steps (timing of the oracle on one core). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ---------------------------------------------------------------- */
 /* Discrete adjoint of one compound step (test infrastructure)         */
 /* ---------------------------------------------------------------- */

@@ -79,6 +79,8 @@ def lib() -> ctypes.CDLL:
         L.orc_adjoint_step.restype = None
         L.orc_threads.argtypes = []
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
         _LIB = L
     return _LIB
 
@@ -104,6 +106,11 @@ def geq(C: float, ux: float, uy: float, w0: float) -> np.ndarray:
 def threads() -> int:
     """OpenMP threads used by one oracle step."""
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads for the following oracle steps."""
+    lib().orc_set_threads(int(n))
 
 
 def tau_g_from_D(D: float, w0: float) -> float:

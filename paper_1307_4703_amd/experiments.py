@@ -329,11 +329,75 @@ def boundary_comparison(storage: str = "f64", steps: int = 30000,
     return out
 
 
+# ---------------------------------------------------------------------------
+# Reduced-precision storage against FP64 at full size
+# ---------------------------------------------------------------------------
+
+def block_means(a: np.ndarray, fluid: np.ndarray, b: int = 8) -> np.ndarray:
+    """Means over b x b blocks of the fluid nodes (NaN for blocks without
+    fluid): the 1024 x 512 view of an 8192 x 4096 field."""
+    ny, nx = a.shape
+    v = np.where(fluid, a, 0.0).reshape(ny // b, b, nx // b, b).sum(axis=(1, 3))
+    n = fluid.reshape(ny // b, b, nx // b, b).sum(axis=(1, 3))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.where(n > 0, v / np.maximum(n, 1), np.nan)
+
+
+def precision_report(wl, storages=("f16",), steps: int = 20000, block: int = 8) -> Dict:
+    """Run the workload from the same initial state in FP64 and in each
+    reduced storage type for `steps` steps (each in its fastest launch form)
+    and report, per field (rho, u = (ux, uy), C), the max and L2 error of the
+    reduced run against the FP64 run, relative to rho0, max |u| and
+    max(1, max C) of the FP64 run: on the block means of `block` x `block`
+    fluid nodes and on the full-resolution fields."""
+    fluid = wl.mask == 0
+    runs = {}
+    for st in ("f64",) + tuple(storages):
+        lat = Lattice.from_workload(wl, storage=st)
+        try:
+            lat.set_two_step(3, 14 if st == "f64" else 6)
+            t0 = time.perf_counter()
+            lat.step(steps)
+            lat.sync()
+            secs = time.perf_counter() - t0
+            runs[st] = (lat.read(), secs)
+        finally:
+            lat.close()
+    (rho0, ux0, uy0, C0), _ = runs["f64"]
+    umax = float(max(np.abs(ux0[fluid]).max(), np.abs(uy0[fluid]).max()))
+    cmax = float(max(1.0, np.abs(C0[fluid]).max()))
+    ref_b = {k: block_means(v, fluid, block) for k, v in
+             (("rho", rho0), ("ux", ux0), ("uy", uy0), ("C", C0))}
+    out = {"workload": wl.name, "steps": steps, "block": block,
+           "fp64_seconds": round(runs["f64"][1], 3), "max_u_fp64": umax, "max_C_fp64": cmax}
+    for st in storages:
+        (rho, ux, uy, C), secs = runs[st]
+        b = {k: block_means(v, fluid, block) for k, v in
+             (("rho", rho), ("ux", ux), ("uy", uy), ("C", C))}
+        rep = {"seconds": round(secs, 3)}
+        for field, scale in (("rho", wl.rho0), ("u", umax), ("C", cmax)):
+            if field == "u":
+                d_full = np.hypot(ux - ux0, uy - uy0)[fluid]
+                db = np.hypot(b["ux"] - ref_b["ux"], b["uy"] - ref_b["uy"])
+            else:
+                d_full = np.abs((rho - rho0) if field == "rho" else (C - C0))[fluid]
+                db = np.abs(b[field] - ref_b[field])
+            db = db[np.isfinite(db)]
+            rep[field] = {"max_block": float(db.max() / scale),
+                          "l2_block": float(np.sqrt(np.mean(db ** 2)) / scale),
+                          "max_full": float(d_full.max() / scale),
+                          "l2_full": float(np.sqrt(np.mean(d_full ** 2)) / scale)}
+        out[st] = rep
+    return out
+
+
 if __name__ == "__main__":
     import argparse
     import json
     ap = argparse.ArgumentParser(description="run the paper's experiments on the GPU")
-    ap.add_argument("experiment", choices=["step-profile", "gradient-formation", "boundaries"])
+    ap.add_argument("experiment", choices=["step-profile", "gradient-formation", "boundaries",
+                                           "precision"])
+    ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--hours", type=float, default=4.0)
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--out", default=None, help="write the full result as JSON")
@@ -343,6 +407,12 @@ if __name__ == "__main__":
         summ = res
     elif args.experiment == "boundaries":
         res = boundary_comparison()
+        summ = res
+    elif args.experiment == "precision":
+        res = {f"pe{int(pe)}": precision_report(W.gradient_generator(scale=4.0, storage="f16",
+                                                                       peclet=pe),
+                                                ("f16", "f32"), steps=args.steps)
+               for pe in (500.0, 2000.0)}
         summ = res
     else:
         res = gradient_formation(hours=args.hours, storage=args.storage,

@@ -169,3 +169,17 @@ def test_gradient_generator_full_size_f32():
     umax_chamber = np.sqrt(uxo[sel] ** 2 + uyo[sel] ** 2).max()
     assert d["max_u_region"] == pytest.approx(umax_chamber, rel=1e-3)
     assert d["max_pe_region"] == pytest.approx(umax_chamber / wl.D, rel=1e-3)
+
+
+def test_f64_full_size_8192_window():
+    """The 8192x4096 gradient generator (the lattice of the FP16 precision
+    report) in FP64 on the GPU against the oracle over a 200-step window
+    from a seeded state, every fluid node: the FP64 GPU run that the
+    reduced-precision runs are measured against is the oracle's run."""
+    wl = W.gradient_generator(scale=4.0, storage="f64", half_period=60)
+    log("full size 8192x4096 FP64, 200 steps against the oracle")
+    lat, o = _run(wl, "f64", 200, seed=11)
+    err = field_errors(lat, o, wl.mask == 0)
+    log(f"errors {err}")
+    for k in ("rho", "u", "C"):
+        assert err[k] < F64_TOL, (k, err)
