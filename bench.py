@@ -406,6 +406,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances leg")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the out-of-cache and FP16 lattices and the copy bandwidth")
+    ap.add_argument("--no-experiments", action="store_true",
+                    help="skip the step-profile, boundary-kind and precision legs")
     ap.add_argument("--cde-only", action="store_true",
                     help="time only the compound-only step on frozen velocity fields")
     ap.add_argument("--cde-steps", type=int, default=0,
@@ -485,6 +487,9 @@ def main():
         out["compound_only_frozen_velocity"] = {
             name: cde_bench(name, steps, flow, rows, args.chunk)
             for name, steps, flow, rows in cde_leg}
+        if not args.no_batch:
+            out["batched_64_instances"] = batch_bench()
+    if not args.no_extra and not args.no_experiments:
         from paper_1307_4703_amd import experiments
         log("step-profile test (Table 3), four cases, FP32")
         out["step_profile_table3"] = experiments.step_profile_summary(storage="f32")
@@ -498,8 +503,6 @@ def main():
             "gg8192_pe2000": experiments.precision_report(
                 W.gradient_generator(scale=4.0, storage="f16", peclet=2000.0), ("f16",)),
             "gg2048_pe500": experiments.precision_report(W.gradient_generator(), ("f32", "f16"))}
-        if not args.no_batch:
-            out["batched_64_instances"] = batch_bench()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
