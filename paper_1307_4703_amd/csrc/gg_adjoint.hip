@@ -71,7 +71,6 @@ template <class S>
 __device__ __forceinline__ void gather_state(CDesc &L, uint32_t node, uint8_t lc, int x, int y,
                                              typename Pop<S>::T *f, typename Pop<S>::T *g) {
   using P = Pop<S>;
-  using T = typename P::T;
   using W = typename P::W;
   const bool odd = (*(const GG_CONST int64_t *)L.t & 1) != 0;
   const int xm = (x == 0 && L.periodic_x) ? L.nx - 1 : x - 1;
