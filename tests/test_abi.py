@@ -80,3 +80,20 @@ def test_null_arguments():
     assert A.lib().gg_create(None, 4, 4, None, A.GG_F32, None, ctypes.byref(h)) == A.GG_ERR_ARG
     assert A.lib().gg_step(None, 1) == A.GG_ERR_ARG
     assert A.lib().gg_read(None, None, None, None, None, A.GG_HOST) == A.GG_ERR_ARG
+
+
+def test_create_rejects_a_lattice_too_large():
+    """One FP32 population plane must stay below 4 GiB (the kernels address
+    it with 32-bit byte offsets); the check comes before any allocation."""
+    big = np.zeros((30000, 40000), np.uint8)  # zero pages, never touched
+    st, err = _create(big)
+    assert st == A.GG_ERR_ARG and "too large" in err
+
+
+def test_null_arguments_of_the_later_calls():
+    assert A.lib().gg_cde_step(None, 2) == A.GG_ERR_ARG
+    assert A.lib().gg_set_velocity_field(None, 0, None, None, 1.0, A.GG_HOST) == A.GG_ERR_ARG
+    assert A.lib().gg_set_phase_fields(None, None, 0) == A.GG_ERR_ARG
+    assert A.lib().gg_set_cde_launch(None, 14) == A.GG_ERR_ARG
+    assert A.lib().gg_set_pressure_segment(None, 2, 1, 0, 1.0, 0.0, 0) == A.GG_ERR_ARG
+    assert A.lib().gg_set_two_step(None, 3, 6) == A.GG_ERR_ARG
