@@ -379,6 +379,11 @@ gg_status gg_step2_timed(gg_lattice *lat, int64_t n_pairs, double *ms_pass);
 gg_status gg_stream_copy(void *dst, const void *src, size_t bytes, int32_t reps,
                          void *hip_stream, double *ms);
 
+/* Instrumentation: shuffle the order of the tiles and strips the steps
+ * are launched over (seeded), e.g. to check that the result does not depend
+ * on the order in which work-groups run. Waits for the stream. */
+gg_status gg_permute_tiles(gg_lattice *lat, uint64_t seed);
+
 /* Wait for all work issued on the lattice's stream. */
 gg_status gg_sync(gg_lattice *lat);
 

@@ -102,6 +102,7 @@ SIGS = {
     "gg_batch_step": [P, I64],
     "gg_batch_set_two_step": [P, I32, I32],
     "gg_batch_info": [P, ctypes.POINTER(I64), ctypes.POINTER(I64)],
+    "gg_permute_tiles": [P, ctypes.c_uint64],
     "gg_stream_copy": [P, P, ctypes.c_size_t, I32, P, ctypes.POINTER(D)],
 }
 

@@ -1,6 +1,7 @@
 // Host runtime behind the C ABI of include/gg.h: geometry classification,
 // boundary segments, valve schedule, device memory, launches and graphs.
 #include <algorithm>
+#include <random>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1697,6 +1698,28 @@ gg_status gg_cde_step(gg_lattice *L, int64_t n) {
     GG_HIP(launch_cde_steps(L, L->t, left, L->stream));
     L->t += left;
   }
+  return GG_OK;
+}
+
+gg_status gg_permute_tiles(gg_lattice *L, uint64_t seed) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  GG_HIP(hipStreamSynchronize(L->stream));
+  std::mt19937_64 rng(seed);
+  auto shuffle = [&](Tile *d, int n) -> hipError_t {
+    if (n <= 1) return hipSuccess;
+    std::vector<Tile> h((size_t)n);
+    hipError_t e = hipMemcpy(h.data(), d, h.size() * sizeof(Tile), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    std::shuffle(h.begin(), h.end(), rng);
+    return hipMemcpy(d, h.data(), h.size() * sizeof(Tile), hipMemcpyHostToDevice);
+  };
+  GG_HIP(shuffle(L->d_tiles, L->n_tiles));
+  GG_HIP(shuffle(L->d_strips, L->n_strips));
+  GG_HIP(shuffle(L->d_seg_strips, L->n_seg_strips));
+  if (L->graph_exec) (void)hipGraphExecDestroy(L->graph_exec);
+  if (L->graph) (void)hipGraphDestroy(L->graph);
+  L->graph_exec = nullptr;
+  L->graph = nullptr;
   return GG_OK;
 }
 

@@ -166,6 +166,10 @@ class Lattice:
     def sync(self) -> None:
         A.call("gg_sync", self._h)
 
+    def permute_tiles(self, seed: int) -> None:
+        """Shuffle the launch order of the tiles and strips (instrumentation)."""
+        A.call("gg_permute_tiles", self._h, int(seed))
+
     # compound alone on frozen velocity fields (include/gg.h, gg_cde_step)
     def set_velocity_field(self, slot: int, ux: Optional[np.ndarray] = None,
                            uy: Optional[np.ndarray] = None, scale: float = 1.0) -> None:
