@@ -39,9 +39,8 @@
  *                                 and otherwise zero-gradient as at an
  *                                 outlet.
  *      Outside the domain counts as wall unless that axis is periodic.
- * The wall and no-flux schemes of the paper (Boundary Conditions section)
- * are not these; the choice of the bounce-back family is a documented
- * reading.
+ * With wall_scheme = 1 the links from walls and closed valves take the
+ * paper's wall conditions instead of bounce-back (see wall_links below).
  *
  * Compile with -ffp-contract=off so every product and sum is rounded as
  * written.
@@ -89,6 +88,7 @@ typedef struct orc_lattice {
   const double *seg_s1;      /* upper halfway-wall tangential coordinate */
   const double *seg_rho;     /* density held by a pressure segment */
   const int32_t *seg_fixc;   /* pressure segment also holds C = C_in */
+  int32_t wall_scheme;       /* 0: halfway bounce-back; 1: the paper's walls */
 } orc_lattice;
 
 /* ---------------------------------------------------------------- */
@@ -235,6 +235,81 @@ static void collide_node(const orc_lattice *L, size_t node, const double *fx,
     gpost[i] = gx[i] - omega_g * (gx[i] - geq[i]) + wg[i] * src;
 }
 
+/* The paper's wall conditions (Boundary Conditions section), for a fluid
+ * node z whose link i comes from a wall or closed-valve cell s = z - e_i:
+ * the cell s is taken as a node whose populations at step t are
+ *   fluid: the equilibrium f_i^eq(rho_s, u_s), its momentum interpolated
+ *     linearly through zero at the wall, which lies halfway between s and
+ *     z (j_s = -j(z)), its density extrapolated linearly from the fluid
+ *     along e_i (rho_s = 2 rho(z) - rho(z + e_i), or rho(z) where z + e_i
+ *     is not fluid), u_s = j_s / rho_s;
+ *   compound: the no-flux condition by non-equilibrium extrapolation (Guo
+ *     et al.): the post-collision population of s is the equilibrium of
+ *     z's concentration at the ghost velocity plus z's non-equilibrium part
+ *     relaxed by the collision, g_i^eq(C(z), u_s) + (1 - omega_g)
+ *     (g_i(z) - g_i^eq(C(z), u(z))) (zero normal gradient of C);
+ * and what it emits along e_i arrives at z at t + 1. Every quantity is of
+ * step t (the populations before the collision), so the rule needs no
+ * value of step t + 1. Fills fz[i] (and gz[i], i <= 4) for every such link
+ * of the node at (x, y); f, g: the state at step t. */
+static void wall_links(const orc_lattice *L, int x, int y, const double *f, const double *g,
+                       const uint8_t *open, double *fz, double *gz) {
+  const int nx = L->nx;
+  const size_t node = (size_t)y * nx + x;
+  const double omega_g = 1.0 / L->tau_g;
+  double rho = 0.0, jx = 0.0, jy = 0.0, C = 0.0;
+  for (int k = 0; k < 9; ++k) {
+    rho += f[9 * node + k];
+    jx += f[9 * node + k] * EX[k];
+    jy += f[9 * node + k] * EY[k];
+  }
+  for (int k = 0; k < 5; ++k) C += g[5 * node + k];
+  const double ux = jx / rho, uy = jy / rho;
+  for (int i = 1; i < 9; ++i) {
+    int xs = 0, ys = 0;
+    int code = cell_code(L, x - EX[i], y - EY[i], &xs, &ys);
+    if (code == 0) continue;
+    if (!(code == 1 || L->seg_kind[code] == ORC_SEG_NONE || !open[code])) continue;
+    double rho_s = rho;
+    int xa = 0, ya = 0;
+    if (cell_code(L, x + EX[i], y + EY[i], &xa, &ya) == 0) {
+      size_t a = (size_t)ya * nx + xa;
+      double rho_a = 0.0;
+      for (int k = 0; k < 9; ++k) rho_a += f[9 * a + k];
+      rho_s = 2.0 * rho - rho_a;
+    }
+    double feq[9];
+    orc_feq(rho_s, -jx / rho_s, -jy / rho_s, feq);
+    fz[i] = feq[i];
+    if (i <= 4) {
+      double gs[5], gz0[5];
+      orc_geq(C, -jx / rho_s, -jy / rho_s, L->w0, gs);
+      orc_geq(C, ux, uy, L->w0, gz0);
+      gz[i] = gs[i] + (1.0 - omega_g) * (g[5 * node + i] - gz0[i]);
+    }
+  }
+}
+
+/* The compound's wall rule of wall_links in the compound-only step, where
+ * the velocity of z is the frozen field's u and the ghost's is -u. */
+static void wall_links_cde(const orc_lattice *L, int x, int y, const double *g, double ux,
+                           double uy, const uint8_t *open, double *gz) {
+  const size_t node = (size_t)y * L->nx + x;
+  const double omega_g = 1.0 / L->tau_g;
+  double C = 0.0;
+  for (int k = 0; k < 5; ++k) C += g[5 * node + k];
+  double gs[5], gz0[5];
+  orc_geq(C, -ux, -uy, L->w0, gs);
+  orc_geq(C, ux, uy, L->w0, gz0);
+  for (int i = 1; i < 5; ++i) {
+    int xs = 0, ys = 0;
+    int code = cell_code(L, x - EX[i], y - EY[i], &xs, &ys);
+    if (code == 0) continue;
+    if (!(code == 1 || L->seg_kind[code] == ORC_SEG_NONE || !open[code])) continue;
+    gz[i] = gs[i] + (1.0 - omega_g) * (g[5 * node + i] - gz0[i]);
+  }
+}
+
 /* open[m]  : nonzero if segment with mask value m is open at step t.
  * c_in[m]  : compound concentration imposed by open inlet m at step t.
  * flux_mass[m], flux_solute[m] : accumulate the net amount of fluid mass and
@@ -336,6 +411,8 @@ void orc_step(const orc_lattice *L, const double *f, const double *g,
           rf[2 * code + 1] += in_g - out_g;
         }
       }
+      /* the paper's walls replace the bounce-back of wall links */
+      if (L->wall_scheme == 1) wall_links(L, x, y, f, g, open, fn + 9 * node, gn + 5 * node);
       /* pressure boundary: rescale the streamed state of the node */
       int m = pressure_segment(L, x, y, open);
       if (m) {
@@ -427,6 +504,7 @@ void orc_cde_step(const orc_lattice *L, const double *g, double *gn,
         gn[5 * node + i] = in;
         rf[code] += in - out;
       }
+      if (L->wall_scheme == 1) wall_links_cde(L, x, y, g, ux[node], uy[node], open, gn + 5 * node);
       int m = pressure_segment(L, x, y, open);
       if (m) rf[m] += rescale_g(L, m, gn + 5 * node, c_in);
     }

@@ -38,6 +38,7 @@ class _OrcLattice(ctypes.Structure):
         ("seg_umax", ctypes.c_void_p), ("seg_s0", ctypes.c_void_p),
         ("seg_s1", ctypes.c_void_p),
         ("seg_rho", ctypes.c_void_p), ("seg_fixc", ctypes.c_void_p),
+        ("wall_scheme", ctypes.c_int32),
     ]
 
 
@@ -146,7 +147,7 @@ class Oracle:
                  periodic: Sequence[bool] = (False, False),
                  segments: Iterable = (), schedule: Optional[Sequence] = None,
                  t_origin: int = 0, R: Optional[np.ndarray] = None,
-                 tau_g: Optional[float] = None):
+                 tau_g: Optional[float] = None, wall_scheme: str = "bounce_back"):
         self.mask = np.ascontiguousarray(mask, dtype=np.uint8)
         self.ny, self.nx = self.mask.shape
         self.w0 = float(w0)
@@ -182,7 +183,8 @@ class Oracle:
             _ptr(self.mask), self.tau_f, self.tau_g, self.w0, self.rho0,
             float(k_decay), _ptr(self.R), _ptr(self._kind), _ptr(self._nrm),
             _ptr(self._umax), _ptr(self._s0), _ptr(self._s1), _ptr(self._rho),
-            _ptr(self._fixc))
+            _ptr(self._fixc), {"bounce_back": 0, "equilibrium": 1}[wall_scheme])
+        self.wall_scheme = wall_scheme
         n = self.nx * self.ny
         self.f = np.zeros((self.ny, self.nx, 9))
         self.g = np.zeros((self.ny, self.nx, 5))
@@ -306,6 +308,8 @@ class Oracle:
         """
         if any(s.kind == "pressure" for s in self.segments.values()):
             raise NotImplementedError("the pressure boundary's rescaling is not linear in g")
+        if self.wall_scheme != "bounce_back":
+            raise NotImplementedError("the adjoint is written for bounce-back walls")
         weight = np.asarray(weight, np.float64).reshape(self.ny, self.nx)
         target = np.asarray(target, np.float64).reshape(self.ny, self.nx)
         fl = self.mask == 0

@@ -14,6 +14,7 @@ from tests import test_oracle_adjoint as AD
 from tests import test_oracle_cde as CD
 from tests import test_oracle_pins as P
 from tests import test_oracle_pressure as PR
+from tests import test_oracle_walls as WL
 
 PINS = [
     (P.test_feq_full_moment_basis, dict(rho=1.03, ux=0.05, uy=-0.02)),
@@ -36,6 +37,17 @@ PINS = [
     (CD.test_cde_step_equals_the_coupled_compound_update, {}),
     (CD.test_cde_uniform_velocity_exact_fourier_evolution, {}),
     (CD.test_cde_closed_box_conserves_solute, {}),
+]
+# the pins of the paper's walls, tried first for mistakes in their code
+WALL_PINS = [
+    (WL.test_ghost_density_extrapolated_linearly, dict(valve=False)),
+    (WL.test_ghost_density_extrapolated_linearly, dict(valve=True)),
+    (WL.test_ghost_momentum_vanishes_at_the_halfway_wall, {}),
+    (WL.test_ghost_compound_even_about_the_wall, {}),
+    (WL.test_compound_only_step_ghost_rule, {}),
+    (WL.test_rest_state_is_fixed_point, {}),
+    (WL.test_compound_uniform_across_the_channel_stays_so, {}),
+    (WL.test_pressure_driven_flow_no_slip_points, {}),
 ]
 # the pressure boundary's pins, tried first for mistakes in its code
 PRESSURE_PINS = [
@@ -98,6 +110,16 @@ MUTATIONS = {
     "pressure compound not counted": ("return c_in[m] - C;", "return 0.0;"),
     "compound-only pressure rule": ("in = L->seg_fixc[code] ? g[5 * node + i] : gp[5 * node + i];",
                                     "in = L->seg_fixc[code] ? gp[5 * node + i] : gp[5 * node + i];"),
+    "paper wall rule: ghost momentum sign": ("orc_feq(rho_s, -jx / rho_s, -jy / rho_s, feq);",
+                                             "orc_feq(rho_s, jx / rho_s, -jy / rho_s, feq);"),
+    "paper wall rule: density extrapolation": ("rho_s = 2.0 * rho - rho_a;", "rho_s = rho_a;"),
+    "paper wall rule: Guo relaxation": ("gz[i] = gs[i] + (1.0 - omega_g) * (g[5 * node + i] - gz0[i]);\n    }\n  }\n}",
+                                        "gz[i] = gs[i] + (g[5 * node + i] - gz0[i]);\n    }\n  }\n}"),
+    "paper wall rule: Guo ghost velocity": ("orc_geq(C, -jx / rho_s, -jy / rho_s, L->w0, gs);",
+                                            "orc_geq(C, -jx / rho_s, jy / rho_s, L->w0, gs);"),
+    "paper wall rule: compound-only ghost": ("orc_geq(C, -ux, -uy, L->w0, gs);", "orc_geq(C, -ux, uy, L->w0, gs);"),
+    "paper wall rule: wall link test": ("    if (!(code == 1 || L->seg_kind[code] == ORC_SEG_NONE || !open[code])) continue;\n    double rho_s",
+                                        "    if (!(code == 1)) continue;\n    double rho_s"),
     "adjoint wall transpose": ("            ls[j] += lx[opp];\n          } else if (kind == ORC_SEG_INLET) {",
                                "            ls[j] += lx[j];\n          } else if (kind == ORC_SEG_INLET) {"),
 }
@@ -114,7 +136,12 @@ def test_some_pin_catches(name, tmp_path):
     lib_path = build_oracle.build(src=mut, out=os.path.join(tmp_path, "libmut.so"))
     orc.use_library(lib_path)
     caught = []
-    pins = PRESSURE_PINS + PINS if "pressure" in name else PINS + PRESSURE_PINS
+    if "pressure" in name:
+        pins = PRESSURE_PINS + PINS
+    elif "wall rule" in name:
+        pins = WALL_PINS + PINS
+    else:
+        pins = PINS + PRESSURE_PINS
     try:
         for fn, kw in pins:
             try:
