@@ -379,6 +379,28 @@ gg_status gg_step2_timed(gg_lattice *lat, int64_t n_pairs, double *ms_pass);
 gg_status gg_stream_copy(void *dst, const void *src, size_t bytes, int32_t reps,
                          void *hip_stream, double *ms);
 
+/* Wall conditions at the links from walls and closed or unconfigured valve
+ * cells (paper, Boundary Conditions section):
+ *   GG_WALL_BOUNCE_BACK (default): halfway bounce-back, the population
+ *     leaving z toward the wall comes back along the opposite link.
+ *   GG_WALL_PAPER : the paper's walls. The wall cell s = z - e_i next to
+ *     fluid node z is a ghost node emitting along e_i the equilibrium
+ *     f_i^eq(rho_s, u_s) of the density extrapolated linearly from the
+ *     fluid, rho_s = 2 rho(z) - rho(z + e_i) (rho(z) where z + e_i is not
+ *     fluid), and the momentum that vanishes at the halfway wall, u_s =
+ *     -j(z) / rho_s; the compound takes the non-equilibrium extrapolation
+ *     of Guo et al. (no flux through the wall): g_i^eq(C(z), u_s) +
+ *     (1 - omega_g) (g_i(z) - g_i^eq(C(z), u(z))). All quantities are those
+ *     of step t (before the collision). In the compound-only step u(z) is
+ *     the frozen field's and u_s = -u(z).
+ * With GG_WALL_PAPER, steps run one at a time (no two-step passes), with a
+ * save kernel before and a fix-up kernel after each; the adjoint, the timed
+ * calls and batches refuse such lattices. Mass is not conserved exactly
+ * (the ghost density is extrapolated). Errors: GG_ERR_ARG for a NULL
+ * lattice or an unknown scheme. */
+typedef enum gg_wall_scheme { GG_WALL_BOUNCE_BACK = 0, GG_WALL_PAPER = 1 } gg_wall_scheme;
+gg_status gg_set_wall_scheme(gg_lattice *lat, int32_t scheme);
+
 /* Instrumentation: shuffle the order of the tiles and strips the steps
  * are launched over (seeded), e.g. to check that the result does not depend
  * on the order in which work-groups run. Waits for the stream. */

@@ -194,6 +194,11 @@ class Oracle:
         self.flux_solute = np.zeros(256)
         self.init()
 
+    def set_wall_scheme(self, wall_scheme: str) -> None:
+        """Switch the wall conditions for the following steps."""
+        self._c.wall_scheme = {"bounce_back": 0, "equilibrium": 1}[wall_scheme]
+        self.wall_scheme = wall_scheme
+
     # -- schedule -------------------------------------------------------
     def phase(self, t: int):
         """(open[256], c_in[256]) in force during step t -> t+1.

@@ -23,6 +23,8 @@ GG_F64, GG_F32, GG_F16_SHIFTED = 0, 1, 2
 GG_HOST, GG_DEVICE = 0, 1
 GG_SEG_INLET, GG_SEG_OUTLET, GG_SEG_PRESSURE = 1, 2, 3
 GG_FIRST_SEGMENT = 2
+GG_WALL_BOUNCE_BACK, GG_WALL_PAPER = 0, 1
+WALL_SCHEMES = {"bounce_back": GG_WALL_BOUNCE_BACK, "equilibrium": GG_WALL_PAPER}
 GG_MAX_SEGMENTS = 16
 GG_MAX_PHASES = 64
 
@@ -103,6 +105,7 @@ SIGS = {
     "gg_batch_set_two_step": [P, I32, I32],
     "gg_batch_info": [P, ctypes.POINTER(I64), ctypes.POINTER(I64)],
     "gg_permute_tiles": [P, ctypes.c_uint64],
+    "gg_set_wall_scheme": [P, I32],
     "gg_stream_copy": [P, P, ctypes.c_size_t, I32, P, ctypes.POINTER(D)],
 }
 

@@ -46,6 +46,15 @@ hipError_t launch_put_field(gg_storage s, const LatDesc *d, const Tile *tiles, i
                             int tx_shift, int slot, const double *ux, const double *uy,
                             double scale, hipStream_t st);
 
+// The paper's walls for the n nodes listed as (x, y) pairs: before step
+// (device counter + dt), save what the rule needs of that step (16 values
+// of the compute type per node) into `save`; after it, write the wall
+// links' values; fluid = false: the compound-only step (frozen field).
+hipError_t launch_wall_save(gg_storage s, const LatDesc *d, const int32_t *xy, int n, int dt,
+                            void *save, hipStream_t st);
+hipError_t launch_wall_apply(gg_storage s, const LatDesc *d, const int32_t *xy, int n, int dt,
+                             const void *save, bool fluid, hipStream_t st);
+
 // Auxiliary kernels: 256-thread work-groups over one lattice's tiles.
 hipError_t launch_init(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                        int tx_shift, const double *rho, const double *ux,

@@ -544,6 +544,187 @@ hipError_t launch_rescale(gg_storage s, const LatDesc *d, const int32_t *xy, int
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// The paper's walls: ghost cells in place of bounce-back (fix-up kernels).
+// ---------------------------------------------------------------------------
+// For a fluid node z and a link i whose source s = z - e_i is a wall or a
+// closed valve, s acts as a ghost node that emits, along e_i, at step t:
+//   f_i^eq(rho_s, u_s), rho_s = 2 rho(z) - rho(z + e_i) (rho(z) where
+//   z + e_i is not fluid), u_s = -j(z) / rho_s (momentum through zero at
+//   the halfway wall), and
+//   g_i^eq(C(z), u_s) + (1 - omega_g) (g_i(z) - g_i^eq(C(z), u(z)))
+//   (Guo's non-equilibrium extrapolation, zero normal gradient of C),
+// all of step t. k_wall_save stores, before the step, what these need of
+// step t (it is overwritten in place by the step); k_wall_apply writes the
+// values, after the step, into z's own slots i, where the step left the
+// bounce-back value (a link from a non-fluid cell arrives in the node's own
+// slot in both parities). In the compound-only step u(z) is the frozen
+// field's and u_s = -u(z).
+constexpr int WALL_SAVE = 16;  // d rho, j_x, j_y, dC, d rho(z + e_k) k = 1..8, dg_1..4
+
+// Mask value of the source cell x - e_j (j = 1..8), wrapped on periodic
+// axes; a wall outside the lattice otherwise.
+__device__ __forceinline__ int source_code(CDesc &L, int x, int y, int j) {
+  int sx = x - EX[j], sy = y - EY[j];
+  if (sx < 0 || sx >= L.nx) {
+    if (!L.periodic_x) return GG_MASK_WALL;
+    sx = (sx + L.nx) % L.nx;
+  }
+  if (sy < 0 || sy >= L.ny) {
+    if (!L.periodic_y) return GG_MASK_WALL;
+    sy = (sy + L.ny) % L.ny;
+  }
+  return ((const GG_GLOBAL uint8_t *)L.mask)[L.node0 + sy * L.pitch + sx];
+}
+
+// A link from source code `code` takes the wall rule at a step in phase ph.
+__device__ __forceinline__ bool wall_link(CDesc &L, int code, const PhaseNow &ph) {
+  if (code == GG_MASK_WALL) return true;
+  if (code < GG_FIRST_SEGMENT) return false;
+  const int q = code - GG_FIRST_SEGMENT;
+  return L.seg_kind[q] == 0 || !((ph.open >> q) & 1u);
+}
+
+template <class S>
+__global__ void __launch_bounds__(256)
+    k_wall_save(const LatDesc *__restrict__ desc, const int32_t *__restrict__ xy, int n, int dt,
+                typename Pop<S>::T *__restrict__ save) {
+#pragma clang fp contract(off)
+  using P = Pop<S>;
+  using T = typename P::T;
+  const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (k >= n) return;
+  CDesc &L = *(CDesc *)desc;
+  const int x = xy[2 * k], y = xy[2 * k + 1];
+  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+  const uint8_t lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
+  const int64_t t = *(const GG_CONST int64_t *)L.t + dt;
+  const bool odd = (t & 1) != 0;
+  const Planes<typename P::W> pl(L);
+  T f[9], g[5];
+  {
+    const Neigh nb(L, x, y);
+    if (odd) load_state<S, true>(pl, node, lc, nb, f, g);
+    else load_state<S, false>(pl, node, lc, nb, f, g);
+  }
+  T *o = save + (size_t)k * WALL_SAVE;
+  {
+    o[0] = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    o[1] = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    o[2] = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
+    o[3] = g[0] + g[1] + g[2] + g[3] + g[4];
+  }
+#pragma unroll
+  for (int i = 1; i < 5; ++i) o[11 + i] = g[i];
+  for (int i = 1; i < 9; ++i) {
+    o[3 + i] = o[0];  // (no fluid at z + e_i: rho(z))
+    if (!((lc >> (OPP[i] - 1)) & 1)) continue;  // the source of link i is fluid
+    int ax = x + EX[i], ay = y + EY[i];
+    bool inside = true;
+    if (ax < 0 || ax >= L.nx) {
+      if (L.periodic_x) ax = (ax + L.nx) % L.nx; else inside = false;
+    }
+    if (ay < 0 || ay >= L.ny) {
+      if (L.periodic_y) ay = (ay + L.ny) % L.ny; else inside = false;
+    }
+    if (!inside) continue;
+    const uint32_t an = (uint32_t)(L.node0 + ay * L.pitch + ax);
+    const uint8_t alc = ((const GG_GLOBAL uint8_t *)L.link)[an];
+    if (alc == NOT_FLUID) continue;
+    T fa[9], ga[5];
+    const Neigh nba(L, ax, ay);
+    if (odd) load_state<S, true>(pl, an, alc, nba, fa, ga);
+    else load_state<S, false>(pl, an, alc, nba, fa, ga);
+    const T ra = fa[0] + fa[1] + fa[2] + fa[3] + fa[4] + fa[5] + fa[6] + fa[7] + fa[8];
+    o[3 + i] = T(2) * o[0] - ra;
+  }
+}
+
+template <class S>
+__global__ void __launch_bounds__(256)
+    k_wall_apply(const LatDesc *__restrict__ desc, const int32_t *__restrict__ xy, int n, int dt,
+                 const typename Pop<S>::T *__restrict__ save, int fluid) {
+#pragma clang fp contract(off)
+  using P = Pop<S>;
+  using T = typename P::T;
+  const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (k >= n) return;
+  CDesc &L = *(CDesc *)desc;
+  const int x = xy[2 * k], y = xy[2 * k + 1];
+  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+  const uint8_t lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
+  const int64_t t = *(const GG_CONST int64_t *)L.t + dt;
+  const PhaseNow ph = phase_at(L, t);
+  const Planes<typename P::W> pl(L);
+  const T *o = save + (size_t)k * WALL_SAVE;
+  const T rho0 = (T)L.rho0, cs = (T)L.c_shift, ics = (T)L.inv_cs2g;
+  const T wga = (T)L.wg_axis;
+  const T wg[5] = {T(1) - T(4) * wga, wga, wga, wga, wga};
+  const T dC = o[3];
+  const T C = cs + dC;
+  T ux, uy;
+  if (fluid) {
+    const T rho = rho0 + o[0];
+    ux = o[1] / rho;
+    uy = o[2] / rho;
+  } else {
+    const int slot = L.phase_field[ph.index];
+    ux = ((const GG_GLOBAL T *)L.ufield)[(int64_t)(2 * slot) * L.plane + node];
+    uy = ((const GG_GLOBAL T *)L.ufield)[(int64_t)(2 * slot + 1) * L.plane + node];
+  }
+  const T omg = T(1) - (T)L.omega_g;
+  for (int i = 1; i < 9; ++i) {
+    if (!((lc >> (OPP[i] - 1)) & 1)) continue;  // the source of link i is fluid
+    if (!fluid && i > 4) break;
+    if (!wall_link(L, source_code(L, x, y, i), ph)) continue;
+    T usx, usy;
+    if (fluid) {
+      const T drs = o[3 + i];
+      const T rs = rho0 + drs;
+      usx = -o[1] / rs;
+      usy = -o[2] / rs;
+      const T eu = (T)EX[i] * usx + (T)EY[i] * usy;
+      const T usq = usx * usx + usy * usy;
+      const T poly = T(3) * eu + T(4.5) * eu * eu - T(1.5) * usq;
+      P::st(pl.at(i, node), (T)WF[i] * (drs + rs * poly));
+    } else {
+      usx = -ux;
+      usy = -uy;
+    }
+    if (i < 5) {
+      const T eus = (T)EX[i] * usx + (T)EY[i] * usy;
+      const T euz = (T)EX[i] * ux + (T)EY[i] * uy;
+      const T eq_s = wg[i] * (dC + C * eus * ics);  // g^eq(C, u_s) - w C_s
+      const T eq_z = wg[i] * (dC + C * euz * ics);  // g^eq(C, u(z)) - w C_s
+      P::st(pl.at(9 + i, node), eq_s + omg * (o[11 + i] - eq_z));
+    }
+  }
+}
+
+hipError_t launch_wall_save(gg_storage s, const LatDesc *d, const int32_t *xy, int n, int dt,
+                            void *save, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int grid = (n + 255) / 256;
+  switch (s) {
+    case GG_F64: k_wall_save<double><<<grid, 256, 0, st>>>(d, xy, n, dt, (double *)save); break;
+    case GG_F32: k_wall_save<float><<<grid, 256, 0, st>>>(d, xy, n, dt, (float *)save); break;
+    case GG_F16_SHIFTED: k_wall_save<__half><<<grid, 256, 0, st>>>(d, xy, n, dt, (float *)save); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_wall_apply(gg_storage s, const LatDesc *d, const int32_t *xy, int n, int dt,
+                             const void *save, bool fluid, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int grid = (n + 255) / 256;
+  switch (s) {
+    case GG_F64: k_wall_apply<double><<<grid, 256, 0, st>>>(d, xy, n, dt, (const double *)save, fluid); break;
+    case GG_F32: k_wall_apply<float><<<grid, 256, 0, st>>>(d, xy, n, dt, (const float *)save, fluid); break;
+    case GG_F16_SHIFTED: k_wall_apply<__half><<<grid, 256, 0, st>>>(d, xy, n, dt, (const float *)save, fluid); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_advance(const LatDesc *descs, int n, int64_t k, hipStream_t st) {
   k_advance<<<(n + 63) / 64, 64, 0, st>>>(descs, n, k);
   return hipGetLastError();

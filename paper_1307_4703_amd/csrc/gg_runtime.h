@@ -72,6 +72,14 @@ struct gg_lattice {
   int32_t *d_press = nullptr;
   int n_press = 0;
   bool press_dirty = true;
+  // the paper's walls (wall_scheme 1): fluid nodes with a link from a wall
+  // or a segment's ghost cell, as (x, y) pairs, and the values of step t
+  // their rule needs (saved before each step)
+  int wall_scheme = 0;
+  int32_t *d_wall = nullptr;
+  int n_wall = 0;
+  void *d_wall_save = nullptr;
+  bool wall_dirty = true;
   // compound alone on frozen velocity fields: n_ufield slots of two planes
   // (u_x, u_y) in the compute type; bit k of ufield_set: slot k written;
   // phase_field[k]: slot used in schedule phase k; graphs of graph_chunk

@@ -69,7 +69,8 @@ void gg_free_device(gg_lattice *L) {
   L->graph = nullptr;
   void *ptrs[] = {L->d_pop, L->d_pop_b, L->d_link, L->d_mask, L->d_region, L->d_R, L->d_t,
                   L->d_flux, L->d_acc, L->d_desc, L->d_tiles, L->d_aux_tiles, L->d_strips,
-                  L->d_seg_strips, L->d_partial, L->d_ufield, L->d_cde_tiles, L->d_press};
+                  L->d_seg_strips, L->d_partial, L->d_ufield, L->d_cde_tiles, L->d_press,
+                  L->d_wall, L->d_wall_save};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (L->cap_stream) (void)hipStreamDestroy(L->cap_stream);
@@ -696,6 +697,42 @@ static gg_status check_segments(gg_lattice *L) {
 // between the two plane sets and end in the first one.
 // One two-step pass: the segment strips on the side stream, forked from and
 // joined back to st (inside a capture this becomes two graph branches).
+// Lattices whose steps must run one at a time with fix-ups around them.
+static bool special_boundaries(const gg_lattice *L) { return has_pressure(L) || L->wall_scheme != 0; }
+
+// The fluid nodes with a link from a wall or from a segment's ghost cell
+// (a valve that may close), for the paper's walls.
+static gg_status wall_nodes(gg_lattice *L) {
+  if (!L->wall_dirty) return GG_OK;
+  std::vector<int32_t> xy;
+  if (L->wall_scheme != 0)
+    for (int y = 0; y < L->ny; ++y)
+      for (int x = 0; x < L->nx; ++x) {
+        const uint8_t lc = L->link[L->nid(x, y)];
+        if (lc == NOT_FLUID || lc == 0) continue;
+        xy.push_back(x);
+        xy.push_back(y);
+      }
+  if (L->d_wall) GG_HIP(hipFree(L->d_wall));
+  if (L->d_wall_save) GG_HIP(hipFree(L->d_wall_save));
+  L->d_wall = nullptr;
+  L->d_wall_save = nullptr;
+  L->n_wall = (int)(xy.size() / 2);
+  if (!xy.empty()) {
+    GG_HIP(hipMalloc(&L->d_wall, xy.size() * sizeof(int32_t)));
+    GG_HIP(hipMemcpy(L->d_wall, xy.data(), xy.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    const size_t tb = L->storage == GG_F64 ? 8 : 4;
+    GG_HIP(hipMalloc(&L->d_wall_save, (size_t)L->n_wall * 16 * tb));
+  }
+  L->wall_dirty = false;
+  if (L->graph_exec) (void)hipGraphExecDestroy(L->graph_exec);
+  if (L->graph) (void)hipGraphDestroy(L->graph);
+  L->graph_exec = nullptr;
+  L->graph = nullptr;
+  gg_drop_cde_graphs(L);
+  return GG_OK;
+}
+
 static hipError_t launch_pass(gg_lattice *L, int dir, int dt, hipStream_t st) {
   hipError_t e = hipSuccess;
   const bool fork = L->n_seg_strips > 0 && L->n_strips > 0;
@@ -723,7 +760,7 @@ static hipError_t launch_pass(gg_lattice *L, int dir, int dt, hipStream_t st) {
 
 static hipError_t launch_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t st) {
   hipError_t e = hipSuccess;
-  if (L->fuse >= 2 && !(t0 & 1) && n % 4 == 0 && L->n_press == 0) {
+  if (L->fuse >= 2 && !(t0 & 1) && n % 4 == 0 && L->n_press == 0 && L->wall_scheme == 0) {
     for (int64_t k = 0; k < n / 2 && e == hipSuccess; ++k)
       e = launch_pass(L, (int)(k & 1), (int)(2 * k), st);
   } else {
@@ -732,8 +769,15 @@ static hipError_t launch_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t
     const int block = L->tile_x * L->tile_y;
     const int txs = ilog2(L->tile_x);
     for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt) {
-      e = launch_step(L->storage, block, ((t0 + dt) & 1) != 0, L->d_desc, L->d_tiles,
-                      L->n_tiles, txs, (int)dt, st);
+      if (L->n_wall > 0)
+        e = launch_wall_save(L->storage, L->d_desc, L->d_wall, L->n_wall, (int)dt,
+                             L->d_wall_save, st);
+      if (e == hipSuccess)
+        e = launch_step(L->storage, block, ((t0 + dt) & 1) != 0, L->d_desc, L->d_tiles,
+                        L->n_tiles, txs, (int)dt, st);
+      if (e == hipSuccess && L->n_wall > 0)
+        e = launch_wall_apply(L->storage, L->d_desc, L->d_wall, L->n_wall, (int)dt,
+                              L->d_wall_save, true, st);
       if (e == hipSuccess && L->n_press > 0)
         e = launch_rescale(L->storage, L->d_desc, L->d_press, L->n_press, (int)dt, true, st);
     }
@@ -747,7 +791,7 @@ gg_status gg_step(gg_lattice *L, int64_t n) {
   if (n < 0) return fail(GG_ERR_ARG, "n must be non-negative");
   gg_status st = check_segments(L);
   if (st != GG_OK) return st;
-  if ((st = pressure_nodes(L)) != GG_OK) return st;
+  if ((st = pressure_nodes(L)) != GG_OK || (st = wall_nodes(L)) != GG_OK) return st;
   int64_t left = n;
   // graph chunk: even (a multiple of 4 with the two-step pass), so every
   // replay starts on an even step and leaves the state in the first plane set
@@ -777,7 +821,7 @@ gg_status gg_step(gg_lattice *L, int64_t n) {
       L->t += K;
     }
   }
-  const int64_t quads = L->fuse >= 2 && L->n_press == 0 ? left / 4 * 4 : 0;
+  const int64_t quads = L->fuse >= 2 && L->n_press == 0 && L->wall_scheme == 0 ? left / 4 * 4 : 0;
   if (quads > 0) {
     GG_HIP(launch_steps(L, L->t, quads, L->stream));
     L->t += quads;
@@ -1010,8 +1054,8 @@ struct AdjointBuffers {
 
 gg_status gg_adjoint(gg_lattice *L, int64_t n, int64_t s, const double *weight,
                      const double *target, const int32_t *r_box, double *d_R, gg_grads *out) {
-  if (L && has_pressure(L))
-    return fail(GG_ERR_STATE, "the adjoint does not cover pressure boundaries");
+  if (L && special_boundaries(L))
+    return fail(GG_ERR_STATE, "the adjoint does not cover pressure boundaries or the paper's walls");
   if (!L || !weight || !target || !out) return fail(GG_ERR_ARG, "NULL argument");
   if (n < 1) return fail(GG_ERR_ARG, "n_steps must be positive");
   if (s < 0) return fail(GG_ERR_ARG, "ckpt_every must be non-negative");
@@ -1235,8 +1279,8 @@ gg_status gg_batch_create(gg_lattice *const *lats, int32_t n, int32_t tile_x, in
       if (lats[j] == lats[k]) return fail(GG_ERR_ARG, "a lattice appears twice in the batch");
     gg_status st = check_segments(lats[k]);
     if (st != GG_OK) return st;
-    if (has_pressure(lats[k]))
-      return fail(GG_ERR_STATE, "batch members may not have pressure boundaries");
+    if (special_boundaries(lats[k]))
+      return fail(GG_ERR_STATE, "batch members may not have pressure boundaries or the paper's walls");
   }
   gg_batch *B = new gg_batch();
   B->lats.assign(lats, lats + n);
@@ -1283,6 +1327,9 @@ gg_status gg_batch_step(gg_batch *B, int64_t n) {
     if (L->t - B->t_created[k] != B->steps)
       return fail(GG_ERR_STATE, "batch member " + std::to_string(k) +
                                     " was stepped, loaded or re-initialised outside the batch");
+    if (special_boundaries(L))
+      return fail(GG_ERR_STATE, "batch member " + std::to_string(k) +
+                                    " has a pressure boundary or the paper's walls");
   }
   int64_t left = n;
   const int K = B->chunk;
@@ -1419,7 +1466,8 @@ void gg_batch_destroy(gg_batch *B) {
 }
 
 gg_status gg_step_timed(gg_lattice *L, int64_t n, double *ms_even, double *ms_odd) {
-  if (L && has_pressure(L)) return fail(GG_ERR_STATE, "timed steps do not cover pressure boundaries");
+  if (L && special_boundaries(L))
+    return fail(GG_ERR_STATE, "timed steps do not cover pressure boundaries or the paper's walls");
   if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
   if (n < 1) return fail(GG_ERR_ARG, "n must be positive");
   gg_status st = check_segments(L);
@@ -1458,7 +1506,8 @@ gg_status gg_step_timed(gg_lattice *L, int64_t n, double *ms_even, double *ms_od
 }
 
 gg_status gg_step2_timed(gg_lattice *L, int64_t n_pairs, double *ms_pass) {
-  if (L && has_pressure(L)) return fail(GG_ERR_STATE, "timed passes do not cover pressure boundaries");
+  if (L && special_boundaries(L))
+    return fail(GG_ERR_STATE, "timed passes do not cover pressure boundaries or the paper's walls");
   if (!L || !ms_pass) return fail(GG_ERR_ARG, "NULL argument");
   if (n_pairs < 1) return fail(GG_ERR_ARG, "n_pairs must be positive");
   if (L->fuse < 2) return fail(GG_ERR_STATE, "the two-step pass is off");
@@ -1640,7 +1689,8 @@ static hipError_t launch_cde_steps(gg_lattice *L, int64_t t0, int64_t n, hipStre
     return launch_cde(L->storage, ((t0 + k) & 1) != 0, L->d_desc, L->d_aux_tiles, L->n_aux_tiles,
                       6, (int)k, st);
   };
-  if (L->cde_rows > 0 && L->d_pop_b && L->cde_tiles_rows == L->cde_rows && L->n_press == 0) {
+  if (L->cde_rows > 0 && L->d_pop_b && L->cde_tiles_rows == L->cde_rows && L->n_press == 0 &&
+      L->wall_scheme == 0) {
     if ((t0 & 1) && n > 0) e = single(dt++);
     const int64_t passes = (n - dt) / 4 * 2;
     for (int64_t k = 0; k < passes && e == hipSuccess; ++k)
@@ -1649,7 +1699,13 @@ static hipError_t launch_cde_steps(gg_lattice *L, int64_t t0, int64_t n, hipStre
     dt += 2 * passes;
   }
   for (; dt < n && e == hipSuccess; ++dt) {
-    e = single(dt);
+    if (L->n_wall > 0)
+      e = launch_wall_save(L->storage, L->d_desc, L->d_wall, L->n_wall, (int)dt, L->d_wall_save,
+                           st);
+    if (e == hipSuccess) e = single(dt);
+    if (e == hipSuccess && L->n_wall > 0)
+      e = launch_wall_apply(L->storage, L->d_desc, L->d_wall, L->n_wall, (int)dt,
+                            L->d_wall_save, false, st);
     if (e == hipSuccess && L->n_press > 0)
       e = launch_rescale(L->storage, L->d_desc, L->d_press, L->n_press, (int)dt, false, st);
   }
@@ -1670,7 +1726,9 @@ gg_status gg_cde_step(gg_lattice *L, int64_t n) {
       return fail(GG_ERR_STATE, "velocity field slot " + std::to_string(s) + " of phase " +
                                     std::to_string(k) + " was never set");
   }
-  if ((st = cde_tiles(L)) != GG_OK || (st = pressure_nodes(L)) != GG_OK) return st;
+  if ((st = cde_tiles(L)) != GG_OK || (st = pressure_nodes(L)) != GG_OK ||
+      (st = wall_nodes(L)) != GG_OK)
+    return st;
   int64_t left = n;
   const int K = L->graph_chunk;  // even
   const int par = (int)(L->t & 1);
@@ -1698,6 +1756,16 @@ gg_status gg_cde_step(gg_lattice *L, int64_t n) {
     GG_HIP(launch_cde_steps(L, L->t, left, L->stream));
     L->t += left;
   }
+  return GG_OK;
+}
+
+gg_status gg_set_wall_scheme(gg_lattice *L, int32_t scheme) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (scheme != GG_WALL_BOUNCE_BACK && scheme != GG_WALL_PAPER)
+    return fail(GG_ERR_ARG, "unknown wall scheme");
+  GG_HIP(hipStreamSynchronize(L->stream));
+  L->wall_scheme = scheme;
+  L->wall_dirty = true;
   return GG_OK;
 }
 

@@ -275,8 +275,12 @@ def boundary_comparison(storage: str = "f64", steps: int = 30000,
     (u_max = 0.05) and by the paper's pressure boundaries holding the
     densities that drive the same flow; for each, the profile's deviation
     from the parabola of its own pressure gradient and the spread of the
-    mass flux along the channel. Then the rate of the 2048 x 1024 gradient
-    generator (FP32) with each kind on its four segments."""
+    mass flux along the channel, and where the fitted parabola vanishes
+    (the no-slip points, relative to the halfway wall at 0.5 from the wall
+    row); then the pressure-driven channel once more with the paper's walls
+    in place of bounce-back. Then the rate of the 2048 x 1024 gradient
+    generator (FP32) with each kind on its four segments, and with the
+    pressure boundaries and the paper's walls."""
     import torch
     out: Dict = {}
     nu = (0.8 - 0.5) / 3
@@ -289,30 +293,37 @@ def boundary_comparison(storage: str = "f64", steps: int = 30000,
                                           fix_c=True),
                                 W.Segment(3, "pressure", (1, 0), rho=1 - drho / 2)],
                       storage=storage)
-    for label, wl in (("velocity_inlet", base), ("pressure", pres)):
+    for label, wl in (("velocity_inlet", base), ("pressure", pres), ("pressure_paper_walls", pres)):
         lat = Lattice.from_workload(wl, storage=storage)
         try:
+            if label.endswith("paper_walls"):
+                lat.set_wall_scheme("equilibrium")
             lat.step(steps)
             rho, ux, _, C = lat.read()
         finally:
             lat.close()
         err, umax = _poiseuille_error(rho, ux, H, nu, base.nx // 2)
         flux = [(rho[1:-1, x] * ux[1:-1, x]).sum() for x in range(1, base.nx - 1)]
+        y = np.arange(1, H + 1, dtype=float)
+        roots = np.sort(np.roots(np.polyfit(y, ux[1:-1, base.nx // 2], 2)).real)
         out[label] = {"profile_error_vs_local_gradient": round(err, 6),
+                      "no_slip_points": [round(float(roots[0]), 4), round(float(roots[1]), 4)],
                       "u_max_local_gradient": round(umax, 6),
                       "u_centre": round(float(ux[1 + H // 2, base.nx // 2]), 6),
                       "mass_flux_spread": float(np.ptp(flux) / np.mean(flux)),
                       "C_outlet_column_mean": round(float(np.nanmean(C[1:-1, -2])), 4)}
     gg = W.gradient_generator(storage="f32")
     stream = torch.cuda.current_stream()
-    for label in ("velocity_inlet", "pressure"):
-        if label == "pressure":
+    for label in ("velocity_inlet", "pressure", "pressure_paper_walls"):
+        if label != "velocity_inlet":
             gg.segments = [W.Segment(2, "pressure", (0, -1), rho=1.002, c_in=1.0, fix_c=True),
                            W.Segment(3, "pressure", (0, 1), rho=0.998),
                            W.Segment(4, "pressure", (0, -1), rho=1.002, c_in=0.0, fix_c=True),
                            W.Segment(5, "pressure", (0, 1), rho=0.998)]
         lat = Lattice.from_workload(gg)
         try:
+            if label.endswith("paper_walls"):
+                lat.set_wall_scheme("equilibrium")
             lat.step(256)
             lat.sync()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

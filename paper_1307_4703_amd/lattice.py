@@ -166,6 +166,16 @@ class Lattice:
     def sync(self) -> None:
         A.call("gg_sync", self._h)
 
+    def set_wall_scheme(self, scheme: str) -> None:
+        """"bounce_back" (halfway bounce-back, the default) or "equilibrium"
+        (the paper's walls: ghost cells emitting the fluid equilibrium at the
+        extrapolated density and the momentum that vanishes at the halfway
+        wall, Guo's non-equilibrium extrapolation for the compound; the
+        Boundary Conditions section). Steps then run one at a time."""
+        if scheme not in A.WALL_SCHEMES:
+            raise ValueError(f"unknown wall scheme {scheme!r}")
+        A.call("gg_set_wall_scheme", self._h, A.WALL_SCHEMES[scheme])
+
     def permute_tiles(self, seed: int) -> None:
         """Shuffle the launch order of the tiles and strips (instrumentation)."""
         A.call("gg_permute_tiles", self._h, int(seed))

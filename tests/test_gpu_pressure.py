@@ -143,6 +143,7 @@ def test_boundary_comparison_runs():
     from paper_1307_4703_amd import experiments as E
     r = E.boundary_comparison(steps=4000, rate_steps=64)
     log(f"boundary comparison (short) {r}")
-    for label in ("velocity_inlet", "pressure"):
+    for label in ("velocity_inlet", "pressure", "pressure_paper_walls"):
         assert np.isfinite(r[label]["profile_error_vs_local_gradient"])
         assert r[label]["gg2048_f32_mlups"] > 0
+        assert 0 < r[label]["no_slip_points"][0] < 1.5

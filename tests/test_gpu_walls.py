@@ -1,0 +1,198 @@
+"""GPU parity of the paper's walls (Boundary Conditions section: ghost cells
+emitting the fluid equilibrium at the linearly extrapolated density and the
+momentum that vanishes at the halfway wall, and Guo's non-equilibrium
+extrapolation for the compound) against the oracle, through the C ABI: a
+pressure-driven channel, a periodic channel, the gradient generator with
+velocity inlets and with pressure boundaries while valves switch (closed
+valves take the wall rule), the compound-only step, a switch back to
+bounce-back with its two-step passes, and the calls that refuse such
+lattices."""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_1307_4703_amd import Batch, Lattice
+from paper_1307_4703_amd import workloads as W
+from paper_1307_4703_amd._abi import GGError, GG_ERR_ARG, GG_ERR_STATE
+from tests.parity_util import field_errors, log, seeded_init
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": {"rho": 1e-12, "u": 1e-12, "C": 1e-12},
+       "f32": {"rho": 1e-6, "u": 2e-5, "C": 2e-5},
+       "f16": {"rho": 3e-4, "u": 8e-3, "C": 1e-2}}
+
+
+def _pressure_channel(storage):
+    nx, ny = 130, 34
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[0, :] = 1
+    mask[-1, :] = 1
+    mask[1:-1, 0] = 2
+    mask[1:-1, -1] = 3
+    segs = [W.Segment(2, "pressure", (-1, 0), rho=1.003, c_in=1.0, fix_c=True),
+            W.Segment(3, "pressure", (1, 0), rho=0.997)]
+    return W.Workload("pressure_channel", mask, tau_f=0.8, D=0.02, segments=segs,
+                      storage=storage)
+
+
+def _periodic_channel(storage):
+    nx, ny = 96, 21
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[0, :] = 1
+    mask[-1, :] = 1
+    return W.Workload("periodic_channel", mask, tau_f=0.7, D=0.03, periodic=(True, False),
+                      storage=storage)
+
+
+def _pressure_gg(storage, half_period=7, drho=0.002):
+    wl = W.gradient_generator(nx=300, ny=150, half_period=half_period, storage=storage)
+    wl.segments = [W.Segment(2, "pressure", (0, -1), rho=1 + drho, c_in=1.0, fix_c=True),
+                   W.Segment(3, "pressure", (0, 1), rho=1 - drho),
+                   W.Segment(4, "pressure", (0, -1), rho=1 + drho, c_in=0.0, fix_c=True),
+                   W.Segment(5, "pressure", (0, 1), rho=1 - drho)]
+    return wl
+
+
+def _oracle(wl, scheme="equilibrium"):
+    return Oracle(wl.mask, tau_f=wl.tau_f, D=wl.D, w0=wl.w0, k_decay=wl.k_decay,
+                  periodic=wl.periodic, segments=wl.segments, schedule=wl.schedule,
+                  t_origin=wl.t_origin, wall_scheme=scheme)
+
+
+def _pair(wl, storage, seed, two_step=None, amp_u=0.02):
+    init = seeded_init(wl, seed, amp_u=amp_u)
+    lat = Lattice.from_workload(wl, storage=storage, init=False)
+    lat.set_launch(64, 4, 8)
+    if two_step is not None:
+        lat.set_two_step(*two_step)
+    lat.set_wall_scheme("equilibrium")
+    lat.init(**init)
+    o = _oracle(wl)
+    o.init(**init)
+    return lat, o
+
+
+def _check(lat, o, wl, storage, label):
+    err = field_errors(lat, o, wl.mask == 0)
+    log(f"{label}: {err}")
+    for k, tol in TOL[storage].items():
+        assert err[k] < tol, (k, err)
+    d = lat.diagnostics()
+    ftol = 1e-10 if storage == "f64" else 1e-3
+    for s in wl.segments:
+        assert d["seg_mass"][s.id - 2] == pytest.approx(o.flux_mass[s.id], rel=ftol, abs=1e-9)
+        assert d["seg_solute"][s.id - 2] == pytest.approx(o.flux_solute[s.id], rel=ftol, abs=1e-9)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_walls_pressure_channel(storage):
+    wl = _pressure_channel(storage)
+    log(f"walls, pressure channel {storage}")
+    lat, o = _pair(wl, storage, seed=1)
+    for n in (37, 200, 63):
+        lat.step(n)
+        o.step(n)
+    _check(lat, o, wl, storage, f"walls, pressure channel {storage}")
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_walls_periodic_channel(storage):
+    """Walls on both sides of a channel periodic along x: the extrapolation
+    partner z + e_i and the wall cells wrap across the seam."""
+    wl = _periodic_channel(storage)
+    log(f"walls, periodic channel {storage}")
+    lat, o = _pair(wl, storage, seed=2)
+    for n in (1, 40, 19):
+        lat.step(n)
+        o.step(n)
+    _check(lat, o, wl, storage, f"walls, periodic channel {storage}")
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_walls_gradient_generator_velocity_inlets(storage):
+    """The gradient generator with its velocity inlets and outlets, valves
+    switching every 7 steps (closed valves take the wall rule); the
+    two-step pass requested but not taken."""
+    wl = W.gradient_generator(nx=300, ny=150, half_period=7, storage=storage)
+    log(f"walls, gradient generator {storage}")
+    lat, o = _pair(wl, storage, seed=4, two_step=(3, 6), amp_u=0.005)
+    for n in (8, 3, 29, 60):
+        lat.step(n)
+        o.step(n)
+    _check(lat, o, wl, storage, f"walls, gradient generator {storage}")
+
+
+def test_walls_pressure_gradient_generator():
+    """Pressure-driven channels and valves switching. The drop is raised to
+    0.04 so that the flow, not FP64 rounding, sets the velocity scale of the
+    relative error; the initial noise stays small (0.005): at 0.02 the
+    oracle alone is ill-conditioned here (ghost populations with the Guo
+    rule's negative relaxation factor cancel the compound of inlet nodes to
+    near zero before the rescaling to C_in, and a 1e-15 change of the
+    initial state moves C by 4e-7)."""
+    wl = _pressure_gg("f64", drho=0.02)
+    log("walls, pressure gradient generator f64")
+    lat, o = _pair(wl, "f64", seed=5, amp_u=0.005)
+    for n in (13, 50):
+        lat.step(n)
+        o.step(n)
+    _check(lat, o, wl, "f64", "walls, pressure gradient generator f64")
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_walls_compound_only(storage):
+    wl = W.gradient_generator(nx=300, ny=150, half_period=9, storage=storage)
+    log(f"walls, compound only {storage}")
+    lat, o = _pair(wl, storage, seed=6, amp_u=0.005)
+    lat.step(11)
+    o.step(11)
+    lat.set_velocity_field(0)
+    _, ux, uy, _ = o.fields()
+    lat.cde_step(40)
+    o.cde_step(40, [(np.nan_to_num(ux), np.nan_to_num(uy))])
+    fl = wl.mask == 0
+    C = lat.read()[3]
+    Co = o.fields()[3]
+    err = float(np.abs(C[fl] - Co[fl]).max() / max(1.0, np.abs(Co[fl]).max()))
+    log(f"walls, compound only {storage}: {err:.3e}")
+    assert err < TOL[storage]["C"]
+    d = lat.diagnostics()
+    for s in wl.segments:
+        assert d["seg_solute"][s.id - 2] == pytest.approx(
+            o.flux_solute[s.id], rel=1e-10 if storage == "f64" else 1e-3, abs=1e-9)
+
+
+def test_walls_switched_back_to_bounce_back():
+    """The paper's walls for 21 steps, then bounce-back again: the steps
+    after the switch take the two-step passes (and their graph) and match
+    the oracle switched at the same step."""
+    wl = W.gradient_generator(nx=300, ny=150, half_period=7, storage="f64")
+    lat, o = _pair(wl, "f64", seed=7, two_step=(3, 6), amp_u=0.005)
+    lat.step(21)
+    o.step(21)
+    lat.set_wall_scheme("bounce_back")
+    o.set_wall_scheme("bounce_back")
+    for n in (1, 16, 16, 5):
+        lat.step(n)
+        o.step(n)
+    _check(lat, o, wl, "f64", "walls then bounce-back")
+
+
+def test_calls_that_refuse_the_paper_walls():
+    wl = _periodic_channel("f32")
+    lat = Lattice.from_workload(wl)
+    batch = Batch([lat])
+    lat.set_wall_scheme("equilibrium")
+    w = np.ones((wl.ny, wl.nx))
+    for call in (lambda: lat.adjoint(4, w, w), lambda: lat.step_timed(2),
+                 lambda: lat.step2_timed(1), lambda: Batch([lat]), lambda: batch.step(4)):
+        with pytest.raises(GGError) as e:
+            call()
+        assert e.value.status == GG_ERR_STATE
+    with pytest.raises(GGError) as e:
+        from paper_1307_4703_amd import _abi as A
+        A.call("gg_set_wall_scheme", lat.handle, 7)
+    assert e.value.status == GG_ERR_ARG
+    lat.step(4)
+    assert lat.info()["t"] == 4
