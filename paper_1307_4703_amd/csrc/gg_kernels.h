@@ -46,14 +46,18 @@ hipError_t launch_put_field(gg_storage s, const LatDesc *d, const Tile *tiles, i
                             int tx_shift, int slot, const double *ux, const double *uy,
                             double scale, hipStream_t st);
 
-// The paper's walls for the n nodes listed as (x, y) pairs: before step
-// (device counter + dt), save what the rule needs of that step (16 values
-// of the compute type per node) into `save`; after it, write the wall
-// links' values; fluid = false: the compound-only step (frozen field).
-hipError_t launch_wall_save(gg_storage s, const LatDesc *d, const int32_t *xy, int n, int dt,
-                            void *save, hipStream_t st);
-hipError_t launch_wall_apply(gg_storage s, const LatDesc *d, const int32_t *xy, int n, int dt,
-                             const void *save, bool fluid, hipStream_t st);
+// The paper's walls for the n nodes listed as (x, y) pairs and their
+// n_links links from non-fluid cells, entries k * 8 + (i - 1) (node k of
+// the list, direction i): before step (device counter + dt), save what the
+// rule needs of that step (16 values of the compute type per node) into
+// `save`; after it, write the links' values where the source is a wall at
+// the step's phase; fluid = false: the compound-only step (frozen field).
+hipError_t launch_wall_save(gg_storage s, const LatDesc *d, const int32_t *xy, int n,
+                            const int32_t *links, int n_links, int dt, bool fluid, void *save,
+                            hipStream_t st);
+hipError_t launch_wall_apply(gg_storage s, const LatDesc *d, const int32_t *xy,
+                             const int32_t *links, int n_links, int dt, const void *save,
+                             bool fluid, hipStream_t st);
 
 // Auxiliary kernels: 256-thread work-groups over one lattice's tiles.
 hipError_t launch_init(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,

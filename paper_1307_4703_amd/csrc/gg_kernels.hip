@@ -585,85 +585,119 @@ __device__ __forceinline__ bool wall_link(CDesc &L, int code, const PhaseNow &ph
   return L.seg_kind[q] == 0 || !((ph.open >> q) & 1u);
 }
 
+// Deviation of the density of the fluid node at element offset `node`
+// (link code lc) at a step of parity `odd`, summed in direction order.
 template <class S>
-__global__ void __launch_bounds__(256)
-    k_wall_save(const LatDesc *__restrict__ desc, const int32_t *__restrict__ xy, int n, int dt,
+__device__ __forceinline__ typename Pop<S>::T node_drho(CDesc &L,
+                                                        const Planes<typename Pop<S>::W> &pl,
+                                                        int x, int y, uint32_t node, uint8_t lc,
+                                                        bool odd) {
+#pragma clang fp contract(off)
+  typename Pop<S>::T f[9], g[5];
+  const Neigh nb(L, x, y);
+  if (odd) load_state<S, true>(pl, node, lc, nb, f, g);
+  else load_state<S, false>(pl, node, lc, nb, f, g);
+  return f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+}
+
+// Before step t (device counter + dt). Threads 0 .. n - 1: the moments of
+// listed node k (d rho, j, dC) and its dg_1..4 into save[k]; threads n ..
+// n + n_links - 1 (fluid steps only): for the link entry k * 8 + (i - 1),
+// the density deviation of z + e_i into save[k][3 + i], or that of z
+// itself where z + e_i is not fluid (then 2 d rho - d rho = d rho exactly:
+// rho_s = rho(z)). One thread per link keeps the loads of a node's
+// extrapolation partners in parallel.
+template <class S>
+__global__ void __launch_bounds__(64)
+    k_wall_save(const LatDesc *__restrict__ desc, const int32_t *__restrict__ xy, int n,
+                const int32_t *__restrict__ links, int n_links, int dt, int fluid,
                 typename Pop<S>::T *__restrict__ save) {
 #pragma clang fp contract(off)
   using P = Pop<S>;
   using T = typename P::T;
-  const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (k >= n) return;
+  const int tid = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (tid >= n + (fluid ? n_links : 0)) return;
   CDesc &L = *(CDesc *)desc;
-  const int x = xy[2 * k], y = xy[2 * k + 1];
-  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
-  const uint8_t lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
   const int64_t t = *(const GG_CONST int64_t *)L.t + dt;
   const bool odd = (t & 1) != 0;
   const Planes<typename P::W> pl(L);
-  T f[9], g[5];
-  {
+  if (tid < n) {
+    const int x = xy[2 * tid], y = xy[2 * tid + 1];
+    const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+    const uint8_t lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
+    T f[9], g[5];
     const Neigh nb(L, x, y);
     if (odd) load_state<S, true>(pl, node, lc, nb, f, g);
     else load_state<S, false>(pl, node, lc, nb, f, g);
-  }
-  T *o = save + (size_t)k * WALL_SAVE;
-  {
+    T *o = save + (size_t)tid * WALL_SAVE;
     o[0] = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
     o[1] = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     o[2] = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
     o[3] = g[0] + g[1] + g[2] + g[3] + g[4];
-  }
 #pragma unroll
-  for (int i = 1; i < 5; ++i) o[11 + i] = g[i];
-  for (int i = 1; i < 9; ++i) {
-    o[3 + i] = o[0];  // (no fluid at z + e_i: rho(z))
-    if (!((lc >> (OPP[i] - 1)) & 1)) continue;  // the source of link i is fluid
-    int ax = x + EX[i], ay = y + EY[i];
-    bool inside = true;
-    if (ax < 0 || ax >= L.nx) {
-      if (L.periodic_x) ax = (ax + L.nx) % L.nx; else inside = false;
-    }
-    if (ay < 0 || ay >= L.ny) {
-      if (L.periodic_y) ay = (ay + L.ny) % L.ny; else inside = false;
-    }
-    if (!inside) continue;
-    const uint32_t an = (uint32_t)(L.node0 + ay * L.pitch + ax);
-    const uint8_t alc = ((const GG_GLOBAL uint8_t *)L.link)[an];
-    if (alc == NOT_FLUID) continue;
-    T fa[9], ga[5];
-    const Neigh nba(L, ax, ay);
-    if (odd) load_state<S, true>(pl, an, alc, nba, fa, ga);
-    else load_state<S, false>(pl, an, alc, nba, fa, ga);
-    const T ra = fa[0] + fa[1] + fa[2] + fa[3] + fa[4] + fa[5] + fa[6] + fa[7] + fa[8];
-    o[3 + i] = T(2) * o[0] - ra;
+    for (int i = 1; i < 5; ++i) o[11 + i] = g[i];
+    return;
   }
+  const int e = links[tid - n];
+  const int k = e >> 3, i = (e & 7) + 1;
+  int x = xy[2 * k], y = xy[2 * k + 1];
+  int ax = x + EX[i], ay = y + EY[i];
+  bool inside = true;
+  if (ax < 0 || ax >= L.nx) {
+    if (L.periodic_x) ax = (ax + L.nx) % L.nx; else inside = false;
+  }
+  if (ay < 0 || ay >= L.ny) {
+    if (L.periodic_y) ay = (ay + L.ny) % L.ny; else inside = false;
+  }
+  uint8_t alc = NOT_FLUID;
+  if (inside) alc = ((const GG_GLOBAL uint8_t *)L.link)[L.node0 + ay * L.pitch + ax];
+  if (alc != NOT_FLUID) {
+    x = ax;
+    y = ay;
+  } else {
+    alc = ((const GG_GLOBAL uint8_t *)L.link)[L.node0 + y * L.pitch + x];
+  }
+  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+  save[(size_t)k * WALL_SAVE + 3 + i] = node_drho<S>(L, pl, x, y, node, alc, odd);
 }
 
+// After step t, before a pressure rescaling: one thread per link entry
+// k * 8 + (i - 1) whose source is, at step t's phase, a wall, a closed
+// valve or an unconfigured segment cell; writes the ghost's populations
+// into node k's own slots i (f, fluid steps only) and 9 + i (g, i <= 4).
 template <class S>
-__global__ void __launch_bounds__(256)
-    k_wall_apply(const LatDesc *__restrict__ desc, const int32_t *__restrict__ xy, int n, int dt,
+__global__ void __launch_bounds__(64)
+    k_wall_apply(const LatDesc *__restrict__ desc, const int32_t *__restrict__ xy,
+                 const int32_t *__restrict__ links, int n_links, int dt,
                  const typename Pop<S>::T *__restrict__ save, int fluid) {
 #pragma clang fp contract(off)
   using P = Pop<S>;
   using T = typename P::T;
-  const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (k >= n) return;
+  const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (j >= n_links) return;
   CDesc &L = *(CDesc *)desc;
+  const int e = links[j];
+  const int k = e >> 3, i = (e & 7) + 1;
+  if (!fluid && i > 4) return;
   const int x = xy[2 * k], y = xy[2 * k + 1];
-  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
-  const uint8_t lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
   const int64_t t = *(const GG_CONST int64_t *)L.t + dt;
   const PhaseNow ph = phase_at(L, t);
+  if (!wall_link(L, source_code(L, x, y, i), ph)) return;
+  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
   const Planes<typename P::W> pl(L);
   const T *o = save + (size_t)k * WALL_SAVE;
-  const T rho0 = (T)L.rho0, cs = (T)L.c_shift, ics = (T)L.inv_cs2g;
-  const T wga = (T)L.wg_axis;
-  const T wg[5] = {T(1) - T(4) * wga, wga, wga, wga, wga};
-  const T dC = o[3];
-  const T C = cs + dC;
-  T ux, uy;
+  const T rho0 = (T)L.rho0;
+  T usx, usy, ux = T(0), uy = T(0);
   if (fluid) {
+    const T drs = T(2) * o[0] - o[3 + i];
+    const T rs = rho0 + drs;
+    usx = -o[1] / rs;
+    usy = -o[2] / rs;
+    const T eu = (T)EX[i] * usx + (T)EY[i] * usy;
+    const T usq = usx * usx + usy * usy;
+    const T poly = T(3) * eu + T(4.5) * eu * eu - T(1.5) * usq;
+    P::st(pl.at(i, node), (T)WF[i] * (drs + rs * poly));
+    if (i > 4) return;
     const T rho = rho0 + o[0];
     ux = o[1] / rho;
     uy = o[2] / rho;
@@ -671,56 +705,55 @@ __global__ void __launch_bounds__(256)
     const int slot = L.phase_field[ph.index];
     ux = ((const GG_GLOBAL T *)L.ufield)[(int64_t)(2 * slot) * L.plane + node];
     uy = ((const GG_GLOBAL T *)L.ufield)[(int64_t)(2 * slot + 1) * L.plane + node];
+    usx = -ux;
+    usy = -uy;
   }
-  const T omg = T(1) - (T)L.omega_g;
-  for (int i = 1; i < 9; ++i) {
-    if (!((lc >> (OPP[i] - 1)) & 1)) continue;  // the source of link i is fluid
-    if (!fluid && i > 4) break;
-    if (!wall_link(L, source_code(L, x, y, i), ph)) continue;
-    T usx, usy;
-    if (fluid) {
-      const T drs = o[3 + i];
-      const T rs = rho0 + drs;
-      usx = -o[1] / rs;
-      usy = -o[2] / rs;
-      const T eu = (T)EX[i] * usx + (T)EY[i] * usy;
-      const T usq = usx * usx + usy * usy;
-      const T poly = T(3) * eu + T(4.5) * eu * eu - T(1.5) * usq;
-      P::st(pl.at(i, node), (T)WF[i] * (drs + rs * poly));
-    } else {
-      usx = -ux;
-      usy = -uy;
-    }
-    if (i < 5) {
-      const T eus = (T)EX[i] * usx + (T)EY[i] * usy;
-      const T euz = (T)EX[i] * ux + (T)EY[i] * uy;
-      const T eq_s = wg[i] * (dC + C * eus * ics);  // g^eq(C, u_s) - w C_s
-      const T eq_z = wg[i] * (dC + C * euz * ics);  // g^eq(C, u(z)) - w C_s
-      P::st(pl.at(9 + i, node), eq_s + omg * (o[11 + i] - eq_z));
-    }
-  }
+  const T cs = (T)L.c_shift, ics = (T)L.inv_cs2g;
+  const T dC = o[3];
+  const T C = cs + dC;
+  const T w = (T)L.wg_axis;  // i = 1..4
+  const T eus = (T)EX[i] * usx + (T)EY[i] * usy;
+  const T euz = (T)EX[i] * ux + (T)EY[i] * uy;
+  const T eq_s = w * (dC + C * eus * ics);  // g^eq(C, u_s) - w C_s
+  const T eq_z = w * (dC + C * euz * ics);  // g^eq(C, u(z)) - w C_s
+  P::st(pl.at(9 + i, node), eq_s + (T(1) - (T)L.omega_g) * (o[11 + i] - eq_z));
 }
 
-hipError_t launch_wall_save(gg_storage s, const LatDesc *d, const int32_t *xy, int n, int dt,
-                            void *save, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  const int grid = (n + 255) / 256;
+hipError_t launch_wall_save(gg_storage s, const LatDesc *d, const int32_t *xy, int n,
+                            const int32_t *links, int n_links, int dt, bool fluid, void *save,
+                            hipStream_t st) {
+  const int m = n + (fluid ? n_links : 0);
+  if (m <= 0) return hipSuccess;
+  const int grid = (m + 63) / 64;
   switch (s) {
-    case GG_F64: k_wall_save<double><<<grid, 256, 0, st>>>(d, xy, n, dt, (double *)save); break;
-    case GG_F32: k_wall_save<float><<<grid, 256, 0, st>>>(d, xy, n, dt, (float *)save); break;
-    case GG_F16_SHIFTED: k_wall_save<__half><<<grid, 256, 0, st>>>(d, xy, n, dt, (float *)save); break;
+    case GG_F64:
+      k_wall_save<double><<<grid, 64, 0, st>>>(d, xy, n, links, n_links, dt, fluid, (double *)save);
+      break;
+    case GG_F32:
+      k_wall_save<float><<<grid, 64, 0, st>>>(d, xy, n, links, n_links, dt, fluid, (float *)save);
+      break;
+    case GG_F16_SHIFTED:
+      k_wall_save<__half><<<grid, 64, 0, st>>>(d, xy, n, links, n_links, dt, fluid, (float *)save);
+      break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_wall_apply(gg_storage s, const LatDesc *d, const int32_t *xy, int n, int dt,
-                             const void *save, bool fluid, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  const int grid = (n + 255) / 256;
+hipError_t launch_wall_apply(gg_storage s, const LatDesc *d, const int32_t *xy,
+                             const int32_t *links, int n_links, int dt, const void *save,
+                             bool fluid, hipStream_t st) {
+  if (n_links <= 0) return hipSuccess;
+  const int grid = (n_links + 63) / 64;
   switch (s) {
-    case GG_F64: k_wall_apply<double><<<grid, 256, 0, st>>>(d, xy, n, dt, (const double *)save, fluid); break;
-    case GG_F32: k_wall_apply<float><<<grid, 256, 0, st>>>(d, xy, n, dt, (const float *)save, fluid); break;
-    case GG_F16_SHIFTED: k_wall_apply<__half><<<grid, 256, 0, st>>>(d, xy, n, dt, (const float *)save, fluid); break;
+    case GG_F64:
+      k_wall_apply<double><<<grid, 64, 0, st>>>(d, xy, links, n_links, dt, (const double *)save, fluid);
+      break;
+    case GG_F32:
+      k_wall_apply<float><<<grid, 64, 0, st>>>(d, xy, links, n_links, dt, (const float *)save, fluid);
+      break;
+    case GG_F16_SHIFTED:
+      k_wall_apply<__half><<<grid, 64, 0, st>>>(d, xy, links, n_links, dt, (const float *)save, fluid);
+      break;
   }
   return hipGetLastError();
 }

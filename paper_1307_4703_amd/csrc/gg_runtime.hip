@@ -70,7 +70,7 @@ void gg_free_device(gg_lattice *L) {
   void *ptrs[] = {L->d_pop, L->d_pop_b, L->d_link, L->d_mask, L->d_region, L->d_R, L->d_t,
                   L->d_flux, L->d_acc, L->d_desc, L->d_tiles, L->d_aux_tiles, L->d_strips,
                   L->d_seg_strips, L->d_partial, L->d_ufield, L->d_cde_tiles, L->d_press,
-                  L->d_wall, L->d_wall_save};
+                  L->d_wall, L->d_wall_links, L->d_wall_save};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (L->cap_stream) (void)hipStreamDestroy(L->cap_stream);
@@ -704,23 +704,32 @@ static bool special_boundaries(const gg_lattice *L) { return has_pressure(L) || 
 // (a valve that may close), for the paper's walls.
 static gg_status wall_nodes(gg_lattice *L) {
   if (!L->wall_dirty) return GG_OK;
-  std::vector<int32_t> xy;
+  std::vector<int32_t> xy, links;
   if (L->wall_scheme != 0)
     for (int y = 0; y < L->ny; ++y)
       for (int x = 0; x < L->nx; ++x) {
         const uint8_t lc = L->link[L->nid(x, y)];
         if (lc == NOT_FLUID || lc == 0) continue;
+        const int k = (int)(xy.size() / 2);
         xy.push_back(x);
         xy.push_back(y);
+        for (int i = 1; i < 9; ++i)  // bit opp(i) - 1: x - e_i is not fluid
+          if ((lc >> (OPP[i] - 1)) & 1) links.push_back(k * 8 + (i - 1));
       }
   if (L->d_wall) GG_HIP(hipFree(L->d_wall));
+  if (L->d_wall_links) GG_HIP(hipFree(L->d_wall_links));
   if (L->d_wall_save) GG_HIP(hipFree(L->d_wall_save));
   L->d_wall = nullptr;
+  L->d_wall_links = nullptr;
   L->d_wall_save = nullptr;
   L->n_wall = (int)(xy.size() / 2);
+  L->n_wall_links = (int)links.size();
   if (!xy.empty()) {
     GG_HIP(hipMalloc(&L->d_wall, xy.size() * sizeof(int32_t)));
     GG_HIP(hipMemcpy(L->d_wall, xy.data(), xy.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    GG_HIP(hipMalloc(&L->d_wall_links, links.size() * sizeof(int32_t)));
+    GG_HIP(hipMemcpy(L->d_wall_links, links.data(), links.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice));
     const size_t tb = L->storage == GG_F64 ? 8 : 4;
     GG_HIP(hipMalloc(&L->d_wall_save, (size_t)L->n_wall * 16 * tb));
   }
@@ -770,14 +779,14 @@ static hipError_t launch_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t
     const int txs = ilog2(L->tile_x);
     for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt) {
       if (L->n_wall > 0)
-        e = launch_wall_save(L->storage, L->d_desc, L->d_wall, L->n_wall, (int)dt,
-                             L->d_wall_save, st);
+        e = launch_wall_save(L->storage, L->d_desc, L->d_wall, L->n_wall, L->d_wall_links,
+                             L->n_wall_links, (int)dt, true, L->d_wall_save, st);
       if (e == hipSuccess)
         e = launch_step(L->storage, block, ((t0 + dt) & 1) != 0, L->d_desc, L->d_tiles,
                         L->n_tiles, txs, (int)dt, st);
       if (e == hipSuccess && L->n_wall > 0)
-        e = launch_wall_apply(L->storage, L->d_desc, L->d_wall, L->n_wall, (int)dt,
-                              L->d_wall_save, true, st);
+        e = launch_wall_apply(L->storage, L->d_desc, L->d_wall, L->d_wall_links,
+                              L->n_wall_links, (int)dt, L->d_wall_save, true, st);
       if (e == hipSuccess && L->n_press > 0)
         e = launch_rescale(L->storage, L->d_desc, L->d_press, L->n_press, (int)dt, true, st);
     }
@@ -1700,12 +1709,12 @@ static hipError_t launch_cde_steps(gg_lattice *L, int64_t t0, int64_t n, hipStre
   }
   for (; dt < n && e == hipSuccess; ++dt) {
     if (L->n_wall > 0)
-      e = launch_wall_save(L->storage, L->d_desc, L->d_wall, L->n_wall, (int)dt, L->d_wall_save,
-                           st);
+      e = launch_wall_save(L->storage, L->d_desc, L->d_wall, L->n_wall, L->d_wall_links,
+                           L->n_wall_links, (int)dt, false, L->d_wall_save, st);
     if (e == hipSuccess) e = single(dt);
     if (e == hipSuccess && L->n_wall > 0)
-      e = launch_wall_apply(L->storage, L->d_desc, L->d_wall, L->n_wall, (int)dt,
-                            L->d_wall_save, false, st);
+      e = launch_wall_apply(L->storage, L->d_desc, L->d_wall, L->d_wall_links,
+                            L->n_wall_links, (int)dt, L->d_wall_save, false, st);
     if (e == hipSuccess && L->n_press > 0)
       e = launch_rescale(L->storage, L->d_desc, L->d_press, L->n_press, (int)dt, false, st);
   }

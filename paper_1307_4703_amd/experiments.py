@@ -281,7 +281,6 @@ def boundary_comparison(storage: str = "f64", steps: int = 30000,
     in place of bounce-back. Then the rate of the 2048 x 1024 gradient
     generator (FP32) with each kind on its four segments, and with the
     pressure boundaries and the paper's walls."""
-    import torch
     out: Dict = {}
     nu = (0.8 - 0.5) / 3
     base = W.straight_channel(storage=storage, steps=steps)
@@ -312,6 +311,17 @@ def boundary_comparison(storage: str = "f64", steps: int = 30000,
                       "u_centre": round(float(ux[1 + H // 2, base.nx // 2]), 6),
                       "mass_flux_spread": float(np.ptp(flux) / np.mean(flux)),
                       "C_outlet_column_mean": round(float(np.nanmean(C[1:-1, -2])), 4)}
+    for label, r in boundary_rates(rate_steps).items():
+        out[label].update(r)
+    return out
+
+
+def boundary_rates(rate_steps: int = 2000) -> Dict:
+    """Rate of the 2048 x 1024 gradient generator (FP32) with velocity
+    inlets and outlets, with pressure boundaries on its four segments, and
+    with the pressure boundaries and the paper's walls."""
+    import torch
+    out: Dict = {}
     gg = W.gradient_generator(storage="f32")
     stream = torch.cuda.current_stream()
     for label in ("velocity_inlet", "pressure", "pressure_paper_walls"):
@@ -335,8 +345,8 @@ def boundary_comparison(storage: str = "f64", steps: int = 30000,
             nf = lat.info()["n_fluid"]
         finally:
             lat.close()
-        out[label]["gg2048_f32_mlups"] = round(nf / (ms * 1e-3) / 1e6, 1)
-        out[label]["gg2048_f32_us_per_step"] = round(ms * 1e3, 3)
+        out[label] = {"gg2048_f32_mlups": round(nf / (ms * 1e-3) / 1e6, 1),
+                      "gg2048_f32_us_per_step": round(ms * 1e3, 3)}
     return out
 
 
@@ -407,7 +417,7 @@ if __name__ == "__main__":
     import json
     ap = argparse.ArgumentParser(description="run the paper's experiments on the GPU")
     ap.add_argument("experiment", choices=["step-profile", "gradient-formation", "boundaries",
-                                           "precision"])
+                                           "boundary-rates", "precision"])
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--hours", type=float, default=4.0)
     ap.add_argument("--storage", default="f32")
@@ -418,6 +428,9 @@ if __name__ == "__main__":
         summ = res
     elif args.experiment == "boundaries":
         res = boundary_comparison()
+        summ = res
+    elif args.experiment == "boundary-rates":
+        res = boundary_rates(args.steps)
         summ = res
     elif args.experiment == "precision":
         res = {f"pe{int(pe)}": precision_report(W.gradient_generator(scale=4.0, storage="f16",
