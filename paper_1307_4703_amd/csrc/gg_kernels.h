@@ -47,17 +47,16 @@ hipError_t launch_put_field(gg_storage s, const LatDesc *d, const Tile *tiles, i
                             double scale, hipStream_t st);
 
 // The paper's walls for the n nodes listed as (x, y) pairs and their
-// n_links links from non-fluid cells, entries k * 8 + (i - 1) (node k of
-// the list, direction i): before step (device counter + dt), save what the
+// n_links links from non-fluid cells, entries (x, y, k * 8 + (i - 1)) (node
+// k of the list at (x, y), direction i): before step (device counter + dt), save what the
 // rule needs of that step (16 values of the compute type per node) into
 // `save`; after it, write the links' values where the source is a wall at
 // the step's phase; fluid = false: the compound-only step (frozen field).
 hipError_t launch_wall_save(gg_storage s, const LatDesc *d, const int32_t *xy, int n,
                             const int32_t *links, int n_links, int dt, bool fluid, void *save,
                             hipStream_t st);
-hipError_t launch_wall_apply(gg_storage s, const LatDesc *d, const int32_t *xy,
-                             const int32_t *links, int n_links, int dt, const void *save,
-                             bool fluid, hipStream_t st);
+hipError_t launch_wall_apply(gg_storage s, const LatDesc *d, const int32_t *links, int n_links,
+                             int dt, const void *save, bool fluid, hipStream_t st);
 
 // Auxiliary kernels: 256-thread work-groups over one lattice's tiles.
 hipError_t launch_init(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
@@ -72,8 +71,11 @@ hipError_t launch_reduce(gg_storage s, const LatDesc *d, const Tile *tiles, int 
                          int tx_shift, double *partial, double *acc, hipStream_t st);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
 // Pressure boundary: after step (device counter + dt), rescale the state at
-// t + 1 of the n nodes listed as (x, y) pairs that take a boundary value
-// from an open pressure segment; fluid = false rescales the compound only.
+// t + 1 of the n nodes listed as (x, y, candidates) triples that take a
+// boundary value from an open pressure segment (candidates: the pressure
+// segments among the node's source cells, one byte each, index + 1, in
+// order of first appearance in direction order); fluid = false rescales the
+// compound only.
 hipError_t launch_rescale(gg_storage s, const LatDesc *d, const int32_t *xy, int n, int dt,
                           bool fluid, hipStream_t st);
 hipError_t launch_advance(const LatDesc *descs, int n, int64_t k, hipStream_t st);

@@ -454,92 +454,89 @@ __device__ __forceinline__ void store_state(const Planes<typename Pop<S>::W> &pl
 // boundary flux. fluid = 0 leaves f alone (compound-only steps). In the
 // deviation form: gamma (w rho0 + df) - w rho0 = gamma df + (gamma - 1) w rho0.
 template <class S>
-__global__ void __launch_bounds__(256)
-    k_rescale(const LatDesc *__restrict__ desc, const int32_t *__restrict__ xy, int n, int dt,
+__global__ void __launch_bounds__(64)
+    k_rescale(const LatDesc *__restrict__ desc, const int32_t *__restrict__ list, int n, int dt,
               int fluid) {
   using P = Pop<S>;
   using T = typename P::T;
   const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (k >= n) return;
   CDesc &L = *(CDesc *)desc;
-  const int x = xy[2 * k], y = xy[2 * k + 1];
-  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
-  const uint8_t lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
   const int64_t t = *(const GG_CONST int64_t *)L.t + dt;
   const PhaseNow ph = phase_at(L, t);
-  int s = -1;
-  for (int j = 1; j < 9 && s < 0; ++j) {
-    if (!((lc >> (OPP[j] - 1)) & 1)) continue;  // x - e_j is fluid
-    int sx = x - EX[j], sy = y - EY[j];
-    bool inside = true;
-    if (sx < 0 || sx >= L.nx) {
-      if (L.periodic_x) sx = (sx + L.nx) % L.nx; else inside = false;
+  Flux flux;
+  // entry: x, y, and the pressure segments among the node's source cells,
+  // one byte each (index + 1), in order of first appearance in direction
+  // order 1..8: the node follows the first of them open at this step
+  int s = -1, x = 0, y = 0;
+  if (k < n) {
+    x = list[3 * k];
+    y = list[3 * k + 1];
+    const uint32_t cand = (uint32_t)list[3 * k + 2];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int q = (int)((cand >> (8 * b)) & 0xFFu) - 1;
+      if (s < 0 && q >= 0 && ((ph.open >> q) & 1u)) s = q;
     }
-    if (sy < 0 || sy >= L.ny) {
-      if (L.periodic_y) sy = (sy + L.ny) % L.ny; else inside = false;
-    }
-    if (!inside) continue;
-    const int code = ((const GG_GLOBAL uint8_t *)L.mask)[L.node0 + sy * L.pitch + sx];
-    if (code < GG_FIRST_SEGMENT) continue;
-    const int q = code - GG_FIRST_SEGMENT;
-    if (L.seg_kind[q] == GG_SEG_PRESSURE && ((ph.open >> q) & 1u)) s = q;
   }
-  if (s < 0) return;
-  const Planes<typename P::W> pl(L);
-  const Neigh nb(L, x, y);
-  T f[9], g[5];
-  const bool odd = ((t + 1) & 1) != 0;  // parity of the state at t + 1
-  if (odd)
-    load_state<S, true>(pl, node, lc, nb, f, g);
-  else
-    load_state<S, false>(pl, node, lc, nb, f, g);
-  double dm = 0.0, dc = 0.0;
-  {
+  if (s >= 0) {
+    const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+    const uint8_t lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
+    const Planes<typename P::W> pl(L);
+    const Neigh nb(L, x, y);
+    T f[9], g[5];
+    const bool odd = ((t + 1) & 1) != 0;  // parity of the state at t + 1
+    if (odd)
+      load_state<S, true>(pl, node, lc, nb, f, g);
+    else
+      load_state<S, false>(pl, node, lc, nb, f, g);
+    double dm = 0.0, dc = 0.0;
+    {
 #pragma clang fp contract(off)
-    if (fluid) {
-      T drho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-      const T rho = (T)L.rho0 + drho;
-      const T rs = SegT<T>::rho(L, s);
-      const T gam = rs / rho;
-      const T rest = (gam - T(1)) * (T)L.rho0;
+      if (fluid) {
+        T drho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+        const T rho = (T)L.rho0 + drho;
+        const T rs = SegT<T>::rho(L, s);
+        const T gam = rs / rho;
+        const T rest = (gam - T(1)) * (T)L.rho0;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) f[i] = fmad(gam, f[i], rest * (T)WF[i]);
-      dm = (double)rs - (double)rho;
-    }
-    if (L.seg_holdc[s]) {
-      const T cs = (T)L.c_shift;
-      const T wga = (T)L.wg_axis;
-      const T wg[5] = {T(1) - T(4) * wga, wga, wga, wga, wga};
-      const T C = cs + (g[0] + g[1] + g[2] + g[3] + g[4]);
-      const T cin = SegT<T>::cin(ph, s);
-      if (C > T(0)) {
-        const T gam = cin / C;
-        const T rest = (gam - T(1)) * cs;
-#pragma unroll
-        for (int i = 0; i < 5; ++i) g[i] = fmad(gam, g[i], rest * wg[i]);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 5; ++i) g[i] = wg[i] * (cin - cs);
+        for (int i = 0; i < 9; ++i) f[i] = fmad(gam, f[i], rest * (T)WF[i]);
+        dm = (double)rs - (double)rho;
       }
-      dc = (double)cin - (double)C;
+      if (L.seg_holdc[s]) {
+        const T cs = (T)L.c_shift;
+        const T wga = (T)L.wg_axis;
+        const T wg[5] = {T(1) - T(4) * wga, wga, wga, wga, wga};
+        const T C = cs + (g[0] + g[1] + g[2] + g[3] + g[4]);
+        const T cin = SegT<T>::cin(ph, s);
+        if (C > T(0)) {
+          const T gam = cin / C;
+          const T rest = (gam - T(1)) * cs;
+#pragma unroll
+          for (int i = 0; i < 5; ++i) g[i] = fmad(gam, g[i], rest * wg[i]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 5; ++i) g[i] = wg[i] * (cin - cs);
+        }
+        dc = (double)cin - (double)C;
+      }
     }
+    if (odd)
+      store_state<S, true>(pl, node, lc, nb, f, g);
+    else
+      store_state<S, false>(pl, node, lc, nb, f, g);
+    flux.add(s, dm, dc);
   }
-  if (odd)
-    store_state<S, true>(pl, node, lc, nb, f, g);
-  else
-    store_state<S, false>(pl, node, lc, nb, f, g);
-  if (dm != 0.0) atomicAdd((double *)L.flux + 2 * s, dm);
-  if (dc != 0.0) atomicAdd((double *)L.flux + 2 * s + 1, dc);
+  flux.flush((double *)L.flux);  // every lane of the wavefront
 }
 
 hipError_t launch_rescale(gg_storage s, const LatDesc *d, const int32_t *xy, int n, int dt,
                           bool fluid, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const int grid = (n + 255) / 256;
+  const int grid = (n + 63) / 64;
   switch (s) {
-    case GG_F64: k_rescale<double><<<grid, 256, 0, st>>>(d, xy, n, dt, fluid); break;
-    case GG_F32: k_rescale<float><<<grid, 256, 0, st>>>(d, xy, n, dt, fluid); break;
-    case GG_F16_SHIFTED: k_rescale<__half><<<grid, 256, 0, st>>>(d, xy, n, dt, fluid); break;
+    case GG_F64: k_rescale<double><<<grid, 64, 0, st>>>(d, xy, n, dt, fluid); break;
+    case GG_F32: k_rescale<float><<<grid, 64, 0, st>>>(d, xy, n, dt, fluid); break;
+    case GG_F16_SHIFTED: k_rescale<__half><<<grid, 64, 0, st>>>(d, xy, n, dt, fluid); break;
   }
   return hipGetLastError();
 }
@@ -602,7 +599,8 @@ __device__ __forceinline__ typename Pop<S>::T node_drho(CDesc &L,
 
 // Before step t (device counter + dt). Threads 0 .. n - 1: the moments of
 // listed node k (d rho, j, dC) and its dg_1..4 into save[k]; threads n ..
-// n + n_links - 1 (fluid steps only): for the link entry k * 8 + (i - 1),
+// n + n_links - 1 (fluid steps only): for the link entry (x, y, k * 8 +
+// (i - 1)) of node k at (x, y),
 // the density deviation of z + e_i into save[k][3 + i], or that of z
 // itself where z + e_i is not fluid (then 2 d rho - d rho = d rho exactly:
 // rho_s = rho(z)). One thread per link keeps the loads of a node's
@@ -638,9 +636,9 @@ __global__ void __launch_bounds__(64)
     for (int i = 1; i < 5; ++i) o[11 + i] = g[i];
     return;
   }
-  const int e = links[tid - n];
-  const int k = e >> 3, i = (e & 7) + 1;
-  int x = xy[2 * k], y = xy[2 * k + 1];
+  const int32_t *le = links + 3 * (tid - n);
+  int x = le[0], y = le[1];
+  const int k = le[2] >> 3, i = (le[2] & 7) + 1;
   int ax = x + EX[i], ay = y + EY[i];
   bool inside = true;
   if (ax < 0 || ax >= L.nx) {
@@ -662,13 +660,13 @@ __global__ void __launch_bounds__(64)
 }
 
 // After step t, before a pressure rescaling: one thread per link entry
-// k * 8 + (i - 1) whose source is, at step t's phase, a wall, a closed
+// (x, y, k * 8 + (i - 1)) whose source is, at step t's phase, a wall, a closed
 // valve or an unconfigured segment cell; writes the ghost's populations
 // into node k's own slots i (f, fluid steps only) and 9 + i (g, i <= 4).
 template <class S>
 __global__ void __launch_bounds__(64)
-    k_wall_apply(const LatDesc *__restrict__ desc, const int32_t *__restrict__ xy,
-                 const int32_t *__restrict__ links, int n_links, int dt,
+    k_wall_apply(const LatDesc *__restrict__ desc, const int32_t *__restrict__ links,
+                 int n_links, int dt,
                  const typename Pop<S>::T *__restrict__ save, int fluid) {
 #pragma clang fp contract(off)
   using P = Pop<S>;
@@ -676,10 +674,10 @@ __global__ void __launch_bounds__(64)
   const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (j >= n_links) return;
   CDesc &L = *(CDesc *)desc;
-  const int e = links[j];
-  const int k = e >> 3, i = (e & 7) + 1;
+  const int32_t *le = links + 3 * j;
+  const int k = le[2] >> 3, i = (le[2] & 7) + 1;
   if (!fluid && i > 4) return;
-  const int x = xy[2 * k], y = xy[2 * k + 1];
+  const int x = le[0], y = le[1];
   const int64_t t = *(const GG_CONST int64_t *)L.t + dt;
   const PhaseNow ph = phase_at(L, t);
   if (!wall_link(L, source_code(L, x, y, i), ph)) return;
@@ -739,20 +737,20 @@ hipError_t launch_wall_save(gg_storage s, const LatDesc *d, const int32_t *xy, i
   return hipGetLastError();
 }
 
-hipError_t launch_wall_apply(gg_storage s, const LatDesc *d, const int32_t *xy,
-                             const int32_t *links, int n_links, int dt, const void *save,
+hipError_t launch_wall_apply(gg_storage s, const LatDesc *d, const int32_t *links, int n_links,
+                             int dt, const void *save,
                              bool fluid, hipStream_t st) {
   if (n_links <= 0) return hipSuccess;
   const int grid = (n_links + 63) / 64;
   switch (s) {
     case GG_F64:
-      k_wall_apply<double><<<grid, 64, 0, st>>>(d, xy, links, n_links, dt, (const double *)save, fluid);
+      k_wall_apply<double><<<grid, 64, 0, st>>>(d, links, n_links, dt, (const double *)save, fluid);
       break;
     case GG_F32:
-      k_wall_apply<float><<<grid, 64, 0, st>>>(d, xy, links, n_links, dt, (const float *)save, fluid);
+      k_wall_apply<float><<<grid, 64, 0, st>>>(d, links, n_links, dt, (const float *)save, fluid);
       break;
     case GG_F16_SHIFTED:
-      k_wall_apply<__half><<<grid, 64, 0, st>>>(d, xy, links, n_links, dt, (const float *)save, fluid);
+      k_wall_apply<__half><<<grid, 64, 0, st>>>(d, links, n_links, dt, (const float *)save, fluid);
       break;
   }
   return hipGetLastError();

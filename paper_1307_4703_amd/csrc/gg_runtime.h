@@ -78,7 +78,7 @@ struct gg_lattice {
   int wall_scheme = 0;
   int32_t *d_wall = nullptr;
   int n_wall = 0;
-  int32_t *d_wall_links = nullptr;  // k * 8 + (i - 1): node k, link from x - e_i
+  int32_t *d_wall_links = nullptr;  // (x, y, k * 8 + (i - 1)): node k, link from x - e_i
   int n_wall_links = 0;
   void *d_wall_save = nullptr;
   bool wall_dirty = true;

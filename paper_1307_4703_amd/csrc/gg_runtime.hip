@@ -543,10 +543,13 @@ static gg_status pressure_nodes(gg_lattice *L) {
       for (int x = 0; x < L->nx; ++x) {
         const uint8_t lc = L->link[L->nid(x, y)];
         if (lc == NOT_FLUID || lc == 0) continue;
-        bool any = false;
-        for (int k = 1; k < 9 && !any; ++k) {
-          if (!((lc >> (k - 1)) & 1)) continue;
-          int xx = x + EX[k], yy = y + EY[k];
+        // the pressure segments among the source cells x - e_j, in order of
+        // first appearance for j = 1..8 (the kernel takes the first open one)
+        uint32_t cand = 0;
+        int n_cand = 0;
+        for (int j = 1; j < 9; ++j) {
+          if (!((lc >> (OPP[j] - 1)) & 1)) continue;  // x - e_j is fluid
+          int xx = x - EX[j], yy = y - EY[j];
           bool inside = true;
           if (xx < 0 || xx >= L->nx) {
             if (L->p.periodic_x) xx = (xx + L->nx) % L->nx; else inside = false;
@@ -556,17 +559,25 @@ static gg_status pressure_nodes(gg_lattice *L) {
           }
           if (!inside) continue;
           const int m = L->mask[(size_t)yy * L->nx + xx];
-          any = m >= GG_FIRST_SEGMENT && L->seg[m - GG_FIRST_SEGMENT].set &&
-                L->seg[m - GG_FIRST_SEGMENT].kind == GG_SEG_PRESSURE;
+          if (m < GG_FIRST_SEGMENT || !L->seg[m - GG_FIRST_SEGMENT].set ||
+              L->seg[m - GG_FIRST_SEGMENT].kind != GG_SEG_PRESSURE)
+            continue;
+          const uint32_t q1 = (uint32_t)(m - GG_FIRST_SEGMENT + 1);
+          bool seen = false;
+          for (int b = 0; b < n_cand; ++b) seen = seen || ((cand >> (8 * b)) & 0xFFu) == q1;
+          if (seen) continue;
+          if (n_cand == 4) return fail(GG_ERR_ARG, "a node touches more than four pressure segments");
+          cand |= q1 << (8 * n_cand++);
         }
-        if (any) {
+        if (n_cand > 0) {
           xy.push_back(x);
           xy.push_back(y);
+          xy.push_back((int32_t)cand);
         }
       }
   if (L->d_press) GG_HIP(hipFree(L->d_press));
   L->d_press = nullptr;
-  L->n_press = (int)(xy.size() / 2);
+  L->n_press = (int)(xy.size() / 3);
   if (!xy.empty()) {
     GG_HIP(hipMalloc(&L->d_press, xy.size() * sizeof(int32_t)));
     GG_HIP(hipMemcpy(L->d_press, xy.data(), xy.size() * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -714,7 +725,11 @@ static gg_status wall_nodes(gg_lattice *L) {
         xy.push_back(x);
         xy.push_back(y);
         for (int i = 1; i < 9; ++i)  // bit opp(i) - 1: x - e_i is not fluid
-          if ((lc >> (OPP[i] - 1)) & 1) links.push_back(k * 8 + (i - 1));
+          if ((lc >> (OPP[i] - 1)) & 1) {
+            links.push_back(x);
+            links.push_back(y);
+            links.push_back(k * 8 + (i - 1));
+          }
       }
   if (L->d_wall) GG_HIP(hipFree(L->d_wall));
   if (L->d_wall_links) GG_HIP(hipFree(L->d_wall_links));
@@ -723,7 +738,7 @@ static gg_status wall_nodes(gg_lattice *L) {
   L->d_wall_links = nullptr;
   L->d_wall_save = nullptr;
   L->n_wall = (int)(xy.size() / 2);
-  L->n_wall_links = (int)links.size();
+  L->n_wall_links = (int)(links.size() / 3);
   if (!xy.empty()) {
     GG_HIP(hipMalloc(&L->d_wall, xy.size() * sizeof(int32_t)));
     GG_HIP(hipMemcpy(L->d_wall, xy.data(), xy.size() * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -785,8 +800,8 @@ static hipError_t launch_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t
         e = launch_step(L->storage, block, ((t0 + dt) & 1) != 0, L->d_desc, L->d_tiles,
                         L->n_tiles, txs, (int)dt, st);
       if (e == hipSuccess && L->n_wall > 0)
-        e = launch_wall_apply(L->storage, L->d_desc, L->d_wall, L->d_wall_links,
-                              L->n_wall_links, (int)dt, L->d_wall_save, true, st);
+        e = launch_wall_apply(L->storage, L->d_desc, L->d_wall_links, L->n_wall_links,
+                              (int)dt, L->d_wall_save, true, st);
       if (e == hipSuccess && L->n_press > 0)
         e = launch_rescale(L->storage, L->d_desc, L->d_press, L->n_press, (int)dt, true, st);
     }
@@ -1713,8 +1728,8 @@ static hipError_t launch_cde_steps(gg_lattice *L, int64_t t0, int64_t n, hipStre
                            L->n_wall_links, (int)dt, false, L->d_wall_save, st);
     if (e == hipSuccess) e = single(dt);
     if (e == hipSuccess && L->n_wall > 0)
-      e = launch_wall_apply(L->storage, L->d_desc, L->d_wall, L->d_wall_links,
-                            L->n_wall_links, (int)dt, L->d_wall_save, false, st);
+      e = launch_wall_apply(L->storage, L->d_desc, L->d_wall_links, L->n_wall_links, (int)dt,
+                            L->d_wall_save, false, st);
     if (e == hipSuccess && L->n_press > 0)
       e = launch_rescale(L->storage, L->d_desc, L->d_press, L->n_press, (int)dt, false, st);
   }
