@@ -243,8 +243,10 @@ gg_status gg_set_launch(gg_lattice *lat, int32_t tile_x, int32_t tile_y,
  *     beside the others on a second stream, which keeps the boundary code
  *     out of the others' register budget).
  * Each collides a one-node halo around its strip or tile once more for the
- * first step. Errors: GG_ERR_ARG for other values, GG_ERR_OOM if the
- * planes do not fit. */
+ * first step. Errors: GG_ERR_ARG for other values, and for fuse = 2 where
+ * two vertically adjacent fluid nodes link to more than two boundary
+ * segments between them (a walking strip sums their fluxes in one record
+ * of two segments); GG_ERR_OOM if the planes do not fit. */
 gg_status gg_set_two_step(gg_lattice *lat, int32_t fuse, int32_t strip_h);
 
 /* Compound alone on frozen velocity fields. The paper lets the flow of a

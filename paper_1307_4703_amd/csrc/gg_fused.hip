@@ -36,7 +36,7 @@ namespace {
 // with the post-collision populations pushed into the neighbours' slots of
 // the destination planes (or, toward a non-fluid neighbour, the value that
 // arrives here along the opposite direction into this node's own slot).
-template <class S, bool SEG>
+template <class S, bool SEG, bool PRESS = false>
 __device__ __forceinline__ void second_step(CDesc &L, const Planes<typename Pop<S>::W> &dst,
                                             int x, int y, uint8_t lc, const PhaseNow &ph,
                                             const typename Pop<S>::T *sf,
@@ -45,7 +45,7 @@ __device__ __forceinline__ void second_step(CDesc &L, const Planes<typename Pop<
   using P = Pop<S>;
   using T = typename P::T;
   T qf[9], qg[5], jf[9], jg[5];
-  collide_node<T, false>(L, x, y, lc, SEG, ph, sf, sg, qf, qg, jf, jg, fx, true, nbr);
+  collide_node<T, PRESS>(L, x, y, lc, SEG, ph, sf, sg, qf, qg, jf, jg, fx, true, nbr);
   const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
   const Neigh nb(L, x, y);
   P::st(dst.at(0, node), qf[0]);
@@ -243,7 +243,12 @@ __global__ void __launch_bounds__(256)
 // wavefront w on lattice row y0 - 1 + w. Every wavefront does step t on its
 // row; the populations that cross rows (f2, f5, f6, g2 up; f4, f7, f8, g4
 // down) go through LDS; after one barrier the owned rows do step t + 1.
-template <class S, bool SEG, int R>
+// PRESS (segment tiles of lattices with pressure segments): the pressure
+// rule at the links, and the rescaling (Eq. 10) of the state at t + 1 of a
+// node next to an open pressure segment, in registers between the two
+// steps, as the rescaling kernel does it in memory after a single step (the
+// one after the pass's second step still runs as that kernel).
+template <class S, bool SEG, int R, bool PRESS = false>
 __global__ void __launch_bounds__((R + 2) * 64)
     k_tile2(const LatDesc *__restrict__ descs, const Tile *__restrict__ tiles, int n_tiles,
             int per_xcd, int dir, int dt) {
@@ -310,7 +315,7 @@ __global__ void __launch_bounds__((R + 2) * 64)
     Flux fx;
     T pf[9], pg[5], inf[9], ing[5];
     if (lc != NOT_FLUID) {
-      collide_node<T, false>(L, x, y, lc, seg, ph1, f, g, pf, pg, inf, ing, fx, own,
+      collide_node<T, PRESS>(L, x, y, lc, seg, ph1, f, g, pf, pg, inf, ing, fx, own,
                              SEG ? nbr : nullptr);
     } else {
 #pragma unroll
@@ -347,8 +352,20 @@ __global__ void __launch_bounds__((R + 2) * 64)
       sf[7] = P::rt(src_solid(lc, 7) ? inf[7] : lds_dn[w + 1][1][lane]);
       sf[8] = P::rt(src_solid(lc, 8) ? inf[8] : lds_dn[w + 1][2][lane]);
       sg[4] = P::rt(src_solid(lc, 4) ? ing[4] : lds_dn[w + 1][3][lane]);
+      if (PRESS && seg) {
+        const int ps = pressure_source(L, lc, ph1, nbr);
+        if (ps >= 0) {
+          double dm, dc;
+          rescale_node<T>(L, ps, ph1, true, sf, sg, dm, dc);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) sf[i] = P::rt(sf[i]);
+#pragma unroll
+          for (int i = 0; i < 5; ++i) sg[i] = P::rt(sg[i]);
+          fx.add(ps, dm, dc);
+        }
+      }
       if (seg)
-        second_step<S, true>(L, dst, x, y, lc, ph2, sf, sg, fx, nbr);
+        second_step<S, true, PRESS>(L, dst, x, y, lc, ph2, sf, sg, fx, nbr);
       else
         second_step<S, false>(L, dst, x, y, lc, ph2, sf, sg, fx);
     }
@@ -378,19 +395,22 @@ hipError_t launch_step2(gg_storage s, bool seg, const LatDesc *d, const Tile *st
 }
 
 hipError_t launch_tile2(gg_storage s, bool seg, int rows, const LatDesc *d, const Tile *tiles,
-                        int n_tiles, int dir, int dt, hipStream_t st) {
+                        int n_tiles, int dir, int dt, hipStream_t st, bool press) {
   if (n_tiles <= 0) return hipSuccess;
   const int per_xcd = (n_tiles + 7) / 8;
   const int grid = 8 * per_xcd;
-#define GG_LAUNCHT(TYPE, SEGV, RV) \
-  k_tile2<TYPE, SEGV, RV><<<grid, ((RV) + 2) * 64, 0, st>>>(d, tiles, n_tiles, per_xcd, dir, dt)
-#define GG_LAUNCHT_S(TYPE)                           \
-  do {                                               \
-    if (seg && rows <= 2) GG_LAUNCHT(TYPE, true, 2); \
-    else if (seg && rows <= 6) GG_LAUNCHT(TYPE, true, 6); \
-    else if (seg) GG_LAUNCHT(TYPE, true, 14);        \
-    else if (rows <= 6) GG_LAUNCHT(TYPE, false, 6);  \
-    else GG_LAUNCHT(TYPE, false, 14);                \
+#define GG_LAUNCHT(TYPE, SEGV, RV, PV) \
+  k_tile2<TYPE, SEGV, RV, PV><<<grid, ((RV) + 2) * 64, 0, st>>>(d, tiles, n_tiles, per_xcd, dir, dt)
+#define GG_LAUNCHT_S(TYPE)                                           \
+  do {                                                               \
+    if (seg && press && rows <= 2) GG_LAUNCHT(TYPE, true, 2, true);  \
+    else if (seg && press && rows <= 6) GG_LAUNCHT(TYPE, true, 6, true); \
+    else if (seg && press) GG_LAUNCHT(TYPE, true, 14, true);         \
+    else if (seg && rows <= 2) GG_LAUNCHT(TYPE, true, 2, false);     \
+    else if (seg && rows <= 6) GG_LAUNCHT(TYPE, true, 6, false);     \
+    else if (seg) GG_LAUNCHT(TYPE, true, 14, false);                 \
+    else if (rows <= 6) GG_LAUNCHT(TYPE, false, 6, false);           \
+    else GG_LAUNCHT(TYPE, false, 14, false);                         \
   } while (0)
   switch (s) {
     case GG_F64: GG_LAUNCHT_S(double); break;

@@ -23,9 +23,11 @@ hipError_t launch_step2(gg_storage s, bool seg, const LatDesc *d, const Tile *st
 // The same two steps row-parallel: one work-group of rows + 2 wavefronts
 // per tile of 62 columns x (flags >> 8) rows, rows 2, 6 or 14; seg selects
 // the kernel that also carries the boundary rules (applied to the tiles
-// whose segment bit is set).
+// whose segment bit is set); press (with seg): the lattice has pressure
+// segments, whose link rule and first rescaling the pass then applies (the
+// rescaling of the state after the pass is launch_rescale's).
 hipError_t launch_tile2(gg_storage s, bool seg, int rows, const LatDesc *d, const Tile *tiles,
-                        int n_tiles, int dir, int dt, hipStream_t st);
+                        int n_tiles, int dir, int dt, hipStream_t st, bool press = false);
 
 // Compound-only step on frozen velocity fields (64 x 4 tiles, 256-thread
 // work-groups, XCD-aware tile order as launch_step); odd = parity of the
@@ -75,9 +77,10 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
 // boundary value from an open pressure segment (candidates: the pressure
 // segments among the node's source cells, one byte each, index + 1, in
 // order of first appearance in direction order); fluid = false rescales the
-// compound only.
+// compound only; other: the state is in the second plane set (after a
+// two-step pass).
 hipError_t launch_rescale(gg_storage s, const LatDesc *d, const int32_t *xy, int n, int dt,
-                          bool fluid, hipStream_t st);
+                          bool fluid, hipStream_t st, bool other = false);
 hipError_t launch_advance(const LatDesc *descs, int n, int64_t k, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
 

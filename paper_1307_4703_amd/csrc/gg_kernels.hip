@@ -456,7 +456,7 @@ __device__ __forceinline__ void store_state(const Planes<typename Pop<S>::W> &pl
 template <class S>
 __global__ void __launch_bounds__(64)
     k_rescale(const LatDesc *__restrict__ desc, const int32_t *__restrict__ list, int n, int dt,
-              int fluid) {
+              int fluid, int other) {
   using P = Pop<S>;
   using T = typename P::T;
   const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
@@ -481,7 +481,7 @@ __global__ void __launch_bounds__(64)
   if (s >= 0) {
     const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
     const uint8_t lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
-    const Planes<typename P::W> pl(L);
+    const Planes<typename P::W> pl(other ? L.pop_b : L.pop, L.plane);
     const Neigh nb(L, x, y);
     T f[9], g[5];
     const bool odd = ((t + 1) & 1) != 0;  // parity of the state at t + 1
@@ -489,37 +489,8 @@ __global__ void __launch_bounds__(64)
       load_state<S, true>(pl, node, lc, nb, f, g);
     else
       load_state<S, false>(pl, node, lc, nb, f, g);
-    double dm = 0.0, dc = 0.0;
-    {
-#pragma clang fp contract(off)
-      if (fluid) {
-        T drho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-        const T rho = (T)L.rho0 + drho;
-        const T rs = SegT<T>::rho(L, s);
-        const T gam = rs / rho;
-        const T rest = (gam - T(1)) * (T)L.rho0;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = fmad(gam, f[i], rest * (T)WF[i]);
-        dm = (double)rs - (double)rho;
-      }
-      if (L.seg_holdc[s]) {
-        const T cs = (T)L.c_shift;
-        const T wga = (T)L.wg_axis;
-        const T wg[5] = {T(1) - T(4) * wga, wga, wga, wga, wga};
-        const T C = cs + (g[0] + g[1] + g[2] + g[3] + g[4]);
-        const T cin = SegT<T>::cin(ph, s);
-        if (C > T(0)) {
-          const T gam = cin / C;
-          const T rest = (gam - T(1)) * cs;
-#pragma unroll
-          for (int i = 0; i < 5; ++i) g[i] = fmad(gam, g[i], rest * wg[i]);
-        } else {
-#pragma unroll
-          for (int i = 0; i < 5; ++i) g[i] = wg[i] * (cin - cs);
-        }
-        dc = (double)cin - (double)C;
-      }
-    }
+    double dm, dc;
+    rescale_node<T>(L, s, ph, fluid != 0, f, g, dm, dc);
     if (odd)
       store_state<S, true>(pl, node, lc, nb, f, g);
     else
@@ -530,13 +501,13 @@ __global__ void __launch_bounds__(64)
 }
 
 hipError_t launch_rescale(gg_storage s, const LatDesc *d, const int32_t *xy, int n, int dt,
-                          bool fluid, hipStream_t st) {
+                          bool fluid, hipStream_t st, bool other) {
   if (n <= 0) return hipSuccess;
   const int grid = (n + 63) / 64;
   switch (s) {
-    case GG_F64: k_rescale<double><<<grid, 64, 0, st>>>(d, xy, n, dt, fluid); break;
-    case GG_F32: k_rescale<float><<<grid, 64, 0, st>>>(d, xy, n, dt, fluid); break;
-    case GG_F16_SHIFTED: k_rescale<__half><<<grid, 64, 0, st>>>(d, xy, n, dt, fluid); break;
+    case GG_F64: k_rescale<double><<<grid, 64, 0, st>>>(d, xy, n, dt, fluid, other); break;
+    case GG_F32: k_rescale<float><<<grid, 64, 0, st>>>(d, xy, n, dt, fluid, other); break;
+    case GG_F16_SHIFTED: k_rescale<__half><<<grid, 64, 0, st>>>(d, xy, n, dt, fluid, other); break;
   }
   return hipGetLastError();
 }

@@ -243,10 +243,10 @@ __device__ __forceinline__ void compound_collide(CDesc &L, int x, int y, const T
 // bytes k - 1 of nbr[0] (k = 1..4) and nbr[1] (k = 5..8).
 //
 // PRESS compiles the pressure-boundary rule in. The two-step passes leave it
-// out (a lattice with pressure segments never runs them: its rescaling must
-// follow every step), which keeps the node's pre-collision populations out
-// of their register budget and their control flow as it was; without it an
-// open pressure link would take the outlet rule.
+// out unless the lattice has pressure segments (their own instantiation),
+// which keeps the node's pre-collision populations out of the others'
+// register budget and their control flow as it was; without it an open
+// pressure link would take the outlet rule.
 template <class T, bool PRESS = true>
 __device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc, bool seg_tile,
                                              const PhaseNow &ph, const T *f, const T *g, T *pf,
@@ -378,6 +378,64 @@ __device__ __forceinline__ void compound_links(CDesc &L, int x, int y, uint8_t l
                                                                                : pg[j];
     in_g[j] = vg;
     if (count) fx.add(s, 0.0, (double)(vg - pg[OPP[j]]));
+  }
+}
+
+// Pressure boundary (Eq. 10): the first segment, in direction order of the
+// source cells x - e_j, that is a pressure segment open at phase ph, or -1.
+// nbr as for collide_node (required).
+__device__ __forceinline__ int pressure_source(CDesc &L, uint8_t lc, const PhaseNow &ph,
+                                               const uint32_t *nbr) {
+  int s = -1;
+#pragma unroll
+  for (int j = 1; j < 9; ++j) {
+    if (s >= 0 || !((lc >> (OPP[j] - 1)) & 1)) continue;  // found, or x - e_j fluid
+    const int code = (int)((nbr[(OPP[j] - 1) >> 2] >> (8 * ((OPP[j] - 1) & 3))) & 0xFFu);
+    if (code < GG_FIRST_SEGMENT) continue;
+    const int q = code - GG_FIRST_SEGMENT;
+    if (L.seg_kind[q] == GG_SEG_PRESSURE && ((ph.open >> q) & 1u)) s = q;
+  }
+  return s;
+}
+
+// The rescaling of a node that takes boundary values from the open pressure
+// segment s at a step of phase ph, applied to its streamed state (the
+// deviations df, dg): every f_i multiplied so that rho = rho_s (velocity
+// unchanged; skipped unless fluid), and where the segment holds the
+// compound, every g_i so that C = C_in, or the equilibrium at rest of C_in
+// where C <= 0. dm, dc: the mass and compound added. In the deviation form
+// gamma (w rho0 + df) - w rho0 = gamma df + (gamma - 1) w rho0.
+template <class T>
+__device__ __forceinline__ void rescale_node(CDesc &L, int s, const PhaseNow &ph, bool fluid,
+                                             T *f, T *g, double &dm, double &dc) {
+#pragma clang fp contract(off)
+  dm = dc = 0.0;
+  if (fluid) {
+    T drho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    const T rho = (T)L.rho0 + drho;
+    const T rs = SegT<T>::rho(L, s);
+    const T gam = rs / rho;
+    const T rest = (gam - T(1)) * (T)L.rho0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = fmad(gam, f[i], rest * (T)WF[i]);
+    dm = (double)rs - (double)rho;
+  }
+  if (L.seg_holdc[s]) {
+    const T cs = (T)L.c_shift;
+    const T wga = (T)L.wg_axis;
+    const T wg[5] = {T(1) - T(4) * wga, wga, wga, wga, wga};
+    const T C = cs + (g[0] + g[1] + g[2] + g[3] + g[4]);
+    const T cin = SegT<T>::cin(ph, s);
+    if (C > T(0)) {
+      const T gam = cin / C;
+      const T rest = (gam - T(1)) * cs;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) g[i] = fmad(gam, g[i], rest * wg[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 5; ++i) g[i] = wg[i] * (cin - cs);
+    }
+    dc = (double)cin - (double)C;
   }
 }
 

@@ -57,6 +57,7 @@ struct gg_lattice {
   // tiles of strip_h rows with the boundary kernel apart or in one kernel);
   // fuse = 1 keeps to single steps
   int fuse = 3, strip_h = 6;
+  bool strip_flux_ok = true;  // no vertical node pair links to > 2 segments
   gg::Tile *d_strips = nullptr;      // strips without segment links
   int n_strips = 0;
   gg::Tile *d_seg_strips = nullptr;  // strips with segment links (2 rows each)

@@ -319,6 +319,8 @@ gg_status gg_create(const uint8_t *mask, int32_t nx, int32_t ny, const gg_params
   // classify links
   L->link.assign((size_t)plane_elems, NOT_FLUID);
   L->touches_seg.assign((size_t)nx * ny, 0);
+  // the segments each fluid node links to (up to two mask values, 0: none)
+  std::vector<uint16_t> node_segs((size_t)nx * ny, 0);
   int64_t nf = 0;
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
@@ -364,10 +366,28 @@ gg_status gg_create(const uint8_t *mask, int32_t nx, int32_t ny, const gg_params
         return s;
       }
       L->touches_seg[(size_t)y * nx + x] = nseg > 0;
+      node_segs[(size_t)y * nx + x] =
+          (uint16_t)((nseg > 0 ? segs[0] : 0) | (nseg > 1 ? segs[1] << 8 : 0));
       L->link[L->nid(x, y)] = code;
       ++nf;
     }
   L->n_fluid = nf;
+  // a walking strip sums the boundary fluxes of a node and of the node
+  // below it in one per-lane record of two segments
+  for (int y = 1; y < ny && L->strip_flux_ok; ++y)
+    for (int x = 0; x < nx; ++x) {
+      const uint16_t a = node_segs[(size_t)y * nx + x], b = node_segs[(size_t)(y - 1) * nx + x];
+      int u[4], nu = 0;
+      for (int v : {a & 0xFF, a >> 8, b & 0xFF, b >> 8}) {
+        bool seen = v == 0;
+        for (int q = 0; q < nu; ++q) seen = seen || u[q] == v;
+        if (!seen) u[nu++] = v;
+      }
+      if (nu > 2) {
+        L->strip_flux_ok = false;
+        break;
+      }
+    }
 
   auto alloc = [&](void **p, size_t bytes) -> gg_status {
     hipError_t e = hipMalloc(p, bytes);
@@ -708,8 +728,14 @@ static gg_status check_segments(gg_lattice *L) {
 // between the two plane sets and end in the first one.
 // One two-step pass: the segment strips on the side stream, forked from and
 // joined back to st (inside a capture this becomes two graph branches).
-// Lattices whose steps must run one at a time with fix-ups around them.
+// Lattices whose steps must run with fix-ups around them.
 static bool special_boundaries(const gg_lattice *L) { return has_pressure(L) || L->wall_scheme != 0; }
+
+// The two-step pass is on and covers the lattice's boundaries: the paper's
+// walls need single steps, pressure segments the row-parallel tiles.
+static bool pass_ok(const gg_lattice *L) {
+  return L->fuse >= 2 && L->wall_scheme == 0 && (L->n_press == 0 || L->fuse >= 3);
+}
 
 // The fluid nodes with a link from a wall or from a segment's ghost cell
 // (a valve that may close), for the paper's walls.
@@ -760,14 +786,15 @@ static gg_status wall_nodes(gg_lattice *L) {
 static hipError_t launch_pass(gg_lattice *L, int dir, int dt, hipStream_t st) {
   hipError_t e = hipSuccess;
   const bool fork = L->n_seg_strips > 0 && L->n_strips > 0;
+  const bool press = L->n_press > 0;  // (fuse 3 and 4 only)
   if (L->fuse == 4)  // one kernel with the boundary rules for every tile
     return launch_tile2(L->storage, true, L->strip_h, L->d_desc, L->d_strips, L->n_strips, dir, dt,
-                        st);
+                        st, press);
   auto run = [&](bool seg, const Tile *list, int n, hipStream_t s) {
     // the segment list holds 2-row tiles
-    return L->fuse == 3
-               ? launch_tile2(L->storage, seg, seg ? 2 : L->strip_h, L->d_desc, list, n, dir, dt, s)
-               : launch_step2(L->storage, seg, L->d_desc, list, n, dir, dt, s);
+    return L->fuse == 3 ? launch_tile2(L->storage, seg, seg ? 2 : L->strip_h, L->d_desc, list, n,
+                                       dir, dt, s, press)
+                        : launch_step2(L->storage, seg, L->d_desc, list, n, dir, dt, s);
   };
   if (fork) {
     e = hipEventRecord(L->ev_fork, st);
@@ -784,9 +811,15 @@ static hipError_t launch_pass(gg_lattice *L, int dir, int dt, hipStream_t st) {
 
 static hipError_t launch_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t st) {
   hipError_t e = hipSuccess;
-  if (L->fuse >= 2 && !(t0 & 1) && n % 4 == 0 && L->n_press == 0 && L->wall_scheme == 0) {
-    for (int64_t k = 0; k < n / 2 && e == hipSuccess; ++k)
+  if (pass_ok(L) && !(t0 & 1) && n % 4 == 0) {
+    // with pressure segments the pass rescales the boundary nodes between
+    // its two steps; the state it leaves is rescaled here
+    for (int64_t k = 0; k < n / 2 && e == hipSuccess; ++k) {
       e = launch_pass(L, (int)(k & 1), (int)(2 * k), st);
+      if (e == hipSuccess && L->n_press > 0)
+        e = launch_rescale(L->storage, L->d_desc, L->d_press, L->n_press, (int)(2 * k + 1), true,
+                           st, (k & 1) == 0);
+    }
   } else {
     // (pressure boundaries: one step at a time, each followed by the
     // rescaling of the boundary nodes)
@@ -845,7 +878,7 @@ gg_status gg_step(gg_lattice *L, int64_t n) {
       L->t += K;
     }
   }
-  const int64_t quads = L->fuse >= 2 && L->n_press == 0 && L->wall_scheme == 0 ? left / 4 * 4 : 0;
+  const int64_t quads = pass_ok(L) ? left / 4 * 4 : 0;
   if (quads > 0) {
     GG_HIP(launch_steps(L, L->t, quads, L->stream));
     L->t += quads;
@@ -1027,6 +1060,9 @@ gg_status gg_set_two_step(gg_lattice *L, int32_t fuse, int32_t strip_h) {
   if (fuse < 1 || fuse > 4) return fail(GG_ERR_ARG, "fuse must be 1, 2, 3 or 4");
   if (fuse == 2 && (strip_h < 1 || strip_h > 4096))
     return fail(GG_ERR_ARG, "strips walk 1..4096 rows");
+  if (fuse == 2 && !L->strip_flux_ok)
+    return fail(GG_ERR_ARG, "walking strips: two vertically adjacent fluid nodes link to more "
+                            "than two boundary segments between them; use fuse 3 or 4");
   if (fuse >= 3 && strip_h != 6 && strip_h != 14)
     return fail(GG_ERR_ARG, "row-parallel tiles have 6 or 14 rows");
   GG_HIP(hipStreamSynchronize(L->stream));

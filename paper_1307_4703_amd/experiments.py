@@ -319,7 +319,9 @@ def boundary_comparison(storage: str = "f64", steps: int = 30000,
 def boundary_rates(rate_steps: int = 2000) -> Dict:
     """Rate of the 2048 x 1024 gradient generator (FP32) with velocity
     inlets and outlets, with pressure boundaries on its four segments, and
-    with the pressure boundaries and the paper's walls."""
+    with the pressure boundaries and the paper's walls; each with the faster
+    of the two row-parallel pass forms (boundary tiles in a kernel of their
+    own beside the others, or every tile in one kernel; 6-row tiles)."""
     import torch
     out: Dict = {}
     gg = W.gradient_generator(storage="f32")
@@ -330,23 +332,31 @@ def boundary_rates(rate_steps: int = 2000) -> Dict:
                            W.Segment(3, "pressure", (0, 1), rho=0.998),
                            W.Segment(4, "pressure", (0, -1), rho=1.002, c_in=0.0, fix_c=True),
                            W.Segment(5, "pressure", (0, 1), rho=0.998)]
-        lat = Lattice.from_workload(gg)
-        try:
-            if label.endswith("paper_walls"):
-                lat.set_wall_scheme("equilibrium")
-            lat.step(256)
-            lat.sync()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            lat.step(rate_steps)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / rate_steps
-            nf = lat.info()["n_fluid"]
-        finally:
-            lat.close()
+        best = None
+        for fuse in (3, 4):
+            lat = Lattice.from_workload(gg)
+            try:
+                lat.set_two_step(fuse, 6)
+                if label.endswith("paper_walls"):
+                    lat.set_wall_scheme("equilibrium")
+                lat.step(256)
+                lat.sync()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                lat.step(rate_steps)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / rate_steps
+                nf = lat.info()["n_fluid"]
+            finally:
+                lat.close()
+            if best is None or ms < best[0]:
+                best = (ms, fuse)
+        ms, fuse = best
         out[label] = {"gg2048_f32_mlups": round(nf / (ms * 1e-3) / 1e6, 1),
-                      "gg2048_f32_us_per_step": round(ms * 1e3, 3)}
+                      "gg2048_f32_us_per_step": round(ms * 1e3, 3),
+                      "pass_form": {"fuse": fuse, "rows": 6}}
     return out
 
 

@@ -17,6 +17,8 @@ import json
 import os
 from typing import Dict, Iterable, List, Optional, Sequence, Tuple
 
+from ._abi import GGError
+
 TILES: Tuple[Tuple[int, int], ...] = ((64, 4), (32, 8), (64, 2), (128, 2), (128, 1),
                                       (64, 8), (128, 4), (256, 1), (32, 4), (16, 8))
 PERSIST: Tuple[int, ...] = (0, 2048, 4096)
@@ -92,7 +94,10 @@ def tune_lattice(lat, steps: int = 64, tiles: Iterable[Tuple[int, int]] = TILES,
     best = min(results, key=lambda r: r["ms_per_step"])
     lat.set_launch(best["tile"][0], best["tile"][1], graph_chunk)
     for fuse, rows in two_step:
-        lat.set_two_step(fuse, rows)
+        try:
+            lat.set_two_step(fuse, rows)
+        except GGError:  # a form this lattice refuses (walking strips, see gg_set_two_step)
+            continue
         results.append({"tile": best["tile"], "fuse": fuse, "rows": rows,
                         "ms_per_step": _time(lat.step, steps)})
     best = min(results, key=lambda r: r["ms_per_step"])

@@ -86,13 +86,41 @@ def test_pressure_channel(storage):
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_pressure_gradient_generator_valves(storage):
-    """Channels driven by pressure, valves switching every 7 steps; the
-    two-step pass requested but not taken (the rescaling follows every
-    step)."""
+    """Channels driven by pressure, valves switching every 7 steps, with the
+    row-parallel two-step pass (the first rescaling of each pass in
+    registers, the second as the rescaling kernel)."""
     wl = _pressure_gg(storage)
     log(f"pressure gradient generator {storage}")
     lat, o = _run_pair(wl, storage, (8, 3, 29, 60), seed=4, two_step=(3, 6))
     _check(lat, o, wl, storage, f"pressure gg {storage}")
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_pressure_passes_equal_single_steps(storage):
+    """Every two-step form that covers pressure segments (row-parallel
+    tiles with the boundary kernel apart or in one kernel, 6 or 14 rows)
+    leaves the state single steps leave, bit for bit, and the same fluxes;
+    the walking strips fall back to single steps."""
+    wl = _pressure_gg(storage, half_period=5)
+    init = seeded_init(wl, 11)
+    lats = []
+    for form in ((1, 6), (3, 6), (3, 14), (4, 6), (4, 14), (2, 8)):
+        lat = Lattice.from_workload(wl, storage=storage, init=False)
+        lat.set_launch(64, 4, 8)
+        lat.set_two_step(*form)
+        lat.init(**init)
+        for n in (8, 3, 29, 60):
+            lat.step(n)
+        lats.append((form, lat))
+    f0, g0 = lats[0][1].populations()
+    d0 = lats[0][1].diagnostics()
+    for form, lat in lats[1:]:
+        f, g = lat.populations()
+        log(f"pressure pass {form} {storage}: max |df| {np.nanmax(np.abs(f - f0)):.3e}")
+        assert np.array_equal(f, f0, equal_nan=True) and np.array_equal(g, g0, equal_nan=True), form
+        d = lat.diagnostics()
+        for k in ("seg_mass", "seg_solute"):
+            np.testing.assert_allclose(d[k], d0[k], rtol=1e-12, atol=1e-12)
 
 
 def test_pressure_closed_valves_conserve():
