@@ -159,10 +159,14 @@ gg_status gg_set_segment(gg_lattice *lat, int32_t id, gg_seg_kind kind,
 /* Configure segment `id` as a pressure boundary (GG_SEG_PRESSURE) holding
  * density rho (> 0; pressure rho / 3) and, if hold_c is nonzero, the
  * compound at c_in (per-phase overrides as for inlets). Geometry rules as
- * for gg_set_segment. While a lattice has such a segment its steps run one
- * at a time (the rescaling follows each step in a kernel of its own), and
- * gg_adjoint, gg_batch_create, gg_step_timed and gg_step2_timed refuse it
- * (GG_ERR_STATE): the rescaling is not linear in the compound. */
+ * for gg_set_segment. While a lattice has such a segment, the rescaling
+ * follows each single step in a kernel of its own; the row-parallel
+ * two-step pass (fuse 3 and 4) rescales between its two steps in registers
+ * and is followed by that kernel (the same state, bit for bit); walking
+ * strips (fuse 2) give way to single steps; the compound-only step runs
+ * single steps. gg_adjoint, gg_batch_create, gg_step_timed and
+ * gg_step2_timed refuse such a lattice (GG_ERR_STATE): the rescaling is
+ * not linear in the compound. */
 gg_status gg_set_pressure_segment(gg_lattice *lat, int32_t id, int32_t nrm_x,
                                   int32_t nrm_y, double rho, double c_in,
                                   int32_t hold_c);
