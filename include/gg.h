@@ -163,8 +163,8 @@ gg_status gg_set_segment(gg_lattice *lat, int32_t id, gg_seg_kind kind,
  * follows each single step in a kernel of its own; the row-parallel
  * two-step pass (fuse 3 and 4) rescales between its two steps in registers
  * and is followed by that kernel (the same state, bit for bit); walking
- * strips (fuse 2) give way to single steps; the compound-only step runs
- * single steps. gg_adjoint, gg_batch_create, gg_step_timed and
+ * strips (fuse 2) give way to single steps; the compound-only passes
+ * (gg_set_cde_launch) do the same for the compound. gg_adjoint, gg_batch_create, gg_step_timed and
  * gg_step2_timed refuse such a lattice (GG_ERR_STATE): the rescaling is
  * not linear in the compound. */
 gg_status gg_set_pressure_segment(gg_lattice *lat, int32_t id, int32_t nrm_x,

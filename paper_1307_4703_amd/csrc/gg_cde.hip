@@ -99,8 +99,12 @@ __global__ void __launch_bounds__(256)
 // between the steps are rounded to the storage type, as a store and load
 // would round them, so the result is the single steps' bit for bit. Per
 // node and pass (FP32): 5 populations read and written, 2 field values and
-// the link code read, 49 bytes for two steps.
-template <class S, int R>
+// the link code read, 49 bytes for two steps. PRESS (lattices with pressure
+// segments): the pressure rule at the links, and the compound's rescaling
+// (Eq. 10) of a node next to an open pressure segment between the two
+// steps, in registers, as the rescaling kernel does it after a single step
+// (that kernel still follows the pass).
+template <class S, int R, bool PRESS = false>
 __global__ void __launch_bounds__((R + 2) * 64)
     k_cde_tile2(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles, int n_tiles,
                 int per_xcd, int dir, int dt) {
@@ -139,12 +143,21 @@ __global__ void __launch_bounds__((R + 2) * 64)
   const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
   uint8_t lc = NOT_FLUID;
   T g[5], ux = T(0), uy = T(0);
+  uint32_t nbr[2] = {0u, 0u};
   if (row && col) {
     lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
 #pragma unroll
     for (int i = 0; i < 5; ++i) g[i] = P::ld(src.at(9 + i, node));
     ux = field_plane<T>(L, s1, 0)[node];
     uy = field_plane<T>(L, s1, 1)[node];
+    // the neighbours' mask values, for the rescaling (cells inside the
+    // lattice only: their neighbours all lie in the padded planes)
+    if (PRESS && seg && x >= 0 && x < nx && y >= 0 && y < ny) {
+      const Neigh nb(L, x, y);
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        nbr[k >> 2] |= (uint32_t)((const GG_GLOBAL uint8_t *)L.mask)[nb.idx[k + 1]] << (8 * (k & 3));
+    }
   }
 
   // step t on this row
@@ -152,7 +165,7 @@ __global__ void __launch_bounds__((R + 2) * 64)
   T pg[5], ing[5];
   if (lc != NOT_FLUID) {
     compound_collide<T>(L, x, y, g, ux, uy, pg);
-    compound_links<T, false>(L, x, y, lc, seg, ph1, g, pg, ing, fx, own);
+    compound_links<T, PRESS>(L, x, y, lc, seg, ph1, g, pg, ing, fx, own);
   } else {
 #pragma unroll
     for (int i = 0; i < 5; ++i) pg[i] = ing[i] = T(0);
@@ -170,13 +183,24 @@ __global__ void __launch_bounds__((R + 2) * 64)
     sg[3] = P::rt(src_solid(lc, 3) ? ing[3] : z3);
     sg[2] = P::rt(src_solid(lc, 2) ? ing[2] : lds_up[w - 1][lane]);
     sg[4] = P::rt(src_solid(lc, 4) ? ing[4] : lds_dn[w + 1][lane]);
+    if (PRESS && seg) {
+      const int ps = pressure_source(L, lc, ph1, nbr);
+      if (ps >= 0) {
+        T unused[9];
+        double dm, dc;
+        rescale_node<T>(L, ps, ph1, false, unused, sg, dm, dc);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) sg[i] = P::rt(sg[i]);
+        fx.add(ps, dm, dc);
+      }
+    }
     if (s2 != s1) {
       ux = field_plane<T>(L, s2, 0)[node];
       uy = field_plane<T>(L, s2, 1)[node];
     }
     T qg[5], jg[5];
     compound_collide<T>(L, x, y, sg, ux, uy, qg);
-    compound_links<T, false>(L, x, y, lc, seg, ph2, sg, qg, jg, fx, true);
+    compound_links<T, PRESS>(L, x, y, lc, seg, ph2, sg, qg, jg, fx, true);
     const Neigh nb(L, x, y);
     P::st(dst.at(9, node), qg[0]);
 #pragma unroll
@@ -269,16 +293,18 @@ hipError_t launch_cde(gg_storage s, bool odd, const LatDesc *d, const Tile *tile
 }
 
 hipError_t launch_cde_tile2(gg_storage s, int rows, const LatDesc *d, const Tile *tiles,
-                            int n_tiles, int dir, int dt, hipStream_t st) {
+                            int n_tiles, int dir, int dt, hipStream_t st, bool press) {
   if (n_tiles <= 0) return hipSuccess;
   const int per_xcd = (n_tiles + 7) / 8;
   const int grid = 8 * per_xcd;
-#define GG_CDE2(TYPE, RV) \
-  k_cde_tile2<TYPE, RV><<<grid, ((RV) + 2) * 64, 0, st>>>(d, tiles, n_tiles, per_xcd, dir, dt)
-#define GG_CDE2_R(TYPE)                    \
-  do {                                     \
-    if (rows <= 6) GG_CDE2(TYPE, 6);       \
-    else GG_CDE2(TYPE, 14);                \
+#define GG_CDE2(TYPE, RV, PV) \
+  k_cde_tile2<TYPE, RV, PV><<<grid, ((RV) + 2) * 64, 0, st>>>(d, tiles, n_tiles, per_xcd, dir, dt)
+#define GG_CDE2_R(TYPE)                                  \
+  do {                                                   \
+    if (press && rows <= 6) GG_CDE2(TYPE, 6, true);      \
+    else if (press) GG_CDE2(TYPE, 14, true);             \
+    else if (rows <= 6) GG_CDE2(TYPE, 6, false);         \
+    else GG_CDE2(TYPE, 14, false);                       \
   } while (0)
   switch (s) {
     case GG_F64: GG_CDE2_R(double); break;

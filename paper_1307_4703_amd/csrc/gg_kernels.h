@@ -37,9 +37,11 @@ hipError_t launch_cde(gg_storage s, bool odd, const LatDesc *d, const Tile *tile
 // Two compound-only steps in one pass (t even, natural order in): one
 // work-group of rows + 2 wavefronts per tile of 62 columns x (flags >> 8)
 // rows, rows 6 or 14; dir 0 reads the compound planes of pop and writes
-// those of pop_b, dir 1 the reverse; dt as for launch_step.
+// those of pop_b, dir 1 the reverse; dt as for launch_step; press: the
+// lattice has pressure segments (their link rule and first rescaling in the
+// pass; launch_rescale after it).
 hipError_t launch_cde_tile2(gg_storage s, int rows, const LatDesc *d, const Tile *tiles,
-                            int n_tiles, int dir, int dt, hipStream_t st);
+                            int n_tiles, int dir, int dt, hipStream_t st, bool press = false);
 // Velocity of the current fluid state times `scale` into field slot `slot`.
 hipError_t launch_capture(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                           int tx_shift, int slot, double scale, hipStream_t st);

@@ -1749,13 +1749,23 @@ static hipError_t launch_cde_steps(gg_lattice *L, int64_t t0, int64_t n, hipStre
     return launch_cde(L->storage, ((t0 + k) & 1) != 0, L->d_desc, L->d_aux_tiles, L->n_aux_tiles,
                       6, (int)k, st);
   };
-  if (L->cde_rows > 0 && L->d_pop_b && L->cde_tiles_rows == L->cde_rows && L->n_press == 0 &&
-      L->wall_scheme == 0) {
-    if ((t0 & 1) && n > 0) e = single(dt++);
+  if (L->cde_rows > 0 && L->d_pop_b && L->cde_tiles_rows == L->cde_rows && L->wall_scheme == 0) {
+    const bool press = L->n_press > 0;
+    if ((t0 & 1) && n > 0) {
+      e = single(dt);
+      if (e == hipSuccess && press)
+        e = launch_rescale(L->storage, L->d_desc, L->d_press, L->n_press, (int)dt, false, st);
+      ++dt;
+    }
     const int64_t passes = (n - dt) / 4 * 2;
-    for (int64_t k = 0; k < passes && e == hipSuccess; ++k)
+    for (int64_t k = 0; k < passes && e == hipSuccess; ++k) {
       e = launch_cde_tile2(L->storage, L->cde_rows, L->d_desc, L->d_cde_tiles, L->n_cde_tiles,
-                           (int)(k & 1), (int)(dt + 2 * k), st);
+                           (int)(k & 1), (int)(dt + 2 * k), st, press);
+      // the rescaling of the state the pass leaves (in pop_b after dir 0)
+      if (e == hipSuccess && press)
+        e = launch_rescale(L->storage, L->d_desc, L->d_press, L->n_press, (int)(dt + 2 * k + 1),
+                           false, st, (k & 1) == 0);
+    }
     dt += 2 * passes;
   }
   for (; dt < n && e == hipSuccess; ++dt) {

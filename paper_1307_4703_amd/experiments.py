@@ -321,7 +321,8 @@ def boundary_rates(rate_steps: int = 2000) -> Dict:
     inlets and outlets, with pressure boundaries on its four segments, and
     with the pressure boundaries and the paper's walls; each with the faster
     of the two row-parallel pass forms (boundary tiles in a kernel of their
-    own beside the others, or every tile in one kernel; 6-row tiles)."""
+    own beside the others, or every tile in one kernel; 6-row tiles). For
+    the first two, also the compound alone on the flow's frozen velocity."""
     import torch
     out: Dict = {}
     gg = W.gradient_generator(storage="f32")
@@ -357,6 +358,28 @@ def boundary_rates(rate_steps: int = 2000) -> Dict:
         out[label] = {"gg2048_f32_mlups": round(nf / (ms * 1e-3) / 1e6, 1),
                       "gg2048_f32_us_per_step": round(ms * 1e3, 3),
                       "pass_form": {"fuse": fuse, "rows": 6}}
+        if label == "pressure_paper_walls":
+            continue
+        # the compound alone on the flow's frozen velocity (two-step passes
+        # of 14-row tiles)
+        lat = Lattice.from_workload(gg)
+        try:
+            lat.step(256)
+            lat.set_velocity_field(0)
+            lat.set_cde_launch(14)
+            lat.cde_step(256)
+            lat.sync()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            lat.cde_step(rate_steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / rate_steps
+        finally:
+            lat.close()
+        out[label]["gg2048_f32_compound_only_mlups"] = round(nf / (ms * 1e-3) / 1e6, 1)
+        out[label]["gg2048_f32_compound_only_us_per_step"] = round(ms * 1e3, 3)
     return out
 
 
