@@ -157,9 +157,11 @@ def test_full_size_gradient_generator_f32():
     times (graph replays of 64 steps): 200 compound-only steps on the
     velocity captured from the initial state against the oracle on the
     whole field, and the solute balance (change = net inflow, no source)."""
+    import bench
     wl = W.gradient_generator()
     init = seeded_init(wl, 4703)
     lat = make_lattice(wl, "f32", init)
+    lat.set_cde_launch([r for n, _, _, r in bench.CDE_LEG if n == "gg2048_f32"][0])
     lat.set_velocity_field(0)
     d0 = lat.diagnostics()
     log("cde full size 2048x1024 f32, 200 steps")

@@ -17,10 +17,12 @@ F32_TOL = {"rho": 1e-6, "u": 2e-5, "C": 2e-5}
 F16_TOL = {"rho": 3e-4, "u": 8e-3, "C": 1e-2}
 
 
-def _run(wl, storage, steps, seed=0, tile=None, chunk=None):
+def _run(wl, storage, steps, seed=0, tile=None, chunk=None, form=None):
     init = seeded_init(wl, seed)
-    log(f"{wl.name} storage={storage} steps={steps} tile={tile} chunk={chunk}")
+    log(f"{wl.name} storage={storage} steps={steps} tile={tile} chunk={chunk} form={form}")
     lat = make_lattice(wl, storage, init, tile=tile, chunk=chunk)
+    if form is not None:
+        lat.set_two_step(*form)
     lat.step(steps)
     lat.sync()
     o = make_oracle(wl)
@@ -151,9 +153,12 @@ def test_save_load_resume_bitwise():
 
 def test_gradient_generator_full_size_f32():
     """The 2048x1024 FP32 gradient generator in the benchmark's launch
-    configuration, 200 steps across a valve switch, against the oracle."""
+    configuration (the two-step form bench.py records for it, 64 x 4
+    single-step tiles, graph chunks of 64), 200 steps across a valve
+    switch, against the oracle."""
+    import bench
     wl = W.gradient_generator(half_period=100)
-    lat, o = _run(wl, "f32", 200, seed=0, tile=(64, 4), chunk=64)
+    lat, o = _run(wl, "f32", 200, seed=0, tile=(64, 4), chunk=64, form=bench.FORMS["gg2048_f32"])
     err = field_errors(lat, o, wl.mask == 0)
     log(f"full-size f32 errors {err}")
     for k, v in F32_TOL.items():
