@@ -178,6 +178,54 @@ def copy_bandwidth(nbytes=2 << 30, reps=20):
     return 2.0 * nbytes / (ms.value * 1e-3) / 1e9
 
 
+# Bytes per fluid node and time step of the adjoint with checkpoints (FP32
+# storage): the forward pass (113), its recomputation segment by segment
+# (113) with the tape of g and u written (7 x 4 = 28), and the adjoint step
+# (FP64 lambda read and written, 2 x 5 x 8 = 80, and the tape read, 28).
+ADJOINT_BYTES_F32 = 113 + 113 + 28 + 80 + 28
+
+
+def adjoint_bench(steps=20000):
+    """The 2048 x 1024 FP32 gradient generator's chamber-misfit gradient
+    (loss window, target ramp and source patch of chamber_misfit_setup)
+    over `steps` steps with sqrt(N) checkpoints, against `steps` plain
+    forward steps of the same lattice; wall-clock (gg_adjoint returns after
+    the gradients are on the host)."""
+    import torch
+    from paper_1307_4703_amd import Lattice
+    from paper_1307_4703_amd import workloads as W
+    wl = workload("gg2048_f32")
+    weight, target, r_box = W.chamber_misfit_setup(wl)
+    lat = Lattice.from_workload(wl)
+    try:
+        lat.set_launch(64, 4, 64)
+        lat.set_two_step(*FORMS["gg2048_f32"])
+        lat.adjoint(64, weight, target, r_box=r_box)  # kernels loaded, graphs captured
+        lat.init(**(wl.init or {}))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = lat.adjoint(steps, weight, target, r_box=r_box)
+        t1 = time.perf_counter()
+        lat.init(**(wl.init or {}))
+        lat.sync()
+        t2 = time.perf_counter()
+        lat.step(steps)
+        lat.sync()
+        t3 = time.perf_counter()
+        nf = lat.info()["n_fluid"]
+    finally:
+        lat.close()
+    sec, fwd = t1 - t0, t3 - t2
+    return {"workload": wl.name, "storage": "f32", "steps": steps, "n_fluid": nf,
+            "ckpt_every": g["ckpt_every"], "n_checkpoints": g["n_checkpoints"],
+            "seconds": round(sec, 4), "forward_seconds": round(fwd, 4),
+            "ratio_to_forward": round(sec / fwd, 2),
+            "gradient_mlups": round(nf * steps / sec / 1e6, 1),
+            "bytes_per_node_step_model": ADJOINT_BYTES_F32,
+            "model_gbs": round(nf * steps * ADJOINT_BYTES_F32 / sec / 1e9, 1),
+            "loss": g["loss"], "d_D": g["d_D"]}
+
+
 def batch_bench(steps=2000, seq_steps=400, n=64, seed=4703, tune_steps=32):
     """64 seeded gradient generators of uneven size (FP32): aggregate
     fluid-node updates per second of one batched, graph-captured launch per
@@ -413,6 +461,8 @@ def main():
                     help="skip the step-profile, boundary-kind and precision legs")
     ap.add_argument("--cde-only", action="store_true",
                     help="time only the compound-only step on frozen velocity fields")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="time only the adjoint (gradient) leg")
     ap.add_argument("--cde-steps", type=int, default=0,
                     help="timed compound-only steps per lattice (0: the defaults)")
     ap.add_argument("--digest", metavar="DIR",
@@ -440,6 +490,9 @@ def main():
     if args.cde_only:
         print(json.dumps({name: cde_bench(name, steps, flow, rows, args.chunk)
                           for name, steps, flow, rows in cde_leg}), flush=True)
+        return
+    if args.adjoint_only:
+        print(json.dumps(adjoint_bench()), flush=True)
         return
 
     form = "tune" if args.tune else ({"fuse": args.fuse, "rows": args.rows} if args.fuse else None)
@@ -492,6 +545,8 @@ def main():
             for name, steps, flow, rows in cde_leg}
         if not args.no_batch:
             out["batched_64_instances"] = batch_bench()
+        log("adjoint: chamber-misfit gradient over 20000 steps, 2048x1024 FP32")
+        out["adjoint_gradient"] = adjoint_bench()
     if not args.no_extra and not args.no_experiments:
         from paper_1307_4703_amd import experiments
         log("step-profile test (Table 3), four cases, FP32")

@@ -5,18 +5,14 @@
 
 namespace gg {
 
-// Gathers g(x,t) and u(x,t) of the lattice state into a tape slot of 7
-// planes (g0..g4, ux, uy) in the compute type.
-hipError_t launch_tape(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
-                       int tx_shift, void *tape, hipStream_t st);
-
 // lam = weight (C - target) at every fluid node; per-tile loss partials.
 hipError_t launch_seed(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                        int tx_shift, const double *weight, const double *target, void *lam,
                        double *partial, hipStream_t st);
 
 // One adjoint step for step t: lam_in = dL/dg(t+1) -> lam_out = dL/dg(t),
-// with the tape of step t; accumulates dL/dR on the box, dL/dC_in per
+// with the tape of step t (written by launch_step_tape: 7 planes g0..g4,
+// ux, uy in the compute type); accumulates dL/dR on the box, dL/dC_in per
 // segment and per-tile dL/domega_g partials.
 hipError_t launch_adjoint(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                           int tx_shift, int64_t t, const void *lam_in, void *lam_out,

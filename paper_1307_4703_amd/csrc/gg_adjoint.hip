@@ -101,34 +101,6 @@ __device__ __forceinline__ void gather_state(CDesc &L, uint32_t node, uint8_t lc
   }
 }
 
-// Tape: dg_i(x,t) = g_i - w_i C_s and u(x,t) of the current state, in the
-// compute type.
-template <class S>
-__global__ void __launch_bounds__(256)
-    k_tape(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles, int n_tiles,
-           int tx_shift, void *__restrict__ tape) {
-  using T = typename Pop<S>::T;
-  const int tile = blockIdx.x;
-  if (tile >= n_tiles) return;
-  const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
-  CDesc &L = *(CDesc *)desc;
-  const int x = tl.x0 + (int)(threadIdx.x & ((1 << tx_shift) - 1));
-  const int y = tl.y0 + (int)(threadIdx.x >> tx_shift);
-  if (x >= L.nx || y >= L.ny) return;
-  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
-  const uint8_t lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
-  if (lc == NOT_FLUID) return;
-  T f[9], g[5];
-  gather_state<S>(L, node, lc, x, y, f, g);
-  const T rho = (T)L.rho0 + (f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8]);
-  const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-  const T jy = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
-  const T inv = T(1) / rho;
-  for (int i = 0; i < 5; ++i) *atw<T>(tape, L.plane, i, node) = g[i];
-  *atw<T>(tape, L.plane, 5, node) = jx * inv;
-  *atw<T>(tape, L.plane, 6, node) = jy * inv;
-}
-
 // Seed: lam(x,i) = weight(x) (C(x) - target(x)) at the final state; the loss
 // 1/2 sum weight (C - target)^2 goes into per-work-group partial sums.
 template <class S>
@@ -300,17 +272,6 @@ __global__ void __launch_bounds__(256)
 }
 
 }  // namespace
-
-hipError_t launch_tape(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
-                       int tx_shift, void *tape, hipStream_t st) {
-  if (n_tiles <= 0) return hipSuccess;
-  switch (s) {
-    case GG_F64: k_tape<double><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, tape); break;
-    case GG_F32: k_tape<float><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, tape); break;
-    case GG_F16_SHIFTED: k_tape<__half><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, tape); break;
-  }
-  return hipGetLastError();
-}
 
 hipError_t launch_seed(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                        int tx_shift, const double *weight, const double *target, void *lam,

@@ -12,6 +12,11 @@ namespace gg {
 // which then stride through the tiles.
 hipError_t launch_step(gg_storage s, int block, bool odd, const LatDesc *d, const Tile *tiles,
                        int n_tiles, int tx_shift, int dt, hipStream_t st, int persist = 0);
+// launch_step that also writes, for each fluid node, the state before the
+// step to `tape` (compute type, plane stride of the populations: dg_0..4,
+// u_x, u_y), the adjoint's tape.
+hipError_t launch_step_tape(gg_storage s, int block, bool odd, const LatDesc *d, const Tile *tiles,
+                            int n_tiles, int tx_shift, int dt, void *tape, hipStream_t st);
 
 // Two steps in one pass (t even, natural order in): strips of 62 columns x
 // (flags >> 8) rows, four per 256-thread work-group; seg selects the kernel

@@ -35,11 +35,14 @@ namespace gg {
 #else
 #define GG_STEP_ATTR
 #endif
-// One tile of the fused step (every lane of the work-group calls it).
-template <class S, bool ODD>
+// One tile of the fused step (every lane of the work-group calls it). TAPE:
+// also write the node's state before the step to `tape` for the adjoint,
+// planes of the compute type with the populations' plane stride: dg_0..4,
+// then u_x, u_y (from the same moments as the collision).
+template <class S, bool ODD, bool TAPE = false>
 __device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
                                           const Tile *__restrict__ tiles, int tile,
-                                          int tx_shift, int dt) {
+                                          int tx_shift, int dt, void *tape = nullptr) {
   using P = Pop<S>;
   using T = typename P::T;
   using W = typename P::W;
@@ -64,6 +67,15 @@ __device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
     const Neigh nb(L, x, y);
     T f[9], g[5];  // deviations from rest, df_i and dg_i
     load_state<S, ODD>(pl, node, lc, nb, f, g);
+    if (TAPE) {
+      T rho, drho, ux, uy;
+      node_velocity<T>(L, f, rho, drho, ux, uy);
+      const Planes<T> tp(tape, L.plane);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) *tp.at(i, node) = g[i];
+      *tp.at(5, node) = ux;
+      *tp.at(6, node) = uy;
+    }
 
     T pf[9], pg[5], in_f[9], in_g[5];
     collide_node<T>(L, x, y, lc, seg_tile, ph, f, g, pf, pg, in_f, in_g, fx, true);
@@ -111,6 +123,18 @@ __global__ void __launch_bounds__(BS) GG_STEP_ATTR
   for (int b = blockIdx.x; b < nb; b += gridDim.x) {
     const int tile = (b & 7) * per_xcd + (b >> 3);
     if (tile < n_tiles) step_tile<S, ODD>(descs, tiles, tile, tx_shift, dt);
+  }
+}
+
+// The fused step that also writes the tape of the adjoint (see step_tile).
+template <class S, int BS, bool ODD>
+__global__ void __launch_bounds__(BS)
+    k_step_tape(const LatDesc *__restrict__ descs, const Tile *__restrict__ tiles, int n_tiles,
+                int per_xcd, int tx_shift, int dt, void *__restrict__ tape) {
+  const int nb = 8 * per_xcd;
+  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int tile = (b & 7) * per_xcd + (b >> 3);
+    if (tile < n_tiles) step_tile<S, ODD, true>(descs, tiles, tile, tx_shift, dt, tape);
   }
 }
 
@@ -368,6 +392,36 @@ hipError_t launch_step(gg_storage s, int block, bool odd, const LatDesc *d, cons
     case GG_F32: return launch_step_s<float>(block, odd, d, tiles, n_tiles, tx_shift, dt, persist, st);
     case GG_F16_SHIFTED: return launch_step_s<__half>(block, odd, d, tiles, n_tiles, tx_shift, dt, persist, st);
   }
+  return hipErrorInvalidValue;
+}
+
+template <class S, bool ODD>
+static hipError_t launch_step_tape_p(int bs, const LatDesc *d, const Tile *tiles, int n_tiles,
+                                     int tx_shift, int dt, void *tape, hipStream_t st) {
+  const int per_xcd = (n_tiles + 7) / 8;
+  const dim3 grid(8 * per_xcd);
+  switch (bs) {
+    case 64: k_step_tape<S, 64, ODD><<<grid, 64, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt, tape); break;
+    case 128: k_step_tape<S, 128, ODD><<<grid, 128, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt, tape); break;
+    case 256: k_step_tape<S, 256, ODD><<<grid, 256, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt, tape); break;
+    case 512: k_step_tape<S, 512, ODD><<<grid, 512, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt, tape); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_step_tape(gg_storage s, int block, bool odd, const LatDesc *d, const Tile *tiles,
+                            int n_tiles, int tx_shift, int dt, void *tape, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+#define GG_TAPE_S(TYPE)                                                                     \
+  return odd ? launch_step_tape_p<TYPE, true>(block, d, tiles, n_tiles, tx_shift, dt, tape, st) \
+             : launch_step_tape_p<TYPE, false>(block, d, tiles, n_tiles, tx_shift, dt, tape, st)
+  switch (s) {
+    case GG_F64: GG_TAPE_S(double);
+    case GG_F32: GG_TAPE_S(float);
+    case GG_F16_SHIFTED: GG_TAPE_S(__half);
+  }
+#undef GG_TAPE_S
   return hipErrorInvalidValue;
 }
 

@@ -1193,13 +1193,10 @@ gg_status gg_adjoint(gg_lattice *L, int64_t n, int64_t s, const double *weight,
                           hipMemcpyDeviceToDevice, L->stream));
     GG_HIP(hipMemcpyAsync(scr_t, &tk, sizeof(tk), hipMemcpyHostToDevice, L->stream));
     GG_HIP(hipStreamSynchronize(L->stream));  // tk lives on the host stack
-    for (int64_t j = 0; j < nk; ++j) {
-      GG_HIP(launch_tape(L->storage, sd, L->d_aux_tiles, L->n_aux_tiles, 6, (char *)tape + (size_t)j * slot,
-                         L->stream));
-      GG_HIP(launch_step(L->storage, block, ((tk + j) & 1) != 0, sd, L->d_tiles, L->n_tiles, txs, 0,
-                         L->stream));
-      GG_HIP(launch_advance(sd, 1, 1, L->stream));
-    }
+    // (the recomputation's counter stays at tk: step j runs with dt = j)
+    for (int64_t j = 0; j < nk; ++j)
+      GG_HIP(launch_step_tape(L->storage, block, ((tk + j) & 1) != 0, sd, L->d_tiles, L->n_tiles,
+                              txs, (int)j, (char *)tape + (size_t)j * slot, L->stream));
     for (int64_t j = nk - 1; j >= 0; --j) {
       GG_HIP(launch_adjoint(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6, tk + j, lam[cur],
                             lam[1 - cur], (const char *)tape + (size_t)j * slot,
