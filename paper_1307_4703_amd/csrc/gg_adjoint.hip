@@ -162,23 +162,32 @@ __global__ void __launch_bounds__(256)
     using T = double;
     const T wga = (T)(TT)L.wg_axis;  // the forward step's weights
     const T wg[5] = {(T)(TT(1) - TT(4) * (TT)L.wg_axis), wga, wga, wga, wga};
+    // every load is issued up front: the tape, lambda here, and lambda of
+    // the four neighbours (addressable in the padded planes whatever they
+    // hold; only the fluid ones are used)
+    T g[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) g[i] = (T)*at<TT>(tape, L.plane, i, node);
+    const T ux = (T)*at<TT>(tape, L.plane, 5, node), uy = (T)*at<TT>(tape, L.plane, 6, node);
     T lx[5];
+#pragma unroll
     for (int i = 0; i < 5; ++i) lx[i] = *at<T>(lam_in, L.plane, i, node);
     const int xm = (x == 0 && L.periodic_x) ? L.nx - 1 : x - 1;
     const int xp = (x == L.nx - 1 && L.periodic_x) ? 0 : x + 1;
     const int ym = (y == 0 && L.periodic_y) ? L.ny - 1 : y - 1;
     const int yp = (y == L.ny - 1 && L.periodic_y) ? 0 : y + 1;
+    T ln[5];
+#pragma unroll
+    for (int j = 1; j < 5; ++j) {
+      const int xx = EX[j] > 0 ? xp : (EX[j] < 0 ? xm : x);
+      const int yy = EY[j] > 0 ? yp : (EY[j] < 0 ? ym : y);
+      ln[j] = *at<T>(lam_in, L.plane, j, (uint32_t)(L.node0 + yy * L.pitch + xx));
+    }
     T ls[5];
     ls[0] = lx[0];
 #pragma unroll
-    for (int j = 1; j < 5; ++j) {
-      ls[j] = T(0);
-      if (!((lc >> (j - 1)) & 1)) {  // x + e_j fluid: g*_j(x) streams there
-        const int xx = EX[j] > 0 ? xp : (EX[j] < 0 ? xm : x);
-        const int yy = EY[j] > 0 ? yp : (EY[j] < 0 ? ym : y);
-        ls[j] = *at<T>(lam_in, L.plane, j, (uint32_t)(L.node0 + yy * L.pitch + xx));
-      }
-    }
+    for (int j = 1; j < 5; ++j)  // x + e_j fluid: g*_j(x) streams there
+      ls[j] = ((lc >> (j - 1)) & 1) ? T(0) : ln[j];
     if (lc != 0) {
 #pragma unroll
       for (int j = 1; j < 5; ++j) {
@@ -225,9 +234,6 @@ __global__ void __launch_bounds__(256)
       }
     }
     // transposed collision with the taped state of step t
-    T g[5];
-    for (int i = 0; i < 5; ++i) g[i] = (T)*at<TT>(tape, L.plane, i, node);
-    const T ux = (T)*at<TT>(tape, L.plane, 5, node), uy = (T)*at<TT>(tape, L.plane, 6, node);
     const T dC = g[0] + g[1] + g[2] + g[3] + g[4];  // taped deviations
     const T C = (T)L.c_shift + dC;
     const T om = (T)L.omega_g, kd = (T)L.k_decay, ics = (T)L.inv_cs2g;
