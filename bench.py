@@ -45,11 +45,13 @@ def workload(name):
     table = {
         "gg2048_f32": lambda: W.gradient_generator(storage="f32"),
         "gg2048_f16": lambda: W.gradient_generator(storage="f16"),
+        "gg2048_f64": lambda: W.gradient_generator(storage="f64"),
         "gg8192_f16": lambda: W.gradient_generator(scale=4.0, storage="f16"),
         "gg8192_f16_pe2000": lambda: W.gradient_generator(scale=4.0, storage="f16", peclet=2000.0),
         "gg8192_f32": lambda: W.gradient_generator(scale=4.0, storage="f32"),
         "allfluid8192_f32": lambda: W.all_fluid_channel(storage="f32"),
         "allfluid8192_f16": lambda: W.all_fluid_channel(storage="f16"),
+        "allfluid8192_f64": lambda: W.all_fluid_channel(storage="f64"),
         # one GPU's slab of the all-fluid 8192 x 4096 lattice split over 8
         # GPUs along y (its two y faces walls here, halo rows there)
         "shard8192x512_f32": lambda: W.all_fluid_channel(ny=512, storage="f32"),
@@ -64,7 +66,8 @@ def workload(name):
 # autotuner picks it on this GPU; --tune re-runs the autotuner
 FORMS = {"gg2048_f32": (4, 6), "gg2048_f16": (4, 6), "gg8192_f16": (3, 6),
          "gg8192_f16_pe2000": (3, 6), "gg8192_f32": (3, 6), "allfluid8192_f32": (3, 14),
-         "allfluid8192_f16": (3, 6), "shard8192x512_f32": (3, 6), "straight_f64": (4, 6)}
+         "allfluid8192_f16": (3, 6), "shard8192x512_f32": (3, 6),
+         "allfluid8192_f64": (3, 14), "gg2048_f64": (3, 14), "straight_f64": (4, 6)}
 
 
 def kernel_hash():
@@ -530,7 +533,8 @@ def main():
         log(f"plain copy: {out['copy_bandwidth_gbs']} GB/s")
         extra = {}
         for name, steps in (("allfluid8192_f32", 1000), ("allfluid8192_f16", 1000),
-                            ("gg8192_f16", 2000), ("shard8192x512_f32", 2000)):
+                            ("gg8192_f16", 2000), ("shard8192x512_f32", 2000),
+                            ("allfluid8192_f64", 400), ("gg2048_f64", 4000)):
             if name == args.workload:
                 continue
             r2 = time_lattice(name, steps, 100, tile, args.chunk, form)
