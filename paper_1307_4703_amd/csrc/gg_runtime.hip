@@ -821,8 +821,10 @@ static hipError_t launch_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t
                            st, (k & 1) == 0);
     }
   } else {
-    // (pressure boundaries: one step at a time, each followed by the
-    // rescaling of the boundary nodes)
+    // single steps: with the paper's walls, the values of step t the wall
+    // rule needs are saved before each step and the wall links written
+    // after it; with pressure segments the boundary nodes are rescaled
+    // after each step
     const int block = L->tile_x * L->tile_y;
     const int txs = ilog2(L->tile_x);
     for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt) {
