@@ -147,6 +147,27 @@ gg_status gg_create(const uint8_t *mask, int32_t nx, int32_t ny,
                     const gg_params *params, gg_storage storage,
                     void *hip_stream, gg_lattice **out);
 
+/* Device memory from the caller (e.g. a framework's caching allocator):
+ * alloc(bytes, ctx) returns device memory of the lattice's GPU, or NULL
+ * when it cannot (the call then fails with GG_ERR_OOM); release(ptr, ctx)
+ * takes back what alloc gave. The library calls release only once the
+ * device is idle, so queued work never touches memory handed back. */
+typedef struct gg_alloc {
+  void *(*alloc)(size_t bytes, void *ctx);
+  void (*release)(void *ptr, void *ctx);
+  void *ctx;
+} gg_alloc;
+
+/* gg_create with every device buffer of the lattice (populations, second
+ * plane set, lists, velocity fields, read-back staging, the adjoint's
+ * checkpoints and tape) taken from `alloc` (NULL: hipMalloc, as gg_create).
+ * The allocator must stay valid until gg_destroy returns. Batches allocate
+ * their own small lists with hipMalloc. Errors as gg_create, and GG_ERR_ARG
+ * for an allocator without both functions. */
+gg_status gg_create_ex(const uint8_t *mask, int32_t nx, int32_t ny,
+                       const gg_params *params, gg_storage storage,
+                       void *hip_stream, const gg_alloc *alloc, gg_lattice **out);
+
 /* Configure segment `id` (a mask value >= GG_FIRST_SEGMENT). (nrm_x, nrm_y)
  * is the outward unit normal, along an axis, pointing from the fluid into
  * the ghost line; every ghost cell of the segment must have a fluid cell

@@ -38,6 +38,14 @@ class gg_params(ctypes.Structure):
                 ("periodic_x", ctypes.c_int32), ("periodic_y", ctypes.c_int32)]
 
 
+GG_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+GG_RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class gg_alloc(ctypes.Structure):
+    _fields_ = [("alloc", GG_ALLOC_FN), ("release", GG_RELEASE_FN), ("ctx", ctypes.c_void_p)]
+
+
 class gg_phase(ctypes.Structure):
     _fields_ = [("duration", ctypes.c_int64), ("open_mask", ctypes.c_uint32),
                 ("c_in_set", ctypes.c_uint32),
@@ -77,6 +85,8 @@ I64 = ctypes.c_int64
 D = ctypes.c_double
 SIGS = {
     "gg_create": [P, I32, I32, ctypes.POINTER(gg_params), ctypes.c_int, P, ctypes.POINTER(P)],
+    "gg_create_ex": [P, I32, I32, ctypes.POINTER(gg_params), ctypes.c_int, P,
+                     ctypes.POINTER(gg_alloc), ctypes.POINTER(P)],
     "gg_set_segment": [P, I32, ctypes.c_int, I32, I32, D, D],
     "gg_set_pressure_segment": [P, I32, I32, I32, D, D, I32],
     "gg_set_schedule": [P, ctypes.POINTER(gg_phase), I32, I64],

@@ -17,6 +17,8 @@ struct SegHost {
 };
 
 struct gg_lattice {
+  gg_alloc alloc{};         // the caller's device allocator (has_alloc)
+  bool has_alloc = false;
   int32_t nx = 0, ny = 0, pitch = 0, node0 = 0;
   int64_t plane_elems = 0;  // addressable elements of one plane (with padding)
   int64_t plane = 0;        // stride between planes

@@ -46,6 +46,24 @@ int ilog2(int v) {
   return r;
 }
 
+// Device memory of a lattice: from the caller's allocator when one was
+// given to gg_create_ex, else hipMalloc / hipFree. Memory goes back to the
+// caller's allocator only after the device is idle (as hipFree waits), so
+// no queued kernel still uses it when the allocator hands it out again.
+hipError_t dev_alloc(const gg_lattice *L, void **p, size_t bytes) {
+  if (!L->has_alloc) return hipMalloc(p, bytes);
+  *p = bytes ? L->alloc.alloc(bytes, L->alloc.ctx) : nullptr;
+  return (*p || !bytes) ? hipSuccess : hipErrorOutOfMemory;
+}
+
+hipError_t dev_free(const gg_lattice *L, void *p) {
+  if (!p) return hipSuccess;
+  if (!L->has_alloc) return hipFree(p);
+  const hipError_t e = hipDeviceSynchronize();
+  L->alloc.release(p, L->alloc.ctx);
+  return e;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -72,7 +90,7 @@ void gg_free_device(gg_lattice *L) {
                   L->d_seg_strips, L->d_partial, L->d_ufield, L->d_cde_tiles, L->d_press,
                   L->d_wall, L->d_wall_links, L->d_wall_save};
   for (void *p : ptrs)
-    if (p) (void)hipFree(p);
+    if (p) (void)dev_free(L, p);
   if (L->cap_stream) (void)hipStreamDestroy(L->cap_stream);
   if (L->side) (void)hipStreamDestroy(L->side);
   if (L->ev_fork) (void)hipEventDestroy(L->ev_fork);
@@ -235,26 +253,26 @@ static void build_strips(const gg_lattice *L, int h, int inst, bool split, std::
 gg_status gg_rebuild_tiles(gg_lattice *L) {
   std::vector<Tile> t;
   build_tiles(L, L->tile_x, L->tile_y, 0, t);
-  if (L->d_tiles) (void)hipFree(L->d_tiles);
+  if (L->d_tiles) (void)dev_free(L, L->d_tiles);
   L->d_tiles = nullptr;
   L->n_tiles = (int)t.size();
   if (!t.empty()) {
-    GG_HIP(hipMalloc(&L->d_tiles, t.size() * sizeof(Tile)));
+    GG_HIP(dev_alloc(L, (void **)&L->d_tiles, t.size() * sizeof(Tile)));
     GG_HIP(hipMemcpy(L->d_tiles, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice));
   }
   std::vector<Tile> sv, ss;
   build_strips(L, L->strip_h, 0, L->fuse != 4, sv, ss);
-  if (L->d_strips) (void)hipFree(L->d_strips);
-  if (L->d_seg_strips) (void)hipFree(L->d_seg_strips);
+  if (L->d_strips) (void)dev_free(L, L->d_strips);
+  if (L->d_seg_strips) (void)dev_free(L, L->d_seg_strips);
   L->d_strips = L->d_seg_strips = nullptr;
   L->n_strips = (int)sv.size();
   L->n_seg_strips = (int)ss.size();
   if (!sv.empty()) {
-    GG_HIP(hipMalloc(&L->d_strips, sv.size() * sizeof(Tile)));
+    GG_HIP(dev_alloc(L, (void **)&L->d_strips, sv.size() * sizeof(Tile)));
     GG_HIP(hipMemcpy(L->d_strips, sv.data(), sv.size() * sizeof(Tile), hipMemcpyHostToDevice));
   }
   if (!ss.empty()) {
-    GG_HIP(hipMalloc(&L->d_seg_strips, ss.size() * sizeof(Tile)));
+    GG_HIP(dev_alloc(L, (void **)&L->d_seg_strips, ss.size() * sizeof(Tile)));
     GG_HIP(hipMemcpy(L->d_seg_strips, ss.data(), ss.size() * sizeof(Tile), hipMemcpyHostToDevice));
   }
   if (L->graph_exec) (void)hipGraphExecDestroy(L->graph_exec);
@@ -281,7 +299,15 @@ const char *gg_last_error(void) { return g_err.c_str(); }
 
 gg_status gg_create(const uint8_t *mask, int32_t nx, int32_t ny, const gg_params *params,
                     gg_storage storage, void *hip_stream, gg_lattice **out) {
+  return gg_create_ex(mask, nx, ny, params, storage, hip_stream, nullptr, out);
+}
+
+gg_status gg_create_ex(const uint8_t *mask, int32_t nx, int32_t ny, const gg_params *params,
+                       gg_storage storage, void *hip_stream, const gg_alloc *allocator,
+                       gg_lattice **out) {
   if (!out) return fail(GG_ERR_ARG, "out is NULL");
+  if (allocator && (!allocator->alloc || !allocator->release))
+    return fail(GG_ERR_ARG, "an allocator needs both its alloc and its release function");
   *out = nullptr;
   if (!mask) return fail(GG_ERR_ARG, "mask is NULL");
   if (nx < 1 || ny < 1) return fail(GG_ERR_ARG, "lattice dimensions must be positive");
@@ -298,6 +324,10 @@ gg_status gg_create(const uint8_t *mask, int32_t nx, int32_t ny, const gg_params
     return fail(GG_ERR_ARG, "lattice too large: one population plane must stay below 4 GiB");
 
   gg_lattice *L = new gg_lattice();
+  if (allocator) {
+    L->alloc = *allocator;
+    L->has_alloc = true;
+  }
   L->nx = nx;
   L->ny = ny;
   L->pitch = pitch;
@@ -390,8 +420,8 @@ gg_status gg_create(const uint8_t *mask, int32_t nx, int32_t ny, const gg_params
     }
 
   auto alloc = [&](void **p, size_t bytes) -> gg_status {
-    hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) return fail(GG_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    hipError_t e = dev_alloc(L, p, bytes);
+    if (e != hipSuccess) return fail(GG_ERR_OOM, std::string("device allocation: ") + hipGetErrorString(e));
     return GG_OK;
   };
   const size_t pop_bytes = (size_t)NPOP * L->plane * esize;
@@ -595,11 +625,11 @@ static gg_status pressure_nodes(gg_lattice *L) {
           xy.push_back((int32_t)cand);
         }
       }
-  if (L->d_press) GG_HIP(hipFree(L->d_press));
+  if (L->d_press) GG_HIP(dev_free(L, L->d_press));
   L->d_press = nullptr;
   L->n_press = (int)(xy.size() / 3);
   if (!xy.empty()) {
-    GG_HIP(hipMalloc(&L->d_press, xy.size() * sizeof(int32_t)));
+    GG_HIP(dev_alloc(L, (void **)&L->d_press, xy.size() * sizeof(int32_t)));
     GG_HIP(hipMemcpy(L->d_press, xy.data(), xy.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   }
   L->press_dirty = false;
@@ -630,7 +660,7 @@ gg_status gg_set_schedule(gg_lattice *L, const gg_phase *phases, int32_t n, int6
 
 gg_status gg_set_source(gg_lattice *L, const double *R, gg_where where) {
   if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
-  if (L->d_R) (void)hipFree(L->d_R);
+  if (L->d_R) (void)dev_free(L, L->d_R);
   L->d_R = nullptr;
   L->r_box[0] = L->r_box[1] = L->r_box[2] = L->r_box[3] = 0;
   if (R) {
@@ -657,7 +687,7 @@ gg_status gg_set_source(gg_lattice *L, const double *R, gg_where where) {
       std::vector<double> patch((size_t)w * hh);
       for (int y = 0; y < hh; ++y)
         for (int x = 0; x < w; ++x) patch[(size_t)y * w + x] = h[(size_t)(y0 + y) * L->nx + x0 + x];
-      GG_HIP(hipMalloc(&L->d_R, patch.size() * sizeof(double)));
+      GG_HIP(dev_alloc(L, (void **)&L->d_R, patch.size() * sizeof(double)));
       GG_HIP(hipMemcpy(L->d_R, patch.data(), patch.size() * sizeof(double), hipMemcpyHostToDevice));
       L->r_box[0] = x0; L->r_box[1] = y0; L->r_box[2] = w; L->r_box[3] = hh;
     }
@@ -667,13 +697,13 @@ gg_status gg_set_source(gg_lattice *L, const double *R, gg_where where) {
 
 gg_status gg_set_region(gg_lattice *L, const uint8_t *region) {
   if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
-  if (L->d_region) (void)hipFree(L->d_region);
+  if (L->d_region) (void)dev_free(L, L->d_region);
   L->d_region = nullptr;
   if (region) {
     std::vector<uint8_t> r((size_t)L->plane_elems, 0);
     for (int y = 0; y < L->ny; ++y)
       for (int x = 0; x < L->nx; ++x) r[L->nid(x, y)] = region[(size_t)y * L->nx + x] ? 1 : 0;
-    GG_HIP(hipMalloc(&L->d_region, r.size()));
+    GG_HIP(dev_alloc(L, (void **)&L->d_region, r.size()));
     GG_HIP(hipMemcpy(L->d_region, r.data(), r.size(), hipMemcpyHostToDevice));
   }
   return gg_upload_desc(L);
@@ -689,7 +719,7 @@ gg_status gg_init(gg_lattice *L, const double *rho, const double *ux, const doub
   if (where == GG_HOST) {
     for (int q = 0; q < 4 && st == GG_OK; ++q) {
       if (!src[q]) continue;
-      if (hipMalloc(&dev[q], n * sizeof(double)) != hipSuccess) {
+      if (dev_alloc(L, (void **)&dev[q], n * sizeof(double)) != hipSuccess) {
         st = fail(GG_ERR_OOM, "hipMalloc of an initial field failed");
         break;
       }
@@ -709,7 +739,7 @@ gg_status gg_init(gg_lattice *L, const double *rho, const double *ux, const doub
   }
   if (where == GG_HOST)
     for (int q = 0; q < 4; ++q)
-      if (dev[q]) (void)hipFree(dev[q]);
+      if (dev[q]) (void)dev_free(L, dev[q]);
   if (st == GG_OK) L->t = 0;
   return st;
 }
@@ -757,22 +787,22 @@ static gg_status wall_nodes(gg_lattice *L) {
             links.push_back(k * 8 + (i - 1));
           }
       }
-  if (L->d_wall) GG_HIP(hipFree(L->d_wall));
-  if (L->d_wall_links) GG_HIP(hipFree(L->d_wall_links));
-  if (L->d_wall_save) GG_HIP(hipFree(L->d_wall_save));
+  if (L->d_wall) GG_HIP(dev_free(L, L->d_wall));
+  if (L->d_wall_links) GG_HIP(dev_free(L, L->d_wall_links));
+  if (L->d_wall_save) GG_HIP(dev_free(L, L->d_wall_save));
   L->d_wall = nullptr;
   L->d_wall_links = nullptr;
   L->d_wall_save = nullptr;
   L->n_wall = (int)(xy.size() / 2);
   L->n_wall_links = (int)(links.size() / 3);
   if (!xy.empty()) {
-    GG_HIP(hipMalloc(&L->d_wall, xy.size() * sizeof(int32_t)));
+    GG_HIP(dev_alloc(L, (void **)&L->d_wall, xy.size() * sizeof(int32_t)));
     GG_HIP(hipMemcpy(L->d_wall, xy.data(), xy.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    GG_HIP(hipMalloc(&L->d_wall_links, links.size() * sizeof(int32_t)));
+    GG_HIP(dev_alloc(L, (void **)&L->d_wall_links, links.size() * sizeof(int32_t)));
     GG_HIP(hipMemcpy(L->d_wall_links, links.data(), links.size() * sizeof(int32_t),
                      hipMemcpyHostToDevice));
     const size_t tb = L->storage == GG_F64 ? 8 : 4;
-    GG_HIP(hipMalloc(&L->d_wall_save, (size_t)L->n_wall * 16 * tb));
+    GG_HIP(dev_alloc(L, (void **)&L->d_wall_save, (size_t)L->n_wall * 16 * tb));
   }
   L->wall_dirty = false;
   if (L->graph_exec) (void)hipGraphExecDestroy(L->graph_exec);
@@ -905,7 +935,7 @@ static gg_status gg_read_impl(gg_lattice *L, double *rho, double *ux, double *uy
   for (int q = 0; q < 6; ++q) {
     if (!user[q]) continue;
     if (where == GG_HOST) {
-      if (hipMalloc(&dev[q], len[q] * sizeof(double)) != hipSuccess) {
+      if (dev_alloc(L, (void **)&dev[q], len[q] * sizeof(double)) != hipSuccess) {
         st = fail(GG_ERR_OOM, "hipMalloc of a read-back buffer failed");
         break;
       }
@@ -928,7 +958,7 @@ static gg_status gg_read_impl(gg_lattice *L, double *rho, double *ux, double *uy
   }
   if (where == GG_HOST)
     for (int q = 0; q < 6; ++q)
-      if (dev[q]) (void)hipFree(dev[q]);
+      if (dev[q]) (void)dev_free(L, dev[q]);
   return st;
 }
 
@@ -943,7 +973,7 @@ gg_status gg_read_populations(gg_lattice *L, double *f, double *g, gg_where wher
 gg_status gg_diagnostics(gg_lattice *L, gg_diag *out) {
   if (!L || !out) return fail(GG_ERR_ARG, "NULL argument");
   if (!L->d_partial && L->n_aux_tiles > 0) {
-    if (hipMalloc(&L->d_partial, (size_t)6 * L->n_aux_tiles * sizeof(double)) != hipSuccess) {
+    if (dev_alloc(L, (void **)&L->d_partial, (size_t)6 * L->n_aux_tiles * sizeof(double)) != hipSuccess) {
       L->d_partial = nullptr;
       return fail(GG_ERR_OOM, "diagnostics partials");
     }
@@ -1070,7 +1100,7 @@ gg_status gg_set_two_step(gg_lattice *L, int32_t fuse, int32_t strip_h) {
   GG_HIP(hipStreamSynchronize(L->stream));
   if (fuse >= 2 && !L->d_pop_b) {
     const size_t pop_bytes = (size_t)NPOP * L->plane * L->esize;
-    hipError_t e = hipMalloc(&L->d_pop_b, pop_bytes);
+    hipError_t e = dev_alloc(L, (void **)&L->d_pop_b, pop_bytes);
     if (e != hipSuccess) {
       L->d_pop_b = nullptr;
       return fail(GG_ERR_OOM, std::string("second plane set: ") + hipGetErrorString(e));
@@ -1078,7 +1108,7 @@ gg_status gg_set_two_step(gg_lattice *L, int32_t fuse, int32_t strip_h) {
     GG_HIP(hipMemset(L->d_pop_b, 0, pop_bytes));
   }
   if (fuse == 1 && L->d_pop_b) {
-    GG_HIP(hipFree(L->d_pop_b));
+    GG_HIP(dev_free(L, L->d_pop_b));
     L->d_pop_b = nullptr;
   }
   L->fuse = fuse;
@@ -1101,14 +1131,16 @@ gg_status gg_info(const gg_lattice *L, int64_t *n_fluid, int64_t *n_tiles, int64
 
 // Device buffers of one adjoint run, freed on every exit path.
 struct AdjointBuffers {
+  const gg_lattice *L;
   std::vector<void *> ptrs;
+  explicit AdjointBuffers(const gg_lattice *lat) : L(lat) {}
   ~AdjointBuffers() {
     for (void *p : ptrs)
-      if (p) (void)hipFree(p);
+      if (p) (void)dev_free(L, p);
   }
   hipError_t alloc(void **p, size_t bytes) {
     *p = nullptr;
-    hipError_t e = hipMalloc(p, bytes);
+    hipError_t e = dev_alloc(L, p, bytes);
     if (e == hipSuccess) ptrs.push_back(*p);
     return e;
   }
@@ -1141,7 +1173,7 @@ gg_status gg_adjoint(gg_lattice *L, int64_t n, int64_t s, const double *weight,
   const size_t nxy = (size_t)L->nx * L->ny;
   const int na = std::max(L->n_aux_tiles, 1);
 
-  AdjointBuffers B;
+  AdjointBuffers B(L);
   void *ckpt, *scr_pop, *scr_desc, *scr_t, *scr_flux, *tape, *lam0, *lam1, *wdev, *tdev, *dRdev,
       *dcin, *pw, *pl;
   const size_t need = (size_t)K * pop_bytes + pop_bytes + (size_t)s * slot + 2 * lam_bytes;
@@ -1636,16 +1668,16 @@ static gg_status grow_fields(gg_lattice *L, int n) {
   if (n <= L->n_ufield) return GG_OK;
   const size_t slot_bytes = 2 * (size_t)L->plane * field_esize(L);
   void *p = nullptr;
-  hipError_t e = hipMalloc(&p, (size_t)n * slot_bytes);
+  hipError_t e = dev_alloc(L, &p, (size_t)n * slot_bytes);
   if (e != hipSuccess) return fail(GG_ERR_OOM, std::string("velocity fields: ") + hipGetErrorString(e));
   e = hipMemset(p, 0, (size_t)n * slot_bytes);
   if (e == hipSuccess && L->d_ufield)
     e = hipMemcpy(p, L->d_ufield, (size_t)L->n_ufield * slot_bytes, hipMemcpyDeviceToDevice);
   if (e != hipSuccess) {
-    (void)hipFree(p);
+    (void)dev_free(L, p);
     return fail(GG_ERR_HIP, std::string("velocity fields: ") + hipGetErrorString(e));
   }
-  if (L->d_ufield) GG_HIP(hipFree(L->d_ufield));
+  if (L->d_ufield) GG_HIP(dev_free(L, L->d_ufield));
   L->d_ufield = p;
   L->n_ufield = n;
   return gg_upload_desc(L);
@@ -1679,7 +1711,7 @@ gg_status gg_set_velocity_field(gg_lattice *L, int32_t slot, const double *ux, c
     }
     dev[0] = dev[1] = nullptr;
     for (int q = 0; q < 2 && st == GG_OK; ++q) {
-      if (hipMalloc(&dev[q], n * sizeof(double)) != hipSuccess)
+      if (dev_alloc(L, (void **)&dev[q], n * sizeof(double)) != hipSuccess)
         st = fail(GG_ERR_OOM, "hipMalloc of a velocity field failed");
       else if (hipMemcpy(dev[q], q ? uy : ux, n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
         st = fail(GG_ERR_HIP, "copy of a velocity field failed");
@@ -1693,7 +1725,7 @@ gg_status gg_set_velocity_field(gg_lattice *L, int32_t slot, const double *ux, c
   }
   if (where == GG_HOST)
     for (int q = 0; q < 2; ++q)
-      if (dev[q]) (void)hipFree(dev[q]);
+      if (dev[q]) (void)dev_free(L, dev[q]);
   if (st == GG_OK) L->ufield_set |= 1u << slot;
   return st;
 }
@@ -1724,12 +1756,12 @@ static gg_status cde_tiles(gg_lattice *L) {
   if (L->cde_rows == 0 || L->cde_tiles_rows == L->cde_rows) return GG_OK;
   std::vector<Tile> list, unused;
   build_strips(L, L->cde_rows, 0, false, list, unused);
-  if (L->d_cde_tiles) GG_HIP(hipFree(L->d_cde_tiles));
+  if (L->d_cde_tiles) GG_HIP(dev_free(L, L->d_cde_tiles));
   L->d_cde_tiles = nullptr;
   L->n_cde_tiles = (int)list.size();
   L->cde_tiles_rows = 0;
   if (!list.empty()) {
-    GG_HIP(hipMalloc(&L->d_cde_tiles, list.size() * sizeof(Tile)));
+    GG_HIP(dev_alloc(L, (void **)&L->d_cde_tiles, list.size() * sizeof(Tile)));
     GG_HIP(hipMemcpy(L->d_cde_tiles, list.data(), list.size() * sizeof(Tile), hipMemcpyHostToDevice));
   }
   L->cde_tiles_rows = L->cde_rows;

@@ -46,13 +46,37 @@ def make_phases(schedule: Sequence) -> "ctypes.Array":
     return arr
 
 
+def _torch_allocator(stream: Optional[int]) -> "A.gg_alloc":
+    """A gg_alloc whose functions take device memory from PyTorch's caching
+    allocator on the given stream (the structure keeps the callbacks alive
+    and must live as long as the lattice)."""
+    import torch
+    dev = torch.cuda.current_device()
+    st = torch.cuda.ExternalStream(stream) if stream else torch.cuda.default_stream(dev)
+
+    def alloc(nbytes, _ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, st)
+        except RuntimeError:  # out of memory: the library reports GG_ERR_OOM
+            return None
+
+    def release(ptr, _ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return A.gg_alloc(A.GG_ALLOC_FN(alloc), A.GG_RELEASE_FN(release), None)
+
+
 class Lattice:
     """A coupled D2Q9 + D2Q5 lattice on the GPU (see include/gg.h)."""
 
     def __init__(self, mask: np.ndarray, *, tau_f: float, D: float,
                  w0: float = 1.0 / 3.0, rho0: float = 1.0, k_decay: float = 0.0,
                  c_shift: float = 0.0, periodic: Tuple[bool, bool] = (False, False),
-                 storage: str = "f32", stream: Optional[int] = None):
+                 storage: str = "f32", stream: Optional[int] = None,
+                 device_allocator: Optional[str] = None):
+        """device_allocator: None (the library's hipMalloc) or "torch" (every
+        device buffer of the lattice from PyTorch's caching allocator on the
+        lattice's stream, gg_create_ex)."""
         self.mask = np.ascontiguousarray(mask, dtype=np.uint8)
         self.ny, self.nx = self.mask.shape
         self.storage = storage
@@ -62,8 +86,17 @@ class Lattice:
                         int(bool(periodic[1])))
         self.stream = _current_stream() if stream is None else stream
         h = ctypes.c_void_p()
-        A.call("gg_create", _dptr(self.mask), self.nx, self.ny, ctypes.byref(p),
-               A.STORAGE[storage], ctypes.c_void_p(self.stream or 0), ctypes.byref(h))
+        self._alloc = None
+        if device_allocator is None:
+            A.call("gg_create", _dptr(self.mask), self.nx, self.ny, ctypes.byref(p),
+                   A.STORAGE[storage], ctypes.c_void_p(self.stream or 0), ctypes.byref(h))
+        elif device_allocator == "torch":
+            self._alloc = _torch_allocator(self.stream)
+            A.call("gg_create_ex", _dptr(self.mask), self.nx, self.ny, ctypes.byref(p),
+                   A.STORAGE[storage], ctypes.c_void_p(self.stream or 0),
+                   ctypes.byref(self._alloc), ctypes.byref(h))
+        else:
+            raise ValueError(f"unknown device allocator {device_allocator!r}")
         self._h = h
         self.segments: Dict[int, object] = {}
 

@@ -97,3 +97,16 @@ def test_null_arguments_of_the_later_calls():
     assert A.lib().gg_set_cde_launch(None, 14) == A.GG_ERR_ARG
     assert A.lib().gg_set_pressure_segment(None, 2, 1, 0, 1.0, 0.0, 0) == A.GG_ERR_ARG
     assert A.lib().gg_set_two_step(None, 3, 6) == A.GG_ERR_ARG
+
+
+def test_create_ex_rejects_an_incomplete_allocator():
+    """An allocator needs both functions; the check comes before any device
+    work."""
+    mask = np.zeros((8, 8), np.uint8)
+    p = A.gg_params(0.8, 0.02, 1.0 / 3.0, 1.0, 0.0, 0.0, 1, 1)
+    h = ctypes.c_void_p()
+    al = A.gg_alloc(A.GG_ALLOC_FN(lambda n, c: None), A.GG_RELEASE_FN(), None)
+    st = A.lib().gg_create_ex(mask.ctypes.data_as(ctypes.c_void_p), 8, 8, ctypes.byref(p),
+                              A.STORAGE["f32"], None, ctypes.byref(al), ctypes.byref(h))
+    assert st == A.GG_ERR_ARG and not h.value
+    assert b"alloc" in A.lib().gg_last_error()
