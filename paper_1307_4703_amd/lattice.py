@@ -61,7 +61,10 @@ def _torch_allocator(stream: Optional[int]) -> "A.gg_alloc":
             return None
 
     def release(ptr, _ctx):
-        torch.cuda.caching_allocator_delete(ptr)
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:  # the interpreter (and torch) may be shutting down
+            pass
 
     return A.gg_alloc(A.GG_ALLOC_FN(alloc), A.GG_RELEASE_FN(release), None)
 
