@@ -96,7 +96,7 @@ def test_walls_pressure_channel(storage):
     _check(lat, o, wl, storage, f"walls, pressure channel {storage}")
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 def test_walls_periodic_channel(storage):
     """Walls on both sides of a channel periodic along x: the extrapolation
     partner z + e_i and the wall cells wrap across the seam."""
@@ -140,7 +140,7 @@ def test_walls_pressure_gradient_generator():
     _check(lat, o, wl, "f64", "walls, pressure gradient generator f64")
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 def test_walls_compound_only(storage):
     wl = W.gradient_generator(nx=300, ny=150, half_period=9, storage=storage)
     log(f"walls, compound only {storage}")
@@ -158,9 +158,11 @@ def test_walls_compound_only(storage):
     log(f"walls, compound only {storage}: {err:.3e}")
     assert err < TOL[storage]["C"]
     d = lat.diagnostics()
+    # boundary fluxes: sums of stored populations, so relative to their
+    # storage rounding like the fields (FP16: as TOL's 1e-2 for C)
+    rel = {"f64": 1e-10, "f32": 1e-3, "f16": 1e-2}[storage]
     for s in wl.segments:
-        assert d["seg_solute"][s.id - 2] == pytest.approx(
-            o.flux_solute[s.id], rel=1e-10 if storage == "f64" else 1e-3, abs=1e-9)
+        assert d["seg_solute"][s.id - 2] == pytest.approx(o.flux_solute[s.id], rel=rel, abs=1e-9)
 
 
 def test_walls_switched_back_to_bounce_back():
