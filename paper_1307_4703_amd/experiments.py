@@ -280,7 +280,8 @@ def boundary_comparison(storage: str = "f64", steps: int = 30000,
     row); then the pressure-driven channel once more with the paper's walls
     in place of bounce-back. Then the rate of the 2048 x 1024 gradient
     generator (FP32) with each kind on its four segments, and with the
-    pressure boundaries and the paper's walls."""
+    pressure boundaries and the paper's walls; and that lattice driven each
+    way for 20000 steps (boundary_gradient_generator)."""
     out: Dict = {}
     nu = (0.8 - 0.5) / 3
     base = W.straight_channel(storage=storage, steps=steps)
@@ -313,6 +314,58 @@ def boundary_comparison(storage: str = "f64", steps: int = 30000,
                       "C_outlet_column_mean": round(float(np.nanmean(C[1:-1, -2])), 4)}
     for label, r in boundary_rates(rate_steps).items():
         out[label].update(r)
+    out["gradient_generator_2048"] = boundary_gradient_generator()
+    return out
+
+
+def boundary_gradient_generator(steps: int = 18000, storage: str = "f32") -> Dict:
+    """The 2048 x 1024 gradient generator from rest with its valves
+    alternating every 2000 steps (source channel open first), driven three
+    ways: velocity inlets and outlets (u_max = 0.04) with bounce-back walls;
+    pressure boundaries whose density drop would drive the same centre
+    speed through a developed straight channel of the channels' width and
+    length, with bounce-back walls; the same with the paper's walls. After
+    `steps` steps (18000: the source channel has just been open for 2000
+    steps): the largest speed in the chamber (the design asks it to be
+    negligible), the centre speed of the source channel at mid-length, the
+    compound there and where its front has reached along the channel's
+    centre line (C = 1/2), and the total mass against its start plus the
+    boundary fluxes (what the boundaries themselves create)."""
+    wl = W.gradient_generator(storage=storage)
+    lay = wl.layout  # type: ignore[attr-defined]
+    la, lb, lc_, ld = lay.left_channel
+    H = lb - la
+    nu = (wl.tau_f - 0.5) / 3
+    drho = 3 * 0.04 * 8 * nu / (H * H) * (ld - lc_)
+    press = [W.Segment(2, "pressure", (0, -1), rho=1 + drho / 2, c_in=1.0, fix_c=True),
+             W.Segment(3, "pressure", (0, 1), rho=1 - drho / 2),
+             W.Segment(4, "pressure", (0, -1), rho=1 + drho / 2, c_in=0.0, fix_c=True),
+             W.Segment(5, "pressure", (0, 1), rho=1 - drho / 2)]
+    xc, ymid = (la + lb) // 2, (lc_ + ld) // 2
+    out: Dict = {"steps": steps, "pressure_drop": round(drho, 6),
+                 "viscous_time_H2_over_nu": round(H * H / nu)}
+    for label in ("velocity_inlet", "pressure", "pressure_paper_walls"):
+        if label != "velocity_inlet":
+            wl.segments = press
+        lat = Lattice.from_workload(wl)
+        try:
+            if label.endswith("paper_walls"):
+                lat.set_wall_scheme("equilibrium")
+            d0 = lat.diagnostics()
+            lat.step(steps)
+            d1 = lat.diagnostics()
+            rho, ux, uy, C = lat.read()
+        finally:
+            lat.close()
+        line = np.nan_to_num(C[lc_:ld, xc])
+        reached = np.nonzero(line >= 0.5)[0]
+        net_in = sum(d1["seg_mass"]) - sum(d0["seg_mass"])
+        out[label] = {
+            "max_u_chamber": float(d1["max_u_region"]),
+            "u_centre_source_channel": float(np.hypot(ux[ymid, xc], uy[ymid, xc])),
+            "C_source_channel_mid": round(float(C[ymid, xc]), 4),
+            "front_C_half_cells_from_inlet": int(reached.max() + 1) if reached.size else 0,
+            "mass_change_minus_net_inflow": float(d1["mass"] - d0["mass"] - net_in)}
     return out
 
 

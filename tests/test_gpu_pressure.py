@@ -201,3 +201,6 @@ def test_boundary_comparison_runs():
         assert np.isfinite(r[label]["profile_error_vs_local_gradient"])
         assert r[label]["gg2048_f32_mlups"] > 0
         assert 0 < r[label]["no_slip_points"][0] < 1.5
+    g = r["gradient_generator_2048"]
+    for label in ("velocity_inlet", "pressure", "pressure_paper_walls"):
+        assert np.isfinite(g[label]["max_u_chamber"]) and g[label]["u_centre_source_channel"] > 0
