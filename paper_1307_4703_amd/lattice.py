@@ -106,14 +106,16 @@ class Lattice:
     # ------------------------------------------------------------------
     @classmethod
     def from_workload(cls, wl, *, storage: Optional[str] = None,
-                      stream: Optional[int] = None, init: bool = True) -> "Lattice":
+                      stream: Optional[int] = None, init: bool = True,
+                      device_allocator: Optional[str] = None) -> "Lattice":
         """The workload's compound shift C_s applies to FP16 storage only; the
         wider types keep C_s = 0, where a compound at rest at 0 or at an
         inlet value is held without rounding."""
         storage = storage or wl.storage
         lat = cls(wl.mask, tau_f=wl.tau_f, D=wl.D, w0=wl.w0, rho0=wl.rho0,
                   k_decay=wl.k_decay, c_shift=wl.c_shift if storage == "f16" else 0.0,
-                  periodic=wl.periodic, storage=storage, stream=stream)
+                  periodic=wl.periodic, storage=storage, stream=stream,
+                  device_allocator=device_allocator)
         for s in wl.segments:
             lat.set_segment(s.id, s.kind, s.normal, s.u_max, s.c_in,
                             getattr(s, "rho", 1.0), getattr(s, "fix_c", False))

@@ -23,12 +23,7 @@ def _pair(storage):
     init = seeded_init(wl, 21, amp_u=0.005)
     base = torch.cuda.memory_allocated()
     a = Lattice.from_workload(wl, storage=storage, init=False)
-    b = Lattice(wl.mask, tau_f=wl.tau_f, D=wl.D, w0=wl.w0, rho0=wl.rho0, k_decay=wl.k_decay,
-                c_shift=wl.c_shift if storage == "f16" else 0.0, periodic=wl.periodic,
-                storage=storage, device_allocator="torch")
-    for s in wl.segments:
-        b.set_segment(s.id, s.kind, s.normal, s.u_max, s.c_in)
-    b.set_schedule(wl.schedule, wl.t_origin)
+    b = Lattice.from_workload(wl, storage=storage, init=False, device_allocator="torch")
     held = torch.cuda.memory_allocated() - base
     for lat in (a, b):
         lat.init(**init)
