@@ -291,7 +291,11 @@ gg_status gg_set_two_step(gg_lattice *lat, int32_t fuse, int32_t strip_h);
  * current fluid state, computed as the coupled step computes it (paper
  * Eq. 7 in the compute type), times scale in the compute type. scale rescales a
  * flow computed at one time step to the compound lattice's larger one (the
- * paper raises the peak velocity to its chosen U^LB this way). Synchronises
+ * paper raises the peak velocity to its chosen U^LB this way). The caller
+ * keeps the scaled speed inside the compound lattice's positivity limit,
+ * |u_x|, |u_y| <= c_sg^2 = (1 - w0) / 2 (1/3 for w0 = 1/3, 1/2 for the
+ * paper's D2Q4): beyond it the linear equilibrium turns negative and the
+ * compound-only steps become unstable. Synchronises
  * the lattice's stream. Errors: GG_ERR_ARG (slot out of range, one of ux/uy
  * NULL, non-finite scale or host entries), GG_ERR_OOM. */
 gg_status gg_set_velocity_field(gg_lattice *lat, int32_t slot, const double *ux,
