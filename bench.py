@@ -466,6 +466,9 @@ def main():
                     help="time only the compound-only step on frozen velocity fields")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="time only the adjoint (gradient) leg")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint (gradient) leg (counter runs: rocprofv3 --pmc "
+                         "ended the process with a segmentation fault inside it)")
     ap.add_argument("--cde-steps", type=int, default=0,
                     help="timed compound-only steps per lattice (0: the defaults)")
     ap.add_argument("--digest", metavar="DIR",
@@ -549,8 +552,9 @@ def main():
             for name, steps, flow, rows in cde_leg}
         if not args.no_batch:
             out["batched_64_instances"] = batch_bench()
-        log("adjoint: chamber-misfit gradient over 20000 steps, 2048x1024 FP32")
-        out["adjoint_gradient"] = adjoint_bench()
+        if not args.no_adjoint:
+            log("adjoint: chamber-misfit gradient over 20000 steps, 2048x1024 FP32")
+            out["adjoint_gradient"] = adjoint_bench()
     if not args.no_extra and not args.no_experiments:
         from paper_1307_4703_amd import experiments
         log("step-profile test (Table 3), four cases, FP32")
