@@ -484,7 +484,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the lattice is not sharded across GPUs in this build)", file=sys.stderr)
+              "(the library does not shard a lattice across GPUs)", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
