@@ -295,9 +295,11 @@ gg_status gg_set_two_step(gg_lattice *lat, int32_t fuse, int32_t strip_h);
  * keeps the scaled speed inside the compound lattice's positivity limit,
  * |u_x|, |u_y| <= c_sg^2 = (1 - w0) / 2 (1/3 for w0 = 1/3, 1/2 for the
  * paper's D2Q4): beyond it the linear equilibrium turns negative and the
- * compound-only steps become unstable. Synchronises
+ * compound-only steps become unstable; host fields beyond it are refused
+ * (GG_ERR_ARG), device fields and captures are not checked. Synchronises
  * the lattice's stream. Errors: GG_ERR_ARG (slot out of range, one of ux/uy
- * NULL, non-finite scale or host entries), GG_ERR_OOM. */
+ * NULL, non-finite scale or host entries, host entries beyond the limit),
+ * GG_ERR_OOM. */
 gg_status gg_set_velocity_field(gg_lattice *lat, int32_t slot, const double *ux,
                                 const double *uy, double scale, gg_where where);
 

@@ -1709,6 +1709,16 @@ gg_status gg_set_velocity_field(gg_lattice *L, int32_t slot, const double *ux, c
           if (L->mask[(size_t)y * L->nx + x] == GG_MASK_FLUID && !std::isfinite(src[(size_t)y * L->nx + x]))
             return fail(GG_ERR_ARG, "velocity field has non-finite entries on the fluid");
     }
+    // the compound's linear equilibrium stays non-negative only for
+    // |u_x|, |u_y| <= c_sg^2 = (1 - w0) / 2
+    double umax = 0.0;
+    for (size_t k = 0; k < n; ++k)
+      if (L->mask[k] == GG_MASK_FLUID)
+        umax = std::max(umax, std::max(std::fabs(scale * ux[k]), std::fabs(scale * uy[k])));
+    if (umax > L->cs2g * (1.0 + 1e-12))
+      return fail(GG_ERR_ARG, "scaled velocity " + std::to_string(umax) +
+                                  " exceeds the compound lattice's positivity limit (1 - w0) / 2 = " +
+                                  std::to_string(L->cs2g));
     dev[0] = dev[1] = nullptr;
     for (int q = 0; q < 2 && st == GG_OK; ++q) {
       if (dev_alloc(L, (void **)&dev[q], n * sizeof(double)) != hipSuccess)

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import Oracle
+from paper_1307_4703_amd import Lattice
 from paper_1307_4703_amd import workloads as W
 from paper_1307_4703_amd._abi import GGError, GG_ERR_ARG, GG_ERR_STATE
 from tests.parity_util import log, make_lattice, make_oracle, seeded_init
@@ -258,3 +259,22 @@ def test_autotuner_keeps_the_result(tmp_path):
     assert res["rows"] in (0, 6, 14) and len(res["all"]) == 3
     one.cde_step(3 * (4 + 16))  # per candidate: 4 warm-up and 16 timed steps
     _same_compound(one, two, 60)
+
+
+def test_host_field_beyond_positivity_limit_refused():
+    """Host fields whose scaled components exceed c_sg^2 = (1 - w0) / 2 (where
+    the compound's linear equilibrium turns negative) are refused; at the
+    limit they are taken (the paper's D2Q4 runs at U = 1/2 exactly)."""
+    from paper_1307_4703_amd._abi import GGError, GG_ERR_ARG
+    mask = np.zeros((16, 32), np.uint8)
+    for w0, ok_speed in ((1.0 / 3.0, 1.0 / 3.0), (0.0, 0.5)):
+        lat = Lattice(mask, tau_f=0.8, D=0.02, w0=w0, periodic=(True, True), storage="f64")
+        ux = np.full(mask.shape, ok_speed)
+        uy = np.zeros(mask.shape)
+        lat.set_velocity_field(0, ux, uy)
+        with pytest.raises(GGError) as e:
+            lat.set_velocity_field(1, ux, uy, scale=1.01)
+        assert e.value.status == GG_ERR_ARG
+        with pytest.raises(GGError):
+            lat.set_velocity_field(1, uy, -1.2 * ux)
+        lat.close()
