@@ -102,8 +102,11 @@ __global__ void __launch_bounds__(256)
 // the link code read, 49 bytes for two steps. PRESS (lattices with pressure
 // segments): the pressure rule at the links, and the compound's rescaling
 // (Eq. 10) of a node next to an open pressure segment between the two
-// steps, in registers, as the rescaling kernel does it after a single step
-// (that kernel still follows the pass).
+// steps, in registers, as the rescaling kernel does it after a single step;
+// with bit 1 of dir set, also of the state at t as loaded, in every row of
+// the tile, halo included (the caller then marks as segment tiles all tiles
+// whose rows or halo hold a node next to a segment), else that kernel
+// follows the pass.
 template <class S, int R, bool PRESS = false>
 __global__ void __launch_bounds__((R + 2) * 64)
     k_cde_tile2(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles, int n_tiles,
@@ -127,8 +130,9 @@ __global__ void __launch_bounds__((R + 2) * 64)
   const PhaseNow ph2 = phase_at(L, t + 1);
   const int s1 = L.phase_field[ph1.index];
   const int s2 = L.phase_field[ph2.index];
-  const Planes<W> src(dir ? L.pop_b : L.pop, L.plane);
-  const Planes<W> dst(dir ? L.pop : L.pop_b, L.plane);
+  const int dsel = PRESS ? (dir & 1) : dir;
+  const Planes<W> src(dsel ? L.pop_b : L.pop, L.plane);
+  const Planes<W> dst(dsel ? L.pop : L.pop_b, L.plane);
 
   const int xr = tl.x0 - 1 + lane;
   int x = xr;
@@ -162,6 +166,19 @@ __global__ void __launch_bounds__((R + 2) * 64)
 
   // step t on this row
   Flux fx;
+  if (PRESS && seg && (dir & 2) && lc != NOT_FLUID && lc != 0) {
+    // the compound's rescaling after step t - 1 (flux counted by the owner)
+    const PhaseNow ph0 = phase_at(L, t - 1);
+    const int ps = pressure_source(L, lc, ph0, nbr);
+    if (ps >= 0) {
+      T unused[9];
+      double dm, dc;
+      rescale_node<T>(L, ps, ph0, false, unused, g, dm, dc);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) g[i] = P::rt(g[i]);
+      if (own) fx.add(ps, dm, dc);
+    }
+  }
   T pg[5], ing[5];
   if (lc != NOT_FLUID) {
     compound_collide<T>(L, x, y, g, ux, uy, pg);

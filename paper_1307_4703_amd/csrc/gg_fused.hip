@@ -246,8 +246,12 @@ __global__ void __launch_bounds__(256)
 // PRESS (segment tiles of lattices with pressure segments): the pressure
 // rule at the links, and the rescaling (Eq. 10) of the state at t + 1 of a
 // node next to an open pressure segment, in registers between the two
-// steps, as the rescaling kernel does it in memory after a single step (the
-// one after the pass's second step still runs as that kernel).
+// steps, as the rescaling kernel does it in memory after a single step.
+// With bit 1 of dir set, the state at t as loaded is taken as not yet
+// rescaled after step t - 1 and every row of the tile, halo included,
+// rescales it first in the same way; the caller then marks as segment tiles
+// all tiles whose rows or halo hold a node next to a segment. Otherwise the
+// rescaling kernel runs after the pass.
 template <class S, bool SEG, int R, bool PRESS = false>
 __global__ void __launch_bounds__((R + 2) * 64)
     k_tile2(const LatDesc *__restrict__ descs, const Tile *__restrict__ tiles, int n_tiles,
@@ -275,8 +279,9 @@ __global__ void __launch_bounds__((R + 2) * 64)
       ph1 = phase_at(L, t);
       ph2 = phase_at(L, t + 1);
     }
-    const Planes<W> src(dir ? L.pop_b : L.pop, L.plane);
-    const Planes<W> dst(dir ? L.pop : L.pop_b, L.plane);
+    const int dsel = PRESS ? (dir & 1) : dir;
+    const Planes<W> src(dsel ? L.pop_b : L.pop, L.plane);
+    const Planes<W> dst(dsel ? L.pop : L.pop_b, L.plane);
 
     const int xr = tl.x0 - 1 + lane;
     const bool col = xr >= -1 && xr <= nx;
@@ -313,6 +318,20 @@ __global__ void __launch_bounds__((R + 2) * 64)
 
     // step t on this row
     Flux fx;
+    if (PRESS && seg && (dir & 2) && lc != NOT_FLUID && lc != 0) {
+      // the rescaling after step t - 1 (the flux counted once, by the owner)
+      const PhaseNow ph0 = phase_at(L, t - 1);
+      const int ps = pressure_source(L, lc, ph0, nbr);
+      if (ps >= 0) {
+        double dm, dc;
+        rescale_node<T>(L, ps, ph0, true, f, g, dm, dc);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = P::rt(f[i]);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) g[i] = P::rt(g[i]);
+        if (own) fx.add(ps, dm, dc);
+      }
+    }
     T pf[9], pg[5], inf[9], ing[5];
     if (lc != NOT_FLUID) {
       collide_node<T, PRESS>(L, x, y, lc, seg, ph1, f, g, pf, pg, inf, ing, fx, own,

@@ -59,6 +59,9 @@ struct gg_lattice {
   // tiles of strip_h rows with the boundary kernel apart or in one kernel);
   // fuse = 1 keeps to single steps
   int fuse = 3, strip_h = 6;
+  // tile lists built with the halo-inclusive segment flag (pressure
+  // segments: the passes rescale the boundary nodes as they load them)
+  bool tiles_halo_seg = false, cde_halo_seg = false;
   bool strip_flux_ok = true;  // no vertical node pair links to > 2 segments
   gg::Tile *d_strips = nullptr;      // strips without segment links
   int n_strips = 0;

@@ -195,7 +195,7 @@ static void build_tiles(const gg_lattice *L, int tx, int ty, int inst,
 // those with segment links go to the second list; otherwise it stays whole
 // in the first. Flags: strip height << 8 | segment bit.
 static void build_strips(const gg_lattice *L, int h, int inst, bool split, std::vector<Tile> &main,
-                         std::vector<Tile> &seg) {
+                         std::vector<Tile> &seg, bool halo_seg = false) {
   auto scan = [&](int x0, int y0, int rows, bool &any, bool &sg) {
     any = sg = false;
     for (int y = y0; y < std::min(y0 + rows, L->ny); ++y)
@@ -203,6 +203,21 @@ static void build_strips(const gg_lattice *L, int h, int inst, bool split, std::
         if (L->link[L->nid(x, y)] == NOT_FLUID) continue;
         any = true;
         if (L->touches_seg[(size_t)y * L->nx + x]) sg = true;
+      }
+    // halo_seg: also when a node of the one-node halo the tile collides
+    // touches a segment (wrapped on periodic axes)
+    for (int yr = y0 - 1; halo_seg && !sg && yr <= y0 + rows; ++yr)
+      for (int xr = x0 - 1; !sg && xr <= x0 + 62; ++xr) {
+        int x = xr, y = yr;
+        if (x < 0 || x >= L->nx) {
+          if (!L->p.periodic_x) continue;
+          x = (x + L->nx) % L->nx;
+        }
+        if (y < 0 || y >= L->ny) {
+          if (!L->p.periodic_y) continue;
+          y = (y + L->ny) % L->ny;
+        }
+        if (L->link[L->nid(x, y)] != NOT_FLUID && L->touches_seg[(size_t)y * L->nx + x]) sg = true;
       }
   };
   std::vector<uint8_t> colany((size_t)L->nx);
@@ -250,6 +265,8 @@ static void build_strips(const gg_lattice *L, int h, int inst, bool split, std::
   }
 }
 
+static bool has_pressure(const gg_lattice *L);
+
 gg_status gg_rebuild_tiles(gg_lattice *L) {
   std::vector<Tile> t;
   build_tiles(L, L->tile_x, L->tile_y, 0, t);
@@ -261,7 +278,10 @@ gg_status gg_rebuild_tiles(gg_lattice *L) {
     GG_HIP(hipMemcpy(L->d_tiles, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice));
   }
   std::vector<Tile> sv, ss;
-  build_strips(L, L->strip_h, 0, L->fuse != 4, sv, ss);
+  // with pressure segments the one-kernel pass rescales the state it loads
+  // in every tile that collides a boundary node, halo included
+  L->tiles_halo_seg = L->fuse == 4 && has_pressure(L);
+  build_strips(L, L->strip_h, 0, L->fuse != 4, sv, ss, L->tiles_halo_seg);
   if (L->d_strips) (void)dev_free(L, L->d_strips);
   if (L->d_seg_strips) (void)dev_free(L, L->d_seg_strips);
   L->d_strips = L->d_seg_strips = nullptr;
@@ -587,6 +607,12 @@ static bool has_pressure(const gg_lattice *L) {
 // ghost cell (in any phase), uploaded as (x, y) pairs.
 static gg_status pressure_nodes(gg_lattice *L) {
   if (!L->press_dirty) return GG_OK;
+  // the tile lists mark the tiles that must rescale what they load
+  if (L->tiles_halo_seg != (L->fuse == 4 && has_pressure(L))) {
+    gg_status st = gg_rebuild_tiles(L);
+    if (st != GG_OK) return st;
+  }
+  if (L->cde_halo_seg != has_pressure(L)) L->cde_tiles_rows = 0;
   std::vector<int32_t> xy;
   if (has_pressure(L))
     for (int y = 0; y < L->ny; ++y)
@@ -843,10 +869,14 @@ static hipError_t launch_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t
   hipError_t e = hipSuccess;
   if (pass_ok(L) && !(t0 & 1) && n % 4 == 0) {
     // with pressure segments the pass rescales the boundary nodes between
-    // its two steps; the state it leaves is rescaled here
-    for (int64_t k = 0; k < n / 2 && e == hipSuccess; ++k) {
-      e = launch_pass(L, (int)(k & 1), (int)(2 * k), st);
-      if (e == hipSuccess && L->n_press > 0)
+    // its two steps; the state it leaves is rescaled by the kernel after
+    // it, or, in the one-kernel form, by the next pass as it loads it (bit
+    // 1 of dir), so that only the last pass of the run needs the kernel
+    const int64_t passes = n / 2;
+    const bool at_load = L->n_press > 0 && L->fuse == 4 && L->tiles_halo_seg;
+    for (int64_t k = 0; k < passes && e == hipSuccess; ++k) {
+      e = launch_pass(L, (int)(k & 1) | (at_load && k > 0 ? 2 : 0), (int)(2 * k), st);
+      if (e == hipSuccess && L->n_press > 0 && (!at_load || k == passes - 1))
         e = launch_rescale(L->storage, L->d_desc, L->d_press, L->n_press, (int)(2 * k + 1), true,
                            st, (k & 1) == 0);
     }
@@ -1765,7 +1795,8 @@ gg_status gg_set_cde_launch(gg_lattice *L, int32_t rows) {
 static gg_status cde_tiles(gg_lattice *L) {
   if (L->cde_rows == 0 || L->cde_tiles_rows == L->cde_rows) return GG_OK;
   std::vector<Tile> list, unused;
-  build_strips(L, L->cde_rows, 0, false, list, unused);
+  L->cde_halo_seg = has_pressure(L);
+  build_strips(L, L->cde_rows, 0, false, list, unused, L->cde_halo_seg);
   if (L->d_cde_tiles) GG_HIP(dev_free(L, L->d_cde_tiles));
   L->d_cde_tiles = nullptr;
   L->n_cde_tiles = (int)list.size();
@@ -1799,11 +1830,14 @@ static hipError_t launch_cde_steps(gg_lattice *L, int64_t t0, int64_t n, hipStre
       ++dt;
     }
     const int64_t passes = (n - dt) / 4 * 2;
+    // (pressure: each pass after the first rescales the state it loads, the
+    // kernel the state the last one leaves, in pop_b after dir 0)
+    const bool at_load = press && L->cde_halo_seg;
     for (int64_t k = 0; k < passes && e == hipSuccess; ++k) {
       e = launch_cde_tile2(L->storage, L->cde_rows, L->d_desc, L->d_cde_tiles, L->n_cde_tiles,
-                           (int)(k & 1), (int)(dt + 2 * k), st, press);
-      // the rescaling of the state the pass leaves (in pop_b after dir 0)
-      if (e == hipSuccess && press)
+                           (int)(k & 1) | (at_load && k > 0 ? 2 : 0), (int)(dt + 2 * k), st,
+                           press);
+      if (e == hipSuccess && press && (!at_load || k == passes - 1))
         e = launch_rescale(L->storage, L->d_desc, L->d_press, L->n_press, (int)(dt + 2 * k + 1),
                            false, st, (k & 1) == 0);
     }
