@@ -183,9 +183,12 @@ gg_status gg_set_segment(gg_lattice *lat, int32_t id, gg_seg_kind kind,
  * for gg_set_segment. While a lattice has such a segment, the rescaling
  * follows each single step in a kernel of its own; the row-parallel
  * two-step pass (fuse 3 and 4) rescales between its two steps in registers
- * and is followed by that kernel (the same state, bit for bit); walking
- * strips (fuse 2) give way to single steps; the compound-only passes
- * (gg_set_cde_launch) do the same for the compound. gg_adjoint, gg_batch_create, gg_step_timed and
+ * and is followed by that kernel, except that in the one-kernel form (fuse
+ * 4) each pass after the first rescales the state it loads instead and
+ * the kernel follows only the last pass of a run (the same state as single
+ * steps, bit for bit); walking strips (fuse 2) give way to single steps;
+ * the compound-only passes (gg_set_cde_launch) rescale the compound as the
+ * one-kernel form does. gg_adjoint, gg_batch_create, gg_step_timed and
  * gg_step2_timed refuse such a lattice (GG_ERR_STATE): the rescaling is
  * not linear in the compound. */
 gg_status gg_set_pressure_segment(gg_lattice *lat, int32_t id, int32_t nrm_x,
