@@ -1,0 +1,97 @@
+"""Host-side helpers of the experiments and of bench.py, on the CPU: block
+means of the precision report, the settling time and curvature of the
+gradient-formation summary, the Poiseuille profile error of the boundary
+comparison, and the digest of counter runs into HBM bytes per launch."""
+import csv
+import json
+
+import numpy as np
+import pytest
+
+import bench
+from paper_1307_4703_amd import experiments as E
+
+
+def test_block_means_fluid_only():
+    a = np.arange(16 * 16, dtype=float).reshape(16, 16)
+    fluid = np.ones_like(a, bool)
+    fluid[:8, :8] = False          # one block without fluid
+    fluid[8, 8] = False            # one node out of another block
+    m = E.block_means(a, fluid)
+    assert m.shape == (2, 2)
+    assert np.isnan(m[0, 0])
+    blk = a[8:16, 8:16].copy()
+    assert m[1, 1] == pytest.approx((blk.sum() - a[8, 8]) / 63)
+    assert m[0, 1] == pytest.approx(a[:8, 8:].mean())
+
+
+def test_time_to_settle_and_curvature():
+    t = np.linspace(0.0, 4.0, 401)
+    c = np.where(t < 2.0, 1 - np.exp(-t / 0.2), np.exp(-(t - 2.0) / 0.5))
+    # 90 % of the rise after t = 0: 0.2 ln 10 hours (to the sample spacing)
+    assert E.time_to_settle(t, c, 0.0, 1.99) == pytest.approx(0.2 * np.log(10), abs=0.011)
+    # the fall after the swap at 2 h, measured to the value at the last
+    # sample before t_to (exp(-3.98), not 0)
+    end = np.exp(-1.98 / 0.5)
+    goal = 1.0 + 0.9 * (end - 1.0)
+    assert E.time_to_settle(t, c, 2.0, 3.99) == pytest.approx(-0.5 * np.log(goal), abs=0.011)
+    assert E.time_to_settle(t, np.ones_like(t), 0.0, 2.0) is None
+    assert E.curvature([1.0, 0.75, 0.5, 0.25, 0.0]) == pytest.approx(0.0)
+    assert E.curvature([1.0, 0.4, 0.25, 0.1, 0.0]) == pytest.approx(-0.25)
+
+
+def test_poiseuille_error_of_an_exact_parabola():
+    """A profile that is the parabola of the pressure gradient it sits in
+    has no error, and the centre speed follows G H^2 / (8 nu rho)."""
+    H, nu, nx = 30, 0.1, 101
+    G = 1e-6
+    s = np.arange(1, H + 1) - 0.5
+    u = G * s * (H - s) / (2 * nu)
+    x = np.arange(nx)
+    rho = 1.0 - 3 * G * (x - nx // 2)          # p = rho / 3 falls by G per cell
+    rho = np.broadcast_to(rho[None, :], (H + 2, nx)).copy()
+    ux = np.zeros((H + 2, nx))
+    ux[1:-1, :] = u[:, None]
+    err, umax = E._poiseuille_error(rho, ux, H, nu, nx // 2)
+    assert err < 1e-12
+    assert umax == pytest.approx(G * H * H / (8 * nu), rel=1e-12)
+
+
+def _counter_csv(path, counter, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, ["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for name, grid, value in rows:
+            w.writerow({"Kernel_Name": name, "Grid_Size": grid, "Counter_Name": counter,
+                        "Counter_Value": value})
+
+
+def test_digest_scales_counters_by_the_copy_kernel(tmp_path):
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what they
+    read for the copy kernel of known size, averaged per kernel, and set
+    against the algorithmic bytes of the named workload."""
+    copy_grid = 1024                               # 1024 lanes x 16 B each way
+    nbytes = copy_grid * 16
+    pf = tmp_path / "pmc_fetch"
+    pw = tmp_path / "pmc_write"
+    pf.mkdir()
+    pw.mkdir()
+    kern = "void gg::(anonymous namespace)::k_tile2<double, false, 14, false>(x)"
+    # the copy reads half of its bytes per FETCH_SIZE unit, writes all
+    _counter_csv(pf / "fetch_counter_collection.csv", "FETCH_SIZE",
+                 [("gg::k_copy(y)", copy_grid, nbytes / 1024 / 2),
+                  (kern, 647168, 1000.0), (kern, 647168, 1200.0)])
+    _counter_csv(pw / "write_counter_collection.csv", "WRITE_SIZE",
+                 [("gg::k_copy(y)", copy_grid, nbytes / 1024),
+                  (kern, 647168, 500.0), (kern, 647168, 500.0)])
+    out = tmp_path / "traffic.json"
+    d = bench.digest_counters(str(tmp_path), {"647168/k_tile2<double, false, 14,": "straight_f64"},
+                              str(out))
+    assert d["fetch_scale"] == pytest.approx(2.0) and d["write_scale"] == pytest.approx(1.0)
+    w = d["workloads"]["straight_f64"]
+    assert w["per_kernel"]["k_tile2<double, false, 14, false>"] == {
+        "fetch_bytes": round(1100.0 * 1024 * 2), "write_bytes": 500 * 1024}
+    n_fluid = int(np.count_nonzero(bench.workload("straight_f64").mask == 0))
+    assert w["algorithmic_bytes_per_launch"] == n_fluid * (14 * 2 * 8 + 1)
+    assert w["bytes_per_launch"] == round(1100.0 * 1024 * 2) + 500 * 1024
+    assert json.loads(out.read_text())["kernel_sha"] == bench.kernel_hash()
