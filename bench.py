@@ -2,10 +2,19 @@
 """Throughput of the coupled D2Q9 + D2Q5 lattice Boltzmann step on one MI355X.
 
 One benchmark step is one coupled time step (collide + stream of both
-lattices, boundary links, valve schedule, FP64 boundary-flux accumulation)
-over the whole synthetic lattice, with the state resident in HBM. The
-default workload is the 2048 x 1024 gradient generator in FP32 storage
-(channel Peclet 500, valves toggling every 2000 steps).
+lattices, boundary links, valve schedule, FP64 boundary-flux accumulation,
+and every `--monitor-every` steps the FP64 mass / compound / velocity /
+Peclet reduction) over the whole synthetic lattice, with the state resident
+in HBM. The default workload is the largest single-GPU configuration: the
+8192 x 4096 gradient generator with FP16-shifted population storage, FP32
+collision arithmetic and FP64 reductions (channel Peclet 500, valves
+toggling every 2000 steps).
+
+The timed region is exactly --steps steps after --warmup untimed ones (and
+at most 3 more that start the timed steps on the two-step pass's parity),
+bracketed by HIP events on the lattice's stream. Inside it, the library
+records an event pair around every launch of the dominant kernel, whose
+mean duration gives the roofline figures.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -94,76 +103,124 @@ def load_traffic(wl_name):
     return ent.get("bytes_per_launch")
 
 
-def time_lattice(name, steps, warmup, tile, chunk, form=None):
-    """Graph-replayed steps timed with HIP events on the lattice's stream
-    (torch's current stream), after the autotuner picked the launch form
-    (single steps or a two-step pass); plus per-kernel timings."""
+def align_steps(t):
+    """Untimed steps that bring step count t to a multiple of 4, where a run
+    of two-step passes starts (each pass from an even step, pairs of passes
+    ending in the first plane set)."""
+    return (-t) % 4
+
+
+def time_lattice(name, steps, warmup, tile, chunk, form=None, monitor_every=1000,
+                 graph_steps=None):
+    """One workload: `warmup` untimed steps (plus at most 3 that align the
+    step count to the pass's parity), then exactly `steps` timed steps of
+    gg_step_profile with the FP64 monitor reduction after every
+    `monitor_every` of them (at least one, after the last step). The timed
+    region is bracketed by HIP events on the lattice's stream (torch's
+    current stream); gg_step_profile also records an event pair on that
+    stream around every launch of the dominant kernel. Then `graph_steps`
+    steps replayed from captured graphs, for comparison."""
     import torch
     from paper_1307_4703_amd import Lattice
     from paper_1307_4703_amd import tune as T
     wl = workload(name)
     lat = Lattice.from_workload(wl)
-    lat.set_launch(tile[0], tile[1], chunk)
-    nf = lat.info()["n_fluid"]
-    if form == "tune":
-        res = T.tune_lattice(lat, steps=64 if nf > 1e7 else 256, graph_chunk=chunk,
-                             use_cache=False)
-        form = {"tile": res["tile"], "fuse": res["fuse"], "rows": res["rows"]}
-    else:
-        if form is None:
-            fuse, rows = FORMS.get(name, (3, 6))
-            form = {"fuse": fuse, "rows": rows}
-        form = {"tile": list(tile), **form}
+    try:
+        lat.set_launch(tile[0], tile[1], chunk)
+        nf = lat.info()["n_fluid"]
+        if form == "tune":
+            res = T.tune_lattice(lat, steps=64 if nf > 1e7 else 256, graph_chunk=chunk,
+                                 use_cache=False)
+            form = {"tile": res["tile"], "fuse": res["fuse"], "rows": res["rows"]}
+        else:
+            if form is None:
+                fuse, rows = FORMS.get(name, (3, 6))
+                form = {"fuse": fuse, "rows": rows}
+            form = {"tile": list(tile), **form}
         lat.set_two_step(form["fuse"], form["rows"])
-    log(f"{wl.name}: {wl.nx}x{wl.ny}, {nf} fluid nodes, storage {wl.storage}, "
-        f"form {form}, graph chunk {chunk}; warmup {warmup}")
-    lat.step(warmup)
-    lat.sync()
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    log(f"timed region: {steps} steps")
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    lat.step(steps)
-    ev1.record(stream)
-    lat.sync()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev_ms = ev0.elapsed_time(ev1)
-    n_k = min(steps, 200 if nf > 1e7 else 1000)
-    extra = {}
-    if form["fuse"] >= 2:
-        extra["ms_pass_plain_launches"] = lat.step2_timed(max(1, n_k // 4))
-    fuse = form["fuse"]
-    lat.set_two_step(1)  # single-step kernels, for the breakdown
-    ms_even, ms_odd = lat.step_timed(n_k)
-    diag = lat.diagnostics(check_finite=False)
-    lat.close()
-    spl = 2 if fuse >= 2 else 1  # steps per launch of the dominant kernel
+        log(f"{wl.name}: {wl.nx}x{wl.ny}, {nf} fluid nodes, storage {wl.storage}, "
+            f"form {form}; warmup {warmup}")
+        lat.step(warmup)
+        extra_warm = align_steps(lat.info()["t"])
+        lat.step(extra_warm)
+        mon = max(1, min(monitor_every, steps)) if steps > 0 else 0
+        lat.set_monitor(mon)
+        lat.sync()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        log(f"timed region: {steps} steps from t = {lat.info()['t']}, "
+            f"monitor every {mon}")
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        prof = lat.step_profile(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ev_ms = ev0.elapsed_time(ev1)
+        diag = lat.monitor(check_finite=False) if mon else lat.diagnostics(check_finite=False)
+        lat.set_monitor(0)
+        graph = None
+        if graph_steps:
+            k = max(4, graph_steps // 4 * 4)
+            lat.step(align_steps(lat.info()["t"]))
+            lat.step(max(chunk, 4))  # graphs captured
+            lat.sync()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            lat.step(k)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            gms = e0.elapsed_time(e1)
+            graph = {"steps": k, "graph_chunk": chunk, "ms_per_step": round(gms / k, 6),
+                     "mlups": round(nf * k / (gms * 1e-3) / 1e6, 1)}
+    finally:
+        lat.close()
     return {"wl": wl, "nf": nf, "wall_s": wall, "event_ms": ev_ms, "form": form,
-            "steps_per_launch": spl, "launch_ms": ev_ms / steps * spl,
-            "ms_even": ms_even, "ms_odd": ms_odd, "diag": diag, **extra}
+            "prof": prof, "diag": diag, "warmup_run": warmup + extra_warm, "steps": steps,
+            "monitor_every": mon, "graph_replayed": graph}
 
 
 def roofline(r, storage, traffic):
-    """Dominant kernel: the two-step pass (each population read and written
-    once per launch, two steps) or the single step; algorithmic bytes per
-    launch = fluid nodes x (14 x 2 x storage bytes + 1 link byte)."""
-    bpl = r["nf"] * bytes_per_update(storage)
-    ach = bpl / (r["launch_ms"] * 1e-3) / 1e9
+    """Dominant kernel: the interior-tile kernel of the two-step pass (or
+    the single-step kernel when no pass ran). A launch of the pass
+    advances each fluid node of its tiles by two updates, so its
+    algorithmic bytes are 2 x (fluid nodes of its tiles) x the bytes per
+    coupled update (14 populations read and written + the 1-byte link
+    code); achieved = those bytes / the kernel's mean event-measured
+    launch duration. Because the pass makes one trip through memory for
+    two updates, this figure can exceed the HBM peak; the counter bytes
+    (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated) per launch, when
+    present for the current kernel source, give the HBM fraction."""
+    p = r["prof"]
+    bpu = bytes_per_update(storage)
+    if p["n_pass"] > 0:
+        ms = p["ms_pass"] / p["n_pass"]
+        units = 2 * p["pass_fluid"]
+        kind = "two-step pass (interior tiles)" if p["fuse"] != 4 else "two-step pass"
+        n_launch = p["n_pass"]
+    else:
+        n_launch = p["n_single"][0] + p["n_single"][1]
+        ms = (p["ms_single"][0] + p["ms_single"][1]) / max(1, n_launch)
+        units = r["nf"]
+        kind = "single step"
+    alg = units * bpu
+    ach = alg / (ms * 1e-3) / 1e9
     out = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
-           "algorithmic_bytes_per_launch": bpl, "steps_per_launch": r["steps_per_launch"],
-           "kernel_ms": round(r["launch_ms"], 5),
-           "single_step_kernel_ms_even_odd": [round(r["ms_even"], 5), round(r["ms_odd"], 5)],
-           # the rate in updates, priced at the single-step bytes per update
-           "update_rate_frac_of_single_step_roofline":
-               round(r["nf"] * bytes_per_update(storage) * r["steps_per_launch"] /
-                     (r["launch_ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
-    if "ms_pass_plain_launches" in r:
-        out["kernel_ms_pass_plain_launches"] = round(r["ms_pass_plain_launches"], 5)
+           "kernel": kind, "launches_timed": n_launch, "kernel_ms": round(ms, 5),
+           "updates_per_launch": units, "bytes_per_update": bpu,
+           "algorithmic_bytes_per_launch": alg}
+    if traffic:
+        out["traffic_gbs"] = round(traffic / (ms * 1e-3) / 1e9, 1)
+        out["traffic_frac"] = round(traffic / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+        out["traffic_per_algorithmic_single_trip"] = round(traffic / (alg / 2 if p["n_pass"] else alg), 4)
+    # whole-step throughput (all kernels of the step) priced at the bytes of
+    # one coupled update
+    out["step_rate_frac"] = round(r["nf"] * bpu * 1e-9 / (r["event_ms"] * 1e-3 / max(1, r.get("steps", 1)))
+                                  / PEAK_HBM_GBS, 4) if r.get("steps") else None
     return out
 
 
@@ -188,7 +245,7 @@ def copy_bandwidth(nbytes=2 << 30, reps=20):
 ADJOINT_BYTES_F32 = 113 + 113 + 28 + 80 + 28
 
 
-def adjoint_bench(steps=20000):
+def adjoint_bench(steps=20000, chunk=64):
     """The 2048 x 1024 FP32 gradient generator's chamber-misfit gradient
     (loss window, target ramp and source patch of chamber_misfit_setup)
     over `steps` steps with sqrt(N) checkpoints, against `steps` plain
@@ -201,7 +258,7 @@ def adjoint_bench(steps=20000):
     weight, target, r_box = W.chamber_misfit_setup(wl)
     lat = Lattice.from_workload(wl)
     try:
-        lat.set_launch(64, 4, 64)
+        lat.set_launch(64, 4, chunk)
         lat.set_two_step(*FORMS["gg2048_f32"])
         lat.adjoint(64, weight, target, r_box=r_box)  # kernels loaded, graphs captured
         lat.init(**(wl.init or {}))
@@ -229,7 +286,7 @@ def adjoint_bench(steps=20000):
             "loss": g["loss"], "d_D": g["d_D"]}
 
 
-def batch_bench(steps=2000, seq_steps=400, n=64, seed=4703, tune_steps=32):
+def batch_bench(steps=2000, seq_steps=400, n=64, seed=4703, tune_steps=32, chunk=64):
     """64 seeded gradient generators of uneven size (FP32): aggregate
     fluid-node updates per second of one batched, graph-captured launch per
     step (launch shape from the autotuner) against stepping the instances
@@ -243,7 +300,7 @@ def batch_bench(steps=2000, seq_steps=400, n=64, seed=4703, tune_steps=32):
     best = tune.tune_batch(lats, steps=tune_steps, use_cache=False)
     log(f"batch: tuned tile {best['tile']} persist {best['persist']} "
         f"fuse {best['fuse']} rows {best['rows']}")
-    b = Batch(lats, tile=tuple(best["tile"]), persist=best["persist"], graph_chunk=64,
+    b = Batch(lats, tile=tuple(best["tile"]), persist=best["persist"], graph_chunk=chunk,
               fuse=best["fuse"], rows=best["rows"])
     b.step(64)
     stream = torch.cuda.current_stream()
@@ -256,7 +313,7 @@ def batch_bench(steps=2000, seq_steps=400, n=64, seed=4703, tune_steps=32):
     t_b = e0.elapsed_time(e1) * 1e-3
     b.close()
     for lat in lats:  # the same kernels, one lattice after the other
-        lat.set_launch(best["tile"][0], best["tile"][1], 64)
+        lat.set_launch(best["tile"][0], best["tile"][1], chunk)
         lat.set_two_step(best["fuse"], best["rows"])
         lat.step(64)
     torch.cuda.synchronize()
@@ -443,14 +500,38 @@ def digest_counters(prof_dir, grids, out_path):
     return data
 
 
-def main():
+def lattice_entry(r, traffic):
+    """Secondary-lattice record: rate, roofline of the dominant kernel."""
+    e = roofline(r, r["wl"].storage, traffic)
+    e["mlups"] = round(r["nf"] * r["steps"] / (r["event_ms"] * 1e-3) / 1e6, 1)
+    e["workload"] = r["wl"].name
+    e["storage"] = r["wl"].storage
+    e["n_fluid"] = r["nf"]
+    e["steps"] = r["steps"]
+    e["launch_form"] = r["form"]
+    if r["graph_replayed"]:
+        e["graph_replayed"] = r["graph_replayed"]
+    return e
+
+
+# secondary lattices of the default run: (workload, timed steps)
+SECONDARY = (("gg2048_f32", 4000), ("allfluid8192_f32", 1000), ("allfluid8192_f16", 1000),
+             ("gg8192_f32", 2000), ("shard8192x512_f32", 2000), ("allfluid8192_f64", 400),
+             ("gg2048_f64", 2000))
+
+
+def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=2000)
-    ap.add_argument("--workload", default="gg2048_f32")
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=400)
+    ap.add_argument("--workload", default="gg8192_f16")
     ap.add_argument("--tile", default="64x4")
-    ap.add_argument("--chunk", type=int, default=64)
+    ap.add_argument("--chunk", type=int, default=64,
+                    help="graph chunk of the graph-replayed comparison and of the batch "
+                         "and adjoint legs (0: plain launches everywhere)")
+    ap.add_argument("--monitor-every", type=int, default=1000,
+                    help="FP64 diagnostics reduction every this many timed steps")
     ap.add_argument("--fuse", type=int, default=0,
                     help="launch form (1 single steps, 2-4 two-step passes); 0: the "
                          "workload's default form")
@@ -458,17 +539,22 @@ def main():
     ap.add_argument("--rows", type=int, default=6, help="rows of the two-step strips or tiles")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) leg")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the FP32/FP16-vs-FP64 error leg")
+    ap.add_argument("--precision-steps", type=int, default=20000)
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the out-of-cache and FP16 lattices and the copy bandwidth")
-    ap.add_argument("--no-experiments", action="store_true",
-                    help="skip the step-profile, boundary-kind and precision legs")
+                    help="headline only: no secondary lattices, copy bandwidth, compound-only, "
+                         "batch, adjoint, precision or experiment legs")
+    ap.add_argument("--experiments", action="store_true",
+                    help="also run the step-profile and boundary-kind experiments")
     ap.add_argument("--cde-only", action="store_true",
                     help="time only the compound-only step on frozen velocity fields")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="time only the adjoint (gradient) leg")
-    ap.add_argument("--no-adjoint", action="store_true",
-                    help="skip the adjoint (gradient) leg (counter runs: rocprofv3 --pmc "
-                         "ended the process with a segmentation fault inside it)")
+    ap.add_argument("--batch-only", action="store_true", help="time only the batched leg")
+    ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--adjoint-steps", type=int, default=20000)
     ap.add_argument("--cde-steps", type=int, default=0,
                     help="timed compound-only steps per lattice (0: the defaults)")
     ap.add_argument("--digest", metavar="DIR",
@@ -476,7 +562,7 @@ def main():
     ap.add_argument("--grids", default="",
                     help="with --digest: grid/kernel=workload pairs, separated by ';' "
                          "(kernel: a part of the kernel name, e.g. k_tile2<float)")
-    args = ap.parse_args()
+    args = ap.parse_args(argv)
     if args.digest:
         grids = dict(kv.split("=") for kv in args.grids.split(";") if kv)
         d = digest_counters(args.digest, grids, os.path.join(ROOT, "profiles", "traffic.json"))
@@ -485,6 +571,9 @@ def main():
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the library does not shard a lattice across GPUs)", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("--steps must be positive and --warmup non-negative", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
@@ -498,12 +587,17 @@ def main():
                           for name, steps, flow, rows in cde_leg}), flush=True)
         return
     if args.adjoint_only:
-        print(json.dumps(adjoint_bench()), flush=True)
+        print(json.dumps(adjoint_bench(args.adjoint_steps, args.chunk)), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps(batch_bench(args.batch_steps, chunk=args.chunk)), flush=True)
         return
 
     form = "tune" if args.tune else ({"fuse": args.fuse, "rows": args.rows} if args.fuse else None)
-    r = time_lattice(args.workload, args.steps, args.warmup, tile, args.chunk, form)
-    wl, nf = r["wl"], r["nf"]
+    r = time_lattice(args.workload, args.steps, args.warmup, tile, args.chunk, form,
+                     args.monitor_every, graph_steps=None if args.no_extra else max(args.steps, 1000))
+    wl, nf, p = r["wl"], r["nf"], r["prof"]
+    d = r["diag"]
     out = {
         "metric": METRIC,
         "value": round(nf * args.steps / (r["event_ms"] * 1e-3) / 1e6, 1),
@@ -518,60 +612,71 @@ def main():
         "dtype": "f64" if wl.storage == "f64" else "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "n_fluid": nf,
-                   "storage": wl.storage, "D": wl.D, "tau_f": wl.tau_f,
+                   "storage": {"f16": "FP16-shifted (f - w rho0, g - w C_s)", "f32": "FP32",
+                               "f64": "FP64"}[wl.storage],
+                   "collision_arithmetic": "f64" if wl.storage == "f64" else "f32",
+                   "reductions": "f64",
+                   "peclet": getattr(wl, "peclet", None), "D": wl.D, "tau_f": wl.tau_f,
                    "valve_half_period": wl.schedule[0].duration if wl.schedule else None,
-                   "launch_form": r["form"], "graph_chunk": args.chunk,
-                   "bytes_per_update_single_step": bytes_per_update(wl.storage),
+                   "launch_form": r["form"],
+                   "launches": {"pass_kernel": p["n_pass"], "single_even": p["n_single"][0],
+                                "single_odd": p["n_single"][1]},
+                   "warmup_steps_run": r["warmup_run"],
+                   "monitor_every": r["monitor_every"], "monitor_reductions": p["n_monitor"],
+                   "bytes_per_update": bytes_per_update(wl.storage),
                    "wall_clock_mlups": round(nf * args.steps / r["wall_s"] / 1e6, 1),
                    "lattice_mlups": round(wl.nx * wl.ny * args.steps / (r["event_ms"] * 1e-3) / 1e6, 1),
                    "parallelism": "single GPU"},
         "roofline": roofline(r, wl.storage, load_traffic(args.workload)),
-        "diagnostics": {"t": r["diag"]["t"], "mass": r["diag"]["mass"],
-                        "n_nonfinite": r["diag"]["n_nonfinite"],
-                        "max_u_chamber": r["diag"]["max_u_region"],
-                        "max_cell_peclet_chamber": r["diag"]["max_pe_region"]},
+        "diagnostics": {"t": d["t"], "mass": d["mass"], "solute": d["solute"],
+                        "n_nonfinite": d["n_nonfinite"], "max_u": d["max_u"],
+                        "max_u_chamber": d["max_u_region"],
+                        "max_cell_peclet_chamber": d["max_pe_region"]},
     }
+    if r["graph_replayed"]:
+        out["graph_replayed"] = r["graph_replayed"]
     if not args.no_extra:
         out["copy_bandwidth_gbs"] = round(copy_bandwidth(), 1)
         log(f"plain copy: {out['copy_bandwidth_gbs']} GB/s")
         extra = {}
-        for name, steps in (("allfluid8192_f32", 1000), ("allfluid8192_f16", 1000),
-                            ("gg8192_f16", 2000), ("shard8192x512_f32", 2000),
-                            ("allfluid8192_f64", 400), ("gg2048_f64", 4000)):
+        for name, steps in SECONDARY:
             if name == args.workload:
                 continue
-            r2 = time_lattice(name, steps, 100, tile, args.chunk, form)
-            e = roofline(r2, r2["wl"].storage, load_traffic(name))
-            e["mlups"] = round(r2["nf"] * steps / (r2["event_ms"] * 1e-3) / 1e6, 1)
-            e["workload"] = r2["wl"].name
-            e["storage"] = r2["wl"].storage
-            extra[name] = e
-        out["roofline_other_lattices"] = extra
+            r2 = time_lattice(name, steps, 100, tile, args.chunk, form, args.monitor_every,
+                              graph_steps=steps)
+            extra[name] = lattice_entry(r2, load_traffic(name))
+        out["other_lattices"] = extra
         out["compound_only_frozen_velocity"] = {
             name: cde_bench(name, steps, flow, rows, args.chunk)
             for name, steps, flow, rows in cde_leg}
         if not args.no_batch:
-            out["batched_64_instances"] = batch_bench()
+            out["batched_64_instances"] = batch_bench(args.batch_steps, chunk=args.chunk)
         if not args.no_adjoint:
-            log("adjoint: chamber-misfit gradient over 20000 steps, 2048x1024 FP32")
-            out["adjoint_gradient"] = adjoint_bench()
-    if not args.no_extra and not args.no_experiments:
-        from paper_1307_4703_amd import experiments
-        log("step-profile test (Table 3), four cases, FP32")
-        out["step_profile_table3"] = experiments.step_profile_summary(storage="f32")
-        log("boundary kinds: velocity inlet / outflow links against the pressure boundary")
-        out["boundary_kinds"] = experiments.boundary_comparison()
-        log("reduced-precision storage against FP64: 8192x4096 (Pe 500, 2000) and 2048x1024")
-        from paper_1307_4703_amd import workloads as W
-        out["precision_vs_fp64"] = {
-            "gg8192_pe500": experiments.precision_report(
-                W.gradient_generator(scale=4.0, storage="f16", peclet=500.0), ("f16", "f32")),
-            "gg8192_pe2000": experiments.precision_report(
-                W.gradient_generator(scale=4.0, storage="f16", peclet=2000.0), ("f16",)),
-            "gg2048_pe500": experiments.precision_report(W.gradient_generator(), ("f32", "f16"))}
+            log(f"adjoint: chamber-misfit gradient over {args.adjoint_steps} steps, 2048x1024 FP32")
+            out["adjoint_gradient"] = adjoint_bench(args.adjoint_steps, args.chunk)
+        if not args.no_precision:
+            from paper_1307_4703_amd import experiments
+            from paper_1307_4703_amd import workloads as W
+            log(f"reduced-precision storage against FP64: 8192x4096, Pe 500 and 2000, "
+                f"{args.precision_steps} steps")
+            out["precision_vs_fp64"] = {
+                "gg8192_pe500": experiments.precision_report(
+                    W.gradient_generator(scale=4.0, storage="f16", peclet=500.0), ("f16", "f32"),
+                    steps=args.precision_steps),
+                "gg8192_pe2000": experiments.precision_report(
+                    W.gradient_generator(scale=4.0, storage="f16", peclet=2000.0), ("f16",),
+                    steps=args.precision_steps)}
+        if args.experiments:
+            from paper_1307_4703_amd import experiments
+            log("step-profile test (Table 3), four cases, FP32")
+            out["step_profile_table3"] = experiments.step_profile_summary(storage="f32")
+            log("boundary kinds: velocity inlet / outflow links against the pressure boundary")
+            out["boundary_kinds"] = experiments.boundary_comparison()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
+        out["cpu_baseline"]["gpu_over_cpu"] = round(out["value"] / out["cpu_baseline"]["value"], 1)
     print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

@@ -346,7 +346,10 @@ gg_status gg_info(const gg_lattice *lat, int64_t *n_fluid, int64_t *n_tiles,
  * graph_chunk steps (0: plain launches). All lattices must share the
  * storage type and the HIP stream; the batch copies their configuration
  * (parameters, segments, schedules) at creation, so later changes to a
- * member need a new batch. The members' states advance in place: after
+ * member need a new batch: once a member was reconfigured (any call that
+ * changes its parameters, segments, schedule, source, region, velocity
+ * fields or plane sets), gg_batch_step and gg_batch_set_two_step return
+ * GG_ERR_STATE. The members' states advance in place: after
  * gg_batch_step(b, n) every member is n steps further, exactly as after
  * gg_step(member, n). tile_x, tile_y as in gg_set_launch (0, 0: 64 x 4);
  * persist > 0 caps the grid at that many work-groups, which then loop over
@@ -436,6 +439,52 @@ gg_status gg_stream_copy(void *dst, const void *src, size_t bytes, int32_t reps,
  * lattice or an unknown scheme. */
 typedef enum gg_wall_scheme { GG_WALL_BOUNCE_BACK = 0, GG_WALL_PAPER = 1 } gg_wall_scheme;
 gg_status gg_set_wall_scheme(gg_lattice *lat, int32_t scheme);
+
+/* Monitor (the diagnostics of the Results section on the hot path: the
+ * flow in the chamber must stay negligible, Abstract and Results; cell
+ * Peclet number of Eq. 12; mass and compound totals of the conservation
+ * checks): with every > 0, gg_step launches the FP64 reduction of
+ * gg_diagnostics on the lattice's stream after each step that ends a
+ * multiple of `every` steps counted from the call, without waiting for the
+ * GPU, and keeps the last result (with a copy of the boundary-flux
+ * accumulators taken at the same point) in device memory; every = 0 turns
+ * it off. Steps between two reductions still run in graph replays and
+ * two-step passes. Device memory: 40 doubles plus 6 doubles per 64 x 4
+ * tile holding fluid, allocated here (GG_ERR_OOM). GG_ERR_ARG for every
+ * < 0. */
+gg_status gg_set_monitor(gg_lattice *lat, int64_t every);
+
+/* The last monitor reduction (waits for the stream): out->t is the step it
+ * was taken at; *count (may be NULL) the reductions since gg_set_monitor.
+ * GG_ERR_STATE if none has run; GG_ERR_NONFINITE (with *out filled) if
+ * that reduction found a non-finite population. */
+gg_status gg_monitor_read(gg_lattice *lat, gg_diag *out, int64_t *count);
+
+/* Result of gg_step_profile. The dominant kernel is the one that takes the
+ * most HBM traffic: the kernel over the interior tile list of each two-step
+ * pass (with fuse 2 and 3 the boundary tiles run in a second kernel beside
+ * it on a side stream; with fuse 4 it is the pass's only kernel), or the
+ * step kernel of each single step. */
+typedef struct gg_profile {
+  double ms_total;          /* HIP events around the whole call */
+  int64_t n_pass;           /* launches of the pass's dominant kernel */
+  double ms_pass;           /* their summed event-measured duration */
+  int64_t n_single[2];      /* single steps at even / odd t */
+  double ms_single[2];      /* their summed duration */
+  int64_t n_monitor;        /* monitor reductions launched (gg_set_monitor) */
+  int64_t pass_fluid;       /* fluid nodes owned by the tiles of the pass's
+                               dominant kernel (two updates each per launch) */
+  int64_t pass_side_fluid;  /* fluid nodes owned by the side kernel's tiles */
+  int32_t fuse, rows;       /* launch form used (fuse 1: single steps only) */
+} gg_profile;
+
+/* Instrumentation: gg_step(lat, n) launched without graph replays, with a
+ * pair of HIP events recorded on the lattice's stream around every launch
+ * of the dominant kernel and a pair around the whole call; waits for the
+ * stream and returns the event-measured durations. The state advances
+ * exactly as with gg_step (monitor reductions included). Errors as
+ * gg_step, GG_ERR_HIP if an event fails. */
+gg_status gg_step_profile(gg_lattice *lat, int64_t n, gg_profile *out);
 
 /* Instrumentation: shuffle the order of the tiles and strips the steps
  * are launched over (seeded), e.g. to check that the result does not depend

@@ -71,6 +71,14 @@ class gg_grads(ctypes.Structure):
                 ("ckpt_every", ctypes.c_int64), ("n_checkpoints", ctypes.c_int64)]
 
 
+class gg_profile(ctypes.Structure):
+    _fields_ = [("ms_total", ctypes.c_double), ("n_pass", ctypes.c_int64),
+                ("ms_pass", ctypes.c_double), ("n_single", ctypes.c_int64 * 2),
+                ("ms_single", ctypes.c_double * 2), ("n_monitor", ctypes.c_int64),
+                ("pass_fluid", ctypes.c_int64), ("pass_side_fluid", ctypes.c_int64),
+                ("fuse", ctypes.c_int32), ("rows", ctypes.c_int32)]
+
+
 class GGError(RuntimeError):
     def __init__(self, status: int, where: str, message: str):
         super().__init__(f"{where} failed with status {status}: {message}")
@@ -117,6 +125,9 @@ SIGS = {
     "gg_permute_tiles": [P, ctypes.c_uint64],
     "gg_set_wall_scheme": [P, I32],
     "gg_stream_copy": [P, P, ctypes.c_size_t, I32, P, ctypes.POINTER(D)],
+    "gg_set_monitor": [P, I64],
+    "gg_monitor_read": [P, ctypes.POINTER(gg_diag), ctypes.POINTER(I64)],
+    "gg_step_profile": [P, I64, ctypes.POINTER(gg_profile)],
 }
 
 

@@ -38,6 +38,10 @@ struct gg_lattice {
   std::vector<gg_phase> phases;
   int64_t t_origin = 0;
   int64_t t = 0;  // host mirror of the device counter
+  // configuration generation: bumped by every call that re-uploads the
+  // descriptor or frees or reallocates a device buffer it points to
+  // (batches copy the descriptor and refuse to run once it changed)
+  uint64_t gen = 0;
   int r_box[4] = {0, 0, 0, 0};
 
   void *d_pop = nullptr;
@@ -103,6 +107,19 @@ struct gg_lattice {
   int n_cde_tiles = 0, cde_tiles_rows = 0;
   hipGraph_t cde_graph[2] = {nullptr, nullptr};
   hipGraphExec_t cde_exec[2] = {nullptr, nullptr};
+  // fluid nodes owned by the tiles of the pass's two lists
+  int64_t strips_fluid = 0, seg_strips_fluid = 0;
+  // monitor: the FP64 reduction of gg_diagnostics launched after every
+  // mon_every-th step (counted from mon_t0) into d_mon (8 totals, then the
+  // 2 * GG_MAX_SEGMENTS flux accumulators copied at the same point)
+  int64_t mon_every = 0, mon_t0 = 0, mon_last_t = -1, mon_count = 0;
+  double *d_mon = nullptr;
+  // profiling (gg_step_profile): plain launches with an event pair around
+  // every launch of the dominant kernel; kind 0 pass, 1 even step, 2 odd step
+  bool prof = false;
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<int8_t> prof_kind;
+  size_t prof_used = 0;
 };
 
 gg_status gg_upload_desc(gg_lattice *L);

@@ -88,9 +88,12 @@ void gg_free_device(gg_lattice *L) {
   void *ptrs[] = {L->d_pop, L->d_pop_b, L->d_link, L->d_mask, L->d_region, L->d_R, L->d_t,
                   L->d_flux, L->d_acc, L->d_desc, L->d_tiles, L->d_aux_tiles, L->d_strips,
                   L->d_seg_strips, L->d_partial, L->d_ufield, L->d_cde_tiles, L->d_press,
-                  L->d_wall, L->d_wall_links, L->d_wall_save};
+                  L->d_wall, L->d_wall_links, L->d_wall_save, L->d_mon};
   for (void *p : ptrs)
     if (p) (void)dev_free(L, p);
+  for (hipEvent_t ev : L->prof_ev)
+    if (ev) (void)hipEventDestroy(ev);
+  L->prof_ev.clear();
   if (L->cap_stream) (void)hipStreamDestroy(L->cap_stream);
   if (L->side) (void)hipStreamDestroy(L->side);
   if (L->ev_fork) (void)hipEventDestroy(L->ev_fork);
@@ -98,6 +101,7 @@ void gg_free_device(gg_lattice *L) {
 }
 
 gg_status gg_upload_desc(gg_lattice *L) {
+  ++L->gen;
   LatDesc &h = L->h;
   std::memset(&h, 0, sizeof(h));
   h.nx = L->nx;
@@ -265,6 +269,17 @@ static void build_strips(const gg_lattice *L, int h, int inst, bool split, std::
   }
 }
 
+// Fluid nodes owned by a list of pass tiles (62 columns x the rows in the
+// flags of each).
+static int64_t owned_fluid(const gg_lattice *L, const std::vector<Tile> &list) {
+  int64_t n = 0;
+  for (const Tile &t : list)
+    for (int y = t.y0; y < std::min(t.y0 + (t.flags >> 8), L->ny); ++y)
+      for (int x = t.x0; x < std::min(t.x0 + 62, L->nx); ++x)
+        n += L->link[L->nid(x, y)] != NOT_FLUID;
+  return n;
+}
+
 static bool has_pressure(const gg_lattice *L);
 
 gg_status gg_rebuild_tiles(gg_lattice *L) {
@@ -287,6 +302,8 @@ gg_status gg_rebuild_tiles(gg_lattice *L) {
   L->d_strips = L->d_seg_strips = nullptr;
   L->n_strips = (int)sv.size();
   L->n_seg_strips = (int)ss.size();
+  L->strips_fluid = owned_fluid(L, sv);
+  L->seg_strips_fluid = owned_fluid(L, ss);
   if (!sv.empty()) {
     GG_HIP(dev_alloc(L, (void **)&L->d_strips, sv.size() * sizeof(Tile)));
     GG_HIP(hipMemcpy(L->d_strips, sv.data(), sv.size() * sizeof(Tile), hipMemcpyHostToDevice));
@@ -686,6 +703,7 @@ gg_status gg_set_schedule(gg_lattice *L, const gg_phase *phases, int32_t n, int6
 
 gg_status gg_set_source(gg_lattice *L, const double *R, gg_where where) {
   if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  ++L->gen;
   if (L->d_R) (void)dev_free(L, L->d_R);
   L->d_R = nullptr;
   L->r_box[0] = L->r_box[1] = L->r_box[2] = L->r_box[3] = 0;
@@ -723,6 +741,7 @@ gg_status gg_set_source(gg_lattice *L, const double *R, gg_where where) {
 
 gg_status gg_set_region(gg_lattice *L, const uint8_t *region) {
   if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  ++L->gen;
   if (L->d_region) (void)dev_free(L, L->d_region);
   L->d_region = nullptr;
   if (region) {
@@ -839,13 +858,42 @@ static gg_status wall_nodes(gg_lattice *L) {
   return GG_OK;
 }
 
+// Profiling (gg_step_profile): an event recorded on st before a launch of
+// the dominant kernel (prof_begin returns its index, or -1 when profiling is
+// off) and one after it (prof_end, tagged with the launch's kind).
+static hipError_t prof_begin(gg_lattice *L, hipStream_t st, long &idx) {
+  idx = -1;
+  if (!L->prof) return hipSuccess;
+  while (L->prof_ev.size() < L->prof_used + 2) {
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return e;
+    L->prof_ev.push_back(ev);
+  }
+  idx = (long)L->prof_used;
+  L->prof_used += 2;
+  return hipEventRecord(L->prof_ev[idx], st);
+}
+
+static hipError_t prof_end(gg_lattice *L, hipStream_t st, long idx, int kind) {
+  if (idx < 0) return hipSuccess;
+  L->prof_kind.push_back((int8_t)kind);
+  return hipEventRecord(L->prof_ev[idx + 1], st);
+}
+
 static hipError_t launch_pass(gg_lattice *L, int dir, int dt, hipStream_t st) {
   hipError_t e = hipSuccess;
   const bool fork = L->n_seg_strips > 0 && L->n_strips > 0;
   const bool press = L->n_press > 0;  // (fuse 3 and 4 only)
-  if (L->fuse == 4)  // one kernel with the boundary rules for every tile
-    return launch_tile2(L->storage, true, L->strip_h, L->d_desc, L->d_strips, L->n_strips, dir, dt,
-                        st, press);
+  long pidx = -1;
+  if (L->fuse == 4) {  // one kernel with the boundary rules for every tile
+    e = prof_begin(L, st, pidx);
+    if (e == hipSuccess)
+      e = launch_tile2(L->storage, true, L->strip_h, L->d_desc, L->d_strips, L->n_strips, dir, dt,
+                       st, press);
+    if (e == hipSuccess) e = prof_end(L, st, pidx, 0);
+    return e;
+  }
   auto run = [&](bool seg, const Tile *list, int n, hipStream_t s) {
     // the segment list holds 2-row tiles
     return L->fuse == 3 ? launch_tile2(L->storage, seg, seg ? 2 : L->strip_h, L->d_desc, list, n,
@@ -860,7 +908,9 @@ static hipError_t launch_pass(gg_lattice *L, int dir, int dt, hipStream_t st) {
   } else if (L->n_seg_strips > 0) {
     e = run(true, L->d_seg_strips, L->n_seg_strips, st);
   }
+  if (e == hipSuccess) e = prof_begin(L, st, pidx);
   if (e == hipSuccess) e = run(false, L->d_strips, L->n_strips, st);
+  if (e == hipSuccess) e = prof_end(L, st, pidx, 0);
   if (fork && e == hipSuccess) e = hipStreamWaitEvent(st, L->ev_join, 0);
   return e;
 }
@@ -891,9 +941,12 @@ static hipError_t launch_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t
       if (L->n_wall > 0)
         e = launch_wall_save(L->storage, L->d_desc, L->d_wall, L->n_wall, L->d_wall_links,
                              L->n_wall_links, (int)dt, true, L->d_wall_save, st);
+      long pidx = -1;
+      if (e == hipSuccess) e = prof_begin(L, st, pidx);
       if (e == hipSuccess)
         e = launch_step(L->storage, block, ((t0 + dt) & 1) != 0, L->d_desc, L->d_tiles,
                         L->n_tiles, txs, (int)dt, st);
+      if (e == hipSuccess) e = prof_end(L, st, pidx, 1 + (int)((t0 + dt) & 1));
       if (e == hipSuccess && L->n_wall > 0)
         e = launch_wall_apply(L->storage, L->d_desc, L->d_wall_links, L->n_wall_links,
                               (int)dt, L->d_wall_save, true, st);
@@ -905,12 +958,9 @@ static hipError_t launch_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t
   return e;
 }
 
-gg_status gg_step(gg_lattice *L, int64_t n) {
-  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
-  if (n < 0) return fail(GG_ERR_ARG, "n must be non-negative");
-  gg_status st = check_segments(L);
-  if (st != GG_OK) return st;
-  if ((st = pressure_nodes(L)) != GG_OK || (st = wall_nodes(L)) != GG_OK) return st;
+// n steps without monitor reductions: an odd-t step first, then graph
+// replays (not while profiling), passes in groups of four, leftovers.
+static gg_status step_run(gg_lattice *L, int64_t n) {
   int64_t left = n;
   // graph chunk: even (a multiple of 4 with the two-step pass), so every
   // replay starts on an even step and leaves the state in the first plane set
@@ -920,7 +970,7 @@ gg_status gg_step(gg_lattice *L, int64_t n) {
     L->t += 1;
     left -= 1;
   }
-  if (K > 0 && left >= K) {
+  if (K > 0 && left >= K && !L->prof) {
     if (!L->graph_exec) {
       GG_HIP(hipStreamBeginCapture(L->cap_stream, hipStreamCaptureModeThreadLocal));
       hipError_t e = launch_steps(L, 0, K, L->cap_stream);
@@ -951,6 +1001,150 @@ gg_status gg_step(gg_lattice *L, int64_t n) {
     L->t += left;
   }
   return GG_OK;
+}
+
+// The FP64 reduction of gg_diagnostics into the monitor record, launched
+// on the lattice's stream at the current step; the flux accumulators are
+// copied beside the totals at the same point.
+static gg_status monitor_launch(gg_lattice *L) {
+  GG_HIP(launch_fill(L->d_mon, 8, 0.0, L->stream));
+  GG_HIP(launch_reduce(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6, L->d_partial,
+                       L->d_mon, L->stream));
+  GG_HIP(hipMemcpyAsync(L->d_mon + 8, L->d_flux, 2 * GG_MAX_SEGMENTS * sizeof(double),
+                        hipMemcpyDeviceToDevice, L->stream));
+  L->mon_last_t = L->t;
+  L->mon_count += 1;
+  return GG_OK;
+}
+
+static int64_t steps_to_monitor(const gg_lattice *L) {
+  const int64_t k = L->mon_every;
+  const int64_t r = ((L->t - L->mon_t0) % k + k) % k;
+  return k - r;
+}
+
+gg_status gg_step(gg_lattice *L, int64_t n) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (n < 0) return fail(GG_ERR_ARG, "n must be non-negative");
+  gg_status st = check_segments(L);
+  if (st != GG_OK) return st;
+  if ((st = pressure_nodes(L)) != GG_OK || (st = wall_nodes(L)) != GG_OK) return st;
+  if (L->mon_every <= 0) return step_run(L, n);
+  int64_t left = n;
+  while (left > 0) {
+    const int64_t run = std::min(left, steps_to_monitor(L));
+    if ((st = step_run(L, run)) != GG_OK) return st;
+    left -= run;
+    if (steps_to_monitor(L) == L->mon_every && (st = monitor_launch(L)) != GG_OK) return st;
+  }
+  return GG_OK;
+}
+
+gg_status gg_set_monitor(gg_lattice *L, int64_t every) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (every < 0) return fail(GG_ERR_ARG, "every must be non-negative");
+  if (every > 0) {
+    if (!L->d_mon && dev_alloc(L, (void **)&L->d_mon, (8 + 2 * GG_MAX_SEGMENTS) * sizeof(double)) != hipSuccess) {
+      L->d_mon = nullptr;
+      return fail(GG_ERR_OOM, "monitor record");
+    }
+    if (!L->d_partial && L->n_aux_tiles > 0 &&
+        dev_alloc(L, (void **)&L->d_partial, (size_t)6 * L->n_aux_tiles * sizeof(double)) != hipSuccess) {
+      L->d_partial = nullptr;
+      return fail(GG_ERR_OOM, "diagnostics partials");
+    }
+  }
+  L->mon_every = every;
+  L->mon_t0 = L->t;
+  L->mon_last_t = -1;
+  L->mon_count = 0;
+  return GG_OK;
+}
+
+static void fill_diag(const gg_lattice *L, const double *acc, const double *flux, int64_t t,
+                      gg_diag *out) {
+  std::memset(out, 0, sizeof(*out));
+  out->t = t;
+  out->n_fluid = L->n_fluid;
+  out->n_nonfinite = (int64_t)acc[4];
+  out->mass = acc[0];
+  out->solute = acc[1];
+  out->max_u = acc[2];
+  out->max_u_region = acc[3];
+  out->max_pe_region = acc[3] / L->p.D;
+  for (int s = 0; s < GG_MAX_SEGMENTS; ++s) {
+    out->seg_mass[s] = flux[2 * s];
+    out->seg_solute[s] = flux[2 * s + 1];
+    if (!L->seg[s].set) continue;
+    if (L->seg[s].kind == GG_SEG_INLET) {
+      out->mass_in += flux[2 * s];
+      out->solute_in += flux[2 * s + 1];
+    } else {
+      out->mass_out += flux[2 * s];
+      out->solute_out += flux[2 * s + 1];
+    }
+  }
+}
+
+gg_status gg_monitor_read(gg_lattice *L, gg_diag *out, int64_t *count) {
+  if (!L || !out) return fail(GG_ERR_ARG, "NULL argument");
+  if (L->mon_count == 0 || !L->d_mon) return fail(GG_ERR_STATE, "no monitor reduction has run");
+  double rec[8 + 2 * GG_MAX_SEGMENTS];
+  GG_HIP(hipStreamSynchronize(L->stream));
+  GG_HIP(hipMemcpy(rec, L->d_mon, sizeof(rec), hipMemcpyDeviceToHost));
+  fill_diag(L, rec, rec + 8, L->mon_last_t, out);
+  if (count) *count = L->mon_count;
+  if (out->n_nonfinite > 0)
+    return fail(GG_ERR_NONFINITE, std::to_string(out->n_nonfinite) + " fluid nodes held non-finite populations at step " + std::to_string(out->t));
+  return GG_OK;
+}
+
+gg_status gg_step_profile(gg_lattice *L, int64_t n, gg_profile *out) {
+  if (!L || !out) return fail(GG_ERR_ARG, "NULL argument");
+  std::memset(out, 0, sizeof(*out));
+  hipEvent_t a = nullptr, b = nullptr;
+  GG_HIP(hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(GG_ERR_HIP, "event creation");
+  }
+  const int64_t mon0 = L->mon_count;
+  L->prof = true;
+  L->prof_used = 0;
+  L->prof_kind.clear();
+  hipError_t e = hipEventRecord(a, L->stream);
+  gg_status st = e == hipSuccess ? gg_step(L, n) : fail(GG_ERR_HIP, hipGetErrorString(e));
+  L->prof = false;
+  if (st == GG_OK && (e = hipEventRecord(b, L->stream)) == hipSuccess)
+    e = hipStreamSynchronize(L->stream);
+  if (st == GG_OK && e != hipSuccess) st = fail(GG_ERR_HIP, std::string("profile: ") + hipGetErrorString(e));
+  float ms = 0.0f;
+  if (st == GG_OK && (e = hipEventElapsedTime(&ms, a, b)) != hipSuccess)
+    st = fail(GG_ERR_HIP, std::string("profile: ") + hipGetErrorString(e));
+  out->ms_total = ms;
+  for (size_t k = 0; k < L->prof_kind.size() && st == GG_OK; ++k) {
+    float x = 0.0f;
+    if ((e = hipEventElapsedTime(&x, L->prof_ev[2 * k], L->prof_ev[2 * k + 1])) != hipSuccess) {
+      st = fail(GG_ERR_HIP, std::string("profile: ") + hipGetErrorString(e));
+      break;
+    }
+    const int kind = L->prof_kind[k];
+    if (kind == 0) {
+      out->n_pass += 1;
+      out->ms_pass += x;
+    } else {
+      out->n_single[kind - 1] += 1;
+      out->ms_single[kind - 1] += x;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  out->n_monitor = L->mon_count - mon0;
+  out->fuse = pass_ok(L) ? L->fuse : 1;
+  out->rows = L->strip_h;
+  out->pass_fluid = L->fuse == 4 ? L->n_fluid : L->strips_fluid;
+  out->pass_side_fluid = L->fuse == 4 ? 0 : L->seg_strips_fluid;
+  return st;
 }
 
 static gg_status gg_read_impl(gg_lattice *L, double *rho, double *ux, double *uy, double *C,
@@ -1017,27 +1211,7 @@ gg_status gg_diagnostics(gg_lattice *L, gg_diag *out) {
   GG_HIP(hipMemcpy(acc, L->d_acc, sizeof(acc), hipMemcpyDeviceToHost));
   GG_HIP(hipMemcpy(flux, L->d_flux, sizeof(flux), hipMemcpyDeviceToHost));
   GG_HIP(hipMemcpy(&t, L->d_t, sizeof(t), hipMemcpyDeviceToHost));
-  std::memset(out, 0, sizeof(*out));
-  out->t = t;
-  out->n_fluid = L->n_fluid;
-  out->n_nonfinite = (int64_t)acc[4];
-  out->mass = acc[0];
-  out->solute = acc[1];
-  out->max_u = acc[2];
-  out->max_u_region = acc[3];
-  out->max_pe_region = acc[3] / L->p.D;
-  for (int s = 0; s < GG_MAX_SEGMENTS; ++s) {
-    out->seg_mass[s] = flux[2 * s];
-    out->seg_solute[s] = flux[2 * s + 1];
-    if (!L->seg[s].set) continue;
-    if (L->seg[s].kind == GG_SEG_INLET) {
-      out->mass_in += flux[2 * s];
-      out->solute_in += flux[2 * s + 1];
-    } else {
-      out->mass_out += flux[2 * s];
-      out->solute_out += flux[2 * s + 1];
-    }
-  }
+  fill_diag(L, acc, flux, t, out);
   if (out->n_nonfinite > 0)
     return fail(GG_ERR_NONFINITE, std::to_string(out->n_nonfinite) + " fluid nodes hold non-finite populations");
   return GG_OK;
@@ -1128,6 +1302,7 @@ gg_status gg_set_two_step(gg_lattice *L, int32_t fuse, int32_t strip_h) {
   if (fuse >= 3 && strip_h != 6 && strip_h != 14)
     return fail(GG_ERR_ARG, "row-parallel tiles have 6 or 14 rows");
   GG_HIP(hipStreamSynchronize(L->stream));
+  ++L->gen;
   if (fuse >= 2 && !L->d_pop_b) {
     const size_t pop_bytes = (size_t)NPOP * L->plane * L->esize;
     hipError_t e = dev_alloc(L, (void **)&L->d_pop_b, pop_bytes);
@@ -1305,6 +1480,10 @@ struct gg_batch {
   int64_t steps = 0;  // steps taken by the batch
   int64_t n_fluid = 0;
   std::vector<int64_t> t_created;  // member times when the batch was made
+  // member configuration generations and second plane sets as copied into
+  // the batch's descriptors at creation
+  std::vector<uint64_t> gen_created;
+  std::vector<uint8_t> pop_b_created;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   // two-step pass over all members (fuse 3 or 4, tiles of `rows` rows)
@@ -1339,6 +1518,17 @@ static bool batch_passes(const gg_batch *B, int64_t s0, int64_t n) {
 }
 
 // n steps of the batch on `st` (group parity from the batch's step count)
+// The batch's copies of the members' descriptors still describe them: no
+// member was reconfigured (buffers freed or reallocated, parameters
+// changed) since the batch was made.
+static gg_status batch_check_members(const gg_batch *B) {
+  for (size_t k = 0; k < B->lats.size(); ++k)
+    if (B->lats[k]->gen != B->gen_created[k])
+      return fail(GG_ERR_STATE, "batch member " + std::to_string(k) +
+                                    " was reconfigured after the batch was made; make a new batch");
+  return GG_OK;
+}
+
 static hipError_t batch_launch(gg_batch *B, int64_t s0, int64_t n, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (batch_passes(B, s0, n)) {
@@ -1418,6 +1608,8 @@ gg_status gg_batch_create(gg_lattice *const *lats, int32_t n, int32_t tile_x, in
     build_tiles(lats[k], tile_x, tile_y, k, tiles[lats[k]->t & 1]);
     B->n_fluid += lats[k]->n_fluid;
     B->t_created.push_back(lats[k]->t);
+    B->gen_created.push_back(lats[k]->gen);
+    B->pop_b_created.push_back(descs[k].pop_b != nullptr);
   }
   hipError_t e = hipStreamSynchronize(B->stream);
   if (e == hipSuccess) e = hipMalloc(&B->d_descs, n * sizeof(LatDesc));
@@ -1452,6 +1644,8 @@ gg_status gg_batch_step(gg_batch *B, int64_t n) {
       return fail(GG_ERR_STATE, "batch member " + std::to_string(k) +
                                     " has a pressure boundary or the paper's walls");
   }
+  gg_status cst = batch_check_members(B);
+  if (cst != GG_OK) return cst;
   int64_t left = n;
   const int K = B->chunk;
   if (B->fuse >= 3) {
@@ -1535,8 +1729,10 @@ gg_status gg_batch_set_two_step(gg_batch *B, int32_t fuse, int32_t rows) {
   if (fuse >= 3 && rows != 6 && rows != 14) return fail(GG_ERR_ARG, "tiles have 6 or 14 rows");
   if (fuse >= 3 && B->n_tiles[0] > 0 && B->n_tiles[1] > 0)
     return fail(GG_ERR_STATE, "the two-step pass needs all members at steps of one parity");
+  gg_status cst = batch_check_members(B);
+  if (cst != GG_OK) return cst;
   for (size_t k = 0; k < B->lats.size() && fuse >= 3; ++k)
-    if (!B->lats[k]->d_pop_b)
+    if (!B->lats[k]->d_pop_b || !B->pop_b_created[k])
       return fail(GG_ERR_STATE, "member " + std::to_string(k) +
                                     " has no second plane set (gg_set_two_step with fuse >= 2)");
   GG_HIP(hipStreamSynchronize(B->stream));
@@ -1707,6 +1903,7 @@ static gg_status grow_fields(gg_lattice *L, int n) {
     (void)dev_free(L, p);
     return fail(GG_ERR_HIP, std::string("velocity fields: ") + hipGetErrorString(e));
   }
+  ++L->gen;
   if (L->d_ufield) GG_HIP(dev_free(L, L->d_ufield));
   L->d_ufield = p;
   L->n_ufield = n;

@@ -201,6 +201,37 @@ class Lattice:
         A.call("gg_step_timed", self._h, int(n), ctypes.byref(a), ctypes.byref(b))
         return a.value, b.value
 
+    def step_profile(self, n: int) -> dict:
+        """gg_step_profile: n steps with plain launches and HIP events
+        around every launch of the dominant kernel (two-step pass or single
+        step); durations in milliseconds."""
+        p = A.gg_profile()
+        A.call("gg_step_profile", self._h, int(n), ctypes.byref(p))
+        return {"ms_total": p.ms_total, "n_pass": p.n_pass, "ms_pass": p.ms_pass,
+                "n_single": list(p.n_single), "ms_single": list(p.ms_single),
+                "n_monitor": p.n_monitor, "pass_fluid": p.pass_fluid,
+                "pass_side_fluid": p.pass_side_fluid, "fuse": p.fuse, "rows": p.rows}
+
+    def set_monitor(self, every: int) -> None:
+        """FP64 diagnostics reduced on the GPU after every `every` steps of
+        gg_step, without waiting (0 turns the monitor off)."""
+        A.call("gg_set_monitor", self._h, int(every))
+
+    def monitor(self, check_finite: bool = True) -> dict:
+        """The last monitor reduction (gg_monitor_read) and the number of
+        reductions since set_monitor."""
+        d = A.gg_diag()
+        cnt = ctypes.c_int64()
+        st = A.lib().gg_monitor_read(self._h, ctypes.byref(d), ctypes.byref(cnt))
+        if st != A.GG_OK and (check_finite or st != A.GG_ERR_NONFINITE):
+            A.check(st, "gg_monitor_read")
+        out = {k: getattr(d, k) for k, _ in A.gg_diag._fields_
+               if k not in ("seg_mass", "seg_solute")}
+        out["seg_mass"] = np.array(d.seg_mass[:])
+        out["seg_solute"] = np.array(d.seg_solute[:])
+        out["count"] = cnt.value
+        return out
+
     def sync(self) -> None:
         A.call("gg_sync", self._h)
 

@@ -1,0 +1,43 @@
+"""bench.py under the arguments the benchmark driver passes (and an odd
+combination): one JSON line with the roofline block, the timed steps all
+accounted for, and the monitor reductions inside the timed region."""
+import json
+
+import pytest
+
+import bench
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(capsys, argv):
+    out = bench.main(argv)
+    lines = [l for l in capsys.readouterr().out.splitlines() if l.strip()]
+    assert len(lines) == 1
+    line = json.loads(lines[0])
+    assert line == json.loads(json.dumps(out))
+    return line
+
+
+@pytest.mark.parametrize("argv, workload", [
+    (["--gpus", "1", "--steps", "20", "--warmup", "5"], "gradient_generator_8192x4096"),
+    (["--gpus", "1", "--steps", "7", "--warmup", "3", "--workload", "gg2048_f32"],
+     "gradient_generator_2048x1024"),
+])
+def test_bench_line(capsys, argv, workload):
+    line = _run(capsys, argv + ["--no-extra", "--no-cpu-baseline"])
+    steps = int(argv[argv.index("--steps") + 1])
+    assert line["steps"] == steps and line["n_gpus"] == 1
+    assert line["config"]["workload"] == workload
+    assert line["value"] > 0 and line["ms_per_step"] > 0
+    launches = line["config"]["launches"]
+    # every timed step is a pass step (two per launch) or a single step
+    assert 2 * launches["pass_kernel"] + launches["single_even"] + launches["single_odd"] == steps
+    assert launches["pass_kernel"] == steps // 4 * 2
+    assert line["config"]["warmup_steps_run"] % 4 == 0
+    rf = line["roofline"]
+    assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
+    assert rf["achieved"] > 0 and rf["frac"] == pytest.approx(rf["achieved"] / 8000.0, rel=1e-3)
+    assert line["config"]["monitor_reductions"] >= 1
+    d = line["diagnostics"]
+    assert d["n_nonfinite"] == 0 and d["mass"] > 0

@@ -95,3 +95,41 @@ def test_digest_scales_counters_by_the_copy_kernel(tmp_path):
     assert w["algorithmic_bytes_per_launch"] == n_fluid * (14 * 2 * 8 + 1)
     assert w["bytes_per_launch"] == round(1100.0 * 1024 * 2) + 500 * 1024
     assert json.loads(out.read_text())["kernel_sha"] == bench.kernel_hash()
+
+
+def test_bench_alignment_steps():
+    # the timed region starts where a run of two-step passes can start
+    for t in range(0, 13):
+        a = bench.align_steps(t)
+        assert 0 <= a < 4 and (t + a) % 4 == 0
+
+
+def _fake_run(nf, steps, event_ms, prof):
+    return {"nf": nf, "steps": steps, "event_ms": event_ms, "prof": prof}
+
+
+def test_bench_roofline_pass_and_single():
+    prof = {"n_pass": 10, "ms_pass": 1.0, "n_single": [0, 0], "ms_single": [0.0, 0.0],
+            "pass_fluid": 1000000, "fuse": 3}
+    r = _fake_run(1100000, 20, 2.0, prof)
+    out = bench.roofline(r, "f16", traffic=None)
+    # two updates of 57 B per fluid node of the pass's tiles per launch
+    assert out["algorithmic_bytes_per_launch"] == 2 * 1000000 * 57
+    assert out["kernel_ms"] == pytest.approx(0.1)
+    assert out["achieved"] == pytest.approx(2 * 1000000 * 57 / 1e-4 / 1e9, rel=1e-3)
+    assert out["frac"] == pytest.approx(out["achieved"] / 8000.0, rel=1e-3)
+    assert "traffic_frac" not in out
+    out = bench.roofline(r, "f16", traffic=60000000)
+    assert out["traffic_gbs"] == pytest.approx(60000000 / 1e-4 / 1e9, rel=1e-3)
+    assert out["traffic_per_algorithmic_single_trip"] == pytest.approx(60 / 57, rel=1e-3)
+    prof = {"n_pass": 0, "ms_pass": 0.0, "n_single": [3, 2], "ms_single": [0.3, 0.2],
+            "pass_fluid": 0, "fuse": 1}
+    out = bench.roofline(_fake_run(500000, 5, 1.0, prof), "f32", traffic=None)
+    assert out["algorithmic_bytes_per_launch"] == 500000 * 113
+    assert out["kernel_ms"] == pytest.approx(0.1)
+
+
+def test_bench_refuses_several_gpus():
+    with pytest.raises(SystemExit) as e:
+        bench.main(["--gpus", "2"])
+    assert e.value.code == 2
