@@ -75,9 +75,13 @@ hipError_t launch_read(gg_storage s, const LatDesc *d, const Tile *tiles, int n_
                        int tx_shift, double *rho, double *ux, double *uy, double *c,
                        double *f, double *g, hipStream_t st);
 // FP64 diagnostics into acc[0..5] (mass, solute, max|u|, region max|u|,
-// non-finite count, fluid count) through partial[6 * n_tiles].
+// non-finite count, fluid count) through partial[6 * groups], groups =
+// n_tiles (one work-group per tile) or, with max_groups > 0, at most
+// max_groups work-groups that each fold every groups-th tile. Every partial
+// and acc[0..5] are written, nothing needs clearing beforehand.
 hipError_t launch_reduce(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
-                         int tx_shift, double *partial, double *acc, hipStream_t st);
+                         int tx_shift, double *partial, double *acc, hipStream_t st,
+                         int max_groups = 0);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
 // Pressure boundary: after step (device counter + dt), rescale the state at
 // t + 1 of the n nodes listed as (x, y, candidates) triples that take a

@@ -264,19 +264,20 @@ template <class S>
 __global__ void __launch_bounds__(256)
     k_reduce(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles,
              int n_tiles, int tx_shift, double *__restrict__ partial) {
+  // Work-group b folds tiles b, b + gridDim.x, ... (one tile each when the
+  // grid has a work-group per tile) into partial[6 * b .. 6 * b + 5].
   using T = typename Pop<S>::T;
   __shared__ double lds[4][6];
-  const int tile = blockIdx.x;
-  if (tile >= n_tiles) return;
-  const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
   CDesc &L = *(CDesc *)desc;
   const int tmask = (1 << tx_shift) - 1;
-  const int x = tl.x0 + (int)(threadIdx.x & tmask);
-  const int y = tl.y0 + (int)(threadIdx.x >> tx_shift);
-  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
-  const uint8_t lc = (x < L.nx && y < L.ny) ? ((const GG_GLOBAL uint8_t *)L.link)[node] : NOT_FLUID;
   double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (lc != NOT_FLUID) {
+  for (int tile = (int)blockIdx.x; tile < n_tiles; tile += (int)gridDim.x) {
+    const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
+    const int x = tl.x0 + (int)(threadIdx.x & tmask);
+    const int y = tl.y0 + (int)(threadIdx.x >> tx_shift);
+    const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+    const uint8_t lc = (x < L.nx && y < L.ny) ? ((const GG_GLOBAL uint8_t *)L.link)[node] : NOT_FLUID;
+    if (lc == NOT_FLUID) continue;
     T fT[9], gT[5];
     gather<S>(L, node, lc, x, y, fT, gT);
     double rho = 0.0, jx = 0.0, jy = 0.0, C = 0.0;  // deviations first
@@ -295,14 +296,15 @@ __global__ void __launch_bounds__(256)
     }
     rho += L.rho0;
     C += L.c_shift;
-    v[5] = 1.0;
+    v[5] += 1.0;
     if (finite) {
-      v[0] = rho;
-      v[1] = C;
-      v[2] = sqrt(jx * jx + jy * jy) / rho;
-      if (L.has_region && ((const GG_GLOBAL uint8_t *)L.region)[node]) v[3] = v[2];
+      v[0] += rho;
+      v[1] += C;
+      const double um = sqrt(jx * jx + jy * jy) / rho;
+      v[2] = fmax(v[2], um);
+      if (L.has_region && ((const GG_GLOBAL uint8_t *)L.region)[node]) v[3] = fmax(v[3], um);
     } else {
-      v[4] = 1.0;
+      v[4] += 1.0;
     }
   }
   const int w = (int)(threadIdx.x >> 6);
@@ -317,7 +319,7 @@ __global__ void __launch_bounds__(256)
     double r = lds[0][k];
     for (int q = 1; q < (int)(blockDim.x >> 6); ++q)
       r = (k == 2 || k == 3) ? fmax(r, lds[q][k]) : r + lds[q][k];
-    partial[6 * tile + k] = r;
+    partial[6 * blockIdx.x + k] = r;
   }
 }
 
@@ -457,14 +459,16 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st) {
 }
 
 hipError_t launch_reduce(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
-                         int tx_shift, double *partial, double *acc, hipStream_t st) {
+                         int tx_shift, double *partial, double *acc, hipStream_t st,
+                         int max_groups) {
   if (n_tiles <= 0) return hipSuccess;
+  const int groups = max_groups > 0 ? std::min(n_tiles, max_groups) : n_tiles;
   switch (s) {
-    case GG_F64: k_reduce<double><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, partial); break;
-    case GG_F32: k_reduce<float><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, partial); break;
-    case GG_F16_SHIFTED: k_reduce<__half><<<n_tiles, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, partial); break;
+    case GG_F64: k_reduce<double><<<groups, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, partial); break;
+    case GG_F32: k_reduce<float><<<groups, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, partial); break;
+    case GG_F16_SHIFTED: k_reduce<__half><<<groups, 256, 0, st>>>(d, tiles, n_tiles, tx_shift, partial); break;
   }
-  k_reduce_final<<<1, 256, 0, st>>>(partial, n_tiles, acc);
+  k_reduce_final<<<1, 256, 0, st>>>(partial, groups, acc);
   return hipGetLastError();
 }
 

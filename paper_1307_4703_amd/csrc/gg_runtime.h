@@ -27,6 +27,7 @@ struct gg_lattice {
   size_t esize = 4;
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
+  int device = 0;  // the HIP device current at creation (owns every buffer)
   gg_params p{};
   double tau_g = 0.0, cs2g = 0.0;
   std::vector<uint8_t> mask;         // nx*ny
@@ -123,6 +124,11 @@ struct gg_lattice {
 };
 
 gg_status gg_upload_desc(gg_lattice *L);
+// Record msg as this thread's last error and return s.
+gg_status gg_fail(gg_status s, const std::string &msg);
+// gg_diag from the reduction totals acc[0..5] and the flux accumulators.
+void gg_fill_diag(const gg_lattice *L, const double *acc, const double *flux, int64_t t,
+                  gg_diag *out);
 gg_status gg_rebuild_tiles(gg_lattice *L);
 void gg_free_device(gg_lattice *L);
 void gg_drop_cde_graphs(gg_lattice *L);

@@ -66,6 +66,34 @@ hipError_t dev_free(const gg_lattice *L, void *p) {
 
 }  // namespace
 
+gg_status gg_fail(gg_status s, const std::string &msg) { return fail(s, msg); }
+
+void gg_fill_diag(const gg_lattice *L, const double *acc, const double *flux, int64_t t,
+                  gg_diag *out) {
+  std::memset(out, 0, sizeof(*out));
+  out->t = t;
+  out->n_fluid = L->n_fluid;
+  out->n_nonfinite = (int64_t)acc[4];
+  out->mass = acc[0];
+  out->solute = acc[1];
+  out->max_u = acc[2];
+  out->max_u_region = acc[3];
+  out->max_pe_region = acc[3] / L->p.D;
+  for (int s = 0; s < GG_MAX_SEGMENTS; ++s) {
+    out->seg_mass[s] = flux[2 * s];
+    out->seg_solute[s] = flux[2 * s + 1];
+    if (!L->seg[s].set) continue;
+    if (L->seg[s].kind == GG_SEG_INLET) {
+      out->mass_in += flux[2 * s];
+      out->solute_in += flux[2 * s + 1];
+    } else {
+      out->mass_out += flux[2 * s];
+      out->solute_out += flux[2 * s + 1];
+    }
+  }
+}
+
+
 // ---------------------------------------------------------------------------
 // Lattice object
 // ---------------------------------------------------------------------------
@@ -456,6 +484,10 @@ gg_status gg_create_ex(const uint8_t *mask, int32_t nx, int32_t ny, const gg_par
       }
     }
 
+  if (hipGetDevice(&L->device) != hipSuccess) {
+    delete L;
+    return fail(GG_ERR_HIP, "hipGetDevice failed");
+  }
   auto alloc = [&](void **p, size_t bytes) -> gg_status {
     hipError_t e = dev_alloc(L, p, bytes);
     if (e != hipSuccess) return fail(GG_ERR_OOM, std::string("device allocation: ") + hipGetErrorString(e));
@@ -1061,38 +1093,13 @@ gg_status gg_set_monitor(gg_lattice *L, int64_t every) {
   return GG_OK;
 }
 
-static void fill_diag(const gg_lattice *L, const double *acc, const double *flux, int64_t t,
-                      gg_diag *out) {
-  std::memset(out, 0, sizeof(*out));
-  out->t = t;
-  out->n_fluid = L->n_fluid;
-  out->n_nonfinite = (int64_t)acc[4];
-  out->mass = acc[0];
-  out->solute = acc[1];
-  out->max_u = acc[2];
-  out->max_u_region = acc[3];
-  out->max_pe_region = acc[3] / L->p.D;
-  for (int s = 0; s < GG_MAX_SEGMENTS; ++s) {
-    out->seg_mass[s] = flux[2 * s];
-    out->seg_solute[s] = flux[2 * s + 1];
-    if (!L->seg[s].set) continue;
-    if (L->seg[s].kind == GG_SEG_INLET) {
-      out->mass_in += flux[2 * s];
-      out->solute_in += flux[2 * s + 1];
-    } else {
-      out->mass_out += flux[2 * s];
-      out->solute_out += flux[2 * s + 1];
-    }
-  }
-}
-
 gg_status gg_monitor_read(gg_lattice *L, gg_diag *out, int64_t *count) {
   if (!L || !out) return fail(GG_ERR_ARG, "NULL argument");
   if (L->mon_count == 0 || !L->d_mon) return fail(GG_ERR_STATE, "no monitor reduction has run");
   double rec[8 + 2 * GG_MAX_SEGMENTS];
   GG_HIP(hipStreamSynchronize(L->stream));
   GG_HIP(hipMemcpy(rec, L->d_mon, sizeof(rec), hipMemcpyDeviceToHost));
-  fill_diag(L, rec, rec + 8, L->mon_last_t, out);
+  gg_fill_diag(L, rec, rec + 8, L->mon_last_t, out);
   if (count) *count = L->mon_count;
   if (out->n_nonfinite > 0)
     return fail(GG_ERR_NONFINITE, std::to_string(out->n_nonfinite) + " fluid nodes held non-finite populations at step " + std::to_string(out->t));
@@ -1211,7 +1218,7 @@ gg_status gg_diagnostics(gg_lattice *L, gg_diag *out) {
   GG_HIP(hipMemcpy(acc, L->d_acc, sizeof(acc), hipMemcpyDeviceToHost));
   GG_HIP(hipMemcpy(flux, L->d_flux, sizeof(flux), hipMemcpyDeviceToHost));
   GG_HIP(hipMemcpy(&t, L->d_t, sizeof(t), hipMemcpyDeviceToHost));
-  fill_diag(L, acc, flux, t, out);
+  gg_fill_diag(L, acc, flux, t, out);
   if (out->n_nonfinite > 0)
     return fail(GG_ERR_NONFINITE, std::to_string(out->n_nonfinite) + " fluid nodes hold non-finite populations");
   return GG_OK;
