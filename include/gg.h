@@ -440,6 +440,23 @@ gg_status gg_stream_copy(void *dst, const void *src, size_t bytes, int32_t reps,
 typedef enum gg_wall_scheme { GG_WALL_BOUNCE_BACK = 0, GG_WALL_PAPER = 1 } gg_wall_scheme;
 gg_status gg_set_wall_scheme(gg_lattice *lat, int32_t scheme);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * diagnostics of gg_diagnostics, with the reduction's partial records in a
+ * fixed array of 6 * 2048 + 8 doubles (98,368 bytes) that the library
+ * holds in device memory on every GPU it runs on until the process ends,
+ * instead of the per-lattice buffer gg_diagnostics allocates on first use.
+ * The reduction runs at most 2048 work-groups, each folding every 2048-th
+ * 64 x 4 tile, so the array fits every lattice: no lattice is too large.
+ * Calls no hipMalloc or hipFree (the array's device address is looked up
+ * once per GPU). Calls that overlap on one GPU (other threads, other
+ * lattices) race on the one array: serialise them. The totals can differ
+ * from gg_diagnostics' in the last bits (another summation order); maxima,
+ * counts and boundary fluxes are the same. Waits for the lattice's stream.
+ * Errors: GG_ERR_ARG (NULL argument), GG_ERR_HIP, GG_ERR_NONFINITE (with
+ * *out filled). */
+gg_status gg_diagnostics_noalloc(gg_lattice *lat, gg_diag *out);
+
 /* Monitor (the diagnostics of the Results section on the hot path: the
  * flow in the chamber must stay negligible, Abstract and Results; cell
  * Peclet number of Eq. 12; mass and compound totals of the conservation

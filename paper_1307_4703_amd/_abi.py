@@ -128,6 +128,7 @@ SIGS = {
     "gg_set_monitor": [P, I64],
     "gg_monitor_read": [P, ctypes.POINTER(gg_diag), ctypes.POINTER(I64)],
     "gg_step_profile": [P, I64, ctypes.POINTER(gg_profile)],
+    "gg_diagnostics_noalloc": [P, ctypes.POINTER(gg_diag)],
 }
 
 

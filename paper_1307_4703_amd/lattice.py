@@ -318,11 +318,14 @@ class Lattice:
         A.call("gg_read_populations", self._h, _dptr(f), _dptr(g), A.GG_HOST)
         return f, g
 
-    def diagnostics(self, check_finite: bool = True) -> dict:
+    def diagnostics(self, check_finite: bool = True, noalloc: bool = False) -> dict:
+        """FP64 diagnostics (gg_diagnostics, or gg_diagnostics_noalloc with
+        the reduction in the library's fixed device array)."""
         d = A.gg_diag()
-        st = A.lib().gg_diagnostics(self._h, ctypes.byref(d))
+        fn = "gg_diagnostics_noalloc" if noalloc else "gg_diagnostics"
+        st = getattr(A.lib(), fn)(self._h, ctypes.byref(d))
         if st != A.GG_OK and (check_finite or st != A.GG_ERR_NONFINITE):
-            A.check(st, "gg_diagnostics")
+            A.check(st, fn)
         out = {k: getattr(d, k) for k, _ in A.gg_diag._fields_
                if k not in ("seg_mass", "seg_solute")}
         out["seg_mass"] = np.array(d.seg_mass[:])
