@@ -130,3 +130,28 @@ def test_autotuner_picks_and_caches(tmp_path):
     rb = tune.tune_batch(lats, steps=8, tiles=((64, 4), (32, 8)), persist=(0, 256),
                          two_step=((4, 6),), path=path)
     assert len(rb["all"]) == 5 and rb["persist"] in (0, 256) and rb["fuse"] in (1, 4)
+
+
+def test_batch_refuses_reconfigured_members():
+    """A batch copies its members' descriptors; a member reconfigured after
+    the batch was made (its second plane set freed and reallocated, its
+    schedule or source changed) makes the batch refuse to run."""
+    wls = _members()[:2]
+    for change in ("two_step", "schedule", "source"):
+        lats = _make(wls)
+        b = Batch(lats, fuse=3, rows=6)
+        b.step(4)
+        if change == "two_step":
+            lats[1].set_two_step(1)
+            lats[1].set_two_step(3, 6)
+        elif change == "schedule":
+            lats[0].set_schedule(wls[0].schedule)
+        else:
+            lats[0].set_source(np.zeros(wls[0].mask.shape))
+        with pytest.raises(A.GGError) as e:
+            b.step(4)
+        assert e.value.status == A.GG_ERR_STATE
+        with pytest.raises(A.GGError) as e:
+            b.set_two_step(4, 6)
+        assert e.value.status == A.GG_ERR_STATE
+        b.close()
