@@ -62,6 +62,9 @@ struct LatDesc {
   double rho0;              // reference density (inlet/outlet links)
   double k_decay;
   double c_shift;           // C_s: the planes hold g_i - w_i C_s
+  // the same constants rounded to FP32 once on the host, for the FP32
+  // compute type (the kernels read them as they are)
+  float rho0_f, omega_f_f, omega_g_f, wg_axis_f, inv_cs2g_f, k_decay_f, c_shift_f, kpad_f;
   // segments, index id - GG_FIRST_SEGMENT
   int32_t seg_kind[GG_MAX_SEGMENTS];
   int32_t seg_nx[GG_MAX_SEGMENTS];

@@ -47,6 +47,46 @@ template <> struct SegT<float> {
   static __device__ __forceinline__ float rho(CDesc &L, int s) { return L.seg_rho_f[s]; }
 };
 
+// Lattice constants in the compute type T: the descriptor's FP64 values, or
+// their FP32 roundings stored beside them (no conversion in the kernels).
+template <class T> struct DK;
+template <> struct DK<double> {
+  static __device__ __forceinline__ double rho0(CDesc &L) { return L.rho0; }
+  static __device__ __forceinline__ double om_f(CDesc &L) { return L.omega_f; }
+  static __device__ __forceinline__ double om_g(CDesc &L) { return L.omega_g; }
+  static __device__ __forceinline__ double wga(CDesc &L) { return L.wg_axis; }
+  static __device__ __forceinline__ double ics(CDesc &L) { return L.inv_cs2g; }
+  static __device__ __forceinline__ double kdec(CDesc &L) { return L.k_decay; }
+  static __device__ __forceinline__ double cs(CDesc &L) { return L.c_shift; }
+};
+template <> struct DK<float> {
+  static __device__ __forceinline__ float rho0(CDesc &L) { return L.rho0_f; }
+  static __device__ __forceinline__ float om_f(CDesc &L) { return L.omega_f_f; }
+  static __device__ __forceinline__ float om_g(CDesc &L) { return L.omega_g_f; }
+  static __device__ __forceinline__ float wga(CDesc &L) { return L.wg_axis_f; }
+  static __device__ __forceinline__ float ics(CDesc &L) { return L.inv_cs2g_f; }
+  static __device__ __forceinline__ float kdec(CDesc &L) { return L.k_decay_f; }
+  static __device__ __forceinline__ float cs(CDesc &L) { return L.c_shift_f; }
+};
+
+// e_i . u for direction i (paper Eq. 3 velocities), written out per
+// direction: the same value as e_x u_x + e_y u_y, without the products by
+// zero and one that IEEE arithmetic would otherwise have to carry out (the
+// rest direction gives +0).
+template <class T> __device__ __forceinline__ T e_dot_u(int i, T ux, T uy) {
+  switch (i) {
+    case 0: return T(0);
+    case 1: return ux;
+    case 2: return uy;
+    case 3: return -ux;
+    case 4: return -uy;
+    case 5: return ux + uy;
+    case 6: return uy - ux;
+    case 7: return -(ux + uy);
+    default: return ux - uy;
+  }
+}
+
 // Sum over the 64 lanes of a wavefront; every lane must be active.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -193,7 +233,7 @@ __device__ __forceinline__ void node_velocity(CDesc &L, const T *f, T &rho, T &d
                                               T &uy) {
 #pragma clang fp contract(off)
   drho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-  rho = (T)L.rho0 + drho;
+  rho = DK<T>::rho0(L) + drho;
   const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const T jy = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
   const T inv_rho = T(1) / rho;
@@ -208,26 +248,26 @@ template <class T>
 __device__ __forceinline__ void compound_collide(CDesc &L, int x, int y, const T *g, T ux, T uy,
                                                  T *pg) {
 #pragma clang fp contract(off)
-  const T cs = (T)L.c_shift;
+  const T cs = DK<T>::cs(L);
   const T dC = g[0] + g[1] + g[2] + g[3] + g[4];
   const T C = cs + dC;
   // The rest weight is 1 - 4 w_axis in the compute type, so the five
   // weights sum to one exactly: with both weights rounded on their own
   // (1/3 and 1/6 in FP32 sum to 1 + 3e-8) every collision would create
   // solute in proportion to C.
-  const T wga = (T)L.wg_axis;
+  const T wga = DK<T>::wga(L);
   const T wg[5] = {T(1) - T(4) * wga, wga, wga, wga, wga};
-  const T ics = (T)L.inv_cs2g;
-  T src = -(T)L.k_decay * C;
+  const T ics = DK<T>::ics(L);
+  T src = -DK<T>::kdec(L) * C;
   if (L.has_source) {
     const int rx = x - L.r_x0, ry = y - L.r_y0;
     if (rx >= 0 && rx < L.r_w && ry >= 0 && ry < L.r_h)
       src += (T)((const GG_GLOBAL double *)L.R)[ry * L.r_w + rx];
   }
-  const T om_g = (T)L.omega_g;
+  const T om_g = DK<T>::om_g(L);
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
-    const T eu = (T)EX[i] * ux + (T)EY[i] * uy;
+    const T eu = e_dot_u<T>(i, ux, uy);
     const T dgeq = wg[i] * fmad(C * eu, ics, dC);
     pg[i] = fmad(wg[i], src, fmad(om_g, dgeq - g[i], g[i]));
   }
@@ -257,17 +297,17 @@ __device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc,
   // each of them rounds exactly the same way whatever code surrounds it.
 #pragma clang fp contract(off)
   const int nx = L.nx, ny = L.ny, pitch = L.pitch;
-  const T rho0 = (T)L.rho0;
+  const T rho0 = DK<T>::rho0(L);
   T rho, drho, ux, uy;
   node_velocity<T>(L, f, rho, drho, ux, uy);
   const T usq = fmad(ux, ux, uy * uy);
 
   // BGK relaxation of f toward the quadratic equilibrium, Eqs. 4-6, for
   // the deviations: f^eq_i - w_i rho0 = w_i (drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)).
-  const T om_f = (T)L.omega_f;
+  const T om_f = DK<T>::om_f(L);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const T eu = (T)EX[i] * ux + (T)EY[i] * uy;
+    const T eu = e_dot_u<T>(i, ux, uy);
     // 3 e.u + 4.5 (e.u)^2 - 1.5 u.u = e.u (4.5 e.u + 3) - 1.5 u.u
     const T poly = fmad(eu, fmad(T(4.5), eu, T(3)), T(-1.5) * usq);
     const T dfeq = (T)WF[i] * fmad(rho, poly, drho);
@@ -275,8 +315,8 @@ __device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc,
   }
 
   compound_collide<T>(L, x, y, g, ux, uy, pg);
-  const T cs = (T)L.c_shift;
-  const T wga = (T)L.wg_axis;
+  const T cs = DK<T>::cs(L);
+  const T wga = DK<T>::wga(L);
   const T wg[5] = {T(1) - T(4) * wga, wga, wga, wga, wga};
 
   // Value arriving at x along direction j when x - e_j is not fluid: the
@@ -327,7 +367,7 @@ __device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc,
       } else {
         // outflow at the reference density with the node's own u;
         // the compound leaves with zero gradient
-        const T eu = (T)EX[j] * ux + (T)EY[j] * uy;
+        const T eu = e_dot_u<T>(j, ux, uy);
         vf = fmad(T(2) * (T)WF[j] * rho0, fmad(T(4.5) * eu, eu, T(-1.5) * usq), -pf[OPP[j]]);
         if (j < 5) vg = pg[j];
       }
@@ -350,8 +390,8 @@ __device__ __forceinline__ void compound_links(CDesc &L, int x, int y, uint8_t l
                                                T *in_g, Flux &fx, bool count) {
 #pragma clang fp contract(off)
   const int nx = L.nx, ny = L.ny, pitch = L.pitch;
-  const T cs = (T)L.c_shift;
-  const T wga = (T)L.wg_axis;
+  const T cs = DK<T>::cs(L);
+  const T wga = DK<T>::wga(L);
   const T wg[5] = {T(1) - T(4) * wga, wga, wga, wga, wga};
 #pragma unroll
   for (int j = 0; j < 5; ++j) in_g[j] = pg[OPP[j]];

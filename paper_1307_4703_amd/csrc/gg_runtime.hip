@@ -161,6 +161,13 @@ gg_status gg_upload_desc(gg_lattice *L) {
   h.rho0 = L->p.rho0;
   h.k_decay = L->p.k_decay;
   h.c_shift = L->p.c_shift;
+  h.rho0_f = (float)h.rho0;
+  h.omega_f_f = (float)h.omega_f;
+  h.omega_g_f = (float)h.omega_g;
+  h.wg_axis_f = (float)h.wg_axis;
+  h.inv_cs2g_f = (float)h.inv_cs2g;
+  h.k_decay_f = (float)h.k_decay;
+  h.c_shift_f = (float)h.c_shift;
   for (int s = 0; s < GG_MAX_SEGMENTS; ++s) {
     const SegHost &g = L->seg[s];
     h.seg_kind[s] = g.set ? g.kind : 0;

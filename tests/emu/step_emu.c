@@ -112,6 +112,22 @@ static T stored(const emu_lattice *L, T v) {
   return v;
 }
 
+/* e_i . u written out per direction, as the kernels form it (+0 for the
+ * rest direction) */
+static T edu(int i, T ux, T uy) {
+  switch (i) {
+    case 0: return (T)0;
+    case 1: return ux;
+    case 2: return uy;
+    case 3: return -ux;
+    case 4: return -uy;
+    case 5: return ux + uy;
+    case 6: return uy - ux;
+    case 7: return -(ux + uy);
+    default: return ux - uy;
+  }
+}
+
 static T fused(T a, T b, T c) {
   return sizeof(T) == 4 ? (T)fmaf((float)a, (float)b, (float)c) : (T)fma((double)a, (double)b, (double)c);
 }
@@ -175,7 +191,7 @@ void emu_step(const emu_lattice *L, int64_t t, const T *h, const T *k, T *h_out,
       const T uu = fused(ux, ux, uy * uy);
       /* fluid: f_i^eq - w_i rho0 = w_i (drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)) */
       for (int i = 0; i < 9; ++i) {
-        const T eu = (T)CX[i] * ux + (T)CY[i] * uy;
+        const T eu = edu(i, ux, uy);
         const T p = fused(eu, fused((T)4.5, eu, (T)3), (T)(-1.5) * uu);
         const T deq = (T)W9[i] * fused(rho, p, dr);
         pf[i] = fused(om_f, deq - f[i], f[i]);
@@ -190,7 +206,7 @@ void emu_step(const emu_lattice *L, int64_t t, const T *h, const T *k, T *h_out,
         if (rx >= 0 && rx < L->r_w && ry >= 0 && ry < L->r_h) src += (T)L->R[(size_t)ry * L->r_w + rx];
       }
       for (int i = 0; i < 5; ++i) {
-        const T eu = (T)CX[i] * ux + (T)CY[i] * uy;
+        const T eu = edu(i, ux, uy);
         const T deq = wg[i] * fused(C * eu, ics, dc);
         pg[i] = fused(wg[i], src, fused(om_g, deq - g[i], g[i]));
       }
@@ -214,7 +230,7 @@ void emu_step(const emu_lattice *L, int64_t t, const T *h, const T *k, T *h_out,
             ing[j] = fused((T)2 * wg[j], cin - cs, -pg[REV[j]]);
           }
         } else {
-          const T eu = (T)CX[j] * ux + (T)CY[j] * uy;
+          const T eu = edu(j, ux, uy);
           inf[j] = fused(((T)2 * (T)W9[j]) * rho0, fused((T)4.5 * eu, eu, (T)(-1.5) * uu), -pf[REV[j]]);
           if (j < 5) ing[j] = pg[j];
         }
