@@ -47,13 +47,23 @@ __device__ __forceinline__ void second_step(CDesc &L, const Planes<typename Pop<
   T qf[9], qg[5], jf[9], jg[5];
   collide_node<T, PRESS>(L, x, y, lc, SEG, ph, sf, sg, qf, qg, jf, jg, fx, true, nbr);
   const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
-  const Neigh nb(L, x, y);
   P::st(dst.at(0, node), qf[0]);
   P::st(dst.at(9, node), qg[0]);
+  if (!L.periodic_x && !L.periodic_y) {
+    // (uniform) the neighbours are node + e_x + e_y pitch, padding included
+    const uint32_t pitch = (uint32_t)L.pitch;
 #pragma unroll
-  for (int i = 1; i < 9; ++i) P::st(dst.at(i, nb.idx[i]), qf[i]);
+    for (int i = 1; i < 9; ++i) P::st(dst.at(i, node + (uint32_t)EX[i] + (uint32_t)EY[i] * pitch), qf[i]);
 #pragma unroll
-  for (int i = 1; i < 5; ++i) P::st(dst.at(9 + i, nb.idx[i]), qg[i]);
+    for (int i = 1; i < 5; ++i)
+      P::st(dst.at(9 + i, node + (uint32_t)EX[i] + (uint32_t)EY[i] * pitch), qg[i]);
+  } else {
+    const Neigh nb(L, x, y);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) P::st(dst.at(i, nb.idx[i]), qf[i]);
+#pragma unroll
+    for (int i = 1; i < 5; ++i) P::st(dst.at(9 + i, nb.idx[i]), qg[i]);
+  }
   if (lc != 0) {
     // x + e_i not fluid: the value arriving along opp(i) stays here
 #pragma unroll
@@ -357,20 +367,36 @@ __global__ void __launch_bounds__((R + 2) * 64)
     // step t + 1 on the owned rows
     if (own && lc != NOT_FLUID) {
       T sf[9], sg[5];
-      sf[0] = P::rt(pf[0]);
-      sg[0] = P::rt(pg[0]);
-      sf[1] = P::rt(src_solid(lc, 1) ? inf[1] : zf1);
-      sf[3] = P::rt(src_solid(lc, 3) ? inf[3] : zf3);
-      sg[1] = P::rt(src_solid(lc, 1) ? ing[1] : zg1);
-      sg[3] = P::rt(src_solid(lc, 3) ? ing[3] : zg3);
-      sf[2] = P::rt(src_solid(lc, 2) ? inf[2] : lds_up[w - 1][0][lane]);
-      sf[5] = P::rt(src_solid(lc, 5) ? inf[5] : lds_up[w - 1][1][lane]);
-      sf[6] = P::rt(src_solid(lc, 6) ? inf[6] : lds_up[w - 1][2][lane]);
-      sg[2] = P::rt(src_solid(lc, 2) ? ing[2] : lds_up[w - 1][3][lane]);
-      sf[4] = P::rt(src_solid(lc, 4) ? inf[4] : lds_dn[w + 1][0][lane]);
-      sf[7] = P::rt(src_solid(lc, 7) ? inf[7] : lds_dn[w + 1][1][lane]);
-      sf[8] = P::rt(src_solid(lc, 8) ? inf[8] : lds_dn[w + 1][2][lane]);
-      sg[4] = P::rt(src_solid(lc, 4) ? ing[4] : lds_dn[w + 1][3][lane]);
+      // the pulled values (read unconditionally, so that the LDS reads are
+      // issued together rather than one by one behind the selects below)
+      sf[0] = pf[0];
+      sg[0] = pg[0];
+      sf[1] = zf1;
+      sf[3] = zf3;
+      sg[1] = zg1;
+      sg[3] = zg3;
+      sf[2] = lds_up[w - 1][0][lane];
+      sf[5] = lds_up[w - 1][1][lane];
+      sf[6] = lds_up[w - 1][2][lane];
+      sg[2] = lds_up[w - 1][3][lane];
+      sf[4] = lds_dn[w + 1][0][lane];
+      sf[7] = lds_dn[w + 1][1][lane];
+      sf[8] = lds_dn[w + 1][2][lane];
+      sg[4] = lds_dn[w + 1][3][lane];
+      // where x - e_j is not fluid, the value from the link rule instead
+      // (skipped when no lane of the wavefront has such a link)
+      if (__any(lc != 0)) {
+#pragma unroll
+        for (int j = 1; j < 9; ++j)
+          if (src_solid(lc, j)) sf[j] = inf[j];
+#pragma unroll
+        for (int j = 1; j < 5; ++j)
+          if (src_solid(lc, j)) sg[j] = ing[j];
+      }
+#pragma unroll
+      for (int j = 0; j < 9; ++j) sf[j] = P::rt(sf[j]);
+#pragma unroll
+      for (int j = 0; j < 5; ++j) sg[j] = P::rt(sg[j]);
       if (PRESS && seg) {
         const int ps = pressure_source(L, lc, ph1, nbr);
         if (ps >= 0) {
