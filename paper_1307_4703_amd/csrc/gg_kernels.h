@@ -93,6 +93,8 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
 hipError_t launch_rescale(gg_storage s, const LatDesc *d, const int32_t *xy, int n, int dt,
                           bool fluid, hipStream_t st, bool other = false);
 hipError_t launch_advance(const LatDesc *descs, int n, int64_t k, hipStream_t st);
+// *t = v on the stream.
+hipError_t launch_set_counter(int64_t *t, int64_t v, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
 
 }  // namespace gg

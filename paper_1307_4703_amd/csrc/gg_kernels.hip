@@ -354,6 +354,12 @@ __global__ void __launch_bounds__(256) k_copy(int4 *__restrict__ dst, const int4
   if (i < n) dst[i] = src[i];
 }
 
+// Set a step counter to v (the adjoint's recomputation copy, without a
+// host round trip).
+__global__ void k_set_counter(int64_t *__restrict__ t, int64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *(GG_GLOBAL int64_t *)t = v;
+}
+
 // Advance the step counters of n lattices by k (after k step launches).
 __global__ void k_advance(const LatDesc *__restrict__ descs, int n, int64_t k) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -782,6 +788,11 @@ hipError_t launch_wall_apply(gg_storage s, const LatDesc *d, const int32_t *link
       k_wall_apply<__half><<<grid, 64, 0, st>>>(d, links, n_links, dt, (const float *)save, fluid);
       break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_set_counter(int64_t *t, int64_t v, hipStream_t st) {
+  k_set_counter<<<1, 64, 0, st>>>(t, v);
   return hipGetLastError();
 }
 

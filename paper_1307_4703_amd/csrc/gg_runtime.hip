@@ -1439,23 +1439,73 @@ gg_status gg_adjoint(gg_lattice *L, int64_t n, int64_t s, const double *weight,
   const int txs = ilog2(L->tile_x);
   void *lam[2] = {lam0, lam1};
   int cur = 0;
+  // Backward sweep, segment by segment from the last checkpoint: the
+  // recomputation of a segment (from its checkpoint, writing the tape) and
+  // the adjoint steps over it. With a second tape (when it fits), the
+  // recomputation of segment k - 1 runs on a stream of its own while the
+  // adjoint steps of segment k run on the lattice's stream: two
+  // independent kernels that each leave part of the GPU idle on their own.
+  void *tape2 = nullptr;
+  const bool overlap = K > 1 && B.alloc(&tape2, (size_t)s * slot) == hipSuccess;
+  (void)hipGetLastError();  // a failed allocation only means no overlap
+  void *tapes[2] = {tape, overlap ? tape2 : tape};
+  struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // ready 0/1, free 0/1
+    ~SideStream() {
+      if (s) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+      }
+      for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    }
+  } side;
+  hipStream_t rs = L->stream;
+  if (overlap) {
+    GG_HIP(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking));
+    for (hipEvent_t &e : side.ev) GG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    rs = side.s;
+    GG_HIP(hipEventRecord(side.ev[0], L->stream));  // the seed and lambda set-up
+    GG_HIP(hipStreamWaitEvent(rs, side.ev[0], 0));
+  }
+  auto recompute = [&](int64_t k, void *tp) -> hipError_t {
+    const int64_t tk = t0 + k * s;
+    const int64_t nk = std::min<int64_t>(s, n - k * s);
+    hipError_t e = hipMemcpyAsync(scr_pop, (char *)ckpt + (size_t)k * pop_bytes, pop_bytes,
+                                  hipMemcpyDeviceToDevice, rs);
+    // (the recomputation's counter stays at tk: step j runs with dt = j)
+    if (e == hipSuccess) e = launch_set_counter((int64_t *)scr_t, tk, rs);
+    for (int64_t j = 0; j < nk && e == hipSuccess; ++j)
+      e = launch_step_tape(L->storage, block, ((tk + j) & 1) != 0, sd, L->d_tiles, L->n_tiles, txs,
+                           (int)j, (char *)tp + (size_t)j * slot, rs);
+    return e;
+  };
+  GG_HIP(recompute(K - 1, tapes[(K - 1) & 1]));
+  if (overlap) GG_HIP(hipEventRecord(side.ev[(K - 1) & 1], rs));
   for (int64_t k = K - 1; k >= 0; --k) {
     const int64_t tk = t0 + k * s;
     const int64_t nk = std::min<int64_t>(s, n - k * s);
-    GG_HIP(hipMemcpyAsync(scr_pop, (char *)ckpt + (size_t)k * pop_bytes, pop_bytes,
-                          hipMemcpyDeviceToDevice, L->stream));
-    GG_HIP(hipMemcpyAsync(scr_t, &tk, sizeof(tk), hipMemcpyHostToDevice, L->stream));
-    GG_HIP(hipStreamSynchronize(L->stream));  // tk lives on the host stack
-    // (the recomputation's counter stays at tk: step j runs with dt = j)
-    for (int64_t j = 0; j < nk; ++j)
-      GG_HIP(launch_step_tape(L->storage, block, ((tk + j) & 1) != 0, sd, L->d_tiles, L->n_tiles,
-                              txs, (int)j, (char *)tape + (size_t)j * slot, L->stream));
+    const int b = (int)(k & 1);
+    if (overlap && k > 0) {
+      // segment k - 1 into the other tape, once the adjoint of segment
+      // k + 1 (which read it) is done
+      if (k + 1 <= K - 1) GG_HIP(hipStreamWaitEvent(rs, side.ev[2 + (1 - b)], 0));
+      GG_HIP(recompute(k - 1, tapes[1 - b]));
+      GG_HIP(hipEventRecord(side.ev[1 - b], rs));
+    }
+    if (overlap) GG_HIP(hipStreamWaitEvent(L->stream, side.ev[b], 0));
     for (int64_t j = nk - 1; j >= 0; --j) {
       GG_HIP(launch_adjoint(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6, tk + j, lam[cur],
-                            lam[1 - cur], (const char *)tape + (size_t)j * slot,
+                            lam[1 - cur], (const char *)tapes[b] + (size_t)j * slot,
                             r_box ? (double *)dRdev : nullptr, box, (double *)dcin, (double *)pw,
                             L->stream));
       cur = 1 - cur;
+    }
+    if (overlap) {
+      GG_HIP(hipEventRecord(side.ev[2 + b], L->stream));
+    } else if (k > 0) {
+      GG_HIP(recompute(k - 1, tapes[0]));
     }
   }
   GG_HIP(hipStreamSynchronize(L->stream));
