@@ -262,10 +262,14 @@ __global__ void __launch_bounds__(256)
 // rescales it first in the same way; the caller then marks as segment tiles
 // all tiles whose rows or halo hold a node next to a segment. Otherwise the
 // rescaling kernel runs after the pass.
-template <class S, bool SEG, int R, bool PRESS = false>
+// TAPE (the adjoint's recomputation): also write each owned node's state
+// before each of the two steps, dg_0..4 then u_x, u_y (from the same
+// moments as the collision), to the planes of the compute type at tape0
+// (step t) and tape1 (step t + 1), as the single step's tape does.
+template <class S, bool SEG, int R, bool PRESS = false, bool TAPE = false>
 __global__ void __launch_bounds__((R + 2) * 64)
     k_tile2(const LatDesc *__restrict__ descs, const Tile *__restrict__ tiles, int n_tiles,
-            int per_xcd, int dir, int dt) {
+            int per_xcd, int dir, int dt, void *__restrict__ tape0, void *__restrict__ tape1) {
   using P = Pop<S>;
   using T = typename P::T;
   using W = typename P::W;
@@ -342,6 +346,15 @@ __global__ void __launch_bounds__((R + 2) * 64)
         if (own) fx.add(ps, dm, dc);
       }
     }
+    if (TAPE && own && lc != NOT_FLUID) {
+      T rho, drho, ux, uy;
+      node_velocity<T>(L, f, rho, drho, ux, uy);
+      const Planes<T> tp(tape0, L.plane);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) *tp.at(i, node) = g[i];
+      *tp.at(5, node) = ux;
+      *tp.at(6, node) = uy;
+    }
     T pf[9], pg[5], inf[9], ing[5];
     if (lc != NOT_FLUID) {
       collide_node<T, PRESS>(L, x, y, lc, seg, ph1, f, g, pf, pg, inf, ing, fx, own,
@@ -409,6 +422,15 @@ __global__ void __launch_bounds__((R + 2) * 64)
           fx.add(ps, dm, dc);
         }
       }
+      if (TAPE) {
+        T rho, drho, ux, uy;
+        node_velocity<T>(L, sf, rho, drho, ux, uy);
+        const Planes<T> tp(tape1, L.plane);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) *tp.at(i, node) = sg[i];
+        *tp.at(5, node) = ux;
+        *tp.at(6, node) = uy;
+      }
       if (seg)
         second_step<S, true, PRESS>(L, dst, x, y, lc, ph2, sf, sg, fx, nbr);
       else
@@ -440,12 +462,36 @@ hipError_t launch_step2(gg_storage s, bool seg, const LatDesc *d, const Tile *st
 }
 
 hipError_t launch_tile2(gg_storage s, bool seg, int rows, const LatDesc *d, const Tile *tiles,
-                        int n_tiles, int dir, int dt, hipStream_t st, bool press) {
+                        int n_tiles, int dir, int dt, hipStream_t st, bool press, void *tape0,
+                        void *tape1) {
   if (n_tiles <= 0) return hipSuccess;
   const int per_xcd = (n_tiles + 7) / 8;
   const int grid = 8 * per_xcd;
+  if (tape0) {  // the adjoint's recomputation (no pressure segments)
+#define GG_LAUNCHTT(TYPE, SEGV, RV)                                                        \
+  k_tile2<TYPE, SEGV, RV, false, true><<<grid, ((RV) + 2) * 64, 0, st>>>(d, tiles, n_tiles, \
+                                                                       per_xcd, dir, dt,   \
+                                                                       tape0, tape1)
+#define GG_LAUNCHTT_S(TYPE)                            \
+  do {                                                 \
+    if (seg && rows <= 2) GG_LAUNCHTT(TYPE, true, 2);  \
+    else if (seg && rows <= 6) GG_LAUNCHTT(TYPE, true, 6); \
+    else if (seg) GG_LAUNCHTT(TYPE, true, 14);         \
+    else if (rows <= 6) GG_LAUNCHTT(TYPE, false, 6);   \
+    else GG_LAUNCHTT(TYPE, false, 14);                 \
+  } while (0)
+    switch (s) {
+      case GG_F64: GG_LAUNCHTT_S(double); break;
+      case GG_F32: GG_LAUNCHTT_S(float); break;
+      case GG_F16_SHIFTED: GG_LAUNCHTT_S(__half); break;
+    }
+#undef GG_LAUNCHTT_S
+#undef GG_LAUNCHTT
+    return hipGetLastError();
+  }
 #define GG_LAUNCHT(TYPE, SEGV, RV, PV) \
-  k_tile2<TYPE, SEGV, RV, PV><<<grid, ((RV) + 2) * 64, 0, st>>>(d, tiles, n_tiles, per_xcd, dir, dt)
+  k_tile2<TYPE, SEGV, RV, PV><<<grid, ((RV) + 2) * 64, 0, st>>>(d, tiles, n_tiles, per_xcd, dir, dt, \
+                                                              nullptr, nullptr)
 #define GG_LAUNCHT_S(TYPE)                                           \
   do {                                                               \
     if (seg && press && rows <= 2) GG_LAUNCHT(TYPE, true, 2, true);  \

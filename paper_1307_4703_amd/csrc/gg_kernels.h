@@ -30,9 +30,12 @@ hipError_t launch_step2(gg_storage s, bool seg, const LatDesc *d, const Tile *st
 // the kernel that also carries the boundary rules (applied to the tiles
 // whose segment bit is set); press (with seg): the lattice has pressure
 // segments, whose link rule and first rescaling the pass then applies (the
-// rescaling of the state after the pass is launch_rescale's).
+// rescaling of the state after the pass is launch_rescale's). tape0,
+// tape1 (the adjoint's recomputation, no pressure segments): tape slots of
+// the pass's two steps, written for the tiles' owned nodes.
 hipError_t launch_tile2(gg_storage s, bool seg, int rows, const LatDesc *d, const Tile *tiles,
-                        int n_tiles, int dir, int dt, hipStream_t st, bool press = false);
+                        int n_tiles, int dir, int dt, hipStream_t st, bool press = false,
+                        void *tape0 = nullptr, void *tape1 = nullptr);
 
 // Compound-only step on frozen velocity fields (64 x 4 tiles, 256-thread
 // work-groups, XCD-aware tile order as launch_step); odd = parity of the

@@ -1429,8 +1429,15 @@ gg_status gg_adjoint(gg_lattice *L, int64_t n, int64_t s, const double *weight,
                      (const double *)tdev, lam0, (double *)pl, L->stream));
 
   // recomputation copy of the lattice: its own state, counter and fluxes
+  // (and, where the lattice steps in row-parallel two-step passes, its own
+  // second plane set: the recomputation then runs in passes too)
+  void *scr_pop_b = nullptr;
+  const bool rec_pass = pass_ok(L) && (L->fuse == 3 || L->fuse == 4) &&
+                        B.alloc(&scr_pop_b, pop_bytes) == hipSuccess;
+  (void)hipGetLastError();
   LatDesc hs = L->h;
   hs.pop = scr_pop;
+  hs.pop_b = scr_pop_b;
   hs.t = (int64_t *)scr_t;
   hs.flux = (double *)scr_flux;
   GG_HIP(hipMemcpy(scr_desc, &hs, sizeof(hs), hipMemcpyHostToDevice));
@@ -1476,9 +1483,36 @@ gg_status gg_adjoint(gg_lattice *L, int64_t n, int64_t s, const double *weight,
                                   hipMemcpyDeviceToDevice, rs);
     // (the recomputation's counter stays at tk: step j runs with dt = j)
     if (e == hipSuccess) e = launch_set_counter((int64_t *)scr_t, tk, rs);
-    for (int64_t j = 0; j < nk && e == hipSuccess; ++j)
+    int64_t j = 0;
+    auto single = [&]() {
       e = launch_step_tape(L->storage, block, ((tk + j) & 1) != 0, sd, L->d_tiles, L->n_tiles, txs,
                            (int)j, (char *)tp + (size_t)j * slot, rs);
+      ++j;
+    };
+    if (rec_pass) {
+      // an odd first step alone, then pairs of passes (four steps, ending
+      // in the first plane set) that tape both of their steps; the
+      // boundary tiles' kernel runs before the others on the same stream
+      if (((tk + j) & 1) && j < nk && e == hipSuccess) single();
+      for (; nk - j >= 4 && e == hipSuccess; j += 4)
+        for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+          char *t0p = (char *)tp + (size_t)(j + 2 * q) * slot;
+          char *t1p = t0p + slot;
+          const int dt = (int)(j + 2 * q);
+          if (L->fuse == 4) {
+            e = launch_tile2(L->storage, true, L->strip_h, sd, L->d_strips, L->n_strips, q, dt, rs,
+                             false, t0p, t1p);
+          } else {
+            if (L->n_seg_strips > 0)
+              e = launch_tile2(L->storage, true, 2, sd, L->d_seg_strips, L->n_seg_strips, q, dt, rs,
+                               false, t0p, t1p);
+            if (e == hipSuccess)
+              e = launch_tile2(L->storage, false, L->strip_h, sd, L->d_strips, L->n_strips, q, dt,
+                               rs, false, t0p, t1p);
+          }
+        }
+    }
+    while (j < nk && e == hipSuccess) single();
     return e;
   };
   GG_HIP(recompute(K - 1, tapes[(K - 1) & 1]));

@@ -22,8 +22,10 @@ def _problem(wl, seed=4):
     return weight, target
 
 
-def _gpu_adjoint(wl, storage, init, steps, weight, target, r_box, ckpt=0, R=None):
+def _gpu_adjoint(wl, storage, init, steps, weight, target, r_box, ckpt=0, R=None, form=None):
     lat = Lattice.from_workload(wl, storage=storage, init=False)
+    if form is not None:
+        lat.set_two_step(*form)
     lat.init(**init)
     if R is not None:
         lat.set_source(R)
@@ -38,8 +40,12 @@ def _oracle_adjoint(wl, init, steps, weight, target, R=None):
     return o.adjoint(steps, weight, target)
 
 
-@pytest.mark.parametrize("ckpt", [0, 1, 7, 60])
-def test_f64_adjoint_matches_oracle(ckpt):
+@pytest.mark.parametrize("ckpt,form", [(0, None), (1, None), (7, None), (60, None),
+                                       (7, (1, 6)), (7, (4, 14)), (13, (3, 14)), (60, (4, 6))])
+def test_f64_adjoint_matches_oracle(ckpt, form):
+    """Checkpoint intervals of 1, 7 (segments starting on odd steps), 13 and
+    60 steps, recomputed in single steps or in taped two-step passes (the
+    boundary tiles apart or in the one kernel)."""
     wl = _small()
     wl.k_decay = 2e-3
     init = seeded_init(wl, 3)
@@ -50,8 +56,8 @@ def test_f64_adjoint_matches_oracle(ckpt):
     y0, x0 = fl[len(fl) // 2]
     R[y0:y0 + 3, x0:x0 + 4] = 1e-3
     r_box = (int(x0) - 5, int(y0) - 4, 16, 12)
-    log(f"f64 adjoint ckpt={ckpt}")
-    lat, g = _gpu_adjoint(wl, "f64", init, steps, weight, target, r_box, ckpt, R=R)
+    log(f"f64 adjoint ckpt={ckpt} form={form}")
+    lat, g = _gpu_adjoint(wl, "f64", init, steps, weight, target, r_box, ckpt, R=R, form=form)
     loss, dcin, dD, dR = _oracle_adjoint(wl, init, steps, weight, target, R=R)
     log(f"loss gpu {g['loss']!r} oracle {loss!r}; dD {g['d_D']!r} {dD!r}")
     assert g["loss"] == pytest.approx(loss, rel=1e-12)
