@@ -286,22 +286,27 @@ def adjoint_bench(steps=20000, chunk=64):
             "loss": g["loss"], "d_D": g["d_D"]}
 
 
-def batch_bench(steps=2000, seq_steps=400, n=64, seed=4703, tune_steps=32, chunk=64):
+def batch_bench(steps=2000, seq_steps=400, n=64, seed=4703, chunk=64):
     """64 seeded gradient generators of uneven size (FP32): aggregate
     fluid-node updates per second of one batched, graph-captured launch per
-    step (launch shape from the autotuner) against stepping the instances
-    one after the other with the same kernels."""
+    step (launch form from the library's autotuner) against stepping the
+    instances one after the other with the same kernels."""
     import torch
-    from paper_1307_4703_amd import Batch, Lattice, tune, workloads as W
+    from paper_1307_4703_amd import Batch, Lattice, workloads as W
     wls = W.batch_instances(n, seed)
     log(f"batch: creating {n} lattices")
     lats = [Lattice.from_workload(wl, storage="f32") for wl in wls]
     nf = sum(l.info()["n_fluid"] for l in lats)
-    best = tune.tune_batch(lats, steps=tune_steps, use_cache=False)
+    # the library's autotuner picks the launch form (gg_batch_create with
+    # GG_AUTOTUNE, the members left as they were)
+    t0 = time.perf_counter()
+    b = Batch(lats, tile=None, graph_chunk=chunk)
+    tune_s = time.perf_counter() - t0
+    f = b.form()
+    best = {"tile": [f["tile_x"], f["tile_y"]], "persist": f["persist"], "fuse": f["fuse"],
+            "rows": f["rows"]}
     log(f"batch: tuned tile {best['tile']} persist {best['persist']} "
-        f"fuse {best['fuse']} rows {best['rows']}")
-    b = Batch(lats, tile=tuple(best["tile"]), persist=best["persist"], graph_chunk=chunk,
-              fuse=best["fuse"], rows=best["rows"])
+        f"fuse {best['fuse']} rows {best['rows']} ({tune_s:.2f} s)")
     b.step(64)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -329,6 +334,7 @@ def batch_bench(steps=2000, seq_steps=400, n=64, seed=4703, tune_steps=32, chunk
     ms = nf * seq_steps / t_s / 1e6
     return {"n_instances": n, "seed": seed, "n_fluid_total": nf, "tile": best["tile"],
             "persist": best["persist"], "fuse": best["fuse"], "rows": best["rows"],
+            "autotune_seconds": round(tune_s, 3),
             "steps": steps, "ms_per_step": round(t_b / steps * 1e3, 5),
             "batched_mlups": round(mb, 1), "sequential_mlups": round(ms, 1),
             "speedup": round(mb / ms, 3),

@@ -210,16 +210,26 @@ gg_status gg_set_source(gg_lattice *lat, const double *R, gg_where where);
  * region velocity and Peclet diagnostics; NULL clears it. */
 gg_status gg_set_region(gg_lattice *lat, const uint8_t *region);
 
-/* Equilibrium initial state f = f^eq(rho, u), g = g^eq(C, u) at every
- * fluid node from nx*ny arrays (NULL: rho0, 0, 0, 0 respectively); resets
- * t to 0 and the accumulated boundary fluxes to zero. */
+/* Equilibrium initial state at every fluid node from nx*ny arrays (NULL:
+ * rho0, 0, 0, 0 respectively): f = f^eq(rho, u), the quadratic equilibrium
+ * of paper Eq. 5 with the weights of Eq. 6, and g = g^eq(C, u), the linear
+ * equilibrium of Eq. 9 (a chip at rest with C = 0 is the Results section's
+ * start). Resets t to 0 and the accumulated boundary fluxes to zero. */
 gg_status gg_init(gg_lattice *lat, const double *rho, const double *ux,
                   const double *uy, const double *C, gg_where where);
 
-/* Advance n >= 0 time steps. Asynchronous. With the two-step pass on (the
- * default, see gg_set_two_step) the steps from an even t go in passes of
- * two steps each, in groups of four steps; a leftover or odd-t step runs
- * as a single step. Both ways give the same state, bit for bit. */
+/* Advance n >= 0 time steps. Each step is the collide-then-stream split the
+ * paper states after Eq. 7, for both lattices at once: at every fluid node
+ * the BGK collision of the fluid (Eq. 4, equilibrium Eqs. 5-6, moments
+ * Eq. 7) and of the compound with the node's own velocity (Eq. 8,
+ * equilibrium Eq. 9, source R - kC of Eq. 2), then streaming along the
+ * velocities of Eq. 3 with the link rules of walls, closed valves and open
+ * segments (Boundary Conditions section; see gg_seg_kind) at the valve
+ * phase of the step (gg_set_schedule). Asynchronous. With the two-step pass
+ * on (the default, see gg_set_two_step) the steps from an even t go in
+ * passes of two steps each, in groups of four steps; a leftover or odd-t
+ * step runs as a single step. Both ways give the same state, bit for bit.
+ * With a monitor set (gg_set_monitor) the FP64 reductions run in between. */
 gg_status gg_step(gg_lattice *lat, int64_t n);
 
 /* Macroscopic fields at the current time (nx*ny doubles each; NaN off the
@@ -235,13 +245,24 @@ gg_status gg_read(gg_lattice *lat, double *rho, double *ux, double *uy,
 gg_status gg_read_populations(gg_lattice *lat, double *f, double *g,
                               gg_where where);
 
-/* FP64 diagnostics; GG_ERR_NONFINITE (with *out filled) if any fluid node
- * holds a non-finite population. */
+/* FP64 diagnostics of the current state: the mass and compound totals and
+ * accumulated boundary fluxes of the conservation checks, max |u| over the
+ * fluid and over the region of gg_set_region (the cell chamber, whose flow
+ * must stay negligible: Abstract and Results section) and the largest cell
+ * Peclet number there (Eq. 12 with one cell as length). Waits for the
+ * stream; the per-tile partial sums live in a buffer allocated on the first
+ * call (see gg_diagnostics_noalloc). GG_ERR_NONFINITE (with *out filled) if
+ * any fluid node holds a non-finite population. */
 gg_status gg_diagnostics(gg_lattice *lat, gg_diag *out);
 
-/* Snapshot of the full state (populations, time, fluxes). With buf NULL,
- * *nbytes receives the size needed. gg_load accepts only a snapshot of a
- * lattice with the same mask dimensions and storage. */
+/* Checkpoint and resume: a snapshot of the full state (populations in their
+ * raw storage form and layout, time, fluxes) to a host buffer, and back.
+ * No passage of the paper defines it; the long runs of its Results section
+ * (four hours of chip time) are what it serves. With buf NULL, *nbytes
+ * receives the size needed. Both wait for the stream. gg_load accepts only a
+ * snapshot of a lattice with the same mask dimensions and storage
+ * (GG_ERR_ARG otherwise); resuming gives bit for bit the run that was not
+ * interrupted. */
 gg_status gg_save(gg_lattice *lat, void *buf, size_t *nbytes);
 gg_status gg_load(gg_lattice *lat, const void *buf, size_t nbytes);
 
@@ -353,11 +374,28 @@ gg_status gg_info(const gg_lattice *lat, int64_t *n_fluid, int64_t *n_tiles,
  * gg_batch_step(b, n) every member is n steps further, exactly as after
  * gg_step(member, n). tile_x, tile_y as in gg_set_launch (0, 0: 64 x 4);
  * persist > 0 caps the grid at that many work-groups, which then loop over
- * the tiles (a persistent launch); 0 launches one work-group per tile. */
+ * the tiles (a persistent launch); 0 launches one work-group per tile.
+ * persist = GG_AUTOTUNE: the library picks the form (tile_x and tile_y are
+ * then ignored): each candidate (single steps over tiles of 64 x 4, 32 x 8
+ * or 128 x 2 nodes; when every member has its second plane set and all sit
+ * at steps of one parity, two-step passes with 6- or 14-row tiles and the
+ * boundary tiles apart, or 6-row tiles in one kernel) advances the members
+ * 20 steps, 16 of them timed with HIP events on their stream, and the
+ * fastest is kept (gg_batch_form reports it). The members' states, step
+ * counts and boundary fluxes are copied aside on the device (hipMalloc of
+ * their total state size, freed before returning) and put back after every
+ * candidate, so the members are left as they were. Waits for the stream. */
+#define GG_AUTOTUNE (-1)
 gg_status gg_batch_create(gg_lattice *const *lats, int32_t n, int32_t tile_x,
                           int32_t tile_y, int32_t persist, int32_t graph_chunk,
                           gg_batch **out);
 gg_status gg_batch_step(gg_batch *batch, int64_t n);
+
+/* The launch form of a batch (tile shape, persistent grid, two-step form
+ * and tile rows as gg_batch_set_two_step takes them); any pointer may be
+ * NULL. */
+gg_status gg_batch_form(const gg_batch *batch, int32_t *tile_x, int32_t *tile_y,
+                        int32_t *persist, int32_t *fuse, int32_t *rows);
 
 /* Two-step pass for the batch (see gg_set_two_step): fuse 3 or 4 with
  * tiles of rows = 6 or 14 rows, over the members' tiles in one flat list

@@ -129,7 +129,9 @@ SIGS = {
     "gg_monitor_read": [P, ctypes.POINTER(gg_diag), ctypes.POINTER(I64)],
     "gg_step_profile": [P, I64, ctypes.POINTER(gg_profile)],
     "gg_diagnostics_noalloc": [P, ctypes.POINTER(gg_diag)],
+    "gg_batch_form": [P] + [ctypes.POINTER(I32)] * 5,
 }
+GG_AUTOTUNE = -1
 
 
 def lib() -> ctypes.CDLL:

@@ -1667,10 +1667,14 @@ static hipError_t batch_launch(gg_batch *B, int64_t s0, int64_t n, hipStream_t s
   return e;
 }
 
+static gg_status batch_autotune(gg_lattice *const *lats, int32_t n, int32_t graph_chunk,
+                                gg_batch **out);
+
 gg_status gg_batch_create(gg_lattice *const *lats, int32_t n, int32_t tile_x, int32_t tile_y,
                           int32_t persist, int32_t graph_chunk, gg_batch **out) {
   if (!out || !lats || n < 1) return fail(GG_ERR_ARG, "need at least one lattice");
   *out = nullptr;
+  if (persist == GG_AUTOTUNE) return batch_autotune(lats, n, graph_chunk, out);
   if (tile_x == 0 && tile_y == 0) {
     tile_x = 64;
     tile_y = 4;
@@ -1725,6 +1729,112 @@ gg_status gg_batch_create(gg_lattice *const *lats, int32_t n, int32_t tile_x, in
     return fail(GG_ERR_HIP, std::string("batch set-up: ") + hipGetErrorString(e));
   }
   *out = B;
+  return GG_OK;
+}
+
+// Library-side autotuner of a batch's launch form: each candidate (single
+// steps over tiles of 64 x 4, 32 x 8 or 128 x 2 nodes; two-step passes over
+// tiles of 6 or 14 rows with the boundary tiles in their own kernel, or of 6
+// rows in the one kernel, when every member has its second plane set and
+// all sit at steps of one parity) advances the members 4 + 16 steps, the 16
+// timed with HIP events on their stream; the members' states, step counts
+// and boundary fluxes are copied aside on the device first and put back
+// after each candidate, so tuning leaves them as they were.
+static gg_status batch_autotune(gg_lattice *const *lats, int32_t n, int32_t graph_chunk,
+                                gg_batch **out) {
+  for (int k = 0; k < n; ++k)
+    if (!lats[k]) return fail(GG_ERR_ARG, "NULL lattice in the batch");
+  hipStream_t st = lats[0]->stream;
+  std::vector<size_t> off(n + 1, 0);
+  for (int k = 0; k < n; ++k)
+    off[k + 1] = off[k] + (size_t)NPOP * lats[k]->plane * lats[k]->esize +
+                 2 * GG_MAX_SEGMENTS * sizeof(double) + sizeof(int64_t);
+  void *save = nullptr;
+  if (hipMalloc(&save, off[n]) != hipSuccess) return fail(GG_ERR_OOM, "autotune: state copies");
+  struct Free {
+    void *p;
+    ~Free() { (void)hipFree(p); }
+  } fr{save};
+  std::vector<int64_t> t0(n);
+  auto copy = [&](bool back) -> hipError_t {
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < n && e == hipSuccess; ++k) {
+      gg_lattice *L = lats[k];
+      char *p = (char *)save + off[k];
+      const size_t pb = (size_t)NPOP * L->plane * L->esize;
+      const size_t fb = 2 * GG_MAX_SEGMENTS * sizeof(double);
+      void *d[3] = {L->d_pop, L->d_flux, L->d_t};
+      void *h[3] = {p, p + pb, p + pb + fb};
+      const size_t sz[3] = {pb, fb, sizeof(int64_t)};
+      for (int q = 0; q < 3 && e == hipSuccess; ++q)
+        e = hipMemcpyAsync(back ? d[q] : h[q], back ? h[q] : d[q], sz[q], hipMemcpyDeviceToDevice, st);
+      if (back) L->t = t0[k];
+    }
+    return e;
+  };
+  for (int k = 0; k < n; ++k) t0[k] = lats[k]->t;
+  GG_HIP(copy(false));
+  bool passes = true;
+  for (int k = 0; k < n; ++k)
+    passes = passes && lats[k]->d_pop_b && ((lats[k]->t ^ lats[0]->t) & 1) == 0;
+  struct Cand {
+    int tx, ty, fuse, rows;
+  };
+  std::vector<Cand> cands = {{64, 4, 1, 6}, {32, 8, 1, 6}, {128, 2, 1, 6}};
+  if (passes) {
+    cands.push_back({64, 4, 3, 6});
+    cands.push_back({64, 4, 3, 14});
+    cands.push_back({64, 4, 4, 6});
+  }
+  hipEvent_t a = nullptr, b = nullptr;
+  GG_HIP(hipEventCreate(&a));
+  GG_HIP(hipEventCreate(&b));
+  double best_ms = 1e300;
+  Cand best = cands[0];
+  gg_status st_all = GG_OK;
+  for (const Cand &c : cands) {
+    gg_batch *B = nullptr;
+    gg_status s = gg_batch_create(lats, n, c.tx, c.ty, 0, graph_chunk, &B);
+    if (s == GG_OK && c.fuse >= 3) s = gg_batch_set_two_step(B, c.fuse, c.rows);
+    float ms = 0.0f;
+    if (s == GG_OK) s = gg_batch_step(B, 4);
+    if (s == GG_OK && hipEventRecord(a, st) != hipSuccess) s = fail(GG_ERR_HIP, "autotune event");
+    if (s == GG_OK) s = gg_batch_step(B, 16);
+    if (s == GG_OK && (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                       hipEventElapsedTime(&ms, a, b) != hipSuccess))
+      s = fail(GG_ERR_HIP, "autotune timing");
+    if (B) gg_batch_destroy(B);
+    if (copy(true) != hipSuccess) {
+      st_all = fail(GG_ERR_HIP, "autotune: restoring the members' states");
+      break;
+    }
+    if (s != GG_OK) continue;  // a candidate the members do not allow
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (st_all != GG_OK) return st_all;
+  GG_HIP(hipStreamSynchronize(st));
+  gg_status s = gg_batch_create(lats, n, best.tx, best.ty, 0, graph_chunk, out);
+  if (s == GG_OK && best.fuse >= 3) s = gg_batch_set_two_step(*out, best.fuse, best.rows);
+  if (s != GG_OK && *out) {
+    gg_batch_destroy(*out);
+    *out = nullptr;
+  }
+  return s;
+}
+
+gg_status gg_batch_form(const gg_batch *B, int32_t *tile_x, int32_t *tile_y, int32_t *persist,
+                        int32_t *fuse, int32_t *rows) {
+  if (!B) return fail(GG_ERR_ARG, "batch is NULL");
+  if (tile_x) *tile_x = B->tile_x;
+  if (tile_y) *tile_y = B->tile_y;
+  if (persist) *persist = B->persist;
+  if (fuse) *fuse = B->fuse;
+  if (rows) *rows = B->rows;
   return GG_OK;
 }
 

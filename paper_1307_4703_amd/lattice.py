@@ -366,18 +366,32 @@ class Batch:
     steps further, exactly as after ``Lattice.step(n)``.
     """
 
-    def __init__(self, lattices: Sequence[Lattice], tile: Tuple[int, int] = (64, 4),
+    def __init__(self, lattices: Sequence[Lattice], tile: Optional[Tuple[int, int]] = (64, 4),
                  persist: int = 0, graph_chunk: int = 64, fuse: int = 1, rows: int = 6):
+        """tile=None: the library's autotuner picks the launch form
+        (gg_batch_create with GG_AUTOTUNE; the members are left as they
+        were); fuse and rows are then ignored."""
         self.lattices = list(lattices)
         arr = (ctypes.c_void_p * len(self.lattices))(*[l.handle.value for l in self.lattices])
         h = ctypes.c_void_p()
-        A.call("gg_batch_create", arr, len(self.lattices), int(tile[0]), int(tile[1]),
-               int(persist), int(graph_chunk), ctypes.byref(h))
+        tx, ty = tile if tile is not None else (0, 0)
+        A.call("gg_batch_create", arr, len(self.lattices), int(tx), int(ty),
+               A.GG_AUTOTUNE if tile is None else int(persist), int(graph_chunk), ctypes.byref(h))
         self._h = h
+        if tile is None:
+            f = self.form()
+            self.tile, self.persist = (f["tile_x"], f["tile_y"]), f["persist"]
+            return
         self.tile = tuple(tile)
         self.persist = int(persist)
         if fuse != 1:
             self.set_two_step(fuse, rows)
+
+    def form(self) -> dict:
+        """The launch form in use (gg_batch_form)."""
+        v = [ctypes.c_int32() for _ in range(5)]
+        A.call("gg_batch_form", self._h, *[ctypes.byref(x) for x in v])
+        return dict(zip(("tile_x", "tile_y", "persist", "fuse", "rows"), [x.value for x in v]))
 
     def set_two_step(self, fuse: int = 4, rows: int = 6) -> None:
         """Two-step passes over all members (fuse 3 or 4) or single steps

@@ -35,7 +35,7 @@ def _gpu_adjoint(wl, storage, init, steps, weight, target, r_box, ckpt=0, R=None
 
 def _oracle_adjoint(wl, init, steps, weight, target, R=None):
     o = Oracle(wl.mask, tau_f=wl.tau_f, D=wl.D, w0=wl.w0, k_decay=wl.k_decay,
-               segments=wl.segments, schedule=wl.schedule, R=R)
+               segments=wl.segments, schedule=wl.schedule, R=R, periodic=wl.periodic)
     o.init(**init)
     return o.adjoint(steps, weight, target)
 
@@ -69,6 +69,27 @@ def test_f64_adjoint_matches_oracle(ckpt, form):
     assert lat.info()["t"] == steps
     if ckpt == 7:
         assert g["n_checkpoints"] == 9 and g["ckpt_every"] == 7
+
+
+@pytest.mark.parametrize("periodic", [(True, True), (True, False), (False, False)])
+def test_f64_adjoint_obstacles_periodic_vs_oracle(periodic):
+    """Obstacles everywhere on a 131 x 67 lattice (an odd width, so column
+    pairs straddle the periodic seam), every node a possible wall neighbour,
+    with a source patch and decay."""
+    m = W.random_mask(131, 67, seed=9, periodic=periodic)
+    wl = W.Workload("random", m, tau_f=0.7, D=0.02, k_decay=1e-3, periodic=periodic)
+    init = seeded_init(wl, 6)
+    weight, target = _problem(wl, seed=8)
+    R = np.zeros(m.shape)
+    R[20:30, 60:75] = 1e-3
+    r_box = (55, 15, 30, 20)
+    log(f"f64 adjoint obstacles periodic={periodic}")
+    lat, g = _gpu_adjoint(wl, "f64", init, 40, weight, target, r_box, 9, R=R)
+    loss, dcin, dD, dR = _oracle_adjoint(wl, init, 40, weight, target, R=R)
+    assert g["loss"] == pytest.approx(loss, rel=1e-12)
+    assert g["d_D"] == pytest.approx(dD, rel=1e-10)
+    ref = dR[r_box[1]:r_box[1] + r_box[3], r_box[0]:r_box[0] + r_box[2]]
+    assert np.max(np.abs(g["d_R"] - ref)) <= 1e-10 * np.max(np.abs(ref))
 
 
 def test_adjoint_leaves_the_same_final_state_as_stepping():

@@ -155,3 +155,28 @@ def test_batch_refuses_reconfigured_members():
             b.set_two_step(4, 6)
         assert e.value.status == A.GG_ERR_STATE
         b.close()
+
+
+def test_library_autotuner_leaves_members_and_steps_like_them():
+    """gg_batch_create with GG_AUTOTUNE: the members come back unchanged
+    from the tuning runs, the batch reports a candidate form, and it steps
+    the members exactly as they step on their own."""
+    wls = _members()
+    ref = _make(wls)
+    lats = _make(wls)
+    before = _states(lats)
+    b = Batch(lats, tile=None, graph_chunk=8)
+    f = b.form()
+    log(f"library autotune picked {f}")
+    assert (f["tile_x"], f["tile_y"]) in ((64, 4), (32, 8), (128, 2))
+    assert (f["fuse"], f["rows"]) in ((1, 6), (3, 6), (3, 14), (4, 6))
+    for (fa, ga), (fb, gb) in zip(before, _states(lats)):
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+    for lat in lats:
+        assert lat.info()["t"] == 0
+    b.step(21)
+    for lat in ref:
+        lat.step(21)
+    for (fa, ga), (fb, gb) in zip(_states(ref), _states(lats)):
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+    b.close()
