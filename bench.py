@@ -243,6 +243,8 @@ def copy_bandwidth(nbytes=2 << 30, reps=20):
 # (113) with the tape of g and u written (7 x 4 = 28), and the adjoint step
 # (FP64 lambda read and written, 2 x 5 x 8 = 80, and the tape read, 28).
 ADJOINT_BYTES_F32 = 113 + 113 + 28 + 80 + 28
+# one adjoint step: FP64 lambda read and written, the tape read, the link code
+ADJOINT_STEP_BYTES_F32 = 80 + 28 + 1
 
 
 def adjoint_bench(steps=20000, chunk=64):
@@ -447,13 +449,81 @@ def cpu_baseline(name, budget_s=15.0, single_budget_s=4.0):
             "cpu_model": model, "nproc": os.cpu_count()}
 
 
-def digest_counters(prof_dir, grids, out_path):
-    """Turn two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per
-    dispatch) into HBM bytes per step launch for the workloads named in
-    ``grids`` ({"grid size/kernel name part": workload}; the bytes of all
-    matching kernels are averaged), scaled by what the same counters read
-    for the plain copy kernel of known size; writes ``out_path`` (JSON)."""
+CTYPE = {"f64": "double", "f32": "float", "f16": "__half"}
+
+
+def counters_leg(leg, tile, chunk_unused=0):
+    """One leg of the counter runs (rocprofv3 --pmc runs the whole process):
+    plain launches only (no graph replays), the calibration copy first, then
+    the leg's kernels. Writes the manifest gpurun_out/counters/counters_<leg>.json
+    naming, per workload, the dominant kernel (a part of its name) and its
+    grid size, which the digest matches against the counter rows."""
+    import torch
+    from paper_1307_4703_amd import Batch, Lattice
+    from paper_1307_4703_amd import workloads as W
+    copy_bandwidth(nbytes=256 << 20, reps=2)
+    manifest = {}
+    if leg == "lattices":
+        for name in ("gg8192_f16",) + tuple(n for n, _ in SECONDARY):
+            wl = workload(name)
+            lat = Lattice.from_workload(wl)
+            lat.set_launch(tile[0], tile[1], 0)
+            fuse, rows = FORMS.get(name, (3, 6))
+            lat.set_two_step(fuse, rows)
+            lat.step(4)
+            p = lat.step_profile(16)
+            lat.close()
+            seg = "true" if p["fuse"] == 4 else "false"
+            grid = 8 * ((p["pass_tiles"] + 7) // 8) * (p["rows"] + 2) * 64
+            manifest[name] = {"kernel": f"k_tile2<{CTYPE[wl.storage]}, {seg}, {p['rows']},",
+                              "grid": grid, "units": 2 * p["pass_fluid"],
+                              "bytes_per_update": bytes_per_update(wl.storage)}
+            log(f"counters: {name} {manifest[name]}")
+    elif leg == "batch":
+        wls = W.batch_instances(64, 4703)
+        lats = [Lattice.from_workload(wl, storage="f32") for wl in wls]
+        b = Batch(lats, tile=(64, 4), graph_chunk=0, fuse=4, rows=6)
+        b.step(20)
+        torch.cuda.synchronize()
+        b.close()
+        nf = sum(l.info()["n_fluid"] for l in lats)
+        manifest["batch64"] = {"kernel": "k_tile2<float, true, 6, false, false>", "grid": None,
+                               "units": 2 * nf, "bytes_per_update": bytes_per_update("f32")}
+    elif leg == "adjoint":
+        wl = workload("gg2048_f32")
+        weight, target, r_box = W.chamber_misfit_setup(wl)
+        lat = Lattice.from_workload(wl)
+        lat.set_launch(64, 4, 0)
+        lat.set_two_step(*FORMS["gg2048_f32"])
+        lat.adjoint(400, weight, target, r_box=r_box, ckpt_every=20)
+        nf = lat.info()["n_fluid"]
+        lat.close()
+        manifest["adjoint:k_adjoint"] = {"kernel": "k_adjoint<float>", "grid": None, "units": nf,
+                                         "bytes_per_update": ADJOINT_STEP_BYTES_F32}
+        manifest["adjoint:taped_pass"] = {"kernel": "k_tile2<float, true, 6, false, true>",
+                                          "grid": None, "units": 2 * nf,
+                                          "bytes_per_update": bytes_per_update("f32") / 2 + 28}
+    elif leg == "cde":
+        for name, steps, flow, rows in CDE_LEG:
+            cde_bench(name, 16, 4, rows, 0)
+    else:
+        raise SystemExit(f"unknown counter leg {leg}")
+    out_dir = os.path.join(ROOT, "gpurun_out", "counters")
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, f"counters_{leg}.json"), "w") as fh:
+        json.dump(manifest, fh, indent=1)
+    print(json.dumps(manifest), flush=True)
+
+
+def digest_counters(prof_dir, out_path):
+    """Turn the counter runs of each leg (rocprofv3 --pmc FETCH_SIZE, then
+    --pmc WRITE_SIZE, KiB per dispatch, under prof_dir/<leg>_fetch and
+    prof_dir/<leg>_write, with the leg's manifest counters_<leg>.json) into
+    HBM bytes per launch of each workload's dominant kernel, scaled per leg
+    by what the same counters read for the plain copy kernel of known size;
+    writes ``out_path`` (JSON)."""
     import csv
+    import glob
     from collections import defaultdict
 
     def per_dispatch(path, counter):
@@ -464,43 +534,42 @@ def digest_counters(prof_dir, grids, out_path):
                     acc[(row["Kernel_Name"], int(row["Grid_Size"]))].append(float(row["Counter_Value"]))
         return {k: sum(v) / len(v) for k, v in acc.items()}
 
-    fetch = per_dispatch(os.path.join(prof_dir, "pmc_fetch", "fetch_counter_collection.csv"),
-                         "FETCH_SIZE")
-    write = per_dispatch(os.path.join(prof_dir, "pmc_write", "write_counter_collection.csv"),
-                         "WRITE_SIZE")
-    copy = [k for k in fetch if "k_copy" in k[0]]
-    if len(copy) != 1:
-        raise SystemExit("expected exactly one copy-kernel grid in the counter runs")
-    ck = copy[0]
-    n_copy = ck[1] * 16  # one 16-byte vector per lane, read and written
-    fs, ws = n_copy / 1024.0 / fetch[ck], n_copy / 1024.0 / write[ck]
     data = {"kernel_sha": kernel_hash(), "source": [os.path.relpath(p, ROOT) for p in KERNEL_SRC],
-            "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
-            "calibration": {"kernel": "gg::k_copy", "bytes_read": n_copy, "bytes_written": n_copy,
-                            "FETCH_SIZE_KiB": fetch[ck], "WRITE_SIZE_KiB": write[ck]},
-            "workloads": {}}
-    for key, name in grids.items():
-        grid, _, kname = key.partition("/")
-        grid = int(grid)
-        steps = {k: v for k, v in fetch.items() if k[1] == grid and kname in k[0]}
-        if not steps:
-            raise SystemExit(f"no kernel {kname!r} with grid size {grid} ({name})")
-        par = {}
-        for k in steps:
-            m = re.search(r"k_\w+(<[^>]*>)?", k[0])
-            tag = m.group(0) if m else k[0]
-            par[tag] = {"fetch_bytes": round(fetch[k] * 1024 * fs),
-                        "write_bytes": round(write.get(k, 0.0) * 1024 * ws)}
-        tot = [v["fetch_bytes"] + v["write_bytes"] for v in par.values()]
-        bpl = round(sum(tot) / len(tot))
-        cde = name.startswith("cde:")
-        wl = workload(name[4:] if cde else name)
-        import numpy as np
-        bpu = cde_bytes_per_update(wl.storage) if cde else bytes_per_update(wl.storage)
-        alg = int(np.count_nonzero(wl.mask == 0)) * bpu
-        data["workloads"][name] = {"bytes_per_launch": bpl, "algorithmic_bytes_per_launch": alg,
-                                   "ratio_to_algorithmic": round(bpl / alg, 4),
-                                   "per_kernel": par, "grid_size": grid, "kernel": kname}
+            "legs": {}, "workloads": {}}
+    for man_path in sorted(glob.glob(os.path.join(prof_dir, "counters_*.json"))):
+        leg = os.path.basename(man_path)[len("counters_"):-len(".json")]
+        with open(man_path) as fh:
+            manifest = json.load(fh)
+        fcsv = glob.glob(os.path.join(prof_dir, f"{leg}_fetch", "*counter_collection.csv"))
+        wcsv = glob.glob(os.path.join(prof_dir, f"{leg}_write", "*counter_collection.csv"))
+        if not fcsv or not wcsv:
+            continue
+        fetch = per_dispatch(fcsv[0], "FETCH_SIZE")
+        write = per_dispatch(wcsv[0], "WRITE_SIZE")
+        copy = [k for k in fetch if "k_copy" in k[0]]
+        if len(copy) != 1:
+            raise SystemExit(f"{leg}: expected exactly one copy-kernel grid")
+        ck = copy[0]
+        n_copy = ck[1] * 16  # one 16-byte vector per lane, read and written
+        fs, ws = n_copy / 1024.0 / fetch[ck], n_copy / 1024.0 / write[ck]
+        data["legs"][leg] = {"fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
+                             "calibration": {"kernel": "gg::k_copy", "bytes_read": n_copy,
+                                             "bytes_written": n_copy,
+                                             "FETCH_SIZE_KiB": fetch[ck],
+                                             "WRITE_SIZE_KiB": write[ck]}}
+        for name, m in manifest.items():
+            keys = [k for k in fetch if m["kernel"] in k[0] and (m["grid"] is None or k[1] == m["grid"])]
+            if not keys:
+                raise SystemExit(f"{leg}: no kernel {m['kernel']!r} grid {m['grid']} ({name})")
+            fb = sum(fetch[k] for k in keys) / len(keys) * 1024 * fs
+            wb = sum(write.get(k, 0.0) for k in keys) / len(keys) * 1024 * ws
+            alg = m["units"] * m["bytes_per_update"]
+            data["workloads"][name] = {
+                "kernel": m["kernel"], "grid_size": m["grid"], "leg": leg,
+                "fetch_bytes_per_launch": round(fb), "write_bytes_per_launch": round(wb),
+                "bytes_per_launch": round(fb + wb),
+                "algorithmic_bytes_per_launch": round(alg),
+                "ratio_to_algorithmic": round((fb + wb) / alg, 4)}
     with open(out_path, "w") as fh:
         json.dump(data, fh, indent=1)
     return data
@@ -563,15 +632,16 @@ def main(argv=None):
     ap.add_argument("--adjoint-steps", type=int, default=20000)
     ap.add_argument("--cde-steps", type=int, default=0,
                     help="timed compound-only steps per lattice (0: the defaults)")
+    ap.add_argument("--counters", metavar="LEG",
+                    choices=["lattices", "batch", "adjoint", "cde"],
+                    help="no benchmark: run one leg with plain launches for rocprofv3 --pmc "
+                         "(the manifest goes to gpurun_out/counters/counters_LEG.json)")
     ap.add_argument("--digest", metavar="DIR",
-                    help="no run: digest rocprofv3 counter CSVs under DIR into profiles/traffic.json")
-    ap.add_argument("--grids", default="",
-                    help="with --digest: grid/kernel=workload pairs, separated by ';' "
-                         "(kernel: a part of the kernel name, e.g. k_tile2<float)")
+                    help="no run: digest rocprofv3 counter CSVs and manifests under DIR "
+                         "into profiles/traffic.json")
     args = ap.parse_args(argv)
     if args.digest:
-        grids = dict(kv.split("=") for kv in args.grids.split(";") if kv)
-        d = digest_counters(args.digest, grids, os.path.join(ROOT, "profiles", "traffic.json"))
+        d = digest_counters(args.digest, os.path.join(ROOT, "profiles", "traffic.json"))
         print(json.dumps(d["workloads"]))
         return
     if args.gpus != 1:
@@ -597,6 +667,9 @@ def main(argv=None):
         return
     if args.batch_only:
         print(json.dumps(batch_bench(args.batch_steps, chunk=args.chunk)), flush=True)
+        return
+    if args.counters:
+        counters_leg(args.counters, tile)
         return
 
     form = "tune" if args.tune else ({"fuse": args.fuse, "rows": args.rows} if args.fuse else None)

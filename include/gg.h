@@ -530,6 +530,10 @@ typedef struct gg_profile {
   int64_t pass_fluid;       /* fluid nodes owned by the tiles of the pass's
                                dominant kernel (two updates each per launch) */
   int64_t pass_side_fluid;  /* fluid nodes owned by the side kernel's tiles */
+  int64_t pass_tiles;       /* tiles of the dominant kernel (one work-group of
+                               rows + 2 wavefronts each, 8 * ceil(tiles / 8)
+                               work-groups launched) */
+  int64_t pass_side_tiles;  /* tiles of the side kernel (2 rows each) */
   int32_t fuse, rows;       /* launch form used (fuse 1: single steps only) */
 } gg_profile;
 

@@ -76,6 +76,7 @@ class gg_profile(ctypes.Structure):
                 ("ms_pass", ctypes.c_double), ("n_single", ctypes.c_int64 * 2),
                 ("ms_single", ctypes.c_double * 2), ("n_monitor", ctypes.c_int64),
                 ("pass_fluid", ctypes.c_int64), ("pass_side_fluid", ctypes.c_int64),
+                ("pass_tiles", ctypes.c_int64), ("pass_side_tiles", ctypes.c_int64),
                 ("fuse", ctypes.c_int32), ("rows", ctypes.c_int32)]
 
 

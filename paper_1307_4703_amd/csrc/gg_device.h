@@ -108,23 +108,8 @@ struct LatDesc {
 #define GG_GLOBAL __attribute__((address_space(1)))
 #define GG_CONST __attribute__((address_space(4)))
 
-// Cache policy of the population streams: nontemporal loads / stores mark
-// the lines for early eviction (every population is touched once a step).
-#ifndef GG_NT_LOAD
-#define GG_NT_LOAD 0
-#endif
-#ifndef GG_NT_STORE
-#define GG_NT_STORE 0
-#endif
-
-template <class V> __device__ __forceinline__ V gload(const GG_GLOBAL V *p) {
-  if constexpr (GG_NT_LOAD) return __builtin_nontemporal_load(p);
-  else return *p;
-}
-template <class V> __device__ __forceinline__ void gstore(GG_GLOBAL V *p, V v) {
-  if constexpr (GG_NT_STORE) __builtin_nontemporal_store(v, p);
-  else *p = v;
-}
+template <class V> __device__ __forceinline__ V gload(const GG_GLOBAL V *p) { return *p; }
+template <class V> __device__ __forceinline__ void gstore(GG_GLOBAL V *p, V v) { *p = v; }
 
 // Storage traits: load into the compute type, store with rounding. W is the
 // raw storage word that sits in the planes. Every storage type holds the

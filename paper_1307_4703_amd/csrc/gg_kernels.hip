@@ -30,11 +30,6 @@ namespace gg {
 // ---------------------------------------------------------------------------
 // ODD is the parity of the step, known to the host (the layout of the state
 // alternates between the two forms above).
-#ifdef GG_WAVES_PER_EU
-#define GG_STEP_ATTR __attribute__((amdgpu_waves_per_eu(GG_WAVES_PER_EU)))
-#else
-#define GG_STEP_ATTR
-#endif
 // One tile of the fused step (every lane of the work-group calls it). TAPE:
 // also write the node's state before the step to `tape` for the adjoint,
 // planes of the compute type with the populations' plane stride: dg_0..4,
@@ -116,7 +111,7 @@ __device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
 // a grid smaller than 8 * per_xcd (a multiple of 8), blocks stride through
 // the list and stay on their XCD's run (persistent launch).
 template <class S, int BS, bool ODD>
-__global__ void __launch_bounds__(BS) GG_STEP_ATTR
+__global__ void __launch_bounds__(BS)
     k_step(const LatDesc *__restrict__ descs, const Tile *__restrict__ tiles,
            int n_tiles, int per_xcd, int tx_shift, int dt) {
   const int nb = 8 * per_xcd;

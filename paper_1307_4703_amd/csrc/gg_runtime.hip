@@ -1158,6 +1158,8 @@ gg_status gg_step_profile(gg_lattice *L, int64_t n, gg_profile *out) {
   out->rows = L->strip_h;
   out->pass_fluid = L->fuse == 4 ? L->n_fluid : L->strips_fluid;
   out->pass_side_fluid = L->fuse == 4 ? 0 : L->seg_strips_fluid;
+  out->pass_tiles = L->n_strips;
+  out->pass_side_tiles = L->fuse == 4 ? 0 : L->n_seg_strips;
   return st;
 }
 

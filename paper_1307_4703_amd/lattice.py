@@ -210,7 +210,8 @@ class Lattice:
         return {"ms_total": p.ms_total, "n_pass": p.n_pass, "ms_pass": p.ms_pass,
                 "n_single": list(p.n_single), "ms_single": list(p.ms_single),
                 "n_monitor": p.n_monitor, "pass_fluid": p.pass_fluid,
-                "pass_side_fluid": p.pass_side_fluid, "fuse": p.fuse, "rows": p.rows}
+                "pass_side_fluid": p.pass_side_fluid, "pass_tiles": p.pass_tiles,
+                "pass_side_tiles": p.pass_side_tiles, "fuse": p.fuse, "rows": p.rows}
 
     def set_monitor(self, every: int) -> None:
         """FP64 diagnostics reduced on the GPU after every `every` steps of

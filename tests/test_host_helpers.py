@@ -67,32 +67,36 @@ def _counter_csv(path, counter, rows):
 
 
 def test_digest_scales_counters_by_the_copy_kernel(tmp_path):
-    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what they
-    read for the copy kernel of known size, averaged per kernel, and set
-    against the algorithmic bytes of the named workload."""
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of each leg are scaled by
+    what they read for the copy kernel of known size in the same run,
+    averaged over the dispatches of the kernel (and grid) the leg's
+    manifest names, and set against the manifest's algorithmic bytes."""
     copy_grid = 1024                               # 1024 lanes x 16 B each way
     nbytes = copy_grid * 16
-    pf = tmp_path / "pmc_fetch"
-    pw = tmp_path / "pmc_write"
+    pf = tmp_path / "lattices_fetch"
+    pw = tmp_path / "lattices_write"
     pf.mkdir()
     pw.mkdir()
-    kern = "void gg::(anonymous namespace)::k_tile2<double, false, 14, false>(x)"
+    kern = "void gg::(anonymous namespace)::k_tile2<double, false, 14, false, false>(x)"
+    other = "void gg::(anonymous namespace)::k_tile2<double, false, 14, false, false>(x)"
     # the copy reads half of its bytes per FETCH_SIZE unit, writes all
     _counter_csv(pf / "fetch_counter_collection.csv", "FETCH_SIZE",
                  [("gg::k_copy(y)", copy_grid, nbytes / 1024 / 2),
-                  (kern, 647168, 1000.0), (kern, 647168, 1200.0)])
+                  (kern, 647168, 1000.0), (kern, 647168, 1200.0), (other, 1024, 9.0)])
     _counter_csv(pw / "write_counter_collection.csv", "WRITE_SIZE",
                  [("gg::k_copy(y)", copy_grid, nbytes / 1024),
-                  (kern, 647168, 500.0), (kern, 647168, 500.0)])
+                  (kern, 647168, 500.0), (kern, 647168, 500.0), (other, 1024, 9.0)])
+    (tmp_path / "counters_lattices.json").write_text(json.dumps(
+        {"straight_f64": {"kernel": "k_tile2<double, false, 14,", "grid": 647168,
+                          "units": 2000, "bytes_per_update": 225}}))
     out = tmp_path / "traffic.json"
-    d = bench.digest_counters(str(tmp_path), {"647168/k_tile2<double, false, 14,": "straight_f64"},
-                              str(out))
-    assert d["fetch_scale"] == pytest.approx(2.0) and d["write_scale"] == pytest.approx(1.0)
+    d = bench.digest_counters(str(tmp_path), str(out))
+    leg = d["legs"]["lattices"]
+    assert leg["fetch_scale"] == pytest.approx(2.0) and leg["write_scale"] == pytest.approx(1.0)
     w = d["workloads"]["straight_f64"]
-    assert w["per_kernel"]["k_tile2<double, false, 14, false>"] == {
-        "fetch_bytes": round(1100.0 * 1024 * 2), "write_bytes": 500 * 1024}
-    n_fluid = int(np.count_nonzero(bench.workload("straight_f64").mask == 0))
-    assert w["algorithmic_bytes_per_launch"] == n_fluid * (14 * 2 * 8 + 1)
+    assert w["fetch_bytes_per_launch"] == round(1100.0 * 1024 * 2)
+    assert w["write_bytes_per_launch"] == 500 * 1024
+    assert w["algorithmic_bytes_per_launch"] == 2000 * 225
     assert w["bytes_per_launch"] == round(1100.0 * 1024 * 2) + 500 * 1024
     assert json.loads(out.read_text())["kernel_sha"] == bench.kernel_hash()
 
