@@ -110,23 +110,28 @@ def align_steps(t):
     return (-t) % 4
 
 
-def time_lattice(name, steps, warmup, tile, chunk, form=None, monitor_every=1000,
+def time_lattice(name, steps, warmup, tile, chunk, form=None, monitor_every=1024,
                  graph_steps=None):
     """One workload: `warmup` untimed steps (plus at most 3 that align the
-    step count to the pass's parity), then exactly `steps` timed steps of
-    gg_step_profile with the FP64 monitor reduction after every
-    `monitor_every` of them (at least one, after the last step). The timed
-    region is bracketed by HIP events on the lattice's stream (torch's
-    current stream); gg_step_profile also records an event pair on that
-    stream around every launch of the dominant kernel. Then `graph_steps`
-    steps replayed from captured graphs, for comparison."""
+    step count to the pass's parity, and one graph chunk that captures the
+    graph), then exactly `steps` timed steps of gg_step_profile — graph
+    replays of `chunk` steps (at most the timed steps, rounded down to a
+    multiple of 4) and plain launches for the rest — with the FP64 monitor
+    reduction after every `monitor_every` of them (at least one, after the
+    last step). The timed region is bracketed by HIP events on the lattice's
+    stream (torch's current stream); gg_step_profile also records an event
+    pair on that stream around every graph replay and every plain launch of
+    the dominant kernel. Then `graph_steps` steps replayed from graphs of
+    `chunk` steps, for comparison."""
     import torch
     from paper_1307_4703_amd import Lattice
     from paper_1307_4703_amd import tune as T
     wl = workload(name)
     lat = Lattice.from_workload(wl)
+    # graph chunk of the timed region: whole replays inside it
+    chunk_t = min(chunk, steps // 4 * 4) if chunk > 0 else 0
     try:
-        lat.set_launch(tile[0], tile[1], chunk)
+        lat.set_launch(tile[0], tile[1], chunk_t)
         nf = lat.info()["n_fluid"]
         if form == "tune":
             res = T.tune_lattice(lat, steps=64 if nf > 1e7 else 256, graph_chunk=chunk,
@@ -143,6 +148,9 @@ def time_lattice(name, steps, warmup, tile, chunk, form=None, monitor_every=1000
         lat.step(warmup)
         extra_warm = align_steps(lat.info()["t"])
         lat.step(extra_warm)
+        if chunk_t > 0:  # the graph is captured (and replayed once) here
+            lat.step(chunk_t)
+            extra_warm += chunk_t
         mon = max(1, min(monitor_every, steps)) if steps > 0 else 0
         lat.set_monitor(mon)
         lat.sync()
@@ -164,6 +172,7 @@ def time_lattice(name, steps, warmup, tile, chunk, form=None, monitor_every=1000
         graph = None
         if graph_steps:
             k = max(4, graph_steps // 4 * 4)
+            lat.set_launch(tile[0], tile[1], chunk)
             lat.step(align_steps(lat.info()["t"]))
             lat.step(max(chunk, 4))  # graphs captured
             lat.sync()
@@ -179,6 +188,7 @@ def time_lattice(name, steps, warmup, tile, chunk, form=None, monitor_every=1000
     finally:
         lat.close()
     return {"wl": wl, "nf": nf, "wall_s": wall, "event_ms": ev_ms, "form": form,
+            "graph_chunk": chunk_t,
             "prof": prof, "diag": diag, "warmup_run": warmup + extra_warm, "steps": steps,
             "monitor_every": mon, "graph_replayed": graph}
 
@@ -196,21 +206,26 @@ def roofline(r, storage, traffic):
     present for the current kernel source, give the HBM fraction."""
     p = r["prof"]
     bpu = bytes_per_update(storage)
-    if p["n_pass"] > 0:
-        ms = p["ms_pass"] / p["n_pass"]
+    passes = p["n_pass"] + p["graph_passes"]
+    if passes > 0:
+        # plain launches timed one by one; graph replays as a whole, divided
+        # by the passes they hold (the boundary tiles' kernel runs beside)
+        ms = (p["ms_pass"] + p["ms_graph"]) / passes
         units = 2 * p["pass_fluid"]
         kind = "two-step pass (interior tiles)" if p["fuse"] != 4 else "two-step pass"
-        n_launch = p["n_pass"]
+        n_launch = passes
     else:
-        n_launch = p["n_single"][0] + p["n_single"][1]
-        ms = (p["ms_single"][0] + p["ms_single"][1]) / max(1, n_launch)
+        n_launch = p["n_single"][0] + p["n_single"][1] + p["graph_singles"]
+        ms = (p["ms_single"][0] + p["ms_single"][1] + p["ms_graph"]) / max(1, n_launch)
         units = r["nf"]
         kind = "single step"
     alg = units * bpu
     ach = alg / (ms * 1e-3) / 1e9
     out = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
-           "kernel": kind, "launches_timed": n_launch, "kernel_ms": round(ms, 5),
+           "kernel": kind, "launches_timed": n_launch,
+           "launches_in_graph_replays": p["graph_passes"] if passes > 0 else p["graph_singles"],
+           "kernel_ms": round(ms, 5),
            "updates_per_launch": units, "bytes_per_update": bpu,
            "algorithmic_bytes_per_launch": alg}
     if traffic:
@@ -605,7 +620,7 @@ def main(argv=None):
     ap.add_argument("--chunk", type=int, default=64,
                     help="graph chunk of the graph-replayed comparison and of the batch "
                          "and adjoint legs (0: plain launches everywhere)")
-    ap.add_argument("--monitor-every", type=int, default=1000,
+    ap.add_argument("--monitor-every", type=int, default=1024,
                     help="FP64 diagnostics reduction every this many timed steps")
     ap.add_argument("--fuse", type=int, default=0,
                     help="launch form (1 single steps, 2-4 two-step passes); 0: the "
@@ -698,8 +713,13 @@ def main(argv=None):
                    "peclet": getattr(wl, "peclet", None), "D": wl.D, "tau_f": wl.tau_f,
                    "valve_half_period": wl.schedule[0].duration if wl.schedule else None,
                    "launch_form": r["form"],
-                   "launches": {"pass_kernel": p["n_pass"], "single_even": p["n_single"][0],
-                                "single_odd": p["n_single"][1]},
+                   "launches": {"pass_kernel": p["n_pass"] + p["graph_passes"],
+                                "pass_kernel_in_graph_replays": p["graph_passes"],
+                                "graph_replays": p["n_graph"],
+                                "single_even": p["n_single"][0],
+                                "single_odd": p["n_single"][1],
+                                "single_in_graph_replays": p["graph_singles"]},
+                   "graph_chunk": r["graph_chunk"],
                    "warmup_steps_run": r["warmup_run"],
                    "monitor_every": r["monitor_every"], "monitor_reductions": p["n_monitor"],
                    "bytes_per_update": bytes_per_update(wl.storage),

@@ -522,8 +522,12 @@ gg_status gg_monitor_read(gg_lattice *lat, gg_diag *out, int64_t *count);
  * step kernel of each single step. */
 typedef struct gg_profile {
   double ms_total;          /* HIP events around the whole call */
-  int64_t n_pass;           /* launches of the pass's dominant kernel */
+  int64_t n_pass;           /* plain launches of the pass's dominant kernel */
   double ms_pass;           /* their summed event-measured duration */
+  int64_t n_graph;          /* graph replays (gg_set_launch graph_chunk) */
+  double ms_graph;          /* their summed event-measured duration */
+  int64_t graph_passes;     /* two-step passes inside those replays */
+  int64_t graph_singles;    /* single steps inside those replays */
   int64_t n_single[2];      /* single steps at even / odd t */
   double ms_single[2];      /* their summed duration */
   int64_t n_monitor;        /* monitor reductions launched (gg_set_monitor) */
@@ -537,12 +541,14 @@ typedef struct gg_profile {
   int32_t fuse, rows;       /* launch form used (fuse 1: single steps only) */
 } gg_profile;
 
-/* Instrumentation: gg_step(lat, n) launched without graph replays, with a
- * pair of HIP events recorded on the lattice's stream around every launch
- * of the dominant kernel and a pair around the whole call; waits for the
- * stream and returns the event-measured durations. The state advances
- * exactly as with gg_step (monitor reductions included). Errors as
- * gg_step, GG_ERR_HIP if an event fails. */
+/* Instrumentation: gg_step(lat, n) with a pair of HIP events recorded on
+ * the lattice's stream around every plain launch of the dominant kernel,
+ * around every graph replay (whose passes or steps are counted) and around
+ * the whole call; waits for the stream and returns the event-measured
+ * durations. The launches are those of gg_step (graph replays, plain
+ * passes, single steps, monitor reductions), and the state advances
+ * exactly as with gg_step. Errors as gg_step, GG_ERR_HIP if an event
+ * fails. */
 gg_status gg_step_profile(gg_lattice *lat, int64_t n, gg_profile *out);
 
 /* Instrumentation: shuffle the order of the tiles and strips the steps

@@ -73,7 +73,9 @@ class gg_grads(ctypes.Structure):
 
 class gg_profile(ctypes.Structure):
     _fields_ = [("ms_total", ctypes.c_double), ("n_pass", ctypes.c_int64),
-                ("ms_pass", ctypes.c_double), ("n_single", ctypes.c_int64 * 2),
+                ("ms_pass", ctypes.c_double), ("n_graph", ctypes.c_int64),
+                ("ms_graph", ctypes.c_double), ("graph_passes", ctypes.c_int64),
+                ("graph_singles", ctypes.c_int64), ("n_single", ctypes.c_int64 * 2),
                 ("ms_single", ctypes.c_double * 2), ("n_monitor", ctypes.c_int64),
                 ("pass_fluid", ctypes.c_int64), ("pass_side_fluid", ctypes.c_int64),
                 ("pass_tiles", ctypes.c_int64), ("pass_side_tiles", ctypes.c_int64),

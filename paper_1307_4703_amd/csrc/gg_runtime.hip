@@ -1009,10 +1009,14 @@ static gg_status step_run(gg_lattice *L, int64_t n) {
     L->t += 1;
     left -= 1;
   }
-  if (K > 0 && left >= K && !L->prof) {
+  if (K > 0 && left >= K) {
     if (!L->graph_exec) {
+      // (no profiling events inside the captured graph)
+      const bool prof = L->prof;
+      L->prof = false;
       GG_HIP(hipStreamBeginCapture(L->cap_stream, hipStreamCaptureModeThreadLocal));
       hipError_t e = launch_steps(L, 0, K, L->cap_stream);
+      L->prof = prof;
       hipGraph_t g = nullptr;
       hipError_t e2 = hipStreamEndCapture(L->cap_stream, &g);
       if (e != hipSuccess || e2 != hipSuccess) {
@@ -1024,7 +1028,11 @@ static gg_status step_run(gg_lattice *L, int64_t n) {
       GG_HIP(hipGraphInstantiate(&L->graph_exec, L->graph, nullptr, nullptr, 0));
     }
     while (left >= K) {
+      // (profiling: one event pair around each replay, kind 3)
+      long pidx = -1;
+      GG_HIP(prof_begin(L, L->stream, pidx));
       GG_HIP(hipGraphLaunch(L->graph_exec, L->stream));
+      GG_HIP(prof_end(L, L->stream, pidx, 3));
       left -= K;
       L->t += K;
     }
@@ -1146,6 +1154,11 @@ gg_status gg_step_profile(gg_lattice *L, int64_t n, gg_profile *out) {
     if (kind == 0) {
       out->n_pass += 1;
       out->ms_pass += x;
+    } else if (kind == 3) {
+      out->n_graph += 1;
+      out->ms_graph += x;
+      if (pass_ok(L)) out->graph_passes += L->graph_chunk / 2;
+      else out->graph_singles += L->graph_chunk;
     } else {
       out->n_single[kind - 1] += 1;
       out->ms_single[kind - 1] += x;

@@ -202,12 +202,14 @@ class Lattice:
         return a.value, b.value
 
     def step_profile(self, n: int) -> dict:
-        """gg_step_profile: n steps with plain launches and HIP events
-        around every launch of the dominant kernel (two-step pass or single
-        step); durations in milliseconds."""
+        """gg_step_profile: n steps of gg_step with HIP events around every
+        plain launch of the dominant kernel (two-step pass or single step)
+        and around every graph replay; durations in milliseconds."""
         p = A.gg_profile()
         A.call("gg_step_profile", self._h, int(n), ctypes.byref(p))
         return {"ms_total": p.ms_total, "n_pass": p.n_pass, "ms_pass": p.ms_pass,
+                "n_graph": p.n_graph, "ms_graph": p.ms_graph, "graph_passes": p.graph_passes,
+                "graph_singles": p.graph_singles,
                 "n_single": list(p.n_single), "ms_single": list(p.ms_single),
                 "n_monitor": p.n_monitor, "pass_fluid": p.pass_fluid,
                 "pass_side_fluid": p.pass_side_fluid, "pass_tiles": p.pass_tiles,

@@ -31,9 +31,13 @@ def test_bench_line(capsys, argv, workload):
     assert line["config"]["workload"] == workload
     assert line["value"] > 0 and line["ms_per_step"] > 0
     launches = line["config"]["launches"]
-    # every timed step is a pass step (two per launch) or a single step
-    assert 2 * launches["pass_kernel"] + launches["single_even"] + launches["single_odd"] == steps
+    # every timed step is a pass step (two per launch) or a single step,
+    # plain or inside a graph replay of the timed steps rounded down to 4
+    assert (2 * launches["pass_kernel"] + launches["single_even"] + launches["single_odd"] +
+            launches["single_in_graph_replays"]) == steps
     assert launches["pass_kernel"] == steps // 4 * 2
+    assert launches["pass_kernel_in_graph_replays"] == steps // 4 * 2
+    assert line["config"]["graph_chunk"] == steps // 4 * 4
     assert line["config"]["warmup_steps_run"] % 4 == 0
     rf = line["roofline"]
     assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0

@@ -62,11 +62,13 @@ def test_profiled_steps_equal_plain_steps(fuse):
     fa, ga = a.populations()
     fb, gb = b.populations()
     assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+    # graph chunk 8: one odd step, two replays of 8 steps, the rest plain
+    assert p["n_graph"] == 2
     if fuse == 1:
-        assert p["n_pass"] == 0 and sum(p["n_single"]) == 22
-        assert p["n_single"] == [11, 11]
+        assert p["n_pass"] == 0 and p["graph_passes"] == 0 and p["graph_singles"] == 16
+        assert sum(p["n_single"]) == 6 and p["n_single"] == [3, 3]
     else:
-        assert p["n_pass"] == 10 and sum(p["n_single"]) == 2
+        assert p["graph_passes"] == 8 and p["n_pass"] == 2 and sum(p["n_single"]) == 2
         assert p["pass_fluid"] + p["pass_side_fluid"] == a.info()["n_fluid"]
-    assert p["ms_total"] > 0 and p["ms_pass"] >= 0
-    assert p["ms_pass"] + sum(p["ms_single"]) <= p["ms_total"] * 1.01
+    assert p["ms_total"] > 0 and p["ms_pass"] >= 0 and p["ms_graph"] > 0
+    assert p["ms_pass"] + p["ms_graph"] + sum(p["ms_single"]) <= p["ms_total"] * 1.01

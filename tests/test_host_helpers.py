@@ -114,6 +114,7 @@ def _fake_run(nf, steps, event_ms, prof):
 
 def test_bench_roofline_pass_and_single():
     prof = {"n_pass": 10, "ms_pass": 1.0, "n_single": [0, 0], "ms_single": [0.0, 0.0],
+            "n_graph": 0, "ms_graph": 0.0, "graph_passes": 0, "graph_singles": 0,
             "pass_fluid": 1000000, "fuse": 3}
     r = _fake_run(1100000, 20, 2.0, prof)
     out = bench.roofline(r, "f16", traffic=None)
@@ -127,9 +128,17 @@ def test_bench_roofline_pass_and_single():
     assert out["traffic_gbs"] == pytest.approx(60000000 / 1e-4 / 1e9, rel=1e-3)
     assert out["traffic_per_algorithmic_single_trip"] == pytest.approx(60 / 57, rel=1e-3)
     prof = {"n_pass": 0, "ms_pass": 0.0, "n_single": [3, 2], "ms_single": [0.3, 0.2],
+            "n_graph": 0, "ms_graph": 0.0, "graph_passes": 0, "graph_singles": 0,
             "pass_fluid": 0, "fuse": 1}
     out = bench.roofline(_fake_run(500000, 5, 1.0, prof), "f32", traffic=None)
     assert out["algorithmic_bytes_per_launch"] == 500000 * 113
+    assert out["kernel_ms"] == pytest.approx(0.1)
+    # graph replays: their duration over the passes they hold
+    prof = {"n_pass": 2, "ms_pass": 0.2, "n_single": [0, 0], "ms_single": [0.0, 0.0],
+            "n_graph": 1, "ms_graph": 0.8, "graph_passes": 8, "graph_singles": 0,
+            "pass_fluid": 1000000, "fuse": 3}
+    out = bench.roofline(_fake_run(1100000, 20, 2.0, prof), "f16", traffic=None)
+    assert out["launches_timed"] == 10 and out["launches_in_graph_replays"] == 8
     assert out["kernel_ms"] == pytest.approx(0.1)
 
 
