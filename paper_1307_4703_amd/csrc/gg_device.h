@@ -6,6 +6,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+#include <limits>
+
 #include "gg.h"
 
 namespace gg {
@@ -21,6 +24,70 @@ constexpr double WF[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9
 // Link code byte per node: bit k-1 set <=> cell x + e_k is not fluid
 // (k = 1..8). NOT_FLUID marks a node that is not updated.
 constexpr uint8_t NOT_FLUID = 0xFF;
+
+// Constants of the two BGK collisions in the compute type T, in the form
+// the collision evaluates them: x* = omc x + (om w_i) x^eq-part, with the
+// relaxation rate folded into the weights (paper Eqs. 4-6 for the fluid,
+// Eqs. 8-9 for the compound).
+//
+// Fluid: ka = om w_axis is taken with at most p - 4 significant bits (p the
+// mantissa width of T; also a multiple of 2^-p when 9 ka < 1/2), so that
+// the rate actually used, 9 ka, and every other constant (om w_0 = 4 ka,
+// om w_diag = ka / 4, 3 om w_axis, 3 om w_diag) is exact in T, and
+// 1 - 9 ka is exact as well. The weights' own rounding then moves neither
+// the mass nor the momentum that the relaxation carries: with weights
+// rounded one by one, the momentum of every node grew or shrank by a fixed
+// factor of about 1e-7 per step in FP32, which acts as a body force on the
+// whole flow. The rate moves by at most 2^(4-p) relative (1e-6 in FP32)
+// for om >= 9/32, and by at most 2^-(p+1) 9/om below.
+//
+// Compound: omc is 1 - om rounded, ome = 1 - omc the rate used (1 - om is
+// exact for om >= 1/2, otherwise omc lies in [1/2, 1), where 1 - omc is
+// exact), and the rest product is ome - 4 (ome w_axis), exact for axis
+// weights (1 - w0)/4 with 0 <= w0 <= 1/2: the five products sum to ome and
+// the collision carries no bias in proportion to C.
+template <class T> struct CollK {
+  T f_omc, f_k0, f_ka, f_kd, f_k3a, f_k3d;  // 1 - om_f; om w_0, w_axis, w_diag; 3 om w_axis, w_diag
+  T g_omc, g_k0, g_ka, g_ki, g_w0, g_pad;   // 1 - om_g; om w_0, w_axis; om w_axis / cs2; 1 - 4 w_axis
+};
+
+// Host side: om w_axis of the fluid rounded as described above.
+inline double collk_fluid_ka(double omega_f, int p) {
+  const double ka = omega_f / 9.0;
+  int ex;
+  std::frexp(ka, &ex);                 // ka = m 2^ex, m in [1/2, 1)
+  int e = ex - (p - 4);                // keep p - 4 bits
+  double q = std::ldexp(std::nearbyint(std::ldexp(ka, -e)), e);
+  if (9.0 * q < 0.5 && e < -p) {       // 1 - 9 ka exact: a multiple of 2^-p
+    e = -p;
+    q = std::ldexp(std::nearbyint(std::ldexp(ka, -e)), e);
+  }
+  return q;
+}
+
+template <class T>
+inline CollK<T> make_collk(double omega_f, double omega_g, double wg_axis, double inv_cs2g) {
+#pragma clang fp contract(off)
+  CollK<T> k;
+  const int p = std::numeric_limits<T>::digits;
+  const T ka = (T)collk_fluid_ka(omega_f, p);
+  k.f_omc = T(1) - T(9) * ka;
+  k.f_k0 = T(4) * ka;
+  k.f_ka = ka;
+  k.f_kd = ka * T(0.25);
+  k.f_k3a = T(3) * ka;
+  k.f_k3d = k.f_k3a * T(0.25);
+  const T omg = (T)omega_g;
+  k.g_omc = T(1) - omg;
+  const T gome = T(1) - k.g_omc;
+  const T wga = (T)wg_axis;
+  k.g_ka = gome * wga;
+  k.g_k0 = gome - T(4) * k.g_ka;
+  k.g_ki = k.g_ka * (T)inv_cs2g;
+  k.g_w0 = T(1) - T(4) * wga;
+  k.g_pad = T(0);
+  return k;
+}
 
 // Tile flag: some node of the tile has a link into a boundary segment.
 constexpr int TILE_TOUCHES_SEGMENT = 1;
@@ -65,6 +132,9 @@ struct LatDesc {
   // the same constants rounded to FP32 once on the host, for the FP32
   // compute type (the kernels read them as they are)
   float rho0_f, omega_f_f, omega_g_f, wg_axis_f, inv_cs2g_f, k_decay_f, c_shift_f, kpad_f;
+  // collision constants, FP64 and FP32 (make_collk)
+  CollK<double> ck;
+  CollK<float> ck_f;
   // segments, index id - GG_FIRST_SEGMENT
   int32_t seg_kind[GG_MAX_SEGMENTS];
   int32_t seg_nx[GG_MAX_SEGMENTS];

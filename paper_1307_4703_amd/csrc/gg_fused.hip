@@ -308,26 +308,27 @@ __global__ void __launch_bounds__((R + 2) * 64)
     const bool row = yr >= -1 && yr <= ny && w <= rows + 1;
     const bool own = own_col && w >= 1 && w <= rows && yr < ny;
     const uint32_t node = (uint32_t)(L.node0 + y * pitch + x);
-    // every load of the row is issued at once: the link code, the
-    // populations of any addressable cell (non-fluid cells hold finite values
-    // nobody uses), and on segment tiles the neighbours' mask values
-    uint8_t lc = NOT_FLUID;
+    // every load of the row is issued at once, by every lane: the link code
+    // and the populations of any addressable cell (non-fluid cells hold
+    // finite values nobody uses; lanes off the addressable cells read node
+    // (0, 0) and take the link code of a non-fluid cell), and on segment
+    // tiles the neighbours' mask values
+    const bool live = row && col;
+    const uint32_t lnode = live ? node : (uint32_t)L.node0;
+    const uint8_t lc = live ? ((const GG_GLOBAL uint8_t *)L.link)[lnode] : NOT_FLUID;
     T f[9], g[5];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = P::ld(src.at(i, lnode));
+#pragma unroll
+    for (int i = 0; i < 5; ++i) g[i] = P::ld(src.at(9 + i, lnode));
     uint32_t nbr[2] = {0u, 0u};
-    if (row && col) {
-      lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
+    // (only for cells inside the lattice, whose neighbours all lie in the
+    // padded planes; the halo cells outside are not fluid)
+    if (seg && live && x >= 0 && x < nx && y >= 0 && y < ny) {
+      const Neigh nb(L, x, y);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) f[i] = P::ld(src.at(i, node));
-#pragma unroll
-      for (int i = 0; i < 5; ++i) g[i] = P::ld(src.at(9 + i, node));
-      // (only for cells inside the lattice, whose neighbours all lie in the
-      // padded planes; the halo cells outside are not fluid)
-      if (seg && x >= 0 && x < nx && y >= 0 && y < ny) {
-        const Neigh nb(L, x, y);
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-          nbr[k >> 2] |= (uint32_t)((const GG_GLOBAL uint8_t *)L.mask)[nb.idx[k + 1]] << (8 * (k & 3));
-      }
+      for (int k = 0; k < 8; ++k)
+        nbr[k >> 2] |= (uint32_t)((const GG_GLOBAL uint8_t *)L.mask)[nb.idx[k + 1]] << (8 * (k & 3));
     }
 
     // step t on this row
@@ -355,8 +356,11 @@ __global__ void __launch_bounds__((R + 2) * 64)
       *tp.at(5, node) = ux;
       *tp.at(6, node) = uy;
     }
+    // step t on every lane of the interior tiles (what a non-fluid lane
+    // computes is never taken: its neighbours take their link rule's value
+    // instead), on the fluid lanes of the segment tiles
     T pf[9], pg[5], inf[9], ing[5];
-    if (lc != NOT_FLUID) {
+    if (!SEG || lc != NOT_FLUID) {
       collide_node<T, PRESS>(L, x, y, lc, seg, ph1, f, g, pf, pg, inf, ing, fx, own,
                              SEG ? nbr : nullptr);
     } else {

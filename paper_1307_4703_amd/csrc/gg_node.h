@@ -58,6 +58,7 @@ template <> struct DK<double> {
   static __device__ __forceinline__ double ics(CDesc &L) { return L.inv_cs2g; }
   static __device__ __forceinline__ double kdec(CDesc &L) { return L.k_decay; }
   static __device__ __forceinline__ double cs(CDesc &L) { return L.c_shift; }
+  static __device__ __forceinline__ const GG_CONST CollK<double> &ck(CDesc &L) { return L.ck; }
 };
 template <> struct DK<float> {
   static __device__ __forceinline__ float rho0(CDesc &L) { return L.rho0_f; }
@@ -67,6 +68,7 @@ template <> struct DK<float> {
   static __device__ __forceinline__ float ics(CDesc &L) { return L.inv_cs2g_f; }
   static __device__ __forceinline__ float kdec(CDesc &L) { return L.k_decay_f; }
   static __device__ __forceinline__ float cs(CDesc &L) { return L.c_shift_f; }
+  static __device__ __forceinline__ const GG_CONST CollK<float> &ck(CDesc &L) { return L.ck_f; }
 };
 
 // e_i . u for direction i (paper Eq. 3 velocities), written out per
@@ -243,34 +245,65 @@ __device__ __forceinline__ void node_velocity(CDesc &L, const T *f, T &rho, T &d
 
 // Compound collision at (x, y) with fluid velocity u: linear equilibrium
 // (Eq. 9), BGK (Eq. 8), source R - kC of Eq. 2 distributed with the
-// lattice weights. With C = C_s + dC: g^eq_i - w_i C_s = w_i (dC + C e.u / cs2).
+// lattice weights. With C = C_s + dC, g^eq_i - w_i C_s = w_i (dC + C e.u / cs2):
+// a part even in e_i, w_i dC, and an odd one, w_i C e.u / cs2, so opposite
+// directions share every product but the last:
+//   pg_i = (1 - om) g_i + om w_i (dC + C e.u / cs2) + w_i src.
 template <class T>
 __device__ __forceinline__ void compound_collide(CDesc &L, int x, int y, const T *g, T ux, T uy,
                                                  T *pg) {
 #pragma clang fp contract(off)
-  const T cs = DK<T>::cs(L);
+  const GG_CONST CollK<T> &K = DK<T>::ck(L);
   const T dC = g[0] + g[1] + g[2] + g[3] + g[4];
-  const T C = cs + dC;
-  // The rest weight is 1 - 4 w_axis in the compute type, so the five
-  // weights sum to one exactly: with both weights rounded on their own
-  // (1/3 and 1/6 in FP32 sum to 1 + 3e-8) every collision would create
-  // solute in proportion to C.
-  const T wga = DK<T>::wga(L);
-  const T wg[5] = {T(1) - T(4) * wga, wga, wga, wga, wga};
-  const T ics = DK<T>::ics(L);
+  const T C = DK<T>::cs(L) + dC;
   T src = -DK<T>::kdec(L) * C;
   if (L.has_source) {
     const int rx = x - L.r_x0, ry = y - L.r_y0;
     if (rx >= 0 && rx < L.r_w && ry >= 0 && ry < L.r_h)
       src += (T)((const GG_GLOBAL double *)L.R)[ry * L.r_w + rx];
   }
-  const T om_g = DK<T>::om_g(L);
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    const T eu = e_dot_u<T>(i, ux, uy);
-    const T dgeq = wg[i] * fmad(C * eu, ics, dC);
-    pg[i] = fmad(wg[i], src, fmad(om_g, dgeq - g[i], g[i]));
-  }
+  const T even0 = fmad(K.g_k0, dC, K.g_w0 * src);
+  const T even = fmad(K.g_ka, dC, DK<T>::wga(L) * src);
+  const T oddC = K.g_ki * C;
+  const T ox = oddC * ux, oy = oddC * uy;
+  pg[0] = fmad(K.g_omc, g[0], even0);
+  pg[1] = fmad(K.g_omc, g[1], even + ox);
+  pg[3] = fmad(K.g_omc, g[3], even - ox);
+  pg[2] = fmad(K.g_omc, g[2], even + oy);
+  pg[4] = fmad(K.g_omc, g[4], even - oy);
+}
+
+// One pair of opposite fluid directions i, o = opp(i) with e = e_i.u: the
+// even part k (q + 4.5 rho e^2) and the odd part r e of om w (f^eq - w rho0)
+// (k = om w, r = 3 om w rho, q = drho - 1.5 rho u.u).
+template <class T>
+__device__ __forceinline__ void relax_pair(T omc, T fi, T fo, T e, T k, T r, T r45, T q, T &pi,
+                                           T &po) {
+#pragma clang fp contract(off)
+  const T ev = k * fmad(r45 * e, e, q);
+  const T od = r * e;
+  pi = fmad(omc, fi, ev + od);
+  po = fmad(omc, fo, ev - od);
+}
+
+// BGK relaxation of the fluid deviations toward the quadratic equilibrium
+// (Eqs. 4-6): f^eq_i - w_i rho0 = w_i (drho + rho (3 e.u + 4.5 (e.u)^2 -
+// 1.5 u.u)), split into the part even in e_i, w_i (drho - 1.5 rho u.u +
+// 4.5 rho (e.u)^2), and the odd one, 3 w_i rho e.u; opposite directions
+// share both:  pf_i = (1 - om) f_i + om w_i (even_i +- odd_i).
+template <class T>
+__device__ __forceinline__ void fluid_collide(CDesc &L, const T *f, T rho, T drho, T ux, T uy,
+                                              T usq, T *pf) {
+#pragma clang fp contract(off)
+  const GG_CONST CollK<T> &K = DK<T>::ck(L);
+  const T q = fmad(rho, T(-1.5) * usq, drho);
+  const T r45 = T(4.5) * rho;
+  const T ra = K.f_k3a * rho, rd = K.f_k3d * rho;
+  pf[0] = fmad(K.f_omc, f[0], K.f_k0 * q);
+  relax_pair<T>(K.f_omc, f[1], f[3], ux, K.f_ka, ra, r45, q, pf[1], pf[3]);
+  relax_pair<T>(K.f_omc, f[2], f[4], uy, K.f_ka, ra, r45, q, pf[2], pf[4]);
+  relax_pair<T>(K.f_omc, f[5], f[7], ux + uy, K.f_kd, rd, r45, q, pf[5], pf[7]);
+  relax_pair<T>(K.f_omc, f[6], f[8], uy - ux, K.f_kd, rd, r45, q, pf[6], pf[8]);
 }
 
 // Collision of fluid node (x, y) with link code lc, from the deviations f, g
@@ -302,18 +335,7 @@ __device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc,
   node_velocity<T>(L, f, rho, drho, ux, uy);
   const T usq = fmad(ux, ux, uy * uy);
 
-  // BGK relaxation of f toward the quadratic equilibrium, Eqs. 4-6, for
-  // the deviations: f^eq_i - w_i rho0 = w_i (drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)).
-  const T om_f = DK<T>::om_f(L);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const T eu = e_dot_u<T>(i, ux, uy);
-    // 3 e.u + 4.5 (e.u)^2 - 1.5 u.u = e.u (4.5 e.u + 3) - 1.5 u.u
-    const T poly = fmad(eu, fmad(T(4.5), eu, T(3)), T(-1.5) * usq);
-    const T dfeq = (T)WF[i] * fmad(rho, poly, drho);
-    pf[i] = fmad(om_f, dfeq - f[i], f[i]);
-  }
-
+  fluid_collide<T>(L, f, rho, drho, ux, uy, usq, pf);
   compound_collide<T>(L, x, y, g, ux, uy, pg);
   const T cs = DK<T>::cs(L);
   const T wga = DK<T>::wga(L);

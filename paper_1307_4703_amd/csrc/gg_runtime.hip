@@ -168,6 +168,8 @@ gg_status gg_upload_desc(gg_lattice *L) {
   h.inv_cs2g_f = (float)h.inv_cs2g;
   h.k_decay_f = (float)h.k_decay;
   h.c_shift_f = (float)h.c_shift;
+  h.ck = make_collk<double>(h.omega_f, h.omega_g, h.wg_axis, h.inv_cs2g);
+  h.ck_f = make_collk<float>(h.omega_f, h.omega_g, h.wg_axis, h.inv_cs2g);
   for (int s = 0; s < GG_MAX_SEGMENTS; ++s) {
     const SegHost &g = L->seg[s];
     h.seg_kind[s] = g.set ? g.kind : 0;

@@ -132,6 +132,21 @@ static T fused(T a, T b, T c) {
   return sizeof(T) == 4 ? (T)fmaf((float)a, (float)b, (float)c) : (T)fma((double)a, (double)b, (double)c);
 }
 
+/* om w_axis of the fluid: omega / 9 with at most p - 4 significant bits,
+ * and a multiple of 2^-p where 9 ka < 1/2 */
+static double fluid_ka(double omega, int p) {
+  const double ka = omega / 9.0;
+  int ex;
+  frexp(ka, &ex);
+  int e = ex - (p - 4);
+  double q = ldexp(nearbyint(ldexp(ka, -e)), e);
+  if (9.0 * q < 0.5 && e < -p) {
+    e = -p;
+    q = ldexp(nearbyint(ldexp(ka, -e)), e);
+  }
+  return q;
+}
+
 /* phase in force during step t (fixed at the start of the step) */
 static int phase_of(const emu_lattice *L, int64_t t) {
   if (L->n_phases == 0) return -1;
@@ -165,10 +180,24 @@ void emu_step(const emu_lattice *L, int64_t t, const T *h, const T *k, T *h_out,
   /* the kernels' constants: derived in double, then taken to the compute type */
   const double cs2g = (1.0 - L->w0) / 2.0;
   const double tau_g = 0.5 + L->D / cs2g;
-  const T om_f = (T)(1.0 / L->tau_f), om_g = (T)(1.0 / tau_g);
+  const T om_g = (T)(1.0 / tau_g);
   const T ics = (T)(1.0 / cs2g), rho0 = (T)L->rho0, cs = (T)L->c_shift;
   const T wa = (T)((1.0 - L->w0) / 4.0);
   const T wg[5] = {(T)1 - (T)4 * wa, wa, wa, wa, wa};
+  /* relaxation written as (1 - om) x + (om w_i) x^eq-part, with the
+   * library's constants: for the fluid om w_axis = ka rounded to p - 4
+   * significant bits (and to a multiple of 2^-p where 9 ka < 1/2), so that
+   * 9 ka, 1 - 9 ka and every product with the weights are exact; for the
+   * compound the rounded 1 - om, the rate 1 - (1 - om) that goes with it,
+   * and its products with the weights */
+  const int p = sizeof(T) == 4 ? 24 : 53;
+  const T f_ka = (T)fluid_ka(1.0 / L->tau_f, p);
+  const T f_omc = (T)1 - (T)9 * f_ka;
+  const T f_k0 = (T)4 * f_ka, f_kd = f_ka * (T)0.25, f_k3a = (T)3 * f_ka, f_k3d = f_k3a * (T)0.25;
+  const T g_omc = (T)1 - om_g, g_ome = (T)1 - g_omc;
+  const T g_ka = g_ome * wa, g_k0 = g_ome - (T)4 * g_ka, g_ki = g_ka * ics;
+  const T fk[9] = {f_k0, f_ka, f_ka, f_ka, f_ka, f_kd, f_kd, f_kd, f_kd};
+  const T fr3[9] = {0, f_k3a, f_k3a, f_k3a, f_k3a, f_k3d, f_k3d, f_k3d, f_k3d};
   const int ph = phase_of(L, t);
   const uint32_t open = ph < 0 ? 0xFFFFFFFFu : L->phase_open[ph];
   /* post-collision values of every node, and the value that arrives at each
@@ -189,14 +218,25 @@ void emu_step(const emu_lattice *L, int64_t t, const T *h, const T *k, T *h_out,
       const T ir = (T)1 / rho;
       const T ux = jx * ir, uy = jy * ir;
       const T uu = fused(ux, ux, uy * uy);
-      /* fluid: f_i^eq - w_i rho0 = w_i (drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)) */
-      for (int i = 0; i < 9; ++i) {
-        const T eu = edu(i, ux, uy);
-        const T p = fused(eu, fused((T)4.5, eu, (T)3), (T)(-1.5) * uu);
-        const T deq = (T)W9[i] * fused(rho, p, dr);
-        pf[i] = fused(om_f, deq - f[i], f[i]);
+      /* fluid: f_i^eq - w_i rho0 = w_i (drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)),
+       * the even part w_i (q + 4.5 rho (e.u)^2) with q = drho - 1.5 rho u.u
+       * and the odd part 3 w_i rho e.u, each times om; pf_i = (1 - om) f_i + both */
+      const T q = fused(rho, (T)(-1.5) * uu, dr);
+      const T r45 = (T)4.5 * rho;
+      pf[0] = fused(f_omc, f[0], f_k0 * q);
+      for (int i = 1; i < 5; ++i) {
+        /* i and its opposite REV[i] share e.u up to the sign; e.u as the
+         * kernels form it for the direction of the pair they take first */
+        const int a = (i <= 2) ? i : 4 + i - 2; /* 1, 2, 5, 6 */
+        const int o = REV[a];
+        const T eu = edu(a, ux, uy);
+        const T ev = fk[a] * fused(r45 * eu, eu, q);
+        const T od = (fr3[a] * rho) * eu;
+        pf[a] = fused(f_omc, f[a], ev + od);
+        pf[o] = fused(f_omc, f[o], ev - od);
       }
-      /* compound: g_i^eq - w_i C_s = w_i (dC + C e.u / cs2), plus w_i (R - kC) */
+      /* compound: g_i^eq - w_i C_s = w_i (dC + C e.u / cs2), plus w_i (R - kC);
+       * pg_i = (1 - om) g_i + om w_i dC + w_i src +- om w_i C e.u / cs2 */
       T dc = g[0];
       for (int i = 1; i < 5; ++i) dc = dc + g[i];
       const T C = cs + dc;
@@ -205,11 +245,15 @@ void emu_step(const emu_lattice *L, int64_t t, const T *h, const T *k, T *h_out,
         const int rx = x - L->r_x0, ry = y - L->r_y0;
         if (rx >= 0 && rx < L->r_w && ry >= 0 && ry < L->r_h) src += (T)L->R[(size_t)ry * L->r_w + rx];
       }
-      for (int i = 0; i < 5; ++i) {
-        const T eu = edu(i, ux, uy);
-        const T deq = wg[i] * fused(C * eu, ics, dc);
-        pg[i] = fused(wg[i], src, fused(om_g, deq - g[i], g[i]));
-      }
+      const T even0 = fused(g_k0, dc, wg[0] * src);
+      const T even = fused(g_ka, dc, wa * src);
+      const T oddc = g_ki * C;
+      const T ox = oddc * ux, oy = oddc * uy;
+      pg[0] = fused(g_omc, g[0], even0);
+      pg[1] = fused(g_omc, g[1], even + ox);
+      pg[3] = fused(g_omc, g[3], even - ox);
+      pg[2] = fused(g_omc, g[2], even + oy);
+      pg[4] = fused(g_omc, g[4], even - oy);
       /* links from non-fluid cells: bounce-back, or an open segment's rule */
       for (int j = 0; j < 9; ++j) inf[j] = pf[REV[j]];
       for (int j = 0; j < 5; ++j) ing[j] = pg[REV[j]];
