@@ -193,15 +193,26 @@ template <> struct Pop<double> {
   using W = double;
   static __device__ __forceinline__ T ld(const GG_GLOBAL W *p) { return gload(p); }
   static __device__ __forceinline__ void st(GG_GLOBAL W *p, T v) { gstore(p, v); }
-  // the value a store followed by a load gives back
+  // two stores at once (one conversion for both where the storage is packed)
+  static __device__ __forceinline__ void st2(GG_GLOBAL W *p, GG_GLOBAL W *q, T a, T b) {
+    gstore(p, a);
+    gstore(q, b);
+  }
+  // the value a store followed by a load gives back (of one, of two values)
   static __device__ __forceinline__ T rt(T v) { return v; }
+  static __device__ __forceinline__ void rt2(T &, T &) {}
 };
 template <> struct Pop<float> {
   using T = float;
   using W = float;
   static __device__ __forceinline__ T ld(const GG_GLOBAL W *p) { return gload(p); }
   static __device__ __forceinline__ void st(GG_GLOBAL W *p, T v) { gstore(p, v); }
+  static __device__ __forceinline__ void st2(GG_GLOBAL W *p, GG_GLOBAL W *q, T a, T b) {
+    gstore(p, a);
+    gstore(q, b);
+  }
   static __device__ __forceinline__ T rt(T v) { return v; }
+  static __device__ __forceinline__ void rt2(T &, T &) {}
 };
 template <> struct Pop<__half> {
   using T = float;
@@ -222,6 +233,28 @@ template <> struct Pop<__half> {
   }
   // the value a store followed by a load gives back
   static __device__ __forceinline__ T rt(T v) { return __half2float(to_half(v)); }
+  // Two values rounded by one packed conversion (v_cvt_pk_f16_f32: round to
+  // nearest even, as the single conversion). A packed conversion is never
+  // folded into the arithmetic before it, so it needs no barrier.
+  using H2 = _Float16 __attribute__((ext_vector_type(2)));
+  using F2 = float __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ H2 to_half2(T a, T b) {
+    F2 v;
+    v[0] = a;
+    v[1] = b;
+    return __builtin_convertvector(v, H2);
+  }
+  static __device__ __forceinline__ void st2(GG_GLOBAL W *p, GG_GLOBAL W *q, T a, T b) {
+    const H2 h = to_half2(a, b);
+    const _Float16 h0 = h[0], h1 = h[1];
+    gstore(p, __builtin_bit_cast(W, h0));
+    gstore(q, __builtin_bit_cast(W, h1));
+  }
+  static __device__ __forceinline__ void rt2(T &a, T &b) {
+    const H2 h = to_half2(a, b);
+    a = (T)h[0];
+    b = (T)h[1];
+  }
 };
 
 }  // namespace gg

@@ -47,23 +47,24 @@ __device__ __forceinline__ void second_step(CDesc &L, const Planes<typename Pop<
   T qf[9], qg[5], jf[9], jg[5];
   collide_node<T, PRESS>(L, x, y, lc, SEG, ph, sf, sg, qf, qg, jf, jg, fx, true, nbr);
   const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
-  P::st(dst.at(0, node), qf[0]);
-  P::st(dst.at(9, node), qg[0]);
+  // (stores in pairs: one conversion for two values where FP16 is stored)
+  P::st2(dst.at(0, node), dst.at(9, node), qf[0], qg[0]);
+  uint32_t nb[9];
   if (!L.periodic_x && !L.periodic_y) {
     // (uniform) the neighbours are node + e_x + e_y pitch, padding included
     const uint32_t pitch = (uint32_t)L.pitch;
 #pragma unroll
-    for (int i = 1; i < 9; ++i) P::st(dst.at(i, node + (uint32_t)EX[i] + (uint32_t)EY[i] * pitch), qf[i]);
-#pragma unroll
-    for (int i = 1; i < 5; ++i)
-      P::st(dst.at(9 + i, node + (uint32_t)EX[i] + (uint32_t)EY[i] * pitch), qg[i]);
+    for (int i = 1; i < 9; ++i) nb[i] = node + (uint32_t)EX[i] + (uint32_t)EY[i] * pitch;
   } else {
-    const Neigh nb(L, x, y);
+    const Neigh n(L, x, y);
 #pragma unroll
-    for (int i = 1; i < 9; ++i) P::st(dst.at(i, nb.idx[i]), qf[i]);
-#pragma unroll
-    for (int i = 1; i < 5; ++i) P::st(dst.at(9 + i, nb.idx[i]), qg[i]);
+    for (int i = 1; i < 9; ++i) nb[i] = n.idx[i];
   }
+#pragma unroll
+  for (int i = 1; i < 9; i += 2) P::st2(dst.at(i, nb[i]), dst.at(i + 1, nb[i + 1]), qf[i], qf[i + 1]);
+#pragma unroll
+  for (int i = 1; i < 5; i += 2)
+    P::st2(dst.at(9 + i, nb[i]), dst.at(10 + i, nb[i + 1]), qg[i], qg[i + 1]);
   if (lc != 0) {
     // x + e_i not fluid: the value arriving along opp(i) stays here
 #pragma unroll
@@ -410,10 +411,12 @@ __global__ void __launch_bounds__((R + 2) * 64)
         for (int j = 1; j < 5; ++j)
           if (src_solid(lc, j)) sg[j] = ing[j];
       }
+      // rounded to the storage type (in pairs)
+      P::rt2(sf[0], sg[0]);
 #pragma unroll
-      for (int j = 0; j < 9; ++j) sf[j] = P::rt(sf[j]);
+      for (int j = 1; j < 9; j += 2) P::rt2(sf[j], sf[j + 1]);
 #pragma unroll
-      for (int j = 0; j < 5; ++j) sg[j] = P::rt(sg[j]);
+      for (int j = 1; j < 5; j += 2) P::rt2(sg[j], sg[j + 1]);
       if (PRESS && seg) {
         const int ps = pressure_source(L, lc, ph1, nbr);
         if (ps >= 0) {
