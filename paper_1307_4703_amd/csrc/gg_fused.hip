@@ -36,16 +36,16 @@ namespace {
 // with the post-collision populations pushed into the neighbours' slots of
 // the destination planes (or, toward a non-fluid neighbour, the value that
 // arrives here along the opposite direction into this node's own slot).
-template <class S, bool SEG, bool PRESS = false>
+template <class S, bool SEG, bool PRESS = false, class FX = Flux>
 __device__ __forceinline__ void second_step(CDesc &L, const Planes<typename Pop<S>::W> &dst,
                                             int x, int y, uint8_t lc, const PhaseNow &ph,
                                             const typename Pop<S>::T *sf,
-                                            const typename Pop<S>::T *sg, Flux &fx,
+                                            const typename Pop<S>::T *sg, FX &fx,
                                             const uint32_t *nbr = nullptr) {
   using P = Pop<S>;
   using T = typename P::T;
   T qf[9], qg[5], jf[9], jg[5];
-  collide_node<T, PRESS>(L, x, y, lc, SEG, ph, sf, sg, qf, qg, jf, jg, fx, true, nbr);
+  collide_node<T, PRESS, FX>(L, x, y, lc, SEG, ph, sf, sg, qf, qg, jf, jg, fx, true, nbr);
   const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
   // (stores in pairs: one conversion for two values where FP16 is stored)
   P::st2(dst.at(0, node), dst.at(9, node), qf[0], qg[0]);
@@ -126,7 +126,7 @@ __device__ __forceinline__ void strip_two_steps(const LatDesc *__restrict__ desc
   for (int i = 0; i < 9; ++i) sf[i] = T(0);
 #pragma unroll
   for (int i = 0; i < 5; ++i) sg[i] = T(0);
-  Flux fx;
+  FluxT<T> fx;
 
   // Software pipeline: the link codes run two rows ahead and the
   // populations one row ahead of the row being computed, so both are in
@@ -177,7 +177,7 @@ __device__ __forceinline__ void strip_two_steps(const LatDesc *__restrict__ desc
     // step t at (x, y)
     T pf[9], pg[5], inf[9], ing[5];
     if (lc != NOT_FLUID) {
-      collide_node<T, false>(L, x, y, lc, SEG, ph1, f, g, pf, pg, inf, ing, fx, own);
+      collide_node<T, false, FluxT<T>>(L, x, y, lc, SEG, ph1, f, g, pf, pg, inf, ing, fx, own);
     } else {
 #pragma unroll
       for (int i = 0; i < 9; ++i) pf[i] = inf[i] = T(0);
@@ -190,13 +190,16 @@ __device__ __forceinline__ void strip_two_steps(const LatDesc *__restrict__ desc
     const T vf5 = from_left(pf[5]), vf6 = from_right(pf[6]);
     const T df7 = from_right(pf[7]), df8 = from_left(pf[8]);
 
+    // (each collision's fluxes leave on their own, as a single step's do;
+    // every lane of the wavefront takes part)
+    if (SEG) fx.flush((double *)L.flux);
     // the previous row pulls f4, f7, f8, g4 from this row: step t + 1 there
     if (own_prev && lcp != NOT_FLUID) {
       if (!src_solid(lcp, 4)) sf[4] = P::rt(pf[4]);
       if (!src_solid(lcp, 7)) sf[7] = P::rt(df7);
       if (!src_solid(lcp, 8)) sf[8] = P::rt(df8);
       if (!src_solid(lcp, 4)) sg[4] = P::rt(pg[4]);
-      second_step<S, SEG>(L, dst, x, yprev, lcp, ph2, sf, sg, fx);
+      second_step<S, SEG, false, FluxT<T>>(L, dst, x, yprev, lcp, ph2, sf, sg, fx);
     }
 
     // state at t + 1 of this row, without the pulls from the row below
@@ -332,8 +335,13 @@ __global__ void __launch_bounds__((R + 2) * 64)
         nbr[k >> 2] |= (uint32_t)((const GG_GLOBAL uint8_t *)L.mask)[nb.idx[k + 1]] << (8 * (k & 3));
     }
 
-    // step t on this row
-    Flux fx;
+    // step t on this row (the boundary fluxes of the tile's two steps summed
+    // per lane in the compute type)
+    // Boundary fluxes: each collision's terms summed per lane in the compute
+    // type (fx) and each rescaling's term in FP64 (fr), as the single steps
+    // and the rescaling kernel sum them
+    FluxT<T> fx;
+    Flux fr;
     if (PRESS && seg && (dir & 2) && lc != NOT_FLUID && lc != 0) {
       // the rescaling after step t - 1 (the flux counted once, by the owner)
       const PhaseNow ph0 = phase_at(L, t - 1);
@@ -345,7 +353,7 @@ __global__ void __launch_bounds__((R + 2) * 64)
         for (int i = 0; i < 9; ++i) f[i] = P::rt(f[i]);
 #pragma unroll
         for (int i = 0; i < 5; ++i) g[i] = P::rt(g[i]);
-        if (own) fx.add(ps, dm, dc);
+        if (own) fr.add(ps, dm, dc);
       }
     }
     if (TAPE && own && lc != NOT_FLUID) {
@@ -362,8 +370,8 @@ __global__ void __launch_bounds__((R + 2) * 64)
     // instead), on the fluid lanes of the segment tiles
     T pf[9], pg[5], inf[9], ing[5];
     if (!SEG || lc != NOT_FLUID) {
-      collide_node<T, PRESS>(L, x, y, lc, seg, ph1, f, g, pf, pg, inf, ing, fx, own,
-                             SEG ? nbr : nullptr);
+      collide_node<T, PRESS, FluxT<T>>(L, x, y, lc, seg, ph1, f, g, pf, pg, inf, ing, fx, own,
+                                       SEG ? nbr : nullptr);
     } else {
 #pragma unroll
       for (int i = 0; i < 9; ++i) pf[i] = inf[i] = T(0);
@@ -380,6 +388,12 @@ __global__ void __launch_bounds__((R + 2) * 64)
     lds_dn[w][1][lane] = from_right(pf[7]);
     lds_dn[w][2][lane] = from_left(pf[8]);
     lds_dn[w][3][lane] = pg[4];
+    // (the first step's fluxes leave before the barrier: the accumulators
+    // are not held across it)
+    if (seg) {
+      fx.flush((double *)L.flux);
+      if (PRESS) fr.flush((double *)L.flux);
+    }
     __syncthreads();
 
     // step t + 1 on the owned rows
@@ -426,7 +440,7 @@ __global__ void __launch_bounds__((R + 2) * 64)
           for (int i = 0; i < 9; ++i) sf[i] = P::rt(sf[i]);
 #pragma unroll
           for (int i = 0; i < 5; ++i) sg[i] = P::rt(sg[i]);
-          fx.add(ps, dm, dc);
+          fr.add(ps, dm, dc);
         }
       }
       if (TAPE) {
@@ -439,11 +453,14 @@ __global__ void __launch_bounds__((R + 2) * 64)
         *tp.at(6, node) = uy;
       }
       if (seg)
-        second_step<S, true, PRESS>(L, dst, x, y, lc, ph2, sf, sg, fx, nbr);
+        second_step<S, true, PRESS, FluxT<T>>(L, dst, x, y, lc, ph2, sf, sg, fx, nbr);
       else
-        second_step<S, false>(L, dst, x, y, lc, ph2, sf, sg, fx);
+        second_step<S, false, false, FluxT<T>>(L, dst, x, y, lc, ph2, sf, sg, fx);
     }
-    if (seg) fx.flush((double *)L.flux);
+    if (seg) {
+      fx.flush((double *)L.flux);
+      if (PRESS) fr.flush((double *)L.flux);
+    }
     __syncthreads();  // the LDS rows are reused by the next tile
   }
 }

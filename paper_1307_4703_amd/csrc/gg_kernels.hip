@@ -55,7 +55,9 @@ __device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
   const uint32_t node = (uint32_t)(L.node0 + y * pitch + x);
   const uint8_t lc = (x < nx && y < ny) ? ((const GG_GLOBAL uint8_t *)L.link)[node] : NOT_FLUID;
 
-  Flux fx;
+  // boundary fluxes: the lane's terms of this step summed in the compute
+  // type (as every form of the step sums them), then in FP64
+  FluxT<T> fx;
 
   if (lc != NOT_FLUID) {
     const Planes<W> pl(L);
@@ -73,7 +75,7 @@ __device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
     }
 
     T pf[9], pg[5], in_f[9], in_g[5];
-    collide_node<T>(L, x, y, lc, seg_tile, ph, f, g, pf, pg, in_f, in_g, fx, true);
+    collide_node<T, true, FluxT<T>>(L, x, y, lc, seg_tile, ph, f, g, pf, pg, in_f, in_g, fx, true);
 
     if (!ODD) {
 #pragma unroll

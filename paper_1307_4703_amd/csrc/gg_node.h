@@ -193,24 +193,27 @@ __device__ __forceinline__ void load_state(const Planes<typename Pop<S>::W> &pl,
 }
 
 // Boundary fluxes of one lane: up to two segments (a node touches at most
-// two), net population change per link, FP64.
-struct Flux {
+// two), net population change per link, summed over the lane's links in A
+// (FP64, or the compute type where the lane's few terms are summed before
+// the FP64 wavefront sum) and flushed into the FP64 accumulators.
+template <class A> struct FluxT {
   int sa = -1, sb = -1;
-  double ma = 0.0, ca = 0.0, mb = 0.0, cb = 0.0;
-  __device__ __forceinline__ void add(int s, double dm, double dc) {
+  A ma = A(0), ca = A(0), mb = A(0), cb = A(0);
+  template <class V> __device__ __forceinline__ void add(int s, V dm, V dc) {
     if (sa < 0 || sa == s) {
-      sa = s; ma += dm; ca += dc;
+      sa = s; ma += (A)dm; ca += (A)dc;
     } else {
-      sb = s; mb += dm; cb += dc;
+      sb = s; mb += (A)dm; cb += (A)dc;
     }
   }
   // every lane of the wavefront must call this
   __device__ __forceinline__ void flush(double *flux) {
-    flush_flux(flux, sa, ma, ca, sb, mb, cb);
+    flush_flux(flux, sa, (double)ma, (double)ca, sb, (double)mb, (double)cb);
     sa = sb = -1;
-    ma = ca = mb = cb = 0.0;
+    ma = ca = mb = cb = A(0);
   }
 };
+using Flux = FluxT<double>;
 
 // Pieces of the two-step passes: 62 owned columns per wavefront (lanes 1..62
 // of the columns x0 - 1 .. x0 + 62), the row count of a tile or strip kept
@@ -320,10 +323,10 @@ __device__ __forceinline__ void fluid_collide(CDesc &L, const T *f, T rho, T drh
 // which keeps the node's pre-collision populations out of the others'
 // register budget and their control flow as it was; without it an open
 // pressure link would take the outlet rule.
-template <class T, bool PRESS = true>
+template <class T, bool PRESS = true, class FX = Flux>
 __device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc, bool seg_tile,
                                              const PhaseNow &ph, const T *f, const T *g, T *pf,
-                                             T *pg, T *in_f, T *in_g, Flux &fx, bool count,
+                                             T *pg, T *in_f, T *in_g, FX &fx, bool count,
                                              const uint32_t *nbr = nullptr) {
   // Every kernel that advances the lattice inlines this function; the fused
   // multiply-adds are written out and no other contraction is allowed, so
@@ -393,8 +396,8 @@ __device__ __forceinline__ void collide_node(CDesc &L, int x, int y, uint8_t lc,
         vf = fmad(T(2) * (T)WF[j] * rho0, fmad(T(4.5) * eu, eu, T(-1.5) * usq), -pf[OPP[j]]);
         if (j < 5) vg = pg[j];
       }
-      const double dm = (double)(vf - pf[OPP[j]]);
-      const double dc = (j < 5) ? (double)(vg - pg[OPP[j]]) : 0.0;
+      const T dm = vf - pf[OPP[j]];
+      const T dc = (j < 5) ? vg - pg[OPP[j]] : T(0);
       in_f[j] = vf;
       if (j < 5) in_g[j] = vg;
       if (count) fx.add(s, dm, dc);
