@@ -520,7 +520,25 @@ def counters_leg(leg, tile, chunk_unused=0):
                                           "bytes_per_update": bytes_per_update("f32") / 2 + 28}
     elif leg == "cde":
         for name, steps, flow, rows in CDE_LEG:
-            cde_bench(name, 16, 4, rows, 0)
+            r = cde_bench(name, 16, 4, rows, 0)
+            ct = CTYPE[r["storage"]]
+            if rows:
+                # the compound-only pass walks the tile list of the one-kernel
+                # coupled pass of the same height
+                lat = Lattice.from_workload(workload(name))
+                lat.set_launch(tile[0], tile[1], 0)
+                lat.set_two_step(4, rows)
+                lat.step(4)
+                p = lat.step_profile(2)
+                lat.close()
+                kern = f"k_cde_tile2<{ct}, {rows},"
+                grid = 8 * ((p["pass_tiles"] + 7) // 8) * (rows + 2) * 64
+            else:
+                kern, grid = f"k_cde<{ct},", None
+            # one trip of the compound's bytes per launch (a pass moves them
+            # once for its two steps)
+            manifest["cde:" + name] = {"kernel": kern, "grid": grid, "units": r["n_fluid"],
+                                       "bytes_per_update": cde_bytes_per_update(r["storage"])}
     else:
         raise SystemExit(f"unknown counter leg {leg}")
     out_dir = os.path.join(ROOT, "gpurun_out", "counters")
