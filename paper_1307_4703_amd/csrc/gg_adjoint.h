@@ -19,4 +19,13 @@ hipError_t launch_adjoint(gg_storage s, const LatDesc *d, const Tile *tiles, int
                           const void *tape, double *dR, const int32_t box[4], double *dcin,
                           double *partial, hipStream_t st);
 
+// Two adjoint steps in one pass (steps t and t - 1): lam_in = dL/dg(t+1)
+// -> lam_out = dL/dg(t-1), with the tapes of both steps, over the tiles of
+// the two-step pass (62 columns x rows, one-node halo; segment flag set
+// where the tile or its halo touches a segment); partials per tile.
+hipError_t launch_adjoint2(gg_storage s, int rows, const LatDesc *d, const Tile *tiles, int n_tiles,
+                           int64_t t, const void *lam_in, void *lam_out, const void *tape_t,
+                           const void *tape_tm1, double *dR, const int32_t box[4], double *dcin,
+                           double *partial, hipStream_t st);
+
 }  // namespace gg

@@ -1407,7 +1407,13 @@ gg_status gg_adjoint(gg_lattice *L, int64_t n, int64_t s, const double *weight,
   const size_t slot = (size_t)7 * L->plane * tsz;
   const size_t lam_bytes = (size_t)5 * L->plane * sizeof(double);
   const size_t nxy = (size_t)L->nx * L->ny;
-  const int na = std::max(L->n_aux_tiles, 1);
+  // Where the lattice steps in two-step passes, the adjoint steps go in
+  // pairs too (the adjoint of the pass) over 62 x 6 tiles of all fluid
+  // nodes, flagged where the tile or its halo touches a segment.
+  std::vector<Tile> adj_tiles, adj_unused;
+  const bool adj_pass = L->fuse >= 3;
+  if (adj_pass) build_strips(L, 6, 0, false, adj_tiles, adj_unused, true);
+  const int na = std::max({L->n_aux_tiles, (int)adj_tiles.size(), 1});
 
   AdjointBuffers B(L);
   void *ckpt, *scr_pop, *scr_desc, *scr_t, *scr_flux, *tape, *lam0, *lam1, *wdev, *tdev, *dRdev,
@@ -1424,6 +1430,13 @@ gg_status gg_adjoint(gg_lattice *L, int64_t n, int64_t s, const double *weight,
       B.alloc(&pw, na * sizeof(double)) != hipSuccess || B.alloc(&pl, na * sizeof(double)) != hipSuccess)
     return fail(GG_ERR_OOM, "adjoint needs about " + std::to_string(need >> 20) +
                                 " MiB of device memory (checkpoints, tape, adjoint fields)");
+  void *d_adj_tiles = nullptr;
+  if (adj_pass && !adj_tiles.empty()) {
+    if (B.alloc(&d_adj_tiles, adj_tiles.size() * sizeof(Tile)) != hipSuccess)
+      return fail(GG_ERR_OOM, "adjoint tile list");
+    GG_HIP(hipMemcpy(d_adj_tiles, adj_tiles.data(), adj_tiles.size() * sizeof(Tile),
+                     hipMemcpyHostToDevice));
+  }
   GG_HIP(hipMemset(lam0, 0, lam_bytes));
   GG_HIP(hipMemset(lam1, 0, lam_bytes));
   GG_HIP(hipMemset(dRdev, 0, std::max<size_t>(1, (size_t)box[2] * box[3]) * sizeof(double)));
@@ -1546,11 +1559,20 @@ gg_status gg_adjoint(gg_lattice *L, int64_t n, int64_t s, const double *weight,
       GG_HIP(hipEventRecord(side.ev[1 - b], rs));
     }
     if (overlap) GG_HIP(hipStreamWaitEvent(L->stream, side.ev[b], 0));
-    for (int64_t j = nk - 1; j >= 0; --j) {
-      GG_HIP(launch_adjoint(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6, tk + j, lam[cur],
-                            lam[1 - cur], (const char *)tapes[b] + (size_t)j * slot,
-                            r_box ? (double *)dRdev : nullptr, box, (double *)dcin, (double *)pw,
-                            L->stream));
+    for (int64_t j = nk - 1; j >= 0;) {
+      const char *tj = (const char *)tapes[b] + (size_t)j * slot;
+      if (d_adj_tiles && j >= 1) {
+        GG_HIP(launch_adjoint2(L->storage, 6, L->d_desc, (const Tile *)d_adj_tiles,
+                               (int)adj_tiles.size(), tk + j, lam[cur], lam[1 - cur], tj, tj - slot,
+                               r_box ? (double *)dRdev : nullptr, box, (double *)dcin,
+                               (double *)pw, L->stream));
+        j -= 2;
+      } else {
+        GG_HIP(launch_adjoint(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6, tk + j,
+                              lam[cur], lam[1 - cur], tj, r_box ? (double *)dRdev : nullptr, box,
+                              (double *)dcin, (double *)pw, L->stream));
+        j -= 1;
+      }
       cur = 1 - cur;
     }
     if (overlap) {
