@@ -513,8 +513,11 @@ def counters_leg(leg, tile, chunk_unused=0):
         lat.adjoint(400, weight, target, r_box=r_box, ckpt_every=20)
         nf = lat.info()["n_fluid"]
         lat.close()
-        manifest["adjoint:k_adjoint"] = {"kernel": "k_adjoint<float>", "grid": None, "units": nf,
-                                         "bytes_per_update": ADJOINT_STEP_BYTES_F32}
+        # (the lattice steps in passes, so the adjoint steps go in pairs: two
+        # adjoint steps per launch)
+        manifest["adjoint:k_adjoint2"] = {"kernel": "k_adjoint2<float, 6>", "grid": None,
+                                          "units": 2 * nf,
+                                          "bytes_per_update": ADJOINT_STEP_BYTES_F32}
         manifest["adjoint:taped_pass"] = {"kernel": "k_tile2<float, true, 6, false, true>",
                                           "grid": None, "units": 2 * nf,
                                           "bytes_per_update": bytes_per_update("f32") / 2 + 28}
