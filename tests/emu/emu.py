@@ -65,6 +65,8 @@ def lib(tag: str) -> ctypes.CDLL:
         L.emu_step.restype = None
         L.emu_to_half.argtypes = [ctypes.c_float]
         L.emu_to_half.restype = ctypes.c_uint16
+        L.emu_fluid_ka.argtypes = [ctypes.c_double, ctypes.c_int]
+        L.emu_fluid_ka.restype = ctypes.c_double
         L.emu_from_half.argtypes = [ctypes.c_uint16]
         L.emu_from_half.restype = ctypes.c_float
         _LIBS[tag] = L

@@ -147,6 +147,8 @@ static double fluid_ka(double omega, int p) {
   return q;
 }
 
+double emu_fluid_ka(double omega, int p) { return fluid_ka(omega, p); }
+
 /* phase in force during step t (fixed at the start of the step) */
 static int phase_of(const emu_lattice *L, int64_t t) {
   if (L->n_phases == 0) return -1;

@@ -47,6 +47,35 @@ def test_half_rounding_matches_numpy():
     assert np.array_equal(got, want)
 
 
+def test_fluid_collision_constants_exact():
+    """The fluid's relaxation constants (om w_axis rounded so that 9 om
+    w_axis, 1 - 9 om w_axis and every weight product are exact in the
+    compute type, the kernels' and the replay's shared rule): for FP32 and
+    FP64 and relaxation rates over (0, 2), each constant is representable,
+    the products with the weights are exact, the rest and the moving
+    weights add up to the rate exactly, and the rate stays within 2^(4-p)
+    relative (2^-(p+1) 9/om absolute below om = 9/32)."""
+    L = emu.lib("f64")
+    rng = np.random.default_rng(7)
+    oms = np.concatenate([rng.uniform(0.02, 1.999, 3000), [1 / 0.8, 1.0, 0.5, 1.9, 9 / 32, 0.05]])
+    for p, ftype in ((24, np.float32), (53, np.float64)):
+        for om in oms:
+            ka = L.emu_fluid_ka(float(om), p)
+            k = ftype(ka)
+            assert float(k) == ka                                  # representable
+            rate = ftype(9) * k
+            assert float(rate) == 9 * ka                           # 9 ka exact
+            omc = ftype(1) - rate
+            assert float(omc) == 1 - 9 * ka                        # 1 - 9 ka exact
+            assert float(ftype(3) * k) == 3 * ka
+            assert float(ftype(4) * k) == 4 * ka
+            assert float(k * ftype(0.25)) == ka / 4
+            # rest + 4 axis + 4 diagonal products sum to the rate exactly
+            assert 4 * ka + 4 * ka + 4 * (ka / 4) == 9 * ka
+            tol = 2.0 ** (4 - p) * om if om >= 9 / 32 else 2.0 ** -(p + 1) * 9
+            assert abs(9 * ka - om) <= tol * (1 + 1e-12)
+
+
 def _deviations(o, rho0, c_shift, w0):
     wg = np.array([w0] + [(1 - w0) / 4] * 4)
     h = np.moveaxis(o.f, 2, 0) - W9[:, None, None] * rho0
