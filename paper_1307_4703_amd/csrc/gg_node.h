@@ -237,9 +237,12 @@ template <class T>
 __device__ __forceinline__ void node_velocity(CDesc &L, const T *f, T &rho, T &drho, T &ux,
                                               T &uy) {
 #pragma clang fp contract(off)
-  drho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+  // the populations moving in +x and in -x, shared by rho and j_x
+  const T a = (f[1] + f[5]) + f[8];
+  const T b = (f[3] + f[6]) + f[7];
+  drho = ((f[0] + f[2]) + f[4]) + (a + b);
   rho = DK<T>::rho0(L) + drho;
-  const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+  const T jx = a - b;
   const T jy = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
   const T inv_rho = T(1) / rho;
   ux = jx * inv_rho;

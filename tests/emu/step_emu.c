@@ -212,10 +212,12 @@ void emu_step(const emu_lattice *L, int64_t t, const T *h, const T *k, T *h_out,
       for (int i = 0; i < 9; ++i) f[i] = h[i * n + id];
       for (int i = 0; i < 5; ++i) g[i] = k[i * n + id];
       /* moments, Eq. 7, on the deviations */
-      T dr = f[0];
-      for (int i = 1; i < 9; ++i) dr = dr + f[i];
+      /* the populations moving in +x (a) and in -x (b), shared with j_x */
+      const T a = (f[1] + f[5]) + f[8];
+      const T b = (f[3] + f[6]) + f[7];
+      const T dr = ((f[0] + f[2]) + f[4]) + (a + b);
       const T rho = rho0 + dr;
-      const T jx = ((f[1] - f[3]) + (f[5] - f[6])) + (f[8] - f[7]);
+      const T jx = a - b;
       const T jy = ((f[2] - f[4]) + (f[5] - f[7])) + (f[6] - f[8]);
       const T ir = (T)1 / rho;
       const T ux = jx * ir, uy = jy * ir;
