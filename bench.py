@@ -74,9 +74,9 @@ def workload(name):
 # launch form per workload ((fuse, rows) of gg_set_two_step), as the
 # autotuner picks it on this GPU; --tune re-runs the autotuner
 FORMS = {"gg2048_f32": (4, 6), "gg2048_f16": (4, 6), "gg8192_f16": (3, 6),
-         "gg8192_f16_pe2000": (3, 6), "gg8192_f32": (3, 6), "allfluid8192_f32": (3, 14),
+         "gg8192_f16_pe2000": (3, 6), "gg8192_f32": (4, 14), "allfluid8192_f32": (4, 14),
          "allfluid8192_f16": (3, 6), "shard8192x512_f32": (3, 6),
-         "allfluid8192_f64": (3, 14), "gg2048_f64": (3, 14), "straight_f64": (4, 6)}
+         "allfluid8192_f64": (3, 14), "gg2048_f64": (4, 14), "straight_f64": (4, 6)}
 
 
 def kernel_hash():
