@@ -110,6 +110,20 @@ def align_steps(t):
     return (-t) % 4
 
 
+def monitor_interval(steps, every):
+    """Timed steps between FP64 monitor reductions: at most `every`, and a
+    divisor of `steps` (between every / 2 and every) where there is one,
+    so that the last reduction falls on the last timed step."""
+    if steps <= 0:
+        return 0
+    if steps <= every:
+        return steps
+    for m in range(every, max(1, every // 2) - 1, -1):
+        if steps % m == 0:
+            return m
+    return every
+
+
 def time_lattice(name, steps, warmup, tile, chunk, form=None, monitor_every=1024,
                  graph_steps=None):
     """One workload: `warmup` untimed steps (plus at most 3 that align the
@@ -151,7 +165,7 @@ def time_lattice(name, steps, warmup, tile, chunk, form=None, monitor_every=1024
         if chunk_t > 0:  # the graph is captured (and replayed once) here
             lat.step(chunk_t)
             extra_warm += chunk_t
-        mon = max(1, min(monitor_every, steps)) if steps > 0 else 0
+        mon = monitor_interval(steps, monitor_every)
         lat.set_monitor(mon)
         lat.sync()
         torch.cuda.synchronize()

@@ -108,6 +108,18 @@ def test_bench_alignment_steps():
         assert 0 <= a < 4 and (t + a) % 4 == 0
 
 
+def test_monitor_interval_ends_on_the_last_step():
+    assert bench.monitor_interval(0, 1024) == 0
+    assert bench.monitor_interval(20, 1024) == 20
+    assert bench.monitor_interval(4000, 1024) == 1000
+    assert bench.monitor_interval(4096, 1024) == 1024
+    for steps in (1025, 3000, 5000, 12345, 20000):
+        m = bench.monitor_interval(steps, 1024)
+        assert 1 <= m <= 1024
+        if any(steps % d == 0 for d in range(512, 1025)):
+            assert steps % m == 0 and m >= 512
+
+
 def _fake_run(nf, steps, event_ms, prof):
     return {"nf": nf, "steps": steps, "event_ms": event_ms, "prof": prof}
 
