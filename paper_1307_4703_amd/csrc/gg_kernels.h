@@ -85,6 +85,11 @@ hipError_t launch_read(gg_storage s, const LatDesc *d, const Tile *tiles, int n_
 hipError_t launch_reduce(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                          int tx_shift, double *partial, double *acc, hipStream_t st,
                          int max_groups = 0);
+// The work-groups of every diagnostics reduction (gg_diagnostics, the
+// monitor and the allocation-free form alike, so that all three sum in the
+// same order): enough to keep the GPU's memory busy, few enough that the
+// final fold of the partial records takes one short work-group.
+constexpr int REDUCE_GROUPS = 2048;
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
 // Pressure boundary: after step (device counter + dt), rescale the state at
 // t + 1 of the n nodes listed as (x, y, candidates) triples that take a

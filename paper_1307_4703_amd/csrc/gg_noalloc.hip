@@ -14,7 +14,7 @@ namespace {
 // Work-groups of the capped reduction: each folds every NOALLOC_GROUPS-th
 // tile of the lattice, so the array holds the same number of partial
 // records whatever the lattice size.
-constexpr int NOALLOC_GROUPS = 2048;
+constexpr int NOALLOC_GROUPS = REDUCE_GROUPS;  // the same order of sums as gg_diagnostics
 constexpr int SCRATCH_DOUBLES = 6 * NOALLOC_GROUPS + 8;  // partials, then totals
 
 // Per device: each GPU holds its own copy at its own address until the

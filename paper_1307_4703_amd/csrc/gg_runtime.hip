@@ -1058,7 +1058,7 @@ static gg_status step_run(gg_lattice *L, int64_t n) {
 static gg_status monitor_launch(gg_lattice *L) {
   GG_HIP(launch_fill(L->d_mon, 8, 0.0, L->stream));
   GG_HIP(launch_reduce(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6, L->d_partial,
-                       L->d_mon, L->stream));
+                       L->d_mon, L->stream, REDUCE_GROUPS));
   GG_HIP(hipMemcpyAsync(L->d_mon + 8, L->d_flux, 2 * GG_MAX_SEGMENTS * sizeof(double),
                         hipMemcpyDeviceToDevice, L->stream));
   L->mon_last_t = L->t;
@@ -1235,7 +1235,7 @@ gg_status gg_diagnostics(gg_lattice *L, gg_diag *out) {
   }
   GG_HIP(hipMemsetAsync(L->d_acc, 0, 8 * sizeof(double), L->stream));
   GG_HIP(launch_reduce(L->storage, L->d_desc, L->d_aux_tiles, L->n_aux_tiles, 6, L->d_partial,
-                       L->d_acc, L->stream));
+                       L->d_acc, L->stream, REDUCE_GROUPS));
   double acc[8], flux[2 * GG_MAX_SEGMENTS];
   int64_t t = 0;
   GG_HIP(hipStreamSynchronize(L->stream));
