@@ -379,7 +379,7 @@ gg_status gg_info(const gg_lattice *lat, int64_t *n_fluid, int64_t *n_tiles,
  * then ignored): each candidate (single steps over tiles of 64 x 4, 32 x 8
  * or 128 x 2 nodes; when every member has its second plane set and all sit
  * at steps of one parity, two-step passes with 6- or 14-row tiles and the
- * boundary tiles apart, or 6-row tiles in one kernel) advances the members
+ * boundary tiles apart, or 6- or 14-row tiles in one kernel) advances the members
  * 20 steps, 16 of them timed with HIP events on their stream, and the
  * fastest is kept (gg_batch_form reports it). The members' states, step
  * counts and boundary fluxes are copied aside on the device (hipMalloc of

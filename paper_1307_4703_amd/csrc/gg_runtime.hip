@@ -1824,6 +1824,7 @@ static gg_status batch_autotune(gg_lattice *const *lats, int32_t n, int32_t grap
     cands.push_back({64, 4, 3, 6});
     cands.push_back({64, 4, 3, 14});
     cands.push_back({64, 4, 4, 6});
+    cands.push_back({64, 4, 4, 14});
   }
   hipEvent_t a = nullptr, b = nullptr;
   GG_HIP(hipEventCreate(&a));
