@@ -157,6 +157,7 @@ def time_lattice(name, steps, warmup, tile, chunk, form=None, monitor_every=1024
                 form = {"fuse": fuse, "rows": rows}
             form = {"tile": list(tile), **form}
         lat.set_two_step(form["fuse"], form["rows"])
+        form["layout"] = lat.layout
         log(f"{wl.name}: {wl.nx}x{wl.ny}, {nf} fluid nodes, storage {wl.storage}, "
             f"form {form}; warmup {warmup}")
         lat.step(warmup)
@@ -393,6 +394,8 @@ def cde_bench(name, steps, flow_steps, rows, chunk=64):
     nf = lat.info()["n_fluid"]
     lat.step(flow_steps)
     lat.set_velocity_field(0)
+    lat.set_layout("planes")  # (the compound alone reads g only)
+    lat_layout = lat.layout
     lat.set_cde_launch(rows)
     lat.cde_step(4 * max(chunk, 4))
     lat.sync()
@@ -413,7 +416,7 @@ def cde_bench(name, steps, flow_steps, rows, chunk=64):
     launch_ms = ms * spl
     ach = nf * bpu / (launch_ms * 1e-3) / 1e9
     return {"workload": wl.name, "storage": wl.storage, "n_fluid": nf, "steps": steps,
-            "launch_form": {"rows": rows, "steps_per_launch": spl},
+            "launch_form": {"rows": rows, "steps_per_launch": spl, "layout": lat_layout},
             "mlups": round(nf / (ms * 1e-3) / 1e6, 1),
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
                          "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),

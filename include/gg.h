@@ -261,8 +261,9 @@ gg_status gg_diagnostics(gg_lattice *lat, gg_diag *out);
  * (four hours of chip time) are what it serves. With buf NULL, *nbytes
  * receives the size needed. Both wait for the stream. gg_load accepts only a
  * snapshot of a lattice with the same mask dimensions and storage
- * (GG_ERR_ARG otherwise); resuming gives bit for bit the run that was not
- * interrupted. */
+ * (GG_ERR_ARG otherwise), converting one of the other population layout
+ * (gg_set_layout) into the lattice's; resuming gives bit for bit the run
+ * that was not interrupted. */
 gg_status gg_save(gg_lattice *lat, void *buf, size_t *nbytes);
 gg_status gg_load(gg_lattice *lat, const void *buf, size_t nbytes);
 
@@ -297,6 +298,24 @@ gg_status gg_set_launch(gg_lattice *lat, int32_t tile_x, int32_t tile_y,
  * segments between them (a walking strip sums their fluxes in one record
  * of two segments); GG_ERR_OOM if the planes do not fit. */
 gg_status gg_set_two_step(gg_lattice *lat, int32_t fuse, int32_t strip_h);
+
+/* Layout of the population planes in device memory (the state's values do
+ * not depend on it; every step computes the same bits in either):
+ *   GG_LAYOUT_PAIRED (a new lattice's layout): f_i and g_i of a node side
+ *     by side for i = 0..4, the fluid and compound populations that stream
+ *     along the same velocity e_i (Eq. 3), so the coupled pass moves each
+ *     such pair with one memory access; f5..f8 in planes of their own;
+ *   GG_LAYOUT_PLANES: one plane per population, node-contiguous, which the
+ *     compound-only steps (gg_cde_step) read at the full width of their
+ *     accesses (in the paired layout they fetch the f halves too).
+ * Switching converts the stored state (through the second plane set, or a
+ * buffer of its size while fuse = 1) and waits for the lattice's stream.
+ * Snapshots record their layout; gg_load converts a snapshot of the other
+ * layout. Errors: GG_ERR_ARG for other values, GG_ERR_OOM. */
+#define GG_LAYOUT_PLANES 0
+#define GG_LAYOUT_PAIRED 1
+gg_status gg_set_layout(gg_lattice *lat, int32_t layout);
+gg_status gg_get_layout(const gg_lattice *lat, int32_t *layout);
 
 /* Compound alone on frozen velocity fields. The paper lets the flow of a
  * valve configuration settle (it does so far faster than the compound) and

@@ -24,6 +24,7 @@ GG_HOST, GG_DEVICE = 0, 1
 GG_SEG_INLET, GG_SEG_OUTLET, GG_SEG_PRESSURE = 1, 2, 3
 GG_FIRST_SEGMENT = 2
 GG_WALL_BOUNCE_BACK, GG_WALL_PAPER = 0, 1
+GG_LAYOUT_PLANES, GG_LAYOUT_PAIRED = 0, 1
 WALL_SCHEMES = {"bounce_back": GG_WALL_BOUNCE_BACK, "equilibrium": GG_WALL_PAPER}
 GG_MAX_SEGMENTS = 16
 GG_MAX_PHASES = 64
@@ -115,6 +116,8 @@ SIGS = {
     "gg_sync": [P],
     "gg_step_timed": [P, I64, ctypes.POINTER(D), ctypes.POINTER(D)],
     "gg_set_two_step": [P, I32, I32],
+    "gg_set_layout": [P, I32],
+    "gg_get_layout": [P, ctypes.POINTER(I32)],
     "gg_step2_timed": [P, I64, ctypes.POINTER(D)],
     "gg_set_velocity_field": [P, I32, P, P, D, ctypes.c_int],
     "gg_set_phase_fields": [P, P, I32],

@@ -18,8 +18,6 @@
 
 namespace gg {
 
-using CDesc = const GG_CONST LatDesc;
-
 namespace {
 
 struct Ph {
@@ -77,28 +75,21 @@ __device__ __forceinline__ void gather_state(CDesc &L, uint32_t node, uint8_t lc
   const int xp = (x == L.nx - 1 && L.periodic_x) ? 0 : x + 1;
   const int ym = (y == 0 && L.periodic_y) ? L.ny - 1 : y - 1;
   const int yp = (y == L.ny - 1 && L.periodic_y) ? 0 : y + 1;
-  for (int i = 0; i < 9; ++i) {
-    uint32_t src = node;
-    int pl = i;
-    if (odd && i > 0 && !((lc >> (OPP[i] - 1)) & 1)) {
-      const int xx = EX[OPP[i]] > 0 ? xp : (EX[OPP[i]] < 0 ? xm : x);
-      const int yy = EY[OPP[i]] > 0 ? yp : (EY[OPP[i]] < 0 ? ym : y);
-      src = (uint32_t)(L.node0 + yy * L.pitch + xx);
-      pl = OPP[i];
+  const Planes<W> pl(L);
+  // population j of this node: its own slot j, or at an odd step the slot
+  // opp(j) of the upstream neighbour x - e_j where that one is fluid
+  auto slot = [&](int j, int k) -> const GG_GLOBAL W * {
+    if (odd && j > 0 && !((lc >> (OPP[j] - 1)) & 1)) {
+      const int xx = EX[OPP[j]] > 0 ? xp : (EX[OPP[j]] < 0 ? xm : x);
+      const int yy = EY[OPP[j]] > 0 ? yp : (EY[OPP[j]] < 0 ? ym : y);
+      return pl.at(k + OPP[j], (uint32_t)(L.node0 + yy * L.pitch + xx));
     }
-    f[i] = P::ld(at<W>(L.pop, L.plane, pl, src));
-  }
-  for (int i = 0; i < 5; ++i) {
-    uint32_t src = node;
-    int pl = i;
-    if (odd && i > 0 && !((lc >> (OPP[i] - 1)) & 1)) {
-      const int xx = EX[OPP[i]] > 0 ? xp : (EX[OPP[i]] < 0 ? xm : x);
-      const int yy = EY[OPP[i]] > 0 ? yp : (EY[OPP[i]] < 0 ? ym : y);
-      src = (uint32_t)(L.node0 + yy * L.pitch + xx);
-      pl = OPP[i];
-    }
-    g[i] = P::ld(at<W>(L.pop, L.plane, 9 + pl, src));
-  }
+    return pl.at(k + j, node);
+  };
+#pragma unroll
+  for (int i = 0; i < 9; ++i) f[i] = P::ld(slot(i, 0));
+#pragma unroll
+  for (int i = 0; i < 5; ++i) g[i] = P::ld(slot(i, 9));
 }
 
 // Seed: lam(x,i) = weight(x) (C(x) - target(x)) at the final state; the loss

@@ -30,7 +30,7 @@ __device__ __forceinline__ const GG_GLOBAL T *field_plane(CDesc &L, int slot, in
 // each XCD does a contiguous run of tiles (work-groups are dealt to the 8
 // XCDs round-robin), and neighbouring tiles, which store into each other's
 // edge lines on odd steps, share an L2.
-template <class S, bool ODD>
+template <class S, bool ODD, bool PAIRS>
 __global__ void __launch_bounds__(256)
     k_cde(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles, int n_tiles,
           int per_xcd, int tx_shift, int dt) {
@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(256)
   const uint8_t lc = (x < L.nx && y < L.ny) ? ((const GG_GLOBAL uint8_t *)L.link)[node] : NOT_FLUID;
   Flux fx;
   if (lc != NOT_FLUID) {
-    const Planes<W> pl(L);
+    const Planes<W> pl(L.pop, L.plane, PAIRS);  // (the lattice's layout)
     const Neigh nb(L, x, y);
     T g[5];
     if (!ODD) {
@@ -107,7 +107,7 @@ __global__ void __launch_bounds__(256)
 // the tile, halo included (the caller then marks as segment tiles all tiles
 // whose rows or halo hold a node next to a segment), else that kernel
 // follows the pass.
-template <class S, int R, bool PRESS = false>
+template <class S, int R, bool PRESS, bool PAIRS>
 __global__ void __launch_bounds__((R + 2) * 64)
     k_cde_tile2(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles, int n_tiles,
                 int per_xcd, int dir, int dt) {
@@ -131,8 +131,8 @@ __global__ void __launch_bounds__((R + 2) * 64)
   const int s1 = L.phase_field[ph1.index];
   const int s2 = L.phase_field[ph2.index];
   const int dsel = PRESS ? (dir & 1) : dir;
-  const Planes<W> src(dsel ? L.pop_b : L.pop, L.plane);
-  const Planes<W> dst(dsel ? L.pop : L.pop_b, L.plane);
+  const Planes<W> src(dsel ? L.pop_b : L.pop, L.plane, PAIRS);  // (the lattice's layout)
+  const Planes<W> dst(dsel ? L.pop : L.pop_b, L.plane, PAIRS);
 
   const int xr = tl.x0 - 1 + lane;
   int x = xr;
@@ -292,30 +292,36 @@ __global__ void __launch_bounds__(256)
 
 }  // namespace
 
-hipError_t launch_cde(gg_storage s, bool odd, const LatDesc *d, const Tile *tiles, int n_tiles,
-                      int tx_shift, int dt, hipStream_t st) {
+hipError_t launch_cde(gg_storage s, bool pairs, bool odd, const LatDesc *d, const Tile *tiles,
+                      int n_tiles, int tx_shift, int dt, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   const int per_xcd = (n_tiles + 7) / 8;
   const int grid = 8 * per_xcd;
-#define GG_CDE(TYPE)                                                                       \
-  (odd ? k_cde<TYPE, true><<<grid, 256, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt) \
-       : k_cde<TYPE, false><<<grid, 256, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt))
+#define GG_CDE_P(TYPE, PV)                                                                    \
+  (odd ? k_cde<TYPE, true, PV><<<grid, 256, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt) \
+       : k_cde<TYPE, false, PV><<<grid, 256, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt))
+#define GG_CDE(TYPE) (pairs ? GG_CDE_P(TYPE, true) : GG_CDE_P(TYPE, false))
   switch (s) {
     case GG_F64: GG_CDE(double); break;
     case GG_F32: GG_CDE(float); break;
     case GG_F16_SHIFTED: GG_CDE(__half); break;
   }
 #undef GG_CDE
+#undef GG_CDE_P
   return hipGetLastError();
 }
 
-hipError_t launch_cde_tile2(gg_storage s, int rows, const LatDesc *d, const Tile *tiles,
-                            int n_tiles, int dir, int dt, hipStream_t st, bool press) {
+hipError_t launch_cde_tile2(gg_storage s, bool pairs, int rows, const LatDesc *d,
+                            const Tile *tiles, int n_tiles, int dir, int dt, hipStream_t st,
+                            bool press) {
   if (n_tiles <= 0) return hipSuccess;
   const int per_xcd = (n_tiles + 7) / 8;
   const int grid = 8 * per_xcd;
-#define GG_CDE2(TYPE, RV, PV) \
-  k_cde_tile2<TYPE, RV, PV><<<grid, ((RV) + 2) * 64, 0, st>>>(d, tiles, n_tiles, per_xcd, dir, dt)
+#define GG_CDE2(TYPE, RV, PV)                                                                \
+  (pairs ? k_cde_tile2<TYPE, RV, PV, true><<<grid, ((RV) + 2) * 64, 0, st>>>(d, tiles, n_tiles, \
+                                                                           per_xcd, dir, dt)   \
+         : k_cde_tile2<TYPE, RV, PV, false><<<grid, ((RV) + 2) * 64, 0, st>>>(d, tiles, n_tiles, \
+                                                                            per_xcd, dir, dt))
 #define GG_CDE2_R(TYPE)                                  \
   do {                                                   \
     if (press && rows <= 6) GG_CDE2(TYPE, 6, true);      \

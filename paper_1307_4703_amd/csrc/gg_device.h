@@ -108,11 +108,12 @@ constexpr int NPOP = 14;  // 9 f planes then 5 g planes
 // padded (pitch > nx, a multiple of 64 elements) and one padding row lies
 // before and after the lattice, so the cells x = -1, x = nx, y = -1 and
 // y = ny are addressable: stores toward a non-fluid neighbour outside the
-// lattice land there and are never read.
+// lattice land there and are never read. The population planes are laid
+// out plane-major or paired (see Planes).
 struct LatDesc {
   int32_t nx, ny, pitch, periodic_x;
   int32_t periodic_y, n_phases, has_source, has_region;
-  int32_t node0, pad0;
+  int32_t node0, pairs;     // pairs: the paired population layout
   int64_t plane;            // elements between population planes
   void *pop;                // 14 planes of the storage type
   void *pop_b;              // second plane set of the two-step pass (or null)
@@ -201,6 +202,19 @@ template <> struct Pop<double> {
   // the value a store followed by a load gives back (of one, of two values)
   static __device__ __forceinline__ T rt(T v) { return v; }
   static __device__ __forceinline__ void rt2(T &, T &) {}
+  // two adjacent elements (f_i, g_i of the paired layout) in one access
+  using W2 = double __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ void ld_pair(const GG_GLOBAL W *p, T &a, T &b) {
+    const W2 v = *(const GG_GLOBAL W2 *)p;
+    a = v[0];
+    b = v[1];
+  }
+  static __device__ __forceinline__ void st_pair(GG_GLOBAL W *p, T a, T b) {
+    W2 v;
+    v[0] = a;
+    v[1] = b;
+    *(GG_GLOBAL W2 *)p = v;
+  }
 };
 template <> struct Pop<float> {
   using T = float;
@@ -213,6 +227,18 @@ template <> struct Pop<float> {
   }
   static __device__ __forceinline__ T rt(T v) { return v; }
   static __device__ __forceinline__ void rt2(T &, T &) {}
+  using W2 = float __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ void ld_pair(const GG_GLOBAL W *p, T &a, T &b) {
+    const W2 v = *(const GG_GLOBAL W2 *)p;
+    a = v[0];
+    b = v[1];
+  }
+  static __device__ __forceinline__ void st_pair(GG_GLOBAL W *p, T a, T b) {
+    W2 v;
+    v[0] = a;
+    v[1] = b;
+    *(GG_GLOBAL W2 *)p = v;
+  }
 };
 template <> struct Pop<__half> {
   using T = float;
@@ -254,6 +280,61 @@ template <> struct Pop<__half> {
     const H2 h = to_half2(a, b);
     a = (T)h[0];
     b = (T)h[1];
+  }
+  // two adjacent elements in one 32-bit access; the store rounds both with
+  // one packed conversion, as st2
+  static __device__ __forceinline__ void ld_pair(const GG_GLOBAL W *p, T &a, T &b) {
+    const uint32_t v = gload((const GG_GLOBAL uint32_t *)p);
+    a = __half2float(__ushort_as_half((unsigned short)(v & 0xffffu)));
+    b = __half2float(__ushort_as_half((unsigned short)(v >> 16)));
+  }
+  static __device__ __forceinline__ void st_pair(GG_GLOBAL W *p, T a, T b) {
+    gstore((GG_GLOBAL H2 *)p, to_half2(a, b));
+  }
+};
+
+using CDesc = const GG_CONST LatDesc;
+
+// The population planes of one plane set: uniform base pointers, elements
+// reached through a 32-bit byte offset (a plane pair is smaller than
+// 4 GiB), which maps onto the scalar-base + vector-offset form of global
+// memory access. Two layouts:
+//   plane-major: population i of node n at element i * plane + n;
+//   paired: f_i and g_i (i = 0..4, the two populations that move along
+//     the same velocity) side by side, at elements 2i * plane + 2n and
+//     2i * plane + 2n + 1, and f5..f8 plane-major in planes 10..13,
+//     so that a pass reads and writes (f_i, g_i) of a node with one access.
+__host__ __device__ constexpr bool paired_slot(int i) { return i < 5 || i >= 9; }
+template <class W> struct Planes {
+  GG_GLOBAL W *p[NPOP];
+  bool pairs;
+  __device__ __forceinline__ Planes(CDesc &L) : Planes(L.pop, L.plane, L.pairs != 0) {}
+  __device__ __forceinline__ Planes(void *pop, int64_t plane, bool paired) : pairs(paired) {
+    GG_GLOBAL W *base = (GG_GLOBAL W *)pop;
+    // (every pointer a select between two constants' products, so that the
+    // array stays in scalar registers when the layout is a run-time value)
+#pragma unroll
+    for (int i = 0; i < NPOP; ++i) {
+      const int k = i < 5 ? 2 * i : (i >= 9 ? 2 * (i - 9) : i + 5);
+      p[i] = base + (int64_t)(paired ? k : i) * plane + (paired && i >= 9 ? 1 : 0);
+    }
+  }
+  __device__ __forceinline__ GG_GLOBAL W *at(int i, uint32_t idx) const {
+    const uint32_t stride = (pairs && paired_slot(i) ? 2u : 1u) * (uint32_t)sizeof(W);
+    return (GG_GLOBAL W *)((GG_GLOBAL char *)p[i] + idx * stride);
+  }
+};
+
+// Plane-major arrays of other per-node records (the adjoint's tapes).
+template <class W> struct TapePlanes {
+  GG_GLOBAL W *p[NPOP];
+  __device__ __forceinline__ TapePlanes(void *base_, int64_t plane) {
+    GG_GLOBAL W *base = (GG_GLOBAL W *)base_;
+#pragma unroll
+    for (int i = 0; i < NPOP; ++i) p[i] = base + (int64_t)i * plane;
+  }
+  __device__ __forceinline__ GG_GLOBAL W *at(int i, uint32_t idx) const {
+    return (GG_GLOBAL W *)((GG_GLOBAL char *)p[i] + idx * (uint32_t)sizeof(W));
   }
 };
 

@@ -47,8 +47,6 @@ __device__ __forceinline__ void second_step(CDesc &L, const Planes<typename Pop<
   T qf[9], qg[5], jf[9], jg[5];
   collide_node<T, PRESS, FX>(L, x, y, lc, SEG, ph, sf, sg, qf, qg, jf, jg, fx, true, nbr);
   const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
-  // (stores in pairs: one conversion for two values where FP16 is stored)
-  P::st2(dst.at(0, node), dst.at(9, node), qf[0], qg[0]);
   uint32_t nb[9];
   if (!L.periodic_x && !L.periodic_y) {
     // (uniform) the neighbours are node + e_x + e_y pitch, padding included
@@ -60,11 +58,23 @@ __device__ __forceinline__ void second_step(CDesc &L, const Planes<typename Pop<
 #pragma unroll
     for (int i = 1; i < 9; ++i) nb[i] = n.idx[i];
   }
+  // (stores in pairs: one conversion for two values where FP16 is stored)
+  if (dst.pairs) {  // (uniform) f_i and g_i to x + e_i in one access
+    P::st_pair(dst.at(0, node), qf[0], qg[0]);
 #pragma unroll
-  for (int i = 1; i < 9; i += 2) P::st2(dst.at(i, nb[i]), dst.at(i + 1, nb[i + 1]), qf[i], qf[i + 1]);
+    for (int i = 1; i < 5; ++i) P::st_pair(dst.at(i, nb[i]), qf[i], qg[i]);
 #pragma unroll
-  for (int i = 1; i < 5; i += 2)
-    P::st2(dst.at(9 + i, nb[i]), dst.at(10 + i, nb[i + 1]), qg[i], qg[i + 1]);
+    for (int i = 5; i < 9; i += 2)
+      P::st2(dst.at(i, nb[i]), dst.at(i + 1, nb[i + 1]), qf[i], qf[i + 1]);
+  } else {
+    P::st2(dst.at(0, node), dst.at(9, node), qf[0], qg[0]);
+#pragma unroll
+    for (int i = 1; i < 9; i += 2)
+      P::st2(dst.at(i, nb[i]), dst.at(i + 1, nb[i + 1]), qf[i], qf[i + 1]);
+#pragma unroll
+    for (int i = 1; i < 5; i += 2)
+      P::st2(dst.at(9 + i, nb[i]), dst.at(10 + i, nb[i + 1]), qg[i], qg[i + 1]);
+  }
   if (lc != 0) {
     // x + e_i not fluid: the value arriving along opp(i) stays here
 #pragma unroll
@@ -76,7 +86,7 @@ __device__ __forceinline__ void second_step(CDesc &L, const Planes<typename Pop<
   }
 }
 
-template <class S, bool SEG>
+template <class S, bool SEG, bool PAIRS>
 __device__ __forceinline__ void strip_two_steps(const LatDesc *__restrict__ descs,
                                                 const Tile *__restrict__ strips, int s, int dir,
                                                 int dt) {
@@ -94,8 +104,8 @@ __device__ __forceinline__ void strip_two_steps(const LatDesc *__restrict__ desc
     ph1 = phase_at(L, t);
     ph2 = phase_at(L, t + 1);
   }
-  const Planes<W> src(dir ? L.pop_b : L.pop, L.plane);
-  const Planes<W> dst(dir ? L.pop : L.pop_b, L.plane);
+  const Planes<W> src(dir ? L.pop_b : L.pop, L.plane, PAIRS);  // (the lattice's layout)
+  const Planes<W> dst(dir ? L.pop : L.pop_b, L.plane, PAIRS);
   const GG_GLOBAL uint8_t *link = (const GG_GLOBAL uint8_t *)L.link;
 
   // this lane's column: addressable for -1 <= x <= nx (wrapped if periodic)
@@ -237,7 +247,7 @@ __device__ __forceinline__ void strip_two_steps(const LatDesc *__restrict__ desc
 // neighbouring strips, which share cache lines at their edges, share an L2).
 // SEG: strips with links to boundary segments (their own kernel, so that
 // the boundary rules do not set the register budget of the others).
-template <class S, bool SEG>
+template <class S, bool SEG, bool PAIRS>
 __global__ void __launch_bounds__(256)
     k_step2(const LatDesc *__restrict__ descs, const Tile *__restrict__ strips, int n_strips,
             int per_xcd, int dir, int dt) {
@@ -247,7 +257,7 @@ __global__ void __launch_bounds__(256)
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   for (int b = blockIdx.x; b < nb; b += gridDim.x) {
     const int s = ((b & 7) * per_xcd + (b >> 3)) * 4 + w;
-    if (s < n_strips) strip_two_steps<S, SEG>(descs, strips, s, dir, dt);
+    if (s < n_strips) strip_two_steps<S, SEG, PAIRS>(descs, strips, s, dir, dt);
   }
 }
 
@@ -270,7 +280,7 @@ __global__ void __launch_bounds__(256)
 // before each of the two steps, dg_0..4 then u_x, u_y (from the same
 // moments as the collision), to the planes of the compute type at tape0
 // (step t) and tape1 (step t + 1), as the single step's tape does.
-template <class S, bool SEG, int R, bool PRESS = false, bool TAPE = false>
+template <class S, bool SEG, int R, bool PRESS, bool TAPE, bool PAIRS>
 __global__ void __launch_bounds__((R + 2) * 64)
     k_tile2(const LatDesc *__restrict__ descs, const Tile *__restrict__ tiles, int n_tiles,
             int per_xcd, int dir, int dt, void *__restrict__ tape0, void *__restrict__ tape1) {
@@ -298,8 +308,9 @@ __global__ void __launch_bounds__((R + 2) * 64)
       ph2 = phase_at(L, t + 1);
     }
     const int dsel = PRESS ? (dir & 1) : dir;
-    const Planes<W> src(dsel ? L.pop_b : L.pop, L.plane);
-    const Planes<W> dst(dsel ? L.pop : L.pop_b, L.plane);
+    // (the layout is the lattice's, PAIRS: known at compile time)
+    const Planes<W> src(dsel ? L.pop_b : L.pop, L.plane, PAIRS);
+    const Planes<W> dst(dsel ? L.pop : L.pop_b, L.plane, PAIRS);
 
     const int xr = tl.x0 - 1 + lane;
     const bool col = xr >= -1 && xr <= nx;
@@ -321,10 +332,17 @@ __global__ void __launch_bounds__((R + 2) * 64)
     const uint32_t lnode = live ? node : (uint32_t)L.node0;
     const uint8_t lc = live ? ((const GG_GLOBAL uint8_t *)L.link)[lnode] : NOT_FLUID;
     T f[9], g[5];
+    if (src.pairs) {  // (uniform) f_i and g_i in one access
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = P::ld(src.at(i, lnode));
+      for (int i = 0; i < 5; ++i) P::ld_pair(src.at(i, lnode), f[i], g[i]);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) g[i] = P::ld(src.at(9 + i, lnode));
+      for (int i = 5; i < 9; ++i) f[i] = P::ld(src.at(i, lnode));
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = P::ld(src.at(i, lnode));
+#pragma unroll
+      for (int i = 0; i < 5; ++i) g[i] = P::ld(src.at(9 + i, lnode));
+    }
     uint32_t nbr[2] = {0u, 0u};
     // (only for cells inside the lattice, whose neighbours all lie in the
     // padded planes; the halo cells outside are not fluid)
@@ -359,7 +377,7 @@ __global__ void __launch_bounds__((R + 2) * 64)
     if (TAPE && own && lc != NOT_FLUID) {
       T rho, drho, ux, uy;
       node_velocity<T>(L, f, rho, drho, ux, uy);
-      const Planes<T> tp(tape0, L.plane);
+      const TapePlanes<T> tp(tape0, L.plane);
 #pragma unroll
       for (int i = 0; i < 5; ++i) *tp.at(i, node) = g[i];
       *tp.at(5, node) = ux;
@@ -446,7 +464,7 @@ __global__ void __launch_bounds__((R + 2) * 64)
       if (TAPE) {
         T rho, drho, ux, uy;
         node_velocity<T>(L, sf, rho, drho, ux, uy);
-        const Planes<T> tp(tape1, L.plane);
+        const TapePlanes<T> tp(tape1, L.plane);
 #pragma unroll
         for (int i = 0; i < 5; ++i) *tp.at(i, node) = sg[i];
         *tp.at(5, node) = ux;
@@ -467,15 +485,16 @@ __global__ void __launch_bounds__((R + 2) * 64)
 
 }  // namespace
 
-hipError_t launch_step2(gg_storage s, bool seg, const LatDesc *d, const Tile *strips, int n_strips,
-                        int dir, int dt, hipStream_t st, int persist) {
+hipError_t launch_step2(gg_storage s, bool pairs, bool seg, const LatDesc *d, const Tile *strips,
+                        int n_strips, int dir, int dt, hipStream_t st, int persist) {
   if (n_strips <= 0) return hipSuccess;
   const int nblk = (n_strips + 3) / 4;
   const int per_xcd = (nblk + 7) / 8;
   int grid = 8 * per_xcd;
   if (persist > 0) grid = std::min(grid, (persist + 7) / 8 * 8);
-#define GG_LAUNCH2(TYPE, SEGV) \
-  k_step2<TYPE, SEGV><<<grid, 256, 0, st>>>(d, strips, n_strips, per_xcd, dir, dt)
+#define GG_LAUNCH2(TYPE, SEGV)                                                              \
+  (pairs ? k_step2<TYPE, SEGV, true><<<grid, 256, 0, st>>>(d, strips, n_strips, per_xcd, dir, dt) \
+         : k_step2<TYPE, SEGV, false><<<grid, 256, 0, st>>>(d, strips, n_strips, per_xcd, dir, dt))
   switch (s) {
     case GG_F64: if (seg) GG_LAUNCH2(double, true); else GG_LAUNCH2(double, false); break;
     case GG_F32: if (seg) GG_LAUNCH2(float, true); else GG_LAUNCH2(float, false); break;
@@ -485,55 +504,53 @@ hipError_t launch_step2(gg_storage s, bool seg, const LatDesc *d, const Tile *st
   return hipGetLastError();
 }
 
-hipError_t launch_tile2(gg_storage s, bool seg, int rows, const LatDesc *d, const Tile *tiles,
-                        int n_tiles, int dir, int dt, hipStream_t st, bool press, void *tape0,
-                        void *tape1) {
+template <class S, bool PAIRS>
+static void tile2_launch(bool seg, int rows, bool press, bool tape, int grid, hipStream_t st,
+                         const LatDesc *d, const Tile *tiles, int n_tiles, int per_xcd, int dir,
+                         int dt, void *tape0, void *tape1) {
+#define GG_T2(SEGV, RV, PV, TV)                                                              \
+  k_tile2<S, SEGV, RV, PV, TV, PAIRS><<<grid, ((RV) + 2) * 64, 0, st>>>(d, tiles, n_tiles,   \
+                                                                     per_xcd, dir, dt, tape0, \
+                                                                     tape1)
+  if (tape) {  // the adjoint's recomputation (no pressure segments)
+    if (seg && rows <= 2) GG_T2(true, 2, false, true);
+    else if (seg && rows <= 6) GG_T2(true, 6, false, true);
+    else if (seg) GG_T2(true, 14, false, true);
+    else if (rows <= 6) GG_T2(false, 6, false, true);
+    else GG_T2(false, 14, false, true);
+  } else if (seg && press) {
+    if (rows <= 2) GG_T2(true, 2, true, false);
+    else if (rows <= 6) GG_T2(true, 6, true, false);
+    else GG_T2(true, 14, true, false);
+  } else if (seg) {
+    if (rows <= 2) GG_T2(true, 2, false, false);
+    else if (rows <= 6) GG_T2(true, 6, false, false);
+    else GG_T2(true, 14, false, false);
+  } else {
+    if (rows <= 6) GG_T2(false, 6, false, false);
+    else GG_T2(false, 14, false, false);
+  }
+#undef GG_T2
+}
+
+hipError_t launch_tile2(gg_storage s, bool pairs, bool seg, int rows, const LatDesc *d,
+                        const Tile *tiles, int n_tiles, int dir, int dt, hipStream_t st, bool press,
+                        void *tape0, void *tape1) {
   if (n_tiles <= 0) return hipSuccess;
   const int per_xcd = (n_tiles + 7) / 8;
   const int grid = 8 * per_xcd;
-  if (tape0) {  // the adjoint's recomputation (no pressure segments)
-#define GG_LAUNCHTT(TYPE, SEGV, RV)                                                        \
-  k_tile2<TYPE, SEGV, RV, false, true><<<grid, ((RV) + 2) * 64, 0, st>>>(d, tiles, n_tiles, \
-                                                                       per_xcd, dir, dt,   \
-                                                                       tape0, tape1)
-#define GG_LAUNCHTT_S(TYPE)                            \
-  do {                                                 \
-    if (seg && rows <= 2) GG_LAUNCHTT(TYPE, true, 2);  \
-    else if (seg && rows <= 6) GG_LAUNCHTT(TYPE, true, 6); \
-    else if (seg) GG_LAUNCHTT(TYPE, true, 14);         \
-    else if (rows <= 6) GG_LAUNCHTT(TYPE, false, 6);   \
-    else GG_LAUNCHTT(TYPE, false, 14);                 \
-  } while (0)
-    switch (s) {
-      case GG_F64: GG_LAUNCHTT_S(double); break;
-      case GG_F32: GG_LAUNCHTT_S(float); break;
-      case GG_F16_SHIFTED: GG_LAUNCHTT_S(__half); break;
-    }
-#undef GG_LAUNCHTT_S
-#undef GG_LAUNCHTT
-    return hipGetLastError();
-  }
-#define GG_LAUNCHT(TYPE, SEGV, RV, PV) \
-  k_tile2<TYPE, SEGV, RV, PV><<<grid, ((RV) + 2) * 64, 0, st>>>(d, tiles, n_tiles, per_xcd, dir, dt, \
-                                                              nullptr, nullptr)
-#define GG_LAUNCHT_S(TYPE)                                           \
-  do {                                                               \
-    if (seg && press && rows <= 2) GG_LAUNCHT(TYPE, true, 2, true);  \
-    else if (seg && press && rows <= 6) GG_LAUNCHT(TYPE, true, 6, true); \
-    else if (seg && press) GG_LAUNCHT(TYPE, true, 14, true);         \
-    else if (seg && rows <= 2) GG_LAUNCHT(TYPE, true, 2, false);     \
-    else if (seg && rows <= 6) GG_LAUNCHT(TYPE, true, 6, false);     \
-    else if (seg) GG_LAUNCHT(TYPE, true, 14, false);                 \
-    else if (rows <= 6) GG_LAUNCHT(TYPE, false, 6, false);           \
-    else GG_LAUNCHT(TYPE, false, 14, false);                         \
-  } while (0)
+  const bool tape = tape0 != nullptr;
+#define GG_T2S(TYPE)                                                                        \
+  (pairs ? tile2_launch<TYPE, true>(seg, rows, press, tape, grid, st, d, tiles, n_tiles,    \
+                                     per_xcd, dir, dt, tape0, tape1)                        \
+         : tile2_launch<TYPE, false>(seg, rows, press, tape, grid, st, d, tiles, n_tiles,   \
+                                      per_xcd, dir, dt, tape0, tape1))
   switch (s) {
-    case GG_F64: GG_LAUNCHT_S(double); break;
-    case GG_F32: GG_LAUNCHT_S(float); break;
-    case GG_F16_SHIFTED: GG_LAUNCHT_S(__half); break;
+    case GG_F64: GG_T2S(double); break;
+    case GG_F32: GG_T2S(float); break;
+    case GG_F16_SHIFTED: GG_T2S(__half); break;
   }
-#undef GG_LAUNCHT_S
-#undef GG_LAUNCHT
+#undef GG_T2S
   return hipGetLastError();
 }
 

@@ -10,20 +10,22 @@ namespace gg {
 // step, dt added to the device step counter of each lattice. persist > 0
 // caps the grid at that many work-groups (rounded up to a multiple of 8),
 // which then stride through the tiles.
-hipError_t launch_step(gg_storage s, int block, bool odd, const LatDesc *d, const Tile *tiles,
-                       int n_tiles, int tx_shift, int dt, hipStream_t st, int persist = 0);
+hipError_t launch_step(gg_storage s, bool pairs, int block, bool odd, const LatDesc *d,
+                       const Tile *tiles, int n_tiles, int tx_shift, int dt, hipStream_t st,
+                       int persist = 0);
 // launch_step that also writes, for each fluid node, the state before the
 // step to `tape` (compute type, plane stride of the populations: dg_0..4,
 // u_x, u_y), the adjoint's tape.
-hipError_t launch_step_tape(gg_storage s, int block, bool odd, const LatDesc *d, const Tile *tiles,
-                            int n_tiles, int tx_shift, int dt, void *tape, hipStream_t st);
+hipError_t launch_step_tape(gg_storage s, bool pairs, int block, bool odd, const LatDesc *d,
+                            const Tile *tiles, int n_tiles, int tx_shift, int dt, void *tape,
+                            hipStream_t st);
 
 // Two steps in one pass (t even, natural order in): strips of 62 columns x
 // (flags >> 8) rows, four per 256-thread work-group; seg selects the kernel
 // for strips with segment links; dir 0 reads the plane set pop and writes
 // pop_b, dir 1 the reverse; dt as for launch_step.
-hipError_t launch_step2(gg_storage s, bool seg, const LatDesc *d, const Tile *strips, int n_strips,
-                        int dir, int dt, hipStream_t st, int persist = 0);
+hipError_t launch_step2(gg_storage s, bool pairs, bool seg, const LatDesc *d, const Tile *strips,
+                        int n_strips, int dir, int dt, hipStream_t st, int persist = 0);
 
 // The same two steps row-parallel: one work-group of rows + 2 wavefronts
 // per tile of 62 columns x (flags >> 8) rows, rows 2, 6 or 14; seg selects
@@ -33,23 +35,26 @@ hipError_t launch_step2(gg_storage s, bool seg, const LatDesc *d, const Tile *st
 // rescaling of the state after the pass is launch_rescale's). tape0,
 // tape1 (the adjoint's recomputation, no pressure segments): tape slots of
 // the pass's two steps, written for the tiles' owned nodes.
-hipError_t launch_tile2(gg_storage s, bool seg, int rows, const LatDesc *d, const Tile *tiles,
-                        int n_tiles, int dir, int dt, hipStream_t st, bool press = false,
-                        void *tape0 = nullptr, void *tape1 = nullptr);
+// pairs: the tiles' lattices hold their populations in the paired layout
+// (all of them, or none).
+hipError_t launch_tile2(gg_storage s, bool pairs, bool seg, int rows, const LatDesc *d,
+                        const Tile *tiles, int n_tiles, int dir, int dt, hipStream_t st,
+                        bool press = false, void *tape0 = nullptr, void *tape1 = nullptr);
 
 // Compound-only step on frozen velocity fields (64 x 4 tiles, 256-thread
 // work-groups, XCD-aware tile order as launch_step); odd = parity of the
 // step, dt as for launch_step.
-hipError_t launch_cde(gg_storage s, bool odd, const LatDesc *d, const Tile *tiles, int n_tiles,
-                      int tx_shift, int dt, hipStream_t st);
+hipError_t launch_cde(gg_storage s, bool pairs, bool odd, const LatDesc *d, const Tile *tiles,
+                      int n_tiles, int tx_shift, int dt, hipStream_t st);
 // Two compound-only steps in one pass (t even, natural order in): one
 // work-group of rows + 2 wavefronts per tile of 62 columns x (flags >> 8)
 // rows, rows 6 or 14; dir 0 reads the compound planes of pop and writes
 // those of pop_b, dir 1 the reverse; dt as for launch_step; press: the
 // lattice has pressure segments (their link rule and first rescaling in the
 // pass; launch_rescale after it).
-hipError_t launch_cde_tile2(gg_storage s, int rows, const LatDesc *d, const Tile *tiles,
-                            int n_tiles, int dir, int dt, hipStream_t st, bool press = false);
+hipError_t launch_cde_tile2(gg_storage s, bool pairs, int rows, const LatDesc *d,
+                            const Tile *tiles, int n_tiles, int dir, int dt, hipStream_t st,
+                            bool press = false);
 // Velocity of the current fluid state times `scale` into field slot `slot`.
 hipError_t launch_capture(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                           int tx_shift, int slot, double scale, hipStream_t st);
@@ -71,6 +76,12 @@ hipError_t launch_wall_apply(gg_storage s, const LatDesc *d, const int32_t *link
                              int dt, const void *save, bool fluid, hipStream_t st);
 
 // Auxiliary kernels: 256-thread work-groups over one lattice's tiles.
+// Population planes (n elements per plane, plane elements apart) from one
+// layout into the other (pairs: the paired layout of Planes), src into dst
+// (distinct buffers).
+hipError_t launch_relayout(gg_storage s, void *src, void *dst, int64_t plane, int64_t n,
+                           bool from_pairs, bool to_pairs, hipStream_t st);
+
 hipError_t launch_init(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                        int tx_shift, const double *rho, const double *ux,
                        const double *uy, const double *c, hipStream_t st);

@@ -34,7 +34,7 @@ namespace gg {
 // also write the node's state before the step to `tape` for the adjoint,
 // planes of the compute type with the populations' plane stride: dg_0..4,
 // then u_x, u_y (from the same moments as the collision).
-template <class S, bool ODD, bool TAPE = false>
+template <class S, bool ODD, bool PAIRS, bool TAPE = false>
 __device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
                                           const Tile *__restrict__ tiles, int tile,
                                           int tx_shift, int dt, void *tape = nullptr) {
@@ -60,14 +60,14 @@ __device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
   FluxT<T> fx;
 
   if (lc != NOT_FLUID) {
-    const Planes<W> pl(L);
+    const Planes<W> pl(L.pop, L.plane, PAIRS);  // (the lattice's layout)
     const Neigh nb(L, x, y);
     T f[9], g[5];  // deviations from rest, df_i and dg_i
     load_state<S, ODD>(pl, node, lc, nb, f, g);
     if (TAPE) {
       T rho, drho, ux, uy;
       node_velocity<T>(L, f, rho, drho, ux, uy);
-      const Planes<T> tp(tape, L.plane);
+      const TapePlanes<T> tp(tape, L.plane);
 #pragma unroll
       for (int i = 0; i < 5; ++i) *tp.at(i, node) = g[i];
       *tp.at(5, node) = ux;
@@ -112,26 +112,26 @@ __device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
 // processes a contiguous run of tiles (neighbouring tiles share an L2). With
 // a grid smaller than 8 * per_xcd (a multiple of 8), blocks stride through
 // the list and stay on their XCD's run (persistent launch).
-template <class S, int BS, bool ODD>
+template <class S, int BS, bool ODD, bool PAIRS>
 __global__ void __launch_bounds__(BS)
     k_step(const LatDesc *__restrict__ descs, const Tile *__restrict__ tiles,
            int n_tiles, int per_xcd, int tx_shift, int dt) {
   const int nb = 8 * per_xcd;
   for (int b = blockIdx.x; b < nb; b += gridDim.x) {
     const int tile = (b & 7) * per_xcd + (b >> 3);
-    if (tile < n_tiles) step_tile<S, ODD>(descs, tiles, tile, tx_shift, dt);
+    if (tile < n_tiles) step_tile<S, ODD, PAIRS>(descs, tiles, tile, tx_shift, dt);
   }
 }
 
 // The fused step that also writes the tape of the adjoint (see step_tile).
-template <class S, int BS, bool ODD>
+template <class S, int BS, bool ODD, bool PAIRS>
 __global__ void __launch_bounds__(BS)
     k_step_tape(const LatDesc *__restrict__ descs, const Tile *__restrict__ tiles, int n_tiles,
                 int per_xcd, int tx_shift, int dt, void *__restrict__ tape) {
   const int nb = 8 * per_xcd;
   for (int b = blockIdx.x; b < nb; b += gridDim.x) {
     const int tile = (b & 7) * per_xcd + (b >> 3);
-    if (tile < n_tiles) step_tile<S, ODD, true>(descs, tiles, tile, tx_shift, dt, tape);
+    if (tile < n_tiles) step_tile<S, ODD, PAIRS, true>(descs, tiles, tile, tx_shift, dt, tape);
   }
 }
 
@@ -366,67 +366,77 @@ __global__ void k_advance(const LatDesc *__restrict__ descs, int n, int64_t k) {
 // ---------------------------------------------------------------------------
 // Host-side launch wrappers.
 // ---------------------------------------------------------------------------
-template <class S, bool ODD>
+template <class S, bool ODD, bool PAIRS>
 static hipError_t launch_step_p(int bs, const LatDesc *d, const Tile *tiles, int n_tiles,
                                 int tx_shift, int dt, int persist, hipStream_t st) {
   const int per_xcd = (n_tiles + 7) / 8;
   const int full = 8 * per_xcd;
   const dim3 grid(persist > 0 ? std::min(full, (persist + 7) / 8 * 8) : full);
   switch (bs) {
-    case 64: k_step<S, 64, ODD><<<grid, 64, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
-    case 128: k_step<S, 128, ODD><<<grid, 128, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
-    case 256: k_step<S, 256, ODD><<<grid, 256, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
-    case 512: k_step<S, 512, ODD><<<grid, 512, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
+    case 64: k_step<S, 64, ODD, PAIRS><<<grid, 64, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
+    case 128: k_step<S, 128, ODD, PAIRS><<<grid, 128, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
+    case 256: k_step<S, 256, ODD, PAIRS><<<grid, 256, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
+    case 512: k_step<S, 512, ODD, PAIRS><<<grid, 512, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 template <class S>
-static hipError_t launch_step_s(int bs, bool odd, const LatDesc *d, const Tile *tiles,
+static hipError_t launch_step_s(int bs, bool odd, bool pairs, const LatDesc *d, const Tile *tiles,
                                 int n_tiles, int tx_shift, int dt, int persist, hipStream_t st) {
-  return odd ? launch_step_p<S, true>(bs, d, tiles, n_tiles, tx_shift, dt, persist, st)
-             : launch_step_p<S, false>(bs, d, tiles, n_tiles, tx_shift, dt, persist, st);
+  if (pairs)
+    return odd ? launch_step_p<S, true, true>(bs, d, tiles, n_tiles, tx_shift, dt, persist, st)
+               : launch_step_p<S, false, true>(bs, d, tiles, n_tiles, tx_shift, dt, persist, st);
+  return odd ? launch_step_p<S, true, false>(bs, d, tiles, n_tiles, tx_shift, dt, persist, st)
+             : launch_step_p<S, false, false>(bs, d, tiles, n_tiles, tx_shift, dt, persist, st);
 }
 
-hipError_t launch_step(gg_storage s, int block, bool odd, const LatDesc *d, const Tile *tiles,
-                       int n_tiles, int tx_shift, int dt, hipStream_t st, int persist) {
+hipError_t launch_step(gg_storage s, bool pairs, int block, bool odd, const LatDesc *d,
+                       const Tile *tiles, int n_tiles, int tx_shift, int dt, hipStream_t st,
+                       int persist) {
   if (n_tiles <= 0) return hipSuccess;
   switch (s) {
-    case GG_F64: return launch_step_s<double>(block, odd, d, tiles, n_tiles, tx_shift, dt, persist, st);
-    case GG_F32: return launch_step_s<float>(block, odd, d, tiles, n_tiles, tx_shift, dt, persist, st);
-    case GG_F16_SHIFTED: return launch_step_s<__half>(block, odd, d, tiles, n_tiles, tx_shift, dt, persist, st);
+    case GG_F64:
+      return launch_step_s<double>(block, odd, pairs, d, tiles, n_tiles, tx_shift, dt, persist, st);
+    case GG_F32:
+      return launch_step_s<float>(block, odd, pairs, d, tiles, n_tiles, tx_shift, dt, persist, st);
+    case GG_F16_SHIFTED:
+      return launch_step_s<__half>(block, odd, pairs, d, tiles, n_tiles, tx_shift, dt, persist, st);
   }
   return hipErrorInvalidValue;
 }
 
-template <class S, bool ODD>
+template <class S, bool ODD, bool PAIRS>
 static hipError_t launch_step_tape_p(int bs, const LatDesc *d, const Tile *tiles, int n_tiles,
                                      int tx_shift, int dt, void *tape, hipStream_t st) {
   const int per_xcd = (n_tiles + 7) / 8;
   const dim3 grid(8 * per_xcd);
   switch (bs) {
-    case 64: k_step_tape<S, 64, ODD><<<grid, 64, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt, tape); break;
-    case 128: k_step_tape<S, 128, ODD><<<grid, 128, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt, tape); break;
-    case 256: k_step_tape<S, 256, ODD><<<grid, 256, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt, tape); break;
-    case 512: k_step_tape<S, 512, ODD><<<grid, 512, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt, tape); break;
+    case 64: k_step_tape<S, 64, ODD, PAIRS><<<grid, 64, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt, tape); break;
+    case 128: k_step_tape<S, 128, ODD, PAIRS><<<grid, 128, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt, tape); break;
+    case 256: k_step_tape<S, 256, ODD, PAIRS><<<grid, 256, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt, tape); break;
+    case 512: k_step_tape<S, 512, ODD, PAIRS><<<grid, 512, 0, st>>>(d, tiles, n_tiles, per_xcd, tx_shift, dt, tape); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_step_tape(gg_storage s, int block, bool odd, const LatDesc *d, const Tile *tiles,
-                            int n_tiles, int tx_shift, int dt, void *tape, hipStream_t st) {
+hipError_t launch_step_tape(gg_storage s, bool pairs, int block, bool odd, const LatDesc *d,
+                            const Tile *tiles, int n_tiles, int tx_shift, int dt, void *tape,
+                            hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-#define GG_TAPE_S(TYPE)                                                                     \
-  return odd ? launch_step_tape_p<TYPE, true>(block, d, tiles, n_tiles, tx_shift, dt, tape, st) \
-             : launch_step_tape_p<TYPE, false>(block, d, tiles, n_tiles, tx_shift, dt, tape, st)
+#define GG_TAPE_P(TYPE, PV)                                                                  \
+  (odd ? launch_step_tape_p<TYPE, true, PV>(block, d, tiles, n_tiles, tx_shift, dt, tape, st) \
+       : launch_step_tape_p<TYPE, false, PV>(block, d, tiles, n_tiles, tx_shift, dt, tape, st))
+#define GG_TAPE_S(TYPE) return pairs ? GG_TAPE_P(TYPE, true) : GG_TAPE_P(TYPE, false)
   switch (s) {
     case GG_F64: GG_TAPE_S(double);
     case GG_F32: GG_TAPE_S(float);
     case GG_F16_SHIFTED: GG_TAPE_S(__half);
   }
 #undef GG_TAPE_S
+#undef GG_TAPE_P
   return hipErrorInvalidValue;
 }
 
@@ -542,7 +552,7 @@ __global__ void __launch_bounds__(64)
   if (s >= 0) {
     const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
     const uint8_t lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
-    const Planes<typename P::W> pl(other ? L.pop_b : L.pop, L.plane);
+    const Planes<typename P::W> pl(other ? L.pop_b : L.pop, L.plane, L.pairs != 0);
     const Neigh nb(L, x, y);
     T f[9], g[5];
     const bool odd = ((t + 1) & 1) != 0;  // parity of the state at t + 1
@@ -795,6 +805,37 @@ hipError_t launch_set_counter(int64_t *t, int64_t v, hipStream_t st) {
 
 hipError_t launch_advance(const LatDesc *descs, int n, int64_t k, hipStream_t st) {
   k_advance<<<(n + 63) / 64, 64, 0, st>>>(descs, n, k);
+  return hipGetLastError();
+}
+
+// Every element of every population plane (padding included) from the
+// layout of src into that of dst.
+template <class W>
+__global__ void __launch_bounds__(256)
+    k_relayout(void *src, void *dst, int64_t plane, int64_t n, int from_pairs, int to_pairs) {
+  const Planes<W> a(src, plane, from_pairs != 0), b(dst, plane, to_pairs != 0);
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
+    const uint32_t idx = (uint32_t)k;
+#pragma unroll
+    for (int i = 0; i < NPOP; ++i) gstore(b.at(i, idx), gload((const GG_GLOBAL W *)a.at(i, idx)));
+  }
+}
+
+hipError_t launch_relayout(gg_storage s, void *src, void *dst, int64_t plane, int64_t n,
+                           bool from_pairs, bool to_pairs, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+  switch (s) {
+    case GG_F64:
+      k_relayout<double><<<grid, 256, 0, st>>>(src, dst, plane, n, from_pairs, to_pairs);
+      break;
+    case GG_F32:
+      k_relayout<float><<<grid, 256, 0, st>>>(src, dst, plane, n, from_pairs, to_pairs);
+      break;
+    case GG_F16_SHIFTED:
+      k_relayout<unsigned short><<<grid, 256, 0, st>>>(src, dst, plane, n, from_pairs, to_pairs);
+      break;
+  }
   return hipGetLastError();
 }
 

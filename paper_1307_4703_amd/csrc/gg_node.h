@@ -9,8 +9,6 @@
 
 namespace gg {
 
-using CDesc = const GG_CONST LatDesc;
-
 struct PhaseNow {
   uint32_t open;
   const GG_CONST double *cin;
@@ -142,22 +140,6 @@ struct Neigh {
       const int yy = EY[k] > 0 ? yp : (EY[k] < 0 ? ym : y);
       idx[k] = (uint32_t)(L.node0 + yy * L.pitch + xx);
     }
-  }
-};
-
-// Uniform base pointers of the 14 population planes. Elements are reached
-// through a 32-bit byte offset (every plane is smaller than 4 GiB), which
-// maps onto the scalar-base + vector-offset form of global memory access.
-template <class W> struct Planes {
-  GG_GLOBAL W *p[NPOP];
-  __device__ __forceinline__ Planes(CDesc &L) : Planes(L.pop, L.plane) {}
-  __device__ __forceinline__ Planes(void *pop, int64_t plane) {
-    GG_GLOBAL W *base = (GG_GLOBAL W *)pop;
-#pragma unroll
-    for (int i = 0; i < NPOP; ++i) p[i] = base + (int64_t)i * plane;
-  }
-  __device__ __forceinline__ GG_GLOBAL W *at(int i, uint32_t idx) const {
-    return (GG_GLOBAL W *)((GG_GLOBAL char *)p[i] + idx * (uint32_t)sizeof(W));
   }
 };
 

@@ -64,6 +64,9 @@ struct gg_lattice {
   // tiles of strip_h rows with the boundary kernel apart or in one kernel);
   // fuse = 1 keeps to single steps
   int fuse = 3, strip_h = 6;
+  // population layout: paired (f_i, g_i side by side, i = 0..4) or
+  // plane-major (gg_set_layout)
+  bool pairs = true;
   // tile lists built with the halo-inclusive segment flag (pressure
   // segments: the passes rescale the boundary nodes as they load them)
   bool tiles_halo_seg = false, cde_halo_seg = false;

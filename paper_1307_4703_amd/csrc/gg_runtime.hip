@@ -136,6 +136,7 @@ gg_status gg_upload_desc(gg_lattice *L) {
   h.ny = L->ny;
   h.pitch = L->pitch;
   h.node0 = L->node0;
+  h.pairs = L->pairs ? 1 : 0;
   h.periodic_x = L->p.periodic_x != 0;
   h.periodic_y = L->p.periodic_y != 0;
   h.plane = L->plane;
@@ -393,9 +394,9 @@ gg_status gg_create_ex(const uint8_t *mask, int32_t nx, int32_t ny, const gg_par
   // padding row on each side; rows start on 64-element boundaries
   const int pitch = (nx + 1 + 63) / 64 * 64;
   const int64_t plane_elems = (int64_t)(ny + 2) * pitch + 128;
-  // kernels address a plane with a 32-bit byte offset
-  if (plane_elems * (int64_t)esize > ((int64_t)1 << 32) - 4096)
-    return fail(GG_ERR_ARG, "lattice too large: one population plane must stay below 4 GiB");
+  // kernels address a plane pair (the paired layout) with a 32-bit byte offset
+  if (2 * plane_elems * (int64_t)esize > ((int64_t)1 << 32) - 4096)
+    return fail(GG_ERR_ARG, "lattice too large: two population planes must stay below 4 GiB");
 
   gg_lattice *L = new gg_lattice();
   if (allocator) {
@@ -930,16 +931,16 @@ static hipError_t launch_pass(gg_lattice *L, int dir, int dt, hipStream_t st) {
   if (L->fuse == 4) {  // one kernel with the boundary rules for every tile
     e = prof_begin(L, st, pidx);
     if (e == hipSuccess)
-      e = launch_tile2(L->storage, true, L->strip_h, L->d_desc, L->d_strips, L->n_strips, dir, dt,
+      e = launch_tile2(L->storage, L->pairs, true, L->strip_h, L->d_desc, L->d_strips, L->n_strips, dir, dt,
                        st, press);
     if (e == hipSuccess) e = prof_end(L, st, pidx, 0);
     return e;
   }
   auto run = [&](bool seg, const Tile *list, int n, hipStream_t s) {
     // the segment list holds 2-row tiles
-    return L->fuse == 3 ? launch_tile2(L->storage, seg, seg ? 2 : L->strip_h, L->d_desc, list, n,
+    return L->fuse == 3 ? launch_tile2(L->storage, L->pairs, seg, seg ? 2 : L->strip_h, L->d_desc, list, n,
                                        dir, dt, s, press)
-                        : launch_step2(L->storage, seg, L->d_desc, list, n, dir, dt, s);
+                        : launch_step2(L->storage, L->pairs, seg, L->d_desc, list, n, dir, dt, s);
   };
   if (fork) {
     e = hipEventRecord(L->ev_fork, st);
@@ -985,7 +986,7 @@ static hipError_t launch_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t
       long pidx = -1;
       if (e == hipSuccess) e = prof_begin(L, st, pidx);
       if (e == hipSuccess)
-        e = launch_step(L->storage, block, ((t0 + dt) & 1) != 0, L->d_desc, L->d_tiles,
+        e = launch_step(L->storage, L->pairs, block, ((t0 + dt) & 1) != 0, L->d_desc, L->d_tiles,
                         L->n_tiles, txs, (int)dt, st);
       if (e == hipSuccess) e = prof_end(L, st, pidx, 1 + (int)((t0 + dt) & 1));
       if (e == hipSuccess && L->n_wall > 0)
@@ -1251,9 +1252,54 @@ gg_status gg_diagnostics(gg_lattice *L, gg_diag *out) {
 // Snapshot layout: header, 14 population planes, fluxes.
 struct SnapHeader {
   char magic[8];
-  int32_t version, nx, ny, storage;
+  int32_t version, nx, ny, storage, pairs, pad;
   int64_t pitch, plane, t;
 };
+
+// The state from the current population layout into the other (pairs =
+// the target), through the second plane set (free between calls) or a
+// buffer of its size; the stream is idle.
+static gg_status relayout(gg_lattice *L, bool pairs) {
+  const size_t pop_bytes = (size_t)NPOP * L->plane * L->esize;
+  void *dst = L->d_pop_b;
+  if (!dst) {
+    hipError_t e = dev_alloc(L, &dst, pop_bytes);
+    if (e != hipSuccess) return fail(GG_ERR_OOM, std::string("relayout: ") + hipGetErrorString(e));
+  }
+  GG_HIP(launch_relayout(L->storage, L->d_pop, dst, L->plane, L->plane_elems, L->pairs, pairs,
+                         L->stream));
+  GG_HIP(hipStreamSynchronize(L->stream));
+  if (L->d_pop_b) {
+    std::swap(L->d_pop, L->d_pop_b);
+  } else {
+    GG_HIP(dev_free(L, L->d_pop));
+    L->d_pop = dst;
+  }
+  L->pairs = pairs;
+  // (captured graphs hold the old configuration)
+  if (L->graph_exec) (void)hipGraphExecDestroy(L->graph_exec);
+  if (L->graph) (void)hipGraphDestroy(L->graph);
+  L->graph_exec = nullptr;
+  L->graph = nullptr;
+  gg_drop_cde_graphs(L);
+  return gg_upload_desc(L);
+}
+
+gg_status gg_set_layout(gg_lattice *L, int32_t layout) {
+  if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
+  if (layout != GG_LAYOUT_PLANES && layout != GG_LAYOUT_PAIRED)
+    return fail(GG_ERR_ARG, "layout must be GG_LAYOUT_PLANES or GG_LAYOUT_PAIRED");
+  const bool pairs = layout == GG_LAYOUT_PAIRED;
+  if (pairs == L->pairs) return GG_OK;
+  GG_HIP(hipStreamSynchronize(L->stream));
+  return relayout(L, pairs);
+}
+
+gg_status gg_get_layout(const gg_lattice *L, int32_t *layout) {
+  if (!L || !layout) return fail(GG_ERR_ARG, "NULL argument");
+  *layout = L->pairs ? GG_LAYOUT_PAIRED : GG_LAYOUT_PLANES;
+  return GG_OK;
+}
 
 gg_status gg_save(gg_lattice *L, void *buf, size_t *nbytes) {
   if (!L || !nbytes) return fail(GG_ERR_ARG, "NULL argument");
@@ -1267,10 +1313,12 @@ gg_status gg_save(gg_lattice *L, void *buf, size_t *nbytes) {
   GG_HIP(hipStreamSynchronize(L->stream));
   SnapHeader h;
   std::memcpy(h.magic, "GGLBMSNP", 8);
-  h.version = 1;
+  h.version = 2;
   h.nx = L->nx;
   h.ny = L->ny;
   h.storage = (int32_t)L->storage;
+  h.pairs = L->pairs ? 1 : 0;
+  h.pad = 0;
   h.pitch = L->pitch;
   h.plane = L->plane;
   GG_HIP(hipMemcpy(&h.t, L->d_t, sizeof(int64_t), hipMemcpyDeviceToHost));
@@ -1290,7 +1338,7 @@ gg_status gg_load(gg_lattice *L, const void *buf, size_t nbytes) {
   if (nbytes < need) return fail(GG_ERR_ARG, "snapshot too small");
   SnapHeader h;
   std::memcpy(&h, buf, sizeof(h));
-  if (std::memcmp(h.magic, "GGLBMSNP", 8) != 0 || h.version != 1)
+  if (std::memcmp(h.magic, "GGLBMSNP", 8) != 0 || h.version != 2 || (h.pairs != 0 && h.pairs != 1))
     return fail(GG_ERR_ARG, "not a lattice snapshot");
   if (h.nx != L->nx || h.ny != L->ny || h.storage != (int32_t)L->storage ||
       h.pitch != L->pitch || h.plane != L->plane)
@@ -1302,6 +1350,12 @@ gg_status gg_load(gg_lattice *L, const void *buf, size_t nbytes) {
                    hipMemcpyHostToDevice));
   GG_HIP(hipMemcpy(L->d_t, &h.t, sizeof(int64_t), hipMemcpyHostToDevice));
   L->t = h.t;
+  // a snapshot of the other population layout: into this lattice's
+  if ((h.pairs != 0) != L->pairs) {
+    const bool want = L->pairs;
+    L->pairs = h.pairs != 0;
+    return relayout(L, want);
+  }
   return GG_OK;
 }
 
@@ -1515,7 +1569,7 @@ gg_status gg_adjoint(gg_lattice *L, int64_t n, int64_t s, const double *weight,
     if (e == hipSuccess) e = launch_set_counter((int64_t *)scr_t, tk, rs);
     int64_t j = 0;
     auto single = [&]() {
-      e = launch_step_tape(L->storage, block, ((tk + j) & 1) != 0, sd, L->d_tiles, L->n_tiles, txs,
+      e = launch_step_tape(L->storage, L->pairs, block, ((tk + j) & 1) != 0, sd, L->d_tiles, L->n_tiles, txs,
                            (int)j, (char *)tp + (size_t)j * slot, rs);
       ++j;
     };
@@ -1530,14 +1584,14 @@ gg_status gg_adjoint(gg_lattice *L, int64_t n, int64_t s, const double *weight,
           char *t1p = t0p + slot;
           const int dt = (int)(j + 2 * q);
           if (L->fuse == 4) {
-            e = launch_tile2(L->storage, true, L->strip_h, sd, L->d_strips, L->n_strips, q, dt, rs,
+            e = launch_tile2(L->storage, L->pairs, true, L->strip_h, sd, L->d_strips, L->n_strips, q, dt, rs,
                              false, t0p, t1p);
           } else {
             if (L->n_seg_strips > 0)
-              e = launch_tile2(L->storage, true, 2, sd, L->d_seg_strips, L->n_seg_strips, q, dt, rs,
+              e = launch_tile2(L->storage, L->pairs, true, 2, sd, L->d_seg_strips, L->n_seg_strips, q, dt, rs,
                                false, t0p, t1p);
             if (e == hipSuccess)
-              e = launch_tile2(L->storage, false, L->strip_h, sd, L->d_strips, L->n_strips, q, dt,
+              e = launch_tile2(L->storage, L->pairs, false, L->strip_h, sd, L->d_strips, L->n_strips, q, dt,
                                rs, false, t0p, t1p);
           }
         }
@@ -1609,6 +1663,7 @@ gg_status gg_adjoint(gg_lattice *L, int64_t n, int64_t s, const double *weight,
 struct gg_batch {
   std::vector<gg_lattice *> lats;
   gg_storage storage = GG_F32;
+  bool pairs = true;  // the members' population layout
   hipStream_t stream = nullptr, cap_stream = nullptr;
   LatDesc *d_descs = nullptr;
   Tile *d_tiles[2] = {nullptr, nullptr};  // lattices at even / odd t at creation
@@ -1673,7 +1728,7 @@ static hipError_t batch_launch(gg_batch *B, int64_t s0, int64_t n, hipStream_t s
     for (int64_t k = 0; k < n / 2 && e == hipSuccess; ++k) {
       const int dir = (int)(k & 1), dt = (int)(2 * k);
       if (B->fuse == 4) {
-        e = launch_tile2(B->storage, true, B->rows, B->d_descs, B->d_strips, B->n_strips, dir, dt,
+        e = launch_tile2(B->storage, B->pairs, true, B->rows, B->d_descs, B->d_strips, B->n_strips, dir, dt,
                          st);
         continue;
       }
@@ -1681,15 +1736,15 @@ static hipError_t batch_launch(gg_batch *B, int64_t s0, int64_t n, hipStream_t s
         e = hipEventRecord(B->ev_fork, st);
         if (e == hipSuccess) e = hipStreamWaitEvent(B->side, B->ev_fork, 0);
         if (e == hipSuccess)
-          e = launch_tile2(B->storage, true, 2, B->d_descs, B->d_seg_strips, B->n_seg_strips, dir,
+          e = launch_tile2(B->storage, B->pairs, true, 2, B->d_descs, B->d_seg_strips, B->n_seg_strips, dir,
                            dt, B->side);
         if (e == hipSuccess) e = hipEventRecord(B->ev_join, B->side);
       } else if (B->n_seg_strips > 0) {
-        e = launch_tile2(B->storage, true, 2, B->d_descs, B->d_seg_strips, B->n_seg_strips, dir,
+        e = launch_tile2(B->storage, B->pairs, true, 2, B->d_descs, B->d_seg_strips, B->n_seg_strips, dir,
                          dt, st);
       }
       if (e == hipSuccess)
-        e = launch_tile2(B->storage, false, B->rows, B->d_descs, B->d_strips, B->n_strips, dir,
+        e = launch_tile2(B->storage, B->pairs, false, B->rows, B->d_descs, B->d_strips, B->n_strips, dir,
                          dt, st);
       if (fork && e == hipSuccess) e = hipStreamWaitEvent(st, B->ev_join, 0);
     }
@@ -1699,7 +1754,7 @@ static hipError_t batch_launch(gg_batch *B, int64_t s0, int64_t n, hipStream_t s
     for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt)
       for (int g = 0; g < 2 && e == hipSuccess; ++g)
         if (B->n_tiles[g] > 0)
-          e = launch_step(B->storage, block, ((s0 + dt + g) & 1) != 0, B->d_descs, B->d_tiles[g],
+          e = launch_step(B->storage, B->pairs, block, ((s0 + dt + g) & 1) != 0, B->d_descs, B->d_tiles[g],
                           B->n_tiles[g], txs, (int)dt, st, B->persist);
   }
   if (e == hipSuccess) e = launch_advance(B->d_descs, (int)B->lats.size(), n, st);
@@ -1726,6 +1781,8 @@ gg_status gg_batch_create(gg_lattice *const *lats, int32_t n, int32_t tile_x, in
   for (int k = 0; k < n; ++k) {
     if (!lats[k]) return fail(GG_ERR_ARG, "NULL lattice in the batch");
     if (lats[k]->storage != lats[0]->storage) return fail(GG_ERR_ARG, "batch members must share the storage type");
+    if (lats[k]->pairs != lats[0]->pairs)
+      return fail(GG_ERR_ARG, "batch members must share the population layout");
     if (lats[k]->stream != lats[0]->stream) return fail(GG_ERR_ARG, "batch members must share the HIP stream");
     for (int j = 0; j < k; ++j)
       if (lats[j] == lats[k]) return fail(GG_ERR_ARG, "a lattice appears twice in the batch");
@@ -1737,6 +1794,7 @@ gg_status gg_batch_create(gg_lattice *const *lats, int32_t n, int32_t tile_x, in
   gg_batch *B = new gg_batch();
   B->lats.assign(lats, lats + n);
   B->storage = lats[0]->storage;
+  B->pairs = lats[0]->pairs;
   B->stream = lats[0]->stream;
   B->tile_x = tile_x;
   B->tile_y = tile_y;
@@ -2046,7 +2104,7 @@ gg_status gg_step_timed(gg_lattice *L, int64_t n, double *ms_even, double *ms_od
   for (int64_t dt = 0; dt < n && e == hipSuccess; ++dt) {
     e = hipEventRecord(ev[2 * dt], L->stream);
     if (e == hipSuccess)
-      e = launch_step(L->storage, block, ((t0 + dt) & 1) != 0, L->d_desc, L->d_tiles,
+      e = launch_step(L->storage, L->pairs, block, ((t0 + dt) & 1) != 0, L->d_desc, L->d_tiles,
                       L->n_tiles, txs, (int)dt, L->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2 * dt + 1], L->stream);
   }
@@ -2263,8 +2321,8 @@ static hipError_t launch_cde_steps(gg_lattice *L, int64_t t0, int64_t n, hipStre
   hipError_t e = hipSuccess;
   int64_t dt = 0;
   auto single = [&](int64_t k) {
-    return launch_cde(L->storage, ((t0 + k) & 1) != 0, L->d_desc, L->d_aux_tiles, L->n_aux_tiles,
-                      6, (int)k, st);
+    return launch_cde(L->storage, L->pairs, ((t0 + k) & 1) != 0, L->d_desc, L->d_aux_tiles,
+                      L->n_aux_tiles, 6, (int)k, st);
   };
   if (L->cde_rows > 0 && L->d_pop_b && L->cde_tiles_rows == L->cde_rows && L->wall_scheme == 0) {
     const bool press = L->n_press > 0;
@@ -2279,7 +2337,7 @@ static hipError_t launch_cde_steps(gg_lattice *L, int64_t t0, int64_t n, hipStre
     // kernel the state the last one leaves, in pop_b after dir 0)
     const bool at_load = press && L->cde_halo_seg;
     for (int64_t k = 0; k < passes && e == hipSuccess; ++k) {
-      e = launch_cde_tile2(L->storage, L->cde_rows, L->d_desc, L->d_cde_tiles, L->n_cde_tiles,
+      e = launch_cde_tile2(L->storage, L->pairs, L->cde_rows, L->d_desc, L->d_cde_tiles, L->n_cde_tiles,
                            (int)(k & 1) | (at_load && k > 0 ? 2 : 0), (int)(dt + 2 * k), st,
                            press);
       if (e == hipSuccess && press && (!at_load || k == passes - 1))

@@ -30,7 +30,7 @@ def step_profile(case: str, storage: str = "f64", n_records: int = 20,
     U, D, steps = W.STEP_PROFILE_CASES[case]
     if steps % (2 * n_records):
         raise ValueError("the record stretches must be an even number of steps")
-    lat = Lattice.from_workload(wl, storage=storage)
+    lat = Lattice.from_workload(wl, storage=storage, layout="planes")
     lat.set_velocity_field(0, ux, uy)
     fluid = wl.mask == 0
     over: List[float] = []
@@ -153,7 +153,8 @@ def gradient_formation(hours: float = 4.0, storage: str = "f32", samples_per_hou
     for label, k in (("decay", GF_K), ("no_decay", 0.0)):
         wl = gradient_generator_paper_scale(storage, k)
         streams[label] = torch.cuda.Stream()
-        lat = Lattice.from_workload(wl, storage=storage, stream=int(streams[label].cuda_stream))
+        lat = Lattice.from_workload(wl, storage=storage, stream=int(streams[label].cuda_stream),
+                                    layout="planes")
         for slot, name in enumerate(("left", "right", "closed")):
             lat.set_velocity_field(slot, *fields[name], scale=scale)
         lat.set_phase_fields([0, 2, 1, 2])  # left open, closed, right open, closed
@@ -419,6 +420,7 @@ def boundary_rates(rate_steps: int = 2000) -> Dict:
         try:
             lat.step(256)
             lat.set_velocity_field(0)
+            lat.set_layout("planes")  # (the compound alone reads g only)
             lat.set_cde_launch(14)
             lat.cde_step(256)
             lat.sync()

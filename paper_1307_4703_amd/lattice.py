@@ -76,10 +76,11 @@ class Lattice:
                  w0: float = 1.0 / 3.0, rho0: float = 1.0, k_decay: float = 0.0,
                  c_shift: float = 0.0, periodic: Tuple[bool, bool] = (False, False),
                  storage: str = "f32", stream: Optional[int] = None,
-                 device_allocator: Optional[str] = None):
+                 device_allocator: Optional[str] = None, layout: str = "paired"):
         """device_allocator: None (the library's hipMalloc) or "torch" (every
         device buffer of the lattice from PyTorch's caching allocator on the
-        lattice's stream, gg_create_ex)."""
+        lattice's stream, gg_create_ex). layout: "paired" or "planes" (see
+        set_layout)."""
         self.mask = np.ascontiguousarray(mask, dtype=np.uint8)
         self.ny, self.nx = self.mask.shape
         self.storage = storage
@@ -102,12 +103,15 @@ class Lattice:
             raise ValueError(f"unknown device allocator {device_allocator!r}")
         self._h = h
         self.segments: Dict[int, object] = {}
+        if layout != "paired":
+            self.set_layout(layout)
 
     # ------------------------------------------------------------------
     @classmethod
     def from_workload(cls, wl, *, storage: Optional[str] = None,
                       stream: Optional[int] = None, init: bool = True,
-                      device_allocator: Optional[str] = None) -> "Lattice":
+                      device_allocator: Optional[str] = None,
+                      layout: str = "paired") -> "Lattice":
         """The workload's compound shift C_s applies to FP16 storage only; the
         wider types keep C_s = 0, where a compound at rest at 0 or at an
         inlet value is held without rounding."""
@@ -115,7 +119,7 @@ class Lattice:
         lat = cls(wl.mask, tau_f=wl.tau_f, D=wl.D, w0=wl.w0, rho0=wl.rho0,
                   k_decay=wl.k_decay, c_shift=wl.c_shift if storage == "f16" else 0.0,
                   periodic=wl.periodic, storage=storage, stream=stream,
-                  device_allocator=device_allocator)
+                  device_allocator=device_allocator, layout=layout)
         for s in wl.segments:
             lat.set_segment(s.id, s.kind, s.normal, s.u_max, s.c_in,
                             getattr(s, "rho", 1.0), getattr(s, "fix_c", False))
@@ -186,6 +190,22 @@ class Lattice:
         the boundary kernel apart; 4: the same in one kernel) or single steps
         (fuse = 1); include/gg.h, gg_set_two_step."""
         A.call("gg_set_two_step", self._h, int(fuse), int(strip_h))
+
+    def set_layout(self, layout: str) -> None:
+        """Population layout in device memory: "paired" (f_i and g_i side by
+        side for i = 0..4, a new lattice's layout, the faster one for coupled
+        steps) or "planes" (one plane per population, the faster one for the
+        compound-only steps); the stored state is converted, the results of
+        every step are the same bits in either; include/gg.h,
+        gg_set_layout."""
+        code = {"planes": A.GG_LAYOUT_PLANES, "paired": A.GG_LAYOUT_PAIRED}[layout]
+        A.call("gg_set_layout", self._h, code)
+
+    @property
+    def layout(self) -> str:
+        v = ctypes.c_int32()
+        A.call("gg_get_layout", self._h, ctypes.byref(v))
+        return "paired" if v.value == A.GG_LAYOUT_PAIRED else "planes"
 
     def step2_timed(self, n_pairs: int) -> float:
         """Run 2 * n_pairs two-step passes between HIP events; mean duration

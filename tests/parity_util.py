@@ -65,3 +65,41 @@ def field_errors(lat, o: Oracle, fluid: np.ndarray) -> Dict[str, float]:
     out["u_l2"] = float(np.sqrt(np.mean((ux[fluid] - uxo[fluid]) ** 2 + (uy[fluid] - uyo[fluid]) ** 2)) / umax)
     out["C_l2"] = float(np.sqrt(np.mean((C[fluid] - Co[fluid]) ** 2)) / max(1.0, np.abs(Co[fluid]).max()))
     return out
+
+
+# Snapshots (gg_save): magic[8], six int32 (version, nx, ny, storage, pairs,
+# pad), three int64 (pitch, plane, t), then the 14 population planes in the
+# lattice's layout (include/gg.h, gg_set_layout), then the fluxes.
+SNAP_DATA = 56
+
+
+def snapshot_header(snap: bytes) -> Dict[str, int]:
+    version, nx, ny, storage, pairs, _ = (int(v) for v in np.frombuffer(snap, np.int32, 6, 8))
+    pitch, plane, t = (int(v) for v in np.frombuffer(snap, np.int64, 3, 32))
+    assert version == 2
+    return {"nx": nx, "ny": ny, "storage": storage, "pairs": pairs, "pitch": pitch,
+            "plane": plane, "t": t, "node0": pitch + 64}
+
+
+def snapshot_slot(h: Dict[str, int], i: int, node: int) -> int:
+    """Element index (from the start of the planes) of population i (f0..f8,
+    then g0..g4) of node `node`."""
+    plane = h["plane"]
+    if not h["pairs"]:
+        return i * plane + node
+    if i < 5:
+        return 2 * i * plane + 2 * node
+    if i >= 9:
+        return 2 * (i - 9) * plane + 2 * node + 1
+    return (i + 5) * plane + node
+
+
+def snapshot_planes(snap: bytes, dtype) -> np.ndarray:
+    """The 14 planes as (14, plane) in population order, whatever the layout."""
+    h = snapshot_header(snap)
+    plane = h["plane"]
+    raw = np.frombuffer(snap, dtype, 14 * plane, SNAP_DATA).reshape(14, plane)
+    if not h["pairs"]:
+        return raw
+    pp = raw[:10].reshape(5, 2 * plane)
+    return np.concatenate([pp[:, 0::2], raw[10:14], pp[:, 1::2]])

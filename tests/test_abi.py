@@ -97,6 +97,8 @@ def test_null_arguments_of_the_later_calls():
     assert A.lib().gg_set_cde_launch(None, 14) == A.GG_ERR_ARG
     assert A.lib().gg_set_pressure_segment(None, 2, 1, 0, 1.0, 0.0, 0) == A.GG_ERR_ARG
     assert A.lib().gg_set_two_step(None, 3, 6) == A.GG_ERR_ARG
+    assert A.lib().gg_set_layout(None, A.GG_LAYOUT_PAIRED) == A.GG_ERR_ARG
+    assert A.lib().gg_get_layout(None, None) == A.GG_ERR_ARG
 
 
 def test_create_ex_rejects_an_incomplete_allocator():

@@ -12,7 +12,7 @@ import pytest
 from paper_1307_4703_amd import Lattice
 from tests.emu import emu
 from tests.emu_cases import cases
-from tests.parity_util import log, seeded_init
+from tests.parity_util import log, seeded_init, snapshot_header, snapshot_planes
 
 pytestmark = pytest.mark.gpu
 
@@ -23,11 +23,10 @@ def _raw_state(lat, storage):
     """Deviation planes (9, ny, nx) and (5, ny, nx) from a snapshot taken at
     an even step (natural order), as values of the compute type."""
     snap = lat.save()
-    hdr = np.frombuffer(snap, np.int64, 3, 24)
-    pitch, plane, t = int(hdr[0]), int(hdr[1]), int(hdr[2])
+    hd = snapshot_header(snap)
+    pitch, t, node0 = hd["pitch"], hd["t"], hd["node0"]
     assert t % 2 == 0
-    node0 = pitch + 64
-    raw = np.frombuffer(snap, RAW[storage], 14 * plane, 48).reshape(14, plane)
+    raw = snapshot_planes(snap, RAW[storage])
     ny, nx = lat.ny, lat.nx
     idx = node0 + np.arange(ny)[:, None] * pitch + np.arange(nx)[None, :]
     vals = raw[:, idx]
@@ -35,13 +34,14 @@ def _raw_state(lat, storage):
     return vals[:9].astype(ct), vals[9:].astype(ct), t
 
 
+@pytest.mark.parametrize("layout", ["paired", "planes"])
 @pytest.mark.parametrize("fuse", [1, 3, 4])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("name", ["gradient_generator", "random_source_decay", "straight_channel"])
-def test_gpu_state_equals_storage_rounded_replay(name, storage, fuse):
+def test_gpu_state_equals_storage_rounded_replay(name, storage, fuse, layout):
     wl, R = cases()[name]
     cs = wl.c_shift if storage == "f16" else 0.0
-    lat = Lattice.from_workload(wl, storage=storage, init=False)
+    lat = Lattice.from_workload(wl, storage=storage, init=False, layout=layout)
     lat.init(**seeded_init(wl, 21))
     if R is not None:
         lat.set_source(R)
@@ -50,7 +50,7 @@ def test_gpu_state_equals_storage_rounded_replay(name, storage, fuse):
     h, k, t = _raw_state(lat, storage)
     e = emu.Emulator(wl, storage, c_shift=cs, R=R)
     fl = wl.mask == 0
-    log(f"bitwise replay {name} {storage} fuse {fuse}")
+    log(f"bitwise replay {name} {storage} fuse {fuse} layout {layout}")
     for n in (2, 10, 12):
         lat.step(n)
         h, k = e.step(h, k, t, n)

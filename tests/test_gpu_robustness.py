@@ -13,7 +13,7 @@ import pytest
 
 from paper_1307_4703_amd import workloads as W
 from paper_1307_4703_amd._abi import GGError, GG_ERR_NONFINITE
-from tests.parity_util import log, make_lattice, seeded_init
+from tests.parity_util import SNAP_DATA, log, make_lattice, seeded_init, snapshot_header, snapshot_slot
 
 pytestmark = pytest.mark.gpu
 
@@ -43,13 +43,11 @@ def test_nonfinite_population_is_reported():
     lat.step(4)
     assert lat.diagnostics()["n_nonfinite"] == 0
     snap = bytearray(lat.save())
-    # header: magic[8], version, nx, ny, storage (int32), pitch, plane, t
-    # (int64); then the 14 planes; node (x, y) at node0 + y * pitch + x
-    pitch = int(np.frombuffer(snap, np.int64, 1, 24)[0])
-    node0 = pitch + 64
+    # node (x, y) at node0 + y * pitch + x; f_0 of it poisoned
+    h = snapshot_header(snap)
     ys, xs = np.nonzero(wl.mask == 0)
     x, y = int(xs[len(xs) // 2]), int(ys[len(ys) // 2])
-    off = 48 + 4 * (node0 + y * pitch + x)  # f_0 of (x, y): plane 0
+    off = SNAP_DATA + 4 * snapshot_slot(h, 0, h["node0"] + y * h["pitch"] + x)
     snap[off:off + 4] = np.array([np.nan], np.float32).tobytes()
     lat.load(bytes(snap))
     with pytest.raises(GGError) as e:

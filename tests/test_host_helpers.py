@@ -158,3 +158,28 @@ def test_bench_refuses_several_gpus():
     with pytest.raises(SystemExit) as e:
         bench.main(["--gpus", "2"])
     assert e.value.code == 2
+
+
+def test_snapshot_slots_follow_both_layouts():
+    """The snapshot reader of the tests: the element of population i of a
+    node in each layout (paired: f_i, g_i side by side for i < 5, f5..f8 in
+    planes 10..13), and the planes gathered back in population order."""
+    from tests.parity_util import snapshot_planes, snapshot_slot, SNAP_DATA
+    plane = 8
+    for pairs in (0, 1):
+        h = {"pairs": pairs, "plane": plane}
+        slots = {(i, n): snapshot_slot(h, i, n) for i in range(14) for n in range(plane // 2)}
+        assert len(set(slots.values())) == len(slots)  # no two share an element
+        assert all(0 <= v < 14 * plane for v in slots.values())
+        if pairs:
+            for i in range(5):
+                assert slots[(9 + i, 3)] == slots[(i, 3)] + 1
+        hdr = (b"GGLBMSNP" + np.array([2, 4, 1, 1, pairs, 0], np.int32).tobytes()
+               + np.array([8, plane, 0], np.int64).tobytes())
+        assert len(hdr) == SNAP_DATA
+        data = np.zeros(14 * plane, np.float32)
+        for (i, n), v in slots.items():
+            data[v] = 100 * i + n
+        got = snapshot_planes(hdr + data.tobytes(), np.float32)
+        for (i, n) in slots:
+            assert got[i, n] == 100 * i + n
