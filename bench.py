@@ -74,9 +74,9 @@ def workload(name):
 # launch form per workload ((fuse, rows) of gg_set_two_step), as the
 # autotuner picks it on this GPU; --tune re-runs the autotuner
 FORMS = {"gg2048_f32": (4, 6), "gg2048_f16": (4, 6), "gg8192_f16": (3, 6),
-         "gg8192_f16_pe2000": (3, 6), "gg8192_f32": (4, 14), "allfluid8192_f32": (4, 14),
-         "allfluid8192_f16": (3, 6), "shard8192x512_f32": (3, 6),
-         "allfluid8192_f64": (3, 14), "gg2048_f64": (4, 14), "straight_f64": (4, 6)}
+         "gg8192_f16_pe2000": (3, 6), "gg8192_f32": (4, 6), "allfluid8192_f32": (3, 14),
+         "allfluid8192_f16": (3, 6), "shard8192x512_f32": (3, 14),
+         "allfluid8192_f64": (3, 14), "gg2048_f64": (3, 6), "straight_f64": (4, 6)}
 
 
 def kernel_hash():
@@ -380,12 +380,13 @@ def cde_bytes_per_update(storage):
     return 5 * 2 * STORAGE_BYTES[storage] + 2 * (8 if storage == "f64" else 4) + 1
 
 
-def cde_bench(name, steps, flow_steps, rows, chunk=64):
+def cde_bench(name, steps, flow_steps, rows, chunk=64, layout="planes"):
     """The compound alone on a frozen velocity field (the paper's decoupled
     path): the flow developed for flow_steps coupled steps, its velocity
     captured into a field slot, then graph-replayed compound-only steps
     (two-step passes over tiles of `rows` rows, or single steps with rows 0)
-    timed with HIP events on the lattice's stream."""
+    timed with HIP events on the lattice's stream, the populations in the
+    given layout (gg_set_layout)."""
     import torch
     from paper_1307_4703_amd import Lattice
     wl = workload(name)
@@ -394,7 +395,7 @@ def cde_bench(name, steps, flow_steps, rows, chunk=64):
     nf = lat.info()["n_fluid"]
     lat.step(flow_steps)
     lat.set_velocity_field(0)
-    lat.set_layout("planes")  # (the compound alone reads g only)
+    lat.set_layout(layout)  # (planes: the compound alone reads g only)
     lat_layout = lat.layout
     lat.set_cde_launch(rows)
     lat.cde_step(4 * max(chunk, 4))
@@ -519,7 +520,7 @@ def counters_leg(leg, tile, chunk_unused=0):
         torch.cuda.synchronize()
         b.close()
         nf = sum(l.info()["n_fluid"] for l in lats)
-        manifest["batch64"] = {"kernel": "k_tile2<float, true, 6, false, false>", "grid": None,
+        manifest["batch64"] = {"kernel": "k_tile2<float, true, 6, false, false, true>", "grid": None,
                                "units": 2 * nf, "bytes_per_update": bytes_per_update("f32")}
     elif leg == "adjoint":
         wl = workload("gg2048_f32")
@@ -535,7 +536,7 @@ def counters_leg(leg, tile, chunk_unused=0):
         manifest["adjoint:k_adjoint2"] = {"kernel": "k_adjoint2<float, 6>", "grid": None,
                                           "units": 2 * nf,
                                           "bytes_per_update": ADJOINT_STEP_BYTES_F32}
-        manifest["adjoint:taped_pass"] = {"kernel": "k_tile2<float, true, 6, false, true>",
+        manifest["adjoint:taped_pass"] = {"kernel": "k_tile2<float, true, 6, false, true, true>",
                                           "grid": None, "units": 2 * nf,
                                           "bytes_per_update": bytes_per_update("f32") / 2 + 28}
     elif leg == "cde":
@@ -685,6 +686,8 @@ def main(argv=None):
     ap.add_argument("--adjoint-steps", type=int, default=20000)
     ap.add_argument("--cde-steps", type=int, default=0,
                     help="timed compound-only steps per lattice (0: the defaults)")
+    ap.add_argument("--cde-layout", choices=["planes", "paired"], default="planes",
+                    help="population layout of the compound-only leg")
     ap.add_argument("--counters", metavar="LEG",
                     choices=["lattices", "batch", "adjoint", "cde"],
                     help="no benchmark: run one leg with plain launches for rocprofv3 --pmc "
@@ -712,7 +715,7 @@ def main(argv=None):
     tile = tuple(int(v) for v in args.tile.split("x"))
     cde_leg = [(n, args.cde_steps or k, f, r) for n, k, f, r in CDE_LEG]
     if args.cde_only:
-        print(json.dumps({name: cde_bench(name, steps, flow, rows, args.chunk)
+        print(json.dumps({name: cde_bench(name, steps, flow, rows, args.chunk, args.cde_layout)
                           for name, steps, flow, rows in cde_leg}), flush=True)
         return
     if args.adjoint_only:
