@@ -323,6 +323,14 @@ template <class W> struct Planes {
     const uint32_t stride = (pairs && paired_slot(i) ? 2u : 1u) * (uint32_t)sizeof(W);
     return (GG_GLOBAL W *)((GG_GLOBAL char *)p[i] + idx * stride);
   }
+  // element idx + drow + dcol of plane i, with the uniform row offset drow
+  // (a multiple of the pitch) added to the scalar base and the column offset
+  // dcol (-1, 0 or 1) left constant, for the instruction's immediate offset
+  __device__ __forceinline__ GG_GLOBAL W *at_nb(int i, uint32_t idx, int drow, int dcol) const {
+    const int stride = (pairs && paired_slot(i) ? 2 : 1) * (int)sizeof(W);
+    GG_GLOBAL char *row = (GG_GLOBAL char *)p[i] + (int64_t)drow * stride;
+    return (GG_GLOBAL W *)(row + idx * (uint32_t)stride + dcol * stride);
+  }
 };
 
 // Plane-major arrays of other per-node records (the adjoint's tapes).

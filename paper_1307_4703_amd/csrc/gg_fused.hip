@@ -47,33 +47,32 @@ __device__ __forceinline__ void second_step(CDesc &L, const Planes<typename Pop<
   T qf[9], qg[5], jf[9], jg[5];
   collide_node<T, PRESS, FX>(L, x, y, lc, SEG, ph, sf, sg, qf, qg, jf, jg, fx, true, nbr);
   const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
-  uint32_t nb[9];
-  if (!L.periodic_x && !L.periodic_y) {
-    // (uniform) the neighbours are node + e_x + e_y pitch, padding included
-    const uint32_t pitch = (uint32_t)L.pitch;
+  // slot i of neighbour x + e_i as nbp(i) gives it
+  auto push = [&](auto nbp) {
+    // (stores in pairs: one conversion for two values where FP16 is stored)
+    if (dst.pairs) {  // (uniform) f_i and g_i to x + e_i in one access
+      P::st_pair(dst.at(0, node), qf[0], qg[0]);
 #pragma unroll
-    for (int i = 1; i < 9; ++i) nb[i] = node + (uint32_t)EX[i] + (uint32_t)EY[i] * pitch;
+      for (int i = 1; i < 5; ++i) P::st_pair(nbp(i), qf[i], qg[i]);
+#pragma unroll
+      for (int i = 5; i < 9; i += 2) P::st2(nbp(i), nbp(i + 1), qf[i], qf[i + 1]);
+    } else {
+      P::st2(dst.at(0, node), dst.at(9, node), qf[0], qg[0]);
+#pragma unroll
+      for (int i = 1; i < 9; i += 2) P::st2(nbp(i), nbp(i + 1), qf[i], qf[i + 1]);
+#pragma unroll
+      for (int i = 1; i < 5; i += 2) P::st2(nbp(9 + i), nbp(10 + i), qg[i], qg[i + 1]);
+    }
+  };
+  if (!L.periodic_x && !L.periodic_y) {
+    // (uniform) the neighbours are node + e_x + e_y pitch, padding included:
+    // the row offset goes into the scalar base, the column offset into the
+    // store's immediate
+    const int pitch = L.pitch;
+    push([&](int k) { return dst.at_nb(k, node, EY[k > 8 ? k - 9 : k] * pitch, EX[k > 8 ? k - 9 : k]); });
   } else {
     const Neigh n(L, x, y);
-#pragma unroll
-    for (int i = 1; i < 9; ++i) nb[i] = n.idx[i];
-  }
-  // (stores in pairs: one conversion for two values where FP16 is stored)
-  if (dst.pairs) {  // (uniform) f_i and g_i to x + e_i in one access
-    P::st_pair(dst.at(0, node), qf[0], qg[0]);
-#pragma unroll
-    for (int i = 1; i < 5; ++i) P::st_pair(dst.at(i, nb[i]), qf[i], qg[i]);
-#pragma unroll
-    for (int i = 5; i < 9; i += 2)
-      P::st2(dst.at(i, nb[i]), dst.at(i + 1, nb[i + 1]), qf[i], qf[i + 1]);
-  } else {
-    P::st2(dst.at(0, node), dst.at(9, node), qf[0], qg[0]);
-#pragma unroll
-    for (int i = 1; i < 9; i += 2)
-      P::st2(dst.at(i, nb[i]), dst.at(i + 1, nb[i + 1]), qf[i], qf[i + 1]);
-#pragma unroll
-    for (int i = 1; i < 5; i += 2)
-      P::st2(dst.at(9 + i, nb[i]), dst.at(10 + i, nb[i + 1]), qg[i], qg[i + 1]);
+    push([&](int k) { return dst.at(k, n.idx[k > 8 ? k - 9 : k]); });
   }
   if (lc != 0) {
     // x + e_i not fluid: the value arriving along opp(i) stays here

@@ -77,20 +77,33 @@ __device__ __forceinline__ void step_tile(const LatDesc *__restrict__ descs,
     T pf[9], pg[5], in_f[9], in_g[5];
     collide_node<T, true, FluxT<T>>(L, x, y, lc, seg_tile, ph, f, g, pf, pg, in_f, in_g, fx, true);
 
-    if (!ODD) {
+    if (!ODD && PAIRS) {  // (f_j, g_j) side by side: one access each
+#pragma unroll
+      for (int j = 0; j < 5; ++j) P::st_pair(pl.at(j, node), in_f[j], in_g[j]);
+#pragma unroll
+      for (int j = 5; j < 9; ++j) P::st(pl.at(j, node), in_f[j]);
+    } else if (!ODD) {
 #pragma unroll
       for (int j = 0; j < 9; ++j) P::st(pl.at(j, node), in_f[j]);
 #pragma unroll
       for (int j = 0; j < 5; ++j) P::st(pl.at(9 + j, node), in_g[j]);
     } else {
-      P::st(pl.at(0, node), pf[0]);
-      P::st(pl.at(9, node), pg[0]);
       // free flight to x + e_i; where that cell is not fluid the value lands
       // in a slot nobody reads
+      if (PAIRS) {
+        P::st_pair(pl.at(0, node), pf[0], pg[0]);
 #pragma unroll
-      for (int i = 1; i < 9; ++i) P::st(pl.at(i, nb.idx[i]), pf[i]);
+        for (int i = 1; i < 5; ++i) P::st_pair(pl.at(i, nb.idx[i]), pf[i], pg[i]);
 #pragma unroll
-      for (int i = 1; i < 5; ++i) P::st(pl.at(9 + i, nb.idx[i]), pg[i]);
+        for (int i = 5; i < 9; ++i) P::st(pl.at(i, nb.idx[i]), pf[i]);
+      } else {
+        P::st(pl.at(0, node), pf[0]);
+        P::st(pl.at(9, node), pg[0]);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) P::st(pl.at(i, nb.idx[i]), pf[i]);
+#pragma unroll
+        for (int i = 1; i < 5; ++i) P::st(pl.at(9 + i, nb.idx[i]), pg[i]);
+      }
       if (lc != 0) {
         // x + e_i not fluid: the value arriving here along opp(i) goes to
         // this node's own slot opp(i)

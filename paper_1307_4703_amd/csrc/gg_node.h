@@ -150,10 +150,25 @@ __device__ __forceinline__ void load_state(const Planes<typename Pop<S>::W> &pl,
                                            typename Pop<S>::T *f, typename Pop<S>::T *g) {
   using P = Pop<S>;
   if (!ODD) {
+    if (pl.pairs) {  // (f_i, g_i) side by side: one access each
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = P::ld(pl.at(i, node));
+      for (int i = 0; i < 5; ++i) P::ld_pair(pl.at(i, node), f[i], g[i]);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) g[i] = P::ld(pl.at(9 + i, node));
+      for (int i = 5; i < 9; ++i) f[i] = P::ld(pl.at(i, node));
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = P::ld(pl.at(i, node));
+#pragma unroll
+      for (int i = 0; i < 5; ++i) g[i] = P::ld(pl.at(9 + i, node));
+    }
+  } else if (pl.pairs) {
+    // streamed in from x - e_i, stored by that node in slot opp(i) (f and g
+    // of one direction side by side)
+    P::ld_pair(pl.at(0, node), f[0], g[0]);
+#pragma unroll
+    for (int i = 1; i < 5; ++i) P::ld_pair(pl.at(OPP[i], nb.idx[OPP[i]]), f[i], g[i]);
+#pragma unroll
+    for (int i = 5; i < 9; ++i) f[i] = P::ld(pl.at(OPP[i], nb.idx[OPP[i]]));
   } else {
     // streamed in from x - e_i, stored by that node in slot opp(i)
     f[0] = P::ld(pl.at(0, node));
@@ -162,6 +177,8 @@ __device__ __forceinline__ void load_state(const Planes<typename Pop<S>::W> &pl,
     g[0] = P::ld(pl.at(9, node));
 #pragma unroll
     for (int i = 1; i < 5; ++i) g[i] = P::ld(pl.at(9 + OPP[i], nb.idx[OPP[i]]));
+  }
+  if (ODD) {
     if (lc != 0) {
       // x - e_i not fluid: this node stored the boundary value in its own slot i
 #pragma unroll
