@@ -246,7 +246,7 @@ def roofline(r, storage, traffic):
     if traffic:
         out["traffic_gbs"] = round(traffic / (ms * 1e-3) / 1e9, 1)
         out["traffic_frac"] = round(traffic / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
-        out["traffic_per_algorithmic_single_trip"] = round(traffic / (alg / 2 if p["n_pass"] else alg), 4)
+        out["traffic_per_algorithmic_single_trip"] = round(traffic / (alg / 2 if passes else alg), 4)
     # whole-step throughput (all kernels of the step) priced at the bytes of
     # one coupled update
     out["step_rate_frac"] = round(r["nf"] * bpu * 1e-9 / (r["event_ms"] * 1e-3 / max(1, r.get("steps", 1)))

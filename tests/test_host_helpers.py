@@ -152,6 +152,13 @@ def test_bench_roofline_pass_and_single():
     out = bench.roofline(_fake_run(1100000, 20, 2.0, prof), "f16", traffic=None)
     assert out["launches_timed"] == 10 and out["launches_in_graph_replays"] == 8
     assert out["kernel_ms"] == pytest.approx(0.1)
+    # every pass inside graph replays (the driver's 20 steps): still one
+    # trip per pass launch
+    prof = {"n_pass": 0, "ms_pass": 0.0, "n_single": [0, 0], "ms_single": [0.0, 0.0],
+            "n_graph": 1, "ms_graph": 1.0, "graph_passes": 10, "graph_singles": 0,
+            "pass_fluid": 1000000, "fuse": 3}
+    out = bench.roofline(_fake_run(1100000, 20, 2.0, prof), "f16", traffic=60000000)
+    assert out["traffic_per_algorithmic_single_trip"] == pytest.approx(60 / 57, rel=1e-3)
 
 
 def test_bench_refuses_several_gpus():
