@@ -931,15 +931,15 @@ static hipError_t launch_pass(gg_lattice *L, int dir, int dt, hipStream_t st) {
   if (L->fuse == 4) {  // one kernel with the boundary rules for every tile
     e = prof_begin(L, st, pidx);
     if (e == hipSuccess)
-      e = launch_tile2(L->storage, L->pairs, true, L->strip_h, L->d_desc, L->d_strips, L->n_strips, dir, dt,
-                       st, press);
+      e = launch_tile2(L->storage, L->pairs, true, L->strip_h, L->d_desc, L->d_strips,
+                       L->n_strips, dir, dt, st, press);
     if (e == hipSuccess) e = prof_end(L, st, pidx, 0);
     return e;
   }
   auto run = [&](bool seg, const Tile *list, int n, hipStream_t s) {
     // the segment list holds 2-row tiles
-    return L->fuse == 3 ? launch_tile2(L->storage, L->pairs, seg, seg ? 2 : L->strip_h, L->d_desc, list, n,
-                                       dir, dt, s, press)
+    return L->fuse == 3 ? launch_tile2(L->storage, L->pairs, seg, seg ? 2 : L->strip_h, L->d_desc,
+                                       list, n, dir, dt, s, press)
                         : launch_step2(L->storage, L->pairs, seg, L->d_desc, list, n, dir, dt, s);
   };
   if (fork) {
@@ -986,8 +986,8 @@ static hipError_t launch_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t
       long pidx = -1;
       if (e == hipSuccess) e = prof_begin(L, st, pidx);
       if (e == hipSuccess)
-        e = launch_step(L->storage, L->pairs, block, ((t0 + dt) & 1) != 0, L->d_desc, L->d_tiles,
-                        L->n_tiles, txs, (int)dt, st);
+        e = launch_step(L->storage, L->pairs, block, ((t0 + dt) & 1) != 0, L->d_desc,
+                        L->d_tiles, L->n_tiles, txs, (int)dt, st);
       if (e == hipSuccess) e = prof_end(L, st, pidx, 1 + (int)((t0 + dt) & 1));
       if (e == hipSuccess && L->n_wall > 0)
         e = launch_wall_apply(L->storage, L->d_desc, L->d_wall_links, L->n_wall_links,
@@ -1266,9 +1266,13 @@ static gg_status relayout(gg_lattice *L, bool pairs) {
     hipError_t e = dev_alloc(L, &dst, pop_bytes);
     if (e != hipSuccess) return fail(GG_ERR_OOM, std::string("relayout: ") + hipGetErrorString(e));
   }
-  GG_HIP(launch_relayout(L->storage, L->d_pop, dst, L->plane, L->plane_elems, L->pairs, pairs,
-                         L->stream));
-  GG_HIP(hipStreamSynchronize(L->stream));
+  hipError_t e = launch_relayout(L->storage, L->d_pop, dst, L->plane, L->plane_elems, L->pairs,
+                                 pairs, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) {  // the state stays where and as it was
+    if (!L->d_pop_b) (void)dev_free(L, dst);
+    return fail(GG_ERR_HIP, std::string("relayout: ") + hipGetErrorString(e));
+  }
   if (L->d_pop_b) {
     std::swap(L->d_pop, L->d_pop_b);
   } else {
@@ -1350,11 +1354,14 @@ gg_status gg_load(gg_lattice *L, const void *buf, size_t nbytes) {
                    hipMemcpyHostToDevice));
   GG_HIP(hipMemcpy(L->d_t, &h.t, sizeof(int64_t), hipMemcpyHostToDevice));
   L->t = h.t;
-  // a snapshot of the other population layout: into this lattice's
+  // a snapshot of the other population layout: into this lattice's (if
+  // that fails, the lattice takes the snapshot's layout)
   if ((h.pairs != 0) != L->pairs) {
     const bool want = L->pairs;
     L->pairs = h.pairs != 0;
-    return relayout(L, want);
+    gg_status st = relayout(L, want);
+    if (st != GG_OK) (void)gg_upload_desc(L);
+    return st;
   }
   return GG_OK;
 }
