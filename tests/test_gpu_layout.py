@@ -55,6 +55,22 @@ def test_both_layouts_give_the_same_steps(storage, form):
     _same(a, b)
 
 
+@pytest.mark.parametrize("form", [(1, 6), (3, 6), (4, 14)])
+@pytest.mark.parametrize("periodic", [(True, False), (False, True), (True, True)])
+def test_periodic_lattices(periodic, form):
+    """Obstacles everywhere, 133x71, periodic axes (the neighbours wrap, so
+    the pushes take their addresses from the neighbour table)."""
+    mask = W.random_mask(133, 71, seed=7, periodic=periodic)
+    wl = W.Workload("random", mask, tau_f=0.7, D=0.03, periodic=periodic, storage="f32")
+    init = seeded_init(wl, 3)
+    log(f"layouts, random mask periodic {periodic}, form {form}")
+    a = _lattice(wl, "f32", init, "planes", form)
+    b = _lattice(wl, "f32", init, "paired", form)
+    for lat in (a, b):
+        lat.step(37)
+    _same(a, b)
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_pressure_segments_and_paper_walls(storage):
     """Pressure boundaries (rescaling between the pass's steps) and the
