@@ -73,9 +73,9 @@ def workload(name):
 
 # launch form per workload ((fuse, rows) of gg_set_two_step), as the
 # autotuner picks it on this GPU; --tune re-runs the autotuner
-FORMS = {"gg2048_f32": (4, 6), "gg2048_f16": (4, 6), "gg8192_f16": (3, 6),
-         "gg8192_f16_pe2000": (3, 6), "gg8192_f32": (4, 6), "allfluid8192_f32": (3, 14),
-         "allfluid8192_f16": (3, 6), "shard8192x512_f32": (3, 14),
+FORMS = {"gg2048_f32": (5, 6), "gg2048_f16": (4, 6), "gg8192_f16": (3, 6),
+         "gg8192_f16_pe2000": (3, 6), "gg8192_f32": (5, 6), "allfluid8192_f32": (5, 6),
+         "allfluid8192_f16": (3, 6), "shard8192x512_f32": (5, 6),
          "allfluid8192_f64": (3, 14), "gg2048_f64": (3, 6), "straight_f64": (4, 6)}
 
 
@@ -209,25 +209,27 @@ def time_lattice(name, steps, warmup, tile, chunk, form=None, monitor_every=1024
 
 
 def roofline(r, storage, traffic):
-    """Dominant kernel: the interior-tile kernel of the two-step pass (or
-    the single-step kernel when no pass ran). A launch of the pass
-    advances each fluid node of its tiles by two updates, so its
-    algorithmic bytes are 2 x (fluid nodes of its tiles) x the bytes per
-    coupled update (14 populations read and written + the 1-byte link
-    code); achieved = those bytes / the kernel's mean event-measured
+    """Dominant kernel: the interior-tile kernel of the two-step (or
+    four-step) pass, or the single-step kernel when no pass ran. A launch of
+    the pass advances each fluid node of its tiles by two (four) updates,
+    so its algorithmic bytes are 2 (4) x (fluid nodes of its tiles) x the
+    bytes per coupled update (14 populations read and written + the 1-byte
+    link code); achieved = those bytes / the kernel's mean event-measured
     launch duration. Because the pass makes one trip through memory for
-    two updates, this figure can exceed the HBM peak; the counter bytes
+    two (four) updates, this figure can exceed the HBM peak; the counter bytes
     (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated) per launch, when
     present for the current kernel source, give the HBM fraction."""
     p = r["prof"]
     bpu = bytes_per_update(storage)
     passes = p["n_pass"] + p["graph_passes"]
+    spp = p.get("steps_per_pass", 2)
     if passes > 0:
         # plain launches timed one by one; graph replays as a whole, divided
         # by the passes they hold (the boundary tiles' kernel runs beside)
         ms = (p["ms_pass"] + p["ms_graph"]) / passes
-        units = 2 * p["pass_fluid"]
-        kind = "two-step pass (interior tiles)" if p["fuse"] != 4 else "two-step pass"
+        units = spp * p["pass_fluid"]
+        kind = ("four-step pass (interior tiles)" if spp == 4 else
+                "two-step pass (interior tiles)" if p["fuse"] != 4 else "two-step pass")
         n_launch = passes
     else:
         n_launch = p["n_single"][0] + p["n_single"][1] + p["graph_singles"]
@@ -246,7 +248,7 @@ def roofline(r, storage, traffic):
     if traffic:
         out["traffic_gbs"] = round(traffic / (ms * 1e-3) / 1e9, 1)
         out["traffic_frac"] = round(traffic / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
-        out["traffic_per_algorithmic_single_trip"] = round(traffic / (alg / 2 if passes else alg), 4)
+        out["traffic_per_algorithmic_single_trip"] = round(traffic / (alg / spp if passes else alg), 4)
     # whole-step throughput (all kernels of the step) priced at the bytes of
     # one coupled update
     out["step_rate_frac"] = round(r["nf"] * bpu * 1e-9 / (r["event_ms"] * 1e-3 / max(1, r.get("steps", 1)))
@@ -507,9 +509,13 @@ def counters_leg(leg, tile, chunk_unused=0):
             p = lat.step_profile(16)
             lat.close()
             seg = "true" if p["fuse"] == 4 else "false"
-            grid = 8 * ((p["pass_tiles"] + 7) // 8) * (p["rows"] + 2) * 64
-            manifest[name] = {"kernel": f"k_tile2<{CTYPE[wl.storage]}, {seg}, {p['rows']},",
-                              "grid": grid, "units": 2 * p["pass_fluid"],
+            spp = p["steps_per_pass"]
+            # rows + 2 wavefronts per tile, rows + 6 in the four-step pass
+            waves = p["rows"] + (6 if spp == 4 else 2)
+            grid = 8 * ((p["pass_tiles"] + 7) // 8) * waves * 64
+            kern = "k_tile4" if spp == 4 else "k_tile2"
+            manifest[name] = {"kernel": f"{kern}<{CTYPE[wl.storage]}, {seg}, {p['rows']},",
+                              "grid": grid, "units": spp * p["pass_fluid"],
                               "bytes_per_update": bytes_per_update(wl.storage)}
             log(f"counters: {name} {manifest[name]}")
     elif leg == "batch":

@@ -271,13 +271,14 @@ gg_status gg_load(gg_lattice *lat, const void *buf, size_t nbytes);
  * (one work-group each, tile_x * tile_y in {64, 128, 256, 512}, tile_x a
  * multiple of 8); only tiles holding a fluid node are launched.
  * graph_chunk > 0 replays gg_step in HIP graphs of that many steps (rounded
- * up to even, to a multiple of 4 with the two-step pass); 0 launches every
- * step. */
+ * up to even, to a multiple of 4 with the two-step pass, of 8 with fuse =
+ * 5); 0 launches every step. */
 gg_status gg_set_launch(gg_lattice *lat, int32_t tile_x, int32_t tile_y,
                         int32_t graph_chunk);
 
 /* Two-step pass (fuse = 2, 3 or 4; a new lattice starts with fuse = 3,
- * strip_h = 6) or single steps only (fuse = 1). The pass reads the state
+ * strip_h = 6), four-step pass (fuse = 5) or single steps only (fuse =
+ * 1). The pass reads the state
  * of an even step once and writes the state two steps later into a second
  * set of population planes (same size as the first; allocated while
  * fuse >= 2, freed by fuse = 1), so every population crosses HBM once per
@@ -291,7 +292,18 @@ gg_status gg_set_launch(gg_lattice *lat, int32_t tile_x, int32_t tile_y,
  *     compiled into the one kernel that does every tile (with 2 and 3 the
  *     strips and tiles that touch a segment run in a kernel of their own,
  *     beside the others on a second stream, which keeps the boundary code
- *     out of the others' register budget).
+ *     out of the others' register budget);
+ *   fuse = 5: runs of 8k steps from an even step in passes of four steps
+ *     (temporal blocking over the AA pairs of steps, collide-and-stream
+ *     after Eq. 7 four times per trip through memory): one work-group of
+ *     12 wavefronts per tile of 58 columns x 6 rows with a three-node halo,
+ *     each step's row-crossing populations through LDS; the tiles whose
+ *     nodes within two of their own link to a segment run as 58 x 2 tiles
+ *     in a kernel of their own on the second stream, as with fuse = 3.
+ *     Other runs step as with fuse = 3 (strip_h 6 or 14). FP32 and FP16
+ *     storage without pressure segments or the paper's walls, periodic
+ *     axes of 4 nodes or more; otherwise fuse = 5 steps as fuse = 3. The
+ *     result is that of single steps, bit for bit, as for every form.
  * Each collides a one-node halo around its strip or tile once more for the
  * first step. Errors: GG_ERR_ARG for other values, and for fuse = 2 where
  * two vertically adjacent fluid nodes link to more than two boundary
@@ -537,8 +549,9 @@ gg_status gg_monitor_read(gg_lattice *lat, gg_diag *out, int64_t *count);
 /* Result of gg_step_profile. The dominant kernel is the one that takes the
  * most HBM traffic: the kernel over the interior tile list of each two-step
  * pass (with fuse 2 and 3 the boundary tiles run in a second kernel beside
- * it on a side stream; with fuse 4 it is the pass's only kernel), or the
- * step kernel of each single step. */
+ * it on a side stream; with fuse 4 it is the pass's only kernel), of each
+ * four-step pass where fuse 5 runs them (two-step passes of leftover steps
+ * are then not timed), or the step kernel of each single step. */
 typedef struct gg_profile {
   double ms_total;          /* HIP events around the whole call */
   int64_t n_pass;           /* plain launches of the pass's dominant kernel */
@@ -551,13 +564,16 @@ typedef struct gg_profile {
   double ms_single[2];      /* their summed duration */
   int64_t n_monitor;        /* monitor reductions launched (gg_set_monitor) */
   int64_t pass_fluid;       /* fluid nodes owned by the tiles of the pass's
-                               dominant kernel (two updates each per launch) */
+                               dominant kernel (steps_per_pass updates each
+                               per launch) */
   int64_t pass_side_fluid;  /* fluid nodes owned by the side kernel's tiles */
   int64_t pass_tiles;       /* tiles of the dominant kernel (one work-group of
                                rows + 2 wavefronts each, 8 * ceil(tiles / 8)
                                work-groups launched) */
   int64_t pass_side_tiles;  /* tiles of the side kernel (2 rows each) */
   int32_t fuse, rows;       /* launch form used (fuse 1: single steps only) */
+  int32_t steps_per_pass;   /* 2, or 4 where the four-step pass runs (fuse
+                               5; its tiles are then the pass_ fields') */
 } gg_profile;
 
 /* Instrumentation: gg_step(lat, n) with a pair of HIP events recorded on

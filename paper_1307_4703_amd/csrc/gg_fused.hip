@@ -482,6 +482,168 @@ __global__ void __launch_bounds__((R + 2) * 64)
   }
 }
 
+// Four coupled steps in one pass over memory: tiles of 58 columns x R rows,
+// R + 6 wavefronts (wavefront w on lattice row y0 - 3 + w, its 64 lanes on
+// the columns x0 - 3 .. x0 + 60). Step t runs on every row and column of
+// the tile and its three-node halo; the populations of each step's result
+// that cross columns go through lane shifts, those that cross rows through
+// LDS (two buffers, alternating), so that steps t + 1 and t + 2 run on the
+// rows and columns whose state they can complete (a node fewer on each side
+// per step), and step t + 3 on the owned nodes, stored into the
+// neighbours' slots of the other plane set as the two-step pass stores its
+// second step. Each collision goes through collide_node with the inputs the
+// single steps give it (the state between steps rounded to the storage
+// type), so the pass leaves what four single steps leave. SEG: the tiles
+// with a segment link among the nodes whose state at t + 1 or t + 2 they
+// complete; the others skip the boundary rules.
+template <class S, bool SEG, int R, bool PAIRS>
+__global__ void __launch_bounds__((R + 6) * 64)
+    k_tile4(const LatDesc *__restrict__ descs, const Tile *__restrict__ tiles, int n_tiles,
+            int per_xcd, int dir, int dt) {
+  using P = Pop<S>;
+  using T = typename P::T;
+  using W = typename P::W;
+  constexpr int NW = R + 6;
+  __shared__ T lds_up[2][NW][4][64];
+  __shared__ T lds_dn[2][NW][4][64];
+  const int lane = (int)(threadIdx.x & 63);
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int nb = 8 * per_xcd;
+  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int tile = (b & 7) * per_xcd + (b >> 3);
+    if (tile >= n_tiles) continue;  // the same for the whole work-group
+    const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
+    CDesc &L = ((CDesc *)descs)[tl.inst];
+    const int nx = L.nx, ny = L.ny, pitch = L.pitch;
+    const int rows = strip_rows(tl.flags);
+    const int64_t t = *(const GG_CONST int64_t *)L.t + dt;
+    const bool seg = SEG && (tl.flags & TILE_TOUCHES_SEGMENT) != 0;
+    PhaseNow ph[4] = {{0u, nullptr}, {0u, nullptr}, {0u, nullptr}, {0u, nullptr}};
+    if (seg) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ph[k] = phase_at(L, t + k);
+    }
+    const Planes<W> src(dir ? L.pop_b : L.pop, L.plane, PAIRS);
+    const Planes<W> dst(dir ? L.pop : L.pop_b, L.plane, PAIRS);
+
+    const int xr = tl.x0 - 3 + lane;
+    // addressable: the padding column on each side, or on a periodic axis
+    // the three-node halo wrapped once
+    const bool col = L.periodic_x ? xr >= -3 && xr <= nx + 2 : xr >= -1 && xr <= nx;
+    int x = xr;
+    if (L.periodic_x) x = xr < 0 ? xr + nx : (xr >= nx ? xr - nx : xr);
+    const bool own_col = lane >= 3 && lane < 3 + STRIP4_W && xr >= 0 && xr < nx;
+    const int yr = tl.y0 - 3 + w;
+    int y = yr;
+    if (L.periodic_y) y = yr < 0 ? yr + ny : (yr >= ny ? yr - ny : yr);
+    const bool row =
+        (L.periodic_y ? yr >= -3 && yr <= ny + 2 : yr >= -1 && yr <= ny) && w <= rows + 5;
+    const bool own = own_col && w >= 3 && w < 3 + rows && yr < ny;
+    const uint32_t node = (uint32_t)(L.node0 + y * pitch + x);
+    const bool live = row && col;
+    const uint32_t lnode = live ? node : (uint32_t)L.node0;
+    const uint8_t lc = live ? ((const GG_GLOBAL uint8_t *)L.link)[lnode] : NOT_FLUID;
+    T f[9], g[5];
+    if (src.pairs) {
+#pragma unroll
+      for (int i = 0; i < 5; ++i) P::ld_pair(src.at(i, lnode), f[i], g[i]);
+#pragma unroll
+      for (int i = 5; i < 9; ++i) f[i] = P::ld(src.at(i, lnode));
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = P::ld(src.at(i, lnode));
+#pragma unroll
+      for (int i = 0; i < 5; ++i) g[i] = P::ld(src.at(9 + i, lnode));
+    }
+    uint32_t nbr[2] = {0u, 0u};
+    if (seg && live && x >= 0 && x < nx && y >= 0 && y < ny) {
+      const Neigh nb(L, x, y);
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        nbr[k >> 2] |= (uint32_t)((const GG_GLOBAL uint8_t *)L.mask)[nb.idx[k + 1]] << (8 * (k & 3));
+    }
+    FluxT<T> fx;
+    T pf[9], pg[5], inf[9], ing[5];
+    if (!SEG || lc != NOT_FLUID) {
+      collide_node<T, false, FluxT<T>>(L, x, y, lc, seg, ph[0], f, g, pf, pg, inf, ing, fx, own,
+                                       SEG ? nbr : nullptr);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) pf[i] = inf[i] = T(0);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) pg[i] = ing[i] = T(0);
+    }
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+      const int q = (k - 1) & 1;
+      const T zf1 = from_left(pf[1]), zf3 = from_right(pf[3]);
+      const T zg1 = from_left(pg[1]), zg3 = from_right(pg[3]);
+      lds_up[q][w][0][lane] = pf[2];
+      lds_up[q][w][1][lane] = from_left(pf[5]);
+      lds_up[q][w][2][lane] = from_right(pf[6]);
+      lds_up[q][w][3][lane] = pg[2];
+      lds_dn[q][w][0][lane] = pf[4];
+      lds_dn[q][w][1][lane] = from_right(pf[7]);
+      lds_dn[q][w][2][lane] = from_left(pf[8]);
+      lds_dn[q][w][3][lane] = pg[4];
+      if (seg) fx.flush((double *)L.flux);
+      __syncthreads();
+      // rows whose state at t + k is needed (wave-uniform)
+      const bool act = w >= k && w < NW - k;
+      const bool run = k < 3 ? act && (!SEG || lc != NOT_FLUID) : own && lc != NOT_FLUID;
+      if (run) {
+        T sf[9], sg[5];
+        sf[0] = pf[0];
+        sg[0] = pg[0];
+        sf[1] = zf1;
+        sf[3] = zf3;
+        sg[1] = zg1;
+        sg[3] = zg3;
+        sf[2] = lds_up[q][w - 1][0][lane];
+        sf[5] = lds_up[q][w - 1][1][lane];
+        sf[6] = lds_up[q][w - 1][2][lane];
+        sg[2] = lds_up[q][w - 1][3][lane];
+        sf[4] = lds_dn[q][w + 1][0][lane];
+        sf[7] = lds_dn[q][w + 1][1][lane];
+        sf[8] = lds_dn[q][w + 1][2][lane];
+        sg[4] = lds_dn[q][w + 1][3][lane];
+        if (__any(lc != 0)) {
+#pragma unroll
+          for (int j = 1; j < 9; ++j)
+            if (src_solid(lc, j)) sf[j] = inf[j];
+#pragma unroll
+          for (int j = 1; j < 5; ++j)
+            if (src_solid(lc, j)) sg[j] = ing[j];
+        }
+        P::rt2(sf[0], sg[0]);
+#pragma unroll
+        for (int j = 1; j < 9; j += 2) P::rt2(sf[j], sf[j + 1]);
+#pragma unroll
+        for (int j = 1; j < 5; j += 2) P::rt2(sg[j], sg[j + 1]);
+        if (k < 3) {
+          collide_node<T, false, FluxT<T>>(L, x, y, lc, seg, ph[k], sf, sg, pf, pg, inf, ing, fx,
+                                           own, SEG ? nbr : nullptr);
+        } else if (seg) {
+          second_step<S, true, false, FluxT<T>>(L, dst, x, y, lc, ph[3], sf, sg, fx, nbr);
+        } else {
+          second_step<S, false, false, FluxT<T>>(L, dst, x, y, lc, ph[3], sf, sg, fx);
+        }
+      }
+    }
+    if (seg) fx.flush((double *)L.flux);
+    __syncthreads();  // the LDS rows are reused by the next tile
+  }
+}
+
+template <class S, bool PAIRS>
+static void tile4_launch(bool seg, int grid, hipStream_t st, const LatDesc *d, const Tile *tiles,
+                         int n_tiles, int per_xcd, int dir, int dt) {
+  if (seg)
+    k_tile4<S, true, 2, PAIRS><<<grid, 8 * 64, 0, st>>>(d, tiles, n_tiles, per_xcd, dir, dt);
+  else
+    k_tile4<S, false, 6, PAIRS><<<grid, 12 * 64, 0, st>>>(d, tiles, n_tiles, per_xcd, dir, dt);
+}
+
 }  // namespace
 
 hipError_t launch_step2(gg_storage s, bool pairs, bool seg, const LatDesc *d, const Tile *strips,
@@ -550,6 +712,25 @@ hipError_t launch_tile2(gg_storage s, bool pairs, bool seg, int rows, const LatD
     case GG_F16_SHIFTED: GG_T2S(__half); break;
   }
 #undef GG_T2S
+  return hipGetLastError();
+}
+
+hipError_t launch_tile4(gg_storage s, bool pairs, bool seg, const LatDesc *d, const Tile *tiles,
+                        int n_tiles, int dir, int dt, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  const int per_xcd = (n_tiles + 7) / 8;
+  const int grid = 8 * per_xcd;
+  switch (s) {
+    case GG_F64: return hipErrorInvalidValue;
+    case GG_F32:
+      if (pairs) tile4_launch<float, true>(seg, grid, st, d, tiles, n_tiles, per_xcd, dir, dt);
+      else tile4_launch<float, false>(seg, grid, st, d, tiles, n_tiles, per_xcd, dir, dt);
+      break;
+    case GG_F16_SHIFTED:
+      if (pairs) tile4_launch<__half, true>(seg, grid, st, d, tiles, n_tiles, per_xcd, dir, dt);
+      else tile4_launch<__half, false>(seg, grid, st, d, tiles, n_tiles, per_xcd, dir, dt);
+      break;
+  }
   return hipGetLastError();
 }
 

@@ -41,6 +41,14 @@ hipError_t launch_tile2(gg_storage s, bool pairs, bool seg, int rows, const LatD
                         const Tile *tiles, int n_tiles, int dir, int dt, hipStream_t st,
                         bool press = false, void *tape0 = nullptr, void *tape1 = nullptr);
 
+// Four steps in one pass (t even, natural order in and out): one work-group
+// of rows + 6 wavefronts per tile of 58 columns x (flags >> 8) rows, rows 2
+// (seg, the boundary kernel) or 6; FP32 and FP16-shifted storage (FP64:
+// hipErrorInvalidValue), no pressure segments; dir and dt as for
+// launch_tile2.
+hipError_t launch_tile4(gg_storage s, bool pairs, bool seg, const LatDesc *d, const Tile *tiles,
+                        int n_tiles, int dir, int dt, hipStream_t st);
+
 // Compound-only step on frozen velocity fields (64 x 4 tiles, 256-thread
 // work-groups, XCD-aware tile order as launch_step); odd = parity of the
 // step, dt as for launch_step.

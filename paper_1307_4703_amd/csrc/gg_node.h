@@ -218,8 +218,10 @@ using Flux = FluxT<double>;
 // of the columns x0 - 1 .. x0 + 62), the row count of a tile or strip kept
 // in its flags above bit 8, lane shifts that carry a population one column
 // right (from_left) or left (from_right), and the test whether x - e_j is
-// not fluid for a node with link code lc (j = 1..8).
+// not fluid for a node with link code lc (j = 1..8). The four-step pass
+// owns 58 columns (lanes 3..60 of the columns x0 - 3 .. x0 + 60).
 constexpr int STRIP_W = 62;
+constexpr int STRIP4_W = 58;
 __device__ __forceinline__ int strip_rows(int flags) { return flags >> 8; }
 template <class T> __device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1); }
 template <class T> __device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1); }

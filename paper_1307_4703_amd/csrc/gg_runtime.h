@@ -62,7 +62,9 @@ struct gg_lattice {
   // two-step pass: fuse = 2, 3, 4 advance pairs of steps in one pass over
   // memory (walking strips of 62 columns x strip_h rows, or row-parallel
   // tiles of strip_h rows with the boundary kernel apart or in one kernel);
-  // fuse = 1 keeps to single steps
+  // fuse = 5 runs runs of eight steps in four-step passes (58 x 6 tiles,
+  // the boundary kernel apart) and other runs as fuse = 3; fuse = 1 keeps
+  // to single steps
   int fuse = 3, strip_h = 6;
   // population layout: paired (f_i, g_i side by side, i = 0..4) or
   // plane-major (gg_set_layout)
@@ -113,6 +115,12 @@ struct gg_lattice {
   hipGraphExec_t cde_exec[2] = {nullptr, nullptr};
   // fluid nodes owned by the tiles of the pass's two lists
   int64_t strips_fluid = 0, seg_strips_fluid = 0;
+  // the four-step pass's lists (fuse = 5 where the lattice allows it: FP32
+  // or FP16 storage, no pressure segments, periodic axes of 4 nodes or more)
+  gg::Tile *d_strips4 = nullptr, *d_seg_strips4 = nullptr;
+  int n_strips4 = 0, n_seg_strips4 = 0;
+  int64_t strips4_fluid = 0, seg_strips4_fluid = 0;
+  bool tiles4 = false;  // the lists were built (pass4_ok held)
   // monitor: the FP64 reduction of gg_diagnostics launched after every
   // mon_every-th step (counted from mon_t0) into d_mon (8 totals, then the
   // 2 * GG_MAX_SEGMENTS flux accumulators copied at the same point)

@@ -115,8 +115,9 @@ void gg_free_device(gg_lattice *L) {
   L->graph = nullptr;
   void *ptrs[] = {L->d_pop, L->d_pop_b, L->d_link, L->d_mask, L->d_region, L->d_R, L->d_t,
                   L->d_flux, L->d_acc, L->d_desc, L->d_tiles, L->d_aux_tiles, L->d_strips,
-                  L->d_seg_strips, L->d_partial, L->d_ufield, L->d_cde_tiles, L->d_press,
-                  L->d_wall, L->d_wall_links, L->d_wall_save, L->d_mon};
+                  L->d_seg_strips, L->d_strips4, L->d_seg_strips4, L->d_partial, L->d_ufield,
+                  L->d_cde_tiles, L->d_press, L->d_wall, L->d_wall_links, L->d_wall_save,
+                  L->d_mon};
   for (void *p : ptrs)
     if (p) (void)dev_free(L, p);
   for (hipEvent_t ev : L->prof_ev)
@@ -227,29 +228,32 @@ static void build_tiles(const gg_lattice *L, int tx, int ty, int inst,
     }
 }
 
-// Strips of the two-step pass: 62 owned columns x h rows holding at least
-// one fluid node, laid from the first column of each run of fluid columns
-// of a band (rows y0 .. y0 + h - 1), listed band by band from left to
-// right: horizontally adjacent strips store into the same cache lines at
+// Strips of the two-step pass: width (62) owned columns x h rows holding at
+// least one fluid node, laid from the first column of each run of fluid
+// columns of a band (rows y0 .. y0 + h - 1), listed band by band from left
+// to right: horizontally adjacent strips store into the same cache lines at
 // their common edge every row, so they go to the same XCD (a contiguous run
 // of the list) and run side by side in one work-group. With split, a band
 // piece with a link to a boundary segment is cut into 2-row strips and
 // those with segment links go to the second list; otherwise it stays whole
-// in the first. Flags: strip height << 8 | segment bit.
+// in the first. Flags: strip height << 8 | segment bit. The four-step pass
+// takes tiles of 58 columns the same way.
 static void build_strips(const gg_lattice *L, int h, int inst, bool split, std::vector<Tile> &main,
-                         std::vector<Tile> &seg, bool halo_seg = false) {
+                         std::vector<Tile> &seg, int halo = 0, int width = 62) {
   auto scan = [&](int x0, int y0, int rows, bool &any, bool &sg) {
     any = sg = false;
     for (int y = y0; y < std::min(y0 + rows, L->ny); ++y)
-      for (int x = x0; x < std::min(x0 + 62, L->nx); ++x) {
+      for (int x = x0; x < std::min(x0 + width, L->nx); ++x) {
         if (L->link[L->nid(x, y)] == NOT_FLUID) continue;
         any = true;
         if (L->touches_seg[(size_t)y * L->nx + x]) sg = true;
       }
-    // halo_seg: also when a node of the one-node halo the tile collides
-    // touches a segment (wrapped on periodic axes)
-    for (int yr = y0 - 1; halo_seg && !sg && yr <= y0 + rows; ++yr)
-      for (int xr = x0 - 1; !sg && xr <= x0 + 62; ++xr) {
+    // halo 1 (pressure segments, rescaled at load): also when a node of
+    // the one-node halo the tile collides touches a segment; halo 2 (the
+    // four-step pass): within two nodes of the tile, the nodes whose state
+    // at t + 1 the tile completes (wrapped on periodic axes)
+    for (int yr = y0 - halo; halo > 0 && !sg && yr <= y0 + rows - 1 + halo; ++yr)
+      for (int xr = x0 - halo; !sg && xr <= x0 + width - 1 + halo; ++xr) {
         int x = xr, y = yr;
         if (x < 0 || x >= L->nx) {
           if (!L->p.periodic_x) continue;
@@ -279,14 +283,14 @@ static void build_strips(const gg_lattice *L, int h, int inst, bool split, std::
       }
       int e = x;
       while (e < L->nx && colany[e]) ++e;
-      if (!runs.empty() && x - runs.back().second < 62)
+      if (!runs.empty() && x - runs.back().second < width)
         runs.back().second = e;
       else
         runs.push_back({x, e});
       x = e;
     }
     for (const auto &run : runs)
-      for (int x0 = run.first; x0 < run.second; x0 += 62) {
+      for (int x0 = run.first; x0 < run.second; x0 += width) {
         bool any, sg;
         scan(x0, y0, h, any, sg);
         if (!any) continue;
@@ -307,18 +311,27 @@ static void build_strips(const gg_lattice *L, int h, int inst, bool split, std::
   }
 }
 
-// Fluid nodes owned by a list of pass tiles (62 columns x the rows in the
-// flags of each).
-static int64_t owned_fluid(const gg_lattice *L, const std::vector<Tile> &list) {
+// Fluid nodes owned by a list of pass tiles (width columns x the rows in
+// the flags of each).
+static int64_t owned_fluid(const gg_lattice *L, const std::vector<Tile> &list, int width = 62) {
   int64_t n = 0;
   for (const Tile &t : list)
     for (int y = t.y0; y < std::min(t.y0 + (t.flags >> 8), L->ny); ++y)
-      for (int x = t.x0; x < std::min(t.x0 + 62, L->nx); ++x)
+      for (int x = t.x0; x < std::min(t.x0 + width, L->nx); ++x)
         n += L->link[L->nid(x, y)] != NOT_FLUID;
   return n;
 }
 
 static bool has_pressure(const gg_lattice *L);
+
+// The four-step pass (fuse 5) covers this lattice: FP32 or FP16 storage
+// (the FP64 tiles would not fit two work-groups per CU), no pressure
+// segments (their rescaling runs between steps) nor the paper's walls, and
+// periodic axes of 4 nodes or more (the tiles' three-node halo wraps once).
+static bool pass4_ok(const gg_lattice *L) {
+  return L->fuse == 5 && L->storage != GG_F64 && !has_pressure(L) && L->wall_scheme == 0 &&
+         (!L->p.periodic_x || L->nx >= 4) && (!L->p.periodic_y || L->ny >= 4);
+}
 
 gg_status gg_rebuild_tiles(gg_lattice *L) {
   std::vector<Tile> t;
@@ -334,7 +347,7 @@ gg_status gg_rebuild_tiles(gg_lattice *L) {
   // with pressure segments the one-kernel pass rescales the state it loads
   // in every tile that collides a boundary node, halo included
   L->tiles_halo_seg = L->fuse == 4 && has_pressure(L);
-  build_strips(L, L->strip_h, 0, L->fuse != 4, sv, ss, L->tiles_halo_seg);
+  build_strips(L, L->strip_h, 0, L->fuse != 4, sv, ss, L->tiles_halo_seg ? 1 : 0);
   if (L->d_strips) (void)dev_free(L, L->d_strips);
   if (L->d_seg_strips) (void)dev_free(L, L->d_seg_strips);
   L->d_strips = L->d_seg_strips = nullptr;
@@ -349,6 +362,29 @@ gg_status gg_rebuild_tiles(gg_lattice *L) {
   if (!ss.empty()) {
     GG_HIP(dev_alloc(L, (void **)&L->d_seg_strips, ss.size() * sizeof(Tile)));
     GG_HIP(hipMemcpy(L->d_seg_strips, ss.data(), ss.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  }
+  // the four-step pass's lists (6-row tiles, 2-row boundary tiles)
+  if (L->d_strips4) (void)dev_free(L, L->d_strips4);
+  if (L->d_seg_strips4) (void)dev_free(L, L->d_seg_strips4);
+  L->d_strips4 = L->d_seg_strips4 = nullptr;
+  L->n_strips4 = L->n_seg_strips4 = 0;
+  L->strips4_fluid = L->seg_strips4_fluid = 0;
+  L->tiles4 = pass4_ok(L);
+  if (L->tiles4) {
+    std::vector<Tile> m4, s4;
+    build_strips(L, 6, 0, true, m4, s4, 2, 58);
+    L->n_strips4 = (int)m4.size();
+    L->n_seg_strips4 = (int)s4.size();
+    L->strips4_fluid = owned_fluid(L, m4, 58);
+    L->seg_strips4_fluid = owned_fluid(L, s4, 58);
+    if (!m4.empty()) {
+      GG_HIP(dev_alloc(L, (void **)&L->d_strips4, m4.size() * sizeof(Tile)));
+      GG_HIP(hipMemcpy(L->d_strips4, m4.data(), m4.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    }
+    if (!s4.empty()) {
+      GG_HIP(dev_alloc(L, (void **)&L->d_seg_strips4, s4.size() * sizeof(Tile)));
+      GG_HIP(hipMemcpy(L->d_seg_strips4, s4.data(), s4.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    }
   }
   if (L->graph_exec) (void)hipGraphExecDestroy(L->graph_exec);
   if (L->graph) (void)hipGraphDestroy(L->graph);
@@ -667,7 +703,7 @@ static bool has_pressure(const gg_lattice *L) {
 static gg_status pressure_nodes(gg_lattice *L) {
   if (!L->press_dirty) return GG_OK;
   // the tile lists mark the tiles that must rescale what they load
-  if (L->tiles_halo_seg != (L->fuse == 4 && has_pressure(L))) {
+  if (L->tiles_halo_seg != (L->fuse == 4 && has_pressure(L)) || L->tiles4 != pass4_ok(L)) {
     gg_status st = gg_rebuild_tiles(L);
     if (st != GG_OK) return st;
   }
@@ -926,8 +962,11 @@ static hipError_t prof_end(gg_lattice *L, hipStream_t st, long idx, int kind) {
 static hipError_t launch_pass(gg_lattice *L, int dir, int dt, hipStream_t st) {
   hipError_t e = hipSuccess;
   const bool fork = L->n_seg_strips > 0 && L->n_strips > 0;
-  const bool press = L->n_press > 0;  // (fuse 3 and 4 only)
+  const bool press = L->n_press > 0;  // (fuse 3, 4 and 5 only)
   long pidx = -1;
+  // (with the four-step pass on, the two-step passes of leftover steps are
+  // not the dominant kernel: no profiling events)
+  const bool prof = !L->tiles4;
   if (L->fuse == 4) {  // one kernel with the boundary rules for every tile
     e = prof_begin(L, st, pidx);
     if (e == hipSuccess)
@@ -938,7 +977,7 @@ static hipError_t launch_pass(gg_lattice *L, int dir, int dt, hipStream_t st) {
   }
   auto run = [&](bool seg, const Tile *list, int n, hipStream_t s) {
     // the segment list holds 2-row tiles
-    return L->fuse == 3 ? launch_tile2(L->storage, L->pairs, seg, seg ? 2 : L->strip_h, L->d_desc,
+    return L->fuse >= 3 ? launch_tile2(L->storage, L->pairs, seg, seg ? 2 : L->strip_h, L->d_desc,
                                        list, n, dir, dt, s, press)
                         : launch_step2(L->storage, L->pairs, seg, L->d_desc, list, n, dir, dt, s);
   };
@@ -950,8 +989,33 @@ static hipError_t launch_pass(gg_lattice *L, int dir, int dt, hipStream_t st) {
   } else if (L->n_seg_strips > 0) {
     e = run(true, L->d_seg_strips, L->n_seg_strips, st);
   }
-  if (e == hipSuccess) e = prof_begin(L, st, pidx);
+  if (e == hipSuccess && prof) e = prof_begin(L, st, pidx);
   if (e == hipSuccess) e = run(false, L->d_strips, L->n_strips, st);
+  if (e == hipSuccess) e = prof_end(L, st, pidx, 0);
+  if (fork && e == hipSuccess) e = hipStreamWaitEvent(st, L->ev_join, 0);
+  return e;
+}
+
+// One four-step pass: the boundary tiles on the side stream as in
+// launch_pass.
+static hipError_t launch_pass4(gg_lattice *L, int dir, int dt, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  const bool fork = L->n_seg_strips4 > 0 && L->n_strips4 > 0;
+  if (fork) {
+    e = hipEventRecord(L->ev_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(L->side, L->ev_fork, 0);
+    if (e == hipSuccess)
+      e = launch_tile4(L->storage, L->pairs, true, L->d_desc, L->d_seg_strips4, L->n_seg_strips4,
+                       dir, dt, L->side);
+    if (e == hipSuccess) e = hipEventRecord(L->ev_join, L->side);
+  } else if (L->n_seg_strips4 > 0) {
+    e = launch_tile4(L->storage, L->pairs, true, L->d_desc, L->d_seg_strips4, L->n_seg_strips4, dir,
+                     dt, st);
+  }
+  long pidx = -1;
+  if (e == hipSuccess) e = prof_begin(L, st, pidx);
+  if (e == hipSuccess)
+    e = launch_tile4(L->storage, L->pairs, false, L->d_desc, L->d_strips4, L->n_strips4, dir, dt, st);
   if (e == hipSuccess) e = prof_end(L, st, pidx, 0);
   if (fork && e == hipSuccess) e = hipStreamWaitEvent(st, L->ev_join, 0);
   return e;
@@ -959,7 +1023,15 @@ static hipError_t launch_pass(gg_lattice *L, int dir, int dt, hipStream_t st) {
 
 static hipError_t launch_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t st) {
   hipError_t e = hipSuccess;
-  if (pass_ok(L) && !(t0 & 1) && n % 4 == 0) {
+  if (L->tiles4 && pass4_ok(L) && !(t0 & 1) && n % 4 == 0) {
+    // four-step passes in pairs (ending in the first plane set), then the
+    // last four steps of a run of 8k + 4 in two two-step passes
+    const int64_t p4 = n / 8 * 2;
+    for (int64_t k = 0; k < p4 && e == hipSuccess; ++k)
+      e = launch_pass4(L, (int)(k & 1), (int)(4 * k), st);
+    for (int64_t k = 0; k < (n % 8) / 2 && e == hipSuccess; ++k)
+      e = launch_pass(L, (int)(k & 1), (int)(4 * p4 + 2 * k), st);
+  } else if (pass_ok(L) && !(t0 & 1) && n % 4 == 0) {
     // with pressure segments the pass rescales the boundary nodes between
     // its two steps; the state it leaves is rescaled by the kernel after
     // it, or, in the one-kernel form, by the next pass as it loads it (bit
@@ -1160,7 +1232,8 @@ gg_status gg_step_profile(gg_lattice *L, int64_t n, gg_profile *out) {
     } else if (kind == 3) {
       out->n_graph += 1;
       out->ms_graph += x;
-      if (pass_ok(L)) out->graph_passes += L->graph_chunk / 2;
+      if (L->tiles4 && pass4_ok(L)) out->graph_passes += L->graph_chunk / 4;
+      else if (pass_ok(L)) out->graph_passes += L->graph_chunk / 2;
       else out->graph_singles += L->graph_chunk;
     } else {
       out->n_single[kind - 1] += 1;
@@ -1172,10 +1245,19 @@ gg_status gg_step_profile(gg_lattice *L, int64_t n, gg_profile *out) {
   out->n_monitor = L->mon_count - mon0;
   out->fuse = pass_ok(L) ? L->fuse : 1;
   out->rows = L->strip_h;
+  out->steps_per_pass = 2;
   out->pass_fluid = L->fuse == 4 ? L->n_fluid : L->strips_fluid;
   out->pass_side_fluid = L->fuse == 4 ? 0 : L->seg_strips_fluid;
   out->pass_tiles = L->n_strips;
   out->pass_side_tiles = L->fuse == 4 ? 0 : L->n_seg_strips;
+  if (L->tiles4 && pass4_ok(L)) {  // the four-step pass's interior kernel
+    out->rows = 6;
+    out->steps_per_pass = 4;
+    out->pass_fluid = L->strips4_fluid;
+    out->pass_side_fluid = L->seg_strips4_fluid;
+    out->pass_tiles = L->n_strips4;
+    out->pass_side_tiles = L->n_seg_strips4;
+  }
   return st;
 }
 
@@ -1376,8 +1458,9 @@ gg_status gg_set_launch(gg_lattice *L, int32_t tile_x, int32_t tile_y, int32_t g
   GG_HIP(hipStreamSynchronize(L->stream));
   L->tile_x = tile_x;
   L->tile_y = tile_y;
-  // even (a multiple of 4 with the two-step pass): replays keep the parity
-  const int q = L->fuse >= 2 ? 4 : 2;
+  // even (a multiple of 4 with the two-step pass, of 8 with the four-step
+  // pass): replays keep the parity and run whole passes
+  const int q = L->fuse == 5 ? 8 : L->fuse >= 2 ? 4 : 2;
   L->graph_chunk = (graph_chunk + q - 1) / q * q;
   gg_drop_cde_graphs(L);
   return gg_rebuild_tiles(L);
@@ -1385,7 +1468,7 @@ gg_status gg_set_launch(gg_lattice *L, int32_t tile_x, int32_t tile_y, int32_t g
 
 gg_status gg_set_two_step(gg_lattice *L, int32_t fuse, int32_t strip_h) {
   if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
-  if (fuse < 1 || fuse > 4) return fail(GG_ERR_ARG, "fuse must be 1, 2, 3 or 4");
+  if (fuse < 1 || fuse > 5) return fail(GG_ERR_ARG, "fuse must be 1, 2, 3, 4 or 5");
   if (fuse == 2 && (strip_h < 1 || strip_h > 4096))
     return fail(GG_ERR_ARG, "strips walk 1..4096 rows");
   if (fuse == 2 && !L->strip_flux_ok)
@@ -1410,7 +1493,7 @@ gg_status gg_set_two_step(gg_lattice *L, int32_t fuse, int32_t strip_h) {
   }
   L->fuse = fuse;
   if (fuse >= 2) L->strip_h = strip_h;
-  const int q = fuse >= 2 ? 4 : 2;
+  const int q = fuse == 5 ? 8 : fuse >= 2 ? 4 : 2;
   L->graph_chunk = (L->graph_chunk + q - 1) / q * q;
   gg_drop_cde_graphs(L);
   gg_status st = gg_upload_desc(L);
@@ -1523,7 +1606,7 @@ gg_status gg_adjoint(gg_lattice *L, int64_t n, int64_t s, const double *weight,
   // (and, where the lattice steps in row-parallel two-step passes, its own
   // second plane set: the recomputation then runs in passes too)
   void *scr_pop_b = nullptr;
-  const bool rec_pass = pass_ok(L) && (L->fuse == 3 || L->fuse == 4) &&
+  const bool rec_pass = pass_ok(L) && L->fuse >= 3 &&
                         B.alloc(&scr_pop_b, pop_bytes) == hipSuccess;
   (void)hipGetLastError();
   LatDesc hs = L->h;
@@ -2421,7 +2504,8 @@ gg_status gg_set_wall_scheme(gg_lattice *L, int32_t scheme) {
   GG_HIP(hipStreamSynchronize(L->stream));
   L->wall_scheme = scheme;
   L->wall_dirty = true;
-  return GG_OK;
+  // (the four-step pass's lists follow the wall scheme)
+  return L->tiles4 != pass4_ok(L) ? gg_rebuild_tiles(L) : GG_OK;
 }
 
 gg_status gg_permute_tiles(gg_lattice *L, uint64_t seed) {

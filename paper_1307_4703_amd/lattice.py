@@ -187,8 +187,10 @@ class Lattice:
     def set_two_step(self, fuse: int = 3, strip_h: int = 6) -> None:
         """Two steps per pass over memory (fuse = 2: walking strips of
         strip_h rows; 3, the default: row-parallel tiles of 6 or 14 rows with
-        the boundary kernel apart; 4: the same in one kernel) or single steps
-        (fuse = 1); include/gg.h, gg_set_two_step."""
+        the boundary kernel apart; 4: the same in one kernel), four steps per
+        pass in runs of 8k steps (fuse = 5, FP32 and FP16 storage; other
+        runs as fuse = 3) or single steps (fuse = 1); include/gg.h,
+        gg_set_two_step."""
         A.call("gg_set_two_step", self._h, int(fuse), int(strip_h))
 
     def set_layout(self, layout: str) -> None:
@@ -233,7 +235,8 @@ class Lattice:
                 "n_single": list(p.n_single), "ms_single": list(p.ms_single),
                 "n_monitor": p.n_monitor, "pass_fluid": p.pass_fluid,
                 "pass_side_fluid": p.pass_side_fluid, "pass_tiles": p.pass_tiles,
-                "pass_side_tiles": p.pass_side_tiles, "fuse": p.fuse, "rows": p.rows}
+                "pass_side_tiles": p.pass_side_tiles, "fuse": p.fuse, "rows": p.rows,
+                "steps_per_pass": p.steps_per_pass}
 
     def set_monitor(self, every: int) -> None:
         """FP64 diagnostics reduced on the GPU after every `every` steps of

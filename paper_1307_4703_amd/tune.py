@@ -3,7 +3,7 @@
 Candidates are tile shapes (tile_x x tile_y nodes per work-group) of the
 single steps, the forms of the two-step pass (walking strips, row-parallel
 tiles with the boundary rules in a kernel of their own or in the one
-kernel), for batches persistent grid sizes, and for the compound-only step
+kernel) and the four-step pass, for batches persistent grid sizes, and for the compound-only step
 the row count of its two-step tiles. Each candidate is timed
 on the GPU with HIP events over a few graph-replayed steps (the lattices
 advance while being tuned, so tune before the run or on a copy). Results are cached in a JSON
@@ -23,7 +23,8 @@ TILES: Tuple[Tuple[int, int], ...] = ((64, 4), (32, 8), (64, 2), (128, 2), (128,
                                       (64, 8), (128, 4), (256, 1), (32, 4), (16, 8))
 PERSIST: Tuple[int, ...] = (0, 2048, 4096)
 # (fuse, rows) of gg_set_two_step; fuse 1 is the single-step path
-TWO_STEP: Tuple[Tuple[int, int], ...] = ((3, 6), (3, 14), (4, 6), (4, 14), (2, 8), (2, 16))
+TWO_STEP: Tuple[Tuple[int, int], ...] = ((3, 6), (3, 14), (4, 6), (4, 14), (5, 6), (2, 8),
+                                         (2, 16))
 
 
 def cache_path() -> str:

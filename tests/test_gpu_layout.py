@@ -36,7 +36,7 @@ def _same(a, b):
         assert db[k] == pytest.approx(da[k], rel=1e-12, abs=1e-12), k
 
 
-FORMS = [(1, 6), (2, 5), (3, 6), (3, 14), (4, 6), (4, 14)]
+FORMS = [(1, 6), (2, 5), (3, 6), (3, 14), (4, 6), (4, 14), (5, 6)]
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
@@ -55,7 +55,7 @@ def test_both_layouts_give_the_same_steps(storage, form):
     _same(a, b)
 
 
-@pytest.mark.parametrize("form", [(1, 6), (3, 6), (4, 14)])
+@pytest.mark.parametrize("form", [(1, 6), (3, 6), (4, 14), (5, 6)])
 @pytest.mark.parametrize("periodic", [(True, False), (False, True), (True, True)])
 def test_periodic_lattices(periodic, form):
     """Obstacles everywhere, 133x71, periodic axes (the neighbours wrap, so

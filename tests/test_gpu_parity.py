@@ -123,10 +123,13 @@ def test_launch_shape_and_graphs_bitwise_identical(tile, chunk):
     assert np.array_equal(f0, f1) and np.array_equal(g0, g1)
 
 
+@pytest.mark.parametrize("form", [None, (5, 6)])
 @pytest.mark.parametrize("storage,tol", [("f32", F32_TOL), ("f16", F16_TOL)])
-def test_reduced_precision_against_f64_oracle(storage, tol):
+def test_reduced_precision_against_f64_oracle(storage, tol, form):
+    """300 steps across valve switches; form (5, 6): four-step passes in
+    graph replays and plain launches, two-step passes for the last four."""
     wl = _ragged_gg(half_period=50, storage=storage)
-    lat, o = _run(wl, storage, 300, seed=4)
+    lat, o = _run(wl, storage, 300, seed=4, chunk=None if form is None else 64, form=form)
     err = field_errors(lat, o, wl.mask == 0)
     log(f"{storage} errors {err}")
     for k, v in tol.items():

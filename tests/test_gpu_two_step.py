@@ -3,7 +3,10 @@ of 62 columns walked row by row, or row-parallel tiles exchanging through
 LDS; a one-node halo collided once more) must be bitwise the state the
 single-step kernels give, for every storage type, boundary kind,
 periodicity, strip height and schedule phase; boundary fluxes agree to
-FP64 rounding (their atomics add in another order)."""
+FP64 rounding (their atomics add in another order). The same for the
+four-step pass (fuse 5: 58 x 6 tiles with a three-node halo, runs of 8k
+steps; other runs in two-step passes), which FP64 lattices and lattices
+with pressure segments decline for the two-step pass."""
 import numpy as np
 import pytest
 
@@ -37,7 +40,7 @@ def _same_state(one, two, steps):
         assert db[k] == pytest.approx(da[k], rel=1e-12, abs=1e-12), k
 
 
-MODES = [(2, 1), (2, 5), (2, 16), (3, 6), (3, 14), (4, 6), (4, 14)]
+MODES = [(2, 1), (2, 5), (2, 16), (3, 6), (3, 14), (4, 6), (4, 14), (5, 6), (5, 14)]
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
@@ -54,35 +57,41 @@ def test_gradient_generator_valves(storage, mode, strip_h):
     _same_state(one, two, 40)
 
 
-@pytest.mark.parametrize("mode,strip_h", [(2, 7), (3, 6), (4, 14)])
+@pytest.mark.parametrize("mode,strip_h", [(2, 7), (3, 6), (4, 14), (5, 6)])
 @pytest.mark.parametrize("periodic", [(True, False), (False, True), (True, True), (False, False)])
 def test_random_masks_periodic(periodic, mode, strip_h):
-    """Obstacles everywhere, 133x71 (not a multiple of the 62-column strip),
-    every combination of periodic axes."""
+    """Obstacles everywhere, 133x71 (not a multiple of the 62- or 58-column
+    tile), every combination of periodic axes (FP32 for the four-step
+    pass)."""
     mask = W.random_mask(133, 71, seed=7, periodic=periodic)
     wl = W.Workload("random", mask, tau_f=0.7, D=0.03, periodic=periodic)
     log(f"two-step vs single, random mask, periodic {periodic}, mode {mode}")
-    one, two = _pair(wl, "f64", 3, strip_h, mode=mode)
-    one.step(36)
-    two.step(36)
-    _same_state(one, two, 36)
+    one, two = _pair(wl, "f32" if mode == 5 else "f64", 3, strip_h, mode=mode)
+    one.step(40)
+    two.step(40)
+    _same_state(one, two, 40)
 
 
-@pytest.mark.parametrize("mode,strip_h", [(2, 4), (3, 14)])
-def test_narrow_periodic_lattice(mode, strip_h):
+@pytest.mark.parametrize("mode,strip_h", [(2, 4), (3, 14), (5, 6)])
+@pytest.mark.parametrize("ny", [24, 5])
+def test_narrow_periodic_lattice(mode, strip_h, ny):
     """A periodic lattice narrower than one strip: the halo lanes wrap onto
-    the strip's own columns."""
-    mask = np.zeros((24, 20), np.uint8)
-    mask[0, :] = 1
-    mask[-1, :] = 1
-    wl = W.Workload("narrow", mask, tau_f=0.9, D=0.02, periodic=(True, False))
+    the strip's own columns (and, periodic in y with 5 rows, the four-step
+    tile's halo rows onto its own rows)."""
+    mask = np.zeros((ny, 20), np.uint8)
+    if ny > 5:
+        mask[0, :] = 1
+        mask[-1, :] = 1
+    else:
+        mask[2, 5:9] = 1
+    wl = W.Workload("narrow", mask, tau_f=0.9, D=0.02, periodic=(True, ny <= 5))
     one, two = _pair(wl, "f32", 4, strip_h, mode=mode)
     one.step(24)
     two.step(24)
     _same_state(one, two, 24)
 
 
-@pytest.mark.parametrize("mode,strip_h", [(2, 16), (3, 6), (4, 6)])
+@pytest.mark.parametrize("mode,strip_h", [(2, 16), (3, 6), (4, 6), (5, 6)])
 def test_source_decay_d2q4_and_graphs(mode, strip_h):
     """w0 = 0 (D2Q4), decay, a source patch, graph-replayed passes."""
     wl = W.gradient_generator(nx=300, ny=150, half_period=11, storage="f32", w0=0.0)
@@ -96,15 +105,32 @@ def test_source_decay_d2q4_and_graphs(mode, strip_h):
     _same_state(one, two, 50)
 
 
-@pytest.mark.parametrize("mode,strip_h", [(2, 16), (3, 14), (4, 6)])
-def test_straight_channel_inlet_outlet(mode, strip_h):
+@pytest.mark.parametrize("mode,strip_h,storage", [(2, 16, "f64"), (3, 14, "f64"), (4, 6, "f64"),
+                                                   (5, 6, "f32"), (5, 6, "f16")])
+def test_straight_channel_inlet_outlet(mode, strip_h, storage):
     """Velocity inlet and pressure outlet on vertical segments (the strip's
     halo lanes sit on the ghost columns)."""
-    wl = W.straight_channel(storage="f64")
-    one, two = _pair(wl, "f64", 0, strip_h, mode=mode)
+    wl = W.straight_channel(storage=storage)
+    one, two = _pair(wl, storage, 0, strip_h, mode=mode)
     one.step(120)
     two.step(120)
     _same_state(one, two, 120)
+
+
+@pytest.mark.parametrize("storage,steps_per_pass", [("f32", 4), ("f16", 4), ("f64", 2)])
+def test_four_step_pass_runs_where_it_applies(storage, steps_per_pass):
+    """fuse 5 runs four-step passes on FP32 and FP16 lattices (the profile
+    times their interior kernel) and two-step passes on FP64 ones; a
+    2048x1024 gradient generator over graph replays of 64 steps and a run
+    of 8k + 4 plain-launched steps is still bitwise the single steps'."""
+    wl = W.gradient_generator(nx=2048, ny=1024, half_period=50, storage=storage)
+    one, two = _pair(wl, storage, 5, 6, chunk=64, mode=5)
+    p = two.step_profile(64)
+    assert p["steps_per_pass"] == steps_per_pass and p["fuse"] == 5
+    assert p["graph_passes"] == 64 // steps_per_pass and p["n_graph"] == 1
+    two.step(140)  # two replays, then 8 + 4 steps: two four-step and two two-step passes
+    one.step(204)
+    _same_state(one, two, 204)
 
 
 @pytest.mark.parametrize("mode,strip_h", [(2, 16), (3, 6)])

@@ -159,6 +159,13 @@ def test_bench_roofline_pass_and_single():
             "pass_fluid": 1000000, "fuse": 3}
     out = bench.roofline(_fake_run(1100000, 20, 2.0, prof), "f16", traffic=60000000)
     assert out["traffic_per_algorithmic_single_trip"] == pytest.approx(60 / 57, rel=1e-3)
+    # the four-step pass: four updates of its tiles' nodes per launch, and
+    # one trip through memory for them
+    prof = dict(prof, steps_per_pass=4, fuse=5)
+    out = bench.roofline(_fake_run(1100000, 20, 2.0, prof), "f32", traffic=120000000)
+    assert out["algorithmic_bytes_per_launch"] == 4 * 1000000 * 113
+    assert out["kernel"].startswith("four-step")
+    assert out["traffic_per_algorithmic_single_trip"] == pytest.approx(120 / 113, rel=1e-3)
 
 
 def test_bench_refuses_several_gpus():
