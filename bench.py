@@ -77,6 +77,11 @@ FORMS = {"gg2048_f32": (5, 6), "gg2048_f16": (4, 6), "gg8192_f16": (3, 6),
          "gg8192_f16_pe2000": (3, 6), "gg8192_f32": (5, 6), "allfluid8192_f32": (5, 6),
          "allfluid8192_f16": (3, 6), "shard8192x512_f32": (5, 6),
          "allfluid8192_f64": (3, 14), "gg2048_f64": (3, 6), "straight_f64": (4, 6)}
+# the adjoint leg's lattice (2048 x 1024 FP32): the one-kernel two-step
+# form, whose taped recomputation passes are one kernel as well (the
+# four-step pass has no taped form; its lattices recompute in the two
+# kernels of fuse 3)
+ADJOINT_FORM = (4, 6)
 
 
 def kernel_hash():
@@ -142,10 +147,8 @@ def time_lattice(name, steps, warmup, tile, chunk, form=None, monitor_every=1024
     from paper_1307_4703_amd import tune as T
     wl = workload(name)
     lat = Lattice.from_workload(wl)
-    # graph chunk of the timed region: whole replays inside it
-    chunk_t = min(chunk, steps // 4 * 4) if chunk > 0 else 0
+    chunk_t = 0
     try:
-        lat.set_launch(tile[0], tile[1], chunk_t)
         nf = lat.info()["n_fluid"]
         if form == "tune":
             res = T.tune_lattice(lat, steps=64 if nf > 1e7 else 256, graph_chunk=chunk,
@@ -158,6 +161,11 @@ def time_lattice(name, steps, warmup, tile, chunk, form=None, monitor_every=1024
             form = {"tile": list(tile), **form}
         lat.set_two_step(form["fuse"], form["rows"])
         form["layout"] = lat.layout
+        # graph chunk of the timed region: whole replays inside it (a
+        # multiple of 4 steps, of 8 with the four-step pass)
+        q = 8 if form["fuse"] == 5 else 4
+        chunk_t = min(chunk, steps // q * q) if chunk > 0 else 0
+        lat.set_launch(form["tile"][0], form["tile"][1], chunk_t)
         log(f"{wl.name}: {wl.nx}x{wl.ny}, {nf} fluid nodes, storage {wl.storage}, "
             f"form {form}; warmup {warmup}")
         lat.step(warmup)
@@ -293,7 +301,7 @@ def adjoint_bench(steps=20000, chunk=64):
     lat = Lattice.from_workload(wl)
     try:
         lat.set_launch(64, 4, chunk)
-        lat.set_two_step(*FORMS["gg2048_f32"])
+        lat.set_two_step(*ADJOINT_FORM)
         lat.adjoint(64, weight, target, r_box=r_box)  # kernels loaded, graphs captured
         lat.init(**(wl.init or {}))
         torch.cuda.synchronize()
@@ -533,7 +541,7 @@ def counters_leg(leg, tile, chunk_unused=0):
         weight, target, r_box = W.chamber_misfit_setup(wl)
         lat = Lattice.from_workload(wl)
         lat.set_launch(64, 4, 0)
-        lat.set_two_step(*FORMS["gg2048_f32"])
+        lat.set_two_step(*ADJOINT_FORM)
         lat.adjoint(400, weight, target, r_box=r_box, ckpt_every=20)
         nf = lat.info()["n_fluid"]
         lat.close()
@@ -761,7 +769,9 @@ def main(argv=None):
                    "valve_half_period": wl.schedule[0].duration if wl.schedule else None,
                    "launch_form": r["form"],
                    "launches": {"pass_kernel": p["n_pass"] + p["graph_passes"],
+                                "steps_per_pass": p["steps_per_pass"],
                                 "pass_kernel_in_graph_replays": p["graph_passes"],
+                                "two_step_pass_beside_four_step": p["n_pass2"],
                                 "graph_replays": p["n_graph"],
                                 "single_even": p["n_single"][0],
                                 "single_odd": p["n_single"][1],

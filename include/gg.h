@@ -551,7 +551,8 @@ gg_status gg_monitor_read(gg_lattice *lat, gg_diag *out, int64_t *count);
  * pass (with fuse 2 and 3 the boundary tiles run in a second kernel beside
  * it on a side stream; with fuse 4 it is the pass's only kernel), of each
  * four-step pass where fuse 5 runs them (two-step passes of leftover steps
- * are then not timed), or the step kernel of each single step. */
+ * are then counted apart, in n_pass2), or the step kernel of each single
+ * step. */
 typedef struct gg_profile {
   double ms_total;          /* HIP events around the whole call */
   int64_t n_pass;           /* plain launches of the pass's dominant kernel */
@@ -571,6 +572,10 @@ typedef struct gg_profile {
                                rows + 2 wavefronts each, 8 * ceil(tiles / 8)
                                work-groups launched) */
   int64_t pass_side_tiles;  /* tiles of the side kernel (2 rows each) */
+  int64_t n_pass2;          /* with the four-step pass: plain launches of the
+                               two-step passes of leftover steps (their
+                               interior kernel), and */
+  double ms_pass2;          /* their summed duration */
   int32_t fuse, rows;       /* launch form used (fuse 1: single steps only) */
   int32_t steps_per_pass;   /* 2, or 4 where the four-step pass runs (fuse
                                5; its tiles are then the pass_ fields') */

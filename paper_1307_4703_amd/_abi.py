@@ -80,6 +80,7 @@ class gg_profile(ctypes.Structure):
                 ("ms_single", ctypes.c_double * 2), ("n_monitor", ctypes.c_int64),
                 ("pass_fluid", ctypes.c_int64), ("pass_side_fluid", ctypes.c_int64),
                 ("pass_tiles", ctypes.c_int64), ("pass_side_tiles", ctypes.c_int64),
+                ("n_pass2", ctypes.c_int64), ("ms_pass2", ctypes.c_double),
                 ("fuse", ctypes.c_int32), ("rows", ctypes.c_int32),
                 ("steps_per_pass", ctypes.c_int32)]
 

@@ -127,7 +127,8 @@ struct gg_lattice {
   int64_t mon_every = 0, mon_t0 = 0, mon_last_t = -1, mon_count = 0;
   double *d_mon = nullptr;
   // profiling (gg_step_profile): plain launches with an event pair around
-  // every launch of the dominant kernel; kind 0 pass, 1 even step, 2 odd step
+  // every launch of the dominant kernel; kind 0 pass, 1 even step, 2 odd
+  // step, 3 graph replay, 4 two-step pass beside the four-step pass
   bool prof = false;
   std::vector<hipEvent_t> prof_ev;
   std::vector<int8_t> prof_kind;

@@ -965,8 +965,8 @@ static hipError_t launch_pass(gg_lattice *L, int dir, int dt, hipStream_t st) {
   const bool press = L->n_press > 0;  // (fuse 3, 4 and 5 only)
   long pidx = -1;
   // (with the four-step pass on, the two-step passes of leftover steps are
-  // not the dominant kernel: no profiling events)
-  const bool prof = !L->tiles4;
+  // not the dominant kernel: profiled apart, kind 4)
+  const int kind = L->tiles4 && pass4_ok(L) ? 4 : 0;
   if (L->fuse == 4) {  // one kernel with the boundary rules for every tile
     e = prof_begin(L, st, pidx);
     if (e == hipSuccess)
@@ -989,9 +989,9 @@ static hipError_t launch_pass(gg_lattice *L, int dir, int dt, hipStream_t st) {
   } else if (L->n_seg_strips > 0) {
     e = run(true, L->d_seg_strips, L->n_seg_strips, st);
   }
-  if (e == hipSuccess && prof) e = prof_begin(L, st, pidx);
+  if (e == hipSuccess) e = prof_begin(L, st, pidx);
   if (e == hipSuccess) e = run(false, L->d_strips, L->n_strips, st);
-  if (e == hipSuccess) e = prof_end(L, st, pidx, 0);
+  if (e == hipSuccess) e = prof_end(L, st, pidx, kind);
   if (fork && e == hipSuccess) e = hipStreamWaitEvent(st, L->ev_join, 0);
   return e;
 }
@@ -1229,6 +1229,9 @@ gg_status gg_step_profile(gg_lattice *L, int64_t n, gg_profile *out) {
     if (kind == 0) {
       out->n_pass += 1;
       out->ms_pass += x;
+    } else if (kind == 4) {
+      out->n_pass2 += 1;
+      out->ms_pass2 += x;
     } else if (kind == 3) {
       out->n_graph += 1;
       out->ms_graph += x;

@@ -236,7 +236,8 @@ class Lattice:
                 "n_monitor": p.n_monitor, "pass_fluid": p.pass_fluid,
                 "pass_side_fluid": p.pass_side_fluid, "pass_tiles": p.pass_tiles,
                 "pass_side_tiles": p.pass_side_tiles, "fuse": p.fuse, "rows": p.rows,
-                "steps_per_pass": p.steps_per_pass}
+                "steps_per_pass": p.steps_per_pass, "n_pass2": p.n_pass2,
+                "ms_pass2": p.ms_pass2}
 
     def set_monitor(self, every: int) -> None:
         """FP64 diagnostics reduced on the GPU after every `every` steps of

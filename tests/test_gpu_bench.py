@@ -31,13 +31,20 @@ def test_bench_line(capsys, argv, workload):
     assert line["config"]["workload"] == workload
     assert line["value"] > 0 and line["ms_per_step"] > 0
     launches = line["config"]["launches"]
-    # every timed step is a pass step (two per launch) or a single step,
-    # plain or inside a graph replay of the timed steps rounded down to 4
-    assert (2 * launches["pass_kernel"] + launches["single_even"] + launches["single_odd"] +
+    # every timed step is a step of a pass (two per launch, four with the
+    # four-step pass, whose leftover runs of four steps go in two-step
+    # passes counted apart) or a single step, plain or inside a graph
+    # replay of the timed steps rounded down to 4 (to 8 with the four-step
+    # pass)
+    spp = launches["steps_per_pass"]
+    q = 2 * spp
+    assert (spp * launches["pass_kernel"] + 2 * launches["two_step_pass_beside_four_step"] +
+            launches["single_even"] + launches["single_odd"] +
             launches["single_in_graph_replays"]) == steps
-    assert launches["pass_kernel"] == steps // 4 * 2
-    assert launches["pass_kernel_in_graph_replays"] == steps // 4 * 2
-    assert line["config"]["graph_chunk"] == steps // 4 * 4
+    assert launches["pass_kernel"] == steps // q * 2
+    assert launches["pass_kernel_in_graph_replays"] == steps // q * 2
+    assert line["config"]["graph_chunk"] == steps // q * q
+    assert spp == (4 if workload == "gradient_generator_2048x1024" else 2)
     assert line["config"]["warmup_steps_run"] % 4 == 0
     rf = line["roofline"]
     assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
