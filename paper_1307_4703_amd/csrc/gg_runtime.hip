@@ -373,6 +373,15 @@ gg_status gg_rebuild_tiles(gg_lattice *L) {
   if (L->tiles4) {
     std::vector<Tile> m4, s4;
     build_strips(L, 6, 0, true, m4, s4, 2, 58);
+    // in eight vertical stripes, each walked band by band: an XCD takes a
+    // contiguous run of the list, and the tiles above and below a tile
+    // (which share its three halo rows, half of what it loads) then run
+    // soon after it on the same L2; a whole band of the lattice with its
+    // halo rows need not fit in one XCD's L2
+    std::stable_sort(m4.begin(), m4.end(), [&](const Tile &a, const Tile &b) {
+      const int sa = (int)((int64_t)a.x0 * 8 / L->nx), sb = (int)((int64_t)b.x0 * 8 / L->nx);
+      return sa != sb ? sa < sb : (a.y0 != b.y0 ? a.y0 < b.y0 : a.x0 < b.x0);
+    });
     L->n_strips4 = (int)m4.size();
     L->n_seg_strips4 = (int)s4.size();
     L->strips4_fluid = owned_fluid(L, m4, 58);
