@@ -410,7 +410,8 @@ gg_status gg_info(const gg_lattice *lat, int64_t *n_fluid, int64_t *n_tiles,
  * then ignored): each candidate (single steps over tiles of 64 x 4, 32 x 8
  * or 128 x 2 nodes; when every member has its second plane set and all sit
  * at steps of one parity, two-step passes with 6- or 14-row tiles and the
- * boundary tiles apart, or 6- or 14-row tiles in one kernel) advances the members
+ * boundary tiles apart, or 6- or 14-row tiles in one kernel, and with FP32
+ * or FP16 storage four-step passes) advances the members
  * 20 steps, 16 of them timed with HIP events on their stream, and the
  * fastest is kept (gg_batch_form reports it). The members' states, step
  * counts and boundary fluxes are copied aside on the device (hipMalloc of
@@ -431,7 +432,11 @@ gg_status gg_batch_form(const gg_batch *batch, int32_t *tile_x, int32_t *tile_y,
 /* Two-step pass for the batch (see gg_set_two_step): fuse 3 or 4 with
  * tiles of rows = 6 or 14 rows, over the members' tiles in one flat list
  * (fuse 3: the boundary tiles of all members in a second list on a second
- * stream); fuse = 1 goes back to single steps. Every member must have its
+ * stream); fuse 5: four-step passes over the members' 58 x 6 tiles (the
+ * boundary tiles apart), runs of 8k + 4 steps ending in two two-step
+ * passes of fuse 3's form with `rows` rows (FP32 and FP16 storage, else
+ * GG_ERR_ARG, as for periodic axes under 4 nodes); fuse = 1 goes back to
+ * single steps. Every member must have its
  * second plane set (fuse >= 2 on the member, the default) and all members
  * must sit at steps of one parity (else GG_ERR_STATE). The states advance
  * exactly as with single steps. */

@@ -1780,10 +1780,14 @@ struct gg_batch {
   std::vector<uint8_t> pop_b_created;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  // two-step pass over all members (fuse 3 or 4, tiles of `rows` rows)
+  // two-step pass over all members (fuse 3 or 4, tiles of `rows` rows);
+  // fuse 5: four-step passes over the members' 58 x 6 tiles (the lists
+  // with 4), two-step passes as fuse 3 for the last four steps of 8k + 4
   int fuse = 1, rows = 6;
   Tile *d_strips = nullptr, *d_seg_strips = nullptr;
   int n_strips = 0, n_seg_strips = 0;
+  Tile *d_strips4 = nullptr, *d_seg_strips4 = nullptr;
+  int n_strips4 = 0, n_seg_strips4 = 0;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
@@ -1796,6 +1800,8 @@ static void batch_free(gg_batch *B) {
     if (B->d_tiles[g]) (void)hipFree(B->d_tiles[g]);
   if (B->d_strips) (void)hipFree(B->d_strips);
   if (B->d_seg_strips) (void)hipFree(B->d_seg_strips);
+  if (B->d_strips4) (void)hipFree(B->d_strips4);
+  if (B->d_seg_strips4) (void)hipFree(B->d_seg_strips4);
   if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
   if (B->side) (void)hipStreamDestroy(B->side);
   if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
@@ -1826,30 +1832,41 @@ static gg_status batch_check_members(const gg_batch *B) {
 static hipError_t batch_launch(gg_batch *B, int64_t s0, int64_t n, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (batch_passes(B, s0, n)) {
-    const bool fork = B->fuse == 3 && B->n_seg_strips > 0 && B->n_strips > 0;
-    for (int64_t k = 0; k < n / 2 && e == hipSuccess; ++k) {
-      const int dir = (int)(k & 1), dt = (int)(2 * k);
-      if (B->fuse == 4) {
-        e = launch_tile2(B->storage, B->pairs, true, B->rows, B->d_descs, B->d_strips, B->n_strips, dir, dt,
-                         st);
-        continue;
-      }
+    // one pass over all members: the boundary tiles' kernel on the side
+    // stream (forked and joined) when both lists hold tiles
+    auto pass = [&](bool four, int dir, int dt) -> hipError_t {
+      const Tile *main = four ? B->d_strips4 : B->d_strips;
+      const Tile *segl = four ? B->d_seg_strips4 : B->d_seg_strips;
+      const int nm = four ? B->n_strips4 : B->n_strips;
+      const int ns = four ? B->n_seg_strips4 : B->n_seg_strips;
+      // (the boundary list holds 2-row tiles; fuse 4's one list, run with
+      // the boundary rules, holds tiles of `rows` rows)
+      auto run = [&](bool seg, bool seg_list, const Tile *list, int nl, hipStream_t s) {
+        return four ? launch_tile4(B->storage, B->pairs, seg, B->d_descs, list, nl, dir, dt, s)
+                    : launch_tile2(B->storage, B->pairs, seg, seg_list ? 2 : B->rows, B->d_descs, list,
+                                   nl, dir, dt, s);
+      };
+      if (B->fuse == 4) return run(true, false, main, nm, st);
+      const bool fork = ns > 0 && nm > 0;
+      hipError_t r = hipSuccess;
       if (fork) {
-        e = hipEventRecord(B->ev_fork, st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(B->side, B->ev_fork, 0);
-        if (e == hipSuccess)
-          e = launch_tile2(B->storage, B->pairs, true, 2, B->d_descs, B->d_seg_strips, B->n_seg_strips, dir,
-                           dt, B->side);
-        if (e == hipSuccess) e = hipEventRecord(B->ev_join, B->side);
-      } else if (B->n_seg_strips > 0) {
-        e = launch_tile2(B->storage, B->pairs, true, 2, B->d_descs, B->d_seg_strips, B->n_seg_strips, dir,
-                         dt, st);
+        r = hipEventRecord(B->ev_fork, st);
+        if (r == hipSuccess) r = hipStreamWaitEvent(B->side, B->ev_fork, 0);
+        if (r == hipSuccess) r = run(true, true, segl, ns, B->side);
+        if (r == hipSuccess) r = hipEventRecord(B->ev_join, B->side);
+      } else if (ns > 0) {
+        r = run(true, true, segl, ns, st);
       }
-      if (e == hipSuccess)
-        e = launch_tile2(B->storage, B->pairs, false, B->rows, B->d_descs, B->d_strips, B->n_strips, dir,
-                         dt, st);
-      if (fork && e == hipSuccess) e = hipStreamWaitEvent(st, B->ev_join, 0);
-    }
+      if (r == hipSuccess) r = run(false, false, main, nm, st);
+      if (fork && r == hipSuccess) r = hipStreamWaitEvent(st, B->ev_join, 0);
+      return r;
+    };
+    // fuse 5: four-step passes in pairs, then the last four steps of a
+    // run of 8k + 4 in two two-step passes
+    const int64_t p4 = B->fuse == 5 ? n / 8 * 2 : 0;
+    for (int64_t k = 0; k < p4 && e == hipSuccess; ++k) e = pass(true, (int)(k & 1), (int)(4 * k));
+    for (int64_t k = 0; k < (n - 4 * p4) / 2 && e == hipSuccess; ++k)
+      e = pass(false, (int)(k & 1), (int)(4 * p4 + 2 * k));
   } else {
     const int block = B->tile_x * B->tile_y;
     const int txs = ilog2(B->tile_x);
@@ -1985,6 +2002,7 @@ static gg_status batch_autotune(gg_lattice *const *lats, int32_t n, int32_t grap
     cands.push_back({64, 4, 3, 14});
     cands.push_back({64, 4, 4, 6});
     cands.push_back({64, 4, 4, 14});
+    if (lats[0]->storage != GG_F64) cands.push_back({64, 4, 5, 6});
   }
   hipEvent_t a = nullptr, b = nullptr;
   GG_HIP(hipEventCreate(&a));
@@ -2133,7 +2151,16 @@ gg_status gg_batch_step(gg_batch *B, int64_t n) {
 
 gg_status gg_batch_set_two_step(gg_batch *B, int32_t fuse, int32_t rows) {
   if (!B) return fail(GG_ERR_ARG, "batch is NULL");
-  if (fuse != 1 && fuse != 3 && fuse != 4) return fail(GG_ERR_ARG, "fuse must be 1, 3 or 4");
+  if (fuse != 1 && fuse != 3 && fuse != 4 && fuse != 5)
+    return fail(GG_ERR_ARG, "fuse must be 1, 3, 4 or 5");
+  if (fuse == 5 && B->storage == GG_F64)
+    return fail(GG_ERR_ARG, "the four-step pass takes FP32 or FP16 storage");
+  for (size_t k = 0; k < B->lats.size() && fuse == 5; ++k) {
+    const gg_lattice *L = B->lats[k];
+    if ((L->p.periodic_x && L->nx < 4) || (L->p.periodic_y && L->ny < 4))
+      return fail(GG_ERR_ARG, "member " + std::to_string(k) +
+                                  ": the four-step pass needs periodic axes of 4 nodes or more");
+  }
   if (fuse >= 3 && rows != 6 && rows != 14) return fail(GG_ERR_ARG, "tiles have 6 or 14 rows");
   if (fuse >= 3 && B->n_tiles[0] > 0 && B->n_tiles[1] > 0)
     return fail(GG_ERR_STATE, "the two-step pass needs all members at steps of one parity");
@@ -2152,12 +2179,28 @@ gg_status gg_batch_set_two_step(gg_batch *B, int32_t fuse, int32_t rows) {
   if (B->d_seg_strips) (void)hipFree(B->d_seg_strips);
   B->d_strips = B->d_seg_strips = nullptr;
   B->n_strips = B->n_seg_strips = 0;
+  if (B->d_strips4) (void)hipFree(B->d_strips4);
+  if (B->d_seg_strips4) (void)hipFree(B->d_seg_strips4);
+  B->d_strips4 = B->d_seg_strips4 = nullptr;
+  B->n_strips4 = B->n_seg_strips4 = 0;
   B->fuse = fuse;
   B->rows = rows;
   if (fuse == 1) return GG_OK;
-  std::vector<Tile> sv, ss;
-  for (size_t k = 0; k < B->lats.size(); ++k)
-    build_strips(B->lats[k], rows, (int)k, fuse == 3, sv, ss);
+  std::vector<Tile> sv, ss, sv4, ss4;
+  for (size_t k = 0; k < B->lats.size(); ++k) {
+    build_strips(B->lats[k], rows, (int)k, fuse != 4, sv, ss);
+    if (fuse == 5) build_strips(B->lats[k], 6, (int)k, true, sv4, ss4, 2, 58);
+  }
+  B->n_strips4 = (int)sv4.size();
+  B->n_seg_strips4 = (int)ss4.size();
+  if (!sv4.empty()) {
+    GG_HIP(hipMalloc(&B->d_strips4, sv4.size() * sizeof(Tile)));
+    GG_HIP(hipMemcpy(B->d_strips4, sv4.data(), sv4.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  }
+  if (!ss4.empty()) {
+    GG_HIP(hipMalloc(&B->d_seg_strips4, ss4.size() * sizeof(Tile)));
+    GG_HIP(hipMemcpy(B->d_seg_strips4, ss4.data(), ss4.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  }
   B->n_strips = (int)sv.size();
   B->n_seg_strips = (int)ss.size();
   if (!sv.empty()) {
@@ -2173,7 +2216,9 @@ gg_status gg_batch_set_two_step(gg_batch *B, int32_t fuse, int32_t rows) {
     GG_HIP(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
     GG_HIP(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming));
   }
-  B->chunk = (B->chunk + 3) / 4 * 4;
+  // replays run whole passes: a multiple of 4 steps, of 8 with fuse 5
+  const int q = fuse == 5 ? 8 : 4;
+  B->chunk = (B->chunk + q - 1) / q * q;
   return GG_OK;
 }
 

@@ -421,8 +421,9 @@ class Batch:
         return dict(zip(("tile_x", "tile_y", "persist", "fuse", "rows"), [x.value for x in v]))
 
     def set_two_step(self, fuse: int = 4, rows: int = 6) -> None:
-        """Two-step passes over all members (fuse 3 or 4) or single steps
-        (fuse 1); include/gg.h, gg_batch_set_two_step."""
+        """Two-step passes over all members (fuse 3 or 4), four-step passes
+        (fuse 5, FP32 and FP16 storage) or single steps (fuse 1);
+        include/gg.h, gg_batch_set_two_step."""
         A.call("gg_batch_set_two_step", self._h, int(fuse), int(rows))
 
     def step(self, n: int = 1) -> None:

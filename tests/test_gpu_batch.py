@@ -53,10 +53,12 @@ def test_batch_equals_individual(tile, persist, chunk):
         assert lat.info()["t"] == 53
 
 
-@pytest.mark.parametrize("fuse,rows,chunk", [(4, 6, 8), (3, 6, 0), (3, 14, 16)])
+@pytest.mark.parametrize("fuse,rows,chunk", [(4, 6, 8), (3, 6, 0), (3, 14, 16), (5, 6, 8),
+                                             (5, 14, 0)])
 def test_batch_two_step_equals_individual(fuse, rows, chunk):
     """Two-step passes over all members in one launch (boundary tiles in the
-    same kernel, or in their own beside it) == each member on its own, also
+    same kernel, or in their own beside it), or four-step passes with runs
+    of 8k + 4 steps ending in two-step ones, == each member on its own, also
     when the batch starts at odd member steps."""
     wls = _members()
     log(f"batch two-step fuse {fuse} rows {rows} chunk {chunk}")
@@ -69,7 +71,8 @@ def test_batch_two_step_equals_individual(fuse, rows, chunk):
         lat.step(45)
     b = Batch(lats, graph_chunk=chunk, fuse=fuse, rows=rows)
     b.step(20)
-    b.step(25)
+    b.step(13)
+    b.step(12)
     b.close()
     for (fa, ga), (fb, gb) in zip(_states(ref), _states(lats)):
         assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
@@ -85,6 +88,16 @@ def test_batch_two_step_needs_one_parity():
     with pytest.raises(A.GGError) as e:
         b.set_two_step(4, 6)
     assert e.value.status == A.GG_ERR_STATE
+
+
+def test_batch_four_step_pass_needs_fp32_or_fp16():
+    wl = W.gradient_generator(nx=256, ny=128, half_period=9, storage="f64")
+    lats = _make([wl, wl])
+    b = Batch(lats)
+    with pytest.raises(A.GGError) as e:
+        b.set_two_step(5, 6)
+    assert e.value.status == A.GG_ERR_ARG
+    b.close()
 
 
 def test_batch_members_at_different_parities():

@@ -86,7 +86,7 @@ def test_batch_two_step_f64_vs_oracle(fuse, rows, chunk):
             assert e[k] <= F64_TOL, (name, k, e[k])
 
 
-@pytest.mark.parametrize("fuse", [1, 4])
+@pytest.mark.parametrize("fuse", [1, 4, 5])
 def test_batch_f32_vs_oracle(fuse):
     log(f"batch vs oracle, FP32, fuse {fuse}")
     errs = _run("f32", 60, pre=(0,),

@@ -101,6 +101,30 @@ def test_digest_scales_counters_by_the_copy_kernel(tmp_path):
     assert json.loads(out.read_text())["kernel_sha"] == bench.kernel_hash()
 
 
+def test_digest_sums_the_kernels_of_a_pass(tmp_path):
+    """sum_kernels: a pass of two kernels (interior and boundary tiles, one
+    launch each per pass) counts the sum of their per-dispatch means."""
+    copy_grid = 1024
+    nbytes = copy_grid * 16
+    (tmp_path / "batch_fetch").mkdir()
+    (tmp_path / "batch_write").mkdir()
+    k1 = "void gg::(anonymous namespace)::k_tile4<float, false, 6, true>(x)"
+    k2 = "void gg::(anonymous namespace)::k_tile4<float, true, 2, true>(x)"
+    _counter_csv(tmp_path / "batch_fetch" / "f_counter_collection.csv", "FETCH_SIZE",
+                 [("gg::k_copy(y)", copy_grid, nbytes / 1024), (k1, 7680, 100.0), (k1, 7680, 300.0),
+                  (k2, 512, 10.0), (k2, 512, 30.0)])
+    _counter_csv(tmp_path / "batch_write" / "w_counter_collection.csv", "WRITE_SIZE",
+                 [("gg::k_copy(y)", copy_grid, nbytes / 1024), (k1, 7680, 50.0), (k1, 7680, 50.0),
+                  (k2, 512, 5.0), (k2, 512, 5.0)])
+    (tmp_path / "counters_batch.json").write_text(json.dumps(
+        {"batch64": {"kernel": "k_tile4<float,", "grid": None, "sum_kernels": True,
+                     "units": 100, "bytes_per_update": 113}}))
+    d = bench.digest_counters(str(tmp_path), str(tmp_path / "t.json"))
+    w = d["workloads"]["batch64"]
+    assert w["fetch_bytes_per_launch"] == (200 + 20) * 1024
+    assert w["write_bytes_per_launch"] == (50 + 5) * 1024
+
+
 def test_bench_alignment_steps():
     # the timed region starts where a run of two-step passes can start
     for t in range(0, 13):
