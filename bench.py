@@ -394,7 +394,8 @@ def cde_bench(name, steps, flow_steps, rows, chunk=64, layout="planes"):
     """The compound alone on a frozen velocity field (the paper's decoupled
     path): the flow developed for flow_steps coupled steps, its velocity
     captured into a field slot, then graph-replayed compound-only steps
-    (two-step passes over tiles of `rows` rows, or single steps with rows 0)
+    (two-step passes over tiles of `rows` rows, four-step passes over tiles
+    of -rows rows, or single steps with rows 0)
     timed with HIP events on the lattice's stream, the populations in the
     given layout (gg_set_layout)."""
     import torch
@@ -423,7 +424,7 @@ def cde_bench(name, steps, flow_steps, rows, chunk=64, layout="planes"):
     d = lat.diagnostics(check_finite=False)
     lat.close()
     bpu = cde_bytes_per_update(wl.storage)
-    spl = 2 if rows else 1  # steps per launch
+    spl = 4 if rows < 0 else (2 if rows else 1)  # steps per launch
     launch_ms = ms * spl
     ach = nf * bpu / (launch_ms * 1e-3) / 1e9
     return {"workload": wl.name, "storage": wl.storage, "n_fluid": nf, "steps": steps,
@@ -440,8 +441,9 @@ def cde_bench(name, steps, flow_steps, rows, chunk=64, layout="planes"):
 
 
 # (workload, timed steps, coupled steps that develop the flow first, rows of
-# the two-step tiles or 0 for single steps, as measured fastest on this GPU)
-CDE_LEG = (("gg2048_f32", 4096, 2000, 14), ("allfluid8192_f32", 512, 64, 14),
+# the two-step tiles, minus the rows of the four-step tiles, or 0 for single
+# steps, as measured fastest on this GPU)
+CDE_LEG = (("gg2048_f32", 4096, 2000, 14), ("allfluid8192_f32", 512, 64, -6),
            ("gg8192_f16", 1024, 512, 0))
 
 
@@ -560,7 +562,10 @@ def counters_leg(leg, tile, chunk_unused=0):
         for name, steps, flow, rows in CDE_LEG:
             r = cde_bench(name, 16, 4, rows, 0)
             ct = CTYPE[r["storage"]]
-            if rows:
+            if rows < 0:
+                # (the only four-step compound kernel of the leg)
+                kern, grid = f"k_cde_tile4<{ct}, {-rows},", None
+            elif rows:
                 # the compound-only pass walks the tile list of the one-kernel
                 # coupled pass of the same height
                 lat = Lattice.from_workload(workload(name))
@@ -574,7 +579,7 @@ def counters_leg(leg, tile, chunk_unused=0):
             else:
                 kern, grid = f"k_cde<{ct},", None
             # one trip of the compound's bytes per launch (a pass moves them
-            # once for its two steps)
+            # once for its two or four steps)
             manifest["cde:" + name] = {"kernel": kern, "grid": grid, "units": r["n_fluid"],
                                        "bytes_per_update": cde_bytes_per_update(r["storage"])}
     else:

@@ -384,8 +384,12 @@ gg_status gg_cde_step(gg_lattice *lat, int64_t n);
  * steps as one pass over memory, one work-group of rows + 2 wavefronts per
  * tile of 62 columns x rows, which reads the compound state and the field
  * once and writes the state two steps later into the second plane set
- * (the compound planes only); rows = 0 keeps to single steps. GG_ERR_ARG
- * for other values. */
+ * (the compound planes only); rows = -6 or -10 runs runs of 8k steps in
+ * passes of four steps (one work-group of -rows + 6 wavefronts per tile of
+ * 58 columns x -rows rows with a three-node halo; lattices with pressure
+ * segments, and the last four steps of a run of 8k + 4, in two-step passes
+ * of 6-row tiles); rows = 0 keeps to single steps. GG_ERR_ARG for other
+ * values. Every form gives the single steps' result bit for bit. */
 gg_status gg_set_cde_launch(gg_lattice *lat, int32_t rows);
 
 /* Number of fluid nodes and launched tiles. */

@@ -290,6 +290,126 @@ __global__ void __launch_bounds__(256)
   ((GG_GLOBAL T *)field_plane<T>(L, slot, 1))[node] = (T)(scale * uy_in[k]);
 }
 
+// Four compound-only steps per pass over memory (no pressure segments):
+// tiles of 58 columns x R rows, R + 6 wavefronts (wavefront w on row
+// y0 - 3 + w, its lanes on the columns x0 - 3 .. x0 + 60), as the coupled
+// four-step pass: step t on every row and column of the tile and its
+// three-node halo, g1/g3 to the next column by lane shifts, g2/g4 to the
+// next row through LDS (two buffers, alternating), steps t + 1 and t + 2 on
+// the rows and columns whose state they can complete, step t + 3 on the
+// owned nodes, pushed into the neighbours' slots of the other plane set. The
+// field is read once, again only when a later step's phase uses another
+// slot. The state between steps is rounded to the storage type, so the
+// pass leaves what four single steps leave. Segment links are taken per
+// tile (flag), for tiles with one within two nodes of their own.
+template <class S, int R, bool PAIRS>
+__global__ void __launch_bounds__((R + 6) * 64)
+    k_cde_tile4(const LatDesc *__restrict__ desc, const Tile *__restrict__ tiles, int n_tiles,
+                int per_xcd, int dir, int dt) {
+  using P = Pop<S>;
+  using T = typename P::T;
+  using W = typename P::W;
+  constexpr int NW = R + 6;
+  __shared__ T lds_up[2][NW][64];
+  __shared__ T lds_dn[2][NW][64];
+  const int lane = (int)(threadIdx.x & 63);
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int tile = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (tile >= n_tiles) return;  // the whole work-group
+  const GG_CONST Tile &tl = ((const GG_CONST Tile *)tiles)[tile];
+  CDesc &L = *(CDesc *)desc;
+  const int nx = L.nx, ny = L.ny;
+  const int rows = strip_rows(tl.flags);
+  const int64_t t = *(const GG_CONST int64_t *)L.t + dt;
+  const bool seg = (tl.flags & TILE_TOUCHES_SEGMENT) != 0;
+  PhaseNow ph[4];
+  int sl[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    ph[k] = phase_at(L, t + k);
+    sl[k] = L.phase_field[ph[k].index];
+  }
+  const Planes<W> src(dir ? L.pop_b : L.pop, L.plane, PAIRS);
+  const Planes<W> dst(dir ? L.pop : L.pop_b, L.plane, PAIRS);
+
+  const int xr = tl.x0 - 3 + lane;
+  // addressable: the padding column on each side, or on a periodic axis
+  // the three-node halo wrapped once
+  const bool col = L.periodic_x ? xr >= -3 && xr <= nx + 2 : xr >= -1 && xr <= nx;
+  int x = xr;
+  if (L.periodic_x) x = xr < 0 ? xr + nx : (xr >= nx ? xr - nx : xr);
+  const bool own_col = lane >= 3 && lane < 3 + STRIP4_W && xr >= 0 && xr < nx;
+  const int yr = tl.y0 - 3 + w;
+  int y = yr;
+  if (L.periodic_y) y = yr < 0 ? yr + ny : (yr >= ny ? yr - ny : yr);
+  const bool row =
+      (L.periodic_y ? yr >= -3 && yr <= ny + 2 : yr >= -1 && yr <= ny) && w <= rows + 5;
+  const bool own = own_col && w >= 3 && w < 3 + rows && yr < ny;
+  const uint32_t node = (uint32_t)(L.node0 + y * L.pitch + x);
+  uint8_t lc = NOT_FLUID;
+  T g[5], ux = T(0), uy = T(0);
+  if (row && col) {
+    lc = ((const GG_GLOBAL uint8_t *)L.link)[node];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) g[i] = P::ld(src.at(9 + i, node));
+    ux = field_plane<T>(L, sl[0], 0)[node];
+    uy = field_plane<T>(L, sl[0], 1)[node];
+  }
+
+  // step t on every row
+  Flux fx;
+  T pg[5], ing[5];
+  if (lc != NOT_FLUID) {
+    compound_collide<T>(L, x, y, g, ux, uy, pg);
+    compound_links<T, false>(L, x, y, lc, seg, ph[0], g, pg, ing, fx, own);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) pg[i] = ing[i] = T(0);
+  }
+#pragma unroll
+  for (int k = 1; k < 4; ++k) {
+    const int q = (k - 1) & 1;
+    const T z1 = from_left(pg[1]), z3 = from_right(pg[3]);
+    lds_up[q][w][lane] = pg[2];
+    lds_dn[q][w][lane] = pg[4];
+    __syncthreads();
+    // rows whose state at t + k is needed (wave-uniform)
+    const bool act = w >= k && w < NW - k;
+    const bool run = (k < 3 ? act : own) && lc != NOT_FLUID;
+    if (run) {
+      T sg[5];
+      sg[0] = P::rt(pg[0]);
+      sg[1] = P::rt(src_solid(lc, 1) ? ing[1] : z1);
+      sg[3] = P::rt(src_solid(lc, 3) ? ing[3] : z3);
+      sg[2] = P::rt(src_solid(lc, 2) ? ing[2] : lds_up[q][w - 1][lane]);
+      sg[4] = P::rt(src_solid(lc, 4) ? ing[4] : lds_dn[q][w + 1][lane]);
+      if (sl[k] != sl[k - 1]) {  // (uniform) the phase of this step uses another field
+        ux = field_plane<T>(L, sl[k], 0)[node];
+        uy = field_plane<T>(L, sl[k], 1)[node];
+      }
+      if (k < 3) {
+        compound_collide<T>(L, x, y, sg, ux, uy, pg);
+        compound_links<T, false>(L, x, y, lc, seg, ph[k], sg, pg, ing, fx, own);
+      } else {
+        T qg[5], jg[5];
+        compound_collide<T>(L, x, y, sg, ux, uy, qg);
+        compound_links<T, false>(L, x, y, lc, seg, ph[3], sg, qg, jg, fx, true);
+        const Neigh nb(L, x, y);
+        P::st(dst.at(9, node), qg[0]);
+#pragma unroll
+        for (int i = 1; i < 5; ++i) P::st(dst.at(9 + i, nb.idx[i]), qg[i]);
+        if (lc != 0) {
+          // x + e_i not fluid: the value arriving along opp(i) stays here
+#pragma unroll
+          for (int i = 1; i < 5; ++i)
+            if ((lc >> (i - 1)) & 1) P::st(dst.at(9 + OPP[i], node), jg[OPP[i]]);
+        }
+      }
+    }
+  }
+  if (seg) fx.flush((double *)L.flux);
+}
+
 }  // namespace
 
 hipError_t launch_cde(gg_storage s, bool pairs, bool odd, const LatDesc *d, const Tile *tiles,
@@ -336,6 +456,27 @@ hipError_t launch_cde_tile2(gg_storage s, bool pairs, int rows, const LatDesc *d
   }
 #undef GG_CDE2_R
 #undef GG_CDE2
+  return hipGetLastError();
+}
+
+hipError_t launch_cde_tile4(gg_storage s, bool pairs, int rows, const LatDesc *d,
+                            const Tile *tiles, int n_tiles, int dir, int dt, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  const int per_xcd = (n_tiles + 7) / 8;
+  const int grid = 8 * per_xcd;
+#define GG_CDE4_R(TYPE, RV)                                                                    \
+  (pairs ? k_cde_tile4<TYPE, RV, true><<<grid, ((RV) + 6) * 64, 0, st>>>(d, tiles, n_tiles,     \
+                                                                         per_xcd, dir, dt)      \
+         : k_cde_tile4<TYPE, RV, false><<<grid, ((RV) + 6) * 64, 0, st>>>(d, tiles, n_tiles,    \
+                                                                          per_xcd, dir, dt))
+#define GG_CDE4(TYPE) (rows <= 6 ? GG_CDE4_R(TYPE, 6) : GG_CDE4_R(TYPE, 10))
+  switch (s) {
+    case GG_F64: GG_CDE4(double); break;
+    case GG_F32: GG_CDE4(float); break;
+    case GG_F16_SHIFTED: GG_CDE4(__half); break;
+  }
+#undef GG_CDE4
+#undef GG_CDE4_R
   return hipGetLastError();
 }
 

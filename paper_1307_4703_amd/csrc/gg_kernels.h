@@ -63,6 +63,11 @@ hipError_t launch_cde(gg_storage s, bool pairs, bool odd, const LatDesc *d, cons
 hipError_t launch_cde_tile2(gg_storage s, bool pairs, int rows, const LatDesc *d,
                             const Tile *tiles, int n_tiles, int dir, int dt, hipStream_t st,
                             bool press = false);
+// Four compound-only steps per pass (t even, no pressure segments): one
+// work-group of rows + 6 wavefronts per tile of 58 columns x (flags >> 8)
+// rows, rows 6 or 10; dir and dt as for launch_tile2.
+hipError_t launch_cde_tile4(gg_storage s, bool pairs, int rows, const LatDesc *d,
+                            const Tile *tiles, int n_tiles, int dir, int dt, hipStream_t st);
 // Velocity of the current fluid state times `scale` into field slot `slot`.
 hipError_t launch_capture(gg_storage s, const LatDesc *d, const Tile *tiles, int n_tiles,
                           int tx_shift, int slot, double scale, hipStream_t st);

@@ -107,10 +107,12 @@ struct gg_lattice {
   uint32_t ufield_set = 0;
   int8_t phase_field[GG_MAX_PHASES] = {};
   // compound-only steps in two-step passes over tiles of cde_rows rows (6 or
-  // 14; 0: single steps only); the tile list is built on first use
+  // 14; 0: single steps only), or in four-step passes over 58-column tiles
+  // of -cde_rows rows (-6 or -10; other runs in two-step passes of 6-row
+  // tiles); the tile lists are built on first use
   int cde_rows = 14;
-  gg::Tile *d_cde_tiles = nullptr;
-  int n_cde_tiles = 0, cde_tiles_rows = 0;
+  gg::Tile *d_cde_tiles = nullptr, *d_cde_tiles4 = nullptr;
+  int n_cde_tiles = 0, n_cde_tiles4 = 0, cde_tiles_rows = 0;
   hipGraph_t cde_graph[2] = {nullptr, nullptr};
   hipGraphExec_t cde_exec[2] = {nullptr, nullptr};
   // fluid nodes owned by the tiles of the pass's two lists

@@ -116,7 +116,8 @@ void gg_free_device(gg_lattice *L) {
   void *ptrs[] = {L->d_pop, L->d_pop_b, L->d_link, L->d_mask, L->d_region, L->d_R, L->d_t,
                   L->d_flux, L->d_acc, L->d_desc, L->d_tiles, L->d_aux_tiles, L->d_strips,
                   L->d_seg_strips, L->d_strips4, L->d_seg_strips4, L->d_partial, L->d_ufield,
-                  L->d_cde_tiles, L->d_press, L->d_wall, L->d_wall_links, L->d_wall_save,
+                  L->d_cde_tiles, L->d_cde_tiles4, L->d_press, L->d_wall, L->d_wall_links,
+                  L->d_wall_save,
                   L->d_mon};
   for (void *p : ptrs)
     if (p) (void)dev_free(L, p);
@@ -2434,36 +2435,54 @@ gg_status gg_set_phase_fields(gg_lattice *L, const int32_t *slots, int32_t n) {
 
 gg_status gg_set_cde_launch(gg_lattice *L, int32_t rows) {
   if (!L) return fail(GG_ERR_ARG, "lattice is NULL");
-  if (rows != 0 && rows != 6 && rows != 14) return fail(GG_ERR_ARG, "rows must be 0, 6 or 14");
+  if (rows != 0 && rows != 6 && rows != 14 && rows != -6 && rows != -10)
+    return fail(GG_ERR_ARG, "rows must be 0, 6, 14 (two-step passes) or -6, -10 (four-step passes)");
   GG_HIP(hipStreamSynchronize(L->stream));
   L->cde_rows = rows;
   gg_drop_cde_graphs(L);
   return GG_OK;
 }
 
-// Tile list of the compound-only passes for the current row count.
+// Tile lists of the compound-only passes for the current row count: the
+// two-step pass's (6 rows when the four-step pass is on) and the four-step
+// pass's (58 columns, segment flag for a link within two nodes of the
+// tile, in vertical stripes per XCD as the coupled four-step pass's).
 static gg_status cde_tiles(gg_lattice *L) {
   if (L->cde_rows == 0 || L->cde_tiles_rows == L->cde_rows) return GG_OK;
-  std::vector<Tile> list, unused;
+  std::vector<Tile> list, unused, list4;
   L->cde_halo_seg = has_pressure(L);
-  build_strips(L, L->cde_rows, 0, false, list, unused, L->cde_halo_seg);
+  build_strips(L, L->cde_rows < 0 ? 6 : L->cde_rows, 0, false, list, unused, L->cde_halo_seg);
+  if (L->cde_rows < 0) {
+    build_strips(L, -L->cde_rows, 0, false, list4, unused, 2, 58);
+    std::stable_sort(list4.begin(), list4.end(), [&](const Tile &a, const Tile &b) {
+      const int sa = (int)((int64_t)a.x0 * 8 / L->nx), sb = (int)((int64_t)b.x0 * 8 / L->nx);
+      return sa != sb ? sa < sb : (a.y0 != b.y0 ? a.y0 < b.y0 : a.x0 < b.x0);
+    });
+  }
   if (L->d_cde_tiles) GG_HIP(dev_free(L, L->d_cde_tiles));
-  L->d_cde_tiles = nullptr;
+  if (L->d_cde_tiles4) GG_HIP(dev_free(L, L->d_cde_tiles4));
+  L->d_cde_tiles = L->d_cde_tiles4 = nullptr;
   L->n_cde_tiles = (int)list.size();
+  L->n_cde_tiles4 = (int)list4.size();
   L->cde_tiles_rows = 0;
   if (!list.empty()) {
     GG_HIP(dev_alloc(L, (void **)&L->d_cde_tiles, list.size() * sizeof(Tile)));
     GG_HIP(hipMemcpy(L->d_cde_tiles, list.data(), list.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  }
+  if (!list4.empty()) {
+    GG_HIP(dev_alloc(L, (void **)&L->d_cde_tiles4, list4.size() * sizeof(Tile)));
+    GG_HIP(hipMemcpy(L->d_cde_tiles4, list4.data(), list4.size() * sizeof(Tile), hipMemcpyHostToDevice));
   }
   L->cde_tiles_rows = L->cde_rows;
   return GG_OK;
 }
 
 // n compound-only steps from a lattice whose counter reads t0 (host mirror),
-// then the counter advances by n. With passes on (cde_rows > 0 and the
+// then the counter advances by n. With passes on (cde_rows != 0 and the
 // second plane set present), the steps from an even t go in pairs of
-// passes (4 steps) that end in the first plane set; an odd-t first step and
-// the leftover run as single steps.
+// passes (8 steps in four-step passes, then 4 in two-step passes) that end
+// in the first plane set; an odd-t first step and the leftover run as
+// single steps.
 static hipError_t launch_cde_steps(gg_lattice *L, int64_t t0, int64_t n, hipStream_t st) {
   hipError_t e = hipSuccess;
   int64_t dt = 0;
@@ -2471,7 +2490,7 @@ static hipError_t launch_cde_steps(gg_lattice *L, int64_t t0, int64_t n, hipStre
     return launch_cde(L->storage, L->pairs, ((t0 + k) & 1) != 0, L->d_desc, L->d_aux_tiles,
                       L->n_aux_tiles, 6, (int)k, st);
   };
-  if (L->cde_rows > 0 && L->d_pop_b && L->cde_tiles_rows == L->cde_rows && L->wall_scheme == 0) {
+  if (L->cde_rows != 0 && L->d_pop_b && L->cde_tiles_rows == L->cde_rows && L->wall_scheme == 0) {
     const bool press = L->n_press > 0;
     if ((t0 & 1) && n > 0) {
       e = single(dt);
@@ -2479,12 +2498,21 @@ static hipError_t launch_cde_steps(gg_lattice *L, int64_t t0, int64_t n, hipStre
         e = launch_rescale(L->storage, L->d_desc, L->d_press, L->n_press, (int)dt, false, st);
       ++dt;
     }
+    if (L->cde_rows < 0 && !press) {
+      // four-step passes in pairs (ending in the first plane set)
+      const int64_t p4 = (n - dt) / 8 * 2;
+      for (int64_t k = 0; k < p4 && e == hipSuccess; ++k)
+        e = launch_cde_tile4(L->storage, L->pairs, -L->cde_rows, L->d_desc, L->d_cde_tiles4,
+                             L->n_cde_tiles4, (int)(k & 1), (int)(dt + 4 * k), st);
+      dt += 4 * p4;
+    }
     const int64_t passes = (n - dt) / 4 * 2;
     // (pressure: each pass after the first rescales the state it loads, the
     // kernel the state the last one leaves, in pop_b after dir 0)
     const bool at_load = press && L->cde_halo_seg;
     for (int64_t k = 0; k < passes && e == hipSuccess; ++k) {
-      e = launch_cde_tile2(L->storage, L->pairs, L->cde_rows, L->d_desc, L->d_cde_tiles, L->n_cde_tiles,
+      e = launch_cde_tile2(L->storage, L->pairs, L->cde_rows < 0 ? 6 : L->cde_rows, L->d_desc,
+                           L->d_cde_tiles, L->n_cde_tiles,
                            (int)(k & 1) | (at_load && k > 0 ? 2 : 0), (int)(dt + 2 * k), st,
                            press);
       if (e == hipSuccess && press && (!at_load || k == passes - 1))

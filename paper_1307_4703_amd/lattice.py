@@ -300,8 +300,9 @@ class Lattice:
         A.call("gg_set_phase_fields", self._h, arr, len(slots))
 
     def set_cde_launch(self, rows: int = 14) -> None:
-        """Two-step passes over tiles of 6 or 14 rows for cde_step, or
-        single steps (rows = 0)."""
+        """Two-step passes over tiles of 6 or 14 rows for cde_step,
+        four-step passes over 58-column tiles of 6 or 10 rows (rows = -6,
+        -10), or single steps (rows = 0); include/gg.h, gg_set_cde_launch."""
         A.call("gg_set_cde_launch", self._h, int(rows))
 
     def cde_step(self, n: int = 2) -> None:

@@ -146,14 +146,16 @@ def tune_batch(lattices: Sequence, steps: int = 32, tiles: Iterable[Tuple[int, i
     return out
 
 
-def tune_cde(lat, steps: int = 256, rows: Iterable[int] = (0, 6, 14), use_cache: bool = True,
+def tune_cde(lat, steps: int = 256, rows: Iterable[int] = (0, 6, 14, -6, -10),
+             use_cache: bool = True,
              path: Optional[str] = None) -> Dict:
     """Pick the launch form of the compound-only step (two-step passes over
-    tiles of 6 or 14 rows, or single steps) with the shortest step time and
+    tiles of 6 or 14 rows, four-step passes over 58-column tiles of 6 or 10
+    rows (rows -6, -10), or single steps) with the shortest step time and
     apply it. Needs a velocity field for every phase; advances the compound
-    (steps should be a multiple of 4)."""
+    (steps should be a multiple of 8)."""
     path = path or cache_path()
-    key = _key([lat], "cde")
+    key = _key([lat], "cde4")
     if use_cache:
         hit = _load(path).get(key)
         if hit:

@@ -53,11 +53,13 @@ def _compare(lat, o, fluid, storage, label):
     return f
 
 
+@pytest.mark.parametrize("rows", [14, -6])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
-def test_given_fields_per_phase(storage):
+def test_given_fields_per_phase(storage, rows):
     """Ragged 300x150 gradient generator, valves switching every 7 steps,
     one field per valve phase, source and decay; 40 steps in graph replays
-    of 8 plus plain launches; the fluid populations stay as they were."""
+    of 8 plus plain launches (two- or four-step passes); the fluid
+    populations stay as they were."""
     wl = W.gradient_generator(nx=300, ny=150, half_period=7, storage=storage)
     wl.k_decay = 1e-3
     rng = np.random.default_rng(9)
@@ -65,6 +67,7 @@ def test_given_fields_per_phase(storage):
     R[50:70, 90:130] = 1e-3 * rng.random((20, 40))
     init = seeded_init(wl, 21)
     lat = make_lattice(wl, storage, init, chunk=8)
+    lat.set_cde_launch(rows)
     lat.set_source(R)
     fields = _fields(wl.mask.shape, 5)
     for k, (ux, uy) in enumerate(fields):
@@ -204,9 +207,10 @@ def _same_compound(one, two, t):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
-@pytest.mark.parametrize("rows", [6, 14])
+@pytest.mark.parametrize("rows", [6, 14, -6, -10])
 def test_passes_equal_single_steps(storage, rows):
-    """Two compound-only steps per pass against single steps, bit for bit:
+    """Two (rows > 0) or four (rows < 0) compound-only steps per pass
+    against single steps, bit for bit:
     ragged gradient generator, valves switching every 7 steps (inside and
     between the steps of a pass) with a field per phase, a source and decay,
     odd starts and leftovers, graph replays."""
@@ -231,11 +235,12 @@ def test_passes_equal_single_steps(storage, rows):
     _same_compound(one, two, 66)
 
 
+@pytest.mark.parametrize("rows", [14, -6])
 @pytest.mark.parametrize("periodic", [(True, False), (False, True), (True, True), (False, False)])
-def test_passes_random_masks_periodic(periodic):
+def test_passes_random_masks_periodic(periodic, rows):
     mask = W.random_mask(133, 71, seed=7, periodic=periodic)
     wl = W.Workload("random", mask, tau_f=0.7, D=0.03, periodic=periodic)
-    one, two = _cde_pair(wl, "f64", 3, 14)
+    one, two = _cde_pair(wl, "f64", 3, rows)
     u = _fields(mask.shape, 2)[0]
     for lat in (one, two):
         lat.set_velocity_field(0, *u)
@@ -248,7 +253,7 @@ def test_passes_random_masks_periodic(periodic):
 
 
 def test_autotuner_keeps_the_result(tmp_path):
-    """tune_cde times single steps and both tile heights, applies the
+    """tune_cde times single steps and the four pass forms, applies the
     fastest, and the state it leaves equals single steps over as many steps."""
     from paper_1307_4703_amd import tune
     wl = W.gradient_generator(nx=300, ny=150, half_period=9, storage="f32")
@@ -256,9 +261,9 @@ def test_autotuner_keeps_the_result(tmp_path):
     for lat in (one, two):
         lat.set_velocity_field(0)
     res = tune.tune_cde(two, steps=16, path=str(tmp_path / "tune.json"), use_cache=False)
-    assert res["rows"] in (0, 6, 14) and len(res["all"]) == 3
-    one.cde_step(3 * (4 + 16))  # per candidate: 4 warm-up and 16 timed steps
-    _same_compound(one, two, 60)
+    assert res["rows"] in (0, 6, 14, -6, -10) and len(res["all"]) == 5
+    one.cde_step(5 * (4 + 16))  # per candidate: 4 warm-up and 16 timed steps
+    _same_compound(one, two, 100)
 
 
 def test_host_field_beyond_positivity_limit_refused():
