@@ -2608,6 +2608,11 @@ gg_status gg_permute_tiles(gg_lattice *L, uint64_t seed) {
   GG_HIP(shuffle(L->d_tiles, L->n_tiles));
   GG_HIP(shuffle(L->d_strips, L->n_strips));
   GG_HIP(shuffle(L->d_seg_strips, L->n_seg_strips));
+  GG_HIP(shuffle(L->d_strips4, L->n_strips4));
+  GG_HIP(shuffle(L->d_seg_strips4, L->n_seg_strips4));
+  GG_HIP(shuffle(L->d_cde_tiles, L->n_cde_tiles));
+  GG_HIP(shuffle(L->d_cde_tiles4, L->n_cde_tiles4));
+  gg_drop_cde_graphs(L);
   if (L->graph_exec) (void)hipGraphExecDestroy(L->graph_exec);
   if (L->graph) (void)hipGraphDestroy(L->graph);
   L->graph_exec = nullptr;

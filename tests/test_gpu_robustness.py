@@ -18,7 +18,7 @@ from tests.parity_util import SNAP_DATA, log, make_lattice, seeded_init, snapsho
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("fuse,rows", [(1, 6), (3, 6), (4, 14), (2, 8)])
+@pytest.mark.parametrize("fuse,rows", [(1, 6), (3, 6), (4, 14), (2, 8), (5, 6)])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_tile_order_does_not_matter(fuse, rows, storage):
     wl = W.gradient_generator(nx=300, ny=150, half_period=7, storage=storage)
