@@ -76,7 +76,7 @@ def workload(name):
 FORMS = {"gg2048_f32": (5, 6), "gg2048_f16": (4, 6), "gg8192_f16": (3, 6),
          "gg8192_f16_pe2000": (3, 6), "gg8192_f32": (5, 6), "allfluid8192_f32": (5, 6),
          "allfluid8192_f16": (3, 6), "shard8192x512_f32": (5, 6),
-         "allfluid8192_f64": (3, 14), "gg2048_f64": (3, 6), "straight_f64": (4, 6)}
+         "allfluid8192_f64": (5, 6), "gg2048_f64": (5, 6), "straight_f64": (4, 6)}
 # the adjoint leg's lattice (2048 x 1024 FP32): the one-kernel two-step
 # form, whose taped recomputation passes are one kernel as well (the
 # four-step pass has no taped form; its lattices recompute in the two

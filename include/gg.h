@@ -300,9 +300,9 @@ gg_status gg_set_launch(gg_lattice *lat, int32_t tile_x, int32_t tile_y,
  *     each step's row-crossing populations through LDS; the tiles whose
  *     nodes within two of their own link to a segment run as 58 x 2 tiles
  *     in a kernel of their own on the second stream, as with fuse = 3.
- *     Other runs step as with fuse = 3 (strip_h 6 or 14). FP32 and FP16
- *     storage without pressure segments or the paper's walls, periodic
- *     axes of 4 nodes or more; otherwise fuse = 5 steps as fuse = 3. The
+ *     Other runs step as with fuse = 3 (strip_h 6 or 14). Lattices without
+ *     pressure segments or the paper's walls, periodic axes of 4 nodes or
+ *     more; otherwise fuse = 5 steps as fuse = 3. The
  *     result is that of single steps, bit for bit, as for every form.
  * Each collides a one-node halo around its strip or tile once more for the
  * first step. Errors: GG_ERR_ARG for other values, and for fuse = 2 where
@@ -414,8 +414,8 @@ gg_status gg_info(const gg_lattice *lat, int64_t *n_fluid, int64_t *n_tiles,
  * then ignored): each candidate (single steps over tiles of 64 x 4, 32 x 8
  * or 128 x 2 nodes; when every member has its second plane set and all sit
  * at steps of one parity, two-step passes with 6- or 14-row tiles and the
- * boundary tiles apart, or 6- or 14-row tiles in one kernel, and with FP32
- * or FP16 storage four-step passes) advances the members
+ * boundary tiles apart, or 6- or 14-row tiles in one kernel, or four-step
+ * passes) advances the members
  * 20 steps, 16 of them timed with HIP events on their stream, and the
  * fastest is kept (gg_batch_form reports it). The members' states, step
  * counts and boundary fluxes are copied aside on the device (hipMalloc of
@@ -438,8 +438,8 @@ gg_status gg_batch_form(const gg_batch *batch, int32_t *tile_x, int32_t *tile_y,
  * (fuse 3: the boundary tiles of all members in a second list on a second
  * stream); fuse 5: four-step passes over the members' 58 x 6 tiles (the
  * boundary tiles apart), runs of 8k + 4 steps ending in two two-step
- * passes of fuse 3's form with `rows` rows (FP32 and FP16 storage, else
- * GG_ERR_ARG, as for periodic axes under 4 nodes); fuse = 1 goes back to
+ * passes of fuse 3's form with `rows` rows (GG_ERR_ARG for a member with a
+ * periodic axis under 4 nodes); fuse = 1 goes back to
  * single steps. Every member must have its
  * second plane set (fuse >= 2 on the member, the default) and all members
  * must sit at steps of one parity (else GG_ERR_STATE). The states advance

@@ -721,7 +721,10 @@ hipError_t launch_tile4(gg_storage s, bool pairs, bool seg, const LatDesc *d, co
   const int per_xcd = (n_tiles + 7) / 8;
   const int grid = 8 * per_xcd;
   switch (s) {
-    case GG_F64: return hipErrorInvalidValue;
+    case GG_F64:
+      if (pairs) tile4_launch<double, true>(seg, grid, st, d, tiles, n_tiles, per_xcd, dir, dt);
+      else tile4_launch<double, false>(seg, grid, st, d, tiles, n_tiles, per_xcd, dir, dt);
+      break;
     case GG_F32:
       if (pairs) tile4_launch<float, true>(seg, grid, st, d, tiles, n_tiles, per_xcd, dir, dt);
       else tile4_launch<float, false>(seg, grid, st, d, tiles, n_tiles, per_xcd, dir, dt);

@@ -43,8 +43,7 @@ hipError_t launch_tile2(gg_storage s, bool pairs, bool seg, int rows, const LatD
 
 // Four steps in one pass (t even, natural order in and out): one work-group
 // of rows + 6 wavefronts per tile of 58 columns x (flags >> 8) rows, rows 2
-// (seg, the boundary kernel) or 6; FP32 and FP16-shifted storage (FP64:
-// hipErrorInvalidValue), no pressure segments; dir and dt as for
+// (seg, the boundary kernel) or 6; no pressure segments; dir and dt as for
 // launch_tile2.
 hipError_t launch_tile4(gg_storage s, bool pairs, bool seg, const LatDesc *d, const Tile *tiles,
                         int n_tiles, int dir, int dt, hipStream_t st);

@@ -117,8 +117,8 @@ struct gg_lattice {
   hipGraphExec_t cde_exec[2] = {nullptr, nullptr};
   // fluid nodes owned by the tiles of the pass's two lists
   int64_t strips_fluid = 0, seg_strips_fluid = 0;
-  // the four-step pass's lists (fuse = 5 where the lattice allows it: FP32
-  // or FP16 storage, no pressure segments, periodic axes of 4 nodes or more)
+  // the four-step pass's lists (fuse = 5 where the lattice allows it: no
+  // pressure segments, periodic axes of 4 nodes or more)
   gg::Tile *d_strips4 = nullptr, *d_seg_strips4 = nullptr;
   int n_strips4 = 0, n_seg_strips4 = 0;
   int64_t strips4_fluid = 0, seg_strips4_fluid = 0;

@@ -325,12 +325,11 @@ static int64_t owned_fluid(const gg_lattice *L, const std::vector<Tile> &list, i
 
 static bool has_pressure(const gg_lattice *L);
 
-// The four-step pass (fuse 5) covers this lattice: FP32 or FP16 storage
-// (the FP64 tiles would not fit two work-groups per CU), no pressure
-// segments (their rescaling runs between steps) nor the paper's walls, and
-// periodic axes of 4 nodes or more (the tiles' three-node halo wraps once).
+// The four-step pass (fuse 5) covers this lattice: no pressure segments
+// (their rescaling runs between steps) nor the paper's walls, and periodic
+// axes of 4 nodes or more (the tiles' three-node halo wraps once).
 static bool pass4_ok(const gg_lattice *L) {
-  return L->fuse == 5 && L->storage != GG_F64 && !has_pressure(L) && L->wall_scheme == 0 &&
+  return L->fuse == 5 && !has_pressure(L) && L->wall_scheme == 0 &&
          (!L->p.periodic_x || L->nx >= 4) && (!L->p.periodic_y || L->ny >= 4);
 }
 
@@ -2003,7 +2002,7 @@ static gg_status batch_autotune(gg_lattice *const *lats, int32_t n, int32_t grap
     cands.push_back({64, 4, 3, 14});
     cands.push_back({64, 4, 4, 6});
     cands.push_back({64, 4, 4, 14});
-    if (lats[0]->storage != GG_F64) cands.push_back({64, 4, 5, 6});
+    cands.push_back({64, 4, 5, 6});
   }
   hipEvent_t a = nullptr, b = nullptr;
   GG_HIP(hipEventCreate(&a));
@@ -2154,8 +2153,6 @@ gg_status gg_batch_set_two_step(gg_batch *B, int32_t fuse, int32_t rows) {
   if (!B) return fail(GG_ERR_ARG, "batch is NULL");
   if (fuse != 1 && fuse != 3 && fuse != 4 && fuse != 5)
     return fail(GG_ERR_ARG, "fuse must be 1, 3, 4 or 5");
-  if (fuse == 5 && B->storage == GG_F64)
-    return fail(GG_ERR_ARG, "the four-step pass takes FP32 or FP16 storage");
   for (size_t k = 0; k < B->lats.size() && fuse == 5; ++k) {
     const gg_lattice *L = B->lats[k];
     if ((L->p.periodic_x && L->nx < 4) || (L->p.periodic_y && L->ny < 4))

@@ -188,8 +188,8 @@ class Lattice:
         """Two steps per pass over memory (fuse = 2: walking strips of
         strip_h rows; 3, the default: row-parallel tiles of 6 or 14 rows with
         the boundary kernel apart; 4: the same in one kernel), four steps per
-        pass in runs of 8k steps (fuse = 5, FP32 and FP16 storage; other
-        runs as fuse = 3) or single steps (fuse = 1); include/gg.h,
+        pass in runs of 8k steps (fuse = 5; other runs as fuse = 3) or
+        single steps (fuse = 1); include/gg.h,
         gg_set_two_step."""
         A.call("gg_set_two_step", self._h, int(fuse), int(strip_h))
 
@@ -423,7 +423,7 @@ class Batch:
 
     def set_two_step(self, fuse: int = 4, rows: int = 6) -> None:
         """Two-step passes over all members (fuse 3 or 4), four-step passes
-        (fuse 5, FP32 and FP16 storage) or single steps (fuse 1);
+        (fuse 5) or single steps (fuse 1);
         include/gg.h, gg_batch_set_two_step."""
         A.call("gg_batch_set_two_step", self._h, int(fuse), int(rows))
 

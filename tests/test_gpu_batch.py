@@ -90,9 +90,10 @@ def test_batch_two_step_needs_one_parity():
     assert e.value.status == A.GG_ERR_STATE
 
 
-def test_batch_four_step_pass_needs_fp32_or_fp16():
-    wl = W.gradient_generator(nx=256, ny=128, half_period=9, storage="f64")
-    lats = _make([wl, wl])
+def test_batch_four_step_pass_needs_periodic_axes_of_four():
+    mask = np.zeros((3, 40), np.uint8)
+    wl = W.Workload("thin", mask, tau_f=0.9, D=0.02, periodic=(True, True), storage="f32")
+    lats = _make([wl])
     b = Batch(lats)
     with pytest.raises(A.GGError) as e:
         b.set_two_step(5, 6)
@@ -182,7 +183,9 @@ def test_library_autotuner_leaves_members_and_steps_like_them():
     f = b.form()
     log(f"library autotune picked {f}")
     assert (f["tile_x"], f["tile_y"]) in ((64, 4), (32, 8), (128, 2))
-    assert (f["fuse"], f["rows"]) in ((1, 6), (3, 6), (3, 14), (4, 6))
+    # (the library's candidates: single steps, the two-step forms, the
+    # four-step pass)
+    assert (f["fuse"], f["rows"]) in ((1, 6), (3, 6), (3, 14), (4, 6), (4, 14), (5, 6))
     for (fa, ga), (fb, gb) in zip(before, _states(lats)):
         assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
     for lat in lats:

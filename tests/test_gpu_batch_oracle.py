@@ -75,7 +75,7 @@ def test_batch_single_steps_f64_vs_oracle(tile, persist, chunk):
             assert e[k] <= F64_TOL, (name, k, e[k])
 
 
-@pytest.mark.parametrize("fuse,rows,chunk", [(3, 6, 8), (4, 14, 0)])
+@pytest.mark.parametrize("fuse,rows,chunk", [(3, 6, 8), (4, 14, 0), (5, 6, 8)])
 def test_batch_two_step_f64_vs_oracle(fuse, rows, chunk):
     log(f"batch vs oracle, two-step fuse {fuse} rows {rows} chunk {chunk}")
     errs = _run("f64", 45, pre=(1,),

@@ -5,8 +5,8 @@ single-step kernels give, for every storage type, boundary kind,
 periodicity, strip height and schedule phase; boundary fluxes agree to
 FP64 rounding (their atomics add in another order). The same for the
 four-step pass (fuse 5: 58 x 6 tiles with a three-node halo, runs of 8k
-steps; other runs in two-step passes), which FP64 lattices and lattices
-with pressure segments decline for the two-step pass."""
+steps; other runs in two-step passes), which lattices with pressure
+segments decline for the two-step pass."""
 import numpy as np
 import pytest
 
@@ -117,10 +117,10 @@ def test_straight_channel_inlet_outlet(mode, strip_h, storage):
     _same_state(one, two, 120)
 
 
-@pytest.mark.parametrize("storage,steps_per_pass", [("f32", 4), ("f16", 4), ("f64", 2)])
+@pytest.mark.parametrize("storage,steps_per_pass", [("f32", 4), ("f16", 4), ("f64", 4)])
 def test_four_step_pass_runs_where_it_applies(storage, steps_per_pass):
-    """fuse 5 runs four-step passes on FP32 and FP16 lattices (the profile
-    times their interior kernel) and two-step passes on FP64 ones; a
+    """fuse 5 runs four-step passes (the profile times their interior
+    kernel) in every storage type; a
     2048x1024 gradient generator over graph replays of 64 steps and a run
     of 8k + 4 plain-launched steps is still bitwise the single steps'."""
     wl = W.gradient_generator(nx=2048, ny=1024, half_period=50, storage=storage)
