@@ -80,7 +80,9 @@ FORMS = {"gg2048_f32": (5, 6), "gg2048_f16": (4, 6), "gg8192_f16": (3, 6),
 # the adjoint leg's lattice (2048 x 1024 FP32): the one-kernel two-step
 # form, whose taped recomputation passes are one kernel as well (the
 # four-step pass has no taped form; its lattices recompute in the two
-# kernels of fuse 3)
+# kernels of fuse 3: the forward sweep gains, 0.138 against 0.164 s over
+# 20000 steps on this GPU, the whole gradient loses, 0.588-0.592 against
+# 0.569-0.580 s)
 ADJOINT_FORM = (4, 6)
 
 
