@@ -142,3 +142,41 @@ def test_timed_passes_keep_the_state(mode, strip_h):
     ms = two.step2_timed(3)
     assert ms > 0.0
     _same_state(one, two, 12)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_four_step_forms_fall_back_with_pressure_segments(storage):
+    """Pressure segments (rescaling between steps) and the paper's walls
+    keep the four-step forms out: fuse 5 then steps as fuse 3 (two-step
+    passes) or in single steps, and the compound-only rows -6 in two-step
+    passes, each bitwise the single steps'."""
+    nx, ny = 130, 34
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[0, :] = 1
+    mask[-1, :] = 1
+    mask[1:-1, 0] = 2
+    mask[1:-1, -1] = 3
+    segs = [W.Segment(2, "pressure", (-1, 0), rho=1.003, c_in=1.0, fix_c=True),
+            W.Segment(3, "pressure", (1, 0), rho=0.997)]
+    wl = W.Workload("pressure_channel", mask, tau_f=0.8, D=0.02, segments=segs, storage=storage)
+    for walls in (False, True):
+        one, two = _pair(wl, storage, 5, 6, mode=5)
+        if walls:
+            for lat in (one, two):
+                lat.set_wall_scheme("equilibrium")
+        log(f"four-step forms with pressure segments, {storage}, paper walls {walls}")
+        p = two.step_profile(16)
+        assert p["steps_per_pass"] == 2 and p["fuse"] == (1 if walls else 5)
+        one.step(16)
+        one.step(24)
+        two.step(24)
+        _same_state(one, two, 40)
+        for lat in (one, two):
+            lat.set_velocity_field(0)
+        one.set_cde_launch(0)
+        two.set_cde_launch(-6)
+        one.cde_step(24)
+        two.cde_step(24)
+        fa, ga = one.populations()
+        fb, gb = two.populations()
+        assert np.array_equal(ga, gb) and np.array_equal(fa, fb)
