@@ -41,11 +41,13 @@ def _oracle_adjoint(wl, init, steps, weight, target, R=None):
 
 
 @pytest.mark.parametrize("ckpt,form", [(0, None), (1, None), (7, None), (60, None),
-                                       (7, (1, 6)), (7, (4, 14)), (13, (3, 14)), (60, (4, 6))])
+                                       (7, (1, 6)), (7, (4, 14)), (13, (3, 14)), (60, (4, 6)),
+                                       (7, (5, 6)), (60, (5, 6))])
 def test_f64_adjoint_matches_oracle(ckpt, form):
     """Checkpoint intervals of 1, 7 (segments starting on odd steps), 13 and
     60 steps, recomputed in single steps or in taped two-step passes (the
-    boundary tiles apart or in the one kernel)."""
+    boundary tiles apart or in the one kernel); with fuse 5 the forward
+    steps run in four-step passes."""
     wl = _small()
     wl.k_decay = 2e-3
     init = seeded_init(wl, 3)
